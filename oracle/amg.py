@@ -1,0 +1,239 @@
+"""Oracle: classical algebraic multigrid as chosen for this build.
+
+The paper applies one AMG V-cycle per inner solve (Sec. 3.2-3.4, Sec. 4.1
+solver settings) with hypre BoomerAMG (CLJP coarsening, classical
+interpolation, hybrid Gauss-Seidel).  The build replaces those components by
+deterministic, data-parallel ones; this module states exactly those:
+
+1. strength: s_i = sign(a_ii) (+1 for a_ii >= 0), m_i = max_{k!=i} -s_i a_ik;
+   j is strong for i iff m_i > 0 and -s_i a_ij >= theta m_i;
+2. PMIS coarsening (De Sterck, Yang, Heys): weights w_i = |S^T_i| + u_i with
+   u_i = (splitmix64(seed ^ i) >> 40) * 2^-24; points with |S^T_i| = 0 start
+   as F; each round an undecided i becomes C iff (w_i, i) beats (w_j, j)
+   lexicographically for every undecided j in S_i u S^T_i; then every
+   undecided j with a new C point in S_j becomes F;
+3. direct interpolation (Stueben): for an F point i with P_i = C n S_i,
+   w_ij = -alpha_i a_ij / a~_ii, alpha_i = sum_{k!=i} a_ik^- / sum_{k in P_i} a_ik^-,
+   where ^- marks entries of sign opposite to a_ii and a~_ii = a_ii plus the
+   same-signed off-diagonal entries (strong points always have the opposite
+   sign, so the same-signed part is always lumped); C rows are injection,
+   coarse points are numbered in ascending fine order;
+4. R = P^T, A_c = R (A P) with the symbolic pattern (no dropping);
+5. stop when n <= coarse_max, n_c == 0, n_c > 0.9 n, or max_levels; the
+   coarsest level is solved by dense LU with partial pivoting when it has at
+   most dense_max rows, otherwise by two l1-Jacobi sweeps;
+6. V(1,1) cycle with l1-Jacobi, d_i = a_ii + s_i sum_{j!=i} |a_ij| (rows
+   with d_i = 0 are not smoothed), zero initial guess on every level.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from .blocks import place_on_pattern, symbolic_product
+
+UNDECIDED, C_PT, F_PT = 0, 1, 2
+MASK64 = (1 << 64) - 1
+
+
+def splitmix64(x: int) -> int:
+    """SplitMix64 output function (Steele, Lea, Flood 2014) of state x."""
+    z = (x + 0x9E3779B97F4A7C15) & MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+    return z ^ (z >> 31)
+
+
+def splitmix64_vec(x: np.ndarray) -> np.ndarray:
+    x = x.astype(np.uint64)
+    with np.errstate(over="ignore"):
+        z = x + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def pmis_random(n: int, seed: int) -> np.ndarray:
+    i = np.arange(n, dtype=np.uint64)
+    z = splitmix64_vec(np.uint64(seed) ^ i)
+    return (z >> np.uint64(40)).astype(np.float64) * 2.0 ** -24
+
+
+def row_index(A):
+    return np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
+
+
+def diag_sign(A):
+    return np.where(A.diagonal() < 0, -1.0, 1.0)
+
+
+def strength(A, theta=0.25):
+    """Boolean mask over the stored entries of A (CSR, sorted)."""
+    n = A.shape[0]
+    rows = row_index(A)
+    cols = A.indices
+    s = diag_sign(A)
+    offd = cols != rows
+    neg = -s[rows] * A.data
+    m = np.full(n, -np.inf)
+    np.maximum.at(m, rows[offd], neg[offd])
+    mr = m[rows]
+    return offd & (mr > 0) & (neg >= theta * mr)
+
+
+def strength_matrix(A, mask):
+    rows = row_index(A)
+    return sp.csr_matrix((np.ones(int(mask.sum()), np.int8), (rows[mask], A.indices[mask])),
+                         shape=A.shape)
+
+
+def pmis(A, mask, seed):
+    """C/F splitting (array of C_PT / F_PT) and the number of rounds."""
+    n = A.shape[0]
+    S = strength_matrix(A, mask)
+    ST = S.T.tocsr()
+    nst = np.diff(ST.indptr)
+    w = nst + pmis_random(n, seed)
+    state = np.full(n, UNDECIDED, np.int8)
+    state[nst == 0] = F_PT
+    G = ((S + ST) > 0).tocsr()
+    gr = row_index(G)
+    gc = G.indices
+    Sr = row_index(S)
+    Sc = S.indices
+    rounds = 0
+    while np.any(state == UNDECIDED):
+        rounds += 1
+        und = state == UNDECIDED
+        live = und[gr] & und[gc]
+        beats = live & ((w[gc] > w[gr]) | ((w[gc] == w[gr]) & (gc > gr)))
+        lose = np.zeros(n, bool)
+        lose[gr[beats]] = True
+        newc = und & ~lose
+        state[newc] = C_PT
+        hasc = np.zeros(n, bool)
+        hasc[Sr[newc[Sc]]] = True
+        state[und & ~newc & hasc] = F_PT
+    return state, rounds
+
+
+def direct_interpolation(A, mask, cf):
+    """P (n x n_c CSR, columns ascending) and the coarse index map."""
+    n = A.shape[0]
+    rows = row_index(A)
+    cols = A.indices
+    vals = A.data
+    diag = A.diagonal()
+    s = diag_sign(A)
+    offd = cols != rows
+    opp = offd & (s[rows] * vals < 0)
+    same = offd & (s[rows] * vals > 0)
+    isc = cf == C_PT
+    cidx = np.cumsum(isc) - 1
+    nc = int(isc.sum())
+    pmask = mask & isc[cols]
+    sum_n_opp = np.bincount(rows[opp], vals[opp], minlength=n)
+    sum_n_same = np.bincount(rows[same], vals[same], minlength=n)
+    sum_p_opp = np.bincount(rows[pmask], vals[pmask], minlength=n)
+    atil = diag + sum_n_same
+    frow = ~isc[rows]
+    emask = pmask & frow
+    er = rows[emask]
+    alpha = sum_n_opp[er] / sum_p_opp[er]
+    wv = -alpha * vals[emask] / atil[er]
+    crow = np.nonzero(isc)[0]
+    r_all = np.concatenate([er, crow])
+    c_all = np.concatenate([cidx[cols[emask]], cidx[crow]])
+    v_all = np.concatenate([wv, np.ones(len(crow))])
+    order = np.lexsort((c_all, r_all))
+    P = sp.csr_matrix((v_all[order], (r_all[order], c_all[order])), shape=(n, nc))
+    # csr_matrix from COO sums duplicates (there are none) and keeps zeros
+    P.sort_indices()
+    return P, cidx
+
+
+def galerkin(A, P):
+    """A_c = R (A P), R = P^T, on the symbolic pattern (no dropping)."""
+    R = P.T.tocsr()
+    R.sort_indices()
+    AP = A @ P
+    val = R @ AP
+    pat = symbolic_product(R, A, P)
+    return place_on_pattern(pat, val), R
+
+
+def l1_diag(A):
+    rows = row_index(A)
+    offd = A.indices != rows
+    s = diag_sign(A)
+    off = np.bincount(rows[offd], np.abs(A.data[offd]), minlength=A.shape[0])
+    return A.diagonal() + s * off
+
+
+class Level:
+    def __init__(self, A):
+        self.A = A.tocsr()
+        self.A.sort_indices()
+        self.n = A.shape[0]
+        d = l1_diag(self.A)
+        # a zero l1 row (a decoupled, empty row) is left unsmoothed
+        self.dinv = np.divide(1.0, d, out=np.zeros_like(d), where=d != 0)
+        self.P = None
+        self.R = None
+        self.mask = None
+        self.cf = None
+
+
+class Hierarchy:
+    """AMG hierarchy; ``levels[-1]`` is the coarsest."""
+
+    def __init__(self, A, theta=0.25, coarse_max=256, max_levels=25, seed=0x5eed,
+                 dense_max=1024):
+        self.levels = []
+        self.dense_max = dense_max
+        A = A.tocsr()
+        A.sort_indices()
+        while True:
+            lvl = Level(A)
+            self.levels.append(lvl)
+            if lvl.n <= coarse_max or len(self.levels) >= max_levels:
+                break
+            mask = strength(lvl.A, theta)
+            cf, _ = pmis(lvl.A, mask, seed)
+            nc = int((cf == C_PT).sum())
+            if nc == 0 or nc > 0.9 * lvl.n:
+                break
+            P, _ = direct_interpolation(lvl.A, mask, cf)
+            Ac, R = galerkin(lvl.A, P)
+            lvl.mask, lvl.cf, lvl.P, lvl.R = mask, cf, P, R
+            A = Ac
+        last = self.levels[-1]
+        self.coarse_dense = last.n <= dense_max
+        if self.coarse_dense:
+            self.lu = sla.lu_factor(last.A.toarray())
+
+    def coarse_solve(self, b):
+        last = self.levels[-1]
+        if self.coarse_dense:
+            return sla.lu_solve(self.lu, b)
+        x = last.dinv * b
+        return x + last.dinv * (b - last.A @ x)
+
+    def vcycle(self, b, level=0):
+        """One V(1,1) cycle with zero initial guess."""
+        if level == len(self.levels) - 1:
+            return self.coarse_solve(b)
+        L = self.levels[level]
+        x = L.dinv * b
+        r = b - L.A @ x
+        xc = self.vcycle(L.R @ r, level + 1)
+        x = x + L.P @ xc
+        return x + L.dinv * (b - L.A @ x)
+
+    def stats(self):
+        rows = [L.n for L in self.levels]
+        nnz = [L.A.nnz for L in self.levels]
+        return dict(levels=len(rows), rows=rows, nnz=nnz,
+                    operator_complexity=sum(nnz) / nnz[0], grid_complexity=sum(rows) / rows[0])

@@ -1,0 +1,394 @@
+"""Pins for the oracle's block views, Schur complement, AMG, ILU(0),
+preconditioners and FGMRES (no GPU)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import amg, blocks, fgmres, ilu, newton, precond, tpfa
+from paper_1611_00127_amd import inputs
+
+
+def _small(nx=6, ny=5, nz=2, seed=1, **kw):
+    """Small case with both phases mobile in every cell (S_n in (0.12, 0.88))."""
+    c = inputs.small_case(nx, ny, nz, seed=seed, **kw)
+    c = inputs.random_state(c, seed + 100, s_lo=0.12, s_hi=0.88)
+    rp, ci, v = tpfa.jacobian(c, c.u, c.u_old)
+    return c, rp, ci, v
+
+
+def _perm_point_to_field(N):
+    """Permutation matrix taking point order (p0,s0,p1,s1,..) to field order."""
+    idx = np.concatenate([np.arange(0, 2 * N, 2), np.arange(1, 2 * N, 2)])
+    return np.eye(2 * N)[idx]
+
+
+# ----------------------------------------------------------------- blocks
+
+
+def test_scalarize_and_spmv_match_dense():
+    c, rp, ci, v = _small()
+    D = tpfa.bcsr_to_dense(rp, ci, v)
+    np.testing.assert_array_equal(blocks.scalarize(rp, ci, v).toarray(), D)
+    x = inputs.random_vector(2 * c.N, 7)
+    np.testing.assert_allclose(tpfa.bcsr_spmv(rp, ci, v, x), D @ x, rtol=0,
+                               atol=1e-14 * np.abs(D).sum(axis=1).max() * np.abs(x).max())
+    # field-ordered blocks are the quadrants of the permuted dense matrix
+    Pm = _perm_point_to_field(c.N)
+    F = Pm @ D @ Pm.T
+    N = c.N
+    for (a, b) in [(0, 0), (0, 1), (1, 0), (1, 1)]:
+        np.testing.assert_array_equal(blocks.block(rp, ci, v, a, b).toarray(),
+                                      F[a * N:(a + 1) * N, b * N:(b + 1) * N])
+
+
+def test_schur_matches_dense():
+    c, rp, ci, v = _small(7, 6, 5, seed=5)
+    App, Aps, Asp, Ass = (blocks.block(rp, ci, v, a, b) for a, b in [(0, 0), (0, 1), (1, 0), (1, 1)])
+    S = blocks.schur_simple(App, Aps, Asp, Ass).toarray()
+    Sd = App.toarray() - Aps.toarray() @ np.diag(1.0 / Ass.diagonal()) @ Asp.toarray()
+    np.testing.assert_allclose(S, Sd, rtol=0, atol=1e-13 * np.abs(Sd).max())
+    # symbolic pattern: 7-point o 7-point = 25 offsets in the interior of a 3D grid
+    Sc = blocks.schur_simple(App, Aps, Asp, Ass)
+    assert np.diff(Sc.indptr).max() == 25
+
+
+def test_schur_closed_form_total_mobility():
+    """Uniform state, P_d = 0, no wells: A_ps = -phi V/dt I, A_ss = phi V/dt I,
+    so S~ = A_pp + A_sp = the total-mobility TPFA operator."""
+    c = inputs.config_c1().replace(pd=0.0, q=np.zeros((1024, 2)),
+                                   prod_cells=np.zeros(0, np.int32), prod_wi=np.zeros(0),
+                                   prod_pbh=np.zeros(0))
+    rp, ci, v = tpfa.jacobian(c, c.u, c.u_old)
+    App, Aps, Asp, Ass = (blocks.block(rp, ci, v, a, b) for a, b in [(0, 0), (0, 1), (1, 0), (1, 1)])
+    np.testing.assert_array_equal(Ass.toarray(), np.diag(c.poro / c.dt))
+    S = blocks.schur_simple(App, Aps, Asp, Ass).toarray()
+    # total mobility operator built independently: sum over faces T (lw+ln) (e_l-e_h)(e_l-e_h)^T
+    sf = tpfa.sat_functions(c, c.u[:, 1])
+    lt = sf["lw"][0] + sf["ln"][0]
+    fl, fh, fd = tpfa.faces(c)
+    T = tpfa.transmissibility(c, fl, fh, fd)
+    B = sp.csr_matrix((np.concatenate([np.ones(len(fl)), -np.ones(len(fl))]),
+                       (np.concatenate([np.arange(len(fl))] * 2), np.concatenate([fl, fh]))),
+                      shape=(len(fl), c.N))
+    L = (B.T @ sp.diags(T * lt) @ B).toarray()
+    np.testing.assert_allclose(S, L, rtol=0, atol=1e-13 * np.abs(L).max())
+
+
+# ----------------------------------------------------------------- AMG
+
+
+def _laplace2d(n, eps=1.0):
+    def d2(m):
+        return sp.diags([-np.ones(m - 1), 2 * np.ones(m), -np.ones(m - 1)], [-1, 0, 1])
+    return (sp.kron(sp.identity(n), d2(n)) + eps * sp.kron(d2(n), sp.identity(n))).tocsr()
+
+
+def test_strength_closed_forms():
+    """Isotropic Laplacian: every neighbour is strong.  Anisotropic with
+    y-coupling eps < theta: only the x-neighbours are strong."""
+    A = _laplace2d(6)
+    m = amg.strength(A, 0.25)
+    rows = amg.row_index(A)
+    assert np.array_equal(m, A.indices != rows)
+    B = _laplace2d(6, eps=0.1)
+    mb = amg.strength(B, 0.25)
+    xnb = np.abs(B.indices - rows) == 1
+    assert np.array_equal(mb, xnb)
+
+
+def test_pmis_invariants_and_determinism():
+    """Every point is C or F; an F point that strongly influences someone has a
+    C point among its strong dependencies; a C point i with a strong C
+    dependency j was chosen in an earlier round, so (w_i, i) > (w_j, j); for a
+    symmetric strength graph the C points are independent.  Re-running gives
+    identical bits."""
+    c, rp, ci, v = _small(12, 10, 3, seed=2)
+    S = blocks.schur_simple(*(blocks.block(rp, ci, v, a, b) for a, b in [(0, 0), (0, 1), (1, 0), (1, 1)]))
+    mask = amg.strength(S, 0.25)
+    cf, rounds = amg.pmis(S, mask, 17)
+    cf2, _ = amg.pmis(S, mask, 17)
+    assert np.array_equal(cf, cf2)
+    assert set(np.unique(cf)) <= {amg.C_PT, amg.F_PT}
+    Sm = amg.strength_matrix(S, mask)
+    nst = np.diff(Sm.T.tocsr().indptr)
+    w = nst + amg.pmis_random(S.shape[0], 17)
+    srows = amg.row_index(Sm)
+    isc = cf == amg.C_PT
+    cc = isc[srows] & isc[Sm.indices]
+    i, j = srows[cc], Sm.indices[cc]
+    assert np.all((w[i] > w[j]) | ((w[i] == w[j]) & (i > j)))
+    has_c = np.zeros(S.shape[0], bool)
+    has_c[srows[isc[Sm.indices]]] = True
+    assert np.all(has_c[(cf == amg.F_PT) & (nst > 0)])
+    # symmetric strength graph (constant-coefficient Laplacian): independent set
+    App = _laplace2d(11)
+    App.sort_indices()
+    m2 = amg.strength(App, 0.25)
+    cf3, _ = amg.pmis(App, m2, 5)
+    S2 = amg.strength_matrix(App, m2)
+    r2 = amg.row_index(S2)
+    isc3 = cf3 == amg.C_PT
+    assert not np.any(isc3[r2] & isc3[S2.indices])
+
+
+def test_splitmix64_published_value():
+    """SplitMix64 from state 0: first output 0xE220A8397B1DCDAF (the
+    published reference sequence of the generator)."""
+    assert amg.splitmix64(0) == 0xE220A8397B1DCDAF
+    assert int(amg.splitmix64_vec(np.array([0], np.uint64))[0]) == 0xE220A8397B1DCDAF
+
+
+def test_direct_interpolation_closed_forms():
+    """1D Laplacian, alternating C/F: linear interpolation (1/2, 1/2).
+    Zero-row-sum rows: P reproduces constants."""
+    n = 9
+    A = sp.diags([-np.ones(n - 1), 2 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1]).tocsr()
+    mask = amg.strength(A, 0.25)
+    cf = np.where(np.arange(n) % 2 == 0, amg.C_PT, amg.F_PT).astype(np.int8)
+    P, _ = amg.direct_interpolation(A, mask, cf)
+    Pd = P.toarray()
+    for i in range(1, n, 2):
+        np.testing.assert_allclose(Pd[i, [i // 2, i // 2 + 1]], [0.5, 0.5], rtol=1e-15)
+    # 2D Neumann Laplacian (zero row sums everywhere)
+    L = _laplace2d(8).tolil()
+    L = sp.csr_matrix(L)
+    L = L - sp.diags(np.asarray(L.sum(axis=1)).ravel())
+    L = L.tocsr(); L.sort_indices()
+    m = amg.strength(L, 0.25)
+    cf, _ = amg.pmis(L, m, 3)
+    P, _ = amg.direct_interpolation(L, m, cf)
+    rs = np.asarray(P.sum(axis=1)).ravel()
+    nonempty = np.diff(P.indptr) > 0
+    np.testing.assert_allclose(rs[nonempty], 1.0, rtol=1e-14)
+
+
+def test_galerkin_matches_dense_and_symmetry():
+    c, rp, ci, v = _small(10, 9, 2, seed=3)
+    App = blocks.block(rp, ci, v, 0, 0)
+    H = amg.Hierarchy(App, coarse_max=20)
+    L0 = H.levels[0]
+    Ac = H.levels[1].A.toarray()
+    dense = L0.P.T.toarray() @ L0.A.toarray() @ L0.P.toarray()
+    np.testing.assert_allclose(Ac, dense, rtol=0, atol=1e-13 * np.abs(dense).max())
+    assert np.allclose(Ac, Ac.T, rtol=0, atol=1e-13 * np.abs(Ac).max())
+
+
+def test_two_level_cycle_matches_dense_formula():
+    """Two levels with exact coarse solve: x = x_pre + D^{-1}(b - A x_pre')...
+    compared with the dense two-grid formula, and iterating it converges to
+    the dense direct solution."""
+    c, rp, ci, v = _small(9, 8, 1, seed=4)
+    App = blocks.block(rp, ci, v, 0, 0)
+    H = amg.Hierarchy(App, coarse_max=40, max_levels=2)
+    assert len(H.levels) == 2 and H.coarse_dense
+    A = App.toarray()
+    L0 = H.levels[0]
+    P = L0.P.toarray()
+    R = P.T
+    Dinv = np.diag(L0.dinv)
+    Ac = R @ A @ P
+    b = inputs.random_vector(A.shape[0], 3)
+    xpre = Dinv @ b
+    x = xpre + P @ np.linalg.solve(Ac, R @ (b - A @ xpre))
+    x = x + Dinv @ (b - A @ x)
+    np.testing.assert_allclose(H.vcycle(b), x, rtol=0, atol=1e-13 * np.abs(x).max())
+    # coarse-grid correction is a projector
+    Q = P @ np.linalg.solve(Ac, R @ A)
+    np.testing.assert_allclose(Q @ Q, Q, atol=1e-12)
+    # stationary iteration with the two-grid cycle converges to the direct solve
+    xe = np.linalg.solve(A, b)
+    xk = np.zeros_like(b)
+    for _ in range(200):
+        xk = xk + H.vcycle(b - A @ xk)
+    np.testing.assert_allclose(xk, xe, rtol=0, atol=1e-12 * np.abs(xe).max())
+
+
+def test_vcycle_symmetric_for_symmetric_matrix():
+    c, rp, ci, v = _small(10, 8, 2, seed=6)
+    App = blocks.block(rp, ci, v, 0, 0)
+    H = amg.Hierarchy(App, coarse_max=15)
+    assert len(H.levels) >= 3
+    n = App.shape[0]
+    M = np.column_stack([H.vcycle(e) for e in np.eye(n)])
+    np.testing.assert_allclose(M, M.T, rtol=0, atol=1e-12 * np.abs(M).max())
+
+
+def test_single_level_is_exact():
+    """n <= coarse_max: one level, dense LU -> AMG-GMRES converges in 1 step."""
+    c, rp, ci, v = _small(5, 4, 2, seed=7)
+    Js = blocks.scalarize(rp, ci, v)
+    H = amg.Hierarchy(Js, coarse_max=256)
+    assert len(H.levels) == 1
+    b = inputs.random_vector(Js.shape[0], 1)
+    x, info = fgmres.fgmres(lambda z: Js @ z, H.vcycle, b, rtol=1e-10)
+    assert info["status"] == fgmres.CONVERGED and info["iterations"] == 1
+
+
+# ----------------------------------------------------------------- ILU(0)
+
+
+def test_bilu0_generic_reproduces_pattern_and_matches_pivot_form():
+    c, rp, ci, v = _small(5, 4, 3, seed=8)
+    lu = ilu.bilu0_generic(rp, ci, v)
+    N = c.N
+    L = np.eye(2 * N)
+    U = np.zeros((2 * N, 2 * N))
+    for i in range(N):
+        for e in range(rp[i], rp[i + 1]):
+            j = ci[e]
+            blk = lu[e]
+            if j < i:
+                L[2 * i:2 * i + 2, 2 * j:2 * j + 2] = blk
+            else:
+                U[2 * i:2 * i + 2, 2 * j:2 * j + 2] = blk
+    LU = L @ U
+    D = tpfa.bcsr_to_dense(rp, ci, v)
+    pat = np.kron((np.abs(D).reshape(N, 2, N, 2).sum(axis=(1, 3)) > 0) | np.eye(N, dtype=bool),
+                  np.ones((2, 2), bool))
+    blockpat = np.zeros((N, N), bool)
+    for i in range(N):
+        blockpat[i, ci[rp[i]:rp[i + 1]]] = True
+    pat = np.kron(blockpat, np.ones((2, 2), bool))
+    np.testing.assert_allclose(LU[pat], D[pat], rtol=0, atol=1e-12 * np.abs(D).max())
+    # pivot (DILU) form gives the same preconditioner
+    B = ilu.Bilu0(rp, ci, v, c.nx, c.ny, c.nz)
+    r = inputs.random_vector(2 * N, 2)
+    z1 = ilu.generic_apply(rp, ci, lu, r)
+    z2 = B.apply(r)
+    np.testing.assert_allclose(z2, z1, rtol=0, atol=1e-12 * np.abs(z1).max())
+    # scalar ILU(0) on the point-ordered matrix is the same factorisation
+    Ls, Us = ilu.ilu0_scalar(blocks.scalarize(rp, ci, v))
+    zs = np.linalg.solve(Us, np.linalg.solve(Ls, r))
+    np.testing.assert_allclose(zs, z1, rtol=0, atol=1e-11 * np.abs(z1).max())
+
+
+def test_bilu0_exact_on_1d_grid():
+    c, rp, ci, v = _small(12, 1, 1, seed=9)
+    B = ilu.Bilu0(rp, ci, v, c.nx, c.ny, c.nz)
+    r = inputs.random_vector(2 * c.N, 4)
+    D = tpfa.bcsr_to_dense(rp, ci, v)
+    np.testing.assert_allclose(B.apply(r), np.linalg.solve(D, r), rtol=0, atol=1e-11)
+
+
+# ----------------------------------------------------------- preconditioners
+
+
+def _dense_blocks(rp, ci, v, N):
+    Pm = _perm_point_to_field(N)
+    F = Pm @ tpfa.bcsr_to_dense(rp, ci, v) @ Pm.T
+    return Pm, F[:N, :N], F[:N, N:], F[N:, :N], F[N:, N:]
+
+
+@pytest.mark.parametrize("kind", ["cpr1", "cpr2", "bf"])
+def test_precond_matches_matrix_form(kind):
+    """With exact inner solves, Algorithms 1-3 equal Eqs. m_comb, m_add, m_bf."""
+    c, rp, ci, v = _small(5, 4, 2, seed=10)
+    N = c.N
+    M = precond.Preconditioner(kind, rp, ci, v, (c.nx, c.ny, c.nz), inner="exact")
+    r = inputs.random_vector(2 * N, 5)
+    z = M.apply(r)
+    Pm, App, Aps, Asp, Ass = _dense_blocks(rp, ci, v, N)
+    J = tpfa.bcsr_to_dense(rp, ci, v)
+    I2 = np.eye(2 * N)
+    Rp = np.zeros((N, 2 * N)); Rp[np.arange(N), 2 * np.arange(N)] = 1
+    Rs = np.zeros((N, 2 * N)); Rs[np.arange(N), 2 * np.arange(N) + 1] = 1
+    if kind in ("cpr1", "cpr2"):
+        B = ilu.Bilu0(rp, ci, v, c.nx, c.ny, c.nz)
+        P1inv = np.column_stack([B.apply(e) for e in I2])
+        P1 = np.linalg.inv(P1inv)
+        corr = Rp.T @ np.linalg.inv(App) @ Rp
+        if kind == "cpr2":
+            corr = corr + Rs.T @ np.linalg.inv(Ass) @ Rs
+        Minv = (I2 - corr @ (J - P1)) @ P1inv
+    else:
+        St = App - Aps @ np.diag(1 / np.diag(Ass)) @ Asp
+        Sti = np.linalg.inv(St)
+        Assi = np.linalg.inv(Ass)
+        Mf = np.block([[Sti, -Sti @ Aps @ Assi], [np.zeros((N, N)), Assi]])
+        Minv = Pm.T @ Mf @ Pm
+    ze = Minv @ r
+    # the dense side goes through explicit inverses (cond ~ 1e4 here)
+    np.testing.assert_allclose(z, ze, rtol=0, atol=1e-10 * np.abs(ze).max())
+
+
+def test_exact_block_factorisations_gmres_steps():
+    """Full LDU with exact S -> 1 step; the upper-triangular M with exact S
+    and A_ss -> at most 2 steps; A_sp = 0 -> M = J -> 1 step."""
+    c, rp, ci, v = _small(5, 4, 1, seed=12)
+    N = c.N
+    Pm, App, Aps, Asp, Ass = _dense_blocks(rp, ci, v, N)
+    J = tpfa.bcsr_to_dense(rp, ci, v)
+    b = inputs.random_vector(2 * N, 8)
+    S = App - Aps @ np.linalg.solve(Ass, Asp)
+    I = np.eye(N)
+    Z = np.zeros((N, N))
+    Uf = np.block([[I, Aps @ np.linalg.inv(Ass)], [Z, I]])
+    Df = np.block([[S, Z], [Z, Ass]])
+    Lf = np.block([[I, Z], [np.linalg.solve(Ass, Asp), I]])
+    for Mf, steps in [(Uf @ Df @ Lf, 1), (Uf @ Df, 2)]:
+        Mp = Pm.T @ Mf @ Pm
+        _, info = fgmres.fgmres(lambda z: J @ z, lambda r: np.linalg.solve(Mp, r), b, rtol=1e-10)
+        assert info["status"] == fgmres.CONVERGED and info["iterations"] <= steps, (steps, info)
+    # A_sp = 0: S_n below the residual saturation everywhere (k_rn = 0)
+    c0 = inputs.small_case(5, 4, 1, seed=12)
+    u = c0.u.copy(); u[:, 1] = 0.05
+    c0 = c0.replace(u=u, u_old=u.copy())
+    rp0, ci0, v0 = tpfa.jacobian(c0, c0.u, c0.u_old)
+    assert np.all(v0[:, 1, 0] == 0)
+    J0 = tpfa.bcsr_to_dense(rp0, ci0, v0)
+    M0 = precond.Preconditioner("bf", rp0, ci0, v0, (5, 4, 1), inner="exact")
+    _, info = fgmres.fgmres(lambda z: J0 @ z, M0.apply, b, rtol=1e-10)
+    assert info["status"] == fgmres.CONVERGED and info["iterations"] == 1
+
+
+@pytest.mark.parametrize("kind", ["cpr1", "cpr2"])
+def test_cpr_exact_on_1d_grid_with_vcycle(kind):
+    c, rp, ci, v = _small(40, 1, 1, seed=13)
+    M = precond.Preconditioner(kind, rp, ci, v, (40, 1, 1), amg_opts=dict(coarse_max=8))
+    J = tpfa.bcsr_to_dense(rp, ci, v)
+    b = inputs.random_vector(80, 9)
+    _, info = fgmres.fgmres(lambda z: J @ z, M.apply, b, rtol=1e-10)
+    assert info["status"] == fgmres.CONVERGED and info["iterations"] == 1
+
+
+# ----------------------------------------------------------------- FGMRES
+
+
+def test_fgmres_first_cycle_is_least_squares_minimiser():
+    c, rp, ci, v = _small(5, 4, 2, seed=14)
+    J = tpfa.bcsr_to_dense(rp, ci, v)
+    M = precond.Preconditioner("bf", rp, ci, v, (5, 4, 2))
+    Minv = np.column_stack([M.apply(e) for e in np.eye(2 * c.N)])
+    b = inputs.random_vector(2 * c.N, 10)
+    A = J @ Minv
+    for k in range(1, 8):
+        x, info = fgmres.fgmres(lambda z: J @ z, lambda r: Minv @ r, b, rtol=1e-30, maxit=k)
+        K = np.column_stack([np.linalg.matrix_power(A, i) @ b for i in range(k)])
+        Q, _ = np.linalg.qr(K)
+        y, *_ = np.linalg.lstsq(A @ Q, b, rcond=None)
+        xe = Minv @ (Q @ y)
+        assert info["iterations"] == k
+        np.testing.assert_allclose(x, xe, rtol=0, atol=1e-10 * np.abs(xe).max())
+
+
+def test_fgmres_exact_preconditioner_and_small_n():
+    c, rp, ci, v = _small(3, 3, 1, seed=15)
+    J = tpfa.bcsr_to_dense(rp, ci, v)
+    b = inputs.random_vector(18, 11)
+    _, info = fgmres.fgmres(lambda z: J @ z, lambda r: np.linalg.solve(J, r), b)
+    assert info["iterations"] == 1 and info["status"] == fgmres.CONVERGED
+    _, info = fgmres.fgmres(lambda z: J @ z, lambda r: r, b, rtol=1e-10)
+    assert info["status"] == fgmres.CONVERGED and info["iterations"] <= 18
+    x, info = fgmres.fgmres(lambda z: J @ z, lambda r: r, np.zeros(18))
+    assert info["iterations"] == 0 and np.all(x == 0)
+
+
+# ----------------------------------------------------------------- full solves
+
+
+@pytest.mark.parametrize("pd", [0.0, 0.1, 1.0])
+def test_bf_converges_across_capillarity(pd):
+    """Trend check only (iteration counts are not pinned by the paper)."""
+    c = inputs.workload_2d_corner(48, 48, 2.0, 8.0, pd, 50.0, 2)
+    _, info, _ = newton.solve(c, "bf")
+    assert info["status"] == fgmres.CONVERGED and info["relres"] <= 1e-8
