@@ -1,0 +1,249 @@
+/*
+ * tpf.h -- C ABI of the MI355X (gfx950) solver library for the Newton
+ * Jacobian of fully implicit two-phase porous-media flow.
+ *
+ * Method: Bui, Elman, Moulton, "Algebraic Multigrid Preconditioners for
+ * Multiphase Flow in Porous Media" (arXiv 1611.00127).
+ *   - Sec. 2: cell-centred finite volumes, two-point flux approximation with
+ *     phase upwinding and harmonic face permeability, backward Euler
+ *     (Eq. fully_discrete_system); unknowns (P_w, S_n) per cell.
+ *   - Sec. 3: Newton's method, J(u_k) delta = -F(u_k); the 2x2 block Jacobian
+ *     (Eq. jacobian) solved by right-preconditioned GMRES (Eq. precon-system).
+ *   - Sec. 3.2-3.4: black-box AMG, CPR-AMG(1)/(2) (Algorithms 1-2, Eqs. m_comb,
+ *     m_add), block factorisation with the approximate Schur complement
+ *     (Algorithm 3, Eqs. SIMPLE-Schur, m_bf).
+ *
+ * Conventions
+ *   - Every function returns an int status (TPF_OK or a negative code);
+ *     tpf_last_error() gives a message for the calling thread.
+ *   - Vectors of unknowns are device FP64 arrays of length 2N in point order:
+ *     element 2i is P_w of cell i, element 2i+1 is S_n of cell i.  Cell index
+ *     i = ix + nx*(iy + ny*iz).  They are owned by the caller.
+ *   - Handles are owned by the library and released with the matching
+ *     *_destroy call; their device memory comes from the allocator installed
+ *     with tpf_set_allocator (hipMalloc/hipFree if none).
+ *   - All device work is ordered on the hipStream_t passed as `stream`
+ *     (NULL = the null stream).  Only tpf_solve, the setup of a
+ *     preconditioner (which reads level sizes back) and tpf_kernel_stats
+ *     synchronise the stream.
+ *   - Handles are not thread safe.
+ */
+#ifndef TPF_H
+#define TPF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define TPF_OK 0
+#define TPF_ERR_INVALID_ARG (-1)
+#define TPF_ERR_OOM (-2)
+#define TPF_ERR_HIP (-3)
+#define TPF_ERR_SINGULAR (-4)        /* zero ILU pivot block or singular coarsest matrix */
+#define TPF_ERR_OVER_BUDGET (-5)
+#define TPF_ERR_NOT_IMPLEMENTED (-6)
+#define TPF_ERR_STATE (-7)           /* call out of order (e.g. apply before setup) */
+
+/* Message for a status code (static storage). */
+const char* tpf_status_string(int status);
+/* Copies the calling thread's last error message into buf (NUL terminated);
+ * returns the status of the failed call. */
+int tpf_last_error(char* buf, size_t n);
+
+/* ---- memory ------------------------------------------------------------ */
+typedef void* (*tpf_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*tpf_free_fn)(void* ptr, void* stream, void* ctx);
+/* Installs the device allocator used for all library memory (e.g. a caching
+ * allocator of the host framework).  Pass NULLs to return to hipMalloc.
+ * Must not change while handles allocated with the previous one live. */
+int tpf_set_allocator(tpf_alloc_fn alloc, tpf_free_fn free_fn, void* ctx);
+/* Bytes currently held by the library through the allocator. */
+int tpf_memory_in_use(size_t* bytes);
+
+/* ---- problem (Sec. 2) -------------------------------------------------- */
+#define TPF_PC_BROOKS_COREY 0 /* P_c = P_d Sb^(-1/lambda), C1-linear below s_eps */
+#define TPF_PC_LINEAR 1       /* P_c = P_0 (1 - Sb); P_0 given in field pd */
+
+typedef struct tpf_problem_desc {
+  int nx, ny, nz;             /* cells per direction; nz = 1 for 2D */
+  double hx, hy, hz;          /* cell sizes */
+  const double* kx;           /* device, N: permeability per direction */
+  const double* ky;
+  const double* kz;
+  const double* poro;         /* device, N */
+  double mu_w, mu_n;          /* viscosities */
+  double rho_w, rho_n, grav;  /* densities and gravity (potential P - rho g z, z = depth) */
+  int pc_model;               /* TPF_PC_* */
+  double bc_lambda;           /* Brooks-Corey lambda (also sets the Burdine relperm exponents) */
+  double swr, snr;            /* residual saturations */
+  double pd;                  /* entry pressure P_d (Brooks-Corey) or P_0 (linear) */
+  double s_eps;               /* effective saturation below which P_c is continued linearly */
+  const double* q;            /* device, 2N constant source rates (q_w, q_n), or NULL */
+  int n_prod;                 /* bottom-hole-pressure producers, at most one per cell */
+  const int* prod_cells;      /* host arrays of length n_prod */
+  const double* prod_wi;      /* well index: q_a = -WI lambda_a(S) (P_w - p_bh) */
+  const double* prod_pbh;
+  int n_dir;                  /* Dirichlet boundary faces */
+  const int* dir_cells;       /* host arrays of length n_dir */
+  const int* dir_face;        /* 0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z (must be a domain face) */
+  const double* dir_p;        /* boundary P_w and S_n at the face centre */
+  const double* dir_s;
+} tpf_problem_desc;
+
+typedef struct tpf_problem tpf_problem;
+typedef struct tpf_jacobian tpf_jacobian;
+
+/* Copies the description (device fields are copied, not referenced) and
+ * computes the face transmissibilities T = gamma K_harm / h (Sec. 2, TPFA
+ * and harmonic averaging). */
+int tpf_problem_create(const tpf_problem_desc* d, void* stream, tpf_problem** out);
+int tpf_problem_destroy(tpf_problem* p);
+/* Number of cells N. */
+int tpf_problem_cells(const tpf_problem* p, int64_t* n_cells);
+
+/* Block-CSR (2x2 blocks) container for J with the static pattern of the
+ * grid: block row i holds its face neighbours and itself, block columns
+ * ascending (-z,-y,-x,self,+x,+y,+z).  Values are written by tpf_assemble. */
+int tpf_jacobian_create(tpf_problem* p, void* stream, tpf_jacobian** out);
+int tpf_jacobian_destroy(tpf_jacobian* J);
+
+/* Residual and exact Jacobian at state u (Sec. 3: Newton linearisation of
+ * Eq. fully_discrete_system, upwind choice frozen).  u, u_old, residual:
+ * device, 2N.  residual may be NULL.  J's values (row-major 2x2 blocks,
+ * entry [a][b] = dR_a/du_b) are overwritten. */
+int tpf_assemble(tpf_problem* p, const double* u, const double* u_old, double dt,
+                 double* residual, tpf_jacobian* J, void* stream);
+
+typedef struct tpf_bcsr_view {
+  int n_block_rows;
+  int64_t nnzb;
+  const int* row_ptr;   /* device, n_block_rows + 1 */
+  const int* col_idx;   /* device, nnzb */
+  const double* vals;   /* device, 4 * nnzb, row-major 2x2 blocks */
+} tpf_bcsr_view;
+/* Read-only device view of J (valid until J is destroyed). */
+int tpf_jacobian_view(const tpf_jacobian* J, tpf_bcsr_view* out);
+
+/* y = J x (x, y device 2N). */
+int tpf_spmv(const tpf_jacobian* J, const double* x, double* y, void* stream);
+/* Newton update u += delta with S_n clamped to [0,1] (device 2N). */
+int tpf_newton_update(tpf_problem* p, double* u, const double* delta, void* stream);
+
+/* ---- preconditioners (Sec. 3.2-3.4) ------------------------------------ */
+#define TPF_PREC_AMG 0   /* one V-cycle on the point-ordered scalar J (Sec. 3.2) */
+#define TPF_PREC_CPR1 1  /* Algorithm 1 (combinative), block ILU(0) + V-cycle on A_pp */
+#define TPF_PREC_CPR2 2  /* Algorithm 2 (additive), + V-cycle on A_ss */
+#define TPF_PREC_BF 3    /* Algorithm 3, V-cycles on A_ss and on S~ */
+#define TPF_PREC_NONE 4  /* identity (tests) */
+
+#define TPF_FP64 0       /* hierarchy and V-cycle in FP64 */
+#define TPF_FP32 1       /* hierarchy stored and V-cycle/ILU solves run in FP32; coarsest in FP64 */
+
+typedef struct tpf_precond_opts {
+  int kind;             /* TPF_PREC_* */
+  int precision;        /* TPF_FP64 / TPF_FP32 */
+  double theta;         /* strength threshold (0.25) */
+  int max_levels;       /* 25; 1 gives an exact dense solve when n <= dense_max */
+  int coarse_max;       /* stop coarsening at n <= coarse_max (256) */
+  int dense_max;        /* dense LU on the coarsest level if n <= dense_max (1024),
+                           else two l1-Jacobi sweeps */
+  uint64_t hash_seed;   /* seed of the PMIS tie-break weights */
+} tpf_precond_opts;
+/* Fills opts with the defaults above for the given kind. */
+int tpf_precond_default_opts(int kind, tpf_precond_opts* opts);
+
+typedef struct tpf_precond tpf_precond;
+int tpf_precond_create(const tpf_precond_opts* o, tpf_precond** out);
+int tpf_precond_destroy(tpf_precond* M);
+/* Builds the preconditioner for J: block views, S~, BILU(0) pivots and the
+ * AMG hierarchies.  reuse_structure = 1 keeps the C/F splittings, P and R of
+ * the previous setup on a J with the same pattern and recomputes every
+ * numeric quantity (blocks, S~, Galerkin products, smoother diagonals,
+ * coarsest inverse, ILU pivots).  Synchronises the stream. */
+int tpf_precond_setup(tpf_precond* M, const tpf_jacobian* J, int reuse_structure, void* stream);
+/* z = M^{-1} r (device 2N). */
+int tpf_precond_apply(tpf_precond* M, const double* r, double* z, void* stream);
+
+#define TPF_MAX_LEVELS 25
+typedef struct tpf_hier_stats {
+  int n_hier;                          /* AMG:1 (J), CPR1:1 (A_pp), CPR2:2 (A_pp,A_ss), BF:2 (A_ss,S~) */
+  int levels[3];
+  int64_t rows[3][TPF_MAX_LEVELS];
+  int64_t nnz[3][TPF_MAX_LEVELS];
+  double operator_complexity[3];
+  double grid_complexity[3];
+  int coarse_dense[3];
+  size_t device_bytes;                 /* bytes held by the preconditioner */
+} tpf_hier_stats;
+int tpf_precond_stats(const tpf_precond* M, tpf_hier_stats* out);
+
+/* ---- introspection for parity checks ----------------------------------- */
+typedef struct tpf_csr_view {
+  int n_rows, n_cols;
+  int64_t nnz;
+  const int* row_ptr;     /* device */
+  const int* col_idx;     /* device */
+  const double* vals;     /* device FP64 values (NULL for pattern-only) */
+} tpf_csr_view;
+#define TPF_MAT_A 0       /* level operator */
+#define TPF_MAT_P 1       /* interpolation (level -> level+1) */
+#define TPF_MAT_R 2       /* restriction P^T */
+#define TPF_MAT_S 3       /* strength graph (pattern only) */
+#define TPF_MAT_APS 10    /* A_ps block (level ignored) */
+#define TPF_MAT_SCHUR 11  /* S~ (BF) */
+/* View of matrix `which` of hierarchy `hier` at `level` (FP64 copy). */
+int tpf_precond_matrix(const tpf_precond* M, int hier, int level, int which, tpf_csr_view* out);
+/* C/F splitting of a level (device int8, 1 = C, 2 = F) and the l1-Jacobi
+ * inverse diagonal (device FP64). */
+int tpf_precond_level_data(const tpf_precond* M, int hier, int level, const int8_t** cf,
+                           const double** dinv, int* n);
+/* Inverse pivot blocks of block ILU(0) (device, 4N, row-major 2x2). */
+int tpf_precond_bilu_dinv(const tpf_precond* M, const double** dinv);
+/* One V-cycle of hierarchy `hier` on b (device FP64, level-0 size). */
+int tpf_precond_vcycle(tpf_precond* M, int hier, const double* b, double* x, void* stream);
+
+/* ---- Krylov solve (Sec. 3, Eq. precon-system) -------------------------- */
+#define TPF_CONVERGED 0
+#define TPF_MAX_ITERS 1
+#define TPF_BREAKDOWN 2
+#define TPF_NONFINITE 3
+
+typedef struct tpf_solve_opts {
+  double rtol;   /* stop when ||b - J x|| <= rtol ||b|| (1e-8) */
+  int restart;   /* Krylov dimension m (30), at most 64 */
+  int maxit;     /* total Arnoldi steps (1000) */
+} tpf_solve_opts;
+
+typedef struct tpf_solve_info {
+  int status;            /* TPF_CONVERGED, TPF_MAX_ITERS, TPF_BREAKDOWN, TPF_NONFINITE */
+  int iterations;        /* Arnoldi steps */
+  double relres_est;     /* |g_{j+1}| / ||b|| at the last step */
+  double relres_true;    /* ||b - J x|| / ||b|| at exit */
+  double ms;             /* wall time of the solve */
+} tpf_solve_info;
+
+/* Right-preconditioned flexible GMRES(m) with CGS2 Arnoldi and Givens
+ * rotations, x_0 = 0; x is overwritten (device 2N).  M may be NULL
+ * (identity).  Non-convergence is reported in info->status, not as an
+ * error.  Synchronises the stream. */
+int tpf_solve(const tpf_jacobian* J, tpf_precond* M, const double* b, double* x,
+              const tpf_solve_opts* o, tpf_solve_info* info, void* stream);
+
+/* ---- kernel timing ----------------------------------------------------- */
+/* When enabled, the launches of the main kernels are bracketed by HIP events
+ * on their stream; tpf_kernel_stats returns the launch count and the summed
+ * event time of every launch of the named kernel since the last reset
+ * (synchronises).  Names: "vcycle_smooth_residual", "vcycle_post_smooth",
+ * "csr_spmv", "bcsr_spmv", "assemble", "cgs2_dots", ... */
+int tpf_kernel_timing(int enable);
+int tpf_kernel_stats(const char* name, int64_t* count, double* total_ms);
+int tpf_kernel_stats_reset(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TPF_H */

@@ -237,3 +237,23 @@ class Hierarchy:
         nnz = [L.A.nnz for L in self.levels]
         return dict(levels=len(rows), rows=rows, nnz=nnz,
                     operator_complexity=sum(nnz) / nnz[0], grid_complexity=sum(rows) / rows[0])
+
+
+def hierarchy_from_levels(As, Ps, dense_max=1024):
+    """An oracle Hierarchy holding given level operators and interpolations
+    (used to apply the oracle's V-cycle to matrices produced elsewhere)."""
+    H = Hierarchy.__new__(Hierarchy)
+    H.levels = []
+    H.dense_max = dense_max
+    for l, A in enumerate(As):
+        L = Level(A)
+        if l < len(Ps):
+            L.P = Ps[l].tocsr()
+            L.R = L.P.T.tocsr()
+            L.R.sort_indices()
+        H.levels.append(L)
+    last = H.levels[-1]
+    H.coarse_dense = last.n <= dense_max
+    if H.coarse_dense:
+        H.lu = sla.lu_factor(last.A.toarray())
+    return H

@@ -1,0 +1,598 @@
+// Classical AMG on the device: strength of connection, PMIS coarsening,
+// direct interpolation, Galerkin coarse operators, dense coarsest inverse,
+// and the V(1,1) cycle with l1-Jacobi smoothing.  The paper applies one
+// AMG V-cycle per inner solve (Sec. 3.2-3.4; solver settings in Sec. 4.1)
+// using BoomerAMG; the components here are data-parallel replacements whose
+// definitions are:
+//   strength  s_i = sign(a_ii) (+1 if a_ii >= 0), m_i = max_{k!=i} -s_i a_ik,
+//             j strong for i iff m_i > 0 and -s_i a_ij >= theta m_i;
+//   PMIS      w_i = |S^T_i| + (splitmix64(seed ^ i) >> 40) 2^-24; |S^T_i| = 0
+//             starts F; per round an undecided i becomes C iff (w_i, i) beats
+//             every undecided j in S_i u S^T_i, then undecided j with a new C
+//             point in S_j become F;
+//   direct interpolation (Stueben): w_ij = -alpha_i a_ij / a~_ii over the
+//             strong C neighbours, alpha_i = sum_{k!=i} a_ik^- / sum_{P_i} a_ik^-,
+//             a~_ii = a_ii + same-signed off-diagonals; C rows inject;
+//   Galerkin  A_c = R (A P), R = P^T, symbolic pattern;
+//   smoother  l1-Jacobi d_i = a_ii + s_i sum_{j!=i} |a_ij|.
+#include <cmath>
+#include <type_traits>
+
+#include "amg.hpp"
+#include "linalg_dev.hpp"
+
+namespace tpf {
+
+namespace {
+constexpr int8_t kUndecided = 0, kC = 1, kF = 2;
+
+__device__ inline uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ inline double row_diag(int i, int a0, int a1, const int* ci, const double* v) {
+  for (int e = a0; e < a1; ++e)
+    if (ci[e] == i) return v[e];
+  return 0.0;
+}
+
+__global__ void k_l1_dinv(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                          const double* __restrict__ v, double* __restrict__ dinv) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int a0 = rp[i], a1 = rp[i + 1];
+  double aii = row_diag(i, a0, a1, ci, v);
+  double s = aii < 0.0 ? -1.0 : 1.0;
+  double off = 0.0;
+  for (int e = a0; e < a1; ++e)
+    if (ci[e] != i) off += fabs(v[e]);
+  double d = aii + s * off;
+  dinv[i] = d != 0.0 ? 1.0 / d : 0.0;
+}
+
+__global__ void k_strength(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                           const double* __restrict__ v, double theta, uint8_t* __restrict__ mask,
+                           int* __restrict__ cnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int a0 = rp[i], a1 = rp[i + 1];
+  double aii = row_diag(i, a0, a1, ci, v);
+  double s = aii < 0.0 ? -1.0 : 1.0;
+  double m = -INFINITY;
+  for (int e = a0; e < a1; ++e)
+    if (ci[e] != i) {
+      double t = -s * v[e];
+      m = t > m ? t : m;
+    }
+  int c = 0;
+  double thr = theta * m;
+  for (int e = a0; e < a1; ++e) {
+    bool st = ci[e] != i && m > 0.0 && (-s * v[e]) >= thr;
+    mask[e] = st;
+    c += st;
+  }
+  cnt[i] = c;
+}
+
+__global__ void k_compact_pattern(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                  const uint8_t* __restrict__ mask, const int* __restrict__ srp,
+                                  int* __restrict__ sci) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int o = srp[i];
+  for (int e = rp[i]; e < rp[i + 1]; ++e)
+    if (mask[e]) sci[o++] = ci[e];
+}
+
+__global__ void k_pmis_init(int n, uint64_t seed, const int* __restrict__ strp,
+                            double* __restrict__ w, int8_t* __restrict__ state) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int nst = strp[i + 1] - strp[i];
+  uint64_t z = splitmix64(seed ^ uint64_t(i));
+  double u = double(z >> 40) * 0x1p-24;
+  w[i] = double(nst) + u;
+  state[i] = nst == 0 ? kF : kUndecided;
+}
+
+__device__ inline bool beats(double wj, int j, double wi, int i) {
+  return wj > wi || (wj == wi && j > i);
+}
+
+__global__ void k_pmis_select(int n, const int* __restrict__ srp, const int* __restrict__ sci,
+                              const int* __restrict__ strp, const int* __restrict__ stci,
+                              const double* __restrict__ w, const int8_t* __restrict__ state,
+                              uint8_t* __restrict__ newc) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (state[i] != kUndecided) {
+    newc[i] = 0;
+    return;
+  }
+  double wi = w[i];
+  bool sel = true;
+  for (int e = srp[i]; e < srp[i + 1] && sel; ++e) {
+    int j = sci[e];
+    if (state[j] == kUndecided && beats(w[j], j, wi, i)) sel = false;
+  }
+  for (int e = strp[i]; e < strp[i + 1] && sel; ++e) {
+    int j = stci[e];
+    if (state[j] == kUndecided && beats(w[j], j, wi, i)) sel = false;
+  }
+  newc[i] = sel;
+}
+
+__global__ void k_pmis_update(int n, const int* __restrict__ srp, const int* __restrict__ sci,
+                              const uint8_t* __restrict__ newc, int8_t* __restrict__ state,
+                              int* __restrict__ undecided) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  bool und = false;
+  if (i < n && state[i] == kUndecided) {
+    if (newc[i]) {
+      state[i] = kC;
+    } else {
+      bool f = false;
+      for (int e = srp[i]; e < srp[i + 1]; ++e)
+        if (newc[sci[e]]) {
+          f = true;
+          break;
+        }
+      if (f)
+        state[i] = kF;
+      else
+        und = true;
+    }
+  }
+  unsigned long long b = __ballot(und);
+  if ((threadIdx.x & 63) == 0 && b) atomicAdd(undecided, int(__popcll(b)));
+}
+
+__global__ void k_is_c(int n, const int8_t* __restrict__ cf, int* __restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = cf[i] == kC;
+}
+
+__global__ void k_interp_count(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                               const uint8_t* __restrict__ mask, const int8_t* __restrict__ cf,
+                               int* __restrict__ cnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (cf[i] == kC) {
+    cnt[i] = 1;
+    return;
+  }
+  int c = 0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) c += mask[e] && cf[ci[e]] == kC;
+  cnt[i] = c;
+}
+
+__global__ void k_interp_fill(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                              const double* __restrict__ v, const uint8_t* __restrict__ mask,
+                              const int8_t* __restrict__ cf, const int* __restrict__ cidx,
+                              const int* __restrict__ prp, int* __restrict__ pci,
+                              double* __restrict__ pv) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int o = prp[i];
+  if (cf[i] == kC) {
+    pci[o] = cidx[i];
+    pv[o] = 1.0;
+    return;
+  }
+  int a0 = rp[i], a1 = rp[i + 1];
+  double aii = row_diag(i, a0, a1, ci, v);
+  double s = aii < 0.0 ? -1.0 : 1.0;
+  double sn_opp = 0.0, sn_same = 0.0, sp_opp = 0.0;
+  for (int e = a0; e < a1; ++e) {
+    int j = ci[e];
+    if (j == i) continue;
+    double a = v[e];
+    if (s * a < 0.0) sn_opp += a;
+    else if (s * a > 0.0) sn_same += a;
+  }
+  for (int e = a0; e < a1; ++e)
+    if (mask[e] && cf[ci[e]] == kC) sp_opp += v[e];
+  double atil = aii + sn_same;
+  for (int e = a0; e < a1; ++e) {
+    int j = ci[e];
+    if (mask[e] && cf[j] == kC) {
+      double alpha = sn_opp / sp_opp;
+      pci[o] = cidx[j];
+      pv[o] = -alpha * v[e] / atil;
+      ++o;
+    }
+  }
+}
+
+// dense [A | I] for Gauss-Jordan (row-major, n x 2n)
+__global__ void k_dense_augment(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                const double* __restrict__ v, double* __restrict__ M) {
+  int i = blockIdx.x;
+  for (int c = threadIdx.x; c < 2 * n; c += blockDim.x) M[int64_t(i) * 2 * n + c] = (c - n == i) ? 1.0 : 0.0;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int e = rp[i]; e < rp[i + 1]; ++e) M[int64_t(i) * 2 * n + ci[e]] += v[e];
+}
+
+// Gauss-Jordan elimination with partial pivoting (largest |a|, lowest row on
+// ties) on [A | I] by one work-group; singular -> *flag = 1.
+__global__ void __launch_bounds__(1024) k_gauss_jordan(int n, double* __restrict__ M,
+                                                       double* __restrict__ fac,
+                                                       int* __restrict__ flag) {
+  __shared__ double best_v[1024];
+  __shared__ int best_i[1024];
+  int w = 2 * n;
+  for (int k = 0; k < n; ++k) {
+    double bv = -1.0;
+    int bi = n;
+    for (int r = k + threadIdx.x; r < n; r += blockDim.x) {
+      double a = fabs(M[int64_t(r) * w + k]);
+      if (a > bv || (a == bv && r < bi)) {
+        bv = a;
+        bi = r;
+      }
+    }
+    best_v[threadIdx.x] = bv;
+    best_i[threadIdx.x] = bi;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+      if (threadIdx.x < st) {
+        double ov = best_v[threadIdx.x + st];
+        int oi = best_i[threadIdx.x + st];
+        if (ov > best_v[threadIdx.x] || (ov == best_v[threadIdx.x] && oi < best_i[threadIdx.x])) {
+          best_v[threadIdx.x] = ov;
+          best_i[threadIdx.x] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    int p = best_i[0];
+    double pv = best_v[0];
+    __syncthreads();
+    if (!(pv > 0.0)) {
+      if (threadIdx.x == 0) *flag = 1;
+      return;
+    }
+    if (p != k)
+      for (int c = threadIdx.x; c < w; c += blockDim.x) {
+        double t = M[int64_t(k) * w + c];
+        M[int64_t(k) * w + c] = M[int64_t(p) * w + c];
+        M[int64_t(p) * w + c] = t;
+      }
+    __syncthreads();
+    double piv = M[int64_t(k) * w + k];
+    __syncthreads();
+    for (int c = threadIdx.x; c < w; c += blockDim.x) M[int64_t(k) * w + c] /= piv;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) fac[r] = M[int64_t(r) * w + k];
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < int64_t(n) * w; t += blockDim.x) {
+      int r = int(t / w), c = int(t % w);
+      if (r != k) M[t] -= fac[r] * M[int64_t(k) * w + c];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_dense_extract(int n, const double* __restrict__ M, double* __restrict__ Ainv) {
+  int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= int64_t(n) * n) return;
+  int r = int(t / n), c = int(t % n);
+  Ainv[t] = M[int64_t(r) * 2 * n + n + c];
+}
+
+// ---------------------------------------------------------------- V-cycle kernels
+// r = b - A (D^{-1} b): pre-smoothing from a zero guess fused with the residual
+template <class T, int LPR>
+__global__ void __launch_bounds__(256) k_vc_pre(int n, const int* __restrict__ rp,
+                                                const int* __restrict__ ci,
+                                                const T* __restrict__ v,
+                                                const T* __restrict__ dinv,
+                                                const T* __restrict__ b, T* __restrict__ r) {
+  int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int row = int(gid / LPR), lane = int(gid % LPR);
+  if (row >= n) return;
+  T sum = row_dot<T, LPR>(row, lane, rp, ci, v, [&](int j) { return dinv[j] * b[j]; });
+  if (lane == 0) r[row] = b[row] - sum;
+}
+
+// y = D^{-1} b + P x_c: prolongation added to the pre-smoothed iterate
+template <class T, int LPR>
+__global__ void __launch_bounds__(256) k_vc_prolong(int n, const int* __restrict__ prp,
+                                                    const int* __restrict__ pci,
+                                                    const T* __restrict__ pv,
+                                                    const T* __restrict__ dinv,
+                                                    const T* __restrict__ b,
+                                                    const T* __restrict__ xc, T* __restrict__ y) {
+  int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int row = int(gid / LPR), lane = int(gid % LPR);
+  if (row >= n) return;
+  T sum = row_dot<T, LPR>(row, lane, prp, pci, pv, [&](int c) { return xc[c]; });
+  if (lane == 0) y[row] = dinv[row] * b[row] + sum;
+}
+
+// x = y + D^{-1} (b - A y): post-smoothing
+template <class T, int LPR>
+__global__ void __launch_bounds__(256) k_vc_post(int n, const int* __restrict__ rp,
+                                                 const int* __restrict__ ci,
+                                                 const T* __restrict__ v,
+                                                 const T* __restrict__ dinv,
+                                                 const T* __restrict__ b,
+                                                 const T* __restrict__ y, T* __restrict__ x) {
+  int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int row = int(gid / LPR), lane = int(gid % LPR);
+  if (row >= n) return;
+  T sum = row_dot<T, LPR>(row, lane, rp, ci, v, [&](int j) { return y[j]; });
+  if (lane == 0) x[row] = y[row] + dinv[row] * (b[row] - sum);
+}
+
+// two l1-Jacobi sweeps from zero: x = D^{-1}b + D^{-1}(b - A D^{-1} b)
+template <class T, int LPR>
+__global__ void __launch_bounds__(256) k_vc_two_sweeps(int n, const int* __restrict__ rp,
+                                                       const int* __restrict__ ci,
+                                                       const T* __restrict__ v,
+                                                       const T* __restrict__ dinv,
+                                                       const T* __restrict__ b,
+                                                       T* __restrict__ x) {
+  int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int row = int(gid / LPR), lane = int(gid % LPR);
+  if (row >= n) return;
+  T sum = row_dot<T, LPR>(row, lane, rp, ci, v, [&](int j) { return dinv[j] * b[j]; });
+  if (lane == 0) {
+    T x0 = dinv[row] * b[row];
+    x[row] = x0 + dinv[row] * (b[row] - sum);
+  }
+}
+
+// x = Ainv b in FP64 (one wavefront per row)
+template <class T>
+__global__ void __launch_bounds__(256) k_dense_gemv(int n, const double* __restrict__ Ainv,
+                                                    const T* __restrict__ b, T* __restrict__ x) {
+  int row = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  int lane = threadIdx.x & (kWave - 1);
+  if (row >= n) return;
+  double sum = 0.0;
+  for (int c = lane; c < n; c += kWave) sum += Ainv[int64_t(row) * n + c] * double(b[c]);
+  sum = wave_sum(sum);
+  if (lane == 0) x[row] = T(sum);
+}
+
+template <class T>
+const T* vals_of(const Csr<double>& M, const Buf<float>& v32);
+template <>
+const double* vals_of<double>(const Csr<double>& M, const Buf<float>&) { return M.v.p; }
+template <>
+const float* vals_of<float>(const Csr<double>&, const Buf<float>& v32) { return v32.p; }
+
+template <class T> T* work(Buf<double>& d, Buf<float>& f);
+template <> double* work<double>(Buf<double>& d, Buf<float>&) { return d.p; }
+template <> float* work<float>(Buf<double>&, Buf<float>& f) { return f.p; }
+template <class T> const T* dinv_of(const Level& L);
+template <> const double* dinv_of<double>(const Level& L) { return L.dinv.p; }
+template <> const float* dinv_of<float>(const Level& L) { return L.dinv32.p; }
+
+}  // namespace
+
+// ---------------------------------------------------------------- setup
+void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
+  o = opts;
+  s = st;
+  lv.clear();
+  auto L0 = std::make_unique<Level>();
+  L0->A = std::move(A0);
+  lv.push_back(std::move(L0));
+  while (true) {
+    Level& L = *lv.back();
+    int n = L.A.nrows;
+    if (n <= o.coarse_max || int(lv.size()) >= o.max_levels) break;
+    // strength of connection
+    L.mask.alloc(L.A.nnz > 0 ? L.A.nnz : 1, s);
+    Buf<int> cnt(n, s);
+    k_strength<<<grid_for(n, 256), 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.A.v.p, o.theta, L.mask.p,
+                                                cnt.p);
+    TPF_CHECK_LAUNCH();
+    L.S.nrows = L.S.ncols = n;
+    L.S.rp.alloc(n + 1, s);
+    L.S.nnz = scan_exclusive(cnt.p, L.S.rp.p, n, s);
+    L.S.ci.alloc(L.S.nnz > 0 ? L.S.nnz : 1, s);
+    k_compact_pattern<<<grid_for(n, 256), 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.mask.p, L.S.rp.p,
+                                                       L.S.ci.p);
+    TPF_CHECK_LAUNCH();
+    Csr<double> ST;
+    transpose(CsrRef<double>{n, n, L.S.nnz, L.S.rp.p, L.S.ci.p, nullptr}, ST, s);
+    // PMIS
+    Buf<double> w(n, s);
+    L.cf.alloc(n, s);
+    Buf<uint8_t> newc(n, s);
+    Buf<int> und(1, s);
+    k_pmis_init<<<grid_for(n, 256), 256, 0, s>>>(n, o.seed, ST.rp.p, w.p, L.cf.p);
+    TPF_CHECK_LAUNCH();
+    int rounds = 0;
+    while (true) {
+      fill_int(und.p, 0, 1, s);
+      k_pmis_select<<<grid_for(n, 256), 256, 0, s>>>(n, L.S.rp.p, L.S.ci.p, ST.rp.p, ST.ci.p, w.p,
+                                                     L.cf.p, newc.p);
+      TPF_CHECK_LAUNCH();
+      k_pmis_update<<<grid_for(n, 256), 256, 0, s>>>(n, L.S.rp.p, L.S.ci.p, newc.p, L.cf.p, und.p);
+      TPF_CHECK_LAUNCH();
+      ++rounds;
+      int left = read_scalar(und.p, s);
+      if (left == 0) break;
+      TPF_REQUIRE(rounds <= n + 1, TPF_ERR_INVALID_ARG, "PMIS did not terminate");
+    }
+    L.pmis_rounds = rounds;
+    // coarse numbering
+    Buf<int> isc(n, s), cidx(n + 1, s);
+    k_is_c<<<grid_for(n, 256), 256, 0, s>>>(n, L.cf.p, isc.p);
+    TPF_CHECK_LAUNCH();
+    int64_t nc = scan_exclusive(isc.p, cidx.p, n, s);
+    if (nc == 0 || double(nc) > 0.9 * double(n)) break;
+    // direct interpolation
+    k_interp_count<<<grid_for(n, 256), 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.mask.p, L.cf.p, cnt.p);
+    TPF_CHECK_LAUNCH();
+    L.P.nrows = n;
+    L.P.ncols = int(nc);
+    L.P.rp.alloc(n + 1, s);
+    L.P.nnz = scan_exclusive(cnt.p, L.P.rp.p, n, s);
+    L.P.ci.alloc(L.P.nnz, s);
+    L.P.v.alloc(L.P.nnz, s);
+    k_interp_fill<<<grid_for(n, 256), 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.A.v.p, L.mask.p, L.cf.p,
+                                                   cidx.p, L.P.rp.p, L.P.ci.p, L.P.v.p);
+    TPF_CHECK_LAUNCH();
+    transpose(ref(L.P), L.R, s);
+    // Galerkin product A_c = R (A P)
+    spgemm(ref(L.A), ref(L.P), L.AP, s);
+    auto next = std::make_unique<Level>();
+    spgemm(ref(L.R), ref(L.AP), next->A, s);
+    lv.push_back(std::move(next));
+  }
+  finish_levels(s);
+}
+
+void Hierarchy::refresh(hipStream_t st) {
+  s = st;
+  for (size_t l = 0; l + 1 < lv.size(); ++l) {
+    Level& L = *lv[l];
+    spgemm(ref(L.A), ref(L.P), L.AP, s, nullptr, 1.0, 1.0, true);
+    spgemm(ref(L.R), ref(L.AP), lv[l + 1]->A, s, nullptr, 1.0, 1.0, true);
+  }
+  finish_levels(s);
+}
+
+void Hierarchy::finish_levels(hipStream_t st) {
+  for (auto& Lp : lv) {
+    Level& L = *Lp;
+    int n = L.A.nrows;
+    L.dinv.ensure(n, st);
+    k_l1_dinv<<<grid_for(n, 256), 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, L.A.v.p, L.dinv.p);
+    TPF_CHECK_LAUNCH();
+    L.r.ensure(n, st);
+    L.y.ensure(n, st);
+    if (&L != lv[0].get()) {
+      L.b.ensure(n, st);
+      L.x.ensure(n, st);
+    }
+    if (o.fp32) {
+      L.Av32.ensure(L.A.nnz, st);
+      cast<double, float>(L.Av32.p, L.A.v.p, L.A.nnz, st);
+      L.dinv32.ensure(n, st);
+      cast<double, float>(L.dinv32.p, L.dinv.p, n, st);
+      if (L.P.rp.p) {
+        L.Pv32.ensure(L.P.nnz, st);
+        cast<double, float>(L.Pv32.p, L.P.v.p, L.P.nnz, st);
+        L.Rv32.ensure(L.R.nnz, st);
+        cast<double, float>(L.Rv32.p, L.R.v.p, L.R.nnz, st);
+      }
+      L.r32.ensure(n, st);
+      L.y32.ensure(n, st);
+      if (&L != lv[0].get()) {
+        L.b32.ensure(n, st);
+        L.x32.ensure(n, st);
+      }
+    }
+  }
+  coarse_setup(st);
+}
+
+void Hierarchy::coarse_setup(hipStream_t st) {
+  Level& L = *lv.back();
+  int n = L.A.nrows;
+  coarse_dense = n <= o.dense_max;
+  if (!coarse_dense) {
+    Ainv.release();
+    return;
+  }
+  Buf<double> M(size_t(n) * 2 * n, st), fac(n, st);
+  Buf<int> flag(1, st);
+  fill_int(flag.p, 0, 1, st);
+  k_dense_augment<<<n, 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, L.A.v.p, M.p);
+  TPF_CHECK_LAUNCH();
+  k_gauss_jordan<<<1, 1024, 0, st>>>(n, M.p, fac.p, flag.p);
+  TPF_CHECK_LAUNCH();
+  int f = read_scalar(flag.p, st);
+  TPF_REQUIRE(f == 0, TPF_ERR_SINGULAR, "coarsest AMG matrix (n = %d) is singular", n);
+  Ainv.ensure(size_t(n) * n, st);
+  k_dense_extract<<<grid_for(int64_t(n) * n, 256), 256, 0, st>>>(n, M.p, Ainv.p);
+  TPF_CHECK_LAUNCH();
+  TPF_HIP(hipStreamSynchronize(st));
+}
+
+size_t Hierarchy::bytes() const {
+  size_t b = Ainv.bytes();
+  for (auto& Lp : lv) {
+    const Level& L = *Lp;
+    b += L.A.bytes() + L.dinv.bytes() + L.mask.bytes() + L.S.bytes() + L.cf.bytes() + L.P.bytes() +
+         L.R.bytes() + L.AP.bytes() + L.Av32.bytes() + L.Pv32.bytes() + L.Rv32.bytes() +
+         L.dinv32.bytes() + L.r.bytes() + L.y.bytes() + L.b.bytes() + L.x.bytes() +
+         L.r32.bytes() + L.y32.bytes() + L.b32.bytes() + L.x32.bytes();
+  }
+  return b;
+}
+
+// ---------------------------------------------------------------- V-cycle
+template <class T>
+void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st) {
+  Level& L = *lv[l];
+  int n = L.A.nrows;
+  const T* Av = vals_of<T>(L.A, L.Av32);
+  const T* dinv = dinv_of<T>(L);
+  int lpr = lanes_per_row(n, L.A.nnz);
+  unsigned blocks = grid_for(int64_t(n) * lpr, 256);
+  bool last = l == int(lv.size()) - 1;
+  if (last) {
+    if (coarse_dense) {
+      k_dense_gemv<T><<<grid_for(int64_t(n) * kWave, 256), 256, 0, st>>>(n, Ainv.p, b, x);
+    } else {
+      DISPATCH_LPR(lpr, LL, {
+        k_vc_two_sweeps<T, LL><<<blocks, 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, Av, dinv, b, x);
+      });
+    }
+    TPF_CHECK_LAUNCH();
+    return;
+  }
+  Level& C = *lv[l + 1];
+  T* r = work<T>(L.r, L.r32);
+  T* y = work<T>(L.y, L.y32);
+  T* bc = work<T>(C.b, C.b32);
+  T* xc = work<T>(C.x, C.x32);
+  {
+    TimedScope ts(l == 0 ? "vcycle_pre_residual_l0" : "vcycle_pre_residual", st);
+    DISPATCH_LPR(lpr, LL, {
+      k_vc_pre<T, LL><<<blocks, 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, Av, dinv, b, r);
+    });
+    TPF_CHECK_LAUNCH();
+  }
+  csr_spmv<T>(ref_with<T>(L.R, vals_of<T>(L.R, L.Rv32)), r, bc, st,
+              l == 0 ? "vcycle_restrict_l0" : "vcycle_restrict");
+  vcycle_level<T>(l + 1, bc, xc, st);
+  {
+    int plpr = lanes_per_row(n, L.P.nnz);
+    TimedScope ts(l == 0 ? "vcycle_prolong_l0" : "vcycle_prolong", st);
+    DISPATCH_LPR(plpr, LL, {
+      k_vc_prolong<T, LL><<<grid_for(int64_t(n) * LL, 256), 256, 0, st>>>(
+          n, L.P.rp.p, L.P.ci.p, vals_of<T>(L.P, L.Pv32), dinv, b, xc, y);
+    });
+    TPF_CHECK_LAUNCH();
+  }
+  {
+    TimedScope ts(l == 0 ? "vcycle_post_smooth_l0" : "vcycle_post_smooth", st);
+    DISPATCH_LPR(lpr, LL, {
+      k_vc_post<T, LL><<<blocks, 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, Av, dinv, b, y, x);
+    });
+    TPF_CHECK_LAUNCH();
+  }
+}
+
+template <class T>
+void Hierarchy::vcycle(const T* b, T* x, hipStream_t st) {
+  TPF_REQUIRE(!lv.empty(), TPF_ERR_STATE, "AMG hierarchy not set up");
+  if (std::is_same<T, float>::value) TPF_REQUIRE(o.fp32, TPF_ERR_STATE, "FP32 copies not built");
+  vcycle_level<T>(0, b, x, st);
+}
+
+template void Hierarchy::vcycle<double>(const double*, double*, hipStream_t);
+template void Hierarchy::vcycle<float>(const float*, float*, hipStream_t);
+
+}  // namespace tpf

@@ -1,0 +1,58 @@
+// Classical AMG hierarchy built and applied on the device.
+#pragma once
+
+#include <memory>
+
+#include "tpf_internal.hpp"
+
+namespace tpf {
+
+struct AmgOpts {
+  double theta = 0.25;
+  int max_levels = 25;
+  int coarse_max = 256;
+  int dense_max = 1024;
+  uint64_t seed = 0x5eed;
+  bool fp32 = false;
+};
+
+struct Level {
+  Csr<double> A;        // level operator
+  Buf<double> dinv;     // inverse l1-Jacobi diagonal (0 where the l1 row sum is 0)
+  Buf<uint8_t> mask;    // strength mask over A's entries
+  Csr<double> S;        // strength graph (pattern only)
+  Buf<int8_t> cf;       // 1 = C, 2 = F
+  Csr<double> P, R, AP; // interpolation, restriction, and A*P (kept for numeric refresh)
+  // FP32 copies of the values (patterns shared)
+  Buf<float> Av32, Pv32, Rv32, dinv32;
+  // workspace: r, y always; b, x on levels >= 1
+  Buf<double> r, y, b, x;
+  Buf<float> r32, y32, b32, x32;
+  int64_t pmis_rounds = 0;
+};
+
+struct Hierarchy {
+  AmgOpts o;
+  std::vector<std::unique_ptr<Level>> lv;
+  bool coarse_dense = false;
+  Buf<double> Ainv;     // dense inverse of the coarsest operator (row-major)
+  hipStream_t s = nullptr;
+
+  // Full setup from the level-0 operator.
+  void build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st);
+  // Numeric refresh after lv[0]->A values changed (same pattern): keeps C/F, P, R.
+  void refresh(hipStream_t st);
+  Csr<double>& A0() { return lv[0]->A; }
+  template <class T>
+  void vcycle(const T* b, T* x, hipStream_t st);
+  size_t bytes() const;
+  int levels() const { return int(lv.size()); }
+
+ private:
+  void finish_levels(hipStream_t st);
+  void coarse_setup(hipStream_t st);
+  template <class T>
+  void vcycle_level(int l, const T* b, T* x, hipStream_t st);
+};
+
+}  // namespace tpf

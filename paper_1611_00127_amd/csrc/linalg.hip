@@ -1,0 +1,261 @@
+// Dense-vector and CSR primitives: scans, fills, casts, deterministic
+// reductions and CSR row kernels (one group of LPR lanes per row, LPR a
+// power of two chosen from the mean row length so that a row is read with
+// consecutive lanes).
+#include "linalg_dev.hpp"
+#include "tpf_internal.hpp"
+
+namespace tpf {
+
+// ---------------------------------------------------------------- scans
+namespace {
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+template <class T, class In>
+__global__ void __launch_bounds__(kScanBlock) k_scan_tile(const In* in, T* out, T* block_sums,
+                                                          int64_t n) {
+  __shared__ T sh[kScanBlock / 64 + 1];
+  int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
+  T v[kScanItems];
+  T local = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    int64_t i = base + k;
+    v[k] = i < n ? T(in[i]) : T(0);
+    local += v[k];
+  }
+  T total;
+  T excl = block_exclusive_scan<T, kScanBlock>(local, sh, total);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    int64_t i = base + k;
+    if (i < n) out[i] = excl;
+    excl += v[k];
+  }
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+template <class T>
+__global__ void k_scan_add(T* out, const T* offsets, int64_t n) {
+  int64_t i = int64_t(blockIdx.x) * kScanTile + threadIdx.x;
+  T off = offsets[blockIdx.x];
+  for (int k = 0; k < kScanItems; ++k, i += kScanBlock)
+    if (i < n) out[i] += off;
+}
+
+// exclusive scan of n values; out has n entries (total returned separately)
+template <class T, class In>
+void scan_rec(const In* in, T* out, int64_t n, hipStream_t s) {
+  int64_t nb = (n + kScanTile - 1) / kScanTile;
+  Buf<T> sums(nb, s);
+  k_scan_tile<T, In><<<unsigned(nb), kScanBlock, 0, s>>>(in, out, sums.p, n);
+  TPF_CHECK_LAUNCH();
+  if (nb > 1) {
+    Buf<T> offs(nb, s);
+    scan_rec<T, T>(sums.p, offs.p, nb, s);
+    k_scan_add<T><<<unsigned(nb), kScanBlock, 0, s>>>(out, offs.p, n);
+    TPF_CHECK_LAUNCH();
+  }
+}
+}  // namespace
+
+int64_t scan_exclusive(const int* in, int* out, int64_t n, hipStream_t s) {
+  // totals are accumulated in 64-bit to detect overflow of the int32 output
+  if (n == 0) {
+    fill_int(out, 0, 1, s);
+    return 0;
+  }
+  Buf<int64_t> tmp(n, s);
+  scan_rec<int64_t, int>(in, tmp.p, n, s);
+  int64_t last_excl = read_scalar(tmp.p + n - 1, s);
+  int last_in = read_scalar(in + n - 1, s);
+  int64_t total = last_excl + last_in;
+  TPF_REQUIRE(total < (int64_t(1) << 31), TPF_ERR_INVALID_ARG,
+              "index count %lld exceeds the int32 range", (long long)total);
+  cast<int64_t, int>(out, tmp.p, n, s);
+  int t32 = int(total);
+  TPF_HIP(hipMemcpyAsync(out + n, &t32, sizeof(int), hipMemcpyHostToDevice, s));
+  TPF_HIP(hipStreamSynchronize(s));
+  return total;
+}
+
+int64_t scan_exclusive64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s) {
+  if (n == 0) {
+    int64_t z = 0;
+    TPF_HIP(hipMemcpyAsync(out, &z, sizeof(z), hipMemcpyHostToDevice, s));
+    TPF_HIP(hipStreamSynchronize(s));
+    return 0;
+  }
+  scan_rec<int64_t, int64_t>(in, out, n, s);
+  int64_t last_excl = read_scalar(out + n - 1, s);
+  int64_t last_in = read_scalar(in + n - 1, s);
+  int64_t total = last_excl + last_in;
+  TPF_HIP(hipMemcpyAsync(out + n, &total, sizeof(total), hipMemcpyHostToDevice, s));
+  TPF_HIP(hipStreamSynchronize(s));
+  return total;
+}
+
+// ---------------------------------------------------------------- fills / copies / casts
+template <class T>
+__global__ void k_fill(T* p, T v, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+template <class A, class B>
+__global__ void k_cast(B* dst, const A* src, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    dst[i] = B(src[i]);
+}
+
+static unsigned stream_grid(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  return unsigned(g);
+}
+
+void fill_int(int* p, int v, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_fill<int><<<stream_grid(n), 256, 0, s>>>(p, v, n);
+  TPF_CHECK_LAUNCH();
+}
+
+template <class T>
+void fill(T* p, T v, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_fill<T><<<stream_grid(n), 256, 0, s>>>(p, v, n);
+  TPF_CHECK_LAUNCH();
+}
+template void fill<double>(double*, double, int64_t, hipStream_t);
+template void fill<float>(float*, float, int64_t, hipStream_t);
+template void fill<int8_t>(int8_t*, int8_t, int64_t, hipStream_t);
+template void fill<int64_t>(int64_t*, int64_t, int64_t, hipStream_t);
+
+template <class T>
+void copy(T* dst, const T* src, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_cast<T, T><<<stream_grid(n), 256, 0, s>>>(dst, src, n);
+  TPF_CHECK_LAUNCH();
+}
+template void copy<double>(double*, const double*, int64_t, hipStream_t);
+template void copy<float>(float*, const float*, int64_t, hipStream_t);
+template void copy<int>(int*, const int*, int64_t, hipStream_t);
+
+template <class A, class B>
+void cast(B* dst, const A* src, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_cast<A, B><<<stream_grid(n), 256, 0, s>>>(dst, src, n);
+  TPF_CHECK_LAUNCH();
+}
+template void cast<double, float>(float*, const double*, int64_t, hipStream_t);
+template void cast<float, double>(double*, const float*, int64_t, hipStream_t);
+template void cast<int64_t, int>(int*, const int64_t*, int64_t, hipStream_t);
+
+// ---------------------------------------------------------------- reductions
+namespace {
+constexpr int kRedBlocks = 512;
+constexpr int kRedThreads = 256;
+
+__global__ void __launch_bounds__(kRedThreads) k_dot_partial(const double* x, const double* y,
+                                                             int64_t n, double* part) {
+  __shared__ double sh[kRedThreads / 64];
+  double acc = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * kRedThreads + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * kRedThreads)
+    acc += x[i] * y[i];
+  acc = block_sum<kRedThreads>(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+__global__ void __launch_bounds__(kRedThreads) k_sum_final(const double* part, int m, double* out,
+                                                           int sqrt_flag) {
+  __shared__ double sh[kRedThreads / 64];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < m; i += kRedThreads) acc += part[i];
+  acc = block_sum<kRedThreads>(acc, sh);
+  if (threadIdx.x == 0) *out = sqrt_flag ? sqrt(acc) : acc;
+}
+}  // namespace
+
+void dot_device(const double* x, const double* y, int64_t n, double* out, hipStream_t s) {
+  Buf<double> part(kRedBlocks, s);
+  k_dot_partial<<<kRedBlocks, kRedThreads, 0, s>>>(x, y, n, part.p);
+  TPF_CHECK_LAUNCH();
+  k_sum_final<<<1, kRedThreads, 0, s>>>(part.p, kRedBlocks, out, 0);
+  TPF_CHECK_LAUNCH();
+}
+
+double nrm2_host(const double* x, int64_t n, hipStream_t s) {
+  Buf<double> part(kRedBlocks + 1, s);
+  k_dot_partial<<<kRedBlocks, kRedThreads, 0, s>>>(x, x, n, part.p);
+  TPF_CHECK_LAUNCH();
+  k_sum_final<<<1, kRedThreads, 0, s>>>(part.p, kRedBlocks, part.p + kRedBlocks, 1);
+  TPF_CHECK_LAUNCH();
+  return read_scalar(part.p + kRedBlocks, s);
+}
+
+// ---------------------------------------------------------------- CSR row kernels
+namespace {
+template <class T, int LPR>
+__global__ void __launch_bounds__(256) k_csr_spmv(int nrows, const int* __restrict__ rp,
+                                                  const int* __restrict__ ci,
+                                                  const T* __restrict__ v,
+                                                  const T* __restrict__ x, T* __restrict__ y) {
+  int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int row = int(gid / LPR);
+  int lane = int(gid % LPR);
+  if (row >= nrows) return;
+  T sum = row_dot<T, LPR>(row, lane, rp, ci, v, [&](int j) { return x[j]; });
+  if (lane == 0) y[row] = sum;
+}
+
+template <class T, int LPR>
+__global__ void __launch_bounds__(256) k_csr_residual(int nrows, const int* __restrict__ rp,
+                                                      const int* __restrict__ ci,
+                                                      const T* __restrict__ v,
+                                                      const T* __restrict__ x,
+                                                      const T* __restrict__ b, T* __restrict__ y) {
+  int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int row = int(gid / LPR);
+  int lane = int(gid % LPR);
+  if (row >= nrows) return;
+  T sum = row_dot<T, LPR>(row, lane, rp, ci, v, [&](int j) { return x[j]; });
+  if (lane == 0) y[row] = b[row] - sum;
+}
+}  // namespace
+
+template <class T>
+void csr_spmv(const CsrRef<T>& A, const T* x, T* y, hipStream_t s, const char* tname) {
+  if (A.nrows == 0) return;
+  int lpr = lanes_per_row(A.nrows, A.nnz);
+  TimedScope ts(tname, s);
+  DISPATCH_LPR(lpr, L, {
+    k_csr_spmv<T, L><<<grid_for(int64_t(A.nrows) * L, 256), 256, 0, s>>>(A.nrows, A.rp, A.ci,
+                                                                          A.v, x, y);
+  });
+  TPF_CHECK_LAUNCH();
+}
+template void csr_spmv<double>(const CsrRef<double>&, const double*, double*, hipStream_t, const char*);
+template void csr_spmv<float>(const CsrRef<float>&, const float*, float*, hipStream_t, const char*);
+
+template <class T>
+void csr_residual(const CsrRef<T>& A, const T* x, const T* b, T* y, hipStream_t s) {
+  if (A.nrows == 0) return;
+  int lpr = lanes_per_row(A.nrows, A.nnz);
+  DISPATCH_LPR(lpr, L, {
+    k_csr_residual<T, L><<<grid_for(int64_t(A.nrows) * L, 256), 256, 0, s>>>(
+        A.nrows, A.rp, A.ci, A.v, x, b, y);
+  });
+  TPF_CHECK_LAUNCH();
+}
+template void csr_residual<double>(const CsrRef<double>&, const double*, const double*, double*,
+                                   hipStream_t);
+template void csr_residual<float>(const CsrRef<float>&, const float*, const float*, float*,
+                                  hipStream_t);
+
+}  // namespace tpf

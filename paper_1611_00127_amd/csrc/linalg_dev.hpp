@@ -1,0 +1,99 @@
+// Device-side helpers: wavefront (64-lane) and block reductions/scans and
+// the CSR row-dot with a power-of-two lane group per row.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace tpf {
+
+constexpr int kWave = 64;
+
+template <class T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_down(v, off, kWave);
+  return v;  // valid in lane 0
+}
+
+// Sum over a block of BLOCK threads (BLOCK a multiple of 64); fixed order,
+// result valid in thread 0.  sh needs BLOCK/64 entries.
+template <int BLOCK, class T>
+__device__ inline T block_sum(T v, T* sh) {
+  v = wave_sum(v);
+  int lane = threadIdx.x & (kWave - 1);
+  int wid = threadIdx.x / kWave;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  T acc = 0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 0; w < BLOCK / kWave; ++w) acc += sh[w];
+  }
+  __syncthreads();
+  return acc;
+}
+
+// Exclusive scan over a block; `total` receives the block sum in every
+// thread.  sh needs BLOCK/64 + 1 entries.
+template <class T, int BLOCK>
+__device__ inline T block_exclusive_scan(T v, T* sh, T& total) {
+  int lane = threadIdx.x & (kWave - 1);
+  int wid = threadIdx.x / kWave;
+  T x = v;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    T y = __shfl_up(x, d, kWave);
+    if (lane >= d) x += y;
+  }
+  if (lane == kWave - 1) sh[wid] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T acc = 0;
+    for (int w = 0; w < BLOCK / kWave; ++w) {
+      T t = sh[w];
+      sh[w] = acc;
+      acc += t;
+    }
+    sh[BLOCK / kWave] = acc;
+  }
+  __syncthreads();
+  T excl = x - v + sh[wid];
+  total = sh[BLOCK / kWave];
+  __syncthreads();
+  return excl;
+}
+
+// Dot of CSR row `row` with gathered values g(col); LPR consecutive lanes
+// share the row; result valid in the group's first lane.
+template <class T, int LPR, class G>
+__device__ inline T row_dot(int row, int lane, const int* __restrict__ rp,
+                            const int* __restrict__ ci, const T* __restrict__ v, G g) {
+  T sum = T(0);
+  int e1 = rp[row + 1];
+  for (int e = rp[row] + lane; e < e1; e += LPR) sum += v[e] * g(ci[e]);
+#pragma unroll
+  for (int off = LPR / 2; off > 0; off >>= 1) sum += __shfl_down(sum, off, LPR);
+  return sum;
+}
+
+inline int lanes_per_row(int64_t nrows, int64_t nnz) {
+  double avg = nrows ? double(nnz) / double(nrows) : 1.0;
+  int l = 1;
+  while (l < 64 && l < avg) l <<= 1;
+  return l;
+}
+
+}  // namespace tpf
+
+#define DISPATCH_LPR(lpr, L, ...)                     \
+  switch (lpr) {                                      \
+    case 1: { constexpr int L = 1; __VA_ARGS__ } break;   \
+    case 2: { constexpr int L = 2; __VA_ARGS__ } break;   \
+    case 4: { constexpr int L = 4; __VA_ARGS__ } break;   \
+    case 8: { constexpr int L = 8; __VA_ARGS__ } break;   \
+    case 16: { constexpr int L = 16; __VA_ARGS__ } break; \
+    case 32: { constexpr int L = 32; __VA_ARGS__ } break; \
+    default: { constexpr int L = 64; __VA_ARGS__ } break; \
+  }

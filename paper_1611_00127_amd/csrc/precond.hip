@@ -1,0 +1,703 @@
+// The paper's preconditioners (Sec. 3.2-3.4):
+//   AMG   one V-cycle on the point-ordered scalar J (black box, Sec. 3.2);
+//   CPR1  Algorithm 1 / Eq. m_comb: u = P_1^{-1} r, r' = r - J u,
+//         z = u + R_p^T V(A_pp; R_p r');
+//   CPR2  Algorithm 2 / Eq. m_add: as CPR1 plus R_s^T V(A_ss; R_s r');
+//   BF    Algorithm 3 / Eq. m_bf: s = V(A_ss; R_s r), t = R_p r - A_ps s,
+//         p = V(S~; t), z = (p, s), with S~ = A_pp - A_ps diag(A_ss)^{-1} A_sp
+//         (Eq. SIMPLE-Schur, trailing factor A_sp as in the exact Schur
+//         complement).
+// P_1 is block ILU(0) (Sec. 3.3) in the lexicographic point order; on the
+// 5/7-point block stencil only the pivot blocks change,
+// D_i = A_ii - sum_{k<i} A_ik D_k^{-1} A_ki, and M = (D+L)D^{-1}(D+U).  The
+// factorisation and both triangular solves proceed by anti-diagonal
+// wavefronts ix+iy+iz = const, whose cells are mutually independent.
+#include <algorithm>
+#include <type_traits>
+
+#include "linalg_dev.hpp"
+#include "precond.hpp"
+
+namespace tpf {
+
+namespace {
+
+__global__ void k_extract_blocks(int64_t nnzb, const double* __restrict__ jv,
+                                 double* __restrict__ app, double* __restrict__ aps,
+                                 double* __restrict__ asp, double* __restrict__ ass) {
+  int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= nnzb) return;
+  double4 b = reinterpret_cast<const double4*>(jv)[e];
+  app[e] = b.x;
+  aps[e] = b.y;
+  asp[e] = b.z;
+  ass[e] = b.w;
+}
+
+// point-ordered scalar matrix: rows 2i+a, columns 2j+b, 4 entries per block
+__global__ void k_scalarize_pattern(int nb, const int* __restrict__ rp, const int* __restrict__ ci,
+                                    int* __restrict__ srp, int* __restrict__ sci) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > nb) return;
+  int r0 = rp[i];
+  if (i == nb) {
+    srp[2 * nb] = 4 * r0;
+    return;
+  }
+  int len = rp[i + 1] - r0;
+  srp[2 * i] = 4 * r0;
+  srp[2 * i + 1] = 4 * r0 + 2 * len;
+  for (int a = 0; a < 2; ++a) {
+    int o = 4 * r0 + a * 2 * len;
+    for (int k = 0; k < len; ++k) {
+      int j = ci[r0 + k];
+      sci[o + 2 * k] = 2 * j;
+      sci[o + 2 * k + 1] = 2 * j + 1;
+    }
+  }
+}
+
+__global__ void k_scalarize_values(int nb, const int* __restrict__ rp, const double* __restrict__ jv,
+                                   double* __restrict__ sv) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  int r0 = rp[i], len = rp[i + 1] - r0;
+  for (int a = 0; a < 2; ++a) {
+    int o = 4 * r0 + a * 2 * len;
+    for (int k = 0; k < len; ++k) {
+      sv[o + 2 * k] = jv[4 * int64_t(r0 + k) + 2 * a];
+      sv[o + 2 * k + 1] = jv[4 * int64_t(r0 + k) + 2 * a + 1];
+    }
+  }
+}
+
+__global__ void k_diag_inv(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                           const double* __restrict__ v, double* __restrict__ dinv) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double d = 0.0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e)
+    if (ci[e] == i) d = v[e];
+  dinv[i] = 1.0 / d;
+}
+
+__global__ void k_scale_cols(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                             const double* __restrict__ v, const double* __restrict__ dinv,
+                             double* __restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) out[e] = v[e] * dinv[ci[e]];
+}
+
+template <class T>
+__global__ void k_gather(int n, const double* __restrict__ r, int comp, T* __restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = T(r[2 * i + comp]);
+}
+
+template <class T>
+__global__ void k_scatter2(int n, const T* __restrict__ p, const T* __restrict__ s,
+                           double* __restrict__ z) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) reinterpret_cast<double2*>(z)[i] = make_double2(double(p[i]), double(s[i]));
+}
+
+template <class T>
+__global__ void k_add_comp(int n, double* __restrict__ z, int comp, const T* __restrict__ v) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[2 * i + comp] += double(v[i]);
+}
+
+// t_i = r_{p,i} - sum_j (A_ps)_ij s_j   (Algorithm 3, step 3)
+template <class T, int LPR>
+__global__ void __launch_bounds__(256) k_bf_rhs(int n, const int* __restrict__ rp,
+                                                const int* __restrict__ ci,
+                                                const double* __restrict__ aps,
+                                                const double* __restrict__ r,
+                                                const T* __restrict__ s, T* __restrict__ t) {
+  int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int row = int(gid / LPR), lane = int(gid % LPR);
+  if (row >= n) return;
+  double sum = row_dot<double, LPR>(row, lane, rp, ci, aps, [&](int j) { return double(s[j]); });
+  if (lane == 0) t[row] = T(r[2 * row] - sum);
+}
+
+// ---------------------------------------------------------------- block ILU(0)
+struct Grid3 {
+  int nx, ny, nz;
+};
+
+__device__ inline int len2d(int m, int nx, int ny) {
+  int lo = m - nx + 1 > 0 ? m - nx + 1 : 0;
+  int hi = m < ny - 1 ? m : ny - 1;
+  return hi >= lo ? hi - lo + 1 : 0;
+}
+
+// position of cell i in the wavefront ordering (fronts ascending, index
+// ascending inside a front)
+__global__ void k_front_place(Grid3 g, const int* __restrict__ fptr, int* __restrict__ cells) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int64_t N = int64_t(g.nx) * g.ny * g.nz;
+  if (i >= N) return;
+  int ix = int(i % g.nx), iy = int((i / g.nx) % g.ny), iz = int(i / (int64_t(g.nx) * g.ny));
+  int L = ix + iy + iz;
+  int64_t pos = fptr[L];
+  for (int z = 0; z < iz; ++z) pos += len2d(L - z, g.nx, g.ny);
+  int m = L - iz;
+  int lo = m - g.nx + 1 > 0 ? m - g.nx + 1 : 0;
+  pos += iy - lo;
+  cells[pos] = int(i);
+}
+
+__device__ inline void mm2(const double* a, const double* b, double* c) {
+  c[0] = a[0] * b[0] + a[1] * b[2];
+  c[1] = a[0] * b[1] + a[1] * b[3];
+  c[2] = a[2] * b[0] + a[3] * b[2];
+  c[3] = a[2] * b[1] + a[3] * b[3];
+}
+
+__global__ void k_bilu_factor(int cnt, const int* __restrict__ cells, const int* __restrict__ rp,
+                              const int* __restrict__ ci, const double* __restrict__ jv,
+                              double* __restrict__ dinv, int* __restrict__ flag) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cnt) return;
+  int i = cells[t];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double d[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    int k = ci[e];
+    if (k == i) {
+      for (int q = 0; q < 4; ++q) d[q] = jv[4 * int64_t(e) + q];
+    } else if (k < i) {
+      int f = rp[k];
+      while (ci[f] != i) ++f;  // A_ki exists: the pattern is symmetric
+      double tmp[4], c[4];
+      mm2(jv + 4 * int64_t(e), dinv + 4 * int64_t(k), tmp);
+      mm2(tmp, jv + 4 * int64_t(f), c);
+      for (int q = 0; q < 4; ++q) acc[q] += c[q];
+    }
+  }
+  for (int q = 0; q < 4; ++q) d[q] = d[q] - acc[q];
+  double det = d[0] * d[3] - d[1] * d[2];
+  if (det == 0.0 || !isfinite(det)) *flag = 1;
+  double* o = dinv + 4 * int64_t(i);
+  o[0] = d[3] / det;
+  o[1] = -d[1] / det;
+  o[2] = -d[2] / det;
+  o[3] = d[0] / det;
+}
+
+// forward: w_i = D_i^{-1} (r_i - sum_{k<i} A_ik w_k)
+template <class T>
+__global__ void k_bilu_fwd(int cnt, const int* __restrict__ cells, const int* __restrict__ rp,
+                           const int* __restrict__ ci, const T* __restrict__ jv,
+                           const T* __restrict__ dinv, const double* __restrict__ r,
+                           T* __restrict__ w) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cnt) return;
+  int i = cells[t];
+  T a0 = 0, a1 = 0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    int k = ci[e];
+    if (k >= i) break;
+    const T* b = jv + 4 * int64_t(e);
+    T w0 = w[2 * k], w1 = w[2 * k + 1];
+    a0 += b[0] * w0 + b[1] * w1;
+    a1 += b[2] * w0 + b[3] * w1;
+  }
+  T x0 = T(r[2 * i]) - a0, x1 = T(r[2 * i + 1]) - a1;
+  const T* di = dinv + 4 * int64_t(i);
+  w[2 * i] = di[0] * x0 + di[1] * x1;
+  w[2 * i + 1] = di[2] * x0 + di[3] * x1;
+}
+
+// backward: z_i = w_i - D_i^{-1} sum_{j>i} A_ij z_j
+template <class T>
+__global__ void k_bilu_bwd(int cnt, const int* __restrict__ cells, const int* __restrict__ rp,
+                           const int* __restrict__ ci, const T* __restrict__ jv,
+                           const T* __restrict__ dinv, const T* __restrict__ w,
+                           T* __restrict__ z) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cnt) return;
+  int i = cells[t];
+  T a0 = 0, a1 = 0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    int j = ci[e];
+    if (j <= i) continue;
+    const T* b = jv + 4 * int64_t(e);
+    T z0 = z[2 * j], z1 = z[2 * j + 1];
+    a0 += b[0] * z0 + b[1] * z1;
+    a1 += b[2] * z0 + b[3] * z1;
+  }
+  const T* di = dinv + 4 * int64_t(i);
+  z[2 * i] = w[2 * i] - (di[0] * a0 + di[1] * a1);
+  z[2 * i + 1] = w[2 * i + 1] - (di[2] * a0 + di[3] * a1);
+}
+
+template <class T>
+__global__ void k_to_double(int64_t n, const T* __restrict__ a, double* __restrict__ b) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = double(a[i]);
+}
+
+Csr<double> block_copy(const tpf_precond* M, const double* vals, hipStream_t s) {
+  Csr<double> A;
+  A.nrows = A.ncols = M->N;
+  A.nnz = M->J->nnzb;
+  A.rp.alloc(M->N + 1, s);
+  A.ci.alloc(A.nnz, s);
+  A.v.alloc(A.nnz, s);
+  copy(A.rp.p, M->brp.p, M->N + 1, s);
+  copy(A.ci.p, M->bci.p, A.nnz, s);
+  copy(A.v.p, vals, A.nnz, s);
+  return A;
+}
+
+AmgOpts amg_opts(const tpf_precond_opts& o) {
+  AmgOpts a;
+  a.theta = o.theta;
+  a.max_levels = o.max_levels;
+  a.coarse_max = o.coarse_max;
+  a.dense_max = o.dense_max;
+  a.seed = o.hash_seed;
+  a.fp32 = o.precision == TPF_FP32;
+  return a;
+}
+
+void bilu_setup(tpf_precond* M, bool reuse, hipStream_t s) {
+  const tpf_jacobian* J = M->J;
+  const Phys& ph = J->prob->ph;
+  int N = M->N;
+  if (!reuse || M->front_ptr.empty()) {
+    int nf = ph.nx + ph.ny + ph.nz - 2;
+    std::vector<int> ptr(nf + 1, 0);
+    for (int L = 0; L < nf; ++L) {
+      int64_t c = 0;
+      for (int z = 0; z < ph.nz; ++z) {
+        int m = L - z;
+        if (m < 0) break;
+        int lo = std::max(0, m - ph.nx + 1), hi = std::min(ph.ny - 1, m);
+        if (hi >= lo) c += hi - lo + 1;
+      }
+      ptr[L + 1] = int(ptr[L] + c);
+    }
+    TPF_REQUIRE(ptr[nf] == N, TPF_ERR_INVALID_ARG, "wavefront ordering does not cover the grid");
+    M->front_ptr = ptr;
+    Buf<int> dptr(nf + 1, s);
+    TPF_HIP(hipMemcpyAsync(dptr.p, ptr.data(), (nf + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+    M->front_cells.alloc(N, s);
+    k_front_place<<<grid_for(N, 256), 256, 0, s>>>(Grid3{ph.nx, ph.ny, ph.nz}, dptr.p,
+                                                   M->front_cells.p);
+    TPF_CHECK_LAUNCH();
+    TPF_HIP(hipStreamSynchronize(s));
+    M->bilu_dinv.alloc(4 * int64_t(N), s);
+  }
+  Buf<int> flag(1, s);
+  fill_int(flag.p, 0, 1, s);
+  int nf = int(M->front_ptr.size()) - 1;
+  for (int f = 0; f < nf; ++f) {
+    int a = M->front_ptr[f], cnt = M->front_ptr[f + 1] - a;
+    k_bilu_factor<<<grid_for(cnt, 256), 256, 0, s>>>(cnt, M->front_cells.p + a, J->rp.p, J->ci.p,
+                                                     J->v.p, M->bilu_dinv.p, flag.p);
+    TPF_CHECK_LAUNCH();
+  }
+  int fl = read_scalar(flag.p, s);
+  TPF_REQUIRE(fl == 0, TPF_ERR_SINGULAR, "zero pivot block in block ILU(0)");
+  if (M->o.precision == TPF_FP32) {
+    M->bilu_dinv32.ensure(4 * int64_t(N), s);
+    cast<double, float>(M->bilu_dinv32.p, M->bilu_dinv.p, 4 * int64_t(N), s);
+    M->jv32.ensure(4 * J->nnzb, s);
+    cast<double, float>(M->jv32.p, J->v.p, 4 * J->nnzb, s);
+  }
+}
+
+template <class T>
+void bilu_apply(tpf_precond* M, const double* r, T* w, T* z, hipStream_t s) {
+  const tpf_jacobian* J = M->J;
+  const T* jv;
+  const T* dinv;
+  if constexpr (std::is_same<T, float>::value) {
+    jv = M->jv32.p;
+    dinv = M->bilu_dinv32.p;
+  } else {
+    jv = J->v.p;
+    dinv = M->bilu_dinv.p;
+  }
+  int nf = int(M->front_ptr.size()) - 1;
+  TimedScope ts("bilu_solve", s);
+  for (int f = 0; f < nf; ++f) {
+    int a = M->front_ptr[f], cnt = M->front_ptr[f + 1] - a;
+    k_bilu_fwd<T><<<grid_for(cnt, 256), 256, 0, s>>>(cnt, M->front_cells.p + a, J->rp.p, J->ci.p,
+                                                     jv, dinv, r, w);
+  }
+  TPF_CHECK_LAUNCH();
+  for (int f = nf - 1; f >= 0; --f) {
+    int a = M->front_ptr[f], cnt = M->front_ptr[f + 1] - a;
+    k_bilu_bwd<T><<<grid_for(cnt, 256), 256, 0, s>>>(cnt, M->front_cells.p + a, J->rp.p, J->ci.p,
+                                                     jv, dinv, w, z);
+  }
+  TPF_CHECK_LAUNCH();
+}
+
+template <class T>
+T* wsel(Buf<double>& d, Buf<float>& f) {
+  if constexpr (std::is_same<T, float>::value)
+    return f.p;
+  else
+    return d.p;
+}
+
+template <class T>
+void apply_t(tpf_precond* M, const double* r, double* z, hipStream_t s) {
+  int N = M->N;
+  unsigned g = grid_for(N, 256);
+  T* v1 = wsel<T>(M->w1, M->f1);
+  T* v2 = wsel<T>(M->w2, M->f2);
+  T* v3 = wsel<T>(M->w3, M->f3);
+  T* v4 = wsel<T>(M->w4, M->f4);
+  switch (M->o.kind) {
+    case TPF_PREC_AMG: {
+      if constexpr (std::is_same<T, float>::value) {
+        cast<double, float>(M->fr.p, r, 2 * int64_t(N), s);
+        M->H[0]->vcycle<float>(M->fr.p, M->fu.p, s);
+        cast<float, double>(z, M->fu.p, 2 * int64_t(N), s);
+      } else {
+        M->H[0]->vcycle<double>(r, z, s);
+      }
+      break;
+    }
+    case TPF_PREC_CPR1:
+    case TPF_PREC_CPR2: {
+      T* uw = wsel<T>(M->r2, M->fr);  // forward sweep result
+      T* uz = wsel<T>(M->u2, M->fu);
+      bilu_apply<T>(M, r, uw, uz, s);
+      // u (FP64) lives in z; r' = r - J u in M->r2 (FP64)
+      if constexpr (std::is_same<T, float>::value) {
+        k_to_double<float><<<grid_for(2 * int64_t(N), 256), 256, 0, s>>>(2 * int64_t(N), uz, z);
+      } else {
+        copy(z, uz, 2 * int64_t(N), s);
+      }
+      TPF_CHECK_LAUNCH();
+      bcsr_apply(M->J, z, r, M->r2.p, s);
+      k_gather<T><<<g, 256, 0, s>>>(N, M->r2.p, 0, v1);
+      TPF_CHECK_LAUNCH();
+      M->H[0]->vcycle<T>(v1, v2, s);
+      if (M->o.kind == TPF_PREC_CPR2) {
+        k_gather<T><<<g, 256, 0, s>>>(N, M->r2.p, 1, v3);
+        TPF_CHECK_LAUNCH();
+        M->H[1]->vcycle<T>(v3, v4, s);
+        k_add_comp<T><<<g, 256, 0, s>>>(N, z, 1, v4);
+        TPF_CHECK_LAUNCH();
+      }
+      k_add_comp<T><<<g, 256, 0, s>>>(N, z, 0, v2);
+      TPF_CHECK_LAUNCH();
+      break;
+    }
+    case TPF_PREC_BF: {
+      k_gather<T><<<g, 256, 0, s>>>(N, r, 1, v1);
+      TPF_CHECK_LAUNCH();
+      M->H[0]->vcycle<T>(v1, v2, s);  // s = V(A_ss; R_s r)
+      int lpr = lanes_per_row(N, M->J->nnzb);
+      {
+        TimedScope ts("bf_rhs", s);
+        DISPATCH_LPR(lpr, L, {
+          k_bf_rhs<T, L><<<grid_for(int64_t(N) * L, 256), 256, 0, s>>>(N, M->brp.p, M->bci.p,
+                                                                       M->aps_v.p, r, v2, v3);
+        });
+        TPF_CHECK_LAUNCH();
+      }
+      M->H[1]->vcycle<T>(v3, v4, s);  // p = V(S~; t)
+      k_scatter2<T><<<g, 256, 0, s>>>(N, v4, v2, z);
+      TPF_CHECK_LAUNCH();
+      break;
+    }
+    default:
+      copy(z, r, 2 * int64_t(N), s);
+  }
+}
+
+}  // namespace
+
+}  // namespace tpf
+
+using namespace tpf;
+
+size_t tpf_precond::bytes() const {
+  size_t b = brp.bytes() + bci.bytes() + app_v.bytes() + aps_v.bytes() + asp_v.bytes() +
+             ass_v.bytes() + y_v.bytes() + ass_dinv.bytes() + schur.bytes() + bilu_dinv.bytes() +
+             bilu_dinv32.bytes() + jv32.bytes() + front_cells.bytes() + w1.bytes() + w2.bytes() +
+             w3.bytes() + w4.bytes() + u2.bytes() + r2.bytes() + f1.bytes() + f2.bytes() +
+             f3.bytes() + f4.bytes() + fu.bytes() + fr.bytes();
+  for (int h = 0; h < 2; ++h)
+    if (H[h]) b += H[h]->bytes();
+  return b;
+}
+
+extern "C" {
+
+int tpf_precond_default_opts(int kind, tpf_precond_opts* o) {
+  return guarded([&] {
+    TPF_REQUIRE(o, TPF_ERR_INVALID_ARG, "null argument");
+    o->kind = kind;
+    o->precision = TPF_FP64;
+    o->theta = 0.25;
+    o->max_levels = 25;
+    o->coarse_max = 256;
+    o->dense_max = 1024;
+    o->hash_seed = 0x5eed;
+  });
+}
+
+int tpf_precond_create(const tpf_precond_opts* o, tpf_precond** out) {
+  return guarded([&] {
+    TPF_REQUIRE(o && out, TPF_ERR_INVALID_ARG, "null argument");
+    TPF_REQUIRE(o->kind >= TPF_PREC_AMG && o->kind <= TPF_PREC_NONE, TPF_ERR_INVALID_ARG,
+                "unknown preconditioner kind %d", o->kind);
+    TPF_REQUIRE(o->precision == TPF_FP64 || o->precision == TPF_FP32, TPF_ERR_INVALID_ARG,
+                "unknown precision");
+    TPF_REQUIRE(o->max_levels >= 1 && o->max_levels <= TPF_MAX_LEVELS, TPF_ERR_INVALID_ARG,
+                "max_levels must be in [1, %d]", TPF_MAX_LEVELS);
+    TPF_REQUIRE(o->coarse_max >= 1 && o->dense_max >= 1 && o->dense_max <= 4096,
+                TPF_ERR_INVALID_ARG, "coarse_max >= 1 and 1 <= dense_max <= 4096 required");
+    TPF_REQUIRE(o->theta > 0 && o->theta < 1, TPF_ERR_INVALID_ARG, "theta must be in (0,1)");
+    auto* M = new tpf_precond();
+    M->o = *o;
+    *out = M;
+  });
+}
+
+int tpf_precond_destroy(tpf_precond* M) {
+  return guarded([&] { delete M; });
+}
+
+int tpf_precond_setup(tpf_precond* M, const tpf_jacobian* J, int reuse, void* stream) {
+  return guarded([&] {
+    TPF_REQUIRE(M && J, TPF_ERR_INVALID_ARG, "null argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    bool re = reuse && M->ready && M->J && M->N == J->nb && M->J->nnzb == J->nnzb;
+    TPF_REQUIRE(!reuse || re, TPF_ERR_STATE,
+                "reuse_structure requires a previous setup on a Jacobian with the same pattern");
+    M->ready = false;
+    M->J = J;
+    M->s = s;
+    int N = J->nb;
+    M->N = N;
+    int kind = M->o.kind;
+    if (kind == TPF_PREC_NONE) {
+      M->n_hier = 0;
+      M->ready = true;
+      return;
+    }
+    int64_t nnzb = J->nnzb;
+    AmgOpts ao = amg_opts(M->o);
+    if (!re) {
+      M->brp.alloc(N + 1, s);
+      M->bci.alloc(nnzb, s);
+      copy(M->brp.p, J->rp.p, N + 1, s);
+      copy(M->bci.p, J->ci.p, nnzb, s);
+      for (auto* b : {&M->app_v, &M->aps_v, &M->asp_v, &M->ass_v}) b->alloc(nnzb, s);
+      for (auto* b : {&M->w1, &M->w2, &M->w3, &M->w4}) b->alloc(N, s);
+      M->u2.alloc(2 * int64_t(N), s);
+      M->r2.alloc(2 * int64_t(N), s);
+      if (M->o.precision == TPF_FP32) {
+        for (auto* b : {&M->f1, &M->f2, &M->f3, &M->f4}) b->alloc(N, s);
+        M->fu.alloc(2 * int64_t(N), s);
+        M->fr.alloc(2 * int64_t(N), s);
+      }
+    }
+    k_extract_blocks<<<grid_for(nnzb, 256), 256, 0, s>>>(nnzb, J->v.p, M->app_v.p, M->aps_v.p,
+                                                         M->asp_v.p, M->ass_v.p);
+    TPF_CHECK_LAUNCH();
+    if (kind == TPF_PREC_AMG) {
+      M->n_hier = 1;
+      if (!re) {
+        Csr<double> Js;
+        Js.nrows = Js.ncols = 2 * N;
+        Js.nnz = 4 * nnzb;
+        Js.rp.alloc(2 * int64_t(N) + 1, s);
+        Js.ci.alloc(Js.nnz, s);
+        Js.v.alloc(Js.nnz, s);
+        k_scalarize_pattern<<<grid_for(N + 1, 256), 256, 0, s>>>(N, J->rp.p, J->ci.p, Js.rp.p,
+                                                                 Js.ci.p);
+        TPF_CHECK_LAUNCH();
+        k_scalarize_values<<<grid_for(N, 256), 256, 0, s>>>(N, J->rp.p, J->v.p, Js.v.p);
+        TPF_CHECK_LAUNCH();
+        M->H[0] = std::make_unique<Hierarchy>();
+        M->H[0]->build(std::move(Js), ao, s);
+      } else {
+        k_scalarize_values<<<grid_for(N, 256), 256, 0, s>>>(N, J->rp.p, J->v.p,
+                                                            M->H[0]->A0().v.p);
+        TPF_CHECK_LAUNCH();
+        M->H[0]->refresh(s);
+      }
+    } else if (kind == TPF_PREC_CPR1 || kind == TPF_PREC_CPR2) {
+      M->n_hier = kind == TPF_PREC_CPR2 ? 2 : 1;
+      bilu_setup(M, re, s);
+      const double* src[2] = {M->app_v.p, M->ass_v.p};
+      for (int h = 0; h < M->n_hier; ++h) {
+        if (!re) {
+          M->H[h] = std::make_unique<Hierarchy>();
+          M->H[h]->build(block_copy(M, src[h], s), ao, s);
+        } else {
+          copy(M->H[h]->A0().v.p, src[h], nnzb, s);
+          M->H[h]->refresh(s);
+        }
+      }
+    } else {  // BF
+      M->n_hier = 2;
+      M->ass_dinv.ensure(N, s);
+      M->y_v.ensure(nnzb, s);
+      k_diag_inv<<<grid_for(N, 256), 256, 0, s>>>(N, M->brp.p, M->bci.p, M->ass_v.p,
+                                                  M->ass_dinv.p);
+      TPF_CHECK_LAUNCH();
+      k_scale_cols<<<grid_for(N, 256), 256, 0, s>>>(N, M->brp.p, M->bci.p, M->aps_v.p,
+                                                    M->ass_dinv.p, M->y_v.p);
+      TPF_CHECK_LAUNCH();
+      CsrRef<double> Y{N, N, nnzb, M->brp.p, M->bci.p, M->y_v.p};
+      CsrRef<double> Asp{N, N, nnzb, M->brp.p, M->bci.p, M->asp_v.p};
+      CsrRef<double> App{N, N, nnzb, M->brp.p, M->bci.p, M->app_v.p};
+      if (!re) {
+        M->H[0] = std::make_unique<Hierarchy>();
+        M->H[0]->build(block_copy(M, M->ass_v.p, s), ao, s);
+        Csr<double> S;
+        spgemm(Y, Asp, S, s, &App, -1.0, 1.0, false);
+        M->H[1] = std::make_unique<Hierarchy>();
+        M->H[1]->build(std::move(S), ao, s);
+      } else {
+        copy(M->H[0]->A0().v.p, M->ass_v.p, nnzb, s);
+        M->H[0]->refresh(s);
+        spgemm(Y, Asp, M->H[1]->A0(), s, &App, -1.0, 1.0, true);
+        M->H[1]->refresh(s);
+      }
+    }
+    TPF_HIP(hipStreamSynchronize(s));
+    M->ready = true;
+  });
+}
+
+int tpf_precond_apply(tpf_precond* M, const double* r, double* z, void* stream) {
+  return guarded([&] {
+    TPF_REQUIRE(M && r && z, TPF_ERR_INVALID_ARG, "null argument");
+    TPF_REQUIRE(M->ready, TPF_ERR_STATE, "preconditioner not set up");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (M->o.precision == TPF_FP32 && M->o.kind != TPF_PREC_NONE)
+      apply_t<float>(M, r, z, s);
+    else
+      apply_t<double>(M, r, z, s);
+  });
+}
+
+int tpf_precond_stats(const tpf_precond* M, tpf_hier_stats* out) {
+  return guarded([&] {
+    TPF_REQUIRE(M && out, TPF_ERR_INVALID_ARG, "null argument");
+    TPF_REQUIRE(M->ready, TPF_ERR_STATE, "preconditioner not set up");
+    std::memset(out, 0, sizeof(*out));
+    out->n_hier = M->n_hier;
+    for (int h = 0; h < M->n_hier; ++h) {
+      const Hierarchy& H = *M->H[h];
+      out->levels[h] = H.levels();
+      double nnz0 = 0, rows0 = 0, snnz = 0, srows = 0;
+      for (int l = 0; l < H.levels(); ++l) {
+        out->rows[h][l] = H.lv[l]->A.nrows;
+        out->nnz[h][l] = H.lv[l]->A.nnz;
+        if (l == 0) {
+          nnz0 = double(H.lv[l]->A.nnz);
+          rows0 = double(H.lv[l]->A.nrows);
+        }
+        snnz += double(H.lv[l]->A.nnz);
+        srows += double(H.lv[l]->A.nrows);
+      }
+      out->operator_complexity[h] = snnz / nnz0;
+      out->grid_complexity[h] = srows / rows0;
+      out->coarse_dense[h] = H.coarse_dense;
+    }
+    out->device_bytes = M->bytes();
+  });
+}
+
+int tpf_precond_matrix(const tpf_precond* M, int hier, int level, int which, tpf_csr_view* out) {
+  return guarded([&] {
+    TPF_REQUIRE(M && out, TPF_ERR_INVALID_ARG, "null argument");
+    TPF_REQUIRE(M->ready, TPF_ERR_STATE, "preconditioner not set up");
+    std::memset(out, 0, sizeof(*out));
+    if (which == TPF_MAT_APS) {
+      TPF_REQUIRE(M->n_hier > 0, TPF_ERR_INVALID_ARG, "no block views for this kind");
+      out->n_rows = out->n_cols = M->N;
+      out->nnz = M->J->nnzb;
+      out->row_ptr = M->brp.p;
+      out->col_idx = M->bci.p;
+      out->vals = M->aps_v.p;
+      return;
+    }
+    if (which == TPF_MAT_SCHUR) {
+      TPF_REQUIRE(M->o.kind == TPF_PREC_BF, TPF_ERR_INVALID_ARG, "S~ exists only for BF");
+      hier = 1;
+      level = 0;
+      which = TPF_MAT_A;
+    }
+    TPF_REQUIRE(hier >= 0 && hier < M->n_hier, TPF_ERR_INVALID_ARG, "hierarchy index out of range");
+    const Hierarchy& H = *M->H[hier];
+    TPF_REQUIRE(level >= 0 && level < H.levels(), TPF_ERR_INVALID_ARG, "level out of range");
+    const Level& L = *H.lv[level];
+    const Csr<double>* C = nullptr;
+    switch (which) {
+      case TPF_MAT_A: C = &L.A; break;
+      case TPF_MAT_P: C = &L.P; break;
+      case TPF_MAT_R: C = &L.R; break;
+      case TPF_MAT_S: C = &L.S; break;
+      default: fail(TPF_ERR_INVALID_ARG, "unknown matrix selector %d", which);
+    }
+    TPF_REQUIRE(C->rp.p != nullptr, TPF_ERR_INVALID_ARG, "matrix not present on this level");
+    out->n_rows = C->nrows;
+    out->n_cols = C->ncols;
+    out->nnz = C->nnz;
+    out->row_ptr = C->rp.p;
+    out->col_idx = C->ci.p;
+    out->vals = which == TPF_MAT_S ? nullptr : C->v.p;
+  });
+}
+
+int tpf_precond_level_data(const tpf_precond* M, int hier, int level, const int8_t** cf,
+                           const double** dinv, int* n) {
+  return guarded([&] {
+    TPF_REQUIRE(M, TPF_ERR_INVALID_ARG, "null argument");
+    TPF_REQUIRE(M->ready, TPF_ERR_STATE, "preconditioner not set up");
+    TPF_REQUIRE(hier >= 0 && hier < M->n_hier, TPF_ERR_INVALID_ARG, "hierarchy index out of range");
+    const Hierarchy& H = *M->H[hier];
+    TPF_REQUIRE(level >= 0 && level < H.levels(), TPF_ERR_INVALID_ARG, "level out of range");
+    const Level& L = *H.lv[level];
+    if (cf) *cf = L.cf.p;
+    if (dinv) *dinv = L.dinv.p;
+    if (n) *n = L.A.nrows;
+  });
+}
+
+int tpf_precond_bilu_dinv(const tpf_precond* M, const double** dinv) {
+  return guarded([&] {
+    TPF_REQUIRE(M && dinv, TPF_ERR_INVALID_ARG, "null argument");
+    TPF_REQUIRE(M->ready && M->bilu_dinv.p, TPF_ERR_STATE, "no block ILU(0) factors");
+    *dinv = M->bilu_dinv.p;
+  });
+}
+
+int tpf_precond_vcycle(tpf_precond* M, int hier, const double* b, double* x, void* stream) {
+  return guarded([&] {
+    TPF_REQUIRE(M && b && x, TPF_ERR_INVALID_ARG, "null argument");
+    TPF_REQUIRE(M->ready, TPF_ERR_STATE, "preconditioner not set up");
+    TPF_REQUIRE(hier >= 0 && hier < M->n_hier, TPF_ERR_INVALID_ARG, "hierarchy index out of range");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Hierarchy& H = *M->H[hier];
+    if (M->o.precision == TPF_FP32) {
+      int n = H.lv[0]->A.nrows;
+      Buf<float> fb(n, s), fx(n, s);
+      cast<double, float>(fb.p, b, n, s);
+      H.vcycle<float>(fb.p, fx.p, s);
+      cast<float, double>(x, fx.p, n, s);
+      TPF_HIP(hipStreamSynchronize(s));
+    } else {
+      H.vcycle<double>(b, x, s);
+    }
+  });
+}
+
+}  // extern "C"

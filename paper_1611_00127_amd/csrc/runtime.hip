@@ -1,0 +1,183 @@
+// Runtime services: error state, allocator hook, kernel timing registry.
+#include <cstdarg>
+#include <map>
+#include <mutex>
+
+#include "tpf_internal.hpp"
+
+namespace tpf {
+
+namespace {
+thread_local int g_last_code = TPF_OK;
+thread_local char g_last_msg[1024] = "";
+
+tpf_alloc_fn g_alloc = nullptr;
+tpf_free_fn g_free = nullptr;
+void* g_ctx = nullptr;
+size_t g_in_use = 0;
+std::mutex g_mem_mu;
+
+bool g_timing = false;
+struct TimedRecord {
+  hipEvent_t e0, e1;
+};
+std::mutex g_time_mu;
+std::map<std::string, std::vector<TimedRecord>> g_records;
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t get_event() {
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  TPF_HIP(hipEventCreate(&e));
+  return e;
+}
+}  // namespace
+
+void set_last_error(int code, const char* msg) {
+  g_last_code = code;
+  std::snprintf(g_last_msg, sizeof(g_last_msg), "%s", msg);
+}
+
+void fail(int code, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  throw Error(code, buf);
+}
+
+void* dalloc(size_t bytes, hipStream_t s) {
+  if (bytes == 0) return nullptr;
+  void* p = nullptr;
+  if (g_alloc) {
+    p = g_alloc(bytes, reinterpret_cast<void*>(s), g_ctx);
+    if (!p) fail(TPF_ERR_OOM, "allocator returned NULL for %zu bytes", bytes);
+  } else {
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      fail(TPF_ERR_OOM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_mem_mu);
+  g_in_use += bytes;
+  return p;
+}
+
+void dfree(void* p, size_t bytes, hipStream_t s) {
+  if (!p) return;
+  if (g_free)
+    g_free(p, reinterpret_cast<void*>(s), g_ctx);
+  else
+    (void)hipFree(p);
+  std::lock_guard<std::mutex> lk(g_mem_mu);
+  g_in_use -= bytes;
+}
+
+HostScratch& host_scratch() {
+  static thread_local HostScratch hs;
+  return hs;
+}
+
+bool timing_enabled() { return g_timing; }
+
+TimedScope::TimedScope(const char* n, hipStream_t st) : name(n), s(st) {
+  if (!g_timing) return;
+  std::lock_guard<std::mutex> lk(g_time_mu);
+  e0 = get_event();
+  e1 = get_event();
+  TPF_HIP(hipEventRecord(e0, s));
+}
+
+TimedScope::~TimedScope() {
+  if (!e0) return;
+  if (hipEventRecord(e1, s) != hipSuccess) return;
+  std::lock_guard<std::mutex> lk(g_time_mu);
+  g_records[name].push_back({e0, e1});
+}
+
+}  // namespace tpf
+
+using namespace tpf;
+
+extern "C" {
+
+const char* tpf_status_string(int st) {
+  switch (st) {
+    case TPF_OK: return "ok";
+    case TPF_ERR_INVALID_ARG: return "invalid argument";
+    case TPF_ERR_OOM: return "out of memory";
+    case TPF_ERR_HIP: return "HIP runtime error";
+    case TPF_ERR_SINGULAR: return "singular pivot";
+    case TPF_ERR_OVER_BUDGET: return "request exceeds the memory budget";
+    case TPF_ERR_NOT_IMPLEMENTED: return "not implemented";
+    case TPF_ERR_STATE: return "call out of order";
+    default: return "unknown status";
+  }
+}
+
+int tpf_last_error(char* buf, size_t n) {
+  if (buf && n) std::snprintf(buf, n, "%s", g_last_msg);
+  return g_last_code;
+}
+
+int tpf_set_allocator(tpf_alloc_fn a, tpf_free_fn f, void* ctx) {
+  if ((a == nullptr) != (f == nullptr)) {
+    set_last_error(TPF_ERR_INVALID_ARG, "alloc and free must both be set or both be NULL");
+    return TPF_ERR_INVALID_ARG;
+  }
+  g_alloc = a;
+  g_free = f;
+  g_ctx = ctx;
+  return TPF_OK;
+}
+
+int tpf_memory_in_use(size_t* bytes) {
+  if (!bytes) return TPF_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(g_mem_mu);
+  *bytes = g_in_use;
+  return TPF_OK;
+}
+
+int tpf_kernel_timing(int enable) {
+  g_timing = enable != 0;
+  return TPF_OK;
+}
+
+int tpf_kernel_stats(const char* name, int64_t* count, double* total_ms) {
+  return guarded([&] {
+    TPF_REQUIRE(name && count && total_ms, TPF_ERR_INVALID_ARG, "null argument");
+    std::lock_guard<std::mutex> lk(g_time_mu);
+    *count = 0;
+    *total_ms = 0.0;
+    auto it = g_records.find(name);
+    if (it == g_records.end()) return;
+    for (auto& r : it->second) {
+      TPF_HIP(hipEventSynchronize(r.e1));
+      float ms = 0.f;
+      TPF_HIP(hipEventElapsedTime(&ms, r.e0, r.e1));
+      *total_ms += ms;
+      ++*count;
+    }
+  });
+}
+
+int tpf_kernel_stats_reset(void) {
+  return guarded([&] {
+    std::lock_guard<std::mutex> lk(g_time_mu);
+    for (auto& kv : g_records)
+      for (auto& r : kv.second) {
+        TPF_HIP(hipEventSynchronize(r.e1));
+        g_event_pool.push_back(r.e0);
+        g_event_pool.push_back(r.e1);
+      }
+    g_records.clear();
+  });
+}
+
+}  // extern "C"

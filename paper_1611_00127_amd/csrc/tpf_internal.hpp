@@ -1,0 +1,194 @@
+// Internal declarations shared by the HIP translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/tpf.h"
+
+namespace tpf {
+
+// ---------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] void fail(int code, const char* fmt, ...);
+void set_last_error(int code, const char* msg);
+
+#define TPF_HIP(x)                                                                  \
+  do {                                                                              \
+    hipError_t e_ = (x);                                                            \
+    if (e_ != hipSuccess)                                                           \
+      ::tpf::fail(TPF_ERR_HIP, "%s:%d %s -> %s", __FILE__, __LINE__, #x,            \
+                  hipGetErrorString(e_));                                           \
+  } while (0)
+
+#define TPF_CHECK_LAUNCH() TPF_HIP(hipGetLastError())
+
+#define TPF_REQUIRE(cond, code, ...)        \
+  do {                                      \
+    if (!(cond)) ::tpf::fail(code, __VA_ARGS__); \
+  } while (0)
+
+// Runs body, converting exceptions to status codes (used by every C entry point).
+template <class F>
+int guarded(F&& body) {
+  try {
+    body();
+    return TPF_OK;
+  } catch (const Error& e) {
+    set_last_error(e.code, e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error(TPF_ERR_OOM, "host allocation failed");
+    return TPF_ERR_OOM;
+  } catch (const std::exception& e) {
+    set_last_error(TPF_ERR_INVALID_ARG, e.what());
+    return TPF_ERR_INVALID_ARG;
+  }
+}
+
+// ---------------------------------------------------------------- memory
+void* dalloc(size_t bytes, hipStream_t s);
+void dfree(void* p, size_t bytes, hipStream_t s);
+
+// Owning device array; frees through the installed allocator.
+template <class T>
+struct Buf {
+  T* p = nullptr;
+  size_t n = 0;
+  hipStream_t s = nullptr;
+  Buf() = default;
+  Buf(size_t count, hipStream_t st) { alloc(count, st); }
+  ~Buf() { release(); }
+  Buf(const Buf&) = delete;
+  Buf& operator=(const Buf&) = delete;
+  Buf(Buf&& o) noexcept : p(o.p), n(o.n), s(o.s) { o.p = nullptr; o.n = 0; }
+  Buf& operator=(Buf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; s = o.s; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  void alloc(size_t count, hipStream_t st) {
+    release();
+    s = st;
+    n = count;
+    p = count ? static_cast<T*>(dalloc(count * sizeof(T), st)) : nullptr;
+  }
+  // grows (discarding contents) when smaller than count
+  void ensure(size_t count, hipStream_t st) { if (n < count || !p) alloc(count < 1 ? 1 : count, st); }
+  void release() {
+    if (p) dfree(p, n * sizeof(T), s);
+    p = nullptr;
+    n = 0;
+  }
+  size_t bytes() const { return n * sizeof(T); }
+  T* get() const { return p; }
+};
+
+// Pinned host scratch for small device->host reads.
+struct HostScratch {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~HostScratch() { if (p) (void)hipHostFree(p); }
+  template <class T> T* get(size_t count) {
+    size_t need = count * sizeof(T);
+    if (need > bytes) {
+      if (p) TPF_HIP(hipHostFree(p));
+      TPF_HIP(hipHostMalloc(&p, need < 4096 ? 4096 : need, hipHostMallocDefault));
+      bytes = need < 4096 ? 4096 : need;
+    }
+    return static_cast<T*>(p);
+  }
+};
+HostScratch& host_scratch();
+
+template <class T>
+T read_scalar(const T* dptr, hipStream_t s) {
+  T* h = host_scratch().get<T>(1);
+  TPF_HIP(hipMemcpyAsync(h, dptr, sizeof(T), hipMemcpyDeviceToHost, s));
+  TPF_HIP(hipStreamSynchronize(s));
+  return *h;
+}
+
+// ---------------------------------------------------------------- sparse
+template <class T>
+struct Csr {
+  int nrows = 0, ncols = 0;
+  int64_t nnz = 0;
+  Buf<int> rp, ci;
+  Buf<T> v;
+  size_t bytes() const { return rp.bytes() + ci.bytes() + v.bytes(); }
+};
+
+// Non-owning view used by kernels (lets FP32 value copies share a pattern).
+template <class T>
+struct CsrRef {
+  int nrows = 0, ncols = 0;
+  int64_t nnz = 0;
+  const int* rp = nullptr;
+  const int* ci = nullptr;
+  const T* v = nullptr;
+};
+template <class T>
+inline CsrRef<T> ref(const Csr<T>& A) {
+  return CsrRef<T>{A.nrows, A.ncols, A.nnz, A.rp.p, A.ci.p, A.v.p};
+}
+template <class T, class U>
+inline CsrRef<T> ref_with(const Csr<U>& A, const T* v) {
+  return CsrRef<T>{A.nrows, A.ncols, A.nnz, A.rp.p, A.ci.p, v};
+}
+
+// ---------------------------------------------------------------- kernel timing
+struct TimedScope {
+  const char* name;
+  hipStream_t s;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  TimedScope(const char* n, hipStream_t st);
+  ~TimedScope();
+};
+bool timing_enabled();
+
+inline unsigned grid_for(int64_t n, int block) {
+  int64_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  return static_cast<unsigned>(g);
+}
+
+// ---------------------------------------------------------------- utilities (linalg.hip)
+// exclusive scan of n ints into out[0..n], out[n] = total; returns total (synchronises)
+int64_t scan_exclusive(const int* in, int* out, int64_t n, hipStream_t s);
+int64_t scan_exclusive64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);
+void fill_int(int* p, int v, int64_t n, hipStream_t s);
+template <class T> void fill(T* p, T v, int64_t n, hipStream_t s);
+template <class T> void copy(T* dst, const T* src, int64_t n, hipStream_t s);
+template <class A, class B> void cast(B* dst, const A* src, int64_t n, hipStream_t s);
+
+// deterministic reductions: result written to device memory *out
+void dot_device(const double* x, const double* y, int64_t n, double* out, hipStream_t s);
+double nrm2_host(const double* x, int64_t n, hipStream_t s);
+
+template <class T>
+void csr_spmv(const CsrRef<T>& A, const T* x, T* y, hipStream_t s, const char* tname = "csr_spmv");
+// y = b - A x (CSR)
+template <class T>
+void csr_residual(const CsrRef<T>& A, const T* x, const T* b, T* y, hipStream_t s);
+
+// ---------------------------------------------------------------- spgemm / transpose
+// C = alpha * A * B (+ beta * D on the union pattern if D != nullptr).  When
+// reuse is true, C's pattern is kept and only values are recomputed.
+void spgemm(const CsrRef<double>& A, const CsrRef<double>& B, Csr<double>& C, hipStream_t s,
+            const CsrRef<double>* D = nullptr, double alpha = 1.0, double beta = 1.0,
+            bool reuse = false);
+// C = A^T (values copied when A.v != nullptr); rows of C sorted by column
+void transpose(const CsrRef<double>& A, Csr<double>& C, hipStream_t s);
+
+}  // namespace tpf

@@ -1,0 +1,101 @@
+"""Device-side plumbing around the C ABI: uploads a workload's arrays to
+torch CUDA tensors and drives assemble / setup / solve through the binding.
+No solver arithmetic happens here."""
+from __future__ import annotations
+
+import numpy as np
+
+from . import tpf
+
+
+class GpuCase:
+    """A problem, its Jacobian and its state resident on the GPU."""
+
+    def __init__(self, case, stream=None):
+        import torch
+        tpf.init()
+        self.case = case
+        self.stream = stream
+        dev = torch.device("cuda")
+        f64 = torch.float64
+        self.N = case.N
+        self.kx = torch.as_tensor(case.kx, dtype=f64, device=dev).contiguous()
+        self.ky = torch.as_tensor(case.ky, dtype=f64, device=dev).contiguous()
+        self.kz = torch.as_tensor(case.kz, dtype=f64, device=dev).contiguous()
+        self.poro = torch.as_tensor(case.poro, dtype=f64, device=dev).contiguous()
+        self.q = torch.as_tensor(np.ascontiguousarray(case.q).reshape(-1), dtype=f64, device=dev)
+        self.u = torch.as_tensor(np.ascontiguousarray(case.u).reshape(-1), dtype=f64, device=dev).clone()
+        self.u_old = torch.as_tensor(np.ascontiguousarray(case.u_old).reshape(-1), dtype=f64,
+                                     device=dev).clone()
+        self.R = torch.zeros(2 * self.N, dtype=f64, device=dev)
+        self.prob = tpf.tpf_problem_create(
+            case.nx, case.ny, case.nz, case.hx, case.hy, case.hz, self.kx, self.ky, self.kz,
+            self.poro, case.mu_w, case.mu_n, case.rho_w, case.rho_n, case.grav, case.pc_model,
+            case.bc_lambda, case.swr, case.snr, case.pd, case.s_eps, q=self.q,
+            prod_cells=case.prod_cells, prod_wi=case.prod_wi, prod_pbh=case.prod_pbh,
+            dir_cells=case.dir_cells, dir_face=case.dir_face, dir_p=case.dir_p, dir_s=case.dir_s,
+            stream=stream)
+        self.J = tpf.tpf_jacobian_create(self.prob, stream=stream)
+
+    def assemble(self):
+        tpf.tpf_assemble(self.prob, self.u, self.u_old, self.case.dt, self.R, self.J,
+                         stream=self.stream)
+
+    def rhs(self):
+        return -self.R
+
+    def bcsr_numpy(self):
+        v = tpf.tpf_jacobian_view(self.J)
+        rp = tpf.device_array(v.row_ptr, v.n_block_rows + 1, np.int32)
+        ci = tpf.device_array(v.col_idx, int(v.nnzb), np.int32)
+        vals = tpf.device_array(v.vals, 4 * int(v.nnzb), np.float64).reshape(-1, 2, 2)
+        return rp, ci, vals
+
+    def close(self):
+        if self.J is not None:
+            tpf.tpf_jacobian_destroy(self.J)
+            self.J = None
+        if self.prob is not None:
+            tpf.tpf_problem_destroy(self.prob)
+            self.prob = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class GpuPrecond:
+    def __init__(self, kind, precision=tpf.TPF_FP64, **opts):
+        o = tpf.tpf_precond_default_opts(tpf.KINDS[kind] if isinstance(kind, str) else kind)
+        o.precision = precision
+        for k, v in opts.items():
+            setattr(o, k, v)
+        self.opts = o
+        self.M = tpf.tpf_precond_create(o)
+
+    def setup(self, gcase, reuse=False):
+        tpf.tpf_precond_setup(self.M, gcase.J, int(reuse), stream=gcase.stream)
+
+    def apply(self, r, z, stream=None):
+        tpf.tpf_precond_apply(self.M, r, z, stream=stream)
+
+    def stats(self):
+        return tpf.tpf_precond_stats(self.M)
+
+    def close(self):
+        if self.M is not None:
+            tpf.tpf_precond_destroy(self.M)
+            self.M = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve(gcase, M, b, x, rtol=1e-8, restart=30, maxit=1000):
+    return tpf.tpf_solve(gcase.J, M.M if M is not None else None, b, x, rtol=rtol,
+                         restart=restart, maxit=maxit, stream=gcase.stream)

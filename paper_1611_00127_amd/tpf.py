@@ -1,0 +1,383 @@
+"""Thin Python binding of libtpf (include/tpf.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls and does no
+arithmetic of its own.  Device arrays are torch CUDA tensors (float64,
+contiguous); host arrays are numpy arrays.  Device memory of the library is
+drawn from torch's caching allocator.  Importing this module fails loudly
+when the HIP library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtpf.so")
+
+# ---- constants (mirror include/tpf.h) -------------------------------------
+TPF_OK = 0
+TPF_PC_BROOKS_COREY, TPF_PC_LINEAR = 0, 1
+TPF_PREC_AMG, TPF_PREC_CPR1, TPF_PREC_CPR2, TPF_PREC_BF, TPF_PREC_NONE = 0, 1, 2, 3, 4
+TPF_FP64, TPF_FP32 = 0, 1
+TPF_CONVERGED, TPF_MAX_ITERS, TPF_BREAKDOWN, TPF_NONFINITE = 0, 1, 2, 3
+TPF_MAT_A, TPF_MAT_P, TPF_MAT_R, TPF_MAT_S, TPF_MAT_APS, TPF_MAT_SCHUR = 0, 1, 2, 3, 10, 11
+TPF_MAX_LEVELS = 25
+KINDS = {"amg": TPF_PREC_AMG, "cpr1": TPF_PREC_CPR1, "cpr2": TPF_PREC_CPR2, "bf": TPF_PREC_BF,
+         "none": TPF_PREC_NONE}
+
+c_int, c_double, c_void_p, c_size_t = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
+c_int64, c_uint64 = ctypes.c_int64, ctypes.c_uint64
+P_int, P_double = ctypes.POINTER(c_int), ctypes.POINTER(c_double)
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [("nx", c_int), ("ny", c_int), ("nz", c_int),
+                ("hx", c_double), ("hy", c_double), ("hz", c_double),
+                ("kx", c_void_p), ("ky", c_void_p), ("kz", c_void_p), ("poro", c_void_p),
+                ("mu_w", c_double), ("mu_n", c_double),
+                ("rho_w", c_double), ("rho_n", c_double), ("grav", c_double),
+                ("pc_model", c_int), ("bc_lambda", c_double), ("swr", c_double), ("snr", c_double),
+                ("pd", c_double), ("s_eps", c_double), ("q", c_void_p),
+                ("n_prod", c_int), ("prod_cells", P_int), ("prod_wi", P_double), ("prod_pbh", P_double),
+                ("n_dir", c_int), ("dir_cells", P_int), ("dir_face", P_int),
+                ("dir_p", P_double), ("dir_s", P_double)]
+
+
+class BcsrView(ctypes.Structure):
+    _fields_ = [("n_block_rows", c_int), ("nnzb", c_int64), ("row_ptr", c_void_p),
+                ("col_idx", c_void_p), ("vals", c_void_p)]
+
+
+class CsrView(ctypes.Structure):
+    _fields_ = [("n_rows", c_int), ("n_cols", c_int), ("nnz", c_int64), ("row_ptr", c_void_p),
+                ("col_idx", c_void_p), ("vals", c_void_p)]
+
+
+class PrecondOpts(ctypes.Structure):
+    _fields_ = [("kind", c_int), ("precision", c_int), ("theta", c_double), ("max_levels", c_int),
+                ("coarse_max", c_int), ("dense_max", c_int), ("hash_seed", c_uint64)]
+
+
+class HierStats(ctypes.Structure):
+    _fields_ = [("n_hier", c_int), ("levels", c_int * 3),
+                ("rows", (c_int64 * TPF_MAX_LEVELS) * 3), ("nnz", (c_int64 * TPF_MAX_LEVELS) * 3),
+                ("operator_complexity", c_double * 3), ("grid_complexity", c_double * 3),
+                ("coarse_dense", c_int * 3), ("device_bytes", c_size_t)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("rtol", c_double), ("restart", c_int), ("maxit", c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("status", c_int), ("iterations", c_int), ("relres_est", c_double),
+                ("relres_true", c_double), ("ms", c_double)]
+
+
+class TpfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"tpf error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+_alloc_cb = None
+_free_cb = None
+
+_SIGS = {
+    "tpf_status_string": (ctypes.c_char_p, [c_int]),
+    "tpf_last_error": (c_int, [ctypes.c_char_p, c_size_t]),
+    "tpf_set_allocator": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "tpf_memory_in_use": (c_int, [ctypes.POINTER(c_size_t)]),
+    "tpf_problem_create": (c_int, [ctypes.POINTER(ProblemDesc), c_void_p, ctypes.POINTER(c_void_p)]),
+    "tpf_problem_destroy": (c_int, [c_void_p]),
+    "tpf_problem_cells": (c_int, [c_void_p, ctypes.POINTER(c_int64)]),
+    "tpf_jacobian_create": (c_int, [c_void_p, c_void_p, ctypes.POINTER(c_void_p)]),
+    "tpf_jacobian_destroy": (c_int, [c_void_p]),
+    "tpf_assemble": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_void_p]),
+    "tpf_jacobian_view": (c_int, [c_void_p, ctypes.POINTER(BcsrView)]),
+    "tpf_spmv": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "tpf_newton_update": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "tpf_precond_default_opts": (c_int, [c_int, ctypes.POINTER(PrecondOpts)]),
+    "tpf_precond_create": (c_int, [ctypes.POINTER(PrecondOpts), ctypes.POINTER(c_void_p)]),
+    "tpf_precond_destroy": (c_int, [c_void_p]),
+    "tpf_precond_setup": (c_int, [c_void_p, c_void_p, c_int, c_void_p]),
+    "tpf_precond_apply": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "tpf_precond_stats": (c_int, [c_void_p, ctypes.POINTER(HierStats)]),
+    "tpf_precond_matrix": (c_int, [c_void_p, c_int, c_int, c_int, ctypes.POINTER(CsrView)]),
+    "tpf_precond_level_data": (c_int, [c_void_p, c_int, c_int, ctypes.POINTER(c_void_p),
+                                       ctypes.POINTER(c_void_p), ctypes.POINTER(c_int)]),
+    "tpf_precond_bilu_dinv": (c_int, [c_void_p, ctypes.POINTER(c_void_p)]),
+    "tpf_precond_vcycle": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
+    "tpf_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(SolveOpts),
+                          ctypes.POINTER(SolveInfo), c_void_p]),
+    "tpf_kernel_timing": (c_int, [c_int]),
+    "tpf_kernel_stats": (c_int, [ctypes.c_char_p, ctypes.POINTER(c_int64), ctypes.POINTER(c_double)]),
+    "tpf_kernel_stats_reset": (c_int, []),
+}
+
+
+def exported_symbols():
+    return sorted(_SIGS)
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Loads libtpf.so (no GPU needed) and declares every signature."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_1611_00127_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != TPF_OK:
+        buf = ctypes.create_string_buffer(1024)
+        _lib.tpf_last_error(buf, 1024)
+        raise TpfError(rc, buf.value.decode(errors="replace"))
+
+
+def _ptr(t):
+    """Device pointer of a contiguous torch tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def use_torch_allocator():
+    """Routes all library device allocations through torch's caching allocator."""
+    global _alloc_cb, _free_cb
+    import torch
+    lib = load()
+    ALLOC = ctypes.CFUNCTYPE(c_void_p, c_size_t, c_void_p, c_void_p)
+    FREE = ctypes.CFUNCTYPE(None, c_void_p, c_void_p, c_void_p)
+
+    def _a(nbytes, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+        except Exception:
+            return None
+
+    def _f(p, stream, ctx):
+        torch.cuda.caching_allocator_delete(int(p))
+
+    _alloc_cb, _free_cb = ALLOC(_a), FREE(_f)
+    _check(lib.tpf_set_allocator(ctypes.cast(_alloc_cb, c_void_p), ctypes.cast(_free_cb, c_void_p), None))
+
+
+def init():
+    """Loads the library for GPU use; raises if HIP/torch has no device."""
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the HIP library needs an MI355X (gfx950)")
+    load()
+    if _alloc_cb is None:
+        use_torch_allocator()
+    return _lib
+
+
+# ---- entry points (same names as the C ABI) --------------------------------
+
+def tpf_status_string(code):
+    return load().tpf_status_string(code).decode()
+
+
+def tpf_memory_in_use():
+    v = c_size_t()
+    _check(load().tpf_memory_in_use(ctypes.byref(v)))
+    return v.value
+
+
+def tpf_problem_create(nx, ny, nz, hx, hy, hz, kx, ky, kz, poro, mu_w, mu_n, rho_w, rho_n, grav,
+                       pc_model, bc_lambda, swr, snr, pd, s_eps, q=None,
+                       prod_cells=None, prod_wi=None, prod_pbh=None,
+                       dir_cells=None, dir_face=None, dir_p=None, dir_s=None, stream=None):
+    lib = init()
+    keep = []
+
+    def host(a, dt, ct):
+        if a is None or len(a) == 0:
+            return None, 0
+        arr = np.ascontiguousarray(a, dtype=dt)
+        keep.append(arr)
+        return arr.ctypes.data_as(ctypes.POINTER(ct)), len(arr)
+
+    pc, npc = host(prod_cells, np.int32, c_int)
+    pw, _ = host(prod_wi, np.float64, c_double)
+    pb, _ = host(prod_pbh, np.float64, c_double)
+    dc, ndc = host(dir_cells, np.int32, c_int)
+    df, _ = host(dir_face, np.int32, c_int)
+    dpv, _ = host(dir_p, np.float64, c_double)
+    dsv, _ = host(dir_s, np.float64, c_double)
+    d = ProblemDesc(nx, ny, nz, hx, hy, hz, _ptr(kx), _ptr(ky), _ptr(kz), _ptr(poro),
+                    mu_w, mu_n, rho_w, rho_n, grav, pc_model, bc_lambda, swr, snr, pd, s_eps,
+                    _ptr(q), npc, pc, pw, pb, ndc, dc, df, dpv, dsv)
+    out = c_void_p()
+    _check(lib.tpf_problem_create(ctypes.byref(d), _stream(stream), ctypes.byref(out)))
+    return out
+
+
+def tpf_problem_destroy(p):
+    _check(load().tpf_problem_destroy(p))
+
+
+def tpf_jacobian_create(p, stream=None):
+    out = c_void_p()
+    _check(load().tpf_jacobian_create(p, _stream(stream), ctypes.byref(out)))
+    return out
+
+
+def tpf_jacobian_destroy(J):
+    _check(load().tpf_jacobian_destroy(J))
+
+
+def tpf_assemble(p, u, u_old, dt, residual, J, stream=None):
+    _check(load().tpf_assemble(p, _ptr(u), _ptr(u_old), dt, _ptr(residual), J, _stream(stream)))
+
+
+def tpf_jacobian_view(J):
+    v = BcsrView()
+    _check(load().tpf_jacobian_view(J, ctypes.byref(v)))
+    return v
+
+
+def tpf_spmv(J, x, y, stream=None):
+    _check(load().tpf_spmv(J, _ptr(x), _ptr(y), _stream(stream)))
+
+
+def tpf_newton_update(p, u, delta, stream=None):
+    _check(load().tpf_newton_update(p, _ptr(u), _ptr(delta), _stream(stream)))
+
+
+def tpf_precond_default_opts(kind):
+    o = PrecondOpts()
+    _check(load().tpf_precond_default_opts(kind, ctypes.byref(o)))
+    return o
+
+
+def tpf_precond_create(opts):
+    out = c_void_p()
+    _check(load().tpf_precond_create(ctypes.byref(opts), ctypes.byref(out)))
+    return out
+
+
+def tpf_precond_destroy(M):
+    _check(load().tpf_precond_destroy(M))
+
+
+def tpf_precond_setup(M, J, reuse_structure=0, stream=None):
+    _check(load().tpf_precond_setup(M, J, int(reuse_structure), _stream(stream)))
+
+
+def tpf_precond_apply(M, r, z, stream=None):
+    _check(load().tpf_precond_apply(M, _ptr(r), _ptr(z), _stream(stream)))
+
+
+def tpf_precond_stats(M):
+    s = HierStats()
+    _check(load().tpf_precond_stats(M, ctypes.byref(s)))
+    return s
+
+
+def tpf_precond_matrix(M, hier, level, which):
+    v = CsrView()
+    _check(load().tpf_precond_matrix(M, hier, level, which, ctypes.byref(v)))
+    return v
+
+
+def tpf_precond_level_data(M, hier, level):
+    cf, dinv, n = c_void_p(), c_void_p(), c_int()
+    _check(load().tpf_precond_level_data(M, hier, level, ctypes.byref(cf), ctypes.byref(dinv),
+                                         ctypes.byref(n)))
+    return cf.value, dinv.value, n.value
+
+
+def tpf_precond_bilu_dinv(M):
+    p = c_void_p()
+    _check(load().tpf_precond_bilu_dinv(M, ctypes.byref(p)))
+    return p.value
+
+
+def tpf_precond_vcycle(M, hier, b, x, stream=None):
+    _check(load().tpf_precond_vcycle(M, hier, _ptr(b), _ptr(x), _stream(stream)))
+
+
+def tpf_solve(J, M, b, x, rtol=1e-8, restart=30, maxit=1000, stream=None):
+    o = SolveOpts(rtol, restart, maxit)
+    info = SolveInfo()
+    _check(load().tpf_solve(J, M, _ptr(b), _ptr(x), ctypes.byref(o), ctypes.byref(info),
+                            _stream(stream)))
+    return info
+
+
+def tpf_kernel_timing(enable):
+    _check(load().tpf_kernel_timing(int(bool(enable))))
+
+
+def tpf_kernel_stats(name):
+    cnt, ms = c_int64(), c_double()
+    _check(load().tpf_kernel_stats(name.encode(), ctypes.byref(cnt), ctypes.byref(ms)))
+    return cnt.value, ms.value
+
+
+def tpf_kernel_stats_reset():
+    _check(load().tpf_kernel_stats_reset())
+
+
+# ---- device <-> host copies of library-owned arrays (marshalling) -----------
+
+def device_array(ptr, count, dtype):
+    """Copies `count` elements of a library-owned device array to numpy."""
+    import torch
+    tdt = {np.int32: torch.int32, np.float64: torch.float64, np.int8: torch.int8,
+           np.uint8: torch.uint8, np.float32: torch.float32}[dtype]
+    out = torch.empty(count, dtype=tdt)
+    if count == 0:
+        return out.numpy()
+    import ctypes as ct
+    hip = _hip_runtime()
+    torch.cuda.synchronize()
+    rc = hip.hipMemcpy(ct.c_void_p(out.data_ptr()), ct.c_void_p(ptr), ct.c_size_t(count * out.element_size()), 2)
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy failed: {rc}")
+    return out.numpy()
+
+
+_hip = None
+
+
+def _hip_runtime():
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.restype = c_int
+        _hip.hipMemcpy.argtypes = [c_void_p, c_void_p, c_size_t, c_int]
+    return _hip
+
+
+def csr_to_numpy(view):
+    """(row_ptr, col_idx, vals or None) numpy copies of a tpf_csr_view."""
+    rp = device_array(view.row_ptr, view.n_rows + 1, np.int32)
+    ci = device_array(view.col_idx, int(view.nnz), np.int32)
+    v = device_array(view.vals, int(view.nnz), np.float64) if view.vals else None
+    return rp, ci, v
