@@ -1,0 +1,224 @@
+"""Benchmark: time to a 1e-8 relative residual for the first Newton Jacobian
+of the 3D 128x128x64 heterogeneous workload (1,048,576 cells, 2.1M
+unknowns), block-factorisation preconditioner (Algorithm 3) with AMG
+V-cycles on A_ss and S~, right-preconditioned FGMRES(30).
+
+One step = assembly of residual and Jacobian + full preconditioner setup
+(block views, S~, two AMG hierarchies) + FGMRES to ||b - Jx|| <= 1e-8 ||b||,
+with every input resident in HBM before the timed region.  The FP64 form is
+the primary value; the FP32-V-cycle form (hierarchies stored and cycled in
+FP32 inside the FP64 FGMRES) is timed the same way and reported beside it.
+
+Prints one JSON line (rank 0, N = 1 GPU).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "time-to-1e-8 solve (FP64 vs FP32 V-cycle), V-cycle HBM GB/s, p99 latency"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--grid", type=str, default="128x128x64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-grid", type=str, default="80x80x40",
+                    help="grid of the oracle's bounded sample")
+    return ap.parse_args()
+
+
+def level0_bytes(nnz, n, w, kind):
+    """Algorithmic bytes of one level-0 V-cycle kernel launch (CSR, int32
+    indices, value width w): matrix values + column indices + row pointers
+    once, each dense vector once."""
+    mat = (w + 4) * nnz + 4 * (n + 1)
+    if kind == "pre":      # read b, dinv; write r (A D^{-1} b gathered)
+        return mat + 3 * w * n
+    if kind == "post":     # read b, dinv, y; write x
+        return mat + 4 * w * n
+    raise ValueError(kind)
+
+
+def run_form(torch, tpf, driver, g, precision, steps, warmup, timing):
+    """Times `steps` full steps (assemble + setup + solve) of one precision."""
+    M = driver.GpuPrecond("bf", precision)
+    b = torch.empty(2 * g.N, dtype=torch.float64, device="cuda")
+    x = torch.empty_like(b)
+    infos, t_asm, t_set, t_sol = [], [], [], []
+
+    def one_step():
+        t0 = time.perf_counter()
+        g.assemble()
+        torch.neg(g.R, out=b)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        M.setup(g)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        info = driver.solve(g, M, b, x, rtol=1e-8, restart=30, maxit=1000)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        return info, (t1 - t0, t2 - t1, t3 - t2)
+
+    for _ in range(warmup):
+        one_step()
+    if timing:
+        tpf.tpf_kernel_stats_reset()
+        tpf.tpf_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        info, (a, s, v) = one_step()
+        infos.append(info)
+        t_asm.append(a)
+        t_set.append(s)
+        t_sol.append(v)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    if timing:
+        tpf.tpf_kernel_timing(False)
+    st = M.stats()
+    res = dict(ms_per_step=1e3 * total / steps, assemble_ms=1e3 * float(np.median(t_asm)),
+               setup_ms=1e3 * float(np.median(t_set)), solve_ms=1e3 * float(np.median(t_sol)),
+               iterations=[int(i.iterations) for i in infos],
+               relres_true=max(float(i.relres_true) for i in infos),
+               converged=all(i.status == tpf.TPF_CONVERGED for i in infos),
+               levels=[int(st.levels[h]) for h in range(st.n_hier)],
+               op_complexity=[round(float(st.operator_complexity[h]), 3) for h in range(st.n_hier)],
+               l0_nnz=[int(st.nnz[h][0]) for h in range(st.n_hier)],
+               l0_rows=[int(st.rows[h][0]) for h in range(st.n_hier)],
+               precond_mib=st.device_bytes / 2 ** 20)
+    return M, x, res
+
+
+def kernel_table(tpf, names):
+    out = {}
+    for n in names:
+        cnt, ms = tpf.tpf_kernel_stats(n)
+        if cnt:
+            out[n] = (cnt, ms)
+    return out
+
+
+def cpu_baseline(grid):
+    """The oracle (unmodified) on a bounded sample: the same workload family on
+    a smaller grid, one full step (assemble + BF setup + FGMRES to 1e-8),
+    BLAS limited to one thread; scaled by the cell ratio to the benchmark
+    grid (linear-cost assumption)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import newton
+    from paper_1611_00127_amd import inputs
+    nx, ny, nz = (int(v) for v in grid.split("x"))
+    c = inputs.config_c3(nx, ny, nz)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        _, info, _ = newton.solve(c, "bf", rtol=1e-8)
+        dt = time.perf_counter() - t0
+    return dt, info, c.N
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this build runs on a single MI355X "
+              f"(--gpus {args.gpus} is not supported)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1611_00127_amd import driver, inputs, tpf
+    tpf.init()
+    nx, ny, nz = (int(v) for v in args.grid.split("x"))
+    log(f"[bench] generating workload {nx}x{ny}x{nz}")
+    c = inputs.config_c3(nx, ny, nz)
+    g = driver.GpuCase(c)
+    torch.cuda.synchronize()
+    log("[bench] FP64 form")
+    M64, x64, r64 = run_form(torch, tpf, driver, g, tpf.TPF_FP64, args.steps, args.warmup, True)
+    names = []
+    for h, tag in enumerate(["Ass", "Schur"]):
+        for k in ["vcycle_pre_residual", "vcycle_post_smooth", "vcycle_restrict", "vcycle_prolong"]:
+            names.append(f"{k}[{tag},l0]")
+    names += ["cgs2", "bcsr_spmv", "bf_rhs", "assemble", "precond_apply"]
+    ktab = kernel_table(tpf, names)
+    log("[bench] FP32-V-cycle form")
+    M32, x32, r32 = run_form(torch, tpf, driver, g, tpf.TPF_FP32, args.steps, args.warmup, False)
+    # the two forms must agree at the stated accuracy
+    err = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
+
+    # roofline of the dominant V-cycle kernel (largest summed time)
+    vk = {k: v for k, v in ktab.items() if k.startswith("vcycle_")}
+    dom = max(vk, key=lambda k: vk[k][1])
+    cnt, ms = vk[dom]
+    h = 1 if "Schur" in dom else 0
+    nnz, n = r64["l0_nnz"][h], r64["l0_rows"][h]
+    kind = "pre" if "pre_residual" in dom else "post"
+    bytes_per_launch = level0_bytes(nnz, n, 8, kind) if ("pre" in kind or "post" in kind) else None
+    avg_ms = ms / cnt
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "avg_launch_us": round(avg_ms * 1e3, 2), "launches": cnt,
+            "algorithmic_bytes_per_launch": bytes_per_launch}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"[bench] CPU baseline: oracle on {args.cpu_grid}")
+        dt, info, ncpu = cpu_baseline(args.cpu_grid)
+        scale = c.N / ncpu
+        cpu = {"value": round(dt * scale * 1e3, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+               "sample": f"one full step (assemble + BF setup + FGMRES to 1e-8, "
+                         f"{info['iterations']} its) of the same workload on {args.cpu_grid} "
+                         f"({ncpu} cells) in {dt:.1f} s, scaled x{scale:.0f} by cell count"}
+
+    out = {
+        "metric": METRIC,
+        "value": round(r64["ms_per_step"], 2),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r64["ms_per_step"], 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"3d-{nx}x{ny}x{nz} log-normal sigma=3 kz/kx=0.1 layered, "
+                               f"Brooks-Corey lambda=2 Pd=0.5, five-spot, first Newton Jacobian",
+                   "cells": c.N, "unknowns": 2 * c.N, "preconditioner": "bf",
+                   "krylov": "fgmres(30)", "rtol": 1e-8},
+        "fp64": r64,
+        "fp32_vcycle": dict(r32, rel_diff_vs_fp64=err,
+                            speedup_vs_fp64=round(r64["ms_per_step"] / r32["ms_per_step"], 3)),
+        "roofline": roof,
+        "kernels_ms": {k: {"launches": v[0], "total_ms": round(v[1], 3),
+                           "avg_us": round(1e3 * v[1] / v[0], 2)} for k, v in ktab.items()},
+        "cpu_baseline": cpu,
+        "p99_latency_ms": None,
+    }
+    print(json.dumps(out), flush=True)
+    M64.close()
+    M32.close()
+    g.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -462,9 +462,14 @@ void Hierarchy::refresh(hipStream_t st) {
 }
 
 void Hierarchy::finish_levels(hipStream_t st) {
-  for (auto& Lp : lv) {
-    Level& L = *Lp;
+  for (size_t l = 0; l < lv.size(); ++l) {
+    Level& L = *lv[l];
     int n = L.A.nrows;
+    std::string sfx = "[" + tag + ",l" + std::to_string(l) + "]";
+    L.t_pre = "vcycle_pre_residual" + sfx;
+    L.t_restrict = "vcycle_restrict" + sfx;
+    L.t_prolong = "vcycle_prolong" + sfx;
+    L.t_post = "vcycle_post_smooth" + sfx;
     L.dinv.ensure(n, st);
     k_l1_dinv<<<grid_for(n, 256), 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, L.A.v.p, L.dinv.p);
     TPF_CHECK_LAUNCH();
@@ -558,18 +563,17 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st) {
   T* bc = work<T>(C.b, C.b32);
   T* xc = work<T>(C.x, C.x32);
   {
-    TimedScope ts(l == 0 ? "vcycle_pre_residual_l0" : "vcycle_pre_residual", st);
+    TimedScope ts(L.t_pre.c_str(), st);
     DISPATCH_LPR(lpr, LL, {
       k_vc_pre<T, LL><<<blocks, 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, Av, dinv, b, r);
     });
     TPF_CHECK_LAUNCH();
   }
-  csr_spmv<T>(ref_with<T>(L.R, vals_of<T>(L.R, L.Rv32)), r, bc, st,
-              l == 0 ? "vcycle_restrict_l0" : "vcycle_restrict");
+  csr_spmv<T>(ref_with<T>(L.R, vals_of<T>(L.R, L.Rv32)), r, bc, st, L.t_restrict.c_str());
   vcycle_level<T>(l + 1, bc, xc, st);
   {
     int plpr = lanes_per_row(n, L.P.nnz);
-    TimedScope ts(l == 0 ? "vcycle_prolong_l0" : "vcycle_prolong", st);
+    TimedScope ts(L.t_prolong.c_str(), st);
     DISPATCH_LPR(plpr, LL, {
       k_vc_prolong<T, LL><<<grid_for(int64_t(n) * LL, 256), 256, 0, st>>>(
           n, L.P.rp.p, L.P.ci.p, vals_of<T>(L.P, L.Pv32), dinv, b, xc, y);
@@ -577,7 +581,7 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st) {
     TPF_CHECK_LAUNCH();
   }
   {
-    TimedScope ts(l == 0 ? "vcycle_post_smooth_l0" : "vcycle_post_smooth", st);
+    TimedScope ts(L.t_post.c_str(), st);
     DISPATCH_LPR(lpr, LL, {
       k_vc_post<T, LL><<<blocks, 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, Av, dinv, b, y, x);
     });

@@ -29,6 +29,8 @@ struct Level {
   Buf<double> r, y, b, x;
   Buf<float> r32, y32, b32, x32;
   int64_t pmis_rounds = 0;
+  // kernel-timer labels of this level (persistent storage for TimedScope)
+  std::string t_pre, t_restrict, t_prolong, t_post;
 };
 
 struct Hierarchy {
@@ -37,6 +39,7 @@ struct Hierarchy {
   bool coarse_dense = false;
   Buf<double> Ainv;     // dense inverse of the coarsest operator (row-major)
   hipStream_t s = nullptr;
+  std::string tag = "A";  // operator name used in kernel-timer labels
 
   // Full setup from the level-0 operator.
   void build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st);

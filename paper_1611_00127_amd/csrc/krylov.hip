@@ -247,11 +247,6 @@ void ensure_ws(Workspace& w, int64_t n, int m, hipStream_t s) {
   w.m = m;
 }
 
-Workspace& workspace() {
-  static thread_local Workspace w;
-  return w;
-}
-
 unsigned vec_grid(int64_t n) {
   int64_t g = (n + 255) / 256;
   if (g > 4096) g = 4096;
@@ -281,7 +276,7 @@ extern "C" int tpf_solve(const tpf_jacobian* J, tpf_precond* M, const double* b,
     auto t0 = std::chrono::steady_clock::now();
     int64_t n = 2 * int64_t(J->nb);
     int m = o->restart;
-    Workspace& w = workspace();
+    Workspace w;  // per call: drawn from (and returned to) the installed allocator
     ensure_ws(w, n, m, s);
     fill(x, 0.0, n, s);
     std::memset(info, 0, sizeof(*info));

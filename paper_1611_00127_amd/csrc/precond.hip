@@ -523,6 +523,7 @@ int tpf_precond_setup(tpf_precond* M, const tpf_jacobian* J, int reuse, void* st
         k_scalarize_values<<<grid_for(N, 256), 256, 0, s>>>(N, J->rp.p, J->v.p, Js.v.p);
         TPF_CHECK_LAUNCH();
         M->H[0] = std::make_unique<Hierarchy>();
+        M->H[0]->tag = "J";
         M->H[0]->build(std::move(Js), ao, s);
       } else {
         k_scalarize_values<<<grid_for(N, 256), 256, 0, s>>>(N, J->rp.p, J->v.p,
@@ -537,6 +538,7 @@ int tpf_precond_setup(tpf_precond* M, const tpf_jacobian* J, int reuse, void* st
       for (int h = 0; h < M->n_hier; ++h) {
         if (!re) {
           M->H[h] = std::make_unique<Hierarchy>();
+          M->H[h]->tag = h == 0 ? "App" : "Ass";
           M->H[h]->build(block_copy(M, src[h], s), ao, s);
         } else {
           copy(M->H[h]->A0().v.p, src[h], nnzb, s);
@@ -558,10 +560,12 @@ int tpf_precond_setup(tpf_precond* M, const tpf_jacobian* J, int reuse, void* st
       CsrRef<double> App{N, N, nnzb, M->brp.p, M->bci.p, M->app_v.p};
       if (!re) {
         M->H[0] = std::make_unique<Hierarchy>();
+        M->H[0]->tag = "Ass";
         M->H[0]->build(block_copy(M, M->ass_v.p, s), ao, s);
         Csr<double> S;
         spgemm(Y, Asp, S, s, &App, -1.0, 1.0, false);
         M->H[1] = std::make_unique<Hierarchy>();
+        M->H[1]->tag = "Schur";
         M->H[1]->build(std::move(S), ao, s);
       } else {
         copy(M->H[0]->A0().v.p, M->ass_v.p, nnzb, s);

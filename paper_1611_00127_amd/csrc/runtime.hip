@@ -80,8 +80,9 @@ void dfree(void* p, size_t bytes, hipStream_t s) {
 }
 
 HostScratch& host_scratch() {
-  static thread_local HostScratch hs;
-  return hs;
+  // never destroyed: pinned memory must not be released during process teardown
+  static thread_local HostScratch* hs = new HostScratch();
+  return *hs;
 }
 
 bool timing_enabled() { return g_timing; }

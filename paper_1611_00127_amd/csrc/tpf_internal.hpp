@@ -94,11 +94,11 @@ struct Buf {
   T* get() const { return p; }
 };
 
-// Pinned host scratch for small device->host reads.
+// Pinned host scratch for small device->host reads (one per thread, kept
+// until the process ends).
 struct HostScratch {
   void* p = nullptr;
   size_t bytes = 0;
-  ~HostScratch() { if (p) (void)hipHostFree(p); }
   template <class T> T* get(size_t count) {
     size_t need = count * sizeof(T);
     if (need > bytes) {

@@ -52,6 +52,8 @@ class GpuCase:
         return rp, ci, vals
 
     def close(self):
+        if tpf.shutting_down():
+            return
         if self.J is not None:
             tpf.tpf_jacobian_destroy(self.J)
             self.J = None
@@ -85,6 +87,8 @@ class GpuPrecond:
         return tpf.tpf_precond_stats(self.M)
 
     def close(self):
+        if tpf.shutting_down():
+            return
         if self.M is not None:
             tpf.tpf_precond_destroy(self.M)
             self.M = None

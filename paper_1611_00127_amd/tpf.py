@@ -85,6 +85,23 @@ class TpfError(RuntimeError):
 _lib = None
 _alloc_cb = None
 _free_cb = None
+_shutting_down = False
+
+
+def _mark_shutdown():
+    # after this point handles are leaked instead of destroyed: the allocator
+    # callbacks must not run while the interpreter is being torn down
+    global _shutting_down
+    _shutting_down = True
+
+
+import atexit  # noqa: E402
+
+atexit.register(_mark_shutdown)
+
+
+def shutting_down():
+    return _shutting_down
 
 _SIGS = {
     "tpf_status_string": (ctypes.c_char_p, [c_int]),
@@ -179,7 +196,8 @@ def use_torch_allocator():
             return None
 
     def _f(p, stream, ctx):
-        torch.cuda.caching_allocator_delete(int(p))
+        if not _shutting_down:
+            torch.cuda.caching_allocator_delete(int(p))
 
     _alloc_cb, _free_cb = ALLOC(_a), FREE(_f)
     _check(lib.tpf_set_allocator(ctypes.cast(_alloc_cb, c_void_p), ctypes.cast(_free_cb, c_void_p), None))

@@ -67,9 +67,7 @@ def test_assembly_parity(gpu, name):
     rp, ci, vals = g.bcsr_numpy()
     orp, oci, ov = tpfa.jacobian(c, c.u, c.u_old)
     assert np.array_equal(rp, orp) and np.array_equal(ci, oci), "BCSR pattern must be bit-exact"
-    ok, worst = _row_scale_close(vals.reshape(-1, 4), ov.reshape(-1, 4), np.repeat(orp, 1), 1e-12) \
-        if False else (True, 0.0)
-    # per block row scale
+    # values: 1e-12 relative to the largest entry of the block row
     N = c.N
     brow = np.repeat(np.arange(N), np.diff(orp))
     scale = np.zeros(N)
@@ -279,9 +277,11 @@ def test_solve_parity_c1(gpu, kind):
 
 @pytest.mark.parametrize("kind", ["bf", "cpr2", "amg"])
 def test_fp32_vcycle_form_reaches_fp64_accuracy(gpu, kind):
+    """FP32 hierarchies and V-cycles inside FP64 FGMRES reach the same 1e-8
+    true residual; the error against the FP64 oracle solution is reported.
+    (Physical first-Newton-Jacobian state of the 3D workload family.)"""
     driver, tpf, torch = gpu
-    c = inputs.small_case(24, 24, 8, seed=15)
-    c = inputs.random_state(c, 16, s_lo=0.15, s_hi=0.85)
+    c = inputs.config_c3(32, 32, 16)
     say(f"[fp32] kind={kind}")
     g, M = _setup(driver, tpf, c, kind, precision=tpf.TPF_FP32)
     b = g.rhs().contiguous()
@@ -297,6 +297,7 @@ def test_fp32_vcycle_form_reaches_fp64_accuracy(gpu, kind):
     xo, io = fgmres.fgmres(lambda v: J @ v, Mo.apply, bn, rtol=1e-8)
     err = np.linalg.norm(xs - xo) / np.linalg.norm(xo)
     say(f"  fp32 its={info.iterations} oracle(fp64) its={io['iterations']} err={err:.2e}")
+    assert io["status"] == fgmres.CONVERGED
     assert err <= 1e-5
     M.close(); g.close()
 
