@@ -130,8 +130,12 @@ int tpf_jacobian_view(const tpf_jacobian* J, tpf_bcsr_view* out);
 
 /* y = J x (x, y device 2N). */
 int tpf_spmv(const tpf_jacobian* J, const double* x, double* y, void* stream);
-/* Newton update u += delta with S_n clamped to [0,1] (device 2N). */
-int tpf_newton_update(tpf_problem* p, double* u, const double* delta, void* stream);
+/* Newton update (Sec. 3; the paper's Newton variant is unspecified): each
+ * saturation increment is first limited to [-ds_max, ds_max] when
+ * ds_max > 0 (per-cell saturation chop), then u += delta and S_n is
+ * clamped to [0,1].  u, delta: device 2N. */
+int tpf_newton_update(tpf_problem* p, double* u, const double* delta, double ds_max,
+                      void* stream);
 
 /* ---- preconditioners (Sec. 3.2-3.4) ------------------------------------ */
 #define TPF_PREC_AMG 0   /* one V-cycle on the point-ordered scalar J (Sec. 3.2) */
@@ -139,6 +143,10 @@ int tpf_newton_update(tpf_problem* p, double* u, const double* delta, void* stre
 #define TPF_PREC_CPR2 2  /* Algorithm 2 (additive), + V-cycle on A_ss */
 #define TPF_PREC_BF 3    /* Algorithm 3, V-cycles on A_ss and on S~ */
 #define TPF_PREC_NONE 4  /* identity (tests) */
+
+#define TPF_INTERP_AUTO 0    /* extended+i for S~, A_pp and the scalar J; direct for A_ss */
+#define TPF_INTERP_DIRECT 1  /* direct (distance-one) interpolation everywhere */
+#define TPF_INTERP_EXTI 2    /* extended+i (distance-two) interpolation everywhere */
 
 #define TPF_FP64 0       /* hierarchy and V-cycle in FP64 */
 #define TPF_FP32 1       /* hierarchy stored and V-cycle/ILU solves run in FP32; coarsest in FP64 */
@@ -151,6 +159,7 @@ typedef struct tpf_precond_opts {
   int coarse_max;       /* stop coarsening at n <= coarse_max (256) */
   int dense_max;        /* dense LU on the coarsest level if n <= dense_max (1024),
                            else two l1-Jacobi sweeps */
+  int interp;           /* TPF_INTERP_* */
   uint64_t hash_seed;   /* seed of the PMIS tie-break weights */
 } tpf_precond_opts;
 /* Fills opts with the defaults above for the given kind. */

@@ -18,6 +18,14 @@ deterministic, data-parallel ones; this module states exactly those:
    same-signed off-diagonal entries (strong points always have the opposite
    sign, so the same-signed part is always lumped); C rows are injection,
    coarse points are numbered in ascending fine order;
+   or extended+i interpolation (De Sterck, Falgout, Nolting, Yang, 2008) for
+   an F point i: C^_i = (C n S_i) u (C n S_k over strong F neighbours k);
+   with a-bar_kl = a_kl when its sign is opposite to a_kk (else 0) and
+   d_ik = sum over l in C^_i u {i} of a-bar_kl,
+   w_ij = -(a_ij + sum_k a_ik a-bar_kj / d_ik) / a~_ii,
+   a~_ii = a_ii + (off-diagonal entries of row i that are neither in C^_i
+   nor strong F) + sum_k a_ik a-bar_ki / d_ik, and a strong F neighbour with
+   d_ik = 0 is lumped into a~_ii;
 4. R = P^T, A_c = R (A P) with the symbolic pattern (no dropping);
 5. stop when n <= coarse_max, n_c == 0, n_c > 0.9 n, or max_levels; the
    coarsest level is solved by dense LU with partial pivoting when it has at
@@ -154,6 +162,72 @@ def direct_interpolation(A, mask, cf):
     return P, cidx
 
 
+def extended_i_interpolation(A, mask, cf):
+    """Extended+i interpolation, one F row at a time (see module docstring)."""
+    A = A.tocsr()
+    n = A.shape[0]
+    rp, ci, av = A.indptr, A.indices, A.data
+    diag = A.diagonal()
+    s = diag_sign(A)
+    isc = cf == C_PT
+    cidx = np.cumsum(isc) - 1
+    nc = int(isc.sum())
+    r_out, c_out, v_out = [], [], []
+    for i in range(n):
+        if isc[i]:
+            r_out.append(i)
+            c_out.append(cidx[i])
+            v_out.append(1.0)
+            continue
+        row = range(rp[i], rp[i + 1])
+        strong_f = [e for e in row if mask[e] and ci[e] != i and not isc[ci[e]]]
+        chat = {int(ci[e]) for e in row if mask[e] and isc[ci[e]]}
+        for e in strong_f:
+            k = ci[e]
+            chat |= {int(ci[f]) for f in range(rp[k], rp[k + 1]) if mask[f] and isc[ci[f]]}
+        w = dict.fromkeys(chat, 0.0)
+        atil = diag[i]
+        sf = set(strong_f)
+        for e in row:
+            j = int(ci[e])
+            if j == i:
+                continue
+            if j in chat:
+                w[j] += av[e]
+            elif e not in sf:
+                atil += av[e]
+        for e in strong_f:
+            k = ci[e]
+            aik = av[e]
+            kr = range(rp[k], rp[k + 1])
+            d = sum(av[f] for f in kr
+                    if s[k] * av[f] < 0 and (int(ci[f]) in chat or ci[f] == i))
+            if d == 0.0:
+                atil += aik
+                continue
+            for f in kr:
+                l = int(ci[f])
+                if s[k] * av[f] < 0:
+                    if l in chat:
+                        w[l] += aik * av[f] / d
+                    elif l == i:
+                        atil += aik * av[f] / d
+        for j in sorted(chat):
+            r_out.append(i)
+            c_out.append(cidx[j])
+            v_out.append(-w[j] / atil)
+    P = sp.csr_matrix((np.array(v_out, float), (np.array(r_out, np.int64), np.array(c_out, np.int64))),
+                      shape=(n, nc))
+    P.sort_indices()
+    return P, cidx
+
+
+def interpolation(A, mask, cf, kind):
+    if kind == "ext+i":
+        return extended_i_interpolation(A, mask, cf)
+    return direct_interpolation(A, mask, cf)
+
+
 def galerkin(A, P):
     """A_c = R (A P), R = P^T, on the symbolic pattern (no dropping)."""
     R = P.T.tocsr()
@@ -190,8 +264,9 @@ class Hierarchy:
     """AMG hierarchy; ``levels[-1]`` is the coarsest."""
 
     def __init__(self, A, theta=0.25, coarse_max=256, max_levels=25, seed=0x5eed,
-                 dense_max=1024):
+                 dense_max=1024, interp="direct"):
         self.levels = []
+        self.interp = interp
         self.dense_max = dense_max
         A = A.tocsr()
         A.sort_indices()
@@ -205,7 +280,7 @@ class Hierarchy:
             nc = int((cf == C_PT).sum())
             if nc == 0 or nc > 0.9 * lvl.n:
                 break
-            P, _ = direct_interpolation(lvl.A, mask, cf)
+            P, _ = interpolation(lvl.A, mask, cf, interp)
             Ac, R = galerkin(lvl.A, P)
             lvl.mask, lvl.cf, lvl.P, lvl.R = mask, cf, P, R
             A = Ac

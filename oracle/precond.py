@@ -11,6 +11,10 @@
 Inner solves A^{-1} are one AMG V-cycle each (Sec. 4.1: one V-cycle), or
 exact sparse LU (``inner='exact'``) for the matrix-form checks.  P_1 is
 block ILU(0), or the exact inverse of J with ``p1='exact'``.
+
+AMG interpolation per operator (unless ``amg_opts['interp']`` is given):
+extended+i for the pressure-like operators (S~, A_pp, the scalar J) and
+direct interpolation for A_ss.
 """
 from __future__ import annotations
 
@@ -31,10 +35,12 @@ class Exact:
         return self.lu.solve(b)
 
 
-def inner_solver(A, inner, amg_opts):
+def inner_solver(A, inner, amg_opts, interp):
     if inner == "exact":
         return Exact(A)
-    return Hierarchy(A, **(amg_opts or {}))
+    opts = dict(amg_opts or {})
+    opts.setdefault("interp", interp)
+    return Hierarchy(A, **opts)
 
 
 class Preconditioner:
@@ -44,7 +50,7 @@ class Preconditioner:
         self.J = bcsr_matrix(row_ptr, col_idx, vals).tocsr()
         if kind == "amg":
             self.Js = blocks.scalarize(row_ptr, col_idx, vals)
-            self.H = inner_solver(self.Js, inner, amg_opts)
+            self.H = inner_solver(self.Js, inner, amg_opts, "ext+i")
             return
         self.App = blocks.block(row_ptr, col_idx, vals, 0, 0)
         self.Aps = blocks.block(row_ptr, col_idx, vals, 0, 1)
@@ -57,13 +63,13 @@ class Preconditioner:
             else:
                 self.P1 = Bilu0(row_ptr, col_idx, vals, *grid)
                 self.p1_apply = self.P1.apply
-            self.Hp = inner_solver(self.App, inner, amg_opts)
+            self.Hp = inner_solver(self.App, inner, amg_opts, "ext+i")
             if kind == "cpr2":
-                self.Hs = inner_solver(self.Ass, inner, amg_opts)
+                self.Hs = inner_solver(self.Ass, inner, amg_opts, "direct")
         elif kind == "bf":
             self.S = blocks.schur_simple(self.App, self.Aps, self.Asp, self.Ass)
-            self.Hs = inner_solver(self.Ass, inner, amg_opts)
-            self.Hschur = inner_solver(self.S, inner, amg_opts)
+            self.Hs = inner_solver(self.Ass, inner, amg_opts, "direct")
+            self.Hschur = inner_solver(self.S, inner, amg_opts, "ext+i")
         else:
             raise ValueError(kind)
 

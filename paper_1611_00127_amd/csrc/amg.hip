@@ -15,6 +15,7 @@
 //             a~_ii = a_ii + same-signed off-diagonals; C rows inject;
 //   Galerkin  A_c = R (A P), R = P^T, symbolic pattern;
 //   smoother  l1-Jacobi d_i = a_ii + s_i sum_{j!=i} |a_ij|.
+#include <climits>
 #include <cmath>
 #include <type_traits>
 
@@ -204,6 +205,144 @@ __global__ void k_interp_fill(int n, const int* __restrict__ rp, const int* __re
       pv[o] = -alpha * v[e] / atil;
       ++o;
     }
+  }
+}
+
+// ---------------------------------------------------------------- extended+i
+// Interpolation set of an F point i: strong C neighbours of i and of every
+// strong F neighbour k, merged in ascending fine index by advancing one
+// cursor per list (own row + one per strong F neighbour).  cur holds the
+// cursors, indexed like A's entries.
+__device__ inline int next_strong_c(int f, int end, const int* __restrict__ ci,
+                                    const uint8_t* __restrict__ mask,
+                                    const int8_t* __restrict__ cf) {
+  while (f < end && !(mask[f] && cf[ci[f]] == kC)) ++f;
+  return f;
+}
+
+template <bool FILL>
+__device__ inline int exti_merge(int i, const int* __restrict__ rp, const int* __restrict__ ci,
+                                 const uint8_t* __restrict__ mask, const int8_t* __restrict__ cf,
+                                 int2* __restrict__ cur, int* __restrict__ out) {
+  int a0 = rp[i], a1 = rp[i + 1];
+  int own = next_strong_c(a0, a1, ci, mask, cf);
+  for (int e = a0; e < a1; ++e) {
+    int k = ci[e];
+    if (mask[e] && k != i && cf[k] == kF) {
+      int k0 = rp[k], k1 = rp[k + 1];
+      cur[e] = make_int2(next_strong_c(k0, k1, ci, mask, cf), k1);
+    }
+  }
+  int count = 0;
+  while (true) {
+    int m = INT_MAX;
+    if (own < a1) m = ci[own];
+    for (int e = a0; e < a1; ++e) {
+      int k = ci[e];
+      if (mask[e] && k != i && cf[k] == kF) {
+        int2 c = cur[e];
+        if (c.x < c.y) {
+          int col = ci[c.x];
+          m = col < m ? col : m;
+        }
+      }
+    }
+    if (m == INT_MAX) break;
+    if (FILL) out[count] = m;
+    ++count;
+    if (own < a1 && ci[own] == m) own = next_strong_c(own + 1, a1, ci, mask, cf);
+    for (int e = a0; e < a1; ++e) {
+      int k = ci[e];
+      if (mask[e] && k != i && cf[k] == kF) {
+        int2 c = cur[e];
+        if (c.x < c.y && ci[c.x] == m) cur[e].x = next_strong_c(c.x + 1, c.y, ci, mask, cf);
+      }
+    }
+  }
+  return count;
+}
+
+__global__ void k_exti_count(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                             const uint8_t* __restrict__ mask, const int8_t* __restrict__ cf,
+                             int2* __restrict__ cur, int* __restrict__ cnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  cnt[i] = cf[i] == kC ? 1 : exti_merge<false>(i, rp, ci, mask, cf, cur, nullptr);
+}
+
+// position of fine index j in the sorted list c[0..len), or -1
+__device__ inline int find_sorted(const int* __restrict__ c, int len, int j) {
+  int lo = 0, hi = len - 1;
+  while (lo <= hi) {
+    int mid = (lo + hi) >> 1;
+    int v = c[mid];
+    if (v == j) return mid;
+    if (v < j) lo = mid + 1;
+    else hi = mid - 1;
+  }
+  return -1;
+}
+
+// weights: w_ij = -(a_ij + sum_k a_ik abar_kj / d_ik) / a~_ii with
+// abar_kl = a_kl if its sign is opposite to a_kk, d_ik = sum over
+// l in C^_i u {i} of abar_kl; weak entries outside C^_i and strong F
+// neighbours with d_ik = 0 are lumped into a~_ii.
+__global__ void k_exti_fill(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                            const double* __restrict__ v, const uint8_t* __restrict__ mask,
+                            const int8_t* __restrict__ cf, const int* __restrict__ cidx,
+                            int2* __restrict__ cur, const int* __restrict__ prp,
+                            int* __restrict__ pci, double* __restrict__ pv) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int o = prp[i];
+  if (cf[i] == kC) {
+    pci[o] = cidx[i];
+    pv[o] = 1.0;
+    return;
+  }
+  int* c = pci + o;
+  double* w = pv + o;
+  int len = exti_merge<true>(i, rp, ci, mask, cf, cur, c);
+  for (int t = 0; t < len; ++t) w[t] = 0.0;
+  int a0 = rp[i], a1 = rp[i + 1];
+  double atil = row_diag(i, a0, a1, ci, v);
+  for (int e = a0; e < a1; ++e) {
+    int j = ci[e];
+    if (j == i) continue;
+    int t = find_sorted(c, len, j);
+    if (t >= 0)
+      w[t] += v[e];
+    else if (!(mask[e] && cf[j] == kF))
+      atil += v[e];
+  }
+  for (int e = a0; e < a1; ++e) {
+    int k = ci[e];
+    if (!(mask[e] && k != i && cf[k] == kF)) continue;
+    double aik = v[e];
+    int k0 = rp[k], k1 = rp[k + 1];
+    double sk = row_diag(k, k0, k1, ci, v) < 0.0 ? -1.0 : 1.0;
+    double d = 0.0;
+    for (int f = k0; f < k1; ++f) {
+      int l = ci[f];
+      if (sk * v[f] < 0.0 && (l == i || find_sorted(c, len, l) >= 0)) d += v[f];
+    }
+    if (d == 0.0) {
+      atil += aik;
+      continue;
+    }
+    for (int f = k0; f < k1; ++f) {
+      if (!(sk * v[f] < 0.0)) continue;
+      int l = ci[f];
+      int t = find_sorted(c, len, l);
+      if (t >= 0)
+        w[t] += aik * v[f] / d;
+      else if (l == i)
+        atil += aik * v[f] / d;
+    }
+  }
+  for (int t = 0; t < len; ++t) {
+    w[t] = -w[t] / atil;
+    c[t] = cidx[c[t]];
   }
 }
 
@@ -429,8 +568,16 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
     TPF_CHECK_LAUNCH();
     int64_t nc = scan_exclusive(isc.p, cidx.p, n, s);
     if (nc == 0 || double(nc) > 0.9 * double(n)) break;
-    // direct interpolation
-    k_interp_count<<<grid_for(n, 256), 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.mask.p, L.cf.p, cnt.p);
+    // interpolation: direct, or extended+i
+    Buf<int2> cur;
+    if (o.ext_i) {
+      cur.alloc(L.A.nnz > 0 ? L.A.nnz : 1, s);
+      k_exti_count<<<grid_for(n, 128), 128, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.mask.p, L.cf.p, cur.p,
+                                                    cnt.p);
+    } else {
+      k_interp_count<<<grid_for(n, 256), 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.mask.p, L.cf.p,
+                                                      cnt.p);
+    }
     TPF_CHECK_LAUNCH();
     L.P.nrows = n;
     L.P.ncols = int(nc);
@@ -438,8 +585,13 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
     L.P.nnz = scan_exclusive(cnt.p, L.P.rp.p, n, s);
     L.P.ci.alloc(L.P.nnz, s);
     L.P.v.alloc(L.P.nnz, s);
-    k_interp_fill<<<grid_for(n, 256), 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.A.v.p, L.mask.p, L.cf.p,
-                                                   cidx.p, L.P.rp.p, L.P.ci.p, L.P.v.p);
+    if (o.ext_i) {
+      k_exti_fill<<<grid_for(n, 128), 128, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.A.v.p, L.mask.p, L.cf.p,
+                                                   cidx.p, cur.p, L.P.rp.p, L.P.ci.p, L.P.v.p);
+    } else {
+      k_interp_fill<<<grid_for(n, 256), 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.A.v.p, L.mask.p,
+                                                     L.cf.p, cidx.p, L.P.rp.p, L.P.ci.p, L.P.v.p);
+    }
     TPF_CHECK_LAUNCH();
     transpose(ref(L.P), L.R, s);
     // Galerkin product A_c = R (A P)

@@ -14,6 +14,7 @@ struct AmgOpts {
   int dense_max = 1024;
   uint64_t seed = 0x5eed;
   bool fp32 = false;
+  bool ext_i = false;   // extended+i instead of direct interpolation
 };
 
 struct Level {

@@ -121,14 +121,16 @@ __global__ void __launch_bounds__(kKBlock) k_cgs_axpy_norm(int64_t n, int nk,
   reduce_store<1>(acc, 1, part);
 }
 
-// out[k] = sum_b part[b][k] (fixed order)
-__global__ void k_reduce_parts(int nb, int kstride, int nk, const double* __restrict__ part,
-                               double* __restrict__ out) {
-  int k = threadIdx.x;
-  if (k >= nk) return;
+// out[k] = sum_b part[b][k]: one wavefront per column k, lanes stride over
+// the blocks, fixed reduction tree (deterministic)
+__global__ void __launch_bounds__(64) k_reduce_parts(int nb, int kstride,
+                                                     const double* __restrict__ part,
+                                                     double* __restrict__ out) {
+  int k = blockIdx.x;
   double t = 0.0;
-  for (int b = 0; b < nb; ++b) t += part[int64_t(b) * kstride + k];
-  out[k] = t;
+  for (int b = threadIdx.x; b < nb; b += 64) t += part[int64_t(b) * kstride + k];
+  t = wave_sum(t);
+  if (threadIdx.x == 0) out[k] = t;
 }
 
 struct GState {
@@ -140,13 +142,16 @@ struct GState {
 
 // Givens update of column j (single thread): h = h1 + h2, apply previous
 // rotations, form the new one, update g.
-__global__ void k_givens(int j, int m, const double* __restrict__ h1, const double* __restrict__ h2,
-                         const double* __restrict__ nrm2_part, int nparts,
-                         double* __restrict__ H, double* __restrict__ cs, double* __restrict__ sn,
-                         double* __restrict__ g, GState* __restrict__ st) {
-  if (threadIdx.x != 0) return;
+__global__ void __launch_bounds__(64) k_givens(int j, int m, const double* __restrict__ h1,
+                                               const double* __restrict__ h2,
+                                               const double* __restrict__ nrm2_part, int nparts,
+                                               double* __restrict__ H, double* __restrict__ cs,
+                                               double* __restrict__ sn, double* __restrict__ g,
+                                               GState* __restrict__ st) {
   double ss = 0.0;
-  for (int b = 0; b < nparts; ++b) ss += nrm2_part[b];
+  for (int b = threadIdx.x; b < nparts; b += 64) ss += nrm2_part[b];
+  ss = wave_sum(ss);
+  if (threadIdx.x != 0) return;
   double hn = sqrt(ss);
   double* col = H + int64_t(j) * (m + 1);
   for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
@@ -331,11 +336,11 @@ extern "C" int tpf_solve(const tpf_jacobian* J, tpf_precond* M, const double* b,
           DISPATCH_K(nk, KM, {
             k_cgs_dots<KM><<<G, kKBlock, 0, s>>>(n, nk, w.V.p, wv, w.part.p);
             TPF_CHECK_LAUNCH();
-            k_reduce_parts<<<1, 64, 0, s>>>(G, KM, nk, w.part.p, w.h1.p);
+            k_reduce_parts<<<nk, 64, 0, s>>>(G, KM, w.part.p, w.h1.p);
             TPF_CHECK_LAUNCH();
             k_cgs_axpy_dots<KM><<<G, kKBlock, 0, s>>>(n, nk, w.V.p, w.h1.p, wv, w.part.p);
             TPF_CHECK_LAUNCH();
-            k_reduce_parts<<<1, 64, 0, s>>>(G, KM, nk, w.part.p, w.h2.p);
+            k_reduce_parts<<<nk, 64, 0, s>>>(G, KM, w.part.p, w.h2.p);
             TPF_CHECK_LAUNCH();
             k_cgs_axpy_norm<KM><<<G, kKBlock, 0, s>>>(n, nk, w.V.p, w.h2.p, wv, w.part.p);
             TPF_CHECK_LAUNCH();

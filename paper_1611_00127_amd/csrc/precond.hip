@@ -253,8 +253,11 @@ Csr<double> block_copy(const tpf_precond* M, const double* vals, hipStream_t s) 
   return A;
 }
 
-AmgOpts amg_opts(const tpf_precond_opts& o) {
+// interpolation per operator: AUTO uses extended+i for the pressure-like
+// operators (S~, A_pp, scalar J) and direct interpolation for A_ss
+AmgOpts amg_opts(const tpf_precond_opts& o, bool pressure_like) {
   AmgOpts a;
+  a.ext_i = o.interp == TPF_INTERP_EXTI || (o.interp == TPF_INTERP_AUTO && pressure_like);
   a.theta = o.theta;
   a.max_levels = o.max_levels;
   a.coarse_max = o.coarse_max;
@@ -444,6 +447,7 @@ int tpf_precond_default_opts(int kind, tpf_precond_opts* o) {
     o->max_levels = 25;
     o->coarse_max = 256;
     o->dense_max = 1024;
+    o->interp = TPF_INTERP_AUTO;
     o->hash_seed = 0x5eed;
   });
 }
@@ -460,6 +464,8 @@ int tpf_precond_create(const tpf_precond_opts* o, tpf_precond** out) {
     TPF_REQUIRE(o->coarse_max >= 1 && o->dense_max >= 1 && o->dense_max <= 4096,
                 TPF_ERR_INVALID_ARG, "coarse_max >= 1 and 1 <= dense_max <= 4096 required");
     TPF_REQUIRE(o->theta > 0 && o->theta < 1, TPF_ERR_INVALID_ARG, "theta must be in (0,1)");
+    TPF_REQUIRE(o->interp >= TPF_INTERP_AUTO && o->interp <= TPF_INTERP_EXTI, TPF_ERR_INVALID_ARG,
+                "unknown interpolation");
     auto* M = new tpf_precond();
     M->o = *o;
     *out = M;
@@ -489,7 +495,8 @@ int tpf_precond_setup(tpf_precond* M, const tpf_jacobian* J, int reuse, void* st
       return;
     }
     int64_t nnzb = J->nnzb;
-    AmgOpts ao = amg_opts(M->o);
+    AmgOpts ao_p = amg_opts(M->o, true);
+    AmgOpts ao_s = amg_opts(M->o, false);
     if (!re) {
       M->brp.alloc(N + 1, s);
       M->bci.alloc(nnzb, s);
@@ -524,7 +531,7 @@ int tpf_precond_setup(tpf_precond* M, const tpf_jacobian* J, int reuse, void* st
         TPF_CHECK_LAUNCH();
         M->H[0] = std::make_unique<Hierarchy>();
         M->H[0]->tag = "J";
-        M->H[0]->build(std::move(Js), ao, s);
+        M->H[0]->build(std::move(Js), ao_p, s);
       } else {
         k_scalarize_values<<<grid_for(N, 256), 256, 0, s>>>(N, J->rp.p, J->v.p,
                                                             M->H[0]->A0().v.p);
@@ -539,7 +546,7 @@ int tpf_precond_setup(tpf_precond* M, const tpf_jacobian* J, int reuse, void* st
         if (!re) {
           M->H[h] = std::make_unique<Hierarchy>();
           M->H[h]->tag = h == 0 ? "App" : "Ass";
-          M->H[h]->build(block_copy(M, src[h], s), ao, s);
+          M->H[h]->build(block_copy(M, src[h], s), h == 0 ? ao_p : ao_s, s);
         } else {
           copy(M->H[h]->A0().v.p, src[h], nnzb, s);
           M->H[h]->refresh(s);
@@ -561,12 +568,12 @@ int tpf_precond_setup(tpf_precond* M, const tpf_jacobian* J, int reuse, void* st
       if (!re) {
         M->H[0] = std::make_unique<Hierarchy>();
         M->H[0]->tag = "Ass";
-        M->H[0]->build(block_copy(M, M->ass_v.p, s), ao, s);
+        M->H[0]->build(block_copy(M, M->ass_v.p, s), ao_s, s);
         Csr<double> S;
         spgemm(Y, Asp, S, s, &App, -1.0, 1.0, false);
         M->H[1] = std::make_unique<Hierarchy>();
         M->H[1]->tag = "Schur";
-        M->H[1]->build(std::move(S), ao, s);
+        M->H[1]->build(std::move(S), ao_p, s);
       } else {
         copy(M->H[0]->A0().v.p, M->ass_v.p, nnzb, s);
         M->H[0]->refresh(s);

@@ -103,3 +103,36 @@ class GpuPrecond:
 def solve(gcase, M, b, x, rtol=1e-8, restart=30, maxit=1000):
     return tpf.tpf_solve(gcase.J, M.M if M is not None else None, b, x, rtol=rtol,
                          restart=restart, maxit=maxit, stream=gcase.stream)
+
+
+def newton_sequence(gcase, M, n_jacobians, reuse=False, ds_max=0.2, rtol=1e-8, restart=30,
+                    maxit=1000, on_step=None):
+    """Consecutive Newton Jacobians of one time step on the GPU: assemble,
+    set up (full, or numeric refresh of the first hierarchy when `reuse`),
+    solve J delta = -F, update u (saturation chop ds_max).  Returns a list of
+    dicts (||F||, iterations, status, relres, setup_ms, solve_ms)."""
+    import time
+
+    import torch
+    out = []
+    b = torch.empty(2 * gcase.N, dtype=torch.float64, device="cuda")
+    x = torch.empty_like(b)
+    for k in range(n_jacobians):
+        gcase.assemble()
+        torch.neg(gcase.R, out=b)
+        fnorm = float(torch.linalg.norm(gcase.R))
+        t0 = time.perf_counter()
+        M.setup(gcase, reuse=bool(reuse and k > 0))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        info = solve(gcase, M, b, x, rtol=rtol, restart=restart, maxit=maxit)
+        t2 = time.perf_counter()
+        tpf.tpf_newton_update(gcase.prob, gcase.u, x, ds_max, stream=gcase.stream)
+        rec = dict(k=k, fnorm=fnorm, iterations=int(info.iterations), status=int(info.status),
+                   relres=float(info.relres_true), setup_ms=1e3 * (t1 - t0),
+                   solve_ms=1e3 * (t2 - t1))
+        out.append(rec)
+        if on_step:
+            on_step(rec)
+    torch.cuda.synchronize()
+    return out

@@ -24,6 +24,7 @@ TPF_FP64, TPF_FP32 = 0, 1
 TPF_CONVERGED, TPF_MAX_ITERS, TPF_BREAKDOWN, TPF_NONFINITE = 0, 1, 2, 3
 TPF_MAT_A, TPF_MAT_P, TPF_MAT_R, TPF_MAT_S, TPF_MAT_APS, TPF_MAT_SCHUR = 0, 1, 2, 3, 10, 11
 TPF_MAX_LEVELS = 25
+TPF_INTERP_AUTO, TPF_INTERP_DIRECT, TPF_INTERP_EXTI = 0, 1, 2
 KINDS = {"amg": TPF_PREC_AMG, "cpr1": TPF_PREC_CPR1, "cpr2": TPF_PREC_CPR2, "bf": TPF_PREC_BF,
          "none": TPF_PREC_NONE}
 
@@ -57,7 +58,8 @@ class CsrView(ctypes.Structure):
 
 class PrecondOpts(ctypes.Structure):
     _fields_ = [("kind", c_int), ("precision", c_int), ("theta", c_double), ("max_levels", c_int),
-                ("coarse_max", c_int), ("dense_max", c_int), ("hash_seed", c_uint64)]
+                ("coarse_max", c_int), ("dense_max", c_int), ("interp", c_int),
+                ("hash_seed", c_uint64)]
 
 
 class HierStats(ctypes.Structure):
@@ -116,7 +118,7 @@ _SIGS = {
     "tpf_assemble": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_void_p]),
     "tpf_jacobian_view": (c_int, [c_void_p, ctypes.POINTER(BcsrView)]),
     "tpf_spmv": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
-    "tpf_newton_update": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "tpf_newton_update": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_void_p]),
     "tpf_precond_default_opts": (c_int, [c_int, ctypes.POINTER(PrecondOpts)]),
     "tpf_precond_create": (c_int, [ctypes.POINTER(PrecondOpts), ctypes.POINTER(c_void_p)]),
     "tpf_precond_destroy": (c_int, [c_void_p]),
@@ -283,8 +285,8 @@ def tpf_spmv(J, x, y, stream=None):
     _check(load().tpf_spmv(J, _ptr(x), _ptr(y), _stream(stream)))
 
 
-def tpf_newton_update(p, u, delta, stream=None):
-    _check(load().tpf_newton_update(p, _ptr(u), _ptr(delta), _stream(stream)))
+def tpf_newton_update(p, u, delta, ds_max=0.0, stream=None):
+    _check(load().tpf_newton_update(p, _ptr(u), _ptr(delta), float(ds_max), _stream(stream)))
 
 
 def tpf_precond_default_opts(kind):

@@ -131,10 +131,12 @@ def test_schur_parity(gpu):
     M.close(); g.close()
 
 
-@pytest.mark.parametrize("kind,hier", [("bf", 0), ("bf", 1), ("cpr1", 0), ("amg", 0)])
-def test_amg_setup_parity_per_level(gpu, kind, hier):
+@pytest.mark.parametrize("kind,hier,interp", [("bf", 0, "direct"), ("bf", 1, "ext+i"),
+                                              ("cpr1", 0, "ext+i"), ("amg", 0, "ext+i"),
+                                              ("cpr2", 1, "direct")])
+def test_amg_setup_parity_per_level(gpu, kind, hier, interp):
     """Each level's setup from the GPU's own level matrix (identical bits):
-    strength graph, C/F, P, R and A_c."""
+    strength graph, C/F, P (direct or extended+i), R and A_c."""
     driver, tpf, torch = gpu
     c = inputs.random_state(inputs.config_c1(), 7, s_lo=0.15, s_hi=0.85)
     say(f"[amg-setup] kind={kind} hier={hier}")
@@ -159,7 +161,7 @@ def test_amg_setup_parity_per_level(gpu, kind, hier):
         ocf, _ = amg.pmis(A, mask, 0x5eed)
         assert np.array_equal(cf, ocf), f"C/F level {l}"
         P = tpf.csr_to_numpy(tpf.tpf_precond_matrix(M.M, hier, l, tpf.TPF_MAT_P))
-        Po, _ = amg.direct_interpolation(A, mask, ocf)
+        Po, _ = amg.interpolation(A, mask, ocf, interp)
         assert np.array_equal(P[0], Po.indptr) and np.array_equal(P[1], Po.indices), f"P level {l}"
         ok, worst = _row_scale_close(P[2], Po.data, Po.indptr, 1e-12)
         assert ok, (l, worst)
@@ -325,29 +327,54 @@ def test_solve_edge_cases(gpu):
 
 
 def test_reuse_structure_matches_rebuild(gpu):
-    """Numeric refresh on a new Jacobian (same pattern) keeps C/F, P, R and
-    gives the same operator values as recomputing the Galerkin products."""
+    """Numeric refresh on the next Newton Jacobian (same pattern) keeps C/F,
+    P, R and gives the Galerkin products of the new level operators."""
     driver, tpf, torch = gpu
-    c = inputs.small_case(18, 16, 5, seed=17)
-    c = inputs.random_state(c, 18, s_lo=0.15, s_hi=0.85)
-    say("[reuse] 18x16x5")
+    c = inputs.config_c3(24, 24, 12)
+    say("[reuse] 24x24x12 Newton step 2 with the step-1 hierarchy")
     g, M = _setup(driver, tpf, c, "bf")
     cf0 = tpf.device_array(tpf.tpf_precond_level_data(M.M, 1, 0)[0], c.N, np.int8)
-    c2 = inputs.random_state(c, 19, s_lo=0.15, s_hi=0.85)
-    g.u.copy_(torch.tensor(c2.u.reshape(-1), device="cuda"))
-    g.assemble()
-    M.setup(g, reuse=True)
-    cf1 = tpf.device_array(tpf.tpf_precond_level_data(M.M, 1, 0)[0], c.N, np.int8)
-    assert np.array_equal(cf0, cf1)
-    A0 = _download_level(tpf, M, 1, 0)
-    P = tpf.csr_to_numpy(tpf.tpf_precond_matrix(M.M, 1, 0, tpf.TPF_MAT_P))
-    A1 = _download_level(tpf, M, 1, 1)
-    Pm = sp.csr_matrix((P[2], P[1], P[0]), shape=(A0.shape[0], A1.shape[0]))
-    A1o, _ = amg.galerkin(A0, Pm)
-    ok, worst = _row_scale_close(A1.data, A1o.data, A1o.indptr, 1e-12)
-    assert ok, worst
     b = g.rhs().contiguous()
     x = torch.empty_like(b)
     info = driver.solve(g, M, b, x)
     assert info.status == tpf.TPF_CONVERGED
+    tpf.tpf_newton_update(g.prob, g.u, x, 0.2)
+    g.assemble()
+    M.setup(g, reuse=True)
+    cf1 = tpf.device_array(tpf.tpf_precond_level_data(M.M, 1, 0)[0], c.N, np.int8)
+    assert np.array_equal(cf0, cf1)
+    for h in range(2):
+        st = M.stats()
+        for l in range(st.levels[h] - 1):
+            A0 = _download_level(tpf, M, h, l)
+            P = tpf.csr_to_numpy(tpf.tpf_precond_matrix(M.M, h, l, tpf.TPF_MAT_P))
+            A1 = _download_level(tpf, M, h, l + 1)
+            Pm = sp.csr_matrix((P[2], P[1], P[0]), shape=(A0.shape[0], A1.shape[0]))
+            A1o, _ = amg.galerkin(A0, Pm)
+            assert np.array_equal(A1.indices, A1o.indices)
+            ok, worst = _row_scale_close(A1.data, A1o.data, A1o.indptr, 1e-12)
+            assert ok, (h, l, worst)
+    b = g.rhs().contiguous()
+    info = driver.solve(g, M, b, x)
+    say(f"  refreshed solve its={info.iterations} relres={info.relres_true:.2e}")
+    assert info.status == tpf.TPF_CONVERGED
+    M.close(); g.close()
+
+
+@pytest.mark.parametrize("reuse", [False, True])
+def test_newton_sequence_matches_oracle(gpu, reuse):
+    """Four Newton Jacobians of one time step (saturation chop 0.2): every
+    linear solve reaches 1e-8, and ||F|| along the sequence follows the
+    oracle's Newton sequence (rebuild) to 1e-6 relative."""
+    driver, tpf, torch = gpu
+    c = inputs.config_c3(20, 20, 10)
+    say(f"[newton] 20x20x10 reuse={reuse}")
+    g = driver.GpuCase(c)
+    M = driver.GpuPrecond("bf")
+    recs = driver.newton_sequence(g, M, 4, reuse=reuse, ds_max=0.2)
+    seq, _ = newton.sequence(c, 4, "bf", ds_max=0.2)
+    for r, (fo, io) in zip(recs, seq):
+        say(f"  k={r['k']} |F| gpu={r['fnorm']:.6e} oracle={fo:.6e} its={r['iterations']}/{io['iterations']}")
+        assert r["status"] == tpf.TPF_CONVERGED and r["relres"] <= 1e-8
+        assert abs(r["fnorm"] - fo) <= 1e-6 * fo
     M.close(); g.close()

@@ -162,6 +162,54 @@ def test_direct_interpolation_closed_forms():
     np.testing.assert_allclose(rs[nonempty], 1.0, rtol=1e-14)
 
 
+def test_extended_i_closed_forms():
+    """1D Laplacian: C F C gives (1/2, 1/2) (no distance-two points, same as
+    direct); C F F C gives linear interpolation (2/3, 1/3) for the F point
+    next to the left C point.  Zero-row-sum rows reproduce constants."""
+    n = 10
+    A = sp.diags([-np.ones(n - 1), 2 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1]).tocsr()
+    mask = amg.strength(A, 0.25)
+    # pattern C F C F F C F F C C
+    cf = np.array([1, 2, 1, 2, 2, 1, 2, 2, 1, 1], np.int8)
+    P, cidx = amg.extended_i_interpolation(A, mask, cf)
+    Pd = P.toarray()
+    np.testing.assert_allclose(Pd[1, [0, 1]], [0.5, 0.5], rtol=1e-15)
+    np.testing.assert_allclose(Pd[3, [1, 2]], [2 / 3, 1 / 3], rtol=1e-14)
+    np.testing.assert_allclose(Pd[4, [1, 2]], [1 / 3, 2 / 3], rtol=1e-14)
+    np.testing.assert_allclose(Pd[6, [2, 3]], [2 / 3, 1 / 3], rtol=1e-14)
+    assert np.count_nonzero(Pd[3]) == 2
+    Pdir, _ = amg.direct_interpolation(A, mask, np.array([1, 2, 1, 2, 1, 2, 1, 2, 1, 2], np.int8))
+    Pext, _ = amg.extended_i_interpolation(A, mask, np.array([1, 2, 1, 2, 1, 2, 1, 2, 1, 2], np.int8))
+    np.testing.assert_allclose(Pext.toarray(), Pdir.toarray(), rtol=1e-15)
+    L = _laplace2d(9).tolil()
+    L = sp.csr_matrix(L)
+    L = (L - sp.diags(np.asarray(L.sum(axis=1)).ravel())).tocsr()
+    L.sort_indices()
+    m = amg.strength(L, 0.25)
+    cf2, _ = amg.pmis(L, m, 3)
+    P2, _ = amg.extended_i_interpolation(L, m, cf2)
+    rs = np.asarray(P2.sum(axis=1)).ravel()
+    nonempty = np.diff(P2.indptr) > 0
+    np.testing.assert_allclose(rs[nonempty], 1.0, rtol=1e-13)
+
+
+def test_extended_i_restores_scalable_schur_cycle():
+    """On the heterogeneous S~ of the 3D workload family the direct
+    interpolation cycle degrades with the grid while extended+i stays flat
+    (the reason it is used for the pressure-like operators)."""
+    its = {}
+    for (nx, ny, nz) in [(16, 16, 8), (32, 32, 16)]:
+        c = inputs.config_c3(nx, ny, nz)
+        rp, ci, v, _ = newton.linear_system(c)
+        M = precond.Preconditioner("bf", rp, ci, v, (nx, ny, nz))
+        b = inputs.random_vector(M.S.shape[0], 1)
+        for interp in ["direct", "ext+i"]:
+            H = amg.Hierarchy(M.S, interp=interp)
+            _, info = fgmres.fgmres(lambda z: M.S @ z, H.vcycle, b, rtol=1e-8, maxit=300)
+            its[(nx, interp)] = info["iterations"]
+    assert its[(32, "ext+i")] <= 16 and its[(32, "ext+i")] < its[(32, "direct")]
+
+
 def test_galerkin_matches_dense_and_symmetry():
     c, rp, ci, v = _small(10, 9, 2, seed=3)
     App = blocks.block(rp, ci, v, 0, 0)
