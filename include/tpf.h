@@ -144,7 +144,7 @@ int tpf_newton_update(tpf_problem* p, double* u, const double* delta, double ds_
 #define TPF_PREC_BF 3    /* Algorithm 3, V-cycles on A_ss and on S~ */
 #define TPF_PREC_NONE 4  /* identity (tests) */
 
-#define TPF_INTERP_AUTO 0    /* extended+i for S~, A_pp and the scalar J; direct for A_ss */
+#define TPF_INTERP_AUTO 0    /* extended+i for S~ and A_pp; direct for A_ss and the scalar J */
 #define TPF_INTERP_DIRECT 1  /* direct (distance-one) interpolation everywhere */
 #define TPF_INTERP_EXTI 2    /* extended+i (distance-two) interpolation everywhere */
 

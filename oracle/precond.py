@@ -13,8 +13,8 @@ exact sparse LU (``inner='exact'``) for the matrix-form checks.  P_1 is
 block ILU(0), or the exact inverse of J with ``p1='exact'``.
 
 AMG interpolation per operator (unless ``amg_opts['interp']`` is given):
-extended+i for the pressure-like operators (S~, A_pp, the scalar J) and
-direct interpolation for A_ss.
+extended+i for the pressure-like operators (S~, A_pp) and direct
+interpolation for A_ss and the point-ordered J of black-box AMG.
 """
 from __future__ import annotations
 
@@ -50,7 +50,7 @@ class Preconditioner:
         self.J = bcsr_matrix(row_ptr, col_idx, vals).tocsr()
         if kind == "amg":
             self.Js = blocks.scalarize(row_ptr, col_idx, vals)
-            self.H = inner_solver(self.Js, inner, amg_opts, "ext+i")
+            self.H = inner_solver(self.Js, inner, amg_opts, "direct")
             return
         self.App = blocks.block(row_ptr, col_idx, vals, 0, 0)
         self.Aps = blocks.block(row_ptr, col_idx, vals, 0, 1)

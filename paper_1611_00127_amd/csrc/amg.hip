@@ -262,11 +262,14 @@ __device__ inline int exti_merge(int i, const int* __restrict__ rp, const int* _
   return count;
 }
 
-__global__ void k_exti_count(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                             const uint8_t* __restrict__ mask, const int8_t* __restrict__ cf,
-                             int2* __restrict__ cur, int* __restrict__ cnt) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// per-thread versions for the rows with the largest candidate sets
+__global__ void k_exti_count(int nl, const int* __restrict__ rows, const int* __restrict__ rp,
+                             const int* __restrict__ ci, const uint8_t* __restrict__ mask,
+                             const int8_t* __restrict__ cf, int2* __restrict__ cur,
+                             int* __restrict__ cnt) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nl) return;
+  int i = rows[t];
   cnt[i] = cf[i] == kC ? 1 : exti_merge<false>(i, rp, ci, mask, cf, cur, nullptr);
 }
 
@@ -287,13 +290,15 @@ __device__ inline int find_sorted(const int* __restrict__ c, int len, int j) {
 // abar_kl = a_kl if its sign is opposite to a_kk, d_ik = sum over
 // l in C^_i u {i} of abar_kl; weak entries outside C^_i and strong F
 // neighbours with d_ik = 0 are lumped into a~_ii.
-__global__ void k_exti_fill(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                            const double* __restrict__ v, const uint8_t* __restrict__ mask,
-                            const int8_t* __restrict__ cf, const int* __restrict__ cidx,
-                            int2* __restrict__ cur, const int* __restrict__ prp,
-                            int* __restrict__ pci, double* __restrict__ pv) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+__global__ void k_exti_fill(int nl, const int* __restrict__ rows, const int* __restrict__ rp,
+                            const int* __restrict__ ci, const double* __restrict__ v,
+                            const uint8_t* __restrict__ mask, const int8_t* __restrict__ cf,
+                            const int* __restrict__ cidx, int2* __restrict__ cur,
+                            const int* __restrict__ prp, int* __restrict__ pci,
+                            double* __restrict__ pv) {
+  int tt = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tt >= nl) return;
+  int i = rows[tt];
   int o = prp[i];
   if (cf[i] == kC) {
     pci[o] = cidx[i];
@@ -344,6 +349,191 @@ __global__ void k_exti_fill(int n, const int* __restrict__ rp, const int* __rest
     w[t] = -w[t] / atil;
     c[t] = cidx[c[t]];
   }
+}
+
+// ---- extended+i, one wavefront per F row (rows whose candidate bound fits
+// kExtCap); the per-thread kernels above handle the rest.
+constexpr int kExtCap = 1024;
+
+__global__ void k_exti_ub(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                          const uint8_t* __restrict__ mask, const int8_t* __restrict__ cf,
+                          int* __restrict__ ub) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (cf[i] == kC) {
+    ub[i] = 0;
+    return;
+  }
+  int64_t t = rp[i + 1] - rp[i];
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    int k = ci[e];
+    if (mask[e] && k != i && cf[k] == kF) t += rp[k + 1] - rp[k];
+  }
+  ub[i] = t > INT_MAX ? INT_MAX : int(t);
+}
+
+// rows of class 0 (ub <= kExtCap, F) and class 1 (the rest, F); C rows are
+// written directly by the fill kernels
+__global__ void k_exti_classify(int n, const int* __restrict__ ub, const int8_t* __restrict__ cf,
+                                int* __restrict__ counts, int* __restrict__ lists) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || cf[i] == kC) return;
+  int c = ub[i] <= kExtCap ? 0 : 1;
+  int pos = atomicAdd(&counts[c], 1);
+  lists[int64_t(c) * n + pos] = i;
+}
+
+// appends the columns of entries e in [e0, e1) that pass the filter to buf
+// (order preserved), returning the new length (wavefront-wide)
+__device__ inline int wave_append_strong_c(int e0, int e1, const int* __restrict__ ci,
+                                           const uint8_t* __restrict__ mask,
+                                           const int8_t* __restrict__ cf, int* buf, int len) {
+  int lane = threadIdx.x & 63;
+  for (int base = e0; base < e1; base += 64) {
+    int e = base + lane;
+    bool f = e < e1 && mask[e] && cf[ci[e]] == kC;
+    unsigned long long b = __ballot(f);
+    int pos = __popcll(b & ((1ull << lane) - 1ull));
+    if (f) buf[len + pos] = ci[e];
+    len += __popcll(b);
+  }
+  return len;
+}
+
+__device__ inline int lds_find(const int* u, int m, int key) {
+  int lo = 0, hi = m;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (u[mid] < key) lo = mid + 1;
+    else hi = mid;
+  }
+  return (lo < m && u[lo] == key) ? lo : -1;
+}
+
+template <bool FILL>
+__global__ void __launch_bounds__(64) k_exti_wave(
+    const int* __restrict__ rows, const int* __restrict__ rp, const int* __restrict__ ci,
+    const double* __restrict__ v, const uint8_t* __restrict__ mask, const int8_t* __restrict__ cf,
+    const int* __restrict__ cidx, int* __restrict__ cnt, const int* __restrict__ prp,
+    int* __restrict__ pci, double* __restrict__ pv) {
+  __shared__ int cand[kExtCap];
+  __shared__ int uniq[kExtCap];
+  __shared__ double w[kExtCap];
+  int lane = threadIdx.x;
+  int i = rows[blockIdx.x];
+  int a0 = rp[i], a1 = rp[i + 1];
+  // candidates: strong C neighbours of i and of its strong F neighbours
+  int len = wave_append_strong_c(a0, a1, ci, mask, cf, cand, 0);
+  for (int e = a0; e < a1; ++e) {
+    int k = ci[e];
+    if (mask[e] && k != i && cf[k] == kF)
+      len = wave_append_strong_c(rp[k], rp[k + 1], ci, mask, cf, cand, len);
+  }
+  int p2 = 1;
+  while (p2 < len) p2 <<= 1;
+  for (int t = len + lane; t < p2; t += 64) cand[t] = INT_MAX;
+  __syncthreads();
+  for (int k = 2; k <= p2; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = lane; t < p2; t += 64) {
+        int q = t ^ j;
+        if (q > t) {
+          int x = cand[t], y = cand[q];
+          bool up = (t & k) == 0;
+          if ((x > y) == up) {
+            cand[t] = y;
+            cand[q] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  int m = 0;
+  for (int base = 0; base < p2; base += 64) {
+    int t = base + lane;
+    bool f = t < p2 && cand[t] != INT_MAX && (t == 0 || cand[t - 1] != cand[t]);
+    unsigned long long b = __ballot(f);
+    int pos = __popcll(b & ((1ull << lane) - 1ull));
+    if (f) uniq[m + pos] = cand[t];
+    m += __popcll(b);
+  }
+  if (!FILL) {
+    if (lane == 0) cnt[i] = m;
+    return;
+  }
+  for (int t = lane; t < m; t += 64) w[t] = 0.0;
+  __syncthreads();
+  // direct couplings; weak entries outside C^_i go to the diagonal
+  double aii = 0.0, lump = 0.0;
+  for (int e = a0 + lane; e < a1; e += 64) {
+    int j = ci[e];
+    if (j == i) {
+      aii = v[e];
+      continue;
+    }
+    int t = lds_find(uniq, m, j);
+    if (t >= 0)
+      w[t] += v[e];
+    else if (!(mask[e] && cf[j] == kF))
+      lump += v[e];
+  }
+  aii = wave_sum(aii);
+  lump = wave_sum(lump);
+  __syncthreads();
+  double extra = 0.0;  // uniform across lanes (computed from wavefront sums)
+  for (int e = a0; e < a1; ++e) {
+    int k = ci[e];
+    if (!(mask[e] && k != i && cf[k] == kF)) continue;
+    double aik = v[e];
+    int k0 = rp[k], k1 = rp[k + 1];
+    double dk = 0.0;
+    for (int f = k0 + lane; f < k1; f += 64)
+      if (ci[f] == k) dk = v[f];
+    dk = __shfl(wave_sum(dk), 0, 64);
+    double sk = dk < 0.0 ? -1.0 : 1.0;
+    double d = 0.0;
+    for (int f = k0 + lane; f < k1; f += 64) {
+      int l = ci[f];
+      if (sk * v[f] < 0.0 && (l == i || lds_find(uniq, m, l) >= 0)) d += v[f];
+    }
+    d = __shfl(wave_sum(d), 0, 64);
+    if (d == 0.0) {
+      extra += aik;
+      continue;
+    }
+    double toi = 0.0;
+    for (int f = k0 + lane; f < k1; f += 64) {
+      if (!(sk * v[f] < 0.0)) continue;
+      int l = ci[f];
+      int t = lds_find(uniq, m, l);
+      if (t >= 0)
+        w[t] += aik * v[f] / d;
+      else if (l == i)
+        toi += aik * v[f] / d;
+    }
+    extra += __shfl(wave_sum(toi), 0, 64);
+    __syncthreads();
+  }
+  double atil = __shfl(aii + lump, 0, 64) + extra;
+  __syncthreads();
+  int o = prp[i];
+  for (int t = lane; t < m; t += 64) {
+    pci[o + t] = cidx[uniq[t]];
+    pv[o + t] = -w[t] / atil;
+  }
+}
+
+__global__ void k_inject_c(int n, const int8_t* __restrict__ cf, const int* __restrict__ cidx,
+                           const int* __restrict__ prp, int* __restrict__ pci,
+                           double* __restrict__ pv, int* __restrict__ cnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || cf[i] != kC) return;
+  if (cnt) {
+    cnt[i] = 1;
+    return;
+  }
+  pci[prp[i]] = cidx[i];
+  pv[prp[i]] = 1.0;
 }
 
 // dense [A | I] for Gauss-Jordan (row-major, n x 2n)
@@ -569,30 +759,55 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
     int64_t nc = scan_exclusive(isc.p, cidx.p, n, s);
     if (nc == 0 || double(nc) > 0.9 * double(n)) break;
     // interpolation: direct, or extended+i
-    Buf<int2> cur;
-    if (o.ext_i) {
-      cur.alloc(L.A.nnz > 0 ? L.A.nnz : 1, s);
-      k_exti_count<<<grid_for(n, 128), 128, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.mask.p, L.cf.p, cur.p,
-                                                    cnt.p);
-    } else {
-      k_interp_count<<<grid_for(n, 256), 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.mask.p, L.cf.p,
-                                                      cnt.p);
-    }
-    TPF_CHECK_LAUNCH();
     L.P.nrows = n;
     L.P.ncols = int(nc);
     L.P.rp.alloc(n + 1, s);
-    L.P.nnz = scan_exclusive(cnt.p, L.P.rp.p, n, s);
-    L.P.ci.alloc(L.P.nnz, s);
-    L.P.v.alloc(L.P.nnz, s);
     if (o.ext_i) {
-      k_exti_fill<<<grid_for(n, 128), 128, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.A.v.p, L.mask.p, L.cf.p,
-                                                   cidx.p, cur.p, L.P.rp.p, L.P.ci.p, L.P.v.p);
+      Buf<int> ub(n, s), counts(2, s), lists(2 * int64_t(n), s);
+      fill_int(counts.p, 0, 2, s);
+      k_exti_ub<<<grid_for(n, 256), 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.mask.p, L.cf.p, ub.p);
+      TPF_CHECK_LAUNCH();
+      k_exti_classify<<<grid_for(n, 256), 256, 0, s>>>(n, ub.p, L.cf.p, counts.p, lists.p);
+      TPF_CHECK_LAUNCH();
+      int hc[2];
+      TPF_HIP(hipMemcpyAsync(hc, counts.p, sizeof(hc), hipMemcpyDeviceToHost, s));
+      TPF_HIP(hipStreamSynchronize(s));
+      Buf<int2> cur;
+      if (hc[1] > 0) cur.alloc(L.A.nnz > 0 ? L.A.nnz : 1, s);
+      const int* l0 = lists.p;
+      const int* l1 = lists.p + n;
+      k_inject_c<<<grid_for(n, 256), 256, 0, s>>>(n, L.cf.p, cidx.p, nullptr, nullptr, nullptr, cnt.p);
+      if (hc[0] > 0)
+        k_exti_wave<false><<<hc[0], 64, 0, s>>>(l0, L.A.rp.p, L.A.ci.p, L.A.v.p, L.mask.p, L.cf.p,
+                                                cidx.p, cnt.p, nullptr, nullptr, nullptr);
+      if (hc[1] > 0)
+        k_exti_count<<<grid_for(hc[1], 128), 128, 0, s>>>(hc[1], l1, L.A.rp.p, L.A.ci.p, L.mask.p,
+                                                          L.cf.p, cur.p, cnt.p);
+      TPF_CHECK_LAUNCH();
+      L.P.nnz = scan_exclusive(cnt.p, L.P.rp.p, n, s);
+      L.P.ci.alloc(L.P.nnz, s);
+      L.P.v.alloc(L.P.nnz, s);
+      k_inject_c<<<grid_for(n, 256), 256, 0, s>>>(n, L.cf.p, cidx.p, L.P.rp.p, L.P.ci.p, L.P.v.p,
+                                                  nullptr);
+      if (hc[0] > 0)
+        k_exti_wave<true><<<hc[0], 64, 0, s>>>(l0, L.A.rp.p, L.A.ci.p, L.A.v.p, L.mask.p, L.cf.p,
+                                               cidx.p, nullptr, L.P.rp.p, L.P.ci.p, L.P.v.p);
+      if (hc[1] > 0)
+        k_exti_fill<<<grid_for(hc[1], 128), 128, 0, s>>>(hc[1], l1, L.A.rp.p, L.A.ci.p, L.A.v.p,
+                                                         L.mask.p, L.cf.p, cidx.p, cur.p, L.P.rp.p,
+                                                         L.P.ci.p, L.P.v.p);
+      TPF_CHECK_LAUNCH();
     } else {
+      k_interp_count<<<grid_for(n, 256), 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.mask.p, L.cf.p,
+                                                      cnt.p);
+      TPF_CHECK_LAUNCH();
+      L.P.nnz = scan_exclusive(cnt.p, L.P.rp.p, n, s);
+      L.P.ci.alloc(L.P.nnz, s);
+      L.P.v.alloc(L.P.nnz, s);
       k_interp_fill<<<grid_for(n, 256), 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.A.v.p, L.mask.p,
                                                      L.cf.p, cidx.p, L.P.rp.p, L.P.ci.p, L.P.v.p);
+      TPF_CHECK_LAUNCH();
     }
-    TPF_CHECK_LAUNCH();
     transpose(ref(L.P), L.R, s);
     // Galerkin product A_c = R (A P)
     spgemm(ref(L.A), ref(L.P), L.AP, s);

@@ -254,7 +254,7 @@ Csr<double> block_copy(const tpf_precond* M, const double* vals, hipStream_t s) 
 }
 
 // interpolation per operator: AUTO uses extended+i for the pressure-like
-// operators (S~, A_pp, scalar J) and direct interpolation for A_ss
+// operators (S~, A_pp) and direct interpolation for A_ss and the scalar J
 AmgOpts amg_opts(const tpf_precond_opts& o, bool pressure_like) {
   AmgOpts a;
   a.ext_i = o.interp == TPF_INTERP_EXTI || (o.interp == TPF_INTERP_AUTO && pressure_like);
@@ -531,7 +531,7 @@ int tpf_precond_setup(tpf_precond* M, const tpf_jacobian* J, int reuse, void* st
         TPF_CHECK_LAUNCH();
         M->H[0] = std::make_unique<Hierarchy>();
         M->H[0]->tag = "J";
-        M->H[0]->build(std::move(Js), ao_p, s);
+        M->H[0]->build(std::move(Js), ao_s, s);
       } else {
         k_scalarize_values<<<grid_for(N, 256), 256, 0, s>>>(N, J->rp.p, J->v.p,
                                                             M->H[0]->A0().v.p);

@@ -2,13 +2,19 @@
 // free) patterns and sorted rows, used for the Galerkin product A_c = R(AP)
 // and for the approximate Schur complement S~ = A_pp - (A_ps D^{-1}) A_sp.
 //
-// Product rows are formed by merging the sorted rows B_k, k in A_i: one
-// thread per output row advances a cursor into every B_k and emits the
-// columns in increasing order, accumulating each value over k in A's column
-// order.  The result is deterministic (no atomics on values) and its
-// pattern never depends on values.
+// Output row i has the sorted unique columns of the rows B_k, k in A_i (and
+// of D_i when a matrix is added).  Rows are grouped by their product count
+// ub_i: one wavefront per row (ub_i <= 1024) or one 256-thread work-group
+// (ub_i <= 4096 or <= 16384) gathers the product columns into LDS,
+// bitonic-sorts them and keeps the unique ones; each output value is then the
+// sum over k in A's column order of A_ik B_kj (B_kj found by binary search),
+// so the result is deterministic and identical for every row class.  Rows
+// above 16384 products fall back to one thread per row merging the sorted B
+// rows with a cursor each (same summation order).
 #include <climits>
+#include <type_traits>
 
+#include "linalg_dev.hpp"
 #include "tpf_internal.hpp"
 
 namespace tpf {
@@ -17,14 +23,15 @@ namespace {
 
 template <bool FILL>
 __global__ void __launch_bounds__(128) k_spgemm_merge(
-    int nrows, const int* __restrict__ arp, const int* __restrict__ aci,
+    int nlist, const int* __restrict__ rows, const int* __restrict__ arp, const int* __restrict__ aci,
     const double* __restrict__ av, const int* __restrict__ brp, const int* __restrict__ bci,
     const double* __restrict__ bv, const int* __restrict__ drp, const int* __restrict__ dci,
     const double* __restrict__ dv, double alpha, double beta, int2* __restrict__ cur,
     int* __restrict__ cnt, const int* __restrict__ crp, int* __restrict__ cci,
     double* __restrict__ cv) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nrows) return;
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nlist) return;
+  int i = rows[t];
   int a0 = arp[i], a1 = arp[i + 1];
   for (int e = a0; e < a1; ++e) {
     int k = aci[e];
@@ -69,6 +76,155 @@ __global__ void __launch_bounds__(128) k_spgemm_merge(
     ++count;
   }
   if (!FILL) cnt[i] = count;
+}
+
+// ---- row classification and the sort-based product
+__global__ void k_spgemm_ub(int nrows, const int* __restrict__ arp, const int* __restrict__ aci,
+                            const int* __restrict__ brp, const int* __restrict__ drp,
+                            int* __restrict__ ub) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  int64_t t = drp ? drp[i + 1] - drp[i] : 0;
+  for (int e = arp[i]; e < arp[i + 1]; ++e) t += brp[aci[e] + 1] - brp[aci[e]];
+  ub[i] = t > INT_MAX ? INT_MAX : int(t);
+}
+
+// appends row i to the list of its size class: 0 wavefront, 1-2 work-group
+// with 32 / 128 KB of LDS, 3 per-thread merge
+__global__ void k_spgemm_classify(int nrows, const int* __restrict__ ub, int cap0, int cap1,
+                                  int cap2, int* __restrict__ counts, int* __restrict__ lists) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  int u = ub[i];
+  int c = u <= cap0 ? 0 : (u <= cap1 ? 1 : (u <= cap2 ? 2 : 3));
+  int pos = atomicAdd(&counts[c], 1);
+  lists[int64_t(c) * nrows + pos] = i;
+}
+
+__device__ inline int bsearch_col(const int* __restrict__ c, int lo, int hi, int key) {
+  // position in the sorted range [lo, hi) holding key, or -1
+  int end = hi;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    int v = c[mid];
+    if (v < key) lo = mid + 1;
+    else hi = mid;
+  }
+  return (lo < end && c[lo] == key) ? lo : -1;
+}
+
+template <int BLOCK, int CAP, bool FILL>
+__global__ void __launch_bounds__(BLOCK) k_spgemm_sorted(
+    const int* __restrict__ rows, const int* __restrict__ ub, const int* __restrict__ arp,
+    const int* __restrict__ aci, const double* __restrict__ av, const int* __restrict__ brp,
+    const int* __restrict__ bci, const double* __restrict__ bv, const int* __restrict__ drp,
+    const int* __restrict__ dci, const double* __restrict__ dv, double alpha, double beta,
+    int* __restrict__ cnt, const int* __restrict__ crp, int* __restrict__ cci,
+    double* __restrict__ cv) {
+  __shared__ int keys[CAP];
+  __shared__ int ukeys[CAP];
+  __shared__ int sh[BLOCK / 64 + 1];
+  int i = rows[blockIdx.x];
+  int u = ub[i];
+  int p2 = 1;
+  while (p2 < u) p2 <<= 1;
+  // gather product columns
+  int off = 0;
+  int a0 = arp[i], a1 = arp[i + 1];
+  for (int e = a0; e < a1; ++e) {
+    int k = aci[e];
+    int b0 = brp[k], b1 = brp[k + 1];
+    for (int t = threadIdx.x; t < b1 - b0; t += BLOCK) keys[off + t] = bci[b0 + t];
+    off += b1 - b0;
+  }
+  if (drp) {
+    int d0 = drp[i], d1 = drp[i + 1];
+    for (int t = threadIdx.x; t < d1 - d0; t += BLOCK) keys[off + t] = dci[d0 + t];
+    off += d1 - d0;
+  }
+  for (int t = off + threadIdx.x; t < p2; t += BLOCK) keys[t] = INT_MAX;
+  __syncthreads();
+  // bitonic sort, ascending
+  for (int k = 2; k <= p2; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = threadIdx.x; t < p2; t += BLOCK) {
+        int q = t ^ j;
+        if (q > t) {
+          int x = keys[t], y = keys[q];
+          bool up = (t & k) == 0;
+          if ((x > y) == up) {
+            keys[t] = y;
+            keys[q] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // unique columns in order
+  int o = FILL ? crp[i] : 0;
+  int running = 0;
+  for (int base = 0; base < p2; base += BLOCK) {
+    int t = base + threadIdx.x;
+    int flag = 0;
+    if (t < p2) {
+      int x = keys[t];
+      flag = x != INT_MAX && (t == 0 || keys[t - 1] != x);
+    }
+    int total;
+    int excl = block_exclusive_scan<int, BLOCK>(flag, sh, total);
+    if (flag) ukeys[running + excl] = keys[t];
+    running += total;
+  }
+  if (!FILL) {
+    if (threadIdx.x == 0) cnt[i] = running;
+    return;
+  }
+  __syncthreads();
+  // columns, then values with a fixed k order per output entry
+  for (int t = threadIdx.x; t < running; t += BLOCK) {
+    int col = ukeys[t];
+    cci[o + t] = col;
+    double sum = 0.0;
+    for (int e = a0; e < a1; ++e) {
+      int k = aci[e];
+      int p = bsearch_col(bci, brp[k], brp[k + 1], col);
+      if (p >= 0) sum += av[e] * bv[p];
+    }
+    double val = alpha * sum;
+    if (drp) {
+      int p = bsearch_col(dci, drp[i], drp[i + 1], col);
+      if (p >= 0) val = beta * dv[p] + val;
+    }
+    cv[o + t] = val;
+  }
+}
+
+// numeric refresh on a known pattern: one wavefront per row
+__global__ void __launch_bounds__(64) k_spgemm_values(
+    int nrows, const int* __restrict__ arp, const int* __restrict__ aci,
+    const double* __restrict__ av, const int* __restrict__ brp, const int* __restrict__ bci,
+    const double* __restrict__ bv, const int* __restrict__ drp, const int* __restrict__ dci,
+    const double* __restrict__ dv, double alpha, double beta, const int* __restrict__ crp,
+    const int* __restrict__ cci, double* __restrict__ cv) {
+  int i = blockIdx.x;
+  if (i >= nrows) return;
+  int a0 = arp[i], a1 = arp[i + 1];
+  for (int t = crp[i] + threadIdx.x; t < crp[i + 1]; t += 64) {
+    int col = cci[t];
+    double sum = 0.0;
+    for (int e = a0; e < a1; ++e) {
+      int k = aci[e];
+      int p = bsearch_col(bci, brp[k], brp[k + 1], col);
+      if (p >= 0) sum += av[e] * bv[p];
+    }
+    double val = alpha * sum;
+    if (drp) {
+      int p = bsearch_col(dci, drp[i], drp[i + 1], col);
+      if (p >= 0) val = beta * dv[p] + val;
+    }
+    cv[t] = val;
+  }
 }
 
 __global__ void k_col_count(int nrows, const int* __restrict__ rp, const int* __restrict__ ci,
@@ -120,34 +276,66 @@ void spgemm(const CsrRef<double>& A, const CsrRef<double>& B, Csr<double>& C, hi
     TPF_REQUIRE(D->nrows == A.nrows && D->ncols == B.ncols, TPF_ERR_INVALID_ARG,
                 "spgemm: added matrix has the wrong shape");
   int n = A.nrows;
-  Buf<int2> cur(A.nnz > 0 ? A.nnz : 1, s);
   const int* drp = D ? D->rp : nullptr;
   const int* dci = D ? D->ci : nullptr;
   const double* dv = D ? D->v : nullptr;
-  if (!reuse) {
-    C.nrows = n;
-    C.ncols = B.ncols;
-    C.rp.alloc(n + 1, s);
-    Buf<int> cnt(n > 0 ? n : 1, s);
-    if (n > 0) {
-      k_spgemm_merge<false><<<grid_for(n, 128), 128, 0, s>>>(
-          n, A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha, beta, cur.p, cnt.p, nullptr,
-          nullptr, nullptr);
-      TPF_CHECK_LAUNCH();
-    }
-    C.nnz = scan_exclusive(cnt.p, C.rp.p, n, s);
-    C.ci.alloc(C.nnz > 0 ? C.nnz : 1, s);
-    C.v.alloc(C.nnz > 0 ? C.nnz : 1, s);
-  } else {
+  if (reuse) {
     TPF_REQUIRE(C.nrows == n && C.ncols == B.ncols && C.rp.p, TPF_ERR_STATE,
                 "spgemm reuse: product pattern missing");
+    if (n > 0) {
+      k_spgemm_values<<<n, 64, 0, s>>>(n, A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha,
+                                       beta, C.rp.p, C.ci.p, C.v.p);
+      TPF_CHECK_LAUNCH();
+    }
+    return;
   }
-  if (n > 0) {
-    k_spgemm_merge<true><<<grid_for(n, 128), 128, 0, s>>>(n, A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp,
-                                                          dci, dv, alpha, beta, cur.p, nullptr,
-                                                          C.rp.p, C.ci.p, C.v.p);
+  C.nrows = n;
+  C.ncols = B.ncols;
+  C.rp.alloc(n + 1, s);
+  if (n == 0) {
+    C.nnz = scan_exclusive(nullptr, C.rp.p, 0, s);
+    C.ci.alloc(1, s);
+    C.v.alloc(1, s);
+    return;
+  }
+  constexpr int kCap0 = 1024, kCap1 = 4096, kCap2 = 16384;
+  Buf<int> ub(n, s), counts(4, s), lists(4 * int64_t(n), s), cnt(n, s);
+  fill_int(counts.p, 0, 4, s);
+  k_spgemm_ub<<<grid_for(n, 256), 256, 0, s>>>(n, A.rp, A.ci, B.rp, drp, ub.p);
+  TPF_CHECK_LAUNCH();
+  k_spgemm_classify<<<grid_for(n, 256), 256, 0, s>>>(n, ub.p, kCap0, kCap1, kCap2, counts.p,
+                                                     lists.p);
+  TPF_CHECK_LAUNCH();
+  int hc[4];
+  TPF_HIP(hipMemcpyAsync(hc, counts.p, sizeof(hc), hipMemcpyDeviceToHost, s));
+  TPF_HIP(hipStreamSynchronize(s));
+  Buf<int2> cur;
+  if (hc[3] > 0) cur.alloc(A.nnz > 0 ? A.nnz : 1, s);
+  auto run = [&](auto fill_tag) {
+    constexpr bool F = decltype(fill_tag)::value;
+    if (hc[0] > 0)
+      k_spgemm_sorted<64, kCap0, F><<<hc[0], 64, 0, s>>>(
+          lists.p, ub.p, A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha, beta, cnt.p,
+          C.rp.p, C.ci.p, C.v.p);
+    if (hc[1] > 0)
+      k_spgemm_sorted<256, kCap1, F><<<hc[1], 256, 0, s>>>(
+          lists.p + n, ub.p, A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha, beta, cnt.p,
+          C.rp.p, C.ci.p, C.v.p);
+    if (hc[2] > 0)
+      k_spgemm_sorted<256, kCap2, F><<<hc[2], 256, 0, s>>>(
+          lists.p + 2 * int64_t(n), ub.p, A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha,
+          beta, cnt.p, C.rp.p, C.ci.p, C.v.p);
+    if (hc[3] > 0)
+      k_spgemm_merge<F><<<grid_for(hc[3], 128), 128, 0, s>>>(
+          hc[3], lists.p + 3 * int64_t(n), A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha,
+          beta, cur.p, cnt.p, C.rp.p, C.ci.p, C.v.p);
     TPF_CHECK_LAUNCH();
-  }
+  };
+  run(std::false_type{});
+  C.nnz = scan_exclusive(cnt.p, C.rp.p, n, s);
+  C.ci.alloc(C.nnz > 0 ? C.nnz : 1, s);
+  C.v.alloc(C.nnz > 0 ? C.nnz : 1, s);
+  run(std::true_type{});
 }
 
 void transpose(const CsrRef<double>& A, Csr<double>& C, hipStream_t s) {

@@ -132,7 +132,7 @@ def test_schur_parity(gpu):
 
 
 @pytest.mark.parametrize("kind,hier,interp", [("bf", 0, "direct"), ("bf", 1, "ext+i"),
-                                              ("cpr1", 0, "ext+i"), ("amg", 0, "ext+i"),
+                                              ("cpr1", 0, "ext+i"), ("amg", 0, "direct"),
                                               ("cpr2", 1, "direct")])
 def test_amg_setup_parity_per_level(gpu, kind, hier, interp):
     """Each level's setup from the GPU's own level matrix (identical bits):
