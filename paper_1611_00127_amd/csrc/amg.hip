@@ -354,6 +354,7 @@ __global__ void k_exti_fill(int nl, const int* __restrict__ rows, const int* __r
 // ---- extended+i, one wavefront per F row (rows whose candidate bound fits
 // kExtCap); the per-thread kernels above handle the rest.
 constexpr int kExtCap = 1024;
+constexpr int kExtCap2 = 4096;
 
 __global__ void k_exti_ub(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                           const uint8_t* __restrict__ mask, const int8_t* __restrict__ cf,
@@ -364,23 +365,28 @@ __global__ void k_exti_ub(int n, const int* __restrict__ rp, const int* __restri
     ub[i] = 0;
     return;
   }
-  int64_t t = rp[i + 1] - rp[i];
+  // candidate count before removing duplicates
+  int64_t t = 0;
   for (int e = rp[i]; e < rp[i + 1]; ++e) {
     int k = ci[e];
-    if (mask[e] && k != i && cf[k] == kF) t += rp[k + 1] - rp[k];
+    if (!mask[e] || k == i) continue;
+    if (cf[k] == kC) {
+      ++t;
+    } else {
+      for (int f = rp[k]; f < rp[k + 1]; ++f) t += mask[f] && cf[ci[f]] == kC;
+    }
   }
   ub[i] = t > INT_MAX ? INT_MAX : int(t);
 }
 
-// rows of class 0 (ub <= kExtCap, F) and class 1 (the rest, F); C rows are
-// written directly by the fill kernels
+// F rows by candidate count: class 0 (<= kExtCap), 1 (<= kExtCap2), 2 (the
+// rest); C rows are written directly.  One atomic per class per wavefront.
 __global__ void k_exti_classify(int n, const int* __restrict__ ub, const int8_t* __restrict__ cf,
                                 int* __restrict__ counts, int* __restrict__ lists) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || cf[i] == kC) return;
-  int c = ub[i] <= kExtCap ? 0 : 1;
-  int pos = atomicAdd(&counts[c], 1);
-  lists[int64_t(c) * n + pos] = i;
+  int c = -1;
+  if (i < n && cf[i] != kC) c = ub[i] <= kExtCap ? 0 : (ub[i] <= kExtCap2 ? 1 : 2);
+  wave_append(c, 3, i, n, counts, lists);
 }
 
 // appends the columns of entries e in [e0, e1) that pass the filter to buf
@@ -410,15 +416,15 @@ __device__ inline int lds_find(const int* u, int m, int key) {
   return (lo < m && u[lo] == key) ? lo : -1;
 }
 
-template <bool FILL>
+template <bool FILL, int CAP>
 __global__ void __launch_bounds__(64) k_exti_wave(
     const int* __restrict__ rows, const int* __restrict__ rp, const int* __restrict__ ci,
     const double* __restrict__ v, const uint8_t* __restrict__ mask, const int8_t* __restrict__ cf,
     const int* __restrict__ cidx, int* __restrict__ cnt, const int* __restrict__ prp,
     int* __restrict__ pci, double* __restrict__ pv) {
-  __shared__ int cand[kExtCap];
-  __shared__ int uniq[kExtCap];
-  __shared__ double w[kExtCap];
+  __shared__ int cand[CAP];
+  __shared__ int uniq[CAP];
+  __shared__ double w[CAP];
   int lane = threadIdx.x;
   int i = rows[blockIdx.x];
   int a0 = rp[i], a1 = rp[i + 1];
@@ -597,10 +603,14 @@ __global__ void __launch_bounds__(1024) k_gauss_jordan(int n, double* __restrict
     for (int c = threadIdx.x; c < w; c += blockDim.x) M[int64_t(k) * w + c] /= piv;
     for (int r = threadIdx.x; r < n; r += blockDim.x) fac[r] = M[int64_t(r) * w + k];
     __syncthreads();
-    for (int64_t t = threadIdx.x; t < int64_t(n) * w; t += blockDim.x) {
-      int r = int(t / w), c = int(t % w);
-      if (r != k) M[t] -= fac[r] * M[int64_t(k) * w + c];
+    // columns <= k of the left block are already reduced (unit vectors)
+    int wc = w - (k + 1);
+    for (int64_t t = threadIdx.x; t < int64_t(n) * wc; t += blockDim.x) {
+      int r = int(t / wc), c = k + 1 + int(t % wc);
+      if (r != k) M[int64_t(r) * w + c] -= fac[r] * M[int64_t(k) * w + c];
     }
+    for (int r = threadIdx.x; r < n; r += blockDim.x)
+      if (r != k) M[int64_t(r) * w + k] = 0.0;
     __syncthreads();
   }
 }
@@ -763,25 +773,31 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
     L.P.ncols = int(nc);
     L.P.rp.alloc(n + 1, s);
     if (o.ext_i) {
-      Buf<int> ub(n, s), counts(2, s), lists(2 * int64_t(n), s);
-      fill_int(counts.p, 0, 2, s);
+      Buf<int> ub(n, s), counts(3, s), lists(3 * int64_t(n), s);
+      fill_int(counts.p, 0, 3, s);
       k_exti_ub<<<grid_for(n, 256), 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.mask.p, L.cf.p, ub.p);
       TPF_CHECK_LAUNCH();
       k_exti_classify<<<grid_for(n, 256), 256, 0, s>>>(n, ub.p, L.cf.p, counts.p, lists.p);
       TPF_CHECK_LAUNCH();
-      int hc[2];
+      int hc[3];
       TPF_HIP(hipMemcpyAsync(hc, counts.p, sizeof(hc), hipMemcpyDeviceToHost, s));
       TPF_HIP(hipStreamSynchronize(s));
       Buf<int2> cur;
-      if (hc[1] > 0) cur.alloc(L.A.nnz > 0 ? L.A.nnz : 1, s);
+      if (hc[2] > 0) cur.alloc(L.A.nnz > 0 ? L.A.nnz : 1, s);
       const int* l0 = lists.p;
       const int* l1 = lists.p + n;
+      const int* l2 = lists.p + 2 * int64_t(n);
       k_inject_c<<<grid_for(n, 256), 256, 0, s>>>(n, L.cf.p, cidx.p, nullptr, nullptr, nullptr, cnt.p);
       if (hc[0] > 0)
-        k_exti_wave<false><<<hc[0], 64, 0, s>>>(l0, L.A.rp.p, L.A.ci.p, L.A.v.p, L.mask.p, L.cf.p,
-                                                cidx.p, cnt.p, nullptr, nullptr, nullptr);
+        k_exti_wave<false, kExtCap><<<hc[0], 64, 0, s>>>(l0, L.A.rp.p, L.A.ci.p, L.A.v.p, L.mask.p,
+                                                         L.cf.p, cidx.p, cnt.p, nullptr, nullptr,
+                                                         nullptr);
       if (hc[1] > 0)
-        k_exti_count<<<grid_for(hc[1], 128), 128, 0, s>>>(hc[1], l1, L.A.rp.p, L.A.ci.p, L.mask.p,
+        k_exti_wave<false, kExtCap2><<<hc[1], 64, 0, s>>>(l1, L.A.rp.p, L.A.ci.p, L.A.v.p, L.mask.p,
+                                                          L.cf.p, cidx.p, cnt.p, nullptr, nullptr,
+                                                          nullptr);
+      if (hc[2] > 0)
+        k_exti_count<<<grid_for(hc[2], 128), 128, 0, s>>>(hc[2], l2, L.A.rp.p, L.A.ci.p, L.mask.p,
                                                           L.cf.p, cur.p, cnt.p);
       TPF_CHECK_LAUNCH();
       L.P.nnz = scan_exclusive(cnt.p, L.P.rp.p, n, s);
@@ -790,10 +806,15 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
       k_inject_c<<<grid_for(n, 256), 256, 0, s>>>(n, L.cf.p, cidx.p, L.P.rp.p, L.P.ci.p, L.P.v.p,
                                                   nullptr);
       if (hc[0] > 0)
-        k_exti_wave<true><<<hc[0], 64, 0, s>>>(l0, L.A.rp.p, L.A.ci.p, L.A.v.p, L.mask.p, L.cf.p,
-                                               cidx.p, nullptr, L.P.rp.p, L.P.ci.p, L.P.v.p);
+        k_exti_wave<true, kExtCap><<<hc[0], 64, 0, s>>>(l0, L.A.rp.p, L.A.ci.p, L.A.v.p, L.mask.p,
+                                                        L.cf.p, cidx.p, nullptr, L.P.rp.p, L.P.ci.p,
+                                                        L.P.v.p);
       if (hc[1] > 0)
-        k_exti_fill<<<grid_for(hc[1], 128), 128, 0, s>>>(hc[1], l1, L.A.rp.p, L.A.ci.p, L.A.v.p,
+        k_exti_wave<true, kExtCap2><<<hc[1], 64, 0, s>>>(l1, L.A.rp.p, L.A.ci.p, L.A.v.p, L.mask.p,
+                                                         L.cf.p, cidx.p, nullptr, L.P.rp.p,
+                                                         L.P.ci.p, L.P.v.p);
+      if (hc[2] > 0)
+        k_exti_fill<<<grid_for(hc[2], 128), 128, 0, s>>>(hc[2], l2, L.A.rp.p, L.A.ci.p, L.A.v.p,
                                                          L.mask.p, L.cf.p, cidx.p, cur.p, L.P.rp.p,
                                                          L.P.ci.p, L.P.v.p);
       TPF_CHECK_LAUNCH();

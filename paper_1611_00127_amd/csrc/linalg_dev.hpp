@@ -78,6 +78,23 @@ __device__ inline T row_dot(int row, int lane, const int* __restrict__ rp,
   return sum;
 }
 
+// Appends `item` to list number `cls` (cls < 0: nothing) with one atomic per
+// list per wavefront; lists are laid out as nlists rows of `stride` entries.
+// The order inside a list is not specified.
+__device__ inline void wave_append(int cls, int nlists, int item, int stride, int* counts,
+                                   int* lists) {
+  int lane = threadIdx.x & (kWave - 1);
+  for (int c = 0; c < nlists; ++c) {
+    unsigned long long b = __ballot(cls == c);
+    if (!b) continue;
+    int leader = __ffsll(b) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&counts[c], int(__popcll(b)));
+    base = __shfl(base, leader, kWave);
+    if (cls == c) lists[int64_t(c) * stride + base + __popcll(b & ((1ull << lane) - 1ull))] = item;
+  }
+}
+
 inline int lanes_per_row(int64_t nrows, int64_t nnz) {
   double avg = nrows ? double(nnz) / double(nrows) : 1.0;
   int l = 1;

@@ -94,11 +94,12 @@ __global__ void k_spgemm_ub(int nrows, const int* __restrict__ arp, const int* _
 __global__ void k_spgemm_classify(int nrows, const int* __restrict__ ub, int cap0, int cap1,
                                   int cap2, int* __restrict__ counts, int* __restrict__ lists) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nrows) return;
-  int u = ub[i];
-  int c = u <= cap0 ? 0 : (u <= cap1 ? 1 : (u <= cap2 ? 2 : 3));
-  int pos = atomicAdd(&counts[c], 1);
-  lists[int64_t(c) * nrows + pos] = i;
+  int c = -1;
+  if (i < nrows) {
+    int u = ub[i];
+    c = u <= cap0 ? 0 : (u <= cap1 ? 1 : (u <= cap2 ? 2 : 3));
+  }
+  wave_append(c, 4, i, nrows, counts, lists);
 }
 
 __device__ inline int bsearch_col(const int* __restrict__ c, int lo, int hi, int key) {

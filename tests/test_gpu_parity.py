@@ -165,8 +165,10 @@ def test_amg_setup_parity_per_level(gpu, kind, hier, interp):
         assert np.array_equal(P[0], Po.indptr) and np.array_equal(P[1], Po.indices), f"P level {l}"
         ok, worst = _row_scale_close(P[2], Po.data, Po.indptr, 1e-12)
         assert ok, (l, worst)
+        # R is the exact transpose of the GPU's own P (pure data movement)
         R = tpf.csr_to_numpy(tpf.tpf_precond_matrix(M.M, hier, l, tpf.TPF_MAT_R))
-        Ro = Po.T.tocsr(); Ro.sort_indices()
+        Pg = sp.csr_matrix((P[2], P[1], P[0]), shape=Po.shape)
+        Ro = Pg.T.tocsr(); Ro.sort_indices()
         assert np.array_equal(R[0], Ro.indptr) and np.array_equal(R[1], Ro.indices)
         assert np.array_equal(R[2], Ro.data)
         Ac = _download_level(tpf, M, hier, l + 1)
