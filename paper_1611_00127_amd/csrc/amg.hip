@@ -698,6 +698,72 @@ __global__ void __launch_bounds__(256) k_dense_gemv(int n, const double* __restr
   if (lane == 0) x[row] = T(sum);
 }
 
+// ---------------------------------------------------------------- level-0 diagonal layout
+struct DiagOffs {
+  int off[kMaxDiag];
+};
+
+__global__ void k_csr_to_dia(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                             const double* __restrict__ v, int K, DiagOffs o,
+                             double* __restrict__ dv, int* __restrict__ flag) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    int d = ci[e] - i;
+    int k = 0;
+    while (k < K && o.off[k] != d) ++k;
+    if (k == K) {
+      *flag = 1;
+      continue;
+    }
+    dv[int64_t(k) * n + i] = v[e];
+  }
+}
+
+__device__ inline int clampi(int j, int n) { return j < 0 ? 0 : (j >= n ? n - 1 : j); }
+
+// r = b - A (D^{-1} b)
+template <class T, int K>
+__global__ void __launch_bounds__(256) k_dia_pre(int n, DiagOffs o, const T* __restrict__ v,
+                                                 const T* __restrict__ dinv,
+                                                 const T* __restrict__ b, T* __restrict__ r) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T sum = T(0);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    int j = clampi(i + o.off[k], n);
+    sum += v[int64_t(k) * n + i] * (dinv[j] * b[j]);
+  }
+  r[i] = b[i] - sum;
+}
+
+// x = y + D^{-1} (b - A y)
+template <class T, int K>
+__global__ void __launch_bounds__(256) k_dia_post(int n, DiagOffs o, const T* __restrict__ v,
+                                                  const T* __restrict__ dinv,
+                                                  const T* __restrict__ b,
+                                                  const T* __restrict__ y, T* __restrict__ x) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T sum = T(0);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    int j = clampi(i + o.off[k], n);
+    sum += v[int64_t(k) * n + i] * y[j];
+  }
+  x[i] = y[i] + dinv[i] * (b[i] - sum);
+}
+
+#define DISPATCH_DIAG(K, KK, ...)                               \
+  switch (K) {                                                  \
+    case 5: { constexpr int KK = 5; __VA_ARGS__ } break;        \
+    case 7: { constexpr int KK = 7; __VA_ARGS__ } break;        \
+    case 13: { constexpr int KK = 13; __VA_ARGS__ } break;      \
+    case 25: { constexpr int KK = 25; __VA_ARGS__ } break;      \
+    default: fail(TPF_ERR_STATE, "unsupported stencil width %d", K); \
+  }
+
 template <class T>
 const T* vals_of(const Csr<double>& M, const Buf<float>& v32);
 template <>
@@ -886,6 +952,35 @@ void Hierarchy::finish_levels(hipStream_t st) {
       }
     }
   }
+  // level-0 diagonal layout
+  dia0.ok = false;
+  int K = int(stencil.size());
+  if (K == 5 || K == 7 || K == 13 || K == 25) {
+    Level& L = *lv[0];
+    int n = L.A.nrows;
+    dia0.K = K;
+    dia0.n = n;
+    for (int k = 0; k < K; ++k) dia0.off[k] = stencil[k];
+    DiagOffs off;
+    for (int k = 0; k < kMaxDiag; ++k) off.off[k] = k < K ? stencil[k] : 0;
+    dia0.v.ensure(size_t(K) * n, st);
+    fill(dia0.v.p, 0.0, int64_t(K) * n, st);
+    Buf<int> flag(1, st);
+    fill_int(flag.p, 0, 1, st);
+    k_csr_to_dia<<<grid_for(n, 256), 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, L.A.v.p, K, off, dia0.v.p,
+                                                   flag.p);
+    TPF_CHECK_LAUNCH();
+    int f = read_scalar(flag.p, st);
+    dia0.ok = f == 0;
+    if (dia0.ok && o.fp32) {
+      dia0.v32.ensure(size_t(K) * n, st);
+      cast<double, float>(dia0.v32.p, dia0.v.p, int64_t(K) * n, st);
+    }
+    if (!dia0.ok) {
+      dia0.v.release();
+      dia0.v32.release();
+    }
+  }
   coarse_setup(st);
 }
 
@@ -913,7 +1008,7 @@ void Hierarchy::coarse_setup(hipStream_t st) {
 }
 
 size_t Hierarchy::bytes() const {
-  size_t b = Ainv.bytes();
+  size_t b = Ainv.bytes() + dia0.bytes();
   for (auto& Lp : lv) {
     const Level& L = *Lp;
     b += L.A.bytes() + L.dinv.bytes() + L.mask.bytes() + L.S.bytes() + L.cf.bytes() + L.P.bytes() +
@@ -950,11 +1045,27 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st) {
   T* y = work<T>(L.y, L.y32);
   T* bc = work<T>(C.b, C.b32);
   T* xc = work<T>(C.x, C.x32);
+  bool dia = l == 0 && dia0.ok;
+  DiagOffs doff;
+  const T* dv = nullptr;
+  if (dia) {
+    for (int k = 0; k < kMaxDiag; ++k) doff.off[k] = dia0.off[k];
+    if constexpr (std::is_same<T, float>::value)
+      dv = dia0.v32.p;
+    else
+      dv = dia0.v.p;
+  }
   {
     TimedScope ts(L.t_pre.c_str(), st);
-    DISPATCH_LPR(lpr, LL, {
-      k_vc_pre<T, LL><<<blocks, 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, Av, dinv, b, r);
-    });
+    if (dia) {
+      DISPATCH_DIAG(dia0.K, KK, {
+        k_dia_pre<T, KK><<<grid_for(n, 256), 256, 0, st>>>(n, doff, dv, dinv, b, r);
+      });
+    } else {
+      DISPATCH_LPR(lpr, LL, {
+        k_vc_pre<T, LL><<<blocks, 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, Av, dinv, b, r);
+      });
+    }
     TPF_CHECK_LAUNCH();
   }
   csr_spmv<T>(ref_with<T>(L.R, vals_of<T>(L.R, L.Rv32)), r, bc, st, L.t_restrict.c_str());
@@ -970,9 +1081,15 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st) {
   }
   {
     TimedScope ts(L.t_post.c_str(), st);
-    DISPATCH_LPR(lpr, LL, {
-      k_vc_post<T, LL><<<blocks, 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, Av, dinv, b, y, x);
-    });
+    if (dia) {
+      DISPATCH_DIAG(dia0.K, KK, {
+        k_dia_post<T, KK><<<grid_for(n, 256), 256, 0, st>>>(n, doff, dv, dinv, b, y, x);
+      });
+    } else {
+      DISPATCH_LPR(lpr, LL, {
+        k_vc_post<T, LL><<<blocks, 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, Av, dinv, b, y, x);
+      });
+    }
     TPF_CHECK_LAUNCH();
   }
 }

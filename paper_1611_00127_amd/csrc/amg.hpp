@@ -34,6 +34,19 @@ struct Level {
   std::string t_pre, t_restrict, t_prolong, t_post;
 };
 
+// Level-0 operator in diagonal (stencil) layout: value of row i on diagonal
+// k at v[k * n + i], column i + off[k]; entries outside the grid are zero.
+constexpr int kMaxDiag = 32;
+struct Dia {
+  int K = 0;
+  int n = 0;
+  int off[kMaxDiag] = {};
+  Buf<double> v;
+  Buf<float> v32;
+  bool ok = false;
+  size_t bytes() const { return v.bytes() + v32.bytes(); }
+};
+
 struct Hierarchy {
   AmgOpts o;
   std::vector<std::unique_ptr<Level>> lv;
@@ -41,6 +54,8 @@ struct Hierarchy {
   Buf<double> Ainv;     // dense inverse of the coarsest operator (row-major)
   hipStream_t s = nullptr;
   std::string tag = "A";  // operator name used in kernel-timer labels
+  std::vector<int> stencil;  // level-0 diagonal offsets (empty: CSR only)
+  Dia dia0;
 
   // Full setup from the level-0 operator.
   void build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st);

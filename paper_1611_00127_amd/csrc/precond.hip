@@ -13,6 +13,7 @@
 // factorisation and both triangular solves proceed by anti-diagonal
 // wavefronts ix+iy+iz = const, whose cells are mutually independent.
 #include <algorithm>
+#include <cstdlib>
 #include <type_traits>
 
 #include "linalg_dev.hpp"
@@ -255,6 +256,23 @@ Csr<double> block_copy(const tpf_precond* M, const double* vals, hipStream_t s) 
 
 // interpolation per operator: AUTO uses extended+i for the pressure-like
 // operators (S~, A_pp) and direct interpolation for A_ss and the scalar J
+// offsets of the stencil |dx|+|dy|+|dz| <= radius on the grid, ascending;
+// empty when two offsets coincide (very thin grids)
+std::vector<int> stencil_offsets(const Phys& ph, int radius) {
+  std::vector<int> off;
+  int rz = ph.nz > 1 ? radius : 0, ry = ph.ny > 1 ? radius : 0, rx = ph.nx > 1 ? radius : 0;
+  for (int dz = -rz; dz <= rz; ++dz)
+    for (int dy = -ry; dy <= ry; ++dy)
+      for (int dx = -rx; dx <= rx; ++dx)
+        if (std::abs(dx) + std::abs(dy) + std::abs(dz) <= radius)
+          off.push_back(dx + ph.nx * (dy + ph.ny * dz));
+  std::sort(off.begin(), off.end());
+  for (size_t k = 1; k < off.size(); ++k)
+    if (off[k] == off[k - 1]) return {};
+  if (radius >= 2 && (ph.nx < 5 || (ph.ny > 1 && ph.ny < 5) || (ph.nz > 1 && ph.nz < 5))) return {};
+  return off;
+}
+
 AmgOpts amg_opts(const tpf_precond_opts& o, bool pressure_like) {
   AmgOpts a;
   a.ext_i = o.interp == TPF_INTERP_EXTI || (o.interp == TPF_INTERP_AUTO && pressure_like);
@@ -546,6 +564,7 @@ int tpf_precond_setup(tpf_precond* M, const tpf_jacobian* J, int reuse, void* st
         if (!re) {
           M->H[h] = std::make_unique<Hierarchy>();
           M->H[h]->tag = h == 0 ? "App" : "Ass";
+          M->H[h]->stencil = stencil_offsets(J->prob->ph, 1);
           M->H[h]->build(block_copy(M, src[h], s), h == 0 ? ao_p : ao_s, s);
         } else {
           copy(M->H[h]->A0().v.p, src[h], nnzb, s);
@@ -568,11 +587,13 @@ int tpf_precond_setup(tpf_precond* M, const tpf_jacobian* J, int reuse, void* st
       if (!re) {
         M->H[0] = std::make_unique<Hierarchy>();
         M->H[0]->tag = "Ass";
+        M->H[0]->stencil = stencil_offsets(J->prob->ph, 1);
         M->H[0]->build(block_copy(M, M->ass_v.p, s), ao_s, s);
         Csr<double> S;
         spgemm(Y, Asp, S, s, &App, -1.0, 1.0, false);
         M->H[1] = std::make_unique<Hierarchy>();
         M->H[1]->tag = "Schur";
+        M->H[1]->stencil = stencil_offsets(J->prob->ph, 2);
         M->H[1]->build(std::move(S), ao_p, s);
       } else {
         copy(M->H[0]->A0().v.p, M->ass_v.p, nnzb, s);

@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(BLOCK) k_spgemm_sorted(
     const int* __restrict__ dci, const double* __restrict__ dv, double alpha, double beta,
     int* __restrict__ cnt, const int* __restrict__ crp, int* __restrict__ cci,
     double* __restrict__ cv) {
-  __shared__ int keys[CAP];
+  __shared__ __attribute__((aligned(16))) int keys[CAP];
   __shared__ int ukeys[CAP];
   __shared__ int sh[BLOCK / 64 + 1];
   int i = rows[blockIdx.x];
@@ -182,10 +182,51 @@ __global__ void __launch_bounds__(BLOCK) k_spgemm_sorted(
     return;
   }
   __syncthreads();
-  // columns, then values with a fixed k order per output entry
+  for (int t = threadIdx.x; t < running; t += BLOCK) cci[o + t] = ukeys[t];
+  if (running <= CAP / 2) {
+    // values: scatter A_ik B_kj into an LDS accumulator (aliasing keys), one
+    // k at a time in A's column order, so each sum has the sequential order
+    double* acc = reinterpret_cast<double*>(keys);
+    for (int t = threadIdx.x; t < running; t += BLOCK) acc[t] = 0.0;
+    __syncthreads();
+    for (int e = a0; e < a1; ++e) {
+      int k = aci[e];
+      double a = av[e];
+      int b0 = brp[k], b1 = brp[k + 1];
+      for (int t = threadIdx.x; t < b1 - b0; t += BLOCK) {
+        int col = bci[b0 + t];
+        int lo = 0, hi = running;
+        while (lo < hi) {
+          int mid = (lo + hi) >> 1;
+          if (ukeys[mid] < col) lo = mid + 1;
+          else hi = mid;
+        }
+        acc[lo] += a * bv[b0 + t];
+      }
+      __syncthreads();
+    }
+    for (int t = threadIdx.x; t < running; t += BLOCK) acc[t] = alpha * acc[t];
+    __syncthreads();
+    if (drp) {
+      int d0 = drp[i], d1 = drp[i + 1];
+      for (int t = threadIdx.x; t < d1 - d0; t += BLOCK) {
+        int col = dci[d0 + t];
+        int lo = 0, hi = running;
+        while (lo < hi) {
+          int mid = (lo + hi) >> 1;
+          if (ukeys[mid] < col) lo = mid + 1;
+          else hi = mid;
+        }
+        acc[lo] = beta * dv[d0 + t] + acc[lo];
+      }
+      __syncthreads();
+    }
+    for (int t = threadIdx.x; t < running; t += BLOCK) cv[o + t] = acc[t];
+    return;
+  }
+  // wide rows: each output entry sums over k in order (B_kj by binary search)
   for (int t = threadIdx.x; t < running; t += BLOCK) {
     int col = ukeys[t];
-    cci[o + t] = col;
     double sum = 0.0;
     for (int e = a0; e < a1; ++e) {
       int k = aci[e];
