@@ -41,14 +41,17 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-grid", type=str, default="80x80x40",
                     help="grid of the oracle's bounded sample")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (calibrates the "
+                         "FETCH_SIZE/WRITE_SIZE counters of a profiler run)")
     return ap.parse_args()
 
 
-def level0_bytes(nnz, n, w, kind):
-    """Algorithmic bytes of one level-0 V-cycle kernel launch (CSR, int32
-    indices, value width w): matrix values + column indices + row pointers
-    once, each dense vector once."""
-    mat = (w + 4) * nnz + 4 * (n + 1)
+def level0_bytes(nnz, n, w, kind, diagonals=0):
+    """Algorithmic bytes of one level-0 V-cycle kernel launch, value width w:
+    the operator once (diagonal layout: K*n values; CSR: values, int32
+    column indices and row pointers) and each dense vector once."""
+    mat = w * diagonals * n if diagonals else (w + 4) * nnz + 4 * (n + 1)
     if kind == "pre":      # read b, dinv; write r (A D^{-1} b gathered)
         return mat + 3 * w * n
     if kind == "post":     # read b, dinv, y; write x
@@ -104,6 +107,10 @@ def run_form(torch, tpf, driver, g, precision, steps, warmup, timing):
                op_complexity=[round(float(st.operator_complexity[h]), 3) for h in range(st.n_hier)],
                l0_nnz=[int(st.nnz[h][0]) for h in range(st.n_hier)],
                l0_rows=[int(st.rows[h][0]) for h in range(st.n_hier)],
+               l0_diagonals=[int(st.l0_diagonals[h]) for h in range(st.n_hier)],
+               rows_per_level=[[int(st.rows[h][l]) for l in range(st.levels[h])]
+                               for h in range(st.n_hier)],
+               coarse_dense=[int(st.coarse_dense[h]) for h in range(st.n_hier)],
                precond_mib=st.device_bytes / 2 ** 20)
     return M, x, res
 
@@ -145,6 +152,15 @@ def main():
 
     from paper_1611_00127_amd import driver, inputs, tpf
     tpf.init()
+    if args.copy_probe > 0:
+        n = args.copy_probe * 2 ** 20 // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {args.copy_probe} MiB read + {args.copy_probe} MiB written")
+        del src, dst
     nx, ny, nz = (int(v) for v in args.grid.split("x"))
     log(f"[bench] generating workload {nx}x{ny}x{nz}")
     c = inputs.config_c3(nx, ny, nz)
@@ -170,10 +186,12 @@ def main():
     h = 1 if "Schur" in dom else 0
     nnz, n = r64["l0_nnz"][h], r64["l0_rows"][h]
     kind = "pre" if "pre_residual" in dom else "post"
-    bytes_per_launch = level0_bytes(nnz, n, 8, kind) if ("pre" in kind or "post" in kind) else None
+    bytes_per_launch = level0_bytes(nnz, n, 8, kind, r64["l0_diagonals"][h])
     avg_ms = ms / cnt
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+    roof = {"kernel": dom, "layout": (f"diagonal, {r64['l0_diagonals'][h]} diagonals"
+                                      if r64["l0_diagonals"][h] else "csr"),
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "avg_launch_us": round(avg_ms * 1e3, 2), "launches": cnt,
             "algorithmic_bytes_per_launch": bytes_per_launch}

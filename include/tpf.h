@@ -186,6 +186,8 @@ typedef struct tpf_hier_stats {
   double operator_complexity[3];
   double grid_complexity[3];
   int coarse_dense[3];
+  int l0_diagonals[3];                 /* level-0 smoother layout: number of stored diagonals
+                                          (diagonal layout), 0 = CSR */
   size_t device_bytes;                 /* bytes held by the preconditioner */
 } tpf_hier_stats;
 int tpf_precond_stats(const tpf_precond* M, tpf_hier_stats* out);

@@ -642,6 +642,7 @@ int tpf_precond_stats(const tpf_precond* M, tpf_hier_stats* out) {
       out->operator_complexity[h] = snnz / nnz0;
       out->grid_complexity[h] = srows / rows0;
       out->coarse_dense[h] = H.coarse_dense;
+      out->l0_diagonals[h] = H.dia0.ok ? H.dia0.K : 0;
     }
     out->device_bytes = M->bytes();
   });

@@ -66,7 +66,8 @@ class HierStats(ctypes.Structure):
     _fields_ = [("n_hier", c_int), ("levels", c_int * 3),
                 ("rows", (c_int64 * TPF_MAX_LEVELS) * 3), ("nnz", (c_int64 * TPF_MAX_LEVELS) * 3),
                 ("operator_complexity", c_double * 3), ("grid_complexity", c_double * 3),
-                ("coarse_dense", c_int * 3), ("device_bytes", c_size_t)]
+                ("coarse_dense", c_int * 3), ("l0_diagonals", c_int * 3),
+                ("device_bytes", c_size_t)]
 
 
 class SolveOpts(ctypes.Structure):
