@@ -356,27 +356,33 @@ __global__ void k_exti_fill(int nl, const int* __restrict__ rows, const int* __r
 constexpr int kExtCap = 1024;
 constexpr int kExtCap2 = 4096;
 
-__global__ void k_exti_ub(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                          const uint8_t* __restrict__ mask, const int8_t* __restrict__ cf,
-                          int* __restrict__ ub) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+// candidate count of F row i before removing duplicates: strong C
+// neighbours of i plus those of each strong F neighbour (one wavefront per
+// row, four rows per block)
+__global__ void __launch_bounds__(256) k_exti_ub(int n, const int* __restrict__ rp,
+                                                 const int* __restrict__ ci,
+                                                 const uint8_t* __restrict__ mask,
+                                                 const int8_t* __restrict__ cf,
+                                                 int* __restrict__ ub) {
+  int i = blockIdx.x * 4 + int(threadIdx.x / 64);
+  int lane = threadIdx.x & 63;
   if (i >= n) return;
   if (cf[i] == kC) {
-    ub[i] = 0;
+    if (lane == 0) ub[i] = 0;
     return;
   }
-  // candidate count before removing duplicates
   int64_t t = 0;
+  for (int e = rp[i] + lane; e < rp[i + 1]; e += 64) {
+    int k = ci[e];
+    if (mask[e] && k != i && cf[k] == kC) ++t;
+  }
   for (int e = rp[i]; e < rp[i + 1]; ++e) {
     int k = ci[e];
-    if (!mask[e] || k == i) continue;
-    if (cf[k] == kC) {
-      ++t;
-    } else {
-      for (int f = rp[k]; f < rp[k + 1]; ++f) t += mask[f] && cf[ci[f]] == kC;
-    }
+    if (!(mask[e] && k != i && cf[k] == kF)) continue;
+    for (int f = rp[k] + lane; f < rp[k + 1]; f += 64) t += mask[f] && cf[ci[f]] == kC;
   }
-  ub[i] = t > INT_MAX ? INT_MAX : int(t);
+  t = wave_sum(t);
+  if (lane == 0) ub[i] = t > INT_MAX ? INT_MAX : int(t);
 }
 
 // F rows by candidate count: class 0 (<= kExtCap), 1 (<= kExtCap2), 2 (the
@@ -841,7 +847,7 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
     if (o.ext_i) {
       Buf<int> ub(n, s), counts(3, s), lists(3 * int64_t(n), s);
       fill_int(counts.p, 0, 3, s);
-      k_exti_ub<<<grid_for(n, 256), 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.mask.p, L.cf.p, ub.p);
+      k_exti_ub<<<grid_for(n, 4), 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.mask.p, L.cf.p, ub.p);
       TPF_CHECK_LAUNCH();
       k_exti_classify<<<grid_for(n, 256), 256, 0, s>>>(n, ub.p, L.cf.p, counts.p, lists.p);
       TPF_CHECK_LAUNCH();

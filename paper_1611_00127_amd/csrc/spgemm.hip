@@ -3,14 +3,17 @@
 // and for the approximate Schur complement S~ = A_pp - (A_ps D^{-1}) A_sp.
 //
 // Output row i has the sorted unique columns of the rows B_k, k in A_i (and
-// of D_i when a matrix is added).  Rows are grouped by their product count
-// ub_i: one wavefront per row (ub_i <= 1024) or one 256-thread work-group
-// (ub_i <= 4096 or <= 16384) gathers the product columns into LDS,
-// bitonic-sorts them and keeps the unique ones; each output value is then the
-// sum over k in A's column order of A_ik B_kj (B_kj found by binary search),
-// so the result is deterministic and identical for every row class.  Rows
-// above 16384 products fall back to one thread per row merging the sorted B
-// rows with a cursor each (same summation order).
+// of D_i when a matrix is added); each value is the sum over k in A's column
+// order of A_ik B_kj, so the result is deterministic and identical for every
+// row class.  Rows are grouped by their product count ub_i:
+//   ub_i <= 512 / 2048  one wavefront / 256-thread work-group takes the
+//                       flattened product list (one load round per lane per
+//                       product), sorts (column, product index) keys in LDS
+//                       and sums each run of equal columns in order;
+//   ub_i <= 16384       one work-group sorts the product columns, then sums
+//                       over k per output entry (B_kj by binary search);
+//   larger              one thread per row merges the sorted B rows with a
+//                       cursor each.
 #include <climits>
 #include <type_traits>
 
@@ -86,11 +89,13 @@ __global__ void k_spgemm_ub(int nrows, const int* __restrict__ arp, const int* _
   if (i >= nrows) return;
   int64_t t = drp ? drp[i + 1] - drp[i] : 0;
   for (int e = arp[i]; e < arp[i + 1]; ++e) t += brp[aci[e] + 1] - brp[aci[e]];
+  int64_t la = arp[i + 1] - arp[i];
+  if (la > t) t = la;  // the flattened kernels also hold A's row in LDS
   ub[i] = t > INT_MAX ? INT_MAX : int(t);
 }
 
-// appends row i to the list of its size class: 0 wavefront, 1-2 work-group
-// with 32 / 128 KB of LDS, 3 per-thread merge
+// appends row i to the list of its size class: 0 flattened wavefront,
+// 1 flattened work-group, 2 sorted-columns work-group, 3 per-thread merge
 __global__ void k_spgemm_classify(int nrows, const int* __restrict__ ub, int cap0, int cap1,
                                   int cap2, int* __restrict__ counts, int* __restrict__ lists) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -242,6 +247,116 @@ __global__ void __launch_bounds__(BLOCK) k_spgemm_sorted(
   }
 }
 
+// Flattened product list (rows with at most CAP products and CAP entries in
+// A's row): product t of row i is (e, p) with e found from the prefix of the
+// B row lengths; keys (col << 32 | t) are bitonic-sorted so that equal
+// columns are adjacent in increasing t, i.e. in A's column order, and each
+// output value is the sequential sum over its run.
+template <int BLOCK, int CAP, bool FILL>
+__global__ void __launch_bounds__(BLOCK) k_spgemm_flat(
+    const int* __restrict__ rows, const int* __restrict__ ub, const int* __restrict__ arp,
+    const int* __restrict__ aci, const double* __restrict__ av, const int* __restrict__ brp,
+    const int* __restrict__ bci, const double* __restrict__ bv, const int* __restrict__ drp,
+    const int* __restrict__ dci, const double* __restrict__ dv, double alpha, double beta,
+    int* __restrict__ cnt, const int* __restrict__ crp, int* __restrict__ cci,
+    double* __restrict__ cv) {
+  __shared__ int offs[CAP + 1];
+  __shared__ unsigned long long keys[CAP];
+  __shared__ double pv[FILL ? CAP : 1];
+  __shared__ int sh[BLOCK / 64 + 1];
+  int i = rows[blockIdx.x];
+  int a0 = arp[i], a1 = arp[i + 1];
+  int la = a1 - a0;
+  // prefix of B row lengths over A's row (block scan in chunks)
+  int run = 0;
+  for (int base = 0; base < la; base += BLOCK) {
+    int e = base + threadIdx.x;
+    int len = 0;
+    if (e < la) {
+      int k = aci[a0 + e];
+      len = brp[k + 1] - brp[k];
+    }
+    int total;
+    int excl = block_exclusive_scan<int, BLOCK>(len, sh, total);
+    if (e < la) offs[e] = run + excl;
+    run += total;
+  }
+  if (threadIdx.x == 0) offs[la] = run;
+  int nprod = run;
+  int nd = drp ? drp[i + 1] - drp[i] : 0;
+  int u = nprod + nd;
+  int p2 = 1;
+  while (p2 < u) p2 <<= 1;
+  __syncthreads();
+  for (int t = threadIdx.x; t < p2; t += BLOCK) {
+    unsigned long long key = ~0ull;
+    if (t < nprod) {
+      int lo = 0, hi = la;  // largest e with offs[e] <= t
+      while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (offs[mid] <= t) lo = mid;
+        else hi = mid;
+      }
+      while (lo + 1 < la && offs[lo + 1] <= t) ++lo;  // skip empty B rows
+      int k = aci[a0 + lo];
+      int p = brp[k] + (t - offs[lo]);
+      key = (static_cast<unsigned long long>(static_cast<unsigned>(bci[p])) << 32) | unsigned(t);
+      if (FILL) pv[t] = av[a0 + lo] * bv[p];
+    } else if (t < u) {
+      int p = drp[i] + (t - nprod);
+      key = (static_cast<unsigned long long>(static_cast<unsigned>(dci[p])) << 32) | unsigned(t);
+      if (FILL) pv[t] = dv[p];
+    }
+    keys[t] = key;
+  }
+  __syncthreads();
+  for (int k = 2; k <= p2; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = threadIdx.x; t < p2; t += BLOCK) {
+        int q = t ^ j;
+        if (q > t) {
+          unsigned long long x = keys[t], y = keys[q];
+          bool up = (t & k) == 0;
+          if ((x > y) == up) {
+            keys[t] = y;
+            keys[q] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  // run heads -> output positions; each head sums its run in order
+  int o = FILL ? crp[i] : 0;
+  int count = 0;
+  for (int base = 0; base < p2; base += BLOCK) {
+    int t = base + threadIdx.x;
+    int head = 0;
+    if (t < u) head = t == 0 || (keys[t - 1] >> 32) != (keys[t] >> 32);
+    int total;
+    int excl = block_exclusive_scan<int, BLOCK>(head, sh, total);
+    if (FILL && head) {
+      int col = int(keys[t] >> 32);
+      double sum = 0.0, dterm = 0.0;
+      bool has_d = false;
+      for (int q = t; q < u && int(keys[q] >> 32) == col; ++q) {
+        int src = int(keys[q] & 0xffffffffu);
+        if (src < nprod) {
+          sum += pv[src];
+        } else {
+          dterm = pv[src];
+          has_d = true;
+        }
+      }
+      double val = alpha * sum;
+      if (has_d) val = beta * dterm + val;
+      cci[o + count + excl] = col;
+      cv[o + count + excl] = val;
+    }
+    count += total;
+  }
+  if (!FILL && threadIdx.x == 0) cnt[i] = count;
+}
+
 // numeric refresh on a known pattern: one wavefront per row
 __global__ void __launch_bounds__(64) k_spgemm_values(
     int nrows, const int* __restrict__ arp, const int* __restrict__ aci,
@@ -340,7 +455,7 @@ void spgemm(const CsrRef<double>& A, const CsrRef<double>& B, Csr<double>& C, hi
     C.v.alloc(1, s);
     return;
   }
-  constexpr int kCap0 = 1024, kCap1 = 4096, kCap2 = 16384;
+  constexpr int kCap0 = 512, kCap1 = 2048, kCap2 = 16384;
   Buf<int> ub(n, s), counts(4, s), lists(4 * int64_t(n), s), cnt(n, s);
   fill_int(counts.p, 0, 4, s);
   k_spgemm_ub<<<grid_for(n, 256), 256, 0, s>>>(n, A.rp, A.ci, B.rp, drp, ub.p);
@@ -356,11 +471,11 @@ void spgemm(const CsrRef<double>& A, const CsrRef<double>& B, Csr<double>& C, hi
   auto run = [&](auto fill_tag) {
     constexpr bool F = decltype(fill_tag)::value;
     if (hc[0] > 0)
-      k_spgemm_sorted<64, kCap0, F><<<hc[0], 64, 0, s>>>(
+      k_spgemm_flat<64, kCap0, F><<<hc[0], 64, 0, s>>>(
           lists.p, ub.p, A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha, beta, cnt.p,
           C.rp.p, C.ci.p, C.v.p);
     if (hc[1] > 0)
-      k_spgemm_sorted<256, kCap1, F><<<hc[1], 256, 0, s>>>(
+      k_spgemm_flat<256, kCap1, F><<<hc[1], 256, 0, s>>>(
           lists.p + n, ub.p, A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha, beta, cnt.p,
           C.rp.p, C.ci.p, C.v.p);
     if (hc[2] > 0)
