@@ -244,6 +244,81 @@ typedef struct tpf_solve_info {
 int tpf_solve(const tpf_jacobian* J, tpf_precond* M, const double* b, double* x,
               const tpf_solve_opts* o, tpf_solve_info* info, void* stream);
 
+/* ---- serving: continuous batching of Newton-step solves ---------------- */
+/* Not part of the paper's method: a request loop over many independent
+ * Newton sequences (realizations) on one GPU.  Each request is one Newton
+ * linear solve (Sec. 3): assemble J(u) and F(u), set up (or numerically
+ * refresh) the preconditioner, and solve J x = -F by FGMRES.
+ *   - Requests of one sequence share a resident Jacobian and preconditioner
+ *     and run one at a time, in submission order; the first builds the AMG
+ *     structure, later ones refresh it numerically when opts.reuse is set.
+ *   - Up to max_active requests of different sequences are in flight, each
+ *     on its own stream; tpf_server_step advances every active request by
+ *     one phase (an Arnoldi step, a cycle end), so their kernels overlap.
+ *   - Admission: a queued request starts only while the bytes held by
+ *     resident sequences and active solves, plus its estimate, fit in
+ *     hbm_budget_bytes; idle sequences are evicted least recently used first.
+ *     A request that cannot fit alone fails with TPF_ERR_OVER_BUDGET.
+ *   - A result does not depend on what else is in flight: every kernel is
+ *     deterministic and a sequence's requests run in order.
+ * Setup and admission run on the calling thread; the server is not thread safe. */
+#define TPF_CANCELLED 4                /* result status of a cancelled request */
+
+typedef struct tpf_server_opts {
+  size_t hbm_budget_bytes;  /* admission budget (device bytes) */
+  int max_active;           /* requests in flight (1..64) */
+  int kind;                 /* preconditioner TPF_PREC_* */
+  int precision;            /* TPF_FP64 / TPF_FP32 */
+  int reuse;                /* 1: refresh a resident sequence's hierarchy numerically */
+  tpf_solve_opts solve;     /* rtol, restart, maxit */
+} tpf_server_opts;
+
+typedef struct tpf_request {
+  uint64_t sequence;           /* realization id; equal ids share resident data */
+  tpf_problem* problem;        /* static data of the realization (caller owned, same for
+                                  every request of a sequence, alive until it is evicted
+                                  or the server is destroyed) */
+  const double* u;             /* device 2N: Newton iterate u_k */
+  const double* u_old;         /* device 2N: previous time level */
+  double dt;
+  double* x;                   /* device 2N: receives the Newton update, J x = -F(u_k) */
+} tpf_request;                 /* u, u_old, x: ready at submit, untouched until polled */
+
+typedef struct tpf_result {
+  int status;             /* TPF_CONVERGED.. / TPF_CANCELLED, or a negative error code */
+  int iterations;
+  double relres_est, relres_true;
+  double setup_ms;        /* assembly + preconditioner setup/refresh */
+  double solve_ms;        /* FGMRES, first phase queued to last phase read */
+  double latency_ms;      /* submit to completion */
+  int refreshed;          /* 1 if the hierarchy was refreshed, 0 if built */
+} tpf_result;
+
+typedef struct tpf_server_counters {
+  int queued, active, resident_sequences;
+  int64_t submitted, completed;
+  size_t bytes_in_use;    /* resident sequences + active solves */
+  size_t peak_bytes;      /* maximum of bytes_in_use */
+  int64_t evictions;
+} tpf_server_counters;
+
+typedef struct tpf_server tpf_server;
+int tpf_server_default_opts(tpf_server_opts* o);
+int tpf_server_create(const tpf_server_opts* o, tpf_server** out);
+/* Queues a request; *ticket identifies it in poll/cancel. */
+int tpf_server_submit(tpf_server* sv, const tpf_request* rq, uint64_t* ticket);
+/* Admits what fits, then advances every active request by one phase
+ * (blocking until each has); *n_done = requests finished in this step. */
+int tpf_server_step(tpf_server* sv, int* n_done);
+/* 1 and the result if the request has finished (the result is then
+ * released), 0 if it is queued or active; TPF_ERR_INVALID_ARG if unknown. */
+int tpf_server_poll(tpf_server* sv, uint64_t ticket, tpf_result* out);
+/* Cancels a queued request at once, an active one at its next phase. */
+int tpf_server_cancel(tpf_server* sv, uint64_t ticket);
+int tpf_server_stats(const tpf_server* sv, tpf_server_counters* out);
+/* Waits for in-flight work, then frees every resident sequence. */
+int tpf_server_destroy(tpf_server* sv);
+
 /* ---- kernel timing ----------------------------------------------------- */
 /* When enabled, the launches of the main kernels are bracketed by HIP events
  * on their stream; tpf_kernel_stats returns the launch count and the summed

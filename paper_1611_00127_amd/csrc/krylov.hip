@@ -13,14 +13,13 @@
 #include <chrono>
 #include <cmath>
 
+#include "krylov.hpp"
 #include "linalg_dev.hpp"
-#include "precond.hpp"
 
 namespace tpf {
 
 namespace {
 constexpr int kKBlock = 256;
-constexpr int kMaxRestart = 64;
 
 int krylov_grid(int64_t n) {
   int64_t g = (n + kKBlock * 4 - 1) / (kKBlock * 4);
@@ -227,31 +226,6 @@ __global__ void k_update_x(int64_t n, int k, const double* __restrict__ Z,
   else if (nk <= 32) { constexpr int KM = 32; __VA_ARGS__ }      \
   else { constexpr int KM = 64; __VA_ARGS__ }
 
-struct Workspace {
-  Buf<double> V, Z, H, cs, sn, g, h1, h2, part, y, r;
-  Buf<GState> st;
-  int64_t n = 0;
-  int m = 0;
-};
-
-void ensure_ws(Workspace& w, int64_t n, int m, hipStream_t s) {
-  if (w.n == n && w.m == m) return;
-  w.V.alloc(size_t(m + 1) * n, s);
-  w.Z.alloc(size_t(m) * n, s);
-  w.H.alloc(size_t(m + 1) * m, s);
-  w.cs.alloc(m, s);
-  w.sn.alloc(m, s);
-  w.g.alloc(m + 1, s);
-  w.h1.alloc(kMaxRestart + 1, s);
-  w.h2.alloc(kMaxRestart + 1, s);
-  w.part.alloc(size_t(1024) * 64, s);
-  w.y.alloc(m, s);
-  w.r.alloc(n, s);
-  w.st.alloc(1, s);
-  w.n = n;
-  w.m = m;
-}
-
 unsigned vec_grid(int64_t n) {
   int64_t g = (n + 255) / 256;
   if (g > 4096) g = 4096;
@@ -261,6 +235,201 @@ unsigned vec_grid(int64_t n) {
 
 }  // namespace
 
+// ---------------------------------------------------------------- resumable solver
+void Fgmres::alloc(int64_t nn, int mm, hipStream_t st) {
+  if (n == nn && m == mm && V.p) return;
+  n = nn;
+  m = mm;
+  V.alloc(size_t(m + 1) * n, st);
+  Z.alloc(size_t(m) * n, st);
+  H.alloc(size_t(m + 1) * m, st);
+  cs.alloc(m, st);
+  sn.alloc(m, st);
+  g.alloc(m + 1, st);
+  h1.alloc(kMaxRestart + 1, st);
+  h2.alloc(kMaxRestart + 1, st);
+  part.alloc(size_t(1024) * 64, st);
+  y.alloc(m, st);
+  r.alloc(n, st);
+  st_dev.alloc(4, st);
+  scal.alloc(2, st);
+}
+
+void Fgmres::begin(const tpf_jacobian* J_, tpf_precond* M_, const double* b_, double* x_,
+                   const tpf_solve_opts& o_, hipStream_t st, void* host_slot) {
+  TPF_REQUIRE(J_ && b_ && x_, TPF_ERR_INVALID_ARG, "null argument");
+  TPF_REQUIRE(o_.restart >= 1 && o_.restart <= kMaxRestart, TPF_ERR_INVALID_ARG,
+              "restart must be in [1, %d]", kMaxRestart);
+  TPF_REQUIRE(o_.maxit >= 1 && o_.rtol > 0, TPF_ERR_INVALID_ARG, "maxit >= 1 and rtol > 0 required");
+  if (M_) {
+    TPF_REQUIRE(M_->ready, TPF_ERR_STATE, "preconditioner not set up");
+    TPF_REQUIRE(M_->o.kind == TPF_PREC_NONE || M_->J == J_, TPF_ERR_STATE,
+                "preconditioner was set up for another Jacobian");
+  }
+  J = J_;
+  M = M_;
+  b = b_;
+  x = x_;
+  o = o_;
+  s = st;
+  TPF_REQUIRE(host_slot, TPF_ERR_INVALID_ARG, "null host slot");
+  host = host_slot;
+  alloc(2 * int64_t(J->nb), o.restart, s);
+  G = krylov_grid(n);
+  total = 0;
+  est = 1.0;
+  status = -1;
+  relres = 0.0;
+  t0 = std::chrono::steady_clock::now();
+  fill(x, 0.0, n, s);
+  nrm2_device(b, n, scal.p, part.p, s);
+  TPF_HIP(hipMemcpyAsync(host, scal.p, sizeof(double), hipMemcpyDeviceToHost, s));
+  phase = kInit;
+}
+
+void Fgmres::launch_cycle_start(const double* rsrc, double beta) {
+  k_scale_by<<<vec_grid(n), 256, 0, s>>>(n, rsrc, 1.0 / beta, V.p);
+  TPF_CHECK_LAUNCH();
+  fill(g.p, 0.0, m + 1, s);
+  fill(g.p, beta, 1, s);
+  j = 0;
+  breakdown = false;
+  launch_step();
+}
+
+void Fgmres::launch_step() {
+  double* vj = V.p + int64_t(j) * n;
+  double* zj = Z.p + int64_t(j) * n;
+  double* wv = V.p + int64_t(j + 1) * n;
+  if (M && M->o.kind != TPF_PREC_NONE) {
+    TimedScope ts("precond_apply", s);
+    int rc = tpf_precond_apply(M, vj, zj, s);
+    if (rc != TPF_OK) {
+      char msg[1024];
+      tpf_last_error(msg, sizeof msg);
+      fail(rc, "%s", msg);
+    }
+  } else {
+    copy(zj, vj, n, s);
+  }
+  bcsr_apply(J, zj, nullptr, wv, s);
+  int nk = j + 1;
+  {
+    TimedScope ts("cgs2", s);
+    DISPATCH_K(nk, KM, {
+      k_cgs_dots<KM><<<G, kKBlock, 0, s>>>(n, nk, V.p, wv, part.p);
+      TPF_CHECK_LAUNCH();
+      k_reduce_parts<<<nk, 64, 0, s>>>(G, KM, part.p, h1.p);
+      TPF_CHECK_LAUNCH();
+      k_cgs_axpy_dots<KM><<<G, kKBlock, 0, s>>>(n, nk, V.p, h1.p, wv, part.p);
+      TPF_CHECK_LAUNCH();
+      k_reduce_parts<<<nk, 64, 0, s>>>(G, KM, part.p, h2.p);
+      TPF_CHECK_LAUNCH();
+      k_cgs_axpy_norm<KM><<<G, kKBlock, 0, s>>>(n, nk, V.p, h2.p, wv, part.p);
+      TPF_CHECK_LAUNCH();
+    });
+  }
+  GState* gs = reinterpret_cast<GState*>(st_dev.p);
+  k_givens<<<1, 64, 0, s>>>(j, m, h1.p, h2.p, part.p, G, H.p, cs.p, sn.p, g.p, gs);
+  TPF_CHECK_LAUNCH();
+  k_scale<<<vec_grid(n), 256, 0, s>>>(n, wv, gs, wv);
+  TPF_CHECK_LAUNCH();
+  TPF_HIP(hipMemcpyAsync(host, gs, sizeof(GState), hipMemcpyDeviceToHost, s));
+  phase = kStep;
+}
+
+void Fgmres::launch_cycle_end() {
+  if (k > 0) {
+    k_trisolve<<<1, 64, 0, s>>>(k, m, H.p, g.p, y.p);
+    TPF_CHECK_LAUNCH();
+    k_update_x<<<vec_grid(n), 256, 0, s>>>(n, k, Z.p, y.p, x);
+    TPF_CHECK_LAUNCH();
+  }
+  bcsr_apply(J, x, b, r.p, s);
+  nrm2_device(r.p, n, scal.p, part.p, s);
+  TPF_HIP(hipMemcpyAsync(host, scal.p, sizeof(double), hipMemcpyDeviceToHost, s));
+  phase = kCycleEnd;
+}
+
+void Fgmres::finish(int st_code, double rel) {
+  status = st_code;
+  relres = rel;
+  phase = kDone;
+  ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+bool Fgmres::complete() {
+  switch (phase) {
+    case kInit: {
+      beta0 = *reinterpret_cast<double*>(host);
+      if (beta0 == 0.0) {
+        finish(TPF_CONVERGED, 0.0);
+        est = 0.0;
+        return true;
+      }
+      if (!std::isfinite(beta0)) {
+        finish(TPF_NONFINITE, NAN);
+        est = NAN;
+        return true;
+      }
+      launch_cycle_start(b, beta0);
+      return false;
+    }
+    case kStep: {
+      GState gst = *reinterpret_cast<GState*>(host);
+      ++total;
+      bool end = false;
+      if (gst.d == 0.0 || !std::isfinite(gst.d)) {
+        breakdown = true;
+        k = j;
+        end = true;
+      } else {
+        k = j + 1;
+        est = gst.est / beta0;
+        end = gst.est <= o.rtol * beta0 || gst.hn == 0.0 || total >= o.maxit || j + 1 >= m;
+      }
+      if (end) {
+        launch_cycle_end();
+      } else {
+        ++j;
+        launch_step();
+      }
+      return false;
+    }
+    case kCycleEnd: {
+      double rn = *reinterpret_cast<double*>(host);
+      if (!std::isfinite(rn)) {
+        finish(TPF_NONFINITE, NAN);
+        return true;
+      }
+      if (rn <= o.rtol * beta0) {
+        finish(TPF_CONVERGED, rn / beta0);
+        return true;
+      }
+      if (breakdown) {
+        finish(TPF_BREAKDOWN, rn / beta0);
+        return true;
+      }
+      if (total >= o.maxit) {
+        finish(TPF_MAX_ITERS, rn / beta0);
+        return true;
+      }
+      launch_cycle_start(r.p, rn);
+      return false;
+    }
+    default:
+      return true;
+  }
+}
+
+void Fgmres::info(tpf_solve_info* out) const {
+  out->status = status;
+  out->iterations = total;
+  out->relres_est = est;
+  out->relres_true = relres;
+  out->ms = ms;
+}
+
 }  // namespace tpf
 
 using namespace tpf;
@@ -269,127 +438,16 @@ extern "C" int tpf_solve(const tpf_jacobian* J, tpf_precond* M, const double* b,
                          const tpf_solve_opts* o, tpf_solve_info* info, void* stream) {
   return guarded([&] {
     TPF_REQUIRE(J && b && x && o && info, TPF_ERR_INVALID_ARG, "null argument");
-    TPF_REQUIRE(o->restart >= 1 && o->restart <= kMaxRestart, TPF_ERR_INVALID_ARG,
-                "restart must be in [1, %d]", kMaxRestart);
-    TPF_REQUIRE(o->maxit >= 1 && o->rtol > 0, TPF_ERR_INVALID_ARG, "maxit >= 1 and rtol > 0 required");
-    if (M) {
-      TPF_REQUIRE(M->ready, TPF_ERR_STATE, "preconditioner not set up");
-      TPF_REQUIRE(M->o.kind == TPF_PREC_NONE || M->J == J, TPF_ERR_STATE,
-                  "preconditioner was set up for another Jacobian");
-    }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    auto t0 = std::chrono::steady_clock::now();
-    int64_t n = 2 * int64_t(J->nb);
-    int m = o->restart;
-    Workspace w;  // per call: drawn from (and returned to) the installed allocator
-    ensure_ws(w, n, m, s);
-    fill(x, 0.0, n, s);
-    std::memset(info, 0, sizeof(*info));
-    double beta0 = nrm2_host(b, n, s);
-    auto finish = [&](int status, double rel_true, double est, int its) {
-      info->status = status;
-      info->relres_true = rel_true;
-      info->relres_est = est;
-      info->iterations = its;
+    Fgmres f;  // workspace drawn from (and returned to) the installed allocator
+    f.begin(J, M, b, x, *o, s, host_scratch().get<double>(8));
+    bool done = false;
+    while (!done) {
       TPF_HIP(hipStreamSynchronize(s));
-      info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    };
-    if (beta0 == 0.0) {
-      finish(TPF_CONVERGED, 0.0, 0.0, 0);
-      return;
+      done = f.complete();
     }
-    if (!std::isfinite(beta0)) {
-      finish(TPF_NONFINITE, NAN, NAN, 0);
-      return;
-    }
-    int G = krylov_grid(n);
-    int total = 0;
-    double est = 1.0;
-    const double* rsrc = b;  // residual of x_0 = 0
-    while (true) {
-      double beta = nrm2_host(rsrc, n, s);
-      k_scale_by<<<vec_grid(n), 256, 0, s>>>(n, rsrc, 1.0 / beta, w.V.p);
-      TPF_CHECK_LAUNCH();
-      fill(w.g.p, 0.0, m + 1, s);
-      fill(w.g.p, beta, 1, s);
-      int k = 0;
-      bool breakdown = false;
-      for (int j = 0; j < m; ++j) {
-        double* vj = w.V.p + int64_t(j) * n;
-        double* zj = w.Z.p + int64_t(j) * n;
-        double* wv = w.V.p + int64_t(j + 1) * n;
-        if (M && M->o.kind != TPF_PREC_NONE) {
-          TimedScope ts("precond_apply", s);
-          int rc = tpf_precond_apply(M, vj, zj, s);
-          if (rc != TPF_OK) {
-            char msg[1024];
-            tpf_last_error(msg, sizeof msg);
-            fail(rc, "%s", msg);
-          }
-        } else {
-          copy(zj, vj, n, s);
-        }
-        bcsr_apply(J, zj, nullptr, wv, s);
-        int nk = j + 1;
-        {
-          TimedScope ts("cgs2", s);
-          DISPATCH_K(nk, KM, {
-            k_cgs_dots<KM><<<G, kKBlock, 0, s>>>(n, nk, w.V.p, wv, w.part.p);
-            TPF_CHECK_LAUNCH();
-            k_reduce_parts<<<nk, 64, 0, s>>>(G, KM, w.part.p, w.h1.p);
-            TPF_CHECK_LAUNCH();
-            k_cgs_axpy_dots<KM><<<G, kKBlock, 0, s>>>(n, nk, w.V.p, w.h1.p, wv, w.part.p);
-            TPF_CHECK_LAUNCH();
-            k_reduce_parts<<<nk, 64, 0, s>>>(G, KM, w.part.p, w.h2.p);
-            TPF_CHECK_LAUNCH();
-            k_cgs_axpy_norm<KM><<<G, kKBlock, 0, s>>>(n, nk, w.V.p, w.h2.p, wv, w.part.p);
-            TPF_CHECK_LAUNCH();
-          });
-        }
-        k_givens<<<1, 64, 0, s>>>(j, m, w.h1.p, w.h2.p, w.part.p, G, w.H.p, w.cs.p, w.sn.p, w.g.p,
-                                  w.st.p);
-        TPF_CHECK_LAUNCH();
-        k_scale<<<vec_grid(n), 256, 0, s>>>(n, wv, w.st.p, wv);
-        TPF_CHECK_LAUNCH();
-        GState* hst = host_scratch().get<GState>(1);
-        TPF_HIP(hipMemcpyAsync(hst, w.st.p, sizeof(GState), hipMemcpyDeviceToHost, s));
-        TPF_HIP(hipStreamSynchronize(s));
-        GState g = *hst;
-        ++total;
-        if (g.d == 0.0 || !std::isfinite(g.d)) {
-          breakdown = true;
-          k = j;
-          break;
-        }
-        k = j + 1;
-        est = g.est / beta0;
-        if (g.est <= o->rtol * beta0 || g.hn == 0.0 || total >= o->maxit) break;
-      }
-      if (k > 0) {
-        k_trisolve<<<1, 64, 0, s>>>(k, m, w.H.p, w.g.p, w.y.p);
-        TPF_CHECK_LAUNCH();
-        k_update_x<<<vec_grid(n), 256, 0, s>>>(n, k, w.Z.p, w.y.p, x);
-        TPF_CHECK_LAUNCH();
-      }
-      bcsr_apply(J, x, b, w.r.p, s);
-      double rn = nrm2_host(w.r.p, n, s);
-      rsrc = w.r.p;
-      if (!std::isfinite(rn)) {
-        finish(TPF_NONFINITE, NAN, est, total);
-        return;
-      }
-      if (rn <= o->rtol * beta0) {
-        finish(TPF_CONVERGED, rn / beta0, est, total);
-        return;
-      }
-      if (breakdown) {
-        finish(TPF_BREAKDOWN, rn / beta0, est, total);
-        return;
-      }
-      if (total >= o->maxit) {
-        finish(TPF_MAX_ITERS, rn / beta0, est, total);
-        return;
-      }
-    }
+    TPF_HIP(hipStreamSynchronize(s));
+    f.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - f.t0).count();
+    f.info(info);
   });
 }

@@ -190,6 +190,13 @@ void dot_device(const double* x, const double* y, int64_t n, double* out, hipStr
   TPF_CHECK_LAUNCH();
 }
 
+void nrm2_device(const double* x, int64_t n, double* out, double* part, hipStream_t s) {
+  k_dot_partial<<<kRedBlocks, kRedThreads, 0, s>>>(x, x, n, part);
+  TPF_CHECK_LAUNCH();
+  k_sum_final<<<1, kRedThreads, 0, s>>>(part, kRedBlocks, out, 1);
+  TPF_CHECK_LAUNCH();
+}
+
 double nrm2_host(const double* x, int64_t n, hipStream_t s) {
   Buf<double> part(kRedBlocks + 1, s);
   k_dot_partial<<<kRedBlocks, kRedThreads, 0, s>>>(x, x, n, part.p);

@@ -1,0 +1,479 @@
+// Serving engine: continuous batching of independent Newton-step solves on
+// one GPU.  Each request is one linear solve of Sec. 3 (assemble J(u_k) and
+// F(u_k), set up or refresh the preconditioner, right-preconditioned FGMRES
+// on J x = -F).  Requests of different sequences run concurrently, each on a
+// stream of its own slot, and advance one solver phase per server step, so
+// the kernels of many solves overlap on the device.
+//
+// Streams and memory:
+//   - assembly and preconditioner setup of every request run on one setup
+//     stream, so everything a resident sequence owns is allocated and freed
+//     on that stream; the slot stream waits for the setup through an event;
+//   - the FGMRES workspace of a request is allocated and released on its
+//     slot stream, after the host has seen the request's last phase finish;
+//   - resident data of a sequence is only touched by one request at a time.
+#include <algorithm>
+#include <chrono>
+#include <deque>
+#include <memory>
+#include <unordered_map>
+#include <vector>
+
+#include "krylov.hpp"
+#include "precond.hpp"
+#include "problem.hpp"
+
+namespace tpf {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double ms_since(Clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+}
+
+void check_rc(int rc) {
+  if (rc == TPF_OK) return;
+  char msg[1024];
+  tpf_last_error(msg, sizeof msg);
+  fail(rc, "%s", msg);
+}
+
+__global__ void k_negate(int64_t n, const double* __restrict__ x, double* __restrict__ y) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    y[i] = -x[i];
+}
+
+// bytes of an FGMRES(m) workspace for 2N unknowns (basis V, Z, residual,
+// partial sums); matches the buffers Fgmres allocates
+size_t krylov_bytes(int64_t cells, int m) {
+  int64_t n = 2 * cells;
+  return size_t(8) * (size_t(2 * m + 2) * n + size_t(1024) * 64 + size_t(m + 1) * (m + 4) +
+                      2 * (kMaxRestart + 1) + 8);
+}
+
+}  // namespace
+
+struct Resident {
+  uint64_t seq = 0;
+  tpf_problem* prob = nullptr;
+  int64_t cells = 0;
+  tpf_jacobian* J = nullptr;
+  tpf_precond* M = nullptr;
+  Buf<double> rhs;
+  bool built = false;  // preconditioner structure exists
+  bool busy = false;
+  size_t bytes = 0;
+  uint64_t last_use = 0;
+  ~Resident() {
+    if (M) tpf_precond_destroy(M);
+    if (J) tpf_jacobian_destroy(J);
+  }
+};
+
+struct Pending {
+  uint64_t ticket = 0;
+  tpf_request rq{};
+  Clock::time_point submit;
+};
+
+struct Slot {
+  hipStream_t s = nullptr;
+  hipEvent_t ev = nullptr;
+  void* host = nullptr;  // pinned readback slot
+  std::unique_ptr<Fgmres> f;
+  Pending req;
+  Resident* res = nullptr;
+  bool busy = false;
+  bool cancel = false;
+  double setup_ms = 0.0;
+  int refreshed = 0;
+  size_t ws_bytes = 0;
+};
+
+}  // namespace tpf
+
+using namespace tpf;
+
+struct tpf_server {
+  tpf_server_opts o{};
+  hipStream_t setup_s = nullptr;
+  hipEvent_t setup_ev = nullptr;
+  void* host_block = nullptr;
+  std::vector<Slot> slots;
+  std::deque<Pending> queue;
+  std::unordered_map<uint64_t, std::unique_ptr<Resident>> res;
+  std::unordered_map<uint64_t, tpf_result> results;
+  uint64_t next_ticket = 1;
+  uint64_t tick = 0;
+  int64_t submitted = 0, completed = 0, evictions = 0;
+  size_t peak = 0;
+  std::vector<std::pair<int64_t, size_t>> seen;  // (cells, resident bytes) of built sequences
+
+  size_t resident_bytes() const {
+    size_t b = 0;
+    for (auto& kv : res) b += kv.second->bytes;
+    return b;
+  }
+  size_t active_bytes() const {
+    size_t b = 0;
+    for (auto& sl : slots)
+      if (sl.busy) b += sl.ws_bytes;
+    return b;
+  }
+  size_t in_use() const { return resident_bytes() + active_bytes(); }
+  void note_peak() { peak = std::max(peak, in_use()); }
+
+  // Resident bytes a new sequence of `cells` cells is expected to need: the
+  // footprint of a built sequence at least as large, else one scaled up
+  // linearly from the largest smaller one (fixed costs scale too, so this
+  // errs high); 3 KiB per cell before any sequence has been built.
+  size_t resident_estimate(int64_t cells) const {
+    double best = -1.0;
+    for (auto& ob : seen) {
+      double e = cells <= ob.first ? double(ob.second)
+                                   : double(ob.second) * double(cells) / double(ob.first);
+      if (best < 0 || e < best) best = e;
+    }
+    return best < 0 ? size_t(3072) * size_t(cells) : size_t(best);
+  }
+
+  bool evict_one(uint64_t keep) {
+    Resident* victim = nullptr;
+    for (auto& kv : res) {
+      Resident* r = kv.second.get();
+      if (r->busy || r->seq == keep) continue;
+      if (!victim || r->last_use < victim->last_use) victim = r;
+    }
+    if (!victim) return false;
+    res.erase(victim->seq);
+    ++evictions;
+    return true;
+  }
+
+  void finish_request(const Pending& p, int status, int iters, double est, double rel,
+                      double setup_ms, double solve_ms, int refreshed) {
+    tpf_result r{};
+    r.status = status;
+    r.iterations = iters;
+    r.relres_est = est;
+    r.relres_true = rel;
+    r.setup_ms = setup_ms;
+    r.solve_ms = solve_ms;
+    r.latency_ms = ms_since(p.submit);
+    r.refreshed = refreshed;
+    results[p.ticket] = r;
+    ++completed;
+  }
+
+  bool sequence_busy(uint64_t seq) const {
+    auto it = res.find(seq);
+    return it != res.end() && it->second->busy;
+  }
+
+  Slot* free_slot() {
+    for (auto& sl : slots)
+      if (!sl.busy) return &sl;
+    return nullptr;
+  }
+
+  // Starts request p on slot sl: assembly and setup on the setup stream,
+  // then the first FGMRES phase on the slot stream.
+  void start(Slot& sl, const Pending& p, int64_t cells) {
+    auto t0 = Clock::now();
+    Resident* r = nullptr;
+    auto it = res.find(p.rq.sequence);
+    bool fresh = it == res.end();
+    size_t before = 0;
+    tpf_memory_in_use(&before);
+    if (fresh) {
+      auto nr = std::make_unique<Resident>();
+      nr->seq = p.rq.sequence;
+      nr->prob = p.rq.problem;
+      nr->cells = cells;
+      r = nr.get();
+      res[p.rq.sequence] = std::move(nr);
+    } else {
+      r = it->second.get();
+    }
+    sl.busy = true;
+    sl.cancel = false;
+    sl.req = p;
+    sl.res = r;
+    r->busy = true;
+    r->last_use = ++tick;
+    try {
+      if (!r->J) check_rc(tpf_jacobian_create(r->prob, setup_s, &r->J));
+      if (!r->M) {
+        tpf_precond_opts po;
+        check_rc(tpf_precond_default_opts(o.kind, &po));
+        po.precision = o.precision;
+        check_rc(tpf_precond_create(&po, &r->M));
+      }
+      r->rhs.ensure(size_t(2 * cells), setup_s);
+      check_rc(tpf_assemble(r->prob, p.rq.u, p.rq.u_old, p.rq.dt, r->rhs.p, r->J, setup_s));
+      k_negate<<<std::min(grid_for(2 * cells, 256), 4096u), 256, 0, setup_s>>>(2 * cells, r->rhs.p,
+                                                                          r->rhs.p);
+      TPF_CHECK_LAUNCH();
+      bool reuse = o.reuse && r->built;
+      check_rc(tpf_precond_setup(r->M, r->J, reuse ? 1 : 0, setup_s));  // synchronises
+      r->built = true;
+      sl.refreshed = reuse ? 1 : 0;
+      size_t after = 0;
+      tpf_memory_in_use(&after);
+      int64_t grown = int64_t(after) - int64_t(before);
+      r->bytes = size_t(std::max<int64_t>(0, int64_t(r->bytes) + grown));
+      if (fresh) seen.emplace_back(cells, r->bytes);
+      sl.setup_ms = ms_since(t0);
+      TPF_HIP(hipEventRecord(setup_ev, setup_s));
+      TPF_HIP(hipStreamWaitEvent(sl.s, setup_ev, 0));
+      sl.f = std::make_unique<Fgmres>();
+      sl.ws_bytes = krylov_bytes(cells, o.solve.restart);
+      sl.f->begin(r->J, r->M, r->rhs.p, p.rq.x, o.solve, sl.s, sl.host);
+      TPF_HIP(hipEventRecord(sl.ev, sl.s));
+      // the estimate may have been low: give back idle sequences first
+      while (in_use() > o.hbm_budget_bytes && evict_one(r->seq)) {
+      }
+      note_peak();
+    } catch (const Error& e) {
+      set_last_error(e.code, e.what());
+      TPF_HIP(hipStreamSynchronize(setup_s));
+      TPF_HIP(hipStreamSynchronize(sl.s));
+      release(sl);
+      res.erase(p.rq.sequence);  // rebuilt from scratch by the next request
+      finish_request(p, e.code, 0, NAN, NAN, ms_since(t0), 0.0, 0);
+    }
+  }
+
+  void release(Slot& sl) {
+    sl.f.reset();  // workspace returned on the slot stream (its work is done)
+    if (sl.res) sl.res->busy = false;
+    sl.res = nullptr;
+    sl.busy = false;
+    sl.ws_bytes = 0;
+  }
+
+  void admit() {
+    for (auto it = queue.begin(); it != queue.end();) {
+      Slot* sl = free_slot();
+      if (!sl) return;
+      const Pending& p = *it;
+      if (sequence_busy(p.rq.sequence)) {
+        ++it;  // waits for the sequence's running request; later sequences may pass
+        continue;
+      }
+      int64_t cells = 0;
+      auto rit = res.find(p.rq.sequence);
+      if (rit != res.end()) {
+        cells = rit->second->cells;
+        if (rit->second->prob != p.rq.problem) {
+          Pending bad = p;
+          it = queue.erase(it);
+          set_last_error(TPF_ERR_INVALID_ARG, "request names another problem than its sequence");
+          finish_request(bad, TPF_ERR_INVALID_ARG, 0, NAN, NAN, 0.0, 0.0, 0);
+          continue;
+        }
+      } else {
+        check_rc(tpf_problem_cells(p.rq.problem, &cells));
+      }
+      size_t need = krylov_bytes(cells, o.solve.restart) +
+                    (rit == res.end() ? resident_estimate(cells) : 0);
+      if (need > o.hbm_budget_bytes) {
+        Pending bad = p;
+        it = queue.erase(it);
+        finish_request(bad, TPF_ERR_OVER_BUDGET, 0, NAN, NAN, 0.0, 0.0, 0);
+        continue;
+      }
+      while (in_use() + need > o.hbm_budget_bytes && evict_one(p.rq.sequence)) {
+      }
+      if (in_use() + need > o.hbm_budget_bytes) {
+        bool any_active = false;
+        for (auto& x : slots) any_active |= x.busy;
+        if (any_active) return;  // waits for active solves to retire
+        Pending bad = p;         // cannot fit even with the device to itself
+        it = queue.erase(it);
+        set_last_error(TPF_ERR_OVER_BUDGET, "request does not fit in the HBM budget");
+        finish_request(bad, TPF_ERR_OVER_BUDGET, 0, NAN, NAN, 0.0, 0.0, 0);
+        continue;
+      }
+      Pending go = p;
+      it = queue.erase(it);
+      start(*sl, go, cells);
+    }
+  }
+
+  int step() {
+    admit();
+    int done = 0;
+    for (auto& sl : slots) {
+      if (!sl.busy) continue;
+      TPF_HIP(hipEventSynchronize(sl.ev));
+      Fgmres& f = *sl.f;
+      bool fin = false;
+      try {
+        if (sl.cancel) {
+          f.finish(TPF_CANCELLED, NAN);
+          fin = true;
+        } else {
+          fin = f.complete();
+        }
+      } catch (const Error& e) {
+        set_last_error(e.code, e.what());
+        TPF_HIP(hipStreamSynchronize(sl.s));
+        f.finish(e.code, NAN);
+        fin = true;
+      }
+      if (!fin) {
+        TPF_HIP(hipEventRecord(sl.ev, sl.s));
+        continue;
+      }
+      TPF_HIP(hipStreamSynchronize(sl.s));
+      finish_request(sl.req, f.status, f.total, f.est, f.relres, sl.setup_ms, ms_since(f.t0),
+                     sl.refreshed);
+      release(sl);
+      ++done;
+    }
+    return done;
+  }
+};
+
+extern "C" int tpf_server_default_opts(tpf_server_opts* o) {
+  return guarded([&] {
+    TPF_REQUIRE(o, TPF_ERR_INVALID_ARG, "null argument");
+    *o = tpf_server_opts{};
+    o->hbm_budget_bytes = size_t(64) << 30;
+    o->max_active = 8;
+    o->kind = TPF_PREC_BF;
+    o->precision = TPF_FP32;
+    o->reuse = 1;
+    o->solve.rtol = 1e-8;
+    o->solve.restart = 30;
+    o->solve.maxit = 1000;
+  });
+}
+
+extern "C" int tpf_server_create(const tpf_server_opts* o, tpf_server** out) {
+  return guarded([&] {
+    TPF_REQUIRE(o && out, TPF_ERR_INVALID_ARG, "null argument");
+    TPF_REQUIRE(o->max_active >= 1 && o->max_active <= 64, TPF_ERR_INVALID_ARG,
+                "max_active must be in [1, 64]");
+    TPF_REQUIRE(o->kind >= TPF_PREC_AMG && o->kind <= TPF_PREC_NONE, TPF_ERR_INVALID_ARG,
+                "unknown preconditioner kind %d", o->kind);
+    TPF_REQUIRE(o->solve.restart >= 1 && o->solve.restart <= kMaxRestart && o->solve.maxit >= 1 &&
+                    o->solve.rtol > 0,
+                TPF_ERR_INVALID_ARG, "invalid solve options");
+    auto sv = std::make_unique<tpf_server>();
+    sv->o = *o;
+    TPF_HIP(hipStreamCreateWithFlags(&sv->setup_s, hipStreamNonBlocking));
+    TPF_HIP(hipEventCreateWithFlags(&sv->setup_ev, hipEventDisableTiming));
+    TPF_HIP(hipHostMalloc(&sv->host_block, size_t(64) * o->max_active, hipHostMallocDefault));
+    sv->slots.resize(o->max_active);
+    for (int i = 0; i < o->max_active; ++i) {
+      Slot& sl = sv->slots[i];
+      TPF_HIP(hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking));
+      TPF_HIP(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+      sl.host = static_cast<char*>(sv->host_block) + 64 * i;
+    }
+    *out = sv.release();
+  });
+}
+
+extern "C" int tpf_server_submit(tpf_server* sv, const tpf_request* rq, uint64_t* ticket) {
+  return guarded([&] {
+    TPF_REQUIRE(sv && rq && ticket, TPF_ERR_INVALID_ARG, "null argument");
+    TPF_REQUIRE(rq->problem && rq->u && rq->u_old && rq->x, TPF_ERR_INVALID_ARG,
+                "request needs problem, u, u_old and x");
+    TPF_REQUIRE(rq->dt > 0, TPF_ERR_INVALID_ARG, "dt must be positive");
+    Pending p;
+    p.ticket = sv->next_ticket++;
+    p.rq = *rq;
+    p.submit = Clock::now();
+    sv->queue.push_back(p);
+    ++sv->submitted;
+    *ticket = p.ticket;
+  });
+}
+
+extern "C" int tpf_server_step(tpf_server* sv, int* n_done) {
+  return guarded([&] {
+    TPF_REQUIRE(sv && n_done, TPF_ERR_INVALID_ARG, "null argument");
+    *n_done = sv->step();
+  });
+}
+
+extern "C" int tpf_server_poll(tpf_server* sv, uint64_t ticket, tpf_result* out) {
+  if (!sv || !out) {
+    set_last_error(TPF_ERR_INVALID_ARG, "null argument");
+    return TPF_ERR_INVALID_ARG;
+  }
+  auto it = sv->results.find(ticket);
+  if (it != sv->results.end()) {
+    *out = it->second;
+    sv->results.erase(it);
+    return 1;
+  }
+  for (auto& p : sv->queue)
+    if (p.ticket == ticket) return 0;
+  for (auto& sl : sv->slots)
+    if (sl.busy && sl.req.ticket == ticket) return 0;
+  set_last_error(TPF_ERR_INVALID_ARG, "unknown ticket");
+  return TPF_ERR_INVALID_ARG;
+}
+
+extern "C" int tpf_server_cancel(tpf_server* sv, uint64_t ticket) {
+  return guarded([&] {
+    TPF_REQUIRE(sv, TPF_ERR_INVALID_ARG, "null argument");
+    for (auto it = sv->queue.begin(); it != sv->queue.end(); ++it) {
+      if (it->ticket == ticket) {
+        Pending p = *it;
+        sv->queue.erase(it);
+        sv->finish_request(p, TPF_CANCELLED, 0, NAN, NAN, 0.0, 0.0, 0);
+        return;
+      }
+    }
+    for (auto& sl : sv->slots) {
+      if (sl.busy && sl.req.ticket == ticket) {
+        sl.cancel = true;
+        return;
+      }
+    }
+    TPF_REQUIRE(sv->results.count(ticket), TPF_ERR_INVALID_ARG, "unknown ticket");
+  });
+}
+
+extern "C" int tpf_server_stats(const tpf_server* sv, tpf_server_counters* out) {
+  return guarded([&] {
+    TPF_REQUIRE(sv && out, TPF_ERR_INVALID_ARG, "null argument");
+    *out = tpf_server_counters{};
+    out->queued = int(sv->queue.size());
+    for (auto& sl : sv->slots) out->active += sl.busy ? 1 : 0;
+    out->resident_sequences = int(sv->res.size());
+    out->submitted = sv->submitted;
+    out->completed = sv->completed;
+    out->bytes_in_use = sv->in_use();
+    out->peak_bytes = sv->peak;
+    out->evictions = sv->evictions;
+  });
+}
+
+extern "C" int tpf_server_destroy(tpf_server* sv) {
+  return guarded([&] {
+    if (!sv) return;
+    std::unique_ptr<tpf_server> own(sv);
+    for (auto& sl : sv->slots) {
+      if (sl.s) (void)hipStreamSynchronize(sl.s);
+      sl.f.reset();
+    }
+    if (sv->setup_s) (void)hipStreamSynchronize(sv->setup_s);
+    sv->res.clear();
+    if (sv->setup_s) (void)hipStreamSynchronize(sv->setup_s);
+    for (auto& sl : sv->slots) {
+      if (sl.ev) (void)hipEventDestroy(sl.ev);
+      if (sl.s) (void)hipStreamDestroy(sl.s);
+    }
+    if (sv->setup_ev) (void)hipEventDestroy(sv->setup_ev);
+    if (sv->setup_s) (void)hipStreamDestroy(sv->setup_s);
+    if (sv->host_block) (void)hipHostFree(sv->host_block);
+  });
+}

@@ -175,6 +175,9 @@ template <class A, class B> void cast(B* dst, const A* src, int64_t n, hipStream
 // deterministic reductions: result written to device memory *out
 void dot_device(const double* x, const double* y, int64_t n, double* out, hipStream_t s);
 double nrm2_host(const double* x, int64_t n, hipStream_t s);
+// *out = ||x||_2 on the device; part: workspace of kNrm2Parts doubles
+constexpr int kNrm2Parts = 512;
+void nrm2_device(const double* x, int64_t n, double* out, double* part, hipStream_t s);
 
 template <class T>
 void csr_spmv(const CsrRef<T>& A, const T* x, T* y, hipStream_t s, const char* tname = "csr_spmv");

@@ -136,3 +136,90 @@ def newton_sequence(gcase, M, n_jacobians, reuse=False, ds_max=0.2, rtol=1e-8, r
             on_step(rec)
     torch.cuda.synchronize()
     return out
+
+
+class Server:
+    """Python side of the serving engine (tpf_server_*): keeps the tensors of
+    every request alive until its result has been polled."""
+
+    def __init__(self, kind="bf", precision=tpf.TPF_FP32, max_active=8, hbm_budget_bytes=64 << 30,
+                 reuse=True, rtol=1e-8, restart=30, maxit=1000):
+        tpf.init()
+        o = tpf.tpf_server_default_opts()
+        o.kind = tpf.KINDS[kind] if isinstance(kind, str) else kind
+        o.precision = precision
+        o.max_active = max_active
+        o.hbm_budget_bytes = int(hbm_budget_bytes)
+        o.reuse = int(bool(reuse))
+        o.solve.rtol, o.solve.restart, o.solve.maxit = rtol, restart, maxit
+        self.opts = o
+        self.sv = tpf.tpf_server_create(o)
+        self._held = {}
+
+    def submit(self, sequence, gcase, u, u_old, x, dt=None):
+        """Queues the Newton solve of realization `sequence` (problem of gcase)
+        at state u; x receives the update.  Tensors must be ready (the caller
+        has synchronised the stream that wrote them)."""
+        t = tpf.tpf_server_submit(self.sv, sequence, gcase.prob, u, u_old,
+                                  gcase.case.dt if dt is None else dt, x)
+        self._held[t] = (gcase, u, u_old, x)
+        return t
+
+    def step(self):
+        return tpf.tpf_server_step(self.sv)
+
+    def poll(self, ticket):
+        r = tpf.tpf_server_poll(self.sv, ticket)
+        if r is not None:
+            self._held.pop(ticket, None)
+        return r
+
+    def cancel(self, ticket):
+        tpf.tpf_server_cancel(self.sv, ticket)
+
+    def stats(self):
+        return tpf.tpf_server_stats(self.sv)
+
+    def drain(self, tickets):
+        """Steps until every ticket has a result; returns {ticket: Result}."""
+        out = {}
+        pending = set(tickets)
+        while pending:
+            self.step()
+            for t in list(pending):
+                r = self.poll(t)
+                if r is not None:
+                    out[t] = r
+                    pending.discard(t)
+        return out
+
+    def close(self):
+        if tpf.shutting_down():
+            return
+        if self.sv is not None:
+            tpf.tpf_server_destroy(self.sv)
+            self.sv = None
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def newton_states(gcase, n_states, kind="bf", ds_max=0.2, rtol=1e-8):
+    """The first n_states Newton iterates u_0..u_{n-1} of gcase's time step
+    (FP64 solves, full setups), as a list of device tensors; gcase.u is left
+    at its initial value."""
+    M = GpuPrecond(kind)
+    u0 = gcase.u.clone()
+    states = [u0.clone()]
+    if n_states > 1:
+        newton_sequence(gcase, M, n_states - 1, ds_max=ds_max, rtol=rtol,
+                        on_step=lambda rec: states.append(gcase.u.clone()))
+    gcase.u.copy_(u0)
+    M.close()
+    import torch
+    torch.cuda.synchronize()
+    return states

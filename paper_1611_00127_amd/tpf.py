@@ -21,7 +21,8 @@ TPF_OK = 0
 TPF_PC_BROOKS_COREY, TPF_PC_LINEAR = 0, 1
 TPF_PREC_AMG, TPF_PREC_CPR1, TPF_PREC_CPR2, TPF_PREC_BF, TPF_PREC_NONE = 0, 1, 2, 3, 4
 TPF_FP64, TPF_FP32 = 0, 1
-TPF_CONVERGED, TPF_MAX_ITERS, TPF_BREAKDOWN, TPF_NONFINITE = 0, 1, 2, 3
+TPF_CONVERGED, TPF_MAX_ITERS, TPF_BREAKDOWN, TPF_NONFINITE, TPF_CANCELLED = 0, 1, 2, 3, 4
+TPF_ERR_OVER_BUDGET = -5
 TPF_MAT_A, TPF_MAT_P, TPF_MAT_R, TPF_MAT_S, TPF_MAT_APS, TPF_MAT_SCHUR = 0, 1, 2, 3, 10, 11
 TPF_MAX_LEVELS = 25
 TPF_INTERP_AUTO, TPF_INTERP_DIRECT, TPF_INTERP_EXTI = 0, 1, 2
@@ -79,6 +80,28 @@ class SolveInfo(ctypes.Structure):
                 ("relres_true", c_double), ("ms", c_double)]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", c_size_t), ("max_active", c_int), ("kind", c_int),
+                ("precision", c_int), ("reuse", c_int), ("solve", SolveOpts)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("sequence", c_uint64), ("problem", c_void_p), ("u", c_void_p),
+                ("u_old", c_void_p), ("dt", c_double), ("x", c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", c_int), ("iterations", c_int), ("relres_est", c_double),
+                ("relres_true", c_double), ("setup_ms", c_double), ("solve_ms", c_double),
+                ("latency_ms", c_double), ("refreshed", c_int)]
+
+
+class ServerCounters(ctypes.Structure):
+    _fields_ = [("queued", c_int), ("active", c_int), ("resident_sequences", c_int),
+                ("submitted", c_int64), ("completed", c_int64), ("bytes_in_use", c_size_t),
+                ("peak_bytes", c_size_t), ("evictions", c_int64)]
+
+
 class TpfError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"tpf error {code}: {msg}")
@@ -133,6 +156,14 @@ _SIGS = {
     "tpf_precond_vcycle": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
     "tpf_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(SolveOpts),
                           ctypes.POINTER(SolveInfo), c_void_p]),
+    "tpf_server_default_opts": (c_int, [ctypes.POINTER(ServerOpts)]),
+    "tpf_server_create": (c_int, [ctypes.POINTER(ServerOpts), ctypes.POINTER(c_void_p)]),
+    "tpf_server_submit": (c_int, [c_void_p, ctypes.POINTER(Request), ctypes.POINTER(c_uint64)]),
+    "tpf_server_step": (c_int, [c_void_p, ctypes.POINTER(c_int)]),
+    "tpf_server_poll": (c_int, [c_void_p, c_uint64, ctypes.POINTER(Result)]),
+    "tpf_server_cancel": (c_int, [c_void_p, c_uint64]),
+    "tpf_server_stats": (c_int, [c_void_p, ctypes.POINTER(ServerCounters)]),
+    "tpf_server_destroy": (c_int, [c_void_p]),
     "tpf_kernel_timing": (c_int, [c_int]),
     "tpf_kernel_stats": (c_int, [ctypes.c_char_p, ctypes.POINTER(c_int64), ctypes.POINTER(c_double)]),
     "tpf_kernel_stats_reset": (c_int, []),
@@ -349,6 +380,54 @@ def tpf_solve(J, M, b, x, rtol=1e-8, restart=30, maxit=1000, stream=None):
     _check(load().tpf_solve(J, M, _ptr(b), _ptr(x), ctypes.byref(o), ctypes.byref(info),
                             _stream(stream)))
     return info
+
+
+def tpf_server_default_opts():
+    o = ServerOpts()
+    _check(load().tpf_server_default_opts(ctypes.byref(o)))
+    return o
+
+
+def tpf_server_create(opts):
+    h = c_void_p()
+    _check(load().tpf_server_create(ctypes.byref(opts), ctypes.byref(h)))
+    return h.value
+
+
+def tpf_server_submit(sv, sequence, problem, u, u_old, dt, x):
+    rq = Request(sequence, problem, _ptr(u), _ptr(u_old), dt, _ptr(x))
+    t = c_uint64()
+    _check(load().tpf_server_submit(sv, ctypes.byref(rq), ctypes.byref(t)))
+    return t.value
+
+
+def tpf_server_step(sv):
+    n = c_int()
+    _check(load().tpf_server_step(sv, ctypes.byref(n)))
+    return n.value
+
+
+def tpf_server_poll(sv, ticket):
+    """The Result of a finished request (released by this call), else None."""
+    r = Result()
+    rc = load().tpf_server_poll(sv, ticket, ctypes.byref(r))
+    if rc < 0:
+        _check(rc)
+    return r if rc == 1 else None
+
+
+def tpf_server_cancel(sv, ticket):
+    _check(load().tpf_server_cancel(sv, ticket))
+
+
+def tpf_server_stats(sv):
+    c = ServerCounters()
+    _check(load().tpf_server_stats(sv, ctypes.byref(c)))
+    return c
+
+
+def tpf_server_destroy(sv):
+    _check(load().tpf_server_destroy(sv))
 
 
 def tpf_kernel_timing(enable):

@@ -47,3 +47,21 @@ def test_host_side_errors_without_gpu():
         tpf.tpf_precond_create(bad)
     assert e.value.code == -1
     assert tpf.tpf_status_string(-4) == "singular pivot"
+
+
+def test_server_host_side_checks():
+    lib = tpf.load()
+    o = tpf.tpf_server_default_opts()
+    assert o.kind == tpf.TPF_PREC_BF and o.precision == tpf.TPF_FP32 and o.reuse == 1
+    assert o.max_active == 8 and o.hbm_budget_bytes == 64 << 30
+    assert o.solve.rtol == 1e-8 and o.solve.restart == 30
+    bad = tpf.tpf_server_default_opts()
+    bad.max_active = 0
+    h = ctypes.c_void_p()
+    assert lib.tpf_server_create(ctypes.byref(bad), ctypes.byref(h)) == -1
+    bad = tpf.tpf_server_default_opts()
+    bad.solve.restart = 65
+    assert lib.tpf_server_create(ctypes.byref(bad), ctypes.byref(h)) == -1
+    t = ctypes.c_uint64()
+    assert lib.tpf_server_submit(None, None, ctypes.byref(t)) == -1
+    assert lib.tpf_server_poll(None, 1, None) == -1

@@ -1,0 +1,176 @@
+"""GPU tests of the serving engine (tpf_server_*), through the C ABI.
+
+* A request's result is the same alone and in a mix with other sequences
+  (bit-identical update and iteration count).
+* The first request of a sequence equals the plain assemble/setup/solve path
+  with the same options (bit-identical).
+* A served update solves the oracle's Newton system J(u) x = -F(u) to the
+  requested 1e-8 relative residual.
+* Admission keeps the bytes in use within the HBM budget, evicting idle
+  sequences; a request that cannot fit fails with TPF_ERR_OVER_BUDGET.
+* Cancellation of queued and active requests.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import tpfa
+from paper_1611_00127_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+EDGES = (10, 12, 8)
+N_STATES = 3
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_1611_00127_amd import driver, tpf
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    tpf.init()
+    seqs = []
+    for r, e in enumerate(EDGES):
+        case = inputs.serving_case(r, edge_override=e)
+        g = driver.GpuCase(case)
+        states = driver.newton_states(g, N_STATES)
+        seqs.append((case, g, states))
+    torch.cuda.synchronize()
+    yield driver, tpf, torch, seqs
+    for _, g, _ in seqs:
+        g.close()
+
+
+def _serve(driver, torch, seqs, order, **kw):
+    """Submits (sequence, state) pairs in `order`, drains, returns
+    {(r, k): (x, Result)}."""
+    sv = driver.Server(**kw)
+    xs, tickets = {}, {}
+    for r, k in order:
+        case, g, states = seqs[r]
+        x = torch.full((2 * case.N,), float("nan"), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        tickets[sv.submit(r, g, states[k], g.u_old, x)] = (r, k)
+        xs[(r, k)] = x
+    res = sv.drain(list(tickets))
+    st = sv.stats()
+    sv.close()
+    torch.cuda.synchronize()
+    return {tickets[t]: (xs[tickets[t]].cpu().numpy(), res[t]) for t in res}, st
+
+
+def test_alone_equals_mix(env):
+    driver, tpf, torch, seqs = env
+    alone = {}
+    for r in range(len(seqs)):
+        say(f"alone: sequence {r} edge {EDGES[r]}")
+        out, _ = _serve(driver, torch, seqs, [(r, k) for k in range(N_STATES)], max_active=1)
+        alone.update(out)
+    order = [(r, k) for k in range(N_STATES) for r in range(len(seqs))]
+    say("mix: all sequences interleaved, max_active 3")
+    mix, st = _serve(driver, torch, seqs, order, max_active=3)
+    assert st.completed == len(order) and st.peak_bytes > 0
+    for key, (x, res) in alone.items():
+        xm, rm = mix[key]
+        say(key, res.status, res.iterations, rm.iterations, res.refreshed, rm.refreshed)
+        assert res.status == tpf.TPF_CONVERGED and rm.status == tpf.TPF_CONVERGED
+        assert res.refreshed == (key[1] > 0) and rm.refreshed == res.refreshed
+        assert rm.iterations == res.iterations
+        assert np.array_equal(x, xm), key
+
+
+def test_first_request_equals_plain_solve(env):
+    driver, tpf, torch, seqs = env
+    for prec in (tpf.TPF_FP64, tpf.TPF_FP32):
+        out, _ = _serve(driver, torch, seqs, [(r, 1) for r in range(len(seqs))], max_active=2,
+                        precision=prec)
+        for r, (case, g, states) in enumerate(seqs):
+            say(f"plain path: sequence {r} precision {prec}")
+            g.u.copy_(states[1])
+            g.assemble()
+            b = -g.R
+            M = driver.GpuPrecond("bf", precision=prec)
+            M.setup(g)
+            x = torch.empty_like(b)
+            info = driver.solve(g, M, b, x)
+            M.close()
+            g.u.copy_(states[0])
+            xs, res = out[(r, 1)]
+            assert res.refreshed == 0
+            assert info.iterations == res.iterations
+            assert np.array_equal(x.cpu().numpy(), xs)
+
+
+def test_served_update_solves_oracle_system(env):
+    driver, tpf, torch, seqs = env
+    out, _ = _serve(driver, torch, seqs, [(0, k) for k in range(N_STATES)])
+    case, g, states = seqs[0]
+    for k in range(N_STATES):
+        u = states[k].cpu().numpy().reshape(-1, 2)
+        ck = case.replace(u=u)
+        rp, ci, v = tpfa.jacobian(ck, ck.u, ck.u_old)
+        F = tpfa.residual(ck, ck.u, ck.u_old).reshape(-1)
+        J = tpfa.bcsr_matrix(rp, ci, v).tocsr()
+        x, res = out[(0, k)]
+        rel = np.linalg.norm(J @ x + F) / np.linalg.norm(F)
+        say(f"state {k}: oracle relres {rel:.3e}, served {res.relres_true:.3e}, its {res.iterations}")
+        assert res.status == tpf.TPF_CONVERGED
+        assert rel <= 1e-8 * (1 + 1e-6)
+        assert abs(rel - res.relres_true) <= 1e-3 * rel + 1e-14
+
+
+def test_budget_admission_and_eviction(env):
+    driver, tpf, torch, seqs = env
+    # three realizations on one grid size, so a built sequence's footprint
+    # predicts the next one's
+    same = []
+    for r in (3, 4, 5):
+        case = inputs.serving_case(r, edge_override=10)
+        g = driver.GpuCase(case)
+        same.append((case, g, [g.u.clone()]))
+    torch.cuda.synchronize()
+    single = 0
+    for r in range(3):
+        _, st = _serve(driver, torch, same, [(r, 0)], max_active=1)
+        single = max(single, st.peak_bytes)
+    budget = int(1.4 * single)   # room for one resident sequence and its solve
+    order = [(r, 0) for r in range(3)] * 2
+    say(f"budget {budget} bytes (single-request peak {single})")
+    res, st = _serve(driver, torch, same, order, max_active=3, hbm_budget_bytes=budget)
+    say(f"peak {st.peak_bytes} evictions {st.evictions}")
+    assert st.peak_bytes <= budget
+    assert st.evictions >= 5
+    assert len(res) == 3  # keys repeat: the second round overwrote the first
+    for key, (x, r) in res.items():
+        assert r.status == tpf.TPF_CONVERGED, key
+        assert np.all(np.isfinite(x))
+    tiny, _ = _serve(driver, torch, same, [(0, 0)], hbm_budget_bytes=1 << 20)
+    assert tiny[(0, 0)][1].status == tpf.TPF_ERR_OVER_BUDGET
+    for _, g, _ in same:
+        g.close()
+
+
+def test_cancel(env):
+    driver, tpf, torch, seqs = env
+    sv = driver.Server(max_active=1)
+    case, g, states = seqs[1]
+    xs = [torch.zeros(2 * case.N, dtype=torch.float64, device="cuda") for _ in range(3)]
+    torch.cuda.synchronize()
+    t = [sv.submit(1, g, states[k], g.u_old, xs[k]) for k in range(3)]
+    sv.cancel(t[1])                 # queued
+    assert sv.poll(t[1]).status == tpf.TPF_CANCELLED
+    sv.step()                       # t[0] admitted and advanced one phase
+    sv.cancel(t[0])                 # active
+    res = sv.drain([t[0], t[2]])
+    assert res[t[0]].status == tpf.TPF_CANCELLED
+    assert res[t[2]].status == tpf.TPF_CONVERGED
+    st = sv.stats()
+    assert st.active == 0 and st.queued == 0
+    sv.close()
