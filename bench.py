@@ -44,6 +44,17 @@ def parse():
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="first run a plain device copy of this many MiB (calibrates the "
                          "FETCH_SIZE/WRITE_SIZE counters of a profiler run)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
+    ap.add_argument("--serve-full", action="store_true",
+                    help="the full stream: 64 realizations x 16 Newton-step requests, "
+                         "grids up to 128^3")
+    ap.add_argument("--serve-realizations", type=int, default=8)
+    ap.add_argument("--serve-requests", type=int, default=4, help="requests per realization")
+    ap.add_argument("--serve-max-edge", type=int, default=64,
+                    help="grid edges drawn above this are clamped to it")
+    ap.add_argument("--serve-active", type=int, default=8, help="requests in flight")
+    ap.add_argument("--serve-load", type=float, default=0.8,
+                    help="Poisson arrival rate as a fraction of the sequential FP64 throughput")
     return ap.parse_args()
 
 
@@ -142,6 +153,126 @@ def cpu_baseline(grid):
     return dt, info, c.N
 
 
+def pct(v, q):
+    return float(np.percentile(np.asarray(v, dtype=float), q)) if len(v) else None
+
+
+def serve_stream(torch, tpf, driver, inputs, args):
+    """Serving stream: R realizations (sigma, P_d, grid per realization r),
+    K Newton-step requests each, arriving interleaved.  The states u_k are
+    generated beforehand by FP64 Newton on the GPU (open loop).  Baseline:
+    the same requests one at a time, plain FP64 (assembly + full setup +
+    FGMRES).  Served: BF with FP32 V-cycles, hierarchy refresh within a
+    realization, up to --serve-active requests in flight."""
+    R, K, emax = args.serve_realizations, args.serve_requests, args.serve_max_edge
+    if args.serve_full:
+        R, K, emax = 64, 16, 128
+    rng = np.random.Generator(np.random.PCG64(7))
+    seqs = []
+    for r in range(R):
+        e = min(inputs.serving_realization(r)["nx"], emax)
+        case = inputs.serving_case(r, edge_override=e)
+        g = driver.GpuCase(case)
+        states = driver.newton_states(g, K)
+        seqs.append((case, g, states))
+        log(f"[serve] realization {r}: {e}^3 cells, {K} states")
+    order = []  # request i = (r, k); realizations interleaved, k ascending per realization
+    nxt = [0] * R
+    for r in rng.permutation(np.repeat(np.arange(R), K)):
+        order.append((int(r), nxt[r]))
+        nxt[r] += 1
+    n = len(order)
+    xb = {}
+    # ---- baseline: one at a time, plain FP64, full setup per request
+    lat_b = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r, k in order:
+        case, g, states = seqs[r]
+        t1 = time.perf_counter()
+        g.u.copy_(states[k])
+        g.assemble()
+        b = -g.R
+        M = driver.GpuPrecond("bf")
+        M.setup(g)
+        x = torch.empty_like(b)
+        info = driver.solve(g, M, b, x)
+        M.close()
+        torch.cuda.synchronize()
+        lat_b.append(1e3 * (time.perf_counter() - t1))
+        xb[(r, k)] = x
+        assert info.status == tpf.TPF_CONVERGED, (r, k, info.status)
+    base_s = time.perf_counter() - t0
+    for case, g, states in seqs:
+        g.u.copy_(states[0])
+    thr_b = n / base_s
+    log(f"[serve] baseline: {n} requests in {base_s:.2f} s ({thr_b:.1f} solves/s)")
+
+    def run(rate):
+        sv = driver.Server("bf", precision=tpf.TPF_FP32, max_active=args.serve_active)
+        arr = np.zeros(n) if rate is None else np.cumsum(rng.exponential(1.0 / rate, n))
+        xs = [torch.empty(2 * seqs[r][0].N, dtype=torch.float64, device="cuda") for r, _ in order]
+        torch.cuda.synchronize()
+        lat, its, rel, errs = [None] * n, [0] * n, [0.0] * n, [0.0] * n
+        tick, i, done = {}, 0, 0
+        t0 = time.perf_counter()
+        while done < n:
+            now = time.perf_counter() - t0
+            while i < n and arr[i] <= now:
+                r, k = order[i]
+                case, g, states = seqs[r]
+                tick[sv.submit(r, g, states[k], g.u_old, xs[i])] = i
+                i += 1
+            st = sv.stats()
+            if st.active == 0 and st.queued == 0:
+                if i < n:
+                    time.sleep(max(0.0, min(arr[i] - (time.perf_counter() - t0), 0.01)))
+                continue
+            sv.step()
+            for t in list(tick):
+                res = sv.poll(t)
+                if res is None:
+                    continue
+                j = tick.pop(t)
+                lat[j] = 1e3 * (time.perf_counter() - t0 - arr[j])
+                its[j] = res.iterations
+                rel[j] = res.relres_true
+                assert res.status == tpf.TPF_CONVERGED, (order[j], res.status)
+                done += 1
+        total = time.perf_counter() - t0
+        st = sv.stats()
+        sv.close()
+        torch.cuda.synchronize()
+        for j, (r, k) in enumerate(order):
+            errs[j] = float(torch.linalg.norm(xs[j] - xb[(r, k)]) / torch.linalg.norm(xb[(r, k)]))
+        return {"arrival_rate_per_s": None if rate is None else round(rate, 2),
+                "solves_per_s": round(n / total, 2), "wall_s": round(total, 3),
+                "p50_latency_ms": round(pct(lat, 50), 2), "p99_latency_ms": round(pct(lat, 99), 2),
+                "mean_iterations": round(float(np.mean(its)), 2),
+                "max_relres_true": float(np.max(rel)),
+                "max_rel_diff_vs_fp64": float(np.max(errs)),
+                "peak_bytes": int(st.peak_bytes), "evictions": int(st.evictions)}
+
+    log("[serve] burst: every request queued at t = 0")
+    burst = run(None)
+    rate = args.serve_load * thr_b
+    log(f"[serve] Poisson arrivals at {rate:.1f}/s")
+    pois = run(rate)
+    for case, g, states in seqs:
+        g.close()
+    edges = sorted({min(inputs.serving_realization(r)["nx"], emax) for r in range(R)})
+    return {
+        "workload": f"{R} realizations x {K} Newton-step requests, edges {edges}, "
+                    f"BF FP32 V-cycle, rtol 1e-8",
+        "requests": n, "max_active": args.serve_active,
+        "baseline_fp64_sequential": {"solves_per_s": round(thr_b, 2), "wall_s": round(base_s, 3),
+                                     "p50_latency_ms": round(pct(lat_b, 50), 2),
+                                     "p99_latency_ms": round(pct(lat_b, 99), 2)},
+        "burst": burst, "poisson": pois,
+        "throughput_speedup_vs_baseline": round(burst["solves_per_s"] / thr_b, 3),
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -167,7 +298,12 @@ def main():
     g = driver.GpuCase(c)
     torch.cuda.synchronize()
     log("[bench] FP64 form")
-    M64, x64, r64 = run_form(torch, tpf, driver, g, tpf.TPF_FP64, args.steps, args.warmup, True)
+    M64, x64, r64 = run_form(torch, tpf, driver, g, tpf.TPF_FP64, args.steps, args.warmup, False)
+    # one more step with every kernel bracketed by HIP events, for the
+    # kernel table and the roofline (kept out of the timed steps above)
+    log("[bench] FP64 instrumented step")
+    Mi, _, _ = run_form(torch, tpf, driver, g, tpf.TPF_FP64, 1, 0, True)
+    Mi.close()
     names = []
     for h, tag in enumerate(["Ass", "Schur"]):
         for k in ["vcycle_pre_residual", "vcycle_post_smooth", "vcycle_restrict", "vcycle_prolong"]:
@@ -195,6 +331,15 @@ def main():
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "avg_launch_us": round(avg_ms * 1e3, 2), "launches": cnt,
             "algorithmic_bytes_per_launch": bytes_per_launch}
+
+    M64.close()
+    M32.close()
+    g.close()
+    serving = None
+    if not args.no_serve:
+        log("[bench] serving stream")
+        tpf.tpf_kernel_timing(0)
+        serving = serve_stream(torch, tpf, driver, inputs, args)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -230,12 +375,10 @@ def main():
         "kernels_ms": {k: {"launches": v[0], "total_ms": round(v[1], 3),
                            "avg_us": round(1e3 * v[1] / v[0], 2)} for k, v in ktab.items()},
         "cpu_baseline": cpu,
-        "p99_latency_ms": None,
+        "serving": serving,
+        "p99_latency_ms": serving["poisson"]["p99_latency_ms"] if serving else None,
     }
     print(json.dumps(out), flush=True)
-    M64.close()
-    M32.close()
-    g.close()
 
 
 if __name__ == "__main__":

@@ -196,10 +196,17 @@ def config_c3(nx=128, ny=128, nz=64, seed=3) -> Case:
                                 name=f"3d-{nx}x{ny}x{nz}")
 
 
-def config_c4() -> Case:
+# Workloads that follow a Newton sequence (the 8M-cell case and the serving
+# stream) run at CFL 1: at CFL 10 the chopped Newton iteration of the 3D
+# five-spot stops converging after two or three iterates and the later
+# Jacobians belong to unphysical states.
+SEQUENCE_CFL = 1.0
+
+
+def config_c4(nx=256, ny=256, nz=128, cfl=SEQUENCE_CFL) -> Case:
     """256x256x128 3D, same statistics as the 1M-cell case, seed 4."""
-    return workload_3d_fivespot(256, 256, 128, 3.0, (16.0, 16.0, 4.0), 0.5, 10.0, 4,
-                                name="3d-256x256x128")
+    return workload_3d_fivespot(nx, ny, nz, 3.0, (16.0, 16.0, 4.0), 0.5, cfl, 4,
+                                name=f"3d-{nx}x{ny}x{nz}-cfl{cfl:g}")
 
 
 def serving_realization(r: int, master_seed: int = 5):
@@ -213,10 +220,10 @@ def serving_realization(r: int, master_seed: int = 5):
     return dict(nx=e, ny=e, nz=e, sigma=float(sig[r]), pd=float(pds[r]), seed=1000 + r)
 
 
-def serving_case(r: int, edge_override: int | None = None) -> Case:
+def serving_case(r: int, edge_override: int | None = None, cfl: float = SEQUENCE_CFL) -> Case:
     d = serving_realization(r)
     e = edge_override or d["nx"]
-    return workload_3d_fivespot(e, e, e, d["sigma"], (16.0, 16.0, 4.0), d["pd"], 10.0,
+    return workload_3d_fivespot(e, e, e, d["sigma"], (16.0, 16.0, 4.0), d["pd"], cfl,
                                 d["seed"], name=f"serve-r{r}-{e}")
 
 
