@@ -156,7 +156,7 @@ typedef struct tpf_precond_opts {
   int precision;        /* TPF_FP64 / TPF_FP32 */
   double theta;         /* strength threshold (0.25) */
   int max_levels;       /* 25; 1 gives an exact dense solve when n <= dense_max */
-  int coarse_max;       /* stop coarsening at n <= coarse_max (256) */
+  int coarse_max;       /* stop coarsening at n <= coarse_max (128) */
   int dense_max;        /* dense LU on the coarsest level if n <= dense_max (1024),
                            else two l1-Jacobi sweeps */
   int interp;           /* TPF_INTERP_* */

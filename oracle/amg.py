@@ -263,7 +263,7 @@ class Level:
 class Hierarchy:
     """AMG hierarchy; ``levels[-1]`` is the coarsest."""
 
-    def __init__(self, A, theta=0.25, coarse_max=256, max_levels=25, seed=0x5eed,
+    def __init__(self, A, theta=0.25, coarse_max=128, max_levels=25, seed=0x5eed,
                  dense_max=1024, interp="direct"):
         self.levels = []
         self.interp = interp

@@ -40,52 +40,93 @@ __device__ inline double row_diag(int i, int a0, int a1, const int* ci, const do
   return 0.0;
 }
 
-__global__ void k_l1_dinv(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                          const double* __restrict__ v, double* __restrict__ dinv) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int a0 = rp[i], a1 = rp[i + 1];
-  double aii = row_diag(i, a0, a1, ci, v);
-  double s = aii < 0.0 ? -1.0 : 1.0;
-  double off = 0.0;
-  for (int e = a0; e < a1; ++e)
-    if (ci[e] != i) off += fabs(v[e]);
-  double d = aii + s * off;
-  dinv[i] = d != 0.0 ? 1.0 / d : 0.0;
+// l1 diagonal d_i = a_ii + s_i sum_{j != i} |a_ij| (s_i = sign a_ii), inverted
+// (0 for a zero row sum); LPR lanes per row
+template <int LPR>
+__global__ void __launch_bounds__(256) k_l1_dinv(int n, const int* __restrict__ rp,
+                                                 const int* __restrict__ ci,
+                                                 const double* __restrict__ v,
+                                                 double* __restrict__ dinv) {
+  int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int i = int(gid / LPR), lane = int(gid % LPR);
+  double dg = 0.0, off = 0.0;
+  if (i < n)
+    for (int e = rp[i] + lane; e < rp[i + 1]; e += LPR) {
+      if (ci[e] == i) dg += v[e];
+      else off += fabs(v[e]);
+    }
+  dg = group_sum<LPR>(dg);
+  off = group_sum<LPR>(off);
+  if (i < n && lane == 0) {
+    double s = dg < 0.0 ? -1.0 : 1.0;
+    double d = dg + s * off;
+    dinv[i] = d != 0.0 ? 1.0 / d : 0.0;
+  }
 }
 
-__global__ void k_strength(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                           const double* __restrict__ v, double theta, uint8_t* __restrict__ mask,
-                           int* __restrict__ cnt) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int a0 = rp[i], a1 = rp[i + 1];
-  double aii = row_diag(i, a0, a1, ci, v);
-  double s = aii < 0.0 ? -1.0 : 1.0;
-  double m = -INFINITY;
-  for (int e = a0; e < a1; ++e)
-    if (ci[e] != i) {
-      double t = -s * v[e];
-      m = t > m ? t : m;
+// classical strength: j strongly influences i iff -s_i a_ij >= theta max_k(-s_i a_ik)
+// (off-diagonal), with a positive maximum; LPR lanes per row
+template <int LPR>
+__global__ void __launch_bounds__(256) k_strength(int n, const int* __restrict__ rp,
+                                                  const int* __restrict__ ci,
+                                                  const double* __restrict__ v, double theta,
+                                                  uint8_t* __restrict__ mask,
+                                                  int* __restrict__ cnt) {
+  int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int i = int(gid / LPR), lane = int(gid % LPR);
+  int a0 = 0, a1 = 0;
+  if (i < n) {
+    a0 = rp[i];
+    a1 = rp[i + 1];
+  }
+  double dg = 0.0, mpos = -INFINITY, mneg = -INFINITY;
+  for (int e = a0 + lane; e < a1; e += LPR) {
+    double x = v[e];
+    if (ci[e] == i) {
+      dg += x;
+    } else {
+      mpos = fmax(mpos, x);
+      mneg = fmax(mneg, -x);
     }
-  int c = 0;
+  }
+  dg = group_sum<LPR>(dg);
+  mpos = group_max<LPR>(mpos);
+  mneg = group_max<LPR>(mneg);
+  double s = dg < 0.0 ? -1.0 : 1.0;
+  double m = dg < 0.0 ? mpos : mneg;  // max of -s a_ij
   double thr = theta * m;
-  for (int e = a0; e < a1; ++e) {
+  int c = 0;
+  for (int e = a0 + lane; e < a1; e += LPR) {
     bool st = ci[e] != i && m > 0.0 && (-s * v[e]) >= thr;
     mask[e] = st;
     c += st;
   }
-  cnt[i] = c;
+  c = group_sum<LPR>(c);
+  if (i < n && lane == 0) cnt[i] = c;
 }
 
-__global__ void k_compact_pattern(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                  const uint8_t* __restrict__ mask, const int* __restrict__ srp,
-                                  int* __restrict__ sci) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int o = srp[i];
-  for (int e = rp[i]; e < rp[i + 1]; ++e)
-    if (mask[e]) sci[o++] = ci[e];
+// strong columns of each row, in row order (LPR lanes per row)
+template <int LPR>
+__global__ void __launch_bounds__(256) k_compact_pattern(int n, const int* __restrict__ rp,
+                                                         const int* __restrict__ ci,
+                                                         const uint8_t* __restrict__ mask,
+                                                         const int* __restrict__ srp,
+                                                         int* __restrict__ sci) {
+  int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int i = int(gid / LPR), lane = int(gid % LPR);
+  int a0 = 0, a1 = 0, o = 0;
+  if (i < n) {
+    a0 = rp[i];
+    a1 = rp[i + 1];
+    o = srp[i];
+  }
+  for (int base = a0; base < a1; base += LPR) {
+    int e = base + lane;
+    bool f = e < a1 && mask[e];
+    unsigned long long g = group_ballot<LPR>(f);
+    if (f) sci[o + __popcll(g & ((1ull << lane) - 1ull))] = ci[e];
+    o += __popcll(g);
+  }
 }
 
 __global__ void k_pmis_init(int n, uint64_t seed, const int* __restrict__ strp,
@@ -609,16 +650,105 @@ __global__ void __launch_bounds__(1024) k_gauss_jordan(int n, double* __restrict
     for (int c = threadIdx.x; c < w; c += blockDim.x) M[int64_t(k) * w + c] /= piv;
     for (int r = threadIdx.x; r < n; r += blockDim.x) fac[r] = M[int64_t(r) * w + k];
     __syncthreads();
-    // columns <= k of the left block are already reduced (unit vectors)
-    int wc = w - (k + 1);
-    for (int64_t t = threadIdx.x; t < int64_t(n) * wc; t += blockDim.x) {
-      int r = int(t / wc), c = k + 1 + int(t % wc);
-      if (r != k) M[int64_t(r) * w + c] -= fac[r] * M[int64_t(k) * w + c];
+    // columns <= k of the left block are already reduced (unit vectors);
+    // one wavefront per row, lanes along the row
+    int lane = threadIdx.x & 63;
+    for (int r = threadIdx.x >> 6; r < n; r += blockDim.x >> 6) {
+      if (r == k) continue;
+      double f = fac[r];
+      for (int c = k + 1 + lane; c < w; c += 64) M[int64_t(r) * w + c] -= f * M[int64_t(k) * w + c];
     }
     for (int r = threadIdx.x; r < n; r += blockDim.x)
       if (r != k) M[int64_t(r) * w + k] = 0.0;
     __syncthreads();
   }
+}
+
+// Gauss-Jordan inversion in place with the whole matrix in LDS (n <= 128):
+// partial pivoting by rows (largest |a|, lowest row on ties), row k
+// normalised, every other row eliminated, column k taking the inverse's
+// entries; the row interchanges are undone on the columns at the end.
+// Reads the CSR operator, writes A^{-1} (row-major n x n); singular ->
+// *flag = 1.
+constexpr int kGjLds = 128;
+__global__ void __launch_bounds__(1024) k_gauss_jordan_lds(int n, const int* __restrict__ rp,
+                                                           const int* __restrict__ ci,
+                                                           const double* __restrict__ v,
+                                                           double* __restrict__ inv,
+                                                           int* __restrict__ flag) {
+  __shared__ double a[kGjLds * kGjLds];
+  __shared__ double fac[kGjLds];
+  __shared__ int perm[kGjLds];
+  __shared__ int piv_row;
+  __shared__ double piv_abs;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
+  for (int t = tid; t < n * n; t += blockDim.x) a[t] = 0.0;
+  __syncthreads();
+  for (int r = wid; r < n; r += nw)
+    for (int e = rp[r] + lane; e < rp[r + 1]; e += 64) a[r * n + ci[e]] += v[e];
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (wid == 0) {
+      double bv = -1.0;
+      int bi = n;
+      for (int r = k + lane; r < n; r += 64) {
+        double x = fabs(a[r * n + k]);
+        if (x > bv || (x == bv && r < bi)) {
+          bv = x;
+          bi = r;
+        }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        double ov = __shfl_xor(bv, off, 64);
+        int oi = __shfl_xor(bi, off, 64);
+        if (ov > bv || (ov == bv && oi < bi)) {
+          bv = ov;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        piv_row = bi;
+        piv_abs = bv;
+        perm[k] = bi;
+      }
+    }
+    __syncthreads();
+    const int p = piv_row;
+    if (!(piv_abs > 0.0)) {
+      if (tid == 0) *flag = 1;
+      return;
+    }
+    if (p != k)
+      for (int c = tid; c < n; c += blockDim.x) {
+        double t = a[k * n + c];
+        a[k * n + c] = a[p * n + c];
+        a[p * n + c] = t;
+      }
+    __syncthreads();
+    const double pv = a[k * n + k];
+    __syncthreads();
+    for (int c = tid; c < n; c += blockDim.x) a[k * n + c] = (c == k ? 1.0 : a[k * n + c]) / pv;
+    for (int r = tid; r < n; r += blockDim.x) fac[r] = r == k ? 0.0 : a[r * n + k];
+    __syncthreads();
+    for (int r = wid; r < n; r += nw) {
+      if (r == k) continue;
+      double f = fac[r];
+      for (int c = lane; c < n; c += 64) a[r * n + c] = (c == k ? 0.0 : a[r * n + c]) - f * a[k * n + c];
+    }
+    __syncthreads();
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    int p = perm[k];
+    if (p != k)
+      for (int r = tid; r < n; r += blockDim.x) {
+        double t = a[r * n + k];
+        a[r * n + k] = a[r * n + p];
+        a[r * n + p] = t;
+      }
+    __syncthreads();
+  }
+  for (int t = tid; t < n * n; t += blockDim.x) inv[t] = a[t];
 }
 
 __global__ void k_dense_extract(int n, const double* __restrict__ M, double* __restrict__ Ainv) {
@@ -801,15 +931,21 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
     // strength of connection
     L.mask.alloc(L.A.nnz > 0 ? L.A.nnz : 1, s);
     Buf<int> cnt(n, s);
-    k_strength<<<grid_for(n, 256), 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.A.v.p, o.theta, L.mask.p,
-                                                cnt.p);
+    const int lpr = lanes_per_row(n, L.A.nnz);
+    const unsigned rblocks = grid_for(int64_t(n) * lpr, 256);
+    DISPATCH_LPR(lpr, LL, {
+      k_strength<LL><<<rblocks, 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.A.v.p, o.theta, L.mask.p,
+                                             cnt.p);
+    });
     TPF_CHECK_LAUNCH();
     L.S.nrows = L.S.ncols = n;
     L.S.rp.alloc(n + 1, s);
     L.S.nnz = scan_exclusive(cnt.p, L.S.rp.p, n, s);
     L.S.ci.alloc(L.S.nnz > 0 ? L.S.nnz : 1, s);
-    k_compact_pattern<<<grid_for(n, 256), 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.mask.p, L.S.rp.p,
-                                                       L.S.ci.p);
+    DISPATCH_LPR(lpr, LL, {
+      k_compact_pattern<LL><<<rblocks, 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.mask.p, L.S.rp.p,
+                                                    L.S.ci.p);
+    });
     TPF_CHECK_LAUNCH();
     Csr<double> ST;
     transpose(CsrRef<double>{n, n, L.S.nnz, L.S.rp.p, L.S.ci.p, nullptr}, ST, s);
@@ -931,7 +1067,13 @@ void Hierarchy::finish_levels(hipStream_t st) {
     L.t_prolong = "vcycle_prolong" + sfx;
     L.t_post = "vcycle_post_smooth" + sfx;
     L.dinv.ensure(n, st);
-    k_l1_dinv<<<grid_for(n, 256), 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, L.A.v.p, L.dinv.p);
+    {
+      const int lpr = lanes_per_row(n, L.A.nnz);
+      DISPATCH_LPR(lpr, LL, {
+        k_l1_dinv<LL><<<grid_for(int64_t(n) * lpr, 256), 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p,
+                                                                       L.A.v.p, L.dinv.p);
+      });
+    }
     TPF_CHECK_LAUNCH();
     L.r.ensure(n, st);
     L.y.ensure(n, st);
@@ -998,16 +1140,23 @@ void Hierarchy::coarse_setup(hipStream_t st) {
     Ainv.release();
     return;
   }
-  Buf<double> M(size_t(n) * 2 * n, st), fac(n, st);
   Buf<int> flag(1, st);
   fill_int(flag.p, 0, 1, st);
+  Ainv.ensure(size_t(n) * n, st);
+  if (n <= kGjLds) {
+    k_gauss_jordan_lds<<<1, 1024, 0, st>>>(n, L.A.rp.p, L.A.ci.p, L.A.v.p, Ainv.p, flag.p);
+    TPF_CHECK_LAUNCH();
+    int f = read_scalar(flag.p, st);
+    TPF_REQUIRE(f == 0, TPF_ERR_SINGULAR, "coarsest AMG matrix (n = %d) is singular", n);
+    return;
+  }
+  Buf<double> M(size_t(n) * 2 * n, st), fac(n, st);
   k_dense_augment<<<n, 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, L.A.v.p, M.p);
   TPF_CHECK_LAUNCH();
   k_gauss_jordan<<<1, 1024, 0, st>>>(n, M.p, fac.p, flag.p);
   TPF_CHECK_LAUNCH();
   int f = read_scalar(flag.p, st);
   TPF_REQUIRE(f == 0, TPF_ERR_SINGULAR, "coarsest AMG matrix (n = %d) is singular", n);
-  Ainv.ensure(size_t(n) * n, st);
   k_dense_extract<<<grid_for(int64_t(n) * n, 256), 256, 0, st>>>(n, M.p, Ainv.p);
   TPF_CHECK_LAUNCH();
   TPF_HIP(hipStreamSynchronize(st));

@@ -81,6 +81,22 @@ int64_t scan_exclusive(const int* in, int* out, int64_t n, hipStream_t s) {
   return total;
 }
 
+int64_t scan_exclusive_wide(const int* in, int64_t* out, int64_t n, hipStream_t s) {
+  if (n == 0) {
+    int64_t z = 0;
+    TPF_HIP(hipMemcpyAsync(out, &z, sizeof(z), hipMemcpyHostToDevice, s));
+    TPF_HIP(hipStreamSynchronize(s));
+    return 0;
+  }
+  scan_rec<int64_t, int>(in, out, n, s);
+  int64_t last_excl = read_scalar(out + n - 1, s);
+  int last_in = read_scalar(in + n - 1, s);
+  int64_t total = last_excl + last_in;
+  TPF_HIP(hipMemcpyAsync(out + n, &total, sizeof(total), hipMemcpyHostToDevice, s));
+  TPF_HIP(hipStreamSynchronize(s));
+  return total;
+}
+
 int64_t scan_exclusive64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s) {
   if (n == 0) {
     int64_t z = 0;

@@ -95,6 +95,33 @@ __device__ inline void wave_append(int cls, int nlists, int item, int stride, in
   }
 }
 
+// Sum / max over a group of LPR consecutive lanes (xor butterfly: every lane
+// of the group ends with the same bits).
+template <int LPR, class T>
+__device__ inline T group_sum(T v) {
+#pragma unroll
+  for (int off = LPR / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, LPR);
+  return v;
+}
+template <int LPR>
+__device__ inline double group_max(double v) {
+#pragma unroll
+  for (int off = LPR / 2; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, LPR));
+  return v;
+}
+
+// Bits of the calling lane's LPR-lane group in a wavefront ballot.
+template <int LPR>
+__device__ inline unsigned long long group_ballot(bool f) {
+  unsigned long long b = __ballot(f);
+  if constexpr (LPR == 64) {
+    return b;
+  } else {
+    int base = (threadIdx.x & (kWave - 1)) & ~(LPR - 1);
+    return (b >> base) & ((1ull << LPR) - 1ull);
+  }
+}
+
 inline int lanes_per_row(int64_t nrows, int64_t nnz) {
   double avg = nrows ? double(nnz) / double(nrows) : 1.0;
   int l = 1;

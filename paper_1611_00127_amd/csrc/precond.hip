@@ -463,7 +463,7 @@ int tpf_precond_default_opts(int kind, tpf_precond_opts* o) {
     o->precision = TPF_FP64;
     o->theta = 0.25;
     o->max_levels = 25;
-    o->coarse_max = 256;
+    o->coarse_max = 128;
     o->dense_max = 1024;
     o->interp = TPF_INTERP_AUTO;
     o->hash_seed = 0x5eed;

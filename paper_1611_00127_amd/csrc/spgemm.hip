@@ -30,7 +30,7 @@ __global__ void __launch_bounds__(128) k_spgemm_merge(
     const double* __restrict__ av, const int* __restrict__ brp, const int* __restrict__ bci,
     const double* __restrict__ bv, const int* __restrict__ drp, const int* __restrict__ dci,
     const double* __restrict__ dv, double alpha, double beta, int2* __restrict__ cur,
-    int* __restrict__ cnt, const int* __restrict__ crp, int* __restrict__ cci,
+    int* __restrict__ cnt, const int64_t* __restrict__ toff, int* __restrict__ cci,
     double* __restrict__ cv) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nlist) return;
@@ -45,7 +45,7 @@ __global__ void __launch_bounds__(128) k_spgemm_merge(
     dp = drp[i];
     de = drp[i + 1];
   }
-  int out = FILL ? crp[i] : 0;
+  int64_t out = FILL ? toff[i] : 0;
   int count = 0;
   while (true) {
     int m = INT_MAX;
@@ -78,7 +78,7 @@ __global__ void __launch_bounds__(128) k_spgemm_merge(
     if (dp < de && dci[dp] == m) ++dp;
     ++count;
   }
-  if (!FILL) cnt[i] = count;
+  cnt[i] = count;
 }
 
 // ---- row classification and the sort-based product
@@ -94,17 +94,25 @@ __global__ void k_spgemm_ub(int nrows, const int* __restrict__ arp, const int* _
   ub[i] = t > INT_MAX ? INT_MAX : int(t);
 }
 
-// appends row i to the list of its size class: 0 flattened wavefront,
-// 1 flattened work-group, 2 sorted-columns work-group, 3 per-thread merge
-__global__ void k_spgemm_classify(int nrows, const int* __restrict__ ub, int cap0, int cap1,
-                                  int cap2, int* __restrict__ counts, int* __restrict__ lists) {
+// appends row i to the list of its size class: the first class whose cap
+// holds ub[i] (flattened wavefront / work-group kernels, then the
+// sorted-columns work-group), else the last list (per-thread merge)
+constexpr int kClasses = 7;
+struct Caps {
+  int c[kClasses - 1];
+};
+__global__ void k_spgemm_classify(int nrows, const int* __restrict__ ub, Caps caps,
+                                  int* __restrict__ counts, int* __restrict__ lists) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int c = -1;
   if (i < nrows) {
     int u = ub[i];
-    c = u <= cap0 ? 0 : (u <= cap1 ? 1 : (u <= cap2 ? 2 : 3));
+    c = kClasses - 1;
+#pragma unroll
+    for (int k = kClasses - 2; k >= 0; --k)
+      if (u <= caps.c[k]) c = k;
   }
-  wave_append(c, 4, i, nrows, counts, lists);
+  wave_append(c, kClasses, i, nrows, counts, lists);
 }
 
 __device__ inline int bsearch_col(const int* __restrict__ c, int lo, int hi, int key) {
@@ -125,7 +133,7 @@ __global__ void __launch_bounds__(BLOCK) k_spgemm_sorted(
     const int* __restrict__ aci, const double* __restrict__ av, const int* __restrict__ brp,
     const int* __restrict__ bci, const double* __restrict__ bv, const int* __restrict__ drp,
     const int* __restrict__ dci, const double* __restrict__ dv, double alpha, double beta,
-    int* __restrict__ cnt, const int* __restrict__ crp, int* __restrict__ cci,
+    int* __restrict__ cnt, const int64_t* __restrict__ toff, int* __restrict__ cci,
     double* __restrict__ cv) {
   __shared__ __attribute__((aligned(16))) int keys[CAP];
   __shared__ int ukeys[CAP];
@@ -168,7 +176,7 @@ __global__ void __launch_bounds__(BLOCK) k_spgemm_sorted(
     }
   }
   // unique columns in order
-  int o = FILL ? crp[i] : 0;
+  int64_t o = FILL ? toff[i] : 0;
   int running = 0;
   for (int base = 0; base < p2; base += BLOCK) {
     int t = base + threadIdx.x;
@@ -182,10 +190,8 @@ __global__ void __launch_bounds__(BLOCK) k_spgemm_sorted(
     if (flag) ukeys[running + excl] = keys[t];
     running += total;
   }
-  if (!FILL) {
-    if (threadIdx.x == 0) cnt[i] = running;
-    return;
-  }
+  if (threadIdx.x == 0) cnt[i] = running;
+  if (!FILL) return;
   __syncthreads();
   for (int t = threadIdx.x; t < running; t += BLOCK) cci[o + t] = ukeys[t];
   if (running <= CAP / 2) {
@@ -258,7 +264,7 @@ __global__ void __launch_bounds__(BLOCK) k_spgemm_flat(
     const int* __restrict__ aci, const double* __restrict__ av, const int* __restrict__ brp,
     const int* __restrict__ bci, const double* __restrict__ bv, const int* __restrict__ drp,
     const int* __restrict__ dci, const double* __restrict__ dv, double alpha, double beta,
-    int* __restrict__ cnt, const int* __restrict__ crp, int* __restrict__ cci,
+    int* __restrict__ cnt, const int64_t* __restrict__ toff, int* __restrict__ cci,
     double* __restrict__ cv) {
   __shared__ int offs[CAP + 1];
   __shared__ unsigned long long keys[CAP];
@@ -326,7 +332,7 @@ __global__ void __launch_bounds__(BLOCK) k_spgemm_flat(
       __syncthreads();
     }
   // run heads -> output positions; each head sums its run in order
-  int o = FILL ? crp[i] : 0;
+  int64_t o = FILL ? toff[i] : 0;
   int count = 0;
   for (int base = 0; base < p2; base += BLOCK) {
     int t = base + threadIdx.x;
@@ -354,7 +360,7 @@ __global__ void __launch_bounds__(BLOCK) k_spgemm_flat(
     }
     count += total;
   }
-  if (!FILL && threadIdx.x == 0) cnt[i] = count;
+  if (threadIdx.x == 0) cnt[i] = count;
 }
 
 // numeric refresh on a known pattern: one wavefront per row
@@ -403,23 +409,64 @@ __global__ void k_transpose_fill(int nrows, const int* __restrict__ rp, const in
   }
 }
 
-// insertion sort of each row by column (rows of a transpose are short)
-__global__ void k_sort_rows(int nrows, const int* __restrict__ rp, int* __restrict__ ci,
-                            double* __restrict__ v) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Sorts each row by column, one wavefront per row.  The columns of a row are
+// distinct, so an entry's position is the number of smaller columns in its
+// row; rows longer than kSortCap fall back to an insertion sort by one lane.
+constexpr int kSortCap = 1024;
+__global__ void __launch_bounds__(64) k_sort_rows(int nrows, const int* __restrict__ rp,
+                                                  int* __restrict__ ci, double* __restrict__ v) {
+  __shared__ int keys[kSortCap];
+  __shared__ double vals[kSortCap];
+  int i = blockIdx.x;
   if (i >= nrows) return;
-  int a = rp[i], b = rp[i + 1];
-  for (int e = a + 1; e < b; ++e) {
-    int key = ci[e];
-    double val = v ? v[e] : 0.0;
-    int f = e - 1;
-    while (f >= a && ci[f] > key) {
-      ci[f + 1] = ci[f];
-      if (v) v[f + 1] = v[f];
-      --f;
+  int a = rp[i], len = rp[i + 1] - a;
+  if (len <= 1) return;
+  if (len > kSortCap) {
+    if (threadIdx.x != 0) return;
+    for (int e = a + 1; e < a + len; ++e) {
+      int key = ci[e];
+      double val = v ? v[e] : 0.0;
+      int f = e - 1;
+      while (f >= a && ci[f] > key) {
+        ci[f + 1] = ci[f];
+        if (v) v[f + 1] = v[f];
+        --f;
+      }
+      ci[f + 1] = key;
+      if (v) v[f + 1] = val;
     }
-    ci[f + 1] = key;
-    if (v) v[f + 1] = val;
+    return;
+  }
+  for (int j = threadIdx.x; j < len; j += 64) {
+    keys[j] = ci[a + j];
+    if (v) vals[j] = v[a + j];
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < len; j += 64) {
+    int key = keys[j];
+    int rank = 0;
+    for (int m = 0; m < len; ++m) rank += keys[m] < key;
+    ci[a + rank] = key;
+    if (v) v[a + rank] = vals[j];
+  }
+}
+
+// moves each row's staged entries to their packed position
+template <int LPR>
+__global__ void __launch_bounds__(256) k_spgemm_pack(int n, const int64_t* __restrict__ toff,
+                                                     const int* __restrict__ crp,
+                                                     const int* __restrict__ tci,
+                                                     const double* __restrict__ tv,
+                                                     int* __restrict__ cci,
+                                                     double* __restrict__ cv) {
+  int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int i = int(gid / LPR), lane = int(gid % LPR);
+  if (i >= n) return;
+  int64_t src = toff[i];
+  int c0 = crp[i], len = crp[i + 1] - c0;
+  for (int t = lane; t < len; t += LPR) {
+    cci[c0 + t] = tci[src + t];
+    cv[c0 + t] = tv[src + t];
   }
 }
 
@@ -455,44 +502,64 @@ void spgemm(const CsrRef<double>& A, const CsrRef<double>& B, Csr<double>& C, hi
     C.v.alloc(1, s);
     return;
   }
-  constexpr int kCap0 = 512, kCap1 = 2048, kCap2 = 16384;
-  Buf<int> ub(n, s), counts(4, s), lists(4 * int64_t(n), s), cnt(n, s);
-  fill_int(counts.p, 0, 4, s);
+  // caps ascending: flat<64,CAP> wavefront kernels, flat<256,2048>, sorted<256,16384>
+  const Caps caps{{64, 128, 256, 512, 2048, 16384}};
+  Buf<int> ub(n, s), counts(kClasses, s), lists(kClasses * int64_t(n), s), cnt(n, s);
+  fill_int(counts.p, 0, kClasses, s);
   k_spgemm_ub<<<grid_for(n, 256), 256, 0, s>>>(n, A.rp, A.ci, B.rp, drp, ub.p);
   TPF_CHECK_LAUNCH();
-  k_spgemm_classify<<<grid_for(n, 256), 256, 0, s>>>(n, ub.p, kCap0, kCap1, kCap2, counts.p,
-                                                     lists.p);
+  k_spgemm_classify<<<grid_for(n, 256), 256, 0, s>>>(n, ub.p, caps, counts.p, lists.p);
   TPF_CHECK_LAUNCH();
-  int hc[4];
+  // one pass: each row writes its sorted unique entries at its upper-bound
+  // offset in a staging area, then the rows are packed
+  Buf<int64_t> toff(size_t(n) + 1, s);
+  int64_t staged = scan_exclusive_wide(ub.p, toff.p, n, s);
+  int hc[kClasses];
   TPF_HIP(hipMemcpyAsync(hc, counts.p, sizeof(hc), hipMemcpyDeviceToHost, s));
   TPF_HIP(hipStreamSynchronize(s));
+  Buf<int> tci(staged > 0 ? size_t(staged) : 1, s);
+  Buf<double> tv(staged > 0 ? size_t(staged) : 1, s);
   Buf<int2> cur;
-  if (hc[3] > 0) cur.alloc(A.nnz > 0 ? A.nnz : 1, s);
-  auto run = [&](auto fill_tag) {
-    constexpr bool F = decltype(fill_tag)::value;
-    if (hc[0] > 0)
-      k_spgemm_flat<64, kCap0, F><<<hc[0], 64, 0, s>>>(
-          lists.p, ub.p, A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha, beta, cnt.p,
-          C.rp.p, C.ci.p, C.v.p);
-    if (hc[1] > 0)
-      k_spgemm_flat<256, kCap1, F><<<hc[1], 256, 0, s>>>(
-          lists.p + n, ub.p, A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha, beta, cnt.p,
-          C.rp.p, C.ci.p, C.v.p);
-    if (hc[2] > 0)
-      k_spgemm_sorted<256, kCap2, F><<<hc[2], 256, 0, s>>>(
-          lists.p + 2 * int64_t(n), ub.p, A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha,
-          beta, cnt.p, C.rp.p, C.ci.p, C.v.p);
-    if (hc[3] > 0)
-      k_spgemm_merge<F><<<grid_for(hc[3], 128), 128, 0, s>>>(
-          hc[3], lists.p + 3 * int64_t(n), A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha,
-          beta, cur.p, cnt.p, C.rp.p, C.ci.p, C.v.p);
-    TPF_CHECK_LAUNCH();
-  };
-  run(std::false_type{});
+  if (hc[kClasses - 1] > 0) cur.alloc(A.nnz > 0 ? A.nnz : 1, s);
+  auto list = [&](int c) { return lists.p + int64_t(c) * n; };
+  if (hc[0] > 0)
+    k_spgemm_flat<64, 64, true><<<hc[0], 64, 0, s>>>(list(0), ub.p, A.rp, A.ci, A.v, B.rp, B.ci,
+                                                     B.v, drp, dci, dv, alpha, beta, cnt.p, toff.p,
+                                                     tci.p, tv.p);
+  if (hc[1] > 0)
+    k_spgemm_flat<64, 128, true><<<hc[1], 64, 0, s>>>(list(1), ub.p, A.rp, A.ci, A.v, B.rp, B.ci,
+                                                      B.v, drp, dci, dv, alpha, beta, cnt.p,
+                                                      toff.p, tci.p, tv.p);
+  if (hc[2] > 0)
+    k_spgemm_flat<64, 256, true><<<hc[2], 64, 0, s>>>(list(2), ub.p, A.rp, A.ci, A.v, B.rp, B.ci,
+                                                      B.v, drp, dci, dv, alpha, beta, cnt.p,
+                                                      toff.p, tci.p, tv.p);
+  if (hc[3] > 0)
+    k_spgemm_flat<64, 512, true><<<hc[3], 64, 0, s>>>(list(3), ub.p, A.rp, A.ci, A.v, B.rp, B.ci,
+                                                      B.v, drp, dci, dv, alpha, beta, cnt.p,
+                                                      toff.p, tci.p, tv.p);
+  if (hc[4] > 0)
+    k_spgemm_flat<256, 2048, true><<<hc[4], 256, 0, s>>>(list(4), ub.p, A.rp, A.ci, A.v, B.rp,
+                                                         B.ci, B.v, drp, dci, dv, alpha, beta,
+                                                         cnt.p, toff.p, tci.p, tv.p);
+  if (hc[5] > 0)
+    k_spgemm_sorted<256, 16384, true><<<hc[5], 256, 0, s>>>(list(5), ub.p, A.rp, A.ci, A.v, B.rp,
+                                                            B.ci, B.v, drp, dci, dv, alpha, beta,
+                                                            cnt.p, toff.p, tci.p, tv.p);
+  if (hc[6] > 0)
+    k_spgemm_merge<true><<<grid_for(hc[6], 128), 128, 0, s>>>(
+        hc[6], list(6), A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha, beta, cur.p, cnt.p,
+        toff.p, tci.p, tv.p);
+  TPF_CHECK_LAUNCH();
   C.nnz = scan_exclusive(cnt.p, C.rp.p, n, s);
   C.ci.alloc(C.nnz > 0 ? C.nnz : 1, s);
   C.v.alloc(C.nnz > 0 ? C.nnz : 1, s);
-  run(std::true_type{});
+  const int lpr = lanes_per_row(n, C.nnz);
+  DISPATCH_LPR(lpr, LL, {
+    k_spgemm_pack<LL><<<grid_for(int64_t(n) * lpr, 256), 256, 0, s>>>(n, toff.p, C.rp.p, tci.p,
+                                                                      tv.p, C.ci.p, C.v.p);
+  });
+  TPF_CHECK_LAUNCH();
 }
 
 void transpose(const CsrRef<double>& A, Csr<double>& C, hipStream_t s) {
@@ -521,7 +588,7 @@ void transpose(const CsrRef<double>& A, Csr<double>& C, hipStream_t s) {
     TPF_CHECK_LAUNCH();
   }
   if (m > 0) {
-    k_sort_rows<<<grid_for(m, 128), 128, 0, s>>>(m, C.rp.p, C.ci.p, C.v.p);
+    k_sort_rows<<<m, 64, 0, s>>>(m, C.rp.p, C.ci.p, C.v.p);
     TPF_CHECK_LAUNCH();
   }
 }

@@ -167,6 +167,8 @@ inline unsigned grid_for(int64_t n, int block) {
 // exclusive scan of n ints into out[0..n], out[n] = total; returns total (synchronises)
 int64_t scan_exclusive(const int* in, int* out, int64_t n, hipStream_t s);
 int64_t scan_exclusive64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);
+// int counts into 64-bit offsets out[0..n] (no overflow check needed)
+int64_t scan_exclusive_wide(const int* in, int64_t* out, int64_t n, hipStream_t s);
 void fill_int(int* p, int v, int64_t n, hipStream_t s);
 template <class T> void fill(T* p, T v, int64_t n, hipStream_t s);
 template <class T> void copy(T* dst, const T* src, int64_t n, hipStream_t s);

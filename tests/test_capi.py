@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
 def test_host_side_errors_without_gpu():
     lib = tpf.load()
     o = tpf.tpf_precond_default_opts(tpf.TPF_PREC_BF)
-    assert o.theta == 0.25 and o.max_levels == 25 and o.coarse_max == 256
+    assert o.theta == 0.25 and o.max_levels == 25 and o.coarse_max == 128
     M = tpf.tpf_precond_create(o)
     # apply before setup is a state error, detected before any device work
     rc = lib.tpf_precond_apply(M, None, None, None)

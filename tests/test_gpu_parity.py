@@ -212,6 +212,29 @@ def test_vcycle_parity(gpu, kind, hier):
     M.close(); g.close()
 
 
+@pytest.mark.parametrize("dims", [(6, 5, 4), (10, 9, 5)])
+def test_coarsest_dense_inverse(gpu, dims):
+    """One-level hierarchy (max_levels 1): the V-cycle is the coarsest dense
+    solve, x = A^{-1} b, checked against a direct solve of the GPU's own
+    operator.  120 rows take the LDS-resident inversion, 450 rows the
+    global-memory one."""
+    driver, tpf, torch = gpu
+    c = inputs.random_state(inputs.small_case(*dims, seed=21), 22, s_lo=0.15, s_hi=0.85)
+    say(f"[coarsest] {dims}")
+    g, M = _setup(driver, tpf, c, "bf", max_levels=1)
+    st = M.stats()
+    assert st.levels[0] == 1 and st.coarse_dense[0] == 1
+    A = _download_level(tpf, M, 0, 0).toarray()
+    b = inputs.random_vector(A.shape[0], 23)
+    bd = torch.tensor(b, device="cuda")
+    xd = torch.empty_like(bd)
+    tpf.tpf_precond_vcycle(M.M, 0, bd, xd)
+    x = xd.cpu().numpy()
+    xo = np.linalg.solve(A, b)
+    assert np.max(np.abs(x - xo)) <= 1e-10 * np.max(np.abs(xo))
+    M.close(); g.close()
+
+
 def test_bilu_parity(gpu):
     driver, tpf, torch = gpu
     c = inputs.small_case(15, 13, 6, seed=10)
