@@ -303,17 +303,7 @@ __device__ inline int exti_merge(int i, const int* __restrict__ rp, const int* _
   return count;
 }
 
-// per-thread versions for the rows with the largest candidate sets
-__global__ void k_exti_count(int nl, const int* __restrict__ rows, const int* __restrict__ rp,
-                             const int* __restrict__ ci, const uint8_t* __restrict__ mask,
-                             const int8_t* __restrict__ cf, int2* __restrict__ cur,
-                             int* __restrict__ cnt) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nl) return;
-  int i = rows[t];
-  cnt[i] = cf[i] == kC ? 1 : exti_merge<false>(i, rp, ci, mask, cf, cur, nullptr);
-}
-
+// per-thread version for the rows with the largest candidate sets
 // position of fine index j in the sorted list c[0..len), or -1
 __device__ inline int find_sorted(const int* __restrict__ c, int len, int j) {
   int lo = 0, hi = len - 1;
@@ -335,20 +325,16 @@ __global__ void k_exti_fill(int nl, const int* __restrict__ rows, const int* __r
                             const int* __restrict__ ci, const double* __restrict__ v,
                             const uint8_t* __restrict__ mask, const int8_t* __restrict__ cf,
                             const int* __restrict__ cidx, int2* __restrict__ cur,
-                            const int* __restrict__ prp, int* __restrict__ pci,
-                            double* __restrict__ pv) {
+                            const int64_t* __restrict__ toff, int* __restrict__ cnt,
+                            int* __restrict__ pci, double* __restrict__ pv) {
   int tt = blockIdx.x * blockDim.x + threadIdx.x;
   if (tt >= nl) return;
   int i = rows[tt];
-  int o = prp[i];
-  if (cf[i] == kC) {
-    pci[o] = cidx[i];
-    pv[o] = 1.0;
-    return;
-  }
+  int64_t o = toff[i];
   int* c = pci + o;
   double* w = pv + o;
   int len = exti_merge<true>(i, rp, ci, mask, cf, cur, c);
+  cnt[i] = len;
   for (int t = 0; t < len; ++t) w[t] = 0.0;
   int a0 = rp[i], a1 = rp[i + 1];
   double atil = row_diag(i, a0, a1, ci, v);
@@ -392,48 +378,309 @@ __global__ void k_exti_fill(int nl, const int* __restrict__ rows, const int* __r
   }
 }
 
-// ---- extended+i, one wavefront per F row (rows whose candidate bound fits
-// kExtCap); the per-thread kernels above handle the rest.
-constexpr int kExtCap = 1024;
-constexpr int kExtCap2 = 4096;
+// ---- extended+i, one wavefront per F row.  The rows of the strong F
+// neighbours are loaded once, flattened over the lanes, into LDS; the
+// candidate set C^_i is sorted there and the weights accumulate over the
+// neighbours k in row order.  Rows whose bounds exceed the wavefront
+// kernels' capacities use the per-thread kernel above.
+constexpr int kExtK = 64;      // strong F neighbours per row (wavefront kernels)
+constexpr int kExtCap0 = 256;  // candidates (with duplicates) / flattened entries: class 0
+constexpr int kExtFlat0 = 512;
+constexpr int kExtCap1 = 1024;  // class 1
+constexpr int kExtFlat1 = 2048;
+constexpr int kExtCap2 = 4096;  // class 2: wide rows, neighbour rows from global memory
 
-// candidate count of F row i before removing duplicates: strong C
-// neighbours of i plus those of each strong F neighbour (one wavefront per
-// row, four rows per block)
-__global__ void __launch_bounds__(256) k_exti_ub(int n, const int* __restrict__ rp,
-                                                 const int* __restrict__ ci,
-                                                 const uint8_t* __restrict__ mask,
-                                                 const int8_t* __restrict__ cf,
-                                                 int* __restrict__ ub) {
-  int i = blockIdx.x * 4 + int(threadIdx.x / 64);
-  int lane = threadIdx.x & 63;
-  if (i >= n) return;
-  if (cf[i] == kC) {
-    if (lane == 0) ub[i] = 0;
-    return;
-  }
-  int64_t t = 0;
-  for (int e = rp[i] + lane; e < rp[i + 1]; e += 64) {
-    int k = ci[e];
-    if (mask[e] && k != i && cf[k] == kC) ++t;
-  }
-  for (int e = rp[i]; e < rp[i + 1]; ++e) {
-    int k = ci[e];
-    if (!(mask[e] && k != i && cf[k] == kF)) continue;
-    for (int f = rp[k] + lane; f < rp[k + 1]; f += 64) t += mask[f] && cf[ci[f]] == kC;
-  }
-  t = wave_sum(t);
-  if (lane == 0) ub[i] = t > INT_MAX ? INT_MAX : int(t);
+__device__ inline unsigned long long lanes_below() {
+  return (1ull << (threadIdx.x & 63)) - 1ull;
 }
 
-// F rows by candidate count: class 0 (<= kExtCap), 1 (<= kExtCap2), 2 (the
-// rest); C rows are written directly.  One atomic per class per wavefront.
-__global__ void k_exti_classify(int n, const int* __restrict__ ub, const int8_t* __restrict__ cf,
+// Per F row i: ub = strong C entries of row i and of the rows of its strong
+// F neighbours (duplicates counted), fl = summed length of those rows, nk =
+// number of strong F neighbours.  C rows get ub = 1 (their injection entry).
+__global__ void __launch_bounds__(64) k_exti_ub(int n, const int* __restrict__ rp,
+                                                const int* __restrict__ ci,
+                                                const uint8_t* __restrict__ mask,
+                                                const int8_t* __restrict__ cf,
+                                                int* __restrict__ ub, int* __restrict__ fl,
+                                                int* __restrict__ nko) {
+  __shared__ int kst[kExtK];
+  __shared__ int ko[kExtK + 1];
+  int i = blockIdx.x;
+  int lane = threadIdx.x;
+  if (i >= n) return;
+  if (cf[i] == kC) {
+    if (lane == 0) {
+      ub[i] = 1;
+      fl[i] = 0;
+      nko[i] = 0;
+    }
+    return;
+  }
+  int a0 = rp[i], a1 = rp[i + 1];
+  int64_t t = 0;
+  int nk = 0;
+  for (int base = a0; base < a1; base += 64) {
+    int e = base + lane;
+    bool sc = false, sf = false;
+    int k = 0;
+    if (e < a1) {
+      k = ci[e];
+      bool m = mask[e] && k != i;
+      int8_t c = cf[k];
+      sc = m && c == kC;
+      sf = m && c == kF;
+    }
+    t += sc;
+    unsigned long long b = __ballot(sf);
+    int pos = nk + __popcll(b & lanes_below());
+    if (sf && pos < kExtK) kst[pos] = k;
+    nk += __popcll(b);
+  }
+  __syncthreads();
+  int64_t flat = 0;
+  if (nk <= kExtK) {
+    int len = 0;
+    if (lane < nk) {
+      int k = kst[lane];
+      int k0 = rp[k];
+      len = rp[k + 1] - k0;
+      kst[lane] = k0;
+    }
+    int incl = len;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      int y = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += y;
+    }
+    if (lane == 0) ko[0] = 0;
+    if (lane < nk) ko[lane + 1] = incl;
+    flat = __shfl(incl, 63, 64);
+    __syncthreads();
+    for (int q = lane; q < flat; q += 64) {
+      int lo = 0, hi = nk;  // largest seg with ko[seg] <= q
+      while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (ko[mid] <= q) lo = mid;
+        else hi = mid;
+      }
+      int f = kst[lo] + (q - ko[lo]);
+      t += mask[f] && cf[ci[f]] == kC;
+    }
+  } else {
+    for (int e = a0; e < a1; ++e) {
+      int k = ci[e];
+      if (!(mask[e] && k != i && cf[k] == kF)) continue;
+      flat += rp[k + 1] - rp[k];
+      for (int f = rp[k] + lane; f < rp[k + 1]; f += 64) t += mask[f] && cf[ci[f]] == kC;
+    }
+  }
+  t = wave_sum(t);
+  if (lane == 0) {
+    ub[i] = t > INT_MAX ? INT_MAX : int(t);
+    fl[i] = flat > INT_MAX ? INT_MAX : int(flat);
+    nko[i] = nk;
+  }
+}
+
+// F rows by their bounds: classes 0 / 1 (flattened wavefront kernels), 2 (wide
+// wavefront kernel), 3 (per thread)
+__global__ void k_exti_classify(int n, const int* __restrict__ ub, const int* __restrict__ fl,
+                                const int* __restrict__ nk, const int8_t* __restrict__ cf,
                                 int* __restrict__ counts, int* __restrict__ lists) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int c = -1;
-  if (i < n && cf[i] != kC) c = ub[i] <= kExtCap ? 0 : (ub[i] <= kExtCap2 ? 1 : 2);
-  wave_append(c, 3, i, n, counts, lists);
+  if (i < n && cf[i] != kC) {
+    if (nk[i] <= kExtK && ub[i] <= kExtCap0 && fl[i] <= kExtFlat0) c = 0;
+    else if (nk[i] <= kExtK && ub[i] <= kExtCap1 && fl[i] <= kExtFlat1) c = 1;
+    else if (ub[i] <= kExtCap2) c = 2;
+    else c = 3;
+  }
+  wave_append(c, 4, i, n, counts, lists);
+}
+
+__device__ inline int lds_find(const int* u, int m, int key) {
+  int lo = 0, hi = m;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (u[mid] < key) lo = mid + 1;
+    else hi = mid;
+  }
+  return (lo < m && u[lo] == key) ? lo : -1;
+}
+
+// Extended+i weights of one F row (see k_exti_fill for the formula); writes
+// the row's sorted coarse columns and weights at toff[i], its length to cnt.
+template <int CAP, int FCAP>
+__global__ void __launch_bounds__(64) k_exti_flat(
+    const int* __restrict__ rows, const int* __restrict__ rp, const int* __restrict__ ci,
+    const double* __restrict__ v, const uint8_t* __restrict__ mask, const int8_t* __restrict__ cf,
+    const int* __restrict__ cidx, const int64_t* __restrict__ toff, int* __restrict__ cnt,
+    int* __restrict__ pci, double* __restrict__ pv) {
+  __shared__ int cand[CAP];
+  __shared__ int uniq[CAP];
+  __shared__ double w[CAP];
+  __shared__ int fcol[FCAP];
+  __shared__ double fval[FCAP];
+  __shared__ int ks[kExtK];
+  __shared__ int kst[kExtK];
+  __shared__ int ko[kExtK + 1];
+  __shared__ double ka[kExtK];
+  __shared__ double kdg[kExtK];
+  const int lane = threadIdx.x;
+  const int i = rows[blockIdx.x];
+  const int a0 = rp[i], a1 = rp[i + 1];
+  // row i: strong C columns are candidates; strong F neighbours in row order
+  int len = 0, nk = 0;
+  for (int base = a0; base < a1; base += 64) {
+    int e = base + lane;
+    bool sc = false, sf = false;
+    int k = 0;
+    if (e < a1) {
+      k = ci[e];
+      bool m = mask[e] && k != i;
+      int8_t c = cf[k];
+      sc = m && c == kC;
+      sf = m && c == kF;
+    }
+    unsigned long long b = __ballot(sc);
+    if (sc) cand[len + __popcll(b & lanes_below())] = k;
+    len += __popcll(b);
+    b = __ballot(sf);
+    if (sf) {
+      int p = nk + __popcll(b & lanes_below());
+      ks[p] = k;
+      ka[p] = v[e];
+    }
+    nk += __popcll(b);
+  }
+  __syncthreads();
+  // neighbour rows: start, length, flattened offsets
+  int rl = 0;
+  if (lane < nk) {
+    int k = ks[lane];
+    int k0 = rp[k];
+    kst[lane] = k0;
+    rl = rp[k + 1] - k0;
+    kdg[lane] = 0.0;
+  }
+  int incl = rl;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int y = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += y;
+  }
+  if (lane == 0) ko[0] = 0;
+  if (lane < nk) ko[lane + 1] = incl;
+  const int flat = __shfl(incl, 63, 64);
+  __syncthreads();
+  for (int q0 = 0; q0 < flat; q0 += 64) {
+    int q = q0 + lane;
+    bool c = false;
+    int col = 0;
+    if (q < flat) {
+      int lo = 0, hi = nk;
+      while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (ko[mid] <= q) lo = mid;
+        else hi = mid;
+      }
+      int f = kst[lo] + (q - ko[lo]);
+      col = ci[f];
+      double x = v[f];
+      fcol[q] = col;
+      fval[q] = x;
+      if (col == ks[lo]) kdg[lo] = x;
+      c = mask[f] && cf[col] == kC;
+    }
+    unsigned long long b = __ballot(c);
+    if (c) cand[len + __popcll(b & lanes_below())] = col;
+    len += __popcll(b);
+  }
+  // sorted unique candidates
+  int p2 = 1;
+  while (p2 < len) p2 <<= 1;
+  for (int t = len + lane; t < p2; t += 64) cand[t] = INT_MAX;
+  __syncthreads();
+  for (int k = 2; k <= p2; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = lane; t < p2; t += 64) {
+        int q = t ^ j;
+        if (q > t) {
+          int x = cand[t], y = cand[q];
+          bool up = (t & k) == 0;
+          if ((x > y) == up) {
+            cand[t] = y;
+            cand[q] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  int m = 0;
+  for (int base = 0; base < p2; base += 64) {
+    int t = base + lane;
+    bool f = t < p2 && cand[t] != INT_MAX && (t == 0 || cand[t - 1] != cand[t]);
+    unsigned long long b = __ballot(f);
+    if (f) uniq[m + __popcll(b & lanes_below())] = cand[t];
+    m += __popcll(b);
+  }
+  for (int t = lane; t < m; t += 64) w[t] = 0.0;
+  __syncthreads();
+  // direct couplings; weak entries outside C^_i go to the diagonal
+  double aii = 0.0, lump = 0.0;
+  for (int e = a0 + lane; e < a1; e += 64) {
+    int j = ci[e];
+    if (j == i) {
+      aii = v[e];
+      continue;
+    }
+    int t = lds_find(uniq, m, j);
+    if (t >= 0)
+      w[t] += v[e];
+    else if (!(mask[e] && cf[j] == kF))
+      lump += v[e];
+  }
+  aii = wave_sum(aii);
+  lump = wave_sum(lump);
+  __syncthreads();
+  double extra = 0.0;  // uniform across lanes
+  for (int s = 0; s < nk; ++s) {
+    const int q0 = ko[s], q1 = ko[s + 1];
+    const double aik = ka[s];
+    const double sk = kdg[s] < 0.0 ? -1.0 : 1.0;
+    double d = 0.0;
+    for (int q = q0 + lane; q < q1; q += 64) {
+      int l = fcol[q];
+      double x = fval[q];
+      if (sk * x < 0.0 && (l == i || lds_find(uniq, m, l) >= 0)) d += x;
+    }
+    d = __shfl(wave_sum(d), 0, 64);
+    if (d == 0.0) {
+      extra += aik;
+      continue;
+    }
+    double toi = 0.0;
+    for (int q = q0 + lane; q < q1; q += 64) {
+      double x = fval[q];
+      if (!(sk * x < 0.0)) continue;
+      int l = fcol[q];
+      int t = lds_find(uniq, m, l);
+      if (t >= 0)
+        w[t] += aik * x / d;
+      else if (l == i)
+        toi += aik * x / d;
+    }
+    extra += __shfl(wave_sum(toi), 0, 64);
+    __syncthreads();
+  }
+  double atil = __shfl(aii + lump, 0, 64) + extra;
+  __syncthreads();
+  const int64_t o = toff[i];
+  for (int t = lane; t < m; t += 64) {
+    pci[o + t] = cidx[uniq[t]];
+    pv[o + t] = -w[t] / atil;
+  }
+  if (lane == 0) cnt[i] = m;
 }
 
 // appends the columns of entries e in [e0, e1) that pass the filter to buf
@@ -453,21 +700,13 @@ __device__ inline int wave_append_strong_c(int e0, int e1, const int* __restrict
   return len;
 }
 
-__device__ inline int lds_find(const int* u, int m, int key) {
-  int lo = 0, hi = m;
-  while (lo < hi) {
-    int mid = (lo + hi) >> 1;
-    if (u[mid] < key) lo = mid + 1;
-    else hi = mid;
-  }
-  return (lo < m && u[lo] == key) ? lo : -1;
-}
-
-template <bool FILL, int CAP>
-__global__ void __launch_bounds__(64) k_exti_wave(
+// Wide rows (many strong F neighbours or long neighbour rows): the same
+// weights with the neighbour rows read from global memory one at a time.
+template <int CAP>
+__global__ void __launch_bounds__(64) k_exti_wide(
     const int* __restrict__ rows, const int* __restrict__ rp, const int* __restrict__ ci,
     const double* __restrict__ v, const uint8_t* __restrict__ mask, const int8_t* __restrict__ cf,
-    const int* __restrict__ cidx, int* __restrict__ cnt, const int* __restrict__ prp,
+    const int* __restrict__ cidx, const int64_t* __restrict__ toff, int* __restrict__ cnt,
     int* __restrict__ pci, double* __restrict__ pv) {
   __shared__ int cand[CAP];
   __shared__ int uniq[CAP];
@@ -509,10 +748,6 @@ __global__ void __launch_bounds__(64) k_exti_wave(
     int pos = __popcll(b & ((1ull << lane) - 1ull));
     if (f) uniq[m + pos] = cand[t];
     m += __popcll(b);
-  }
-  if (!FILL) {
-    if (lane == 0) cnt[i] = m;
-    return;
   }
   for (int t = lane; t < m; t += 64) w[t] = 0.0;
   __syncthreads();
@@ -569,24 +804,23 @@ __global__ void __launch_bounds__(64) k_exti_wave(
   }
   double atil = __shfl(aii + lump, 0, 64) + extra;
   __syncthreads();
-  int o = prp[i];
+  const int64_t o = toff[i];
   for (int t = lane; t < m; t += 64) {
     pci[o + t] = cidx[uniq[t]];
     pv[o + t] = -w[t] / atil;
   }
+  if (lane == 0) cnt[i] = m;
 }
 
+
 __global__ void k_inject_c(int n, const int8_t* __restrict__ cf, const int* __restrict__ cidx,
-                           const int* __restrict__ prp, int* __restrict__ pci,
-                           double* __restrict__ pv, int* __restrict__ cnt) {
+                           const int64_t* __restrict__ toff, int* __restrict__ cnt,
+                           int* __restrict__ pci, double* __restrict__ pv) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n || cf[i] != kC) return;
-  if (cnt) {
-    cnt[i] = 1;
-    return;
-  }
-  pci[prp[i]] = cidx[i];
-  pv[prp[i]] = 1.0;
+  pci[toff[i]] = cidx[i];
+  pv[toff[i]] = 1.0;
+  cnt[i] = 1;
 }
 
 // dense [A | I] for Gauss-Jordan (row-major, n x 2n)
@@ -981,51 +1215,48 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
     L.P.ncols = int(nc);
     L.P.rp.alloc(n + 1, s);
     if (o.ext_i) {
-      Buf<int> ub(n, s), counts(3, s), lists(3 * int64_t(n), s);
-      fill_int(counts.p, 0, 3, s);
-      k_exti_ub<<<grid_for(n, 4), 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.mask.p, L.cf.p, ub.p);
+      Buf<int> ub(n, s), fl(n, s), nk(n, s), counts(4, s), lists(4 * int64_t(n), s);
+      fill_int(counts.p, 0, 4, s);
+      k_exti_ub<<<n, 64, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.mask.p, L.cf.p, ub.p, fl.p, nk.p);
       TPF_CHECK_LAUNCH();
-      k_exti_classify<<<grid_for(n, 256), 256, 0, s>>>(n, ub.p, L.cf.p, counts.p, lists.p);
+      k_exti_classify<<<grid_for(n, 256), 256, 0, s>>>(n, ub.p, fl.p, nk.p, L.cf.p, counts.p,
+                                                       lists.p);
       TPF_CHECK_LAUNCH();
-      int hc[3];
+      // single pass: rows staged at their candidate bound, then packed
+      Buf<int64_t> toff(size_t(n) + 1, s);
+      int64_t staged = scan_exclusive_wide(ub.p, toff.p, n, s);
+      int hc[4];
       TPF_HIP(hipMemcpyAsync(hc, counts.p, sizeof(hc), hipMemcpyDeviceToHost, s));
       TPF_HIP(hipStreamSynchronize(s));
+      Buf<int> tci(staged > 0 ? size_t(staged) : 1, s);
+      Buf<double> tv(staged > 0 ? size_t(staged) : 1, s);
       Buf<int2> cur;
-      if (hc[2] > 0) cur.alloc(L.A.nnz > 0 ? L.A.nnz : 1, s);
+      if (hc[3] > 0) cur.alloc(L.A.nnz > 0 ? L.A.nnz : 1, s);
       const int* l0 = lists.p;
       const int* l1 = lists.p + n;
       const int* l2 = lists.p + 2 * int64_t(n);
-      k_inject_c<<<grid_for(n, 256), 256, 0, s>>>(n, L.cf.p, cidx.p, nullptr, nullptr, nullptr, cnt.p);
+      const int* l3 = lists.p + 3 * int64_t(n);
+      k_inject_c<<<grid_for(n, 256), 256, 0, s>>>(n, L.cf.p, cidx.p, toff.p, cnt.p, tci.p, tv.p);
       if (hc[0] > 0)
-        k_exti_wave<false, kExtCap><<<hc[0], 64, 0, s>>>(l0, L.A.rp.p, L.A.ci.p, L.A.v.p, L.mask.p,
-                                                         L.cf.p, cidx.p, cnt.p, nullptr, nullptr,
-                                                         nullptr);
+        k_exti_flat<kExtCap0, kExtFlat0><<<hc[0], 64, 0, s>>>(l0, L.A.rp.p, L.A.ci.p, L.A.v.p,
+                                                              L.mask.p, L.cf.p, cidx.p, toff.p,
+                                                              cnt.p, tci.p, tv.p);
       if (hc[1] > 0)
-        k_exti_wave<false, kExtCap2><<<hc[1], 64, 0, s>>>(l1, L.A.rp.p, L.A.ci.p, L.A.v.p, L.mask.p,
-                                                          L.cf.p, cidx.p, cnt.p, nullptr, nullptr,
-                                                          nullptr);
+        k_exti_flat<kExtCap1, kExtFlat1><<<hc[1], 64, 0, s>>>(l1, L.A.rp.p, L.A.ci.p, L.A.v.p,
+                                                              L.mask.p, L.cf.p, cidx.p, toff.p,
+                                                              cnt.p, tci.p, tv.p);
       if (hc[2] > 0)
-        k_exti_count<<<grid_for(hc[2], 128), 128, 0, s>>>(hc[2], l2, L.A.rp.p, L.A.ci.p, L.mask.p,
-                                                          L.cf.p, cur.p, cnt.p);
+        k_exti_wide<kExtCap2><<<hc[2], 64, 0, s>>>(l2, L.A.rp.p, L.A.ci.p, L.A.v.p, L.mask.p,
+                                                   L.cf.p, cidx.p, toff.p, cnt.p, tci.p, tv.p);
+      if (hc[3] > 0)
+        k_exti_fill<<<grid_for(hc[3], 128), 128, 0, s>>>(hc[3], l3, L.A.rp.p, L.A.ci.p, L.A.v.p,
+                                                         L.mask.p, L.cf.p, cidx.p, cur.p, toff.p,
+                                                         cnt.p, tci.p, tv.p);
       TPF_CHECK_LAUNCH();
       L.P.nnz = scan_exclusive(cnt.p, L.P.rp.p, n, s);
-      L.P.ci.alloc(L.P.nnz, s);
-      L.P.v.alloc(L.P.nnz, s);
-      k_inject_c<<<grid_for(n, 256), 256, 0, s>>>(n, L.cf.p, cidx.p, L.P.rp.p, L.P.ci.p, L.P.v.p,
-                                                  nullptr);
-      if (hc[0] > 0)
-        k_exti_wave<true, kExtCap><<<hc[0], 64, 0, s>>>(l0, L.A.rp.p, L.A.ci.p, L.A.v.p, L.mask.p,
-                                                        L.cf.p, cidx.p, nullptr, L.P.rp.p, L.P.ci.p,
-                                                        L.P.v.p);
-      if (hc[1] > 0)
-        k_exti_wave<true, kExtCap2><<<hc[1], 64, 0, s>>>(l1, L.A.rp.p, L.A.ci.p, L.A.v.p, L.mask.p,
-                                                         L.cf.p, cidx.p, nullptr, L.P.rp.p,
-                                                         L.P.ci.p, L.P.v.p);
-      if (hc[2] > 0)
-        k_exti_fill<<<grid_for(hc[2], 128), 128, 0, s>>>(hc[2], l2, L.A.rp.p, L.A.ci.p, L.A.v.p,
-                                                         L.mask.p, L.cf.p, cidx.p, cur.p, L.P.rp.p,
-                                                         L.P.ci.p, L.P.v.p);
-      TPF_CHECK_LAUNCH();
+      L.P.ci.alloc(L.P.nnz > 0 ? L.P.nnz : 1, s);
+      L.P.v.alloc(L.P.nnz > 0 ? L.P.nnz : 1, s);
+      pack_rows(n, toff.p, L.P.rp.p, L.P.nnz, tci.p, tv.p, L.P.ci.p, L.P.v.p, s);
     } else {
       k_interp_count<<<grid_for(n, 256), 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.mask.p, L.cf.p,
                                                       cnt.p);

@@ -222,6 +222,37 @@ double nrm2_host(const double* x, int64_t n, hipStream_t s) {
   return read_scalar(part.p + kRedBlocks, s);
 }
 
+// ---------------------------------------------------------------- staged rows
+namespace {
+template <int LPR>
+__global__ void __launch_bounds__(256) k_pack_rows(int n, const int64_t* __restrict__ toff,
+                                                   const int* __restrict__ crp,
+                                                   const int* __restrict__ tci,
+                                                   const double* __restrict__ tv,
+                                                   int* __restrict__ cci, double* __restrict__ cv) {
+  int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int i = int(gid / LPR), lane = int(gid % LPR);
+  if (i >= n) return;
+  int64_t src = toff[i];
+  int c0 = crp[i], len = crp[i + 1] - c0;
+  for (int t = lane; t < len; t += LPR) {
+    cci[c0 + t] = tci[src + t];
+    cv[c0 + t] = tv[src + t];
+  }
+}
+}  // namespace
+
+void pack_rows(int n, const int64_t* toff, const int* crp, int64_t nnz, const int* tci,
+               const double* tv, int* cci, double* cv, hipStream_t s) {
+  if (n <= 0) return;
+  const int lpr = lanes_per_row(n, nnz);
+  DISPATCH_LPR(lpr, LL, {
+    k_pack_rows<LL><<<grid_for(int64_t(n) * lpr, 256), 256, 0, s>>>(n, toff, crp, tci, tv, cci,
+                                                                     cv);
+  });
+  TPF_CHECK_LAUNCH();
+}
+
 // ---------------------------------------------------------------- CSR row kernels
 namespace {
 template <class T, int LPR>

@@ -451,25 +451,6 @@ __global__ void __launch_bounds__(64) k_sort_rows(int nrows, const int* __restri
   }
 }
 
-// moves each row's staged entries to their packed position
-template <int LPR>
-__global__ void __launch_bounds__(256) k_spgemm_pack(int n, const int64_t* __restrict__ toff,
-                                                     const int* __restrict__ crp,
-                                                     const int* __restrict__ tci,
-                                                     const double* __restrict__ tv,
-                                                     int* __restrict__ cci,
-                                                     double* __restrict__ cv) {
-  int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  int i = int(gid / LPR), lane = int(gid % LPR);
-  if (i >= n) return;
-  int64_t src = toff[i];
-  int c0 = crp[i], len = crp[i + 1] - c0;
-  for (int t = lane; t < len; t += LPR) {
-    cci[c0 + t] = tci[src + t];
-    cv[c0 + t] = tv[src + t];
-  }
-}
-
 }  // namespace
 
 void spgemm(const CsrRef<double>& A, const CsrRef<double>& B, Csr<double>& C, hipStream_t s,
@@ -554,12 +535,7 @@ void spgemm(const CsrRef<double>& A, const CsrRef<double>& B, Csr<double>& C, hi
   C.nnz = scan_exclusive(cnt.p, C.rp.p, n, s);
   C.ci.alloc(C.nnz > 0 ? C.nnz : 1, s);
   C.v.alloc(C.nnz > 0 ? C.nnz : 1, s);
-  const int lpr = lanes_per_row(n, C.nnz);
-  DISPATCH_LPR(lpr, LL, {
-    k_spgemm_pack<LL><<<grid_for(int64_t(n) * lpr, 256), 256, 0, s>>>(n, toff.p, C.rp.p, tci.p,
-                                                                      tv.p, C.ci.p, C.v.p);
-  });
-  TPF_CHECK_LAUNCH();
+  pack_rows(n, toff.p, C.rp.p, C.nnz, tci.p, tv.p, C.ci.p, C.v.p, s);
 }
 
 void transpose(const CsrRef<double>& A, Csr<double>& C, hipStream_t s) {

@@ -169,6 +169,10 @@ int64_t scan_exclusive(const int* in, int* out, int64_t n, hipStream_t s);
 int64_t scan_exclusive64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);
 // int counts into 64-bit offsets out[0..n] (no overflow check needed)
 int64_t scan_exclusive_wide(const int* in, int64_t* out, int64_t n, hipStream_t s);
+// Rows built in a staging area (row i at toff[i]) moved to packed CSR
+// storage with row pointers crp (nnz entries in total).
+void pack_rows(int n, const int64_t* toff, const int* crp, int64_t nnz, const int* tci,
+               const double* tv, int* cci, double* cv, hipStream_t s);
 void fill_int(int* p, int v, int64_t n, hipStream_t s);
 template <class T> void fill(T* p, T v, int64_t n, hipStream_t s);
 template <class T> void copy(T* dst, const T* src, int64_t n, hipStream_t s);
