@@ -1224,10 +1224,11 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
       TPF_CHECK_LAUNCH();
       // single pass: rows staged at their candidate bound, then packed
       Buf<int64_t> toff(size_t(n) + 1, s);
-      int64_t staged = scan_exclusive_wide(ub.p, toff.p, n, s);
+      int* hc_pinned = host_counts_slot();
+      TPF_HIP(hipMemcpyAsync(hc_pinned, counts.p, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+      int64_t staged = scan_exclusive_wide(ub.p, toff.p, n, s);  // synchronises
       int hc[4];
-      TPF_HIP(hipMemcpyAsync(hc, counts.p, sizeof(hc), hipMemcpyDeviceToHost, s));
-      TPF_HIP(hipStreamSynchronize(s));
+      std::memcpy(hc, hc_pinned, sizeof(hc));
       Buf<int> tci(staged > 0 ? size_t(staged) : 1, s);
       Buf<double> tv(staged > 0 ? size_t(staged) : 1, s);
       Buf<int2> cur;

@@ -61,56 +61,66 @@ void scan_rec(const In* in, T* out, int64_t n, hipStream_t s) {
 }
 }  // namespace
 
+namespace {
+// total = tmp[n-1] + in[n-1] into out[n] and *tot; optionally out[i] = tmp[i]
+// narrowed (out != tmp)
+template <class T, class In, class Out>
+__global__ void k_scan_finish(const T* __restrict__ tmp, const In* __restrict__ in, int64_t n,
+                              Out* __restrict__ out, bool narrow, int64_t* __restrict__ tot) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (narrow)
+    for (; i < n; i += int64_t(gridDim.x) * blockDim.x) out[i] = Out(tmp[i]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    int64_t t = int64_t(tmp[n - 1]) + int64_t(in[n - 1]);
+    out[n] = Out(t);
+    *tot = t;
+  }
+}
+
+// reads the 64-bit total written by k_scan_finish (one round trip)
+int64_t read_total(const int64_t* tot, hipStream_t s) { return read_scalar(tot, s); }
+}  // namespace
+
 int64_t scan_exclusive(const int* in, int* out, int64_t n, hipStream_t s) {
   // totals are accumulated in 64-bit to detect overflow of the int32 output
   if (n == 0) {
     fill_int(out, 0, 1, s);
     return 0;
   }
-  Buf<int64_t> tmp(n, s);
+  Buf<int64_t> tmp(n + 1, s);
   scan_rec<int64_t, int>(in, tmp.p, n, s);
-  int64_t last_excl = read_scalar(tmp.p + n - 1, s);
-  int last_in = read_scalar(in + n - 1, s);
-  int64_t total = last_excl + last_in;
+  unsigned g = grid_for(n, 256);
+  k_scan_finish<int64_t, int, int><<<g > 4096 ? 4096 : g, 256, 0, s>>>(tmp.p, in, n, out, true,
+                                                                         tmp.p + n);
+  TPF_CHECK_LAUNCH();
+  int64_t total = read_total(tmp.p + n, s);
   TPF_REQUIRE(total < (int64_t(1) << 31), TPF_ERR_INVALID_ARG,
               "index count %lld exceeds the int32 range", (long long)total);
-  cast<int64_t, int>(out, tmp.p, n, s);
-  int t32 = int(total);
-  TPF_HIP(hipMemcpyAsync(out + n, &t32, sizeof(int), hipMemcpyHostToDevice, s));
-  TPF_HIP(hipStreamSynchronize(s));
   return total;
 }
 
 int64_t scan_exclusive_wide(const int* in, int64_t* out, int64_t n, hipStream_t s) {
   if (n == 0) {
-    int64_t z = 0;
-    TPF_HIP(hipMemcpyAsync(out, &z, sizeof(z), hipMemcpyHostToDevice, s));
-    TPF_HIP(hipStreamSynchronize(s));
+    fill(out, int64_t(0), 1, s);
     return 0;
   }
+  Buf<int64_t> tot(1, s);
   scan_rec<int64_t, int>(in, out, n, s);
-  int64_t last_excl = read_scalar(out + n - 1, s);
-  int last_in = read_scalar(in + n - 1, s);
-  int64_t total = last_excl + last_in;
-  TPF_HIP(hipMemcpyAsync(out + n, &total, sizeof(total), hipMemcpyHostToDevice, s));
-  TPF_HIP(hipStreamSynchronize(s));
-  return total;
+  k_scan_finish<int64_t, int, int64_t><<<1, 64, 0, s>>>(out, in, n, out, false, tot.p);
+  TPF_CHECK_LAUNCH();
+  return read_total(tot.p, s);
 }
 
 int64_t scan_exclusive64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s) {
   if (n == 0) {
-    int64_t z = 0;
-    TPF_HIP(hipMemcpyAsync(out, &z, sizeof(z), hipMemcpyHostToDevice, s));
-    TPF_HIP(hipStreamSynchronize(s));
+    fill(out, int64_t(0), 1, s);
     return 0;
   }
+  Buf<int64_t> tot(1, s);
   scan_rec<int64_t, int64_t>(in, out, n, s);
-  int64_t last_excl = read_scalar(out + n - 1, s);
-  int64_t last_in = read_scalar(in + n - 1, s);
-  int64_t total = last_excl + last_in;
-  TPF_HIP(hipMemcpyAsync(out + n, &total, sizeof(total), hipMemcpyHostToDevice, s));
-  TPF_HIP(hipStreamSynchronize(s));
-  return total;
+  k_scan_finish<int64_t, int64_t, int64_t><<<1, 64, 0, s>>>(out, in, n, out, false, tot.p);
+  TPF_CHECK_LAUNCH();
+  return read_total(tot.p, s);
 }
 
 // ---------------------------------------------------------------- fills / copies / casts

@@ -14,6 +14,8 @@
 // wavefronts ix+iy+iz = const, whose cells are mutually independent.
 #include <algorithm>
 #include <cstdlib>
+#include <exception>
+#include <thread>
 #include <type_traits>
 
 #include "linalg_dev.hpp"
@@ -454,6 +456,50 @@ size_t tpf_precond::bytes() const {
   return b;
 }
 
+tpf_precond::~tpf_precond() {
+  H[0].reset();  // hierarchy buffers are released before their stream goes
+  H[1].reset();
+  if (aux_ev) (void)hipEventDestroy(aux_ev);
+  if (aux) (void)hipStreamDestroy(aux);
+}
+
+namespace {
+// Runs a(aux) on a second host thread, with its own stream that first waits
+// for everything queued on s, and b(s) on this thread; returns when both are
+// done (a's stream drained) and rethrows the first failure.
+template <class A, class B>
+void run_pair(tpf_precond* M, hipStream_t s, A&& a, B&& b) {
+  if (!M->aux) {
+    TPF_HIP(hipStreamCreateWithFlags(&M->aux, hipStreamNonBlocking));
+    TPF_HIP(hipEventCreateWithFlags(&M->aux_ev, hipEventDisableTiming));
+  }
+  TPF_HIP(hipEventRecord(M->aux_ev, s));
+  TPF_HIP(hipStreamWaitEvent(M->aux, M->aux_ev, 0));
+  int dev = 0;
+  TPF_HIP(hipGetDevice(&dev));
+  hipStream_t aux = M->aux;
+  std::exception_ptr err_a, err_b;
+  std::thread worker([&] {
+    try {
+      TPF_HIP(hipSetDevice(dev));
+      a(aux);
+      TPF_HIP(hipStreamSynchronize(aux));
+    } catch (...) {
+      err_a = std::current_exception();
+      (void)hipStreamSynchronize(aux);
+    }
+  });
+  try {
+    b(s);
+  } catch (...) {
+    err_b = std::current_exception();
+  }
+  worker.join();
+  if (err_b) std::rethrow_exception(err_b);
+  if (err_a) std::rethrow_exception(err_a);
+}
+}  // namespace
+
 extern "C" {
 
 int tpf_precond_default_opts(int kind, tpf_precond_opts* o) {
@@ -493,6 +539,8 @@ int tpf_precond_create(const tpf_precond_opts* o, tpf_precond** out) {
 int tpf_precond_destroy(tpf_precond* M) {
   return guarded([&] { delete M; });
 }
+
+
 
 int tpf_precond_setup(tpf_precond* M, const tpf_jacobian* J, int reuse, void* stream) {
   return guarded([&] {
@@ -558,19 +606,26 @@ int tpf_precond_setup(tpf_precond* M, const tpf_jacobian* J, int reuse, void* st
       }
     } else if (kind == TPF_PREC_CPR1 || kind == TPF_PREC_CPR2) {
       M->n_hier = kind == TPF_PREC_CPR2 ? 2 : 1;
-      bilu_setup(M, re, s);
       const double* src[2] = {M->app_v.p, M->ass_v.p};
-      for (int h = 0; h < M->n_hier; ++h) {
+      auto hier = [&](int h, hipStream_t hs) {
         if (!re) {
-          M->H[h] = std::make_unique<Hierarchy>();
-          M->H[h]->tag = h == 0 ? "App" : "Ass";
-          M->H[h]->stencil = stencil_offsets(J->prob->ph, 1);
-          M->H[h]->build(block_copy(M, src[h], s), h == 0 ? ao_p : ao_s, s);
+          auto H = std::make_unique<Hierarchy>();
+          H->tag = h == 0 ? "App" : "Ass";
+          H->stencil = stencil_offsets(J->prob->ph, 1);
+          H->build(block_copy(M, src[h], hs), h == 0 ? ao_p : ao_s, hs);
+          M->H[h] = std::move(H);
         } else {
-          copy(M->H[h]->A0().v.p, src[h], nnzb, s);
-          M->H[h]->refresh(s);
+          copy(M->H[h]->A0().v.p, src[h], nnzb, hs);
+          M->H[h]->refresh(hs);
         }
-      }
+      };
+      // the A_pp hierarchy on a second stream; block ILU(0) and A_ss here
+      run_pair(
+          M, s, [&](hipStream_t as) { hier(0, as); },
+          [&](hipStream_t ms) {
+            bilu_setup(M, re, ms);
+            if (M->n_hier == 2) hier(1, ms);
+          });
     } else {  // BF
       M->n_hier = 2;
       M->ass_dinv.ensure(N, s);
@@ -584,23 +639,35 @@ int tpf_precond_setup(tpf_precond* M, const tpf_jacobian* J, int reuse, void* st
       CsrRef<double> Y{N, N, nnzb, M->brp.p, M->bci.p, M->y_v.p};
       CsrRef<double> Asp{N, N, nnzb, M->brp.p, M->bci.p, M->asp_v.p};
       CsrRef<double> App{N, N, nnzb, M->brp.p, M->bci.p, M->app_v.p};
-      if (!re) {
-        M->H[0] = std::make_unique<Hierarchy>();
-        M->H[0]->tag = "Ass";
-        M->H[0]->stencil = stencil_offsets(J->prob->ph, 1);
-        M->H[0]->build(block_copy(M, M->ass_v.p, s), ao_s, s);
-        Csr<double> S;
-        spgemm(Y, Asp, S, s, &App, -1.0, 1.0, false);
-        M->H[1] = std::make_unique<Hierarchy>();
-        M->H[1]->tag = "Schur";
-        M->H[1]->stencil = stencil_offsets(J->prob->ph, 2);
-        M->H[1]->build(std::move(S), ao_p, s);
-      } else {
-        copy(M->H[0]->A0().v.p, M->ass_v.p, nnzb, s);
-        M->H[0]->refresh(s);
-        spgemm(Y, Asp, M->H[1]->A0(), s, &App, -1.0, 1.0, true);
-        M->H[1]->refresh(s);
-      }
+      // the A_ss hierarchy on a second stream, S~ and its hierarchy here
+      run_pair(
+          M, s,
+          [&](hipStream_t as) {
+            if (!re) {
+              auto H = std::make_unique<Hierarchy>();
+              H->tag = "Ass";
+              H->stencil = stencil_offsets(J->prob->ph, 1);
+              H->build(block_copy(M, M->ass_v.p, as), ao_s, as);
+              M->H[0] = std::move(H);
+            } else {
+              copy(M->H[0]->A0().v.p, M->ass_v.p, nnzb, as);
+              M->H[0]->refresh(as);
+            }
+          },
+          [&](hipStream_t ms) {
+            if (!re) {
+              Csr<double> S;
+              spgemm(Y, Asp, S, ms, &App, -1.0, 1.0, false);
+              auto H = std::make_unique<Hierarchy>();
+              H->tag = "Schur";
+              H->stencil = stencil_offsets(J->prob->ph, 2);
+              H->build(std::move(S), ao_p, ms);
+              M->H[1] = std::move(H);
+            } else {
+              spgemm(Y, Asp, M->H[1]->A0(), ms, &App, -1.0, 1.0, true);
+              M->H[1]->refresh(ms);
+            }
+          });
     }
     TPF_HIP(hipStreamSynchronize(s));
     M->ready = true;

@@ -26,5 +26,9 @@ struct tpf_precond {
   // workspaces
   tpf::Buf<double> w1, w2, w3, w4, u2, r2;   // N or 2N
   tpf::Buf<float> f1, f2, f3, f4, fu, fr;
+  // second stream (and host thread) for building two hierarchies at once
+  hipStream_t aux = nullptr;
+  hipEvent_t aux_ev = nullptr;
   size_t bytes() const;
+  ~tpf_precond();
 };

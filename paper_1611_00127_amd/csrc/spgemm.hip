@@ -494,10 +494,11 @@ void spgemm(const CsrRef<double>& A, const CsrRef<double>& B, Csr<double>& C, hi
   // one pass: each row writes its sorted unique entries at its upper-bound
   // offset in a staging area, then the rows are packed
   Buf<int64_t> toff(size_t(n) + 1, s);
-  int64_t staged = scan_exclusive_wide(ub.p, toff.p, n, s);
+  int* hc_pinned = host_counts_slot();
+  TPF_HIP(hipMemcpyAsync(hc_pinned, counts.p, kClasses * sizeof(int), hipMemcpyDeviceToHost, s));
+  int64_t staged = scan_exclusive_wide(ub.p, toff.p, n, s);  // synchronises: counts arrived
   int hc[kClasses];
-  TPF_HIP(hipMemcpyAsync(hc, counts.p, sizeof(hc), hipMemcpyDeviceToHost, s));
-  TPF_HIP(hipStreamSynchronize(s));
+  std::memcpy(hc, hc_pinned, sizeof(hc));
   Buf<int> tci(staged > 0 ? size_t(staged) : 1, s);
   Buf<double> tv(staged > 0 ? size_t(staged) : 1, s);
   Buf<int2> cur;

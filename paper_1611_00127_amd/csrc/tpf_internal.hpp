@@ -110,6 +110,11 @@ struct HostScratch {
   }
 };
 HostScratch& host_scratch();
+// pinned slot for small arrays read back together with a later scalar read
+// (bytes 1024..4095 of the calling thread's scratch; read_scalar uses the start)
+inline int* host_counts_slot() {
+  return reinterpret_cast<int*>(host_scratch().get<char>(4096) + 1024);
+}
 
 template <class T>
 T read_scalar(const T* dptr, hipStream_t s) {
