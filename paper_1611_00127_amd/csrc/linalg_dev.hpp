@@ -66,13 +66,25 @@ __device__ inline T block_exclusive_scan(T v, T* sh, T& total) {
 }
 
 // Dot of CSR row `row` with gathered values g(col); LPR consecutive lanes
-// share the row; result valid in the group's first lane.
+// share the row, each lane summing entries lane, lane + LPR, ... in order
+// (loads issued four entries ahead); result valid in the group's first lane.
 template <class T, int LPR, class G>
 __device__ inline T row_dot(int row, int lane, const int* __restrict__ rp,
                             const int* __restrict__ ci, const T* __restrict__ v, G g) {
   T sum = T(0);
-  int e1 = rp[row + 1];
-  for (int e = rp[row] + lane; e < e1; e += LPR) sum += v[e] * g(ci[e]);
+  const int e1 = rp[row + 1];
+  int e = rp[row] + lane;
+  for (; e + 3 * LPR < e1; e += 4 * LPR) {
+    T p0 = v[e] * g(ci[e]);
+    T p1 = v[e + LPR] * g(ci[e + LPR]);
+    T p2 = v[e + 2 * LPR] * g(ci[e + 2 * LPR]);
+    T p3 = v[e + 3 * LPR] * g(ci[e + 3 * LPR]);
+    sum += p0;
+    sum += p1;
+    sum += p2;
+    sum += p3;
+  }
+  for (; e < e1; e += LPR) sum += v[e] * g(ci[e]);
 #pragma unroll
   for (int off = LPR / 2; off > 0; off >>= 1) sum += __shfl_down(sum, off, LPR);
   return sum;
@@ -122,10 +134,11 @@ __device__ inline unsigned long long group_ballot(bool f) {
   }
 }
 
+// Lanes per row for the CSR row kernels: about four entries per lane.
 inline int lanes_per_row(int64_t nrows, int64_t nnz) {
   double avg = nrows ? double(nnz) / double(nrows) : 1.0;
   int l = 1;
-  while (l < 64 && l < avg) l <<= 1;
+  while (l < 64 && 4 * l < avg) l <<= 1;
   return l;
 }
 
