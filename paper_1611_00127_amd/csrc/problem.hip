@@ -13,6 +13,7 @@
 #include <cmath>
 #include <map>
 
+#include "linalg_dev.hpp"
 #include "problem.hpp"
 
 namespace tpf {
@@ -345,35 +346,46 @@ __global__ void k_newton_update(int64_t N, double* u, const double* du, double d
 }
 
 // ------------------------------------------------------------ BCSR SpMV
-// y_i = sum_e B_e x_{col(e)}, one thread per block row.
+// y_i = sum_e B_e x_{col(e)} (or b_i minus it): eight lanes per block row,
+// lane k taking blocks k, k + 8, ... so that a wavefront reads eight rows'
+// blocks as one contiguous stretch; the lanes' partial sums are combined by
+// an xor butterfly.
+constexpr int kBcsrLanes = 8;
 __global__ void __launch_bounds__(256) k_bcsr_spmv(int nb, const int* __restrict__ rp,
                                                    const int* __restrict__ ci,
                                                    const double* __restrict__ v,
                                                    const double* __restrict__ x,
                                                    const double* __restrict__ b,
                                                    double* __restrict__ y) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nb) return;
+  int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int i = int(gid / kBcsrLanes), lane = int(gid % kBcsrLanes);
   double y0 = 0.0, y1 = 0.0;
-  for (int e = rp[i]; e < rp[i + 1]; ++e) {
-    int j = ci[e];
-    double2 xj = reinterpret_cast<const double2*>(x)[j];
-    const double2* blk = reinterpret_cast<const double2*>(v + 4 * int64_t(e));
-    double2 r0 = blk[0], r1 = blk[1];
-    y0 += r0.x * xj.x + r0.y * xj.y;
-    y1 += r1.x * xj.x + r1.y * xj.y;
+  if (i < nb) {
+    for (int e = rp[i] + lane; e < rp[i + 1]; e += kBcsrLanes) {
+      int j = ci[e];
+      double2 xj = reinterpret_cast<const double2*>(x)[j];
+      const double2* blk = reinterpret_cast<const double2*>(v + 4 * int64_t(e));
+      double2 r0 = blk[0], r1 = blk[1];
+      y0 += r0.x * xj.x + r0.y * xj.y;
+      y1 += r1.x * xj.x + r1.y * xj.y;
+    }
   }
-  if (b) {
-    y0 = b[2 * i] - y0;
-    y1 = b[2 * i + 1] - y1;
+  y0 = group_sum<kBcsrLanes>(y0);
+  y1 = group_sum<kBcsrLanes>(y1);
+  if (i < nb && lane == 0) {
+    if (b) {
+      y0 = b[2 * i] - y0;
+      y1 = b[2 * i + 1] - y1;
+    }
+    reinterpret_cast<double2*>(y)[i] = make_double2(y0, y1);
   }
-  reinterpret_cast<double2*>(y)[i] = make_double2(y0, y1);
 }
 
 void bcsr_apply(const tpf_jacobian* J, const double* x, const double* b, double* y,
                 hipStream_t s) {
   TimedScope ts("bcsr_spmv", s);
-  k_bcsr_spmv<<<grid_for(J->nb, 256), 256, 0, s>>>(J->nb, J->rp.p, J->ci.p, J->v.p, x, b, y);
+  k_bcsr_spmv<<<grid_for(int64_t(J->nb) * kBcsrLanes, 256), 256, 0, s>>>(J->nb, J->rp.p, J->ci.p,
+                                                                         J->v.p, x, b, y);
   TPF_CHECK_LAUNCH();
 }
 
