@@ -63,7 +63,7 @@ def level0_bytes(nnz, n, w, kind, diagonals=0):
     the operator once (diagonal layout: K*n values; CSR: values, int32
     column indices and row pointers) and each dense vector once."""
     mat = w * diagonals * n if diagonals else (w + 4) * nnz + 4 * (n + 1)
-    if kind == "pre":      # read b, dinv; write r (A D^{-1} b gathered)
+    if kind == "pre":      # read b and D^{-1} b (CSR: dinv); write r
         return mat + 3 * w * n
     if kind == "post":     # read b, dinv, y; write x
         return mat + 4 * w * n
@@ -325,8 +325,11 @@ def main():
     bytes_per_launch = level0_bytes(nnz, n, 8, kind, r64["l0_diagonals"][h])
     avg_ms = ms / cnt
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    roof = {"kernel": dom, "layout": (f"diagonal, {r64['l0_diagonals'][h]} diagonals"
-                                      if r64["l0_diagonals"][h] else "csr"),
+    K = r64["l0_diagonals"][h]
+    gpu_kernel = (f"k_dia_{kind}{'2' if n % 2 == 0 else ''}<double, {K}>" if K
+                  else f"k_vc_{kind}<double, *>")
+    roof = {"kernel": gpu_kernel, "timer": dom,
+            "layout": f"diagonal, {K} diagonals" if K else "csr",
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "avg_launch_us": round(avg_ms * 1e3, 2), "launches": cnt,

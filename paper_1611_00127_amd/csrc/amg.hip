@@ -1092,20 +1092,91 @@ __global__ void k_csr_to_dia(int n, const int* __restrict__ rp, const int* __res
 
 __device__ inline int clampi(int j, int n) { return j < 0 ? 0 : (j >= n ? n - 1 : j); }
 
-// r = b - A (D^{-1} b)
+// Work-groups are handed to the eight XCDs round-robin (group b to XCD
+// b % 8).  This renumbering gives each XCD a contiguous eighth of the
+// groups, so the neighbouring rows a stencil row gathers from sit in the
+// same XCD's L2.  It is a bijection on [0, gridDim.x).
+__device__ inline int xcd_contiguous_block() {
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int q = nb / 8, r = nb % 8;
+  const int x = b % 8, t = b / 8;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + t;
+}
+
+// g = D^{-1} b (the pre-smoothed iterate from a zero guess)
+template <class T>
+__global__ void __launch_bounds__(256) k_jacobi_guess(int n, const T* __restrict__ dinv,
+                                                      const T* __restrict__ b,
+                                                      T* __restrict__ g) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) g[i] = dinv[i] * b[i];
+}
+
+// r = b - A g with g = D^{-1} b
 template <class T, int K>
 __global__ void __launch_bounds__(256) k_dia_pre(int n, DiagOffs o, const T* __restrict__ v,
-                                                 const T* __restrict__ dinv,
+                                                 const T* __restrict__ g,
                                                  const T* __restrict__ b, T* __restrict__ r) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int i = xcd_contiguous_block() * blockDim.x + threadIdx.x;
   if (i >= n) return;
   T sum = T(0);
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     int j = clampi(i + o.off[k], n);
-    sum += v[int64_t(k) * n + i] * (dinv[j] * b[j]);
+    sum += v[int64_t(k) * n + i] * g[j];
   }
   r[i] = b[i] - sum;
+}
+
+template <class T> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
+
+// Two rows per thread (n even): the diagonals and the row vectors are read
+// as pairs.  Same sums, in the same order, as the one-row kernels.
+template <class T, int K>
+__global__ void __launch_bounds__(256) k_dia_pre2(int n, DiagOffs o, const T* __restrict__ v,
+                                                  const T* __restrict__ g,
+                                                  const T* __restrict__ b, T* __restrict__ r) {
+  using T2 = typename Vec2<T>::type;
+  int i = 2 * (xcd_contiguous_block() * blockDim.x + threadIdx.x);
+  if (i >= n) return;
+  T s0 = T(0), s1 = T(0);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    T2 a = *reinterpret_cast<const T2*>(v + int64_t(k) * n + i);
+    s0 += a.x * g[clampi(i + o.off[k], n)];
+    s1 += a.y * g[clampi(i + 1 + o.off[k], n)];
+  }
+  T2 bb = *reinterpret_cast<const T2*>(b + i);
+  T2 out;
+  out.x = bb.x - s0;
+  out.y = bb.y - s1;
+  *reinterpret_cast<T2*>(r + i) = out;
+}
+
+template <class T, int K>
+__global__ void __launch_bounds__(256) k_dia_post2(int n, DiagOffs o, const T* __restrict__ v,
+                                                   const T* __restrict__ dinv,
+                                                   const T* __restrict__ b,
+                                                   const T* __restrict__ y, T* __restrict__ x) {
+  using T2 = typename Vec2<T>::type;
+  int i = 2 * (xcd_contiguous_block() * blockDim.x + threadIdx.x);
+  if (i >= n) return;
+  T s0 = T(0), s1 = T(0);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    T2 a = *reinterpret_cast<const T2*>(v + int64_t(k) * n + i);
+    s0 += a.x * y[clampi(i + o.off[k], n)];
+    s1 += a.y * y[clampi(i + 1 + o.off[k], n)];
+  }
+  T2 yy = *reinterpret_cast<const T2*>(y + i);
+  T2 dd = *reinterpret_cast<const T2*>(dinv + i);
+  T2 bb = *reinterpret_cast<const T2*>(b + i);
+  T2 out;
+  out.x = yy.x + dd.x * (bb.x - s0);
+  out.y = yy.y + dd.y * (bb.y - s1);
+  *reinterpret_cast<T2*>(x + i) = out;
 }
 
 // x = y + D^{-1} (b - A y)
@@ -1114,7 +1185,7 @@ __global__ void __launch_bounds__(256) k_dia_post(int n, DiagOffs o, const T* __
                                                   const T* __restrict__ dinv,
                                                   const T* __restrict__ b,
                                                   const T* __restrict__ y, T* __restrict__ x) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int i = xcd_contiguous_block() * blockDim.x + threadIdx.x;
   if (i >= n) return;
   T sum = T(0);
 #pragma unroll
@@ -1295,6 +1366,7 @@ void Hierarchy::finish_levels(hipStream_t st) {
     int n = L.A.nrows;
     std::string sfx = "[" + tag + ",l" + std::to_string(l) + "]";
     L.t_pre = "vcycle_pre_residual" + sfx;
+    L.t_guess = "vcycle_jacobi_guess" + sfx;
     L.t_restrict = "vcycle_restrict" + sfx;
     L.t_prolong = "vcycle_prolong" + sfx;
     L.t_post = "vcycle_post_smooth" + sfx;
@@ -1433,6 +1505,9 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st) {
   T* bc = work<T>(C.b, C.b32);
   T* xc = work<T>(C.x, C.x32);
   bool dia = l == 0 && dia0.ok;
+  // the two-row diagonal kernels read pairs: n even and every vector aligned
+  auto al2 = [](const void* p) { return reinterpret_cast<uintptr_t>(p) % (2 * sizeof(T)) == 0; };
+  const bool pairs = n % 2 == 0 && al2(b) && al2(x) && al2(r) && al2(y) && al2(dinv);
   DiagOffs doff;
   const T* dv = nullptr;
   if (dia) {
@@ -1442,12 +1517,24 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st) {
     else
       dv = dia0.v.p;
   }
+  if (dia) {
+    // y holds D^{-1} b until the prolongation overwrites it
+    TimedScope ts(L.t_guess.c_str(), st);
+    k_jacobi_guess<T><<<grid_for(n, 256), 256, 0, st>>>(n, dinv, b, y);
+    TPF_CHECK_LAUNCH();
+  }
   {
     TimedScope ts(L.t_pre.c_str(), st);
     if (dia) {
-      DISPATCH_DIAG(dia0.K, KK, {
-        k_dia_pre<T, KK><<<grid_for(n, 256), 256, 0, st>>>(n, doff, dv, dinv, b, r);
-      });
+      if (pairs) {
+        DISPATCH_DIAG(dia0.K, KK, {
+          k_dia_pre2<T, KK><<<grid_for(n / 2, 256), 256, 0, st>>>(n, doff, dv, y, b, r);
+        });
+      } else {
+        DISPATCH_DIAG(dia0.K, KK, {
+          k_dia_pre<T, KK><<<grid_for(n, 256), 256, 0, st>>>(n, doff, dv, y, b, r);
+        });
+      }
     } else {
       DISPATCH_LPR(lpr, LL, {
         k_vc_pre<T, LL><<<blocks, 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, Av, dinv, b, r);
@@ -1469,9 +1556,15 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st) {
   {
     TimedScope ts(L.t_post.c_str(), st);
     if (dia) {
-      DISPATCH_DIAG(dia0.K, KK, {
-        k_dia_post<T, KK><<<grid_for(n, 256), 256, 0, st>>>(n, doff, dv, dinv, b, y, x);
-      });
+      if (pairs) {
+        DISPATCH_DIAG(dia0.K, KK, {
+          k_dia_post2<T, KK><<<grid_for(n / 2, 256), 256, 0, st>>>(n, doff, dv, dinv, b, y, x);
+        });
+      } else {
+        DISPATCH_DIAG(dia0.K, KK, {
+          k_dia_post<T, KK><<<grid_for(n, 256), 256, 0, st>>>(n, doff, dv, dinv, b, y, x);
+        });
+      }
     } else {
       DISPATCH_LPR(lpr, LL, {
         k_vc_post<T, LL><<<blocks, 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, Av, dinv, b, y, x);

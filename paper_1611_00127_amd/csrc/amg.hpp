@@ -31,7 +31,7 @@ struct Level {
   Buf<float> r32, y32, b32, x32;
   int64_t pmis_rounds = 0;
   // kernel-timer labels of this level (persistent storage for TimedScope)
-  std::string t_pre, t_restrict, t_prolong, t_post;
+  std::string t_pre, t_guess, t_restrict, t_prolong, t_post;
 };
 
 // Level-0 operator in diagonal (stencil) layout: value of row i on diagonal
