@@ -70,6 +70,44 @@ def level0_bytes(nnz, n, w, kind, diagonals=0):
     raise ValueError(kind)
 
 
+AMG_SRC = os.path.join(ROOT, "paper_1611_00127_amd", "csrc", "amg.hip")
+
+
+def kernel_digest(path=AMG_SRC, names=("clampi", "xcd_contiguous_block", "k_dia_pre2")):
+    """sha256 of the source text of the named device functions (each from
+    its name to the first closing brace at column 0): identifies the kernel
+    build that a stored counter measurement belongs to."""
+    import hashlib
+    import re
+    text = open(path).read()
+    h = hashlib.sha256()
+    for nm in names:
+        m = re.search(r"\b" + re.escape(nm) + r"\(", text)
+        if not m:
+            return None
+        start = text.rfind("\n", 0, m.start()) + 1
+        end = text.find("\n}\n", m.end())
+        if end < 0:
+            return None
+        h.update(text[start:end + 3].encode())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
+    WRITE_SIZE measurement (scaled by its copy-kernel calibration), or None
+    when there is none or the kernel's source has changed since."""
+    path = os.path.join(ROOT, "profiles", "k_dia_pre2_d25_3d_128x128x64_hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel") != kernel or rec.get("source_sha256") != kernel_digest():
+        return None
+    kib = (rec["fetch_kib_per_dispatch"] * rec["fetch_scale"]
+           + rec["write_kib_per_dispatch"] * rec["write_scale"])
+    return int(round(kib * 1024))
+
+
 def run_form(torch, tpf, driver, g, precision, steps, warmup, timing):
     """Times `steps` full steps (assemble + setup + solve) of one precision."""
     M = driver.GpuPrecond("bf", precision)
@@ -331,7 +369,8 @@ def main():
     roof = {"kernel": gpu_kernel, "timer": dom,
             "layout": f"diagonal, {K} diagonals" if K else "csr",
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": stored_traffic(gpu_kernel),
             "avg_launch_us": round(avg_ms * 1e3, 2), "launches": cnt,
             "algorithmic_bytes_per_launch": bytes_per_launch}
 
