@@ -97,14 +97,15 @@ def stored_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
     WRITE_SIZE measurement (scaled by its copy-kernel calibration), or None
     when there is none or the kernel's source has changed since."""
-    path = os.path.join(ROOT, "profiles", "k_dia_pre2_d25_3d_128x128x64_hbm_traffic.json")
+    path = os.path.join(ROOT, "profiles", "k_dia_d25_3d_128x128x64_hbm_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("kernel") != kernel or rec.get("source_sha256") != kernel_digest():
+    k = rec["kernels"].get(kernel)
+    if k is None or k["source_sha256"] != kernel_digest(names=tuple(k["digest_of"])):
         return None
-    kib = (rec["fetch_kib_per_dispatch"] * rec["fetch_scale"]
-           + rec["write_kib_per_dispatch"] * rec["write_scale"])
+    kib = (k["fetch_kib_per_dispatch"] * rec["fetch_scale"]
+           + k["write_kib_per_dispatch"] * rec["write_scale"])
     return int(round(kib * 1024))
 
 
