@@ -55,6 +55,13 @@ def parse():
     ap.add_argument("--serve-active", type=int, default=8, help="requests in flight")
     ap.add_argument("--serve-load", type=float, default=0.8,
                     help="Poisson arrival rate as a fraction of the sequential FP64 throughput")
+    ap.add_argument("--study", choices=["c2", "newton"], default=None,
+                    help="instead of the benchmark line, print one JSON line for a study: "
+                         "c2 = first Jacobian of the 512x512 workload for P_d in {0, 0.1, 1} and "
+                         "all four preconditioners; newton = 10 consecutive Newton Jacobians of "
+                         "the 256x256x128 workload, BF, rebuild vs reuse x FP64 vs FP32")
+    ap.add_argument("--study-grid", type=str, default=None,
+                    help="grid of the study workload (default: 512x512 / 256x256x128)")
     return ap.parse_args()
 
 
@@ -112,14 +119,13 @@ def stored_traffic(kernel):
 def run_form(torch, tpf, driver, g, precision, steps, warmup, timing):
     """Times `steps` full steps (assemble + setup + solve) of one precision."""
     M = driver.GpuPrecond("bf", precision)
-    b = torch.empty(2 * g.N, dtype=torch.float64, device="cuda")
-    x = torch.empty_like(b)
+    x = torch.empty(2 * g.N, dtype=torch.float64, device="cuda")
+    b = g.R  # J x = F: the Newton step is -x (same solve as with -F)
     infos, t_asm, t_set, t_sol = [], [], [], []
 
     def one_step():
         t0 = time.perf_counter()
         g.assemble()
-        torch.neg(g.R, out=b)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         M.setup(g)
@@ -231,7 +237,7 @@ def serve_stream(torch, tpf, driver, inputs, args):
         t1 = time.perf_counter()
         g.u.copy_(states[k])
         g.assemble()
-        b = -g.R
+        b = g.R  # J x = F, the negated Newton step
         M = driver.GpuPrecond("bf")
         M.setup(g)
         x = torch.empty_like(b)
@@ -283,7 +289,8 @@ def serve_stream(torch, tpf, driver, inputs, args):
         sv.close()
         torch.cuda.synchronize()
         for j, (r, k) in enumerate(order):
-            errs[j] = float(torch.linalg.norm(xs[j] - xb[(r, k)]) / torch.linalg.norm(xb[(r, k)]))
+            # served x is the Newton step; the baseline solved J x = F (its negative)
+            errs[j] = float(torch.linalg.norm(xs[j] + xb[(r, k)]) / torch.linalg.norm(xb[(r, k)]))
         return {"arrival_rate_per_s": None if rate is None else round(rate, 2),
                 "solves_per_s": round(n / total, 2), "wall_s": round(total, 3),
                 "p50_latency_ms": round(pct(lat, 50), 2), "p99_latency_ms": round(pct(lat, 99), 2),
@@ -312,6 +319,84 @@ def serve_stream(torch, tpf, driver, inputs, args):
     }
 
 
+def study_c2(torch, tpf, driver, inputs, args):
+    """First Newton Jacobian of the 2D 512x512 workload for P_d in {0, 0.1,
+    1}: setup and solve time, iterations and true residual of the four
+    preconditioners (FP64), each timed after one warm-up."""
+    nx, ny = (int(v) for v in (args.study_grid or "512x512").split("x"))
+    rows = []
+    for pd in (0.0, 0.1, 1.0):
+        c = inputs.workload_2d_corner(nx, ny, 2.0, 16.0, pd, 50.0, 2, name=f"2d-{nx}x{ny}-pd{pd}")
+        g = driver.GpuCase(c)
+        g.assemble()
+        b = g.R  # J x = F, the negated Newton step
+        x = torch.empty_like(b)
+        for kind in ("amg", "cpr1", "cpr2", "bf"):
+            M = driver.GpuPrecond(kind)
+            rec = None
+            for rep in range(2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                M.setup(g)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                info = driver.solve(g, M, b, x)
+                t2 = time.perf_counter()
+                st = M.stats()
+                rec = {"pd": pd, "kind": kind, "setup_ms": round(1e3 * (t1 - t0), 2),
+                       "solve_ms": round(1e3 * (t2 - t1), 2), "iterations": int(info.iterations),
+                       "status": int(info.status), "relres_true": float(info.relres_true),
+                       "levels": [int(st.levels[h]) for h in range(st.n_hier)],
+                       "op_complexity": [round(float(st.operator_complexity[h]), 3)
+                                         for h in range(st.n_hier)]}
+            log(f"[c2] P_d {pd} {kind}: {rec['iterations']} its, setup {rec['setup_ms']} ms, "
+                f"solve {rec['solve_ms']} ms")
+            rows.append(rec)
+            M.close()
+        g.close()
+    return {"study": "c2", "workload": f"2d-{nx}x{ny} sigma=2 corr=16 CFL 50, first Newton "
+                                      f"Jacobian", "precision": "f64", "results": rows}
+
+
+def study_newton(torch, tpf, driver, inputs, args):
+    """10 consecutive Newton Jacobians of one time step on the 3D 256x256x128
+    workload with BF: full setup at every Jacobian (rebuild) or numeric
+    refresh of the first hierarchy (reuse), FP64 and FP32 V-cycles; per
+    Jacobian ||F||, iterations, setup and solve time; HBM bytes by part."""
+    nx, ny, nz = (int(v) for v in (args.study_grid or "256x256x128").split("x"))
+    c = inputs.config_c4(nx, ny, nz)
+    out = {"study": "newton", "workload": f"3d-{nx}x{ny}x{nz} log-normal sigma=3, CFL "
+                                          f"{inputs.SEQUENCE_CFL:g}, BF, 10 Jacobians",
+           "cells": c.N, "sequences": []}
+    for precision, pname in ((tpf.TPF_FP64, "f64"), (tpf.TPF_FP32, "f32")):
+        for reuse in (False, True):
+            g = driver.GpuCase(c)
+            M = driver.GpuPrecond("bf", precision)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            recs = driver.newton_sequence(g, M, 10, reuse=reuse, ds_max=0.2)
+            torch.cuda.synchronize()
+            total = time.perf_counter() - t0
+            st = M.stats()
+            v = tpf.tpf_jacobian_view(g.J)
+            seq = {"precision": pname, "structure": "reuse" if reuse else "rebuild",
+                   "total_s": round(total, 3),
+                   "jacobians": [{k: (round(val, 3) if isinstance(val, float) else val)
+                                  for k, val in r.items()} for r in recs],
+                   "hbm_bytes": {"jacobian": int(v.nnzb) * 36 + 4 * (v.n_block_rows + 1),
+                                 "preconditioner": int(st.device_bytes),
+                                 "hierarchy_A_ss": int(st.hier_bytes[0]),
+                                 "hierarchy_S": int(st.hier_bytes[1]),
+                                 "krylov_workspace": 8 * (2 * 30 + 2) * 2 * c.N,
+                                 "state_vectors": 8 * 2 * c.N * 4}}
+            log(f"[newton] {pname} {seq['structure']}: {total:.2f} s, its "
+                f"{[r['iterations'] for r in recs]}")
+            out["sequences"].append(seq)
+            M.close()
+            g.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -322,6 +407,10 @@ def main():
 
     from paper_1611_00127_amd import driver, inputs, tpf
     tpf.init()
+    if args.study:
+        fn = study_c2 if args.study == "c2" else study_newton
+        print(json.dumps(fn(torch, tpf, driver, inputs, args)), flush=True)
+        return
     if args.copy_probe > 0:
         n = args.copy_probe * 2 ** 20 // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")

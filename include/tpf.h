@@ -130,12 +130,13 @@ int tpf_jacobian_view(const tpf_jacobian* J, tpf_bcsr_view* out);
 
 /* y = J x (x, y device 2N). */
 int tpf_spmv(const tpf_jacobian* J, const double* x, double* y, void* stream);
-/* Newton update (Sec. 3; the paper's Newton variant is unspecified): each
- * saturation increment is first limited to [-ds_max, ds_max] when
- * ds_max > 0 (per-cell saturation chop), then u += delta and S_n is
- * clamped to [0,1].  u, delta: device 2N. */
-int tpf_newton_update(tpf_problem* p, double* u, const double* delta, double ds_max,
-                      void* stream);
+/* Newton update (Sec. 3; the paper's Newton variant is unspecified): the
+ * step is alpha * delta (alpha = -1 when delta solves J delta = +F, i.e. the
+ * residual itself was the right-hand side); each saturation increment is
+ * limited to [-ds_max, ds_max] when ds_max > 0 (per-cell saturation chop),
+ * then u += step and S_n is clamped to [0,1].  u, delta: device 2N. */
+int tpf_newton_update(tpf_problem* p, double* u, const double* delta, double alpha,
+                      double ds_max, void* stream);
 
 /* ---- preconditioners (Sec. 3.2-3.4) ------------------------------------ */
 #define TPF_PREC_AMG 0   /* one V-cycle on the point-ordered scalar J (Sec. 3.2) */
@@ -189,6 +190,8 @@ typedef struct tpf_hier_stats {
   int l0_diagonals[3];                 /* level-0 smoother layout: number of stored diagonals
                                           (diagonal layout), 0 = CSR */
   size_t device_bytes;                 /* bytes held by the preconditioner */
+  size_t hier_bytes[3];                /* of which each hierarchy (levels, transfer operators,
+                                          work vectors, coarsest inverse) */
 } tpf_hier_stats;
 int tpf_precond_stats(const tpf_precond* M, tpf_hier_stats* out);
 

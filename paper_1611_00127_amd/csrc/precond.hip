@@ -712,6 +712,7 @@ int tpf_precond_stats(const tpf_precond* M, tpf_hier_stats* out) {
       out->l0_diagonals[h] = H.dia0.ok ? H.dia0.K : 0;
     }
     out->device_bytes = M->bytes();
+    for (int h = 0; h < M->n_hier; ++h) out->hier_bytes[h] = M->H[h]->bytes();
   });
 }
 

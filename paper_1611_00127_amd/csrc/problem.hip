@@ -335,11 +335,12 @@ __global__ void k_assemble_dirichlet(Phys ph, int ncell, const int* __restrict__
   dd[3] += a11;
 }
 
-__global__ void k_newton_update(int64_t N, double* u, const double* du, double ds_max) {
+__global__ void k_newton_update(int64_t N, double* u, const double* du, double alpha,
+                                double ds_max) {
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= N) return;
-  u[2 * i] += du[2 * i];
-  double d = du[2 * i + 1];
+  u[2 * i] += alpha * du[2 * i];
+  double d = alpha * du[2 * i + 1];
   if (ds_max > 0.0) d = d < -ds_max ? -ds_max : (d > ds_max ? ds_max : d);
   double s = u[2 * i + 1] + d;
   u[2 * i + 1] = s < 0.0 ? 0.0 : (s > 1.0 ? 1.0 : s);
@@ -624,11 +625,12 @@ int tpf_spmv(const tpf_jacobian* J, const double* x, double* y, void* stream) {
   });
 }
 
-int tpf_newton_update(tpf_problem* p, double* u, const double* du, double ds_max, void* stream) {
+int tpf_newton_update(tpf_problem* p, double* u, const double* du, double alpha, double ds_max,
+                      void* stream) {
   return guarded([&] {
     TPF_REQUIRE(p && u && du, TPF_ERR_INVALID_ARG, "null argument");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    k_newton_update<<<grid_for(p->ph.N, 256), 256, 0, s>>>(p->ph.N, u, du, ds_max);
+    k_newton_update<<<grid_for(p->ph.N, 256), 256, 0, s>>>(p->ph.N, u, du, alpha, ds_max);
     TPF_CHECK_LAUNCH();
   });
 }

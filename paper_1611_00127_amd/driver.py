@@ -115,19 +115,18 @@ def newton_sequence(gcase, M, n_jacobians, reuse=False, ds_max=0.2, rtol=1e-8, r
 
     import torch
     out = []
-    b = torch.empty(2 * gcase.N, dtype=torch.float64, device="cuda")
-    x = torch.empty_like(b)
+    x = torch.empty(2 * gcase.N, dtype=torch.float64, device="cuda")
     for k in range(n_jacobians):
         gcase.assemble()
-        torch.neg(gcase.R, out=b)
         fnorm = float(torch.linalg.norm(gcase.R))
         t0 = time.perf_counter()
         M.setup(gcase, reuse=bool(reuse and k > 0))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        info = solve(gcase, M, b, x, rtol=rtol, restart=restart, maxit=maxit)
+        # J x = F, so the Newton step is -x
+        info = solve(gcase, M, gcase.R, x, rtol=rtol, restart=restart, maxit=maxit)
         t2 = time.perf_counter()
-        tpf.tpf_newton_update(gcase.prob, gcase.u, x, ds_max, stream=gcase.stream)
+        tpf.tpf_newton_update(gcase.prob, gcase.u, x, ds_max, alpha=-1.0, stream=gcase.stream)
         rec = dict(k=k, fnorm=fnorm, iterations=int(info.iterations), status=int(info.status),
                    relres=float(info.relres_true), setup_ms=1e3 * (t1 - t0),
                    solve_ms=1e3 * (t2 - t1))

@@ -68,7 +68,7 @@ class HierStats(ctypes.Structure):
                 ("rows", (c_int64 * TPF_MAX_LEVELS) * 3), ("nnz", (c_int64 * TPF_MAX_LEVELS) * 3),
                 ("operator_complexity", c_double * 3), ("grid_complexity", c_double * 3),
                 ("coarse_dense", c_int * 3), ("l0_diagonals", c_int * 3),
-                ("device_bytes", c_size_t)]
+                ("device_bytes", c_size_t), ("hier_bytes", c_size_t * 3)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -142,7 +142,7 @@ _SIGS = {
     "tpf_assemble": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_void_p]),
     "tpf_jacobian_view": (c_int, [c_void_p, ctypes.POINTER(BcsrView)]),
     "tpf_spmv": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
-    "tpf_newton_update": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_void_p]),
+    "tpf_newton_update": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_double, c_void_p]),
     "tpf_precond_default_opts": (c_int, [c_int, ctypes.POINTER(PrecondOpts)]),
     "tpf_precond_create": (c_int, [ctypes.POINTER(PrecondOpts), ctypes.POINTER(c_void_p)]),
     "tpf_precond_destroy": (c_int, [c_void_p]),
@@ -317,8 +317,9 @@ def tpf_spmv(J, x, y, stream=None):
     _check(load().tpf_spmv(J, _ptr(x), _ptr(y), _stream(stream)))
 
 
-def tpf_newton_update(p, u, delta, ds_max=0.0, stream=None):
-    _check(load().tpf_newton_update(p, _ptr(u), _ptr(delta), float(ds_max), _stream(stream)))
+def tpf_newton_update(p, u, delta, ds_max=0.0, alpha=1.0, stream=None):
+    _check(load().tpf_newton_update(p, _ptr(u), _ptr(delta), float(alpha), float(ds_max),
+                                    _stream(stream)))
 
 
 def tpf_precond_default_opts(kind):
