@@ -267,6 +267,7 @@ __global__ void __launch_bounds__(BLOCK) k_spgemm_flat(
     int* __restrict__ cnt, const int64_t* __restrict__ toff, int* __restrict__ cci,
     double* __restrict__ cv) {
   __shared__ int offs[CAP + 1];
+  __shared__ int bst[CAP];  // start of B row k_e for each entry e of A's row
   __shared__ unsigned long long keys[CAP];
   __shared__ double pv[FILL ? CAP : 1];
   __shared__ int sh[BLOCK / 64 + 1];
@@ -277,14 +278,18 @@ __global__ void __launch_bounds__(BLOCK) k_spgemm_flat(
   int run = 0;
   for (int base = 0; base < la; base += BLOCK) {
     int e = base + threadIdx.x;
-    int len = 0;
+    int len = 0, b0 = 0;
     if (e < la) {
       int k = aci[a0 + e];
-      len = brp[k + 1] - brp[k];
+      b0 = brp[k];
+      len = brp[k + 1] - b0;
     }
     int total;
     int excl = block_exclusive_scan<int, BLOCK>(len, sh, total);
-    if (e < la) offs[e] = run + excl;
+    if (e < la) {
+      offs[e] = run + excl;
+      bst[e] = b0;
+    }
     run += total;
   }
   if (threadIdx.x == 0) offs[la] = run;
@@ -294,8 +299,15 @@ __global__ void __launch_bounds__(BLOCK) k_spgemm_flat(
   int p2 = 1;
   while (p2 < u) p2 <<= 1;
   __syncthreads();
-  for (int t = threadIdx.x; t < p2; t += BLOCK) {
-    unsigned long long key = ~0ull;
+  // products: each lane's CAP / BLOCK slots are located in LDS first, then
+  // all their loads are issued together
+  constexpr int PER = CAP / BLOCK;
+  int src[PER], ent[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int t = threadIdx.x + q * BLOCK;
+    src[q] = -1;
+    ent[q] = 0;
     if (t < nprod) {
       int lo = 0, hi = la;  // largest e with offs[e] <= t
       while (hi - lo > 1) {
@@ -304,16 +316,36 @@ __global__ void __launch_bounds__(BLOCK) k_spgemm_flat(
         else hi = mid;
       }
       while (lo + 1 < la && offs[lo + 1] <= t) ++lo;  // skip empty B rows
-      int k = aci[a0 + lo];
-      int p = brp[k] + (t - offs[lo]);
-      key = (static_cast<unsigned long long>(static_cast<unsigned>(bci[p])) << 32) | unsigned(t);
-      if (FILL) pv[t] = av[a0 + lo] * bv[p];
+      src[q] = bst[lo] + (t - offs[lo]);
+      ent[q] = lo;
     } else if (t < u) {
-      int p = drp[i] + (t - nprod);
-      key = (static_cast<unsigned long long>(static_cast<unsigned>(dci[p])) << 32) | unsigned(t);
-      if (FILL) pv[t] = dv[p];
+      src[q] = drp[i] + (t - nprod);
     }
-    keys[t] = key;
+  }
+  int col[PER];
+  double val[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int t = threadIdx.x + q * BLOCK;
+    col[q] = 0;
+    val[q] = 0.0;
+    if (t < nprod) {
+      col[q] = bci[src[q]];
+      if (FILL) val[q] = av[a0 + ent[q]] * bv[src[q]];
+    } else if (t < u) {
+      col[q] = dci[src[q]];
+      if (FILL) val[q] = dv[src[q]];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int t = threadIdx.x + q * BLOCK;
+    if (t < p2) {
+      keys[t] = t < u ? (static_cast<unsigned long long>(static_cast<unsigned>(col[q])) << 32) |
+                            unsigned(t)
+                      : ~0ull;
+      if (FILL && t < u) pv[t] = val[q];
+    }
   }
   __syncthreads();
   for (int k = 2; k <= p2; k <<= 1)
