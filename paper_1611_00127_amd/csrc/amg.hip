@@ -1131,6 +1131,8 @@ __global__ void __launch_bounds__(256) k_dia_pre(int n, DiagOffs o, const T* __r
 template <class T> struct Vec2;
 template <> struct Vec2<double> { using type = double2; };
 template <> struct Vec2<float> { using type = float2; };
+// clang vector of two T (what the non-temporal builtin accepts)
+template <class T> using nt2 = T __attribute__((ext_vector_type(2)));
 
 // Two rows per thread (n even): the diagonals and the row vectors are read
 // as pairs.  Same sums, in the same order, as the one-row kernels.
@@ -1144,7 +1146,8 @@ __global__ void __launch_bounds__(256) k_dia_pre2(int n, DiagOffs o, const T* __
   T s0 = T(0), s1 = T(0);
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    T2 a = *reinterpret_cast<const T2*>(v + int64_t(k) * n + i);
+    // the diagonals are streamed once: non-temporal, so L2 keeps the gathered vector
+    nt2<T> a = __builtin_nontemporal_load(reinterpret_cast<const nt2<T>*>(v + int64_t(k) * n + i));
     s0 += a.x * g[clampi(i + o.off[k], n)];
     s1 += a.y * g[clampi(i + 1 + o.off[k], n)];
   }
@@ -1166,7 +1169,7 @@ __global__ void __launch_bounds__(256) k_dia_post2(int n, DiagOffs o, const T* _
   T s0 = T(0), s1 = T(0);
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    T2 a = *reinterpret_cast<const T2*>(v + int64_t(k) * n + i);
+    nt2<T> a = __builtin_nontemporal_load(reinterpret_cast<const nt2<T>*>(v + int64_t(k) * n + i));
     s0 += a.x * y[clampi(i + o.off[k], n)];
     s1 += a.y * y[clampi(i + 1 + o.off[k], n)];
   }
