@@ -5,17 +5,24 @@
 // stream of its own slot, and advance one solver phase per server step, so
 // the kernels of many solves overlap on the device.
 //
-// Streams and memory:
-//   - assembly and preconditioner setup of every request run on one setup
+// Threads, streams and memory:
+//   - the calling thread admits requests and advances the running solves;
+//     a setup thread does each admitted request's assembly and
+//     preconditioner setup (host-synchronous work) meanwhile, on one setup
 //     stream, so everything a resident sequence owns is allocated and freed
-//     on that stream; the slot stream waits for the setup through an event;
+//     on that stream; the request's slot stream waits for it by an event;
 //   - the FGMRES workspace of a request is allocated and released on its
 //     slot stream, after the host has seen the request's last phase finish;
 //   - resident data of a sequence is only touched by one request at a time.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <deque>
 #include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -64,11 +71,18 @@ struct Resident {
   Buf<double> rhs;
   bool built = false;  // preconditioner structure exists
   bool busy = false;
-  size_t bytes = 0;
+  std::atomic<size_t> bytes{0};
   uint64_t last_use = 0;
   ~Resident() {
     if (M) tpf_precond_destroy(M);
     if (J) tpf_jacobian_destroy(J);
+  }
+  // device bytes this sequence holds (Jacobian, preconditioner, right-hand side)
+  size_t measure() const {
+    size_t b = rhs.bytes();
+    if (J) b += J->rp.bytes() + J->ci.bytes() + J->v.bytes();
+    if (M) b += M->bytes();
+    return b;
   }
 };
 
@@ -78,18 +92,26 @@ struct Pending {
   Clock::time_point submit;
 };
 
+enum SlotState { kFree, kSetup, kReady, kFailed };
+
 struct Slot {
   hipStream_t s = nullptr;
   hipEvent_t ev = nullptr;
   void* host = nullptr;  // pinned readback slot
+  std::atomic<int> state{kFree};
   std::unique_ptr<Fgmres> f;
   Pending req;
   Resident* res = nullptr;
-  bool busy = false;
+  int64_t cells = 0;
+  bool fresh = false;
   bool cancel = false;
+  bool started = false;  // first phase seen by the calling thread
   double setup_ms = 0.0;
   int refreshed = 0;
-  size_t ws_bytes = 0;
+  size_t ws_bytes = 0;   // reserved while in setup, the FGMRES workspace after
+  int err_code = TPF_OK;
+  std::string err_msg;
+  bool busy() const { return state.load(std::memory_order_acquire) != kFree; }
 };
 
 }  // namespace tpf
@@ -101,7 +123,8 @@ struct tpf_server {
   hipStream_t setup_s = nullptr;
   hipEvent_t setup_ev = nullptr;
   void* host_block = nullptr;
-  std::vector<Slot> slots;
+  int device = 0;
+  std::vector<std::unique_ptr<Slot>> slots;
   std::deque<Pending> queue;
   std::unordered_map<uint64_t, std::unique_ptr<Resident>> res;
   std::unordered_map<uint64_t, tpf_result> results;
@@ -109,17 +132,23 @@ struct tpf_server {
   uint64_t tick = 0;
   int64_t submitted = 0, completed = 0, evictions = 0;
   size_t peak = 0;
+  // shared with the setup thread
+  std::mutex mu;
+  std::condition_variable cv_job, cv_done;
+  std::deque<Slot*> jobs;
+  bool stop = false;
   std::vector<std::pair<int64_t, size_t>> seen;  // (cells, resident bytes) of built sequences
+  std::thread worker;
 
   size_t resident_bytes() const {
     size_t b = 0;
-    for (auto& kv : res) b += kv.second->bytes;
+    for (auto& kv : res) b += kv.second->bytes.load();
     return b;
   }
   size_t active_bytes() const {
     size_t b = 0;
     for (auto& sl : slots)
-      if (sl.busy) b += sl.ws_bytes;
+      if (sl->busy()) b += sl->ws_bytes;
     return b;
   }
   size_t in_use() const { return resident_bytes() + active_bytes(); }
@@ -129,7 +158,8 @@ struct tpf_server {
   // footprint of a built sequence at least as large, else one scaled up
   // linearly from the largest smaller one (fixed costs scale too, so this
   // errs high); 3 KiB per cell before any sequence has been built.
-  size_t resident_estimate(int64_t cells) const {
+  size_t resident_estimate(int64_t cells) {
+    std::lock_guard<std::mutex> lk(mu);
     double best = -1.0;
     for (auto& ob : seen) {
       double e = cells <= ob.first ? double(ob.second)
@@ -174,35 +204,18 @@ struct tpf_server {
 
   Slot* free_slot() {
     for (auto& sl : slots)
-      if (!sl.busy) return &sl;
+      if (!sl->busy()) return sl.get();
     return nullptr;
   }
 
-  // Starts request p on slot sl: assembly and setup on the setup stream,
-  // then the first FGMRES phase on the slot stream.
-  void start(Slot& sl, const Pending& p, int64_t cells) {
+  // Setup thread: assembly, right-hand side -F, preconditioner setup or
+  // refresh on the setup stream, then the first FGMRES phase on the slot
+  // stream.  Touches only the slot and its resident sequence.
+  void run_setup(Slot& sl) {
     auto t0 = Clock::now();
-    Resident* r = nullptr;
-    auto it = res.find(p.rq.sequence);
-    bool fresh = it == res.end();
-    size_t before = 0;
-    tpf_memory_in_use(&before);
-    if (fresh) {
-      auto nr = std::make_unique<Resident>();
-      nr->seq = p.rq.sequence;
-      nr->prob = p.rq.problem;
-      nr->cells = cells;
-      r = nr.get();
-      res[p.rq.sequence] = std::move(nr);
-    } else {
-      r = it->second.get();
-    }
-    sl.busy = true;
-    sl.cancel = false;
-    sl.req = p;
-    sl.res = r;
-    r->busy = true;
-    r->last_use = ++tick;
+    Resident* r = sl.res;
+    const Pending& p = sl.req;
+    const int64_t cells = sl.cells;
     try {
       if (!r->J) check_rc(tpf_jacobian_create(r->prob, setup_s, &r->J));
       if (!r->M) {
@@ -220,38 +233,86 @@ struct tpf_server {
       check_rc(tpf_precond_setup(r->M, r->J, reuse ? 1 : 0, setup_s));  // synchronises
       r->built = true;
       sl.refreshed = reuse ? 1 : 0;
-      size_t after = 0;
-      tpf_memory_in_use(&after);
-      int64_t grown = int64_t(after) - int64_t(before);
-      r->bytes = size_t(std::max<int64_t>(0, int64_t(r->bytes) + grown));
-      if (fresh) seen.emplace_back(cells, r->bytes);
+      r->bytes.store(r->measure());
       sl.setup_ms = ms_since(t0);
       TPF_HIP(hipEventRecord(setup_ev, setup_s));
       TPF_HIP(hipStreamWaitEvent(sl.s, setup_ev, 0));
       sl.f = std::make_unique<Fgmres>();
-      sl.ws_bytes = krylov_bytes(cells, o.solve.restart);
       sl.f->begin(r->J, r->M, r->rhs.p, p.rq.x, o.solve, sl.s, sl.host);
       TPF_HIP(hipEventRecord(sl.ev, sl.s));
-      // the estimate may have been low: give back idle sequences first
-      while (in_use() > o.hbm_budget_bytes && evict_one(r->seq)) {
-      }
-      note_peak();
+      sl.err_code = TPF_OK;
     } catch (const Error& e) {
-      set_last_error(e.code, e.what());
-      TPF_HIP(hipStreamSynchronize(setup_s));
-      TPF_HIP(hipStreamSynchronize(sl.s));
-      release(sl);
-      res.erase(p.rq.sequence);  // rebuilt from scratch by the next request
-      finish_request(p, e.code, 0, NAN, NAN, ms_since(t0), 0.0, 0);
+      sl.err_code = e.code;
+      sl.err_msg = e.what();
+      (void)hipStreamSynchronize(setup_s);
+      (void)hipStreamSynchronize(sl.s);
+      sl.setup_ms = ms_since(t0);
     }
+  }
+
+  void worker_loop() {
+    (void)hipSetDevice(device);
+    while (true) {
+      Slot* sl = nullptr;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv_job.wait(lk, [&] { return stop || !jobs.empty(); });
+        if (jobs.empty()) return;  // stop requested and nothing left
+        sl = jobs.front();
+        jobs.pop_front();
+      }
+      run_setup(*sl);
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        if (sl->err_code == TPF_OK && sl->fresh) seen.emplace_back(sl->cells, sl->res->bytes.load());
+        sl->state.store(sl->err_code == TPF_OK ? kReady : kFailed, std::memory_order_release);
+      }
+      cv_done.notify_all();
+    }
+  }
+
+  // Reserves slot sl for request p and hands its setup to the setup thread.
+  void start(Slot& sl, const Pending& p, int64_t cells, size_t reserve) {
+    Resident* r = nullptr;
+    auto it = res.find(p.rq.sequence);
+    bool fresh = it == res.end();
+    if (fresh) {
+      auto nr = std::make_unique<Resident>();
+      nr->seq = p.rq.sequence;
+      nr->prob = p.rq.problem;
+      nr->cells = cells;
+      r = nr.get();
+      res[p.rq.sequence] = std::move(nr);
+    } else {
+      r = it->second.get();
+    }
+    r->busy = true;
+    r->last_use = ++tick;
+    sl.req = p;
+    sl.res = r;
+    sl.cells = cells;
+    sl.fresh = fresh;
+    sl.cancel = false;
+    sl.started = false;
+    sl.refreshed = 0;
+    sl.ws_bytes = reserve;
+    sl.err_code = TPF_OK;
+    sl.err_msg.clear();
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      sl.state.store(kSetup, std::memory_order_release);
+      jobs.push_back(&sl);
+    }
+    cv_job.notify_one();
+    note_peak();
   }
 
   void release(Slot& sl) {
     sl.f.reset();  // workspace returned on the slot stream (its work is done)
     if (sl.res) sl.res->busy = false;
     sl.res = nullptr;
-    sl.busy = false;
     sl.ws_bytes = 0;
+    sl.state.store(kFree, std::memory_order_release);
   }
 
   void admit() {
@@ -277,8 +338,9 @@ struct tpf_server {
       } else {
         check_rc(tpf_problem_cells(p.rq.problem, &cells));
       }
-      size_t need = krylov_bytes(cells, o.solve.restart) +
-                    (rit == res.end() ? resident_estimate(cells) : 0);
+      const size_t ws = krylov_bytes(cells, o.solve.restart);
+      const size_t est = rit == res.end() ? resident_estimate(cells) : 0;
+      const size_t need = ws + est;
       if (need > o.hbm_budget_bytes) {
         Pending bad = p;
         it = queue.erase(it);
@@ -289,7 +351,7 @@ struct tpf_server {
       }
       if (in_use() + need > o.hbm_budget_bytes) {
         bool any_active = false;
-        for (auto& x : slots) any_active |= x.busy;
+        for (auto& x : slots) any_active |= x->busy();
         if (any_active) return;  // waits for active solves to retire
         Pending bad = p;         // cannot fit even with the device to itself
         it = queue.erase(it);
@@ -299,15 +361,53 @@ struct tpf_server {
       }
       Pending go = p;
       it = queue.erase(it);
-      start(*sl, go, cells);
+      start(*sl, go, cells, need);
     }
   }
 
+  // Advances every request whose setup has finished by one phase; waits for
+  // a setup to finish when nothing else can advance.
   int step() {
     admit();
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      auto runnable = [&] {
+        bool setup = false;
+        for (auto& sl : slots) {
+          int st = sl->state.load(std::memory_order_acquire);
+          if (st == kReady || st == kFailed) return true;
+          setup |= st == kSetup;
+        }
+        return !setup;
+      };
+      cv_done.wait(lk, runnable);
+    }
     int done = 0;
-    for (auto& sl : slots) {
-      if (!sl.busy) continue;
+    for (auto& slp : slots) {
+      Slot& sl = *slp;
+      int st = sl.state.load(std::memory_order_acquire);
+      if (st == kFailed) {
+        set_last_error(sl.err_code, sl.err_msg.c_str());
+        Pending p = sl.req;
+        uint64_t seq = p.rq.sequence;
+        double setup_ms = sl.setup_ms;
+        int code = sl.err_code;
+        release(sl);
+        res.erase(seq);  // rebuilt from scratch by the next request
+        finish_request(p, code, 0, NAN, NAN, setup_ms, 0.0, 0);
+        ++done;
+        continue;
+      }
+      if (st != kReady) continue;
+      if (!sl.started) {
+        // the resident size is known now: the workspace replaces the reservation,
+        // and idle sequences give way if the estimate was low
+        sl.started = true;
+        sl.ws_bytes = krylov_bytes(sl.cells, o.solve.restart);
+        while (in_use() > o.hbm_budget_bytes && evict_one(sl.res->seq)) {
+        }
+        note_peak();
+      }
       TPF_HIP(hipEventSynchronize(sl.ev));
       Fgmres& f = *sl.f;
       bool fin = false;
@@ -335,6 +435,15 @@ struct tpf_server {
       ++done;
     }
     return done;
+  }
+
+  void shutdown() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      stop = true;
+    }
+    cv_job.notify_all();
+    if (worker.joinable()) worker.join();
   }
 };
 
@@ -368,13 +477,16 @@ extern "C" int tpf_server_create(const tpf_server_opts* o, tpf_server** out) {
     TPF_HIP(hipStreamCreateWithFlags(&sv->setup_s, hipStreamNonBlocking));
     TPF_HIP(hipEventCreateWithFlags(&sv->setup_ev, hipEventDisableTiming));
     TPF_HIP(hipHostMalloc(&sv->host_block, size_t(64) * o->max_active, hipHostMallocDefault));
-    sv->slots.resize(o->max_active);
     for (int i = 0; i < o->max_active; ++i) {
-      Slot& sl = sv->slots[i];
+      sv->slots.push_back(std::make_unique<Slot>());
+      Slot& sl = *sv->slots.back();
       TPF_HIP(hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking));
       TPF_HIP(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
       sl.host = static_cast<char*>(sv->host_block) + 64 * i;
     }
+    TPF_HIP(hipGetDevice(&sv->device));
+    tpf_server* raw = sv.get();
+    sv->worker = std::thread([raw] { raw->worker_loop(); });
     *out = sv.release();
   });
 }
@@ -416,7 +528,7 @@ extern "C" int tpf_server_poll(tpf_server* sv, uint64_t ticket, tpf_result* out)
   for (auto& p : sv->queue)
     if (p.ticket == ticket) return 0;
   for (auto& sl : sv->slots)
-    if (sl.busy && sl.req.ticket == ticket) return 0;
+    if (sl->busy() && sl->req.ticket == ticket) return 0;
   set_last_error(TPF_ERR_INVALID_ARG, "unknown ticket");
   return TPF_ERR_INVALID_ARG;
 }
@@ -433,8 +545,8 @@ extern "C" int tpf_server_cancel(tpf_server* sv, uint64_t ticket) {
       }
     }
     for (auto& sl : sv->slots) {
-      if (sl.busy && sl.req.ticket == ticket) {
-        sl.cancel = true;
+      if (sl->busy() && sl->req.ticket == ticket) {
+        sl->cancel = true;  // read by the calling thread once the setup is done
         return;
       }
     }
@@ -447,7 +559,7 @@ extern "C" int tpf_server_stats(const tpf_server* sv, tpf_server_counters* out) 
     TPF_REQUIRE(sv && out, TPF_ERR_INVALID_ARG, "null argument");
     *out = tpf_server_counters{};
     out->queued = int(sv->queue.size());
-    for (auto& sl : sv->slots) out->active += sl.busy ? 1 : 0;
+    for (auto& sl : sv->slots) out->active += sl->busy() ? 1 : 0;
     out->resident_sequences = int(sv->res.size());
     out->submitted = sv->submitted;
     out->completed = sv->completed;
@@ -461,16 +573,17 @@ extern "C" int tpf_server_destroy(tpf_server* sv) {
   return guarded([&] {
     if (!sv) return;
     std::unique_ptr<tpf_server> own(sv);
+    sv->shutdown();  // the setup thread finishes the setups it holds, then exits
     for (auto& sl : sv->slots) {
-      if (sl.s) (void)hipStreamSynchronize(sl.s);
-      sl.f.reset();
+      if (sl->s) (void)hipStreamSynchronize(sl->s);
+      sl->f.reset();
     }
     if (sv->setup_s) (void)hipStreamSynchronize(sv->setup_s);
     sv->res.clear();
     if (sv->setup_s) (void)hipStreamSynchronize(sv->setup_s);
     for (auto& sl : sv->slots) {
-      if (sl.ev) (void)hipEventDestroy(sl.ev);
-      if (sl.s) (void)hipStreamDestroy(sl.s);
+      if (sl->ev) (void)hipEventDestroy(sl->ev);
+      if (sl->s) (void)hipStreamDestroy(sl->s);
     }
     if (sv->setup_ev) (void)hipEventDestroy(sv->setup_ev);
     if (sv->setup_s) (void)hipStreamDestroy(sv->setup_s);
