@@ -159,12 +159,9 @@ __device__ inline void mm2(const double* a, const double* b, double* c) {
   c[3] = a[2] * b[1] + a[3] * b[3];
 }
 
-__global__ void k_bilu_factor(int cnt, const int* __restrict__ cells, const int* __restrict__ rp,
-                              const int* __restrict__ ci, const double* __restrict__ jv,
-                              double* __restrict__ dinv, int* __restrict__ flag) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= cnt) return;
-  int i = cells[t];
+__device__ inline void bilu_factor_cell(int i, const int* __restrict__ rp,
+                                        const int* __restrict__ ci, const double* __restrict__ jv,
+                                        double* __restrict__ dinv, int* __restrict__ flag) {
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   double d[4] = {0.0, 0.0, 0.0, 0.0};
   for (int e = rp[i]; e < rp[i + 1]; ++e) {
@@ -190,15 +187,19 @@ __global__ void k_bilu_factor(int cnt, const int* __restrict__ cells, const int*
   o[3] = d[0] / det;
 }
 
-// forward: w_i = D_i^{-1} (r_i - sum_{k<i} A_ik w_k)
-template <class T>
-__global__ void k_bilu_fwd(int cnt, const int* __restrict__ cells, const int* __restrict__ rp,
-                           const int* __restrict__ ci, const T* __restrict__ jv,
-                           const T* __restrict__ dinv, const double* __restrict__ r,
-                           T* __restrict__ w) {
+__global__ void k_bilu_factor(int cnt, const int* __restrict__ cells, const int* __restrict__ rp,
+                              const int* __restrict__ ci, const double* __restrict__ jv,
+                              double* __restrict__ dinv, int* __restrict__ flag) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= cnt) return;
-  int i = cells[t];
+  bilu_factor_cell(cells[t], rp, ci, jv, dinv, flag);
+}
+
+// forward: w_i = D_i^{-1} (r_i - sum_{k<i} A_ik w_k)
+template <class T>
+__device__ inline void bilu_fwd_cell(int i, const int* __restrict__ rp, const int* __restrict__ ci,
+                                     const T* __restrict__ jv, const T* __restrict__ dinv,
+                                     const double* __restrict__ r, T* __restrict__ w) {
   T a0 = 0, a1 = 0;
   for (int e = rp[i]; e < rp[i + 1]; ++e) {
     int k = ci[e];
@@ -216,13 +217,9 @@ __global__ void k_bilu_fwd(int cnt, const int* __restrict__ cells, const int* __
 
 // backward: z_i = w_i - D_i^{-1} sum_{j>i} A_ij z_j
 template <class T>
-__global__ void k_bilu_bwd(int cnt, const int* __restrict__ cells, const int* __restrict__ rp,
-                           const int* __restrict__ ci, const T* __restrict__ jv,
-                           const T* __restrict__ dinv, const T* __restrict__ w,
-                           T* __restrict__ z) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= cnt) return;
-  int i = cells[t];
+__device__ inline void bilu_bwd_cell(int i, const int* __restrict__ rp, const int* __restrict__ ci,
+                                     const T* __restrict__ jv, const T* __restrict__ dinv,
+                                     const T* __restrict__ w, T* __restrict__ z) {
   T a0 = 0, a1 = 0;
   for (int e = rp[i]; e < rp[i + 1]; ++e) {
     int j = ci[e];
@@ -235,6 +232,64 @@ __global__ void k_bilu_bwd(int cnt, const int* __restrict__ cells, const int* __
   const T* di = dinv + 4 * int64_t(i);
   z[2 * i] = w[2 * i] - (di[0] * a0 + di[1] * a1);
   z[2 * i + 1] = w[2 * i + 1] - (di[2] * a0 + di[3] * a1);
+}
+
+// one launch per wavefront (large fronts)
+template <class T>
+__global__ void k_bilu_fwd(int cnt, const int* __restrict__ cells, const int* __restrict__ rp,
+                           const int* __restrict__ ci, const T* __restrict__ jv,
+                           const T* __restrict__ dinv, const double* __restrict__ r,
+                           T* __restrict__ w) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < cnt) bilu_fwd_cell<T>(cells[t], rp, ci, jv, dinv, r, w);
+}
+
+template <class T>
+__global__ void k_bilu_bwd(int cnt, const int* __restrict__ cells, const int* __restrict__ rp,
+                           const int* __restrict__ ci, const T* __restrict__ jv,
+                           const T* __restrict__ dinv, const T* __restrict__ w,
+                           T* __restrict__ z) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < cnt) bilu_bwd_cell<T>(cells[t], rp, ci, jv, dinv, w, z);
+}
+
+// Whole sweeps in one work-group (fronts of at most kFrontWg cells, as on
+// 2D grids): the fronts are taken in order with a barrier between them, in
+// place of one launch per front.  FWD: forward sweep, else backward.
+constexpr int kFrontWg = 2048;
+template <class T, bool FWD>
+__global__ void __launch_bounds__(1024) k_bilu_sweep_wg(int nf, const int* __restrict__ fptr,
+                                                        const int* __restrict__ cells,
+                                                        const int* __restrict__ rp,
+                                                        const int* __restrict__ ci,
+                                                        const T* __restrict__ jv,
+                                                        const T* __restrict__ dinv,
+                                                        const double* __restrict__ r,
+                                                        T* __restrict__ w, T* __restrict__ z) {
+  for (int q = 0; q < nf; ++q) {
+    const int f = FWD ? q : nf - 1 - q;
+    for (int t = fptr[f] + threadIdx.x; t < fptr[f + 1]; t += blockDim.x) {
+      if (FWD)
+        bilu_fwd_cell<T>(cells[t], rp, ci, jv, dinv, r, w);
+      else
+        bilu_bwd_cell<T>(cells[t], rp, ci, jv, dinv, w, z);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_bilu_factor_wg(int nf, const int* __restrict__ fptr,
+                                                         const int* __restrict__ cells,
+                                                         const int* __restrict__ rp,
+                                                         const int* __restrict__ ci,
+                                                         const double* __restrict__ jv,
+                                                         double* __restrict__ dinv,
+                                                         int* __restrict__ flag) {
+  for (int f = 0; f < nf; ++f) {
+    for (int t = fptr[f] + threadIdx.x; t < fptr[f + 1]; t += blockDim.x)
+      bilu_factor_cell(cells[t], rp, ci, jv, dinv, flag);
+    __syncthreads();
+  }
 }
 
 template <class T>
@@ -306,10 +361,13 @@ void bilu_setup(tpf_precond* M, bool reuse, hipStream_t s) {
     }
     TPF_REQUIRE(ptr[nf] == N, TPF_ERR_INVALID_ARG, "wavefront ordering does not cover the grid");
     M->front_ptr = ptr;
-    Buf<int> dptr(nf + 1, s);
-    TPF_HIP(hipMemcpyAsync(dptr.p, ptr.data(), (nf + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+    M->front_max = 0;
+    for (int L = 0; L < nf; ++L) M->front_max = std::max(M->front_max, ptr[L + 1] - ptr[L]);
+    M->front_ptr_dev.alloc(nf + 1, s);
+    TPF_HIP(hipMemcpyAsync(M->front_ptr_dev.p, ptr.data(), (nf + 1) * sizeof(int),
+                           hipMemcpyHostToDevice, s));
     M->front_cells.alloc(N, s);
-    k_front_place<<<grid_for(N, 256), 256, 0, s>>>(Grid3{ph.nx, ph.ny, ph.nz}, dptr.p,
+    k_front_place<<<grid_for(N, 256), 256, 0, s>>>(Grid3{ph.nx, ph.ny, ph.nz}, M->front_ptr_dev.p,
                                                    M->front_cells.p);
     TPF_CHECK_LAUNCH();
     TPF_HIP(hipStreamSynchronize(s));
@@ -318,11 +376,17 @@ void bilu_setup(tpf_precond* M, bool reuse, hipStream_t s) {
   Buf<int> flag(1, s);
   fill_int(flag.p, 0, 1, s);
   int nf = int(M->front_ptr.size()) - 1;
-  for (int f = 0; f < nf; ++f) {
-    int a = M->front_ptr[f], cnt = M->front_ptr[f + 1] - a;
-    k_bilu_factor<<<grid_for(cnt, 256), 256, 0, s>>>(cnt, M->front_cells.p + a, J->rp.p, J->ci.p,
-                                                     J->v.p, M->bilu_dinv.p, flag.p);
+  if (M->front_max <= kFrontWg) {
+    k_bilu_factor_wg<<<1, 1024, 0, s>>>(nf, M->front_ptr_dev.p, M->front_cells.p, J->rp.p,
+                                        J->ci.p, J->v.p, M->bilu_dinv.p, flag.p);
     TPF_CHECK_LAUNCH();
+  } else {
+    for (int f = 0; f < nf; ++f) {
+      int a = M->front_ptr[f], cnt = M->front_ptr[f + 1] - a;
+      k_bilu_factor<<<grid_for(cnt, 256), 256, 0, s>>>(cnt, M->front_cells.p + a, J->rp.p,
+                                                       J->ci.p, J->v.p, M->bilu_dinv.p, flag.p);
+      TPF_CHECK_LAUNCH();
+    }
   }
   int fl = read_scalar(flag.p, s);
   TPF_REQUIRE(fl == 0, TPF_ERR_SINGULAR, "zero pivot block in block ILU(0)");
@@ -348,6 +412,15 @@ void bilu_apply(tpf_precond* M, const double* r, T* w, T* z, hipStream_t s) {
   }
   int nf = int(M->front_ptr.size()) - 1;
   TimedScope ts("bilu_solve", s);
+  if (M->front_max <= kFrontWg) {
+    k_bilu_sweep_wg<T, true><<<1, 1024, 0, s>>>(nf, M->front_ptr_dev.p, M->front_cells.p, J->rp.p,
+                                               J->ci.p, jv, dinv, r, w, z);
+    TPF_CHECK_LAUNCH();
+    k_bilu_sweep_wg<T, false><<<1, 1024, 0, s>>>(nf, M->front_ptr_dev.p, M->front_cells.p,
+                                                J->rp.p, J->ci.p, jv, dinv, r, w, z);
+    TPF_CHECK_LAUNCH();
+    return;
+  }
   for (int f = 0; f < nf; ++f) {
     int a = M->front_ptr[f], cnt = M->front_ptr[f + 1] - a;
     k_bilu_fwd<T><<<grid_for(cnt, 256), 256, 0, s>>>(cnt, M->front_cells.p + a, J->rp.p, J->ci.p,

@@ -23,6 +23,8 @@ struct tpf_precond {
   tpf::Buf<float> bilu_dinv32, jv32;
   tpf::Buf<int> front_cells;      // cells ordered by wavefront ix+iy+iz
   std::vector<int> front_ptr;     // host copy, nfronts + 1
+  tpf::Buf<int> front_ptr_dev;    // device copy
+  int front_max = 0;              // cells in the largest front
   // workspaces
   tpf::Buf<double> w1, w2, w3, w4, u2, r2;   // N or 2N
   tpf::Buf<float> f1, f2, f3, f4, fu, fr;

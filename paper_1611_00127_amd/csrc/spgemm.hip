@@ -258,7 +258,15 @@ __global__ void __launch_bounds__(BLOCK) k_spgemm_sorted(
 // B row lengths; keys (col << 32 | t) are bitonic-sorted so that equal
 // columns are adjacent in increasing t, i.e. in A's column order, and each
 // output value is the sequential sum over its run.
-template <int BLOCK, int CAP, bool FILL>
+// Keys are (column, product index) packed into KEY: 32 bits when the column
+// count leaves room for log2(CAP) index bits (the caller checks), else 64.
+template <class KEY, int CAP>
+struct FlatKey {
+  static constexpr int kIdxBits = sizeof(KEY) == 8 ? 32 : __builtin_ctz(CAP);
+  static constexpr KEY kIdxMask = (KEY(1) << kIdxBits) - 1;
+};
+
+template <int BLOCK, int CAP, bool FILL, class KEY>
 __global__ void __launch_bounds__(BLOCK) k_spgemm_flat(
     const int* __restrict__ rows, const int* __restrict__ ub, const int* __restrict__ arp,
     const int* __restrict__ aci, const double* __restrict__ av, const int* __restrict__ brp,
@@ -268,7 +276,8 @@ __global__ void __launch_bounds__(BLOCK) k_spgemm_flat(
     double* __restrict__ cv) {
   __shared__ int offs[CAP + 1];
   __shared__ int bst[CAP];  // start of B row k_e for each entry e of A's row
-  __shared__ unsigned long long keys[CAP];
+  using FK = FlatKey<KEY, CAP>;
+  __shared__ KEY keys[CAP];
   __shared__ double pv[FILL ? CAP : 1];
   __shared__ int sh[BLOCK / 64 + 1];
   int i = rows[blockIdx.x];
@@ -341,9 +350,8 @@ __global__ void __launch_bounds__(BLOCK) k_spgemm_flat(
   for (int q = 0; q < PER; ++q) {
     const int t = threadIdx.x + q * BLOCK;
     if (t < p2) {
-      keys[t] = t < u ? (static_cast<unsigned long long>(static_cast<unsigned>(col[q])) << 32) |
-                            unsigned(t)
-                      : ~0ull;
+      keys[t] = t < u ? (static_cast<KEY>(static_cast<unsigned>(col[q])) << FK::kIdxBits) | KEY(t)
+                      : ~KEY(0);
       if (FILL && t < u) pv[t] = val[q];
     }
   }
@@ -353,7 +361,7 @@ __global__ void __launch_bounds__(BLOCK) k_spgemm_flat(
       for (int t = threadIdx.x; t < p2; t += BLOCK) {
         int q = t ^ j;
         if (q > t) {
-          unsigned long long x = keys[t], y = keys[q];
+          KEY x = keys[t], y = keys[q];
           bool up = (t & k) == 0;
           if ((x > y) == up) {
             keys[t] = y;
@@ -369,15 +377,15 @@ __global__ void __launch_bounds__(BLOCK) k_spgemm_flat(
   for (int base = 0; base < p2; base += BLOCK) {
     int t = base + threadIdx.x;
     int head = 0;
-    if (t < u) head = t == 0 || (keys[t - 1] >> 32) != (keys[t] >> 32);
+    if (t < u) head = t == 0 || (keys[t - 1] >> FK::kIdxBits) != (keys[t] >> FK::kIdxBits);
     int total;
     int excl = block_exclusive_scan<int, BLOCK>(head, sh, total);
     if (FILL && head) {
-      int col = int(keys[t] >> 32);
+      int col = int(keys[t] >> FK::kIdxBits);
       double sum = 0.0, dterm = 0.0;
       bool has_d = false;
-      for (int q = t; q < u && int(keys[q] >> 32) == col; ++q) {
-        int src = int(keys[q] & 0xffffffffu);
+      for (int q = t; q < u && int(keys[q] >> FK::kIdxBits) == col; ++q) {
+        int src = int(keys[q] & FK::kIdxMask);
         if (src < nprod) {
           sum += pv[src];
         } else {
@@ -441,12 +449,73 @@ __global__ void k_transpose_fill(int nrows, const int* __restrict__ rp, const in
   }
 }
 
-// Sorts each row by column, one wavefront per row.  The columns of a row are
-// distinct, so an entry's position is the number of smaller columns in its
-// row; rows longer than kSortCap fall back to an insertion sort by one lane.
+// Ascending bitonic sort of keys[0, p2) (p2 a power of two, padded with
+// INT_MAX) carrying vals along when given; all threads of the block take
+// part.
+template <int NT>
+__device__ inline void bitonic_kv(int* keys, double* vals, int p2) {
+  for (int k = 2; k <= p2; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = threadIdx.x; t < p2; t += NT) {
+        int q = t ^ j;
+        if (q > t) {
+          int x = keys[t], y = keys[q];
+          bool up = (t & k) == 0;
+          if ((x > y) == up) {
+            keys[t] = y;
+            keys[q] = x;
+            if (vals) {
+              double vx = vals[t];
+              vals[t] = vals[q];
+              vals[q] = vx;
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+}
+
+// Sorts row i of (ci, v) by column with the NT threads of the block: rows of
+// at most 64 entries by rank (the columns of a row are distinct, so an
+// entry's position is the number of smaller columns), longer rows by a
+// bitonic sort in LDS (CAP entries at most).
+template <int NT, int CAP>
+__device__ inline void sort_row(int a, int len, int* __restrict__ ci, double* __restrict__ v,
+                                int* keys, double* vals) {
+  for (int j = threadIdx.x; j < len; j += NT) {
+    keys[j] = ci[a + j];
+    if (v) vals[j] = v[a + j];
+  }
+  if (len <= 64) {
+    __syncthreads();
+    for (int j = threadIdx.x; j < len; j += NT) {
+      int key = keys[j];
+      int rank = 0;
+      for (int m = 0; m < len; ++m) rank += keys[m] < key;
+      ci[a + rank] = key;
+      if (v) v[a + rank] = vals[j];
+    }
+    return;
+  }
+  int p2 = 1;
+  while (p2 < len) p2 <<= 1;
+  for (int j = len + threadIdx.x; j < p2; j += NT) keys[j] = INT_MAX;
+  __syncthreads();
+  bitonic_kv<NT>(keys, v ? vals : nullptr, p2);
+  for (int j = threadIdx.x; j < len; j += NT) {
+    ci[a + j] = keys[j];
+    if (v) v[a + j] = vals[j];
+  }
+}
+
+// One wavefront per row; rows longer than kSortCap are queued for
+// k_sort_long_rows.
 constexpr int kSortCap = 1024;
 __global__ void __launch_bounds__(64) k_sort_rows(int nrows, const int* __restrict__ rp,
-                                                  int* __restrict__ ci, double* __restrict__ v) {
+                                                  int* __restrict__ ci, double* __restrict__ v,
+                                                  int* __restrict__ nlong,
+                                                  int* __restrict__ long_rows) {
   __shared__ int keys[kSortCap];
   __shared__ double vals[kSortCap];
   int i = blockIdx.x;
@@ -454,32 +523,46 @@ __global__ void __launch_bounds__(64) k_sort_rows(int nrows, const int* __restri
   int a = rp[i], len = rp[i + 1] - a;
   if (len <= 1) return;
   if (len > kSortCap) {
-    if (threadIdx.x != 0) return;
-    for (int e = a + 1; e < a + len; ++e) {
-      int key = ci[e];
-      double val = v ? v[e] : 0.0;
-      int f = e - 1;
-      while (f >= a && ci[f] > key) {
-        ci[f + 1] = ci[f];
-        if (v) v[f + 1] = v[f];
-        --f;
-      }
-      ci[f + 1] = key;
-      if (v) v[f + 1] = val;
-    }
+    if (threadIdx.x == 0) long_rows[atomicAdd(nlong, 1)] = i;
     return;
   }
-  for (int j = threadIdx.x; j < len; j += 64) {
-    keys[j] = ci[a + j];
-    if (v) vals[j] = v[a + j];
-  }
-  __syncthreads();
-  for (int j = threadIdx.x; j < len; j += 64) {
-    int key = keys[j];
-    int rank = 0;
-    for (int m = 0; m < len; ++m) rank += keys[m] < key;
-    ci[a + rank] = key;
-    if (v) v[a + rank] = vals[j];
+  sort_row<64, kSortCap>(a, len, ci, v, keys, vals);
+}
+
+// The queued long rows, one 256-thread work-group per row (bitonic sort in
+// LDS up to kSortLongCap entries, else an insertion sort by one thread).  The
+// work-groups stride over the queue, whose length they read.
+constexpr int kSortLongCap = 4096;
+__global__ void __launch_bounds__(256) k_sort_long_rows(const int* __restrict__ nlong,
+                                                         const int* __restrict__ long_rows,
+                                                         const int* __restrict__ rp,
+                                                         int* __restrict__ ci,
+                                                         double* __restrict__ v) {
+  __shared__ int keys[kSortLongCap];
+  __shared__ double vals[kSortLongCap];
+  const int cnt = *nlong;
+  for (int q = blockIdx.x; q < cnt; q += gridDim.x) {
+    const int i = long_rows[q];
+    const int a = rp[i], len = rp[i + 1] - a;
+    if (len > kSortLongCap) {
+      if (threadIdx.x == 0) {
+        for (int e = a + 1; e < a + len; ++e) {
+          int key = ci[e];
+          double val = v ? v[e] : 0.0;
+          int f = e - 1;
+          while (f >= a && ci[f] > key) {
+            ci[f + 1] = ci[f];
+            if (v) v[f + 1] = v[f];
+            --f;
+          }
+          ci[f + 1] = key;
+          if (v) v[f + 1] = val;
+        }
+      }
+    } else {
+      sort_row<256, kSortLongCap>(a, len, ci, v, keys, vals);
+    }
+    __syncthreads();
   }
 }
 
@@ -536,26 +619,26 @@ void spgemm(const CsrRef<double>& A, const CsrRef<double>& B, Csr<double>& C, hi
   Buf<int2> cur;
   if (hc[kClasses - 1] > 0) cur.alloc(A.nnz > 0 ? A.nnz : 1, s);
   auto list = [&](int c) { return lists.p + int64_t(c) * n; };
-  if (hc[0] > 0)
-    k_spgemm_flat<64, 64, true><<<hc[0], 64, 0, s>>>(list(0), ub.p, A.rp, A.ci, A.v, B.rp, B.ci,
-                                                     B.v, drp, dci, dv, alpha, beta, cnt.p, toff.p,
-                                                     tci.p, tv.p);
-  if (hc[1] > 0)
-    k_spgemm_flat<64, 128, true><<<hc[1], 64, 0, s>>>(list(1), ub.p, A.rp, A.ci, A.v, B.rp, B.ci,
-                                                      B.v, drp, dci, dv, alpha, beta, cnt.p,
-                                                      toff.p, tci.p, tv.p);
-  if (hc[2] > 0)
-    k_spgemm_flat<64, 256, true><<<hc[2], 64, 0, s>>>(list(2), ub.p, A.rp, A.ci, A.v, B.rp, B.ci,
-                                                      B.v, drp, dci, dv, alpha, beta, cnt.p,
-                                                      toff.p, tci.p, tv.p);
-  if (hc[3] > 0)
-    k_spgemm_flat<64, 512, true><<<hc[3], 64, 0, s>>>(list(3), ub.p, A.rp, A.ci, A.v, B.rp, B.ci,
-                                                      B.v, drp, dci, dv, alpha, beta, cnt.p,
-                                                      toff.p, tci.p, tv.p);
-  if (hc[4] > 0)
-    k_spgemm_flat<256, 2048, true><<<hc[4], 256, 0, s>>>(list(4), ub.p, A.rp, A.ci, A.v, B.rp,
-                                                         B.ci, B.v, drp, dci, dv, alpha, beta,
-                                                         cnt.p, toff.p, tci.p, tv.p);
+  // 32-bit keys when the column count leaves room for the product index
+  auto flat = [&](auto block_tag, auto cap_tag, int c) {
+    constexpr int BL = decltype(block_tag)::value, CP = decltype(cap_tag)::value;
+    if (hc[c] == 0) return;
+    if (int64_t(B.ncols) < (int64_t(1) << (32 - __builtin_ctz(CP))))
+      k_spgemm_flat<BL, CP, true, uint32_t><<<hc[c], BL, 0, s>>>(
+          list(c), ub.p, A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha, beta, cnt.p, toff.p,
+          tci.p, tv.p);
+    else
+      k_spgemm_flat<BL, CP, true, uint64_t><<<hc[c], BL, 0, s>>>(
+          list(c), ub.p, A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha, beta, cnt.p, toff.p,
+          tci.p, tv.p);
+  };
+  using I64 = std::integral_constant<int, 64>;
+  using I256 = std::integral_constant<int, 256>;
+  flat(I64{}, std::integral_constant<int, 64>{}, 0);
+  flat(I64{}, std::integral_constant<int, 128>{}, 1);
+  flat(I64{}, std::integral_constant<int, 256>{}, 2);
+  flat(I64{}, std::integral_constant<int, 512>{}, 3);
+  flat(I256{}, std::integral_constant<int, 2048>{}, 4);
   if (hc[5] > 0)
     k_spgemm_sorted<256, 16384, true><<<hc[5], 256, 0, s>>>(list(5), ub.p, A.rp, A.ci, A.v, B.rp,
                                                             B.ci, B.v, drp, dci, dv, alpha, beta,
@@ -597,7 +680,11 @@ void transpose(const CsrRef<double>& A, Csr<double>& C, hipStream_t s) {
     TPF_CHECK_LAUNCH();
   }
   if (m > 0) {
-    k_sort_rows<<<m, 64, 0, s>>>(m, C.rp.p, C.ci.p, C.v.p);
+    Buf<int> nlong(1, s), long_rows(m, s);
+    fill_int(nlong.p, 0, 1, s);
+    k_sort_rows<<<m, 64, 0, s>>>(m, C.rp.p, C.ci.p, C.v.p, nlong.p, long_rows.p);
+    TPF_CHECK_LAUNCH();
+    k_sort_long_rows<<<64, 256, 0, s>>>(nlong.p, long_rows.p, C.rp.p, C.ci.p, C.v.p);
     TPF_CHECK_LAUNCH();
   }
 }
