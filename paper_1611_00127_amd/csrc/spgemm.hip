@@ -266,6 +266,23 @@ struct FlatKey {
   static constexpr KEY kIdxMask = (KEY(1) << kIdxBits) - 1;
 };
 
+// Compare-exchange of the bitonic stage with distance 64 * QJ inside each
+// lane's registers (element t = lane + 64 q).
+template <int QJ, int PER, class KEY>
+__device__ inline void bitonic_in_lane(KEY (&kr)[PER], int lane, int kk) {
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    if ((q & QJ) == 0 && (q | QJ) < PER) {
+      const int qp = q | QJ;
+      const bool up = ((lane + q * 64) & kk) == 0;
+      const KEY x = kr[q], y = kr[qp];
+      const bool sw = (x > y) == up;
+      kr[q] = sw ? y : x;
+      kr[qp] = sw ? x : y;
+    }
+  }
+}
+
 template <int BLOCK, int CAP, bool FILL, class KEY>
 __global__ void __launch_bounds__(BLOCK) k_spgemm_flat(
     const int* __restrict__ rows, const int* __restrict__ ub, const int* __restrict__ arp,
@@ -346,31 +363,73 @@ __global__ void __launch_bounds__(BLOCK) k_spgemm_flat(
       if (FILL) val[q] = dv[src[q]];
     }
   }
+  if constexpr (BLOCK == 64) {
+    // one wavefront: the bitonic network runs in registers, element t in
+    // lane t % 64, register t / 64; pairs in one lane are exchanged in
+    // place, pairs across lanes through shuffles
+    const int lane = threadIdx.x;
+    KEY kr[PER];
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int t = threadIdx.x + q * BLOCK;
-    if (t < p2) {
-      keys[t] = t < u ? (static_cast<KEY>(static_cast<unsigned>(col[q])) << FK::kIdxBits) | KEY(t)
-                      : ~KEY(0);
+    for (int q = 0; q < PER; ++q) {
+      const int t = lane + q * 64;
+      kr[q] = t < u ? (static_cast<KEY>(static_cast<unsigned>(col[q])) << FK::kIdxBits) | KEY(t)
+                    : ~KEY(0);
       if (FILL && t < u) pv[t] = val[q];
     }
-  }
-  __syncthreads();
-  for (int k = 2; k <= p2; k <<= 1)
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int t = threadIdx.x; t < p2; t += BLOCK) {
-        int q = t ^ j;
-        if (q > t) {
-          KEY x = keys[t], y = keys[q];
-          bool up = (t & k) == 0;
-          if ((x > y) == up) {
-            keys[t] = y;
-            keys[q] = x;
+    for (int kk = 2; kk <= p2; kk <<= 1)
+      for (int j = kk >> 1; j > 0; j >>= 1) {
+        if (j >= 64) {
+          switch (j >> 6) {
+            case 1: bitonic_in_lane<1>(kr, lane, kk); break;
+            case 2: bitonic_in_lane<2>(kr, lane, kk); break;
+            default: bitonic_in_lane<4>(kr, lane, kk); break;
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < PER; ++q) {
+            if (q * 64 >= p2) break;
+            const int t = lane + q * 64;
+            const KEY x = kr[q];
+            const KEY y = __shfl_xor(x, j, 64);
+            const bool up = (t & kk) == 0, lower = (lane & j) == 0;
+            const KEY mn = x < y ? x : y, mx = x < y ? y : x;
+            kr[q] = lower == up ? mn : mx;
           }
         }
       }
-      __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int t = lane + q * 64;
+      if (t < p2) keys[t] = kr[q];
     }
+    __syncthreads();
+  } else {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int t = threadIdx.x + q * BLOCK;
+      if (t < p2) {
+        keys[t] = t < u ? (static_cast<KEY>(static_cast<unsigned>(col[q])) << FK::kIdxBits) | KEY(t)
+                        : ~KEY(0);
+        if (FILL && t < u) pv[t] = val[q];
+      }
+    }
+    __syncthreads();
+    for (int k = 2; k <= p2; k <<= 1)
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int t = threadIdx.x; t < p2; t += BLOCK) {
+          int q = t ^ j;
+          if (q > t) {
+            KEY x = keys[t], y = keys[q];
+            bool up = (t & k) == 0;
+            if ((x > y) == up) {
+              keys[t] = y;
+              keys[q] = x;
+            }
+          }
+        }
+        __syncthreads();
+      }
+  }
   // run heads -> output positions; each head sums its run in order
   int64_t o = FILL ? toff[i] : 0;
   int count = 0;
