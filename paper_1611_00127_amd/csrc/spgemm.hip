@@ -267,14 +267,14 @@ struct FlatKey {
 };
 
 // Compare-exchange of the bitonic stage with distance 64 * QJ inside each
-// lane's registers (element t = lane + 64 q).
+// lane's registers (element t = base + 64 q, base = wavefront offset + lane).
 template <int QJ, int PER, class KEY>
-__device__ inline void bitonic_in_lane(KEY (&kr)[PER], int lane, int kk) {
+__device__ inline void bitonic_in_lane(KEY (&kr)[PER], int base, int kk) {
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     if ((q & QJ) == 0 && (q | QJ) < PER) {
       const int qp = q | QJ;
-      const bool up = ((lane + q * 64) & kk) == 0;
+      const bool up = ((base + q * 64) & kk) == 0;
       const KEY x = kr[q], y = kr[qp];
       const bool sw = (x > y) == up;
       kr[q] = sw ? y : x;
@@ -328,10 +328,12 @@ __global__ void __launch_bounds__(BLOCK) k_spgemm_flat(
   // products: each lane's CAP / BLOCK slots are located in LDS first, then
   // all their loads are issued together
   constexpr int PER = CAP / BLOCK;
+  // element t of this thread's slot q: wave w holds t in [w * 64 PER, (w + 1) * 64 PER)
+  const int lane = threadIdx.x & 63, wbase = (threadIdx.x >> 6) * 64 * PER;
   int src[PER], ent[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int t = threadIdx.x + q * BLOCK;
+    const int t = wbase + q * 64 + lane;
     src[q] = -1;
     ent[q] = 0;
     if (t < nprod) {
@@ -352,7 +354,7 @@ __global__ void __launch_bounds__(BLOCK) k_spgemm_flat(
   double val[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int t = threadIdx.x + q * BLOCK;
+    const int t = wbase + q * 64 + lane;
     col[q] = 0;
     val[q] = 0.0;
     if (t < nprod) {
@@ -363,73 +365,56 @@ __global__ void __launch_bounds__(BLOCK) k_spgemm_flat(
       if (FILL) val[q] = dv[src[q]];
     }
   }
-  if constexpr (BLOCK == 64) {
-    // one wavefront: the bitonic network runs in registers, element t in
-    // lane t % 64, register t / 64; pairs in one lane are exchanged in
-    // place, pairs across lanes through shuffles
-    const int lane = threadIdx.x;
-    KEY kr[PER];
+  // bitonic network in registers: exchanges inside a lane (distance 64 ..
+  // 32 PER) in place, across lanes (distance < 64) through shuffles, across
+  // wavefronts (distance >= 64 PER) through LDS
+  KEY kr[PER];
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int t = lane + q * 64;
-      kr[q] = t < u ? (static_cast<KEY>(static_cast<unsigned>(col[q])) << FK::kIdxBits) | KEY(t)
-                    : ~KEY(0);
-      if (FILL && t < u) pv[t] = val[q];
-    }
-    for (int kk = 2; kk <= p2; kk <<= 1)
-      for (int j = kk >> 1; j > 0; j >>= 1) {
-        if (j >= 64) {
-          switch (j >> 6) {
-            case 1: bitonic_in_lane<1>(kr, lane, kk); break;
-            case 2: bitonic_in_lane<2>(kr, lane, kk); break;
-            default: bitonic_in_lane<4>(kr, lane, kk); break;
-          }
-        } else {
+  for (int q = 0; q < PER; ++q) {
+    const int t = wbase + q * 64 + lane;
+    kr[q] = t < u ? (static_cast<KEY>(static_cast<unsigned>(col[q])) << FK::kIdxBits) | KEY(t)
+                  : ~KEY(0);
+    if (FILL && t < u) pv[t] = val[q];
+  }
+  for (int kk = 2; kk <= p2; kk <<= 1)
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      if (j >= 64 * PER) {
 #pragma unroll
-          for (int q = 0; q < PER; ++q) {
-            if (q * 64 >= p2) break;
-            const int t = lane + q * 64;
-            const KEY x = kr[q];
-            const KEY y = __shfl_xor(x, j, 64);
-            const bool up = (t & kk) == 0, lower = (lane & j) == 0;
-            const KEY mn = x < y ? x : y, mx = x < y ? y : x;
-            kr[q] = lower == up ? mn : mx;
-          }
-        }
-      }
+        for (int q = 0; q < PER; ++q) keys[wbase + q * 64 + lane] = kr[q];
+        __syncthreads();
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int t = lane + q * 64;
-      if (t < p2) keys[t] = kr[q];
-    }
-    __syncthreads();
-  } else {
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int t = threadIdx.x + q * BLOCK;
-      if (t < p2) {
-        keys[t] = t < u ? (static_cast<KEY>(static_cast<unsigned>(col[q])) << FK::kIdxBits) | KEY(t)
-                        : ~KEY(0);
-        if (FILL && t < u) pv[t] = val[q];
-      }
-    }
-    __syncthreads();
-    for (int k = 2; k <= p2; k <<= 1)
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        for (int t = threadIdx.x; t < p2; t += BLOCK) {
-          int q = t ^ j;
-          if (q > t) {
-            KEY x = keys[t], y = keys[q];
-            bool up = (t & k) == 0;
-            if ((x > y) == up) {
-              keys[t] = y;
-              keys[q] = x;
-            }
-          }
+        for (int q = 0; q < PER; ++q) {
+          const int t = wbase + q * 64 + lane;
+          const KEY x = kr[q], y = keys[t ^ j];
+          const bool up = (t & kk) == 0, lower = (t & j) == 0;
+          const KEY mn = x < y ? x : y, mx = x < y ? y : x;
+          kr[q] = lower == up ? mn : mx;
         }
         __syncthreads();
+      } else if (j >= 64) {
+        switch (j >> 6) {
+          case 1: bitonic_in_lane<1>(kr, wbase + lane, kk); break;
+          case 2: bitonic_in_lane<2>(kr, wbase + lane, kk); break;
+          default: bitonic_in_lane<4>(kr, wbase + lane, kk); break;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          const int t = wbase + q * 64 + lane;
+          const KEY x = kr[q];
+          const KEY y = __shfl_xor(x, j, 64);
+          const bool up = (t & kk) == 0, lower = (lane & j) == 0;
+          const KEY mn = x < y ? x : y, mx = x < y ? y : x;
+          kr[q] = lower == up ? mn : mx;
+        }
       }
+    }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int t = wbase + q * 64 + lane;
+    if (t < p2) keys[t] = kr[q];
   }
+  __syncthreads();
   // run heads -> output positions; each head sums its run in order
   int64_t o = FILL ? toff[i] : 0;
   int count = 0;
