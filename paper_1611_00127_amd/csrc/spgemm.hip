@@ -4,16 +4,21 @@
 //
 // Output row i has the sorted unique columns of the rows B_k, k in A_i (and
 // of D_i when a matrix is added); each value is the sum over k in A's column
-// order of A_ik B_kj, so the result is deterministic and identical for every
-// row class.  Rows are grouped by their product count ub_i:
-//   ub_i <= 512 / 2048  one wavefront / 256-thread work-group takes the
-//                       flattened product list (one load round per lane per
-//                       product), sorts (column, product index) keys in LDS
-//                       and sums each run of equal columns in order;
+// order of A_ik B_kj, so the result is deterministic.  Rows are grouped by
+// their product count ub_i:
+//   ub_i <= 64 .. 512   one wavefront, ub_i <= 2048 a 256-thread and
+//   ub_i <= 8192        a 512-thread work-group (A rows of at most 2048
+//                       entries) take the flattened product list: the
+//                       (column, product index) keys are sorted by a bitonic
+//                       network held in registers (in-lane exchanges,
+//                       shuffles across lanes, LDS only across wavefronts),
+//                       and each run of equal columns is summed in order;
 //   ub_i <= 16384       one work-group sorts the product columns, then sums
-//                       over k per output entry (B_kj by binary search);
+//                       over k per output entry;
 //   larger              one thread per row merges the sorted B rows with a
 //                       cursor each.
+// Every row is written once, at an upper-bound offset in a staging area, and
+// the rows are packed afterwards.
 #include <climits>
 #include <type_traits>
 
@@ -97,20 +102,22 @@ __global__ void k_spgemm_ub(int nrows, const int* __restrict__ arp, const int* _
 // appends row i to the list of its size class: the first class whose cap
 // holds ub[i] (flattened wavefront / work-group kernels, then the
 // sorted-columns work-group), else the last list (per-thread merge)
-constexpr int kClasses = 7;
+constexpr int kClasses = 8;
 struct Caps {
-  int c[kClasses - 1];
+  int c[kClasses - 1];   // product bound of each class
+  int la[kClasses - 1];  // bound on A's row length
 };
-__global__ void k_spgemm_classify(int nrows, const int* __restrict__ ub, Caps caps,
+__global__ void k_spgemm_classify(int nrows, const int* __restrict__ ub,
+                                  const int* __restrict__ arp, Caps caps,
                                   int* __restrict__ counts, int* __restrict__ lists) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int c = -1;
   if (i < nrows) {
-    int u = ub[i];
+    int u = ub[i], la = arp[i + 1] - arp[i];
     c = kClasses - 1;
 #pragma unroll
     for (int k = kClasses - 2; k >= 0; --k)
-      if (u <= caps.c[k]) c = k;
+      if (u <= caps.c[k] && la <= caps.la[k]) c = k;
   }
   wave_append(c, kClasses, i, nrows, counts, lists);
 }
@@ -283,7 +290,7 @@ __device__ inline void bitonic_in_lane(KEY (&kr)[PER], int base, int kk) {
   }
 }
 
-template <int BLOCK, int CAP, bool FILL, class KEY>
+template <int BLOCK, int CAP, bool FILL, class KEY, int LACAP = CAP>
 __global__ void __launch_bounds__(BLOCK) k_spgemm_flat(
     const int* __restrict__ rows, const int* __restrict__ ub, const int* __restrict__ arp,
     const int* __restrict__ aci, const double* __restrict__ av, const int* __restrict__ brp,
@@ -291,8 +298,8 @@ __global__ void __launch_bounds__(BLOCK) k_spgemm_flat(
     const int* __restrict__ dci, const double* __restrict__ dv, double alpha, double beta,
     int* __restrict__ cnt, const int64_t* __restrict__ toff, int* __restrict__ cci,
     double* __restrict__ cv) {
-  __shared__ int offs[CAP + 1];
-  __shared__ int bst[CAP];  // start of B row k_e for each entry e of A's row
+  __shared__ int offs[LACAP + 1];
+  __shared__ int bst[LACAP];  // start of B row k_e for each entry e of A's row
   using FK = FlatKey<KEY, CAP>;
   __shared__ KEY keys[CAP];
   __shared__ double pv[FILL ? CAP : 1];
@@ -395,7 +402,8 @@ __global__ void __launch_bounds__(BLOCK) k_spgemm_flat(
         switch (j >> 6) {
           case 1: bitonic_in_lane<1>(kr, wbase + lane, kk); break;
           case 2: bitonic_in_lane<2>(kr, wbase + lane, kk); break;
-          default: bitonic_in_lane<4>(kr, wbase + lane, kk); break;
+          case 4: bitonic_in_lane<4>(kr, wbase + lane, kk); break;
+          default: bitonic_in_lane<8>(kr, wbase + lane, kk); break;
         }
       } else {
 #pragma unroll
@@ -642,13 +650,14 @@ void spgemm(const CsrRef<double>& A, const CsrRef<double>& B, Csr<double>& C, hi
     C.v.alloc(1, s);
     return;
   }
-  // caps ascending: flat<64,CAP> wavefront kernels, flat<256,2048>, sorted<256,16384>
-  const Caps caps{{64, 128, 256, 512, 2048, 16384}};
+  // caps ascending: flat<64,CAP> wavefront kernels, flat<256,2048>, flat<512,8192> (A rows of
+  // at most 2048 entries), sorted<256,16384>; beyond, the per-thread merge
+  const Caps caps{{64, 128, 256, 512, 2048, 8192, 16384}, {64, 128, 256, 512, 2048, 2048, 16384}};
   Buf<int> ub(n, s), counts(kClasses, s), lists(kClasses * int64_t(n), s), cnt(n, s);
   fill_int(counts.p, 0, kClasses, s);
   k_spgemm_ub<<<grid_for(n, 256), 256, 0, s>>>(n, A.rp, A.ci, B.rp, drp, ub.p);
   TPF_CHECK_LAUNCH();
-  k_spgemm_classify<<<grid_for(n, 256), 256, 0, s>>>(n, ub.p, caps, counts.p, lists.p);
+  k_spgemm_classify<<<grid_for(n, 256), 256, 0, s>>>(n, ub.p, A.rp, caps, counts.p, lists.p);
   TPF_CHECK_LAUNCH();
   // one pass: each row writes its sorted unique entries at its upper-bound
   // offset in a staging area, then the rows are packed
@@ -664,32 +673,41 @@ void spgemm(const CsrRef<double>& A, const CsrRef<double>& B, Csr<double>& C, hi
   if (hc[kClasses - 1] > 0) cur.alloc(A.nnz > 0 ? A.nnz : 1, s);
   auto list = [&](int c) { return lists.p + int64_t(c) * n; };
   // 32-bit keys when the column count leaves room for the product index
-  auto flat = [&](auto block_tag, auto cap_tag, int c) {
+  auto flat = [&](auto block_tag, auto cap_tag, auto la_tag, int c) {
     constexpr int BL = decltype(block_tag)::value, CP = decltype(cap_tag)::value;
+    constexpr int LC = decltype(la_tag)::value;
     if (hc[c] == 0) return;
     if (int64_t(B.ncols) < (int64_t(1) << (32 - __builtin_ctz(CP))))
-      k_spgemm_flat<BL, CP, true, uint32_t><<<hc[c], BL, 0, s>>>(
+      k_spgemm_flat<BL, CP, true, uint32_t, LC><<<hc[c], BL, 0, s>>>(
           list(c), ub.p, A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha, beta, cnt.p, toff.p,
           tci.p, tv.p);
     else
-      k_spgemm_flat<BL, CP, true, uint64_t><<<hc[c], BL, 0, s>>>(
+      k_spgemm_flat<BL, CP, true, uint64_t, LC><<<hc[c], BL, 0, s>>>(
           list(c), ub.p, A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha, beta, cnt.p, toff.p,
           tci.p, tv.p);
   };
-  using I64 = std::integral_constant<int, 64>;
-  using I256 = std::integral_constant<int, 256>;
-  flat(I64{}, std::integral_constant<int, 64>{}, 0);
-  flat(I64{}, std::integral_constant<int, 128>{}, 1);
-  flat(I64{}, std::integral_constant<int, 256>{}, 2);
-  flat(I64{}, std::integral_constant<int, 512>{}, 3);
-  flat(I256{}, std::integral_constant<int, 2048>{}, 4);
-  if (hc[5] > 0)
-    k_spgemm_sorted<256, 16384, true><<<hc[5], 256, 0, s>>>(list(5), ub.p, A.rp, A.ci, A.v, B.rp,
+  using W1 = std::integral_constant<int, 64>;
+  using W4 = std::integral_constant<int, 256>;
+  using W8 = std::integral_constant<int, 512>;
+  using C64 = std::integral_constant<int, 64>;
+  using C128 = std::integral_constant<int, 128>;
+  using C256 = std::integral_constant<int, 256>;
+  using C512 = std::integral_constant<int, 512>;
+  using C2048 = std::integral_constant<int, 2048>;
+  using C8192 = std::integral_constant<int, 8192>;
+  flat(W1{}, C64{}, C64{}, 0);
+  flat(W1{}, C128{}, C128{}, 1);
+  flat(W1{}, C256{}, C256{}, 2);
+  flat(W1{}, C512{}, C512{}, 3);
+  flat(W4{}, C2048{}, C2048{}, 4);
+  flat(W8{}, C8192{}, C2048{}, 5);
+  if (hc[6] > 0)
+    k_spgemm_sorted<256, 16384, true><<<hc[6], 256, 0, s>>>(list(6), ub.p, A.rp, A.ci, A.v, B.rp,
                                                             B.ci, B.v, drp, dci, dv, alpha, beta,
                                                             cnt.p, toff.p, tci.p, tv.p);
-  if (hc[6] > 0)
-    k_spgemm_merge<true><<<grid_for(hc[6], 128), 128, 0, s>>>(
-        hc[6], list(6), A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha, beta, cur.p, cnt.p,
+  if (hc[7] > 0)
+    k_spgemm_merge<true><<<grid_for(hc[7], 128), 128, 0, s>>>(
+        hc[7], list(7), A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha, beta, cur.p, cnt.p,
         toff.p, tci.p, tv.p);
   TPF_CHECK_LAUNCH();
   C.nnz = scan_exclusive(cnt.p, C.rp.p, n, s);
