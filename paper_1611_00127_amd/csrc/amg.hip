@@ -495,7 +495,7 @@ __global__ void k_exti_classify(int n, const int* __restrict__ ub, const int* __
     else if (ub[i] <= kExtCap2) c = 2;
     else c = 3;
   }
-  wave_append(c, 4, i, n, counts, lists);
+  block_append<4, 256>(c, i, n, counts, lists);
 }
 
 __device__ inline int lds_find(const int* u, int m, int key) {

@@ -107,6 +107,37 @@ __device__ inline void wave_append(int cls, int nlists, int item, int stride, in
   }
 }
 
+// Appends `item` to list number `cls` (cls < 0: nothing) with one atomic per
+// list per work-group of BLOCK threads; every thread of the block must call
+// it.  Lists are nlists rows of `stride` entries; order inside a list is not
+// specified.
+template <int NL, int BLOCK>
+__device__ inline void block_append(int cls, int item, int stride, int* counts, int* lists) {
+  __shared__ int wcnt[BLOCK / kWave][NL];
+  __shared__ int base[NL];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  int myoff = 0;
+#pragma unroll
+  for (int c = 0; c < NL; ++c) {
+    unsigned long long b = __ballot(cls == c);
+    if (cls == c) myoff = __popcll(b & ((1ull << lane) - 1ull));
+    if (lane == 0) wcnt[w][c] = __popcll(b);
+  }
+  __syncthreads();
+  if (threadIdx.x < NL) {
+    const int c = threadIdx.x;
+    int tot = 0;
+    for (int ww = 0; ww < BLOCK / kWave; ++ww) {
+      int t = wcnt[ww][c];
+      wcnt[ww][c] = tot;
+      tot += t;
+    }
+    base[c] = tot ? atomicAdd(&counts[c], tot) : 0;
+  }
+  __syncthreads();
+  if (cls >= 0) lists[int64_t(cls) * stride + base[cls] + wcnt[w][cls] + myoff] = item;
+}
+
 // Sum / max over a group of LPR consecutive lanes (xor butterfly: every lane
 // of the group ends with the same bits).
 template <int LPR, class T>

@@ -87,16 +87,33 @@ __global__ void __launch_bounds__(128) k_spgemm_merge(
 }
 
 // ---- row classification and the sort-based product
-__global__ void k_spgemm_ub(int nrows, const int* __restrict__ arp, const int* __restrict__ aci,
-                            const int* __restrict__ brp, const int* __restrict__ drp,
-                            int* __restrict__ ub) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nrows) return;
-  int64_t t = drp ? drp[i + 1] - drp[i] : 0;
-  for (int e = arp[i]; e < arp[i + 1]; ++e) t += brp[aci[e] + 1] - brp[aci[e]];
-  int64_t la = arp[i + 1] - arp[i];
-  if (la > t) t = la;  // the flattened kernels also hold A's row in LDS
-  ub[i] = t > INT_MAX ? INT_MAX : int(t);
+// ub_i = products of row i (plus D's row), at least A's row length; LPR
+// lanes per row
+template <int LPR>
+__global__ void __launch_bounds__(256) k_spgemm_ub(int nrows, const int* __restrict__ arp,
+                                                   const int* __restrict__ aci,
+                                                   const int* __restrict__ brp,
+                                                   const int* __restrict__ drp,
+                                                   int* __restrict__ ub) {
+  int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int i = int(gid / LPR), lane = int(gid % LPR);
+  int64_t t = 0;
+  int a0 = 0, a1 = 0;
+  if (i < nrows) {
+    a0 = arp[i];
+    a1 = arp[i + 1];
+  }
+  for (int e = a0 + lane; e < a1; e += LPR) {
+    int k = aci[e];
+    t += brp[k + 1] - brp[k];
+  }
+  t = group_sum<LPR>(t);
+  if (i < nrows && lane == 0) {
+    if (drp) t += drp[i + 1] - drp[i];
+    int64_t la = a1 - a0;
+    if (la > t) t = la;  // the flattened kernels also hold A's row in LDS
+    ub[i] = t > INT_MAX ? INT_MAX : int(t);
+  }
 }
 
 // appends row i to the list of its size class: the first class whose cap
@@ -119,7 +136,7 @@ __global__ void k_spgemm_classify(int nrows, const int* __restrict__ ub,
     for (int k = kClasses - 2; k >= 0; --k)
       if (u <= caps.c[k] && la <= caps.la[k]) c = k;
   }
-  wave_append(c, kClasses, i, nrows, counts, lists);
+  block_append<kClasses, 256>(c, i, nrows, counts, lists);
 }
 
 __device__ inline int bsearch_col(const int* __restrict__ c, int lo, int hi, int key) {
@@ -655,8 +672,14 @@ void spgemm(const CsrRef<double>& A, const CsrRef<double>& B, Csr<double>& C, hi
   const Caps caps{{64, 128, 256, 512, 2048, 8192, 16384}, {64, 128, 256, 512, 2048, 2048, 16384}};
   Buf<int> ub(n, s), counts(kClasses, s), lists(kClasses * int64_t(n), s), cnt(n, s);
   fill_int(counts.p, 0, kClasses, s);
-  k_spgemm_ub<<<grid_for(n, 256), 256, 0, s>>>(n, A.rp, A.ci, B.rp, drp, ub.p);
-  TPF_CHECK_LAUNCH();
+  {
+    const int lpr = lanes_per_row(n, A.nnz);
+    DISPATCH_LPR(lpr, LL, {
+      k_spgemm_ub<LL><<<grid_for(int64_t(n) * LL, 256), 256, 0, s>>>(n, A.rp, A.ci, B.rp, drp,
+                                                                     ub.p);
+    });
+    TPF_CHECK_LAUNCH();
+  }
   k_spgemm_classify<<<grid_for(n, 256), 256, 0, s>>>(n, ub.p, A.rp, caps, counts.p, lists.p);
   TPF_CHECK_LAUNCH();
   // one pass: each row writes its sorted unique entries at its upper-bound
