@@ -166,6 +166,66 @@ __device__ inline unsigned long long group_ballot(bool f) {
 }
 
 // Lanes per row for the CSR row kernels: about four entries per lane.
+// Ascending bitonic sort of p2 keys (a power of two) held in registers:
+// element t = wbase + 64 q + lane sits in register q of lane `lane` of the
+// wavefront whose first element is wbase (wbase a multiple of 64 PER).
+// Exchanges at distance 64 .. 32 PER stay inside a lane, shorter ones go
+// through shuffles and longer ones (several wavefronts) through `lds`, which
+// must hold 64 PER entries per wavefront of the block.  All threads of the
+// block must call it.
+template <int QJ, int PER, class KEY>
+__device__ inline void bitonic_in_lane(KEY (&kr)[PER], int base, int kk) {
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    if ((q & QJ) == 0 && (q | QJ) < PER) {
+      const int qp = q | QJ;
+      const bool up = ((base + q * 64) & kk) == 0;
+      const KEY x = kr[q], y = kr[qp];
+      const bool sw = (x > y) == up;
+      kr[q] = sw ? y : x;
+      kr[qp] = sw ? x : y;
+    }
+  }
+}
+
+template <int PER, class KEY>
+__device__ inline void bitonic_regs(KEY (&kr)[PER], int wbase, int lane, int p2, KEY* lds) {
+  for (int kk = 2; kk <= p2; kk <<= 1)
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      if (j >= 64 * PER) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) lds[wbase + q * 64 + lane] = kr[q];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          const int t = wbase + q * 64 + lane;
+          const KEY x = kr[q], y = lds[t ^ j];
+          const bool up = (t & kk) == 0, lower = (t & j) == 0;
+          const KEY mn = x < y ? x : y, mx = x < y ? y : x;
+          kr[q] = lower == up ? mn : mx;
+        }
+        __syncthreads();
+      } else if (j >= 64) {
+        switch (j >> 6) {
+          case 1: bitonic_in_lane<1>(kr, wbase + lane, kk); break;
+          case 2: bitonic_in_lane<2>(kr, wbase + lane, kk); break;
+          case 4: bitonic_in_lane<4>(kr, wbase + lane, kk); break;
+          default: bitonic_in_lane<8>(kr, wbase + lane, kk); break;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          const int t = wbase + q * 64 + lane;
+          const KEY x = kr[q];
+          const KEY y = __shfl_xor(x, j, 64);
+          const bool up = (t & kk) == 0, lower = (lane & j) == 0;
+          const KEY mn = x < y ? x : y, mx = x < y ? y : x;
+          kr[q] = lower == up ? mn : mx;
+        }
+      }
+    }
+}
+
 inline int lanes_per_row(int64_t nrows, int64_t nnz) {
   double avg = nrows ? double(nnz) / double(nrows) : 1.0;
   int l = 1;

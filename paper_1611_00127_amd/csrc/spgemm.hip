@@ -290,23 +290,6 @@ struct FlatKey {
   static constexpr KEY kIdxMask = (KEY(1) << kIdxBits) - 1;
 };
 
-// Compare-exchange of the bitonic stage with distance 64 * QJ inside each
-// lane's registers (element t = base + 64 q, base = wavefront offset + lane).
-template <int QJ, int PER, class KEY>
-__device__ inline void bitonic_in_lane(KEY (&kr)[PER], int base, int kk) {
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    if ((q & QJ) == 0 && (q | QJ) < PER) {
-      const int qp = q | QJ;
-      const bool up = ((base + q * 64) & kk) == 0;
-      const KEY x = kr[q], y = kr[qp];
-      const bool sw = (x > y) == up;
-      kr[q] = sw ? y : x;
-      kr[qp] = sw ? x : y;
-    }
-  }
-}
-
 template <int BLOCK, int CAP, bool FILL, class KEY, int LACAP = CAP>
 __global__ void __launch_bounds__(BLOCK) k_spgemm_flat(
     const int* __restrict__ rows, const int* __restrict__ ub, const int* __restrict__ arp,
@@ -400,40 +383,7 @@ __global__ void __launch_bounds__(BLOCK) k_spgemm_flat(
                   : ~KEY(0);
     if (FILL && t < u) pv[t] = val[q];
   }
-  for (int kk = 2; kk <= p2; kk <<= 1)
-    for (int j = kk >> 1; j > 0; j >>= 1) {
-      if (j >= 64 * PER) {
-#pragma unroll
-        for (int q = 0; q < PER; ++q) keys[wbase + q * 64 + lane] = kr[q];
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-          const int t = wbase + q * 64 + lane;
-          const KEY x = kr[q], y = keys[t ^ j];
-          const bool up = (t & kk) == 0, lower = (t & j) == 0;
-          const KEY mn = x < y ? x : y, mx = x < y ? y : x;
-          kr[q] = lower == up ? mn : mx;
-        }
-        __syncthreads();
-      } else if (j >= 64) {
-        switch (j >> 6) {
-          case 1: bitonic_in_lane<1>(kr, wbase + lane, kk); break;
-          case 2: bitonic_in_lane<2>(kr, wbase + lane, kk); break;
-          case 4: bitonic_in_lane<4>(kr, wbase + lane, kk); break;
-          default: bitonic_in_lane<8>(kr, wbase + lane, kk); break;
-        }
-      } else {
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-          const int t = wbase + q * 64 + lane;
-          const KEY x = kr[q];
-          const KEY y = __shfl_xor(x, j, 64);
-          const bool up = (t & kk) == 0, lower = (lane & j) == 0;
-          const KEY mn = x < y ? x : y, mx = x < y ? y : x;
-          kr[q] = lower == up ? mn : mx;
-        }
-      }
-    }
+  bitonic_regs<PER>(kr, wbase, lane, p2, keys);
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int t = wbase + q * 64 + lane;
