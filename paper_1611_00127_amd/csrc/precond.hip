@@ -467,20 +467,17 @@ void apply_t(tpf_precond* M, const double* r, double* z, hipStream_t s) {
       T* uw = wsel<T>(M->r2, M->fr);  // forward sweep result
       T* uz = wsel<T>(M->u2, M->fu);
       bilu_apply<T>(M, r, uw, uz, s);
-      // u (FP64) lives in z; r' = r - J u in M->r2 (FP64)
+      // u (FP64) lives in z
       if constexpr (std::is_same<T, float>::value) {
         k_to_double<float><<<grid_for(2 * int64_t(N), 256), 256, 0, s>>>(2 * int64_t(N), uz, z);
       } else {
         copy(z, uz, 2 * int64_t(N), s);
       }
       TPF_CHECK_LAUNCH();
-      bcsr_apply(M->J, z, r, M->r2.p, s);
-      k_gather<T><<<g, 256, 0, s>>>(N, M->r2.p, 0, v1);
-      TPF_CHECK_LAUNCH();
+      // R_p (r - J u) (and R_s (r - J u) for CPR2), straight from J's blocks
+      bcsr_residual_split<T>(M->J, z, r, v1, M->o.kind == TPF_PREC_CPR2 ? v3 : nullptr, s);
       M->H[0]->vcycle<T>(v1, v2, s);
       if (M->o.kind == TPF_PREC_CPR2) {
-        k_gather<T><<<g, 256, 0, s>>>(N, M->r2.p, 1, v3);
-        TPF_CHECK_LAUNCH();
         M->H[1]->vcycle<T>(v3, v4, s);
         k_add_comp<T><<<g, 256, 0, s>>>(N, z, 1, v4);
         TPF_CHECK_LAUNCH();

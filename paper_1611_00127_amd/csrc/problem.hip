@@ -382,6 +382,64 @@ __global__ void __launch_bounds__(256) k_bcsr_spmv(int nb, const int* __restrict
   }
 }
 
+// r = b - J x split by component: the pressure rows into rp, the saturation
+// rows into rs (either may be omitted, and then its half of every block is
+// not read); outputs in T.
+template <class T, bool P, bool S>
+__global__ void __launch_bounds__(256) k_bcsr_residual_split(int nb, const int* __restrict__ rp,
+                                                             const int* __restrict__ ci,
+                                                             const double* __restrict__ v,
+                                                             const double* __restrict__ x,
+                                                             const double* __restrict__ b,
+                                                             T* __restrict__ out_p,
+                                                             T* __restrict__ out_s) {
+  int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int i = int(gid / kBcsrLanes), lane = int(gid % kBcsrLanes);
+  double y0 = 0.0, y1 = 0.0;
+  if (i < nb) {
+    for (int e = rp[i] + lane; e < rp[i + 1]; e += kBcsrLanes) {
+      int j = ci[e];
+      double2 xj = reinterpret_cast<const double2*>(x)[j];
+      const double2* blk = reinterpret_cast<const double2*>(v + 4 * int64_t(e));
+      if (P) {
+        double2 r0 = blk[0];
+        y0 += r0.x * xj.x + r0.y * xj.y;
+      }
+      if (S) {
+        double2 r1 = blk[1];
+        y1 += r1.x * xj.x + r1.y * xj.y;
+      }
+    }
+  }
+  if (P) y0 = group_sum<kBcsrLanes>(y0);
+  if (S) y1 = group_sum<kBcsrLanes>(y1);
+  if (i < nb && lane == 0) {
+    if (P) out_p[i] = T(b[2 * i] - y0);
+    if (S) out_s[i] = T(b[2 * i + 1] - y1);
+  }
+}
+
+template <class T>
+void bcsr_residual_split(const tpf_jacobian* J, const double* x, const double* b, T* out_p,
+                         T* out_s, hipStream_t s) {
+  TimedScope ts("bcsr_spmv", s);
+  unsigned g = grid_for(int64_t(J->nb) * kBcsrLanes, 256);
+  if (out_p && out_s)
+    k_bcsr_residual_split<T, true, true><<<g, 256, 0, s>>>(J->nb, J->rp.p, J->ci.p, J->v.p, x, b,
+                                                           out_p, out_s);
+  else if (out_p)
+    k_bcsr_residual_split<T, true, false><<<g, 256, 0, s>>>(J->nb, J->rp.p, J->ci.p, J->v.p, x, b,
+                                                            out_p, nullptr);
+  else
+    k_bcsr_residual_split<T, false, true><<<g, 256, 0, s>>>(J->nb, J->rp.p, J->ci.p, J->v.p, x, b,
+                                                            nullptr, out_s);
+  TPF_CHECK_LAUNCH();
+}
+template void bcsr_residual_split<double>(const tpf_jacobian*, const double*, const double*,
+                                          double*, double*, hipStream_t);
+template void bcsr_residual_split<float>(const tpf_jacobian*, const double*, const double*,
+                                         float*, float*, hipStream_t);
+
 void bcsr_apply(const tpf_jacobian* J, const double* x, const double* b, double* y,
                 hipStream_t s) {
   TimedScope ts("bcsr_spmv", s);

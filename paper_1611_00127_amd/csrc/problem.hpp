@@ -45,4 +45,8 @@ struct tpf_jacobian {
 namespace tpf {
 // y = J x, or y = b - J x when b != nullptr
 void bcsr_apply(const tpf_jacobian* J, const double* x, const double* b, double* y, hipStream_t s);
+// r = b - J x by component: pressure rows to out_p, saturation rows to out_s (either may be null)
+template <class T>
+void bcsr_residual_split(const tpf_jacobian* J, const double* x, const double* b, T* out_p,
+                         T* out_s, hipStream_t s);
 }  // namespace tpf
