@@ -394,6 +394,30 @@ __device__ inline unsigned long long lanes_below() {
   return (1ull << (threadIdx.x & 63)) - 1ull;
 }
 
+// Largest power of two below n (1 when n <= 2): the first step of the
+// binary-lifting searches over n sorted offsets.
+__device__ inline int lift_top(int n) {
+  int top = 1;
+  while (2 * top < n) top <<= 1;
+  return top;
+}
+
+// Segment of B flattened positions q[b]: the largest s < nseg with
+// off[s] <= q[b] (off ascending, off[0] = 0); the searches advance together.
+template <int B>
+__device__ inline void segment_of_batch(const int* off, int nseg, int top, const int (&q)[B],
+                                        int (&seg)[B]) {
+#pragma unroll
+  for (int b = 0; b < B; ++b) seg[b] = 0;
+  for (int step = top; step > 0; step >>= 1) {
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int c = seg[b] + step;
+      if (c < nseg && off[c] <= q[b]) seg[b] = c;
+    }
+  }
+}
+
 // Per F row i: ub = strong C entries of row i and of the rows of its strong
 // F neighbours (duplicates counted), fl = summed length of those rows, nk =
 // number of strong F neighbours.  C rows get ub = 1 (their injection entry).
@@ -419,22 +443,29 @@ __global__ void __launch_bounds__(64) k_exti_ub(int n, const int* __restrict__ r
   int a0 = rp[i], a1 = rp[i + 1];
   int64_t t = 0;
   int nk = 0;
-  for (int base = a0; base < a1; base += 64) {
-    int e = base + lane;
-    bool sc = false, sf = false;
-    int k = 0;
-    if (e < a1) {
-      k = ci[e];
-      bool m = mask[e] && k != i;
-      int8_t c = cf[k];
-      sc = m && c == kC;
-      sf = m && c == kF;
+  constexpr int RB = 4;  // row entries per lane in flight (clamped reads, one wait)
+  for (int base = a0; base < a1; base += 64 * RB) {
+    int k[RB];
+    uint8_t m[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const int e = min(base + b * 64 + lane, a1 - 1);
+      k[b] = ci[e];
+      m[b] = mask[e];
     }
-    t += sc;
-    unsigned long long b = __ballot(sf);
-    int pos = nk + __popcll(b & lanes_below());
-    if (sf && pos < kExtK) kst[pos] = k;
-    nk += __popcll(b);
+    int8_t c[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) c[b] = cf[k[b]];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const bool mm = base + b * 64 + lane < a1 && m[b] && k[b] != i;
+      const bool sc = mm && c[b] == kC, sf = mm && c[b] == kF;
+      t += sc;
+      unsigned long long bal = __ballot(sf);
+      int pos = nk + __popcll(bal & lanes_below());
+      if (sf && pos < kExtK) kst[pos] = k[b];
+      nk += __popcll(bal);
+    }
   }
   __syncthreads();
   int64_t flat = 0;
@@ -456,15 +487,26 @@ __global__ void __launch_bounds__(64) k_exti_ub(int n, const int* __restrict__ r
     if (lane < nk) ko[lane + 1] = incl;
     flat = __shfl(incl, 63, 64);
     __syncthreads();
-    for (int q = lane; q < flat; q += 64) {
-      int lo = 0, hi = nk;  // largest seg with ko[seg] <= q
-      while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (ko[mid] <= q) lo = mid;
-        else hi = mid;
+    constexpr int FB = 8;  // flattened entries per lane in flight (clamped reads, one wait)
+    const int top = lift_top(nk);
+    for (int q0 = 0; q0 < flat; q0 += 64 * FB) {
+      int q[FB], seg[FB];
+#pragma unroll
+      for (int b = 0; b < FB; ++b) q[b] = min(q0 + b * 64 + lane, int(flat) - 1);
+      segment_of_batch<FB>(ko, nk, top, q, seg);
+      int col[FB];
+      uint8_t m[FB];
+#pragma unroll
+      for (int b = 0; b < FB; ++b) {
+        const int f = kst[seg[b]] + (q[b] - ko[seg[b]]);
+        col[b] = ci[f];
+        m[b] = mask[f];
       }
-      int f = kst[lo] + (q - ko[lo]);
-      t += mask[f] && cf[ci[f]] == kC;
+      int8_t c[FB];
+#pragma unroll
+      for (int b = 0; b < FB; ++b) c[b] = cf[col[b]];
+#pragma unroll
+      for (int b = 0; b < FB; ++b) t += q0 + b * 64 + lane < flat && m[b] && c[b] == kC;
     }
   } else {
     for (int e = a0; e < a1; ++e) {
@@ -508,50 +550,89 @@ __device__ inline int lds_find(const int* u, int m, int key) {
   return (lo < m && u[lo] == key) ? lo : -1;
 }
 
+// Positions of B keys in the sorted u[0, m) (-1 when absent); top is the
+// largest power of two <= m (0 when m = 0).  The B searches advance together,
+// so their LDS reads overlap.
+template <int B>
+__device__ inline void lds_find_batch(const int* u, int m, int top, const int (&key)[B],
+                                      int (&pos)[B]) {
+  int lo[B];
+#pragma unroll
+  for (int b = 0; b < B; ++b) lo[b] = -1;  // u[lo] < key
+  for (int step = top; step > 0; step >>= 1) {
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int c = lo[b] + step;
+      if (c < m && u[c] < key[b]) lo[b] = c;
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const int p = lo[b] + 1;
+    pos[b] = (p < m && u[p] == key[b]) ? p : -1;
+  }
+}
+
 // Extended+i weights of one F row (see k_exti_fill for the formula); writes
 // the row's sorted coarse columns and weights at toff[i], its length to cnt.
+// After the candidates are sorted, every flattened neighbour entry gets its
+// candidate index once (or -2 for column i, -1 otherwise); the sums d_ik run
+// one neighbour per lane; the weights then accumulate over the neighbours k
+// in row order, one neighbour row per step.
 template <int CAP, int FCAP>
 __global__ void __launch_bounds__(64) k_exti_flat(
     const int* __restrict__ rows, const int* __restrict__ rp, const int* __restrict__ ci,
     const double* __restrict__ v, const uint8_t* __restrict__ mask, const int8_t* __restrict__ cf,
     const int* __restrict__ cidx, const int64_t* __restrict__ toff, int* __restrict__ cnt,
     int* __restrict__ pci, double* __restrict__ pv) {
+  constexpr int PC = CAP / 64;
+  constexpr int kB = 8;  // searches per lane in flight
   __shared__ int cand[CAP];
   __shared__ int uniq[CAP];
   __shared__ double w[CAP];
-  __shared__ int fcol[FCAP];
+  __shared__ int fcol[FCAP];  // column, then candidate index / -2 (column i) / -1
   __shared__ double fval[FCAP];
   __shared__ int ks[kExtK];
   __shared__ int kst[kExtK];
   __shared__ int ko[kExtK + 1];
   __shared__ double ka[kExtK];
   __shared__ double kdg[kExtK];
+  __shared__ double kd[kExtK];
   const int lane = threadIdx.x;
   const int i = rows[blockIdx.x];
   const int a0 = rp[i], a1 = rp[i + 1];
   // row i: strong C columns are candidates; strong F neighbours in row order
+  constexpr int RB = 4;  // row entries per lane in flight (clamped reads, one wait)
   int len = 0, nk = 0;
-  for (int base = a0; base < a1; base += 64) {
-    int e = base + lane;
-    bool sc = false, sf = false;
-    int k = 0;
-    if (e < a1) {
-      k = ci[e];
-      bool m = mask[e] && k != i;
-      int8_t c = cf[k];
-      sc = m && c == kC;
-      sf = m && c == kF;
+  for (int base = a0; base < a1; base += 64 * RB) {
+    int k[RB];
+    uint8_t m[RB];
+    double x[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const int e = min(base + b * 64 + lane, a1 - 1);
+      k[b] = ci[e];
+      m[b] = mask[e];
+      x[b] = v[e];
     }
-    unsigned long long b = __ballot(sc);
-    if (sc) cand[len + __popcll(b & lanes_below())] = k;
-    len += __popcll(b);
-    b = __ballot(sf);
-    if (sf) {
-      int p = nk + __popcll(b & lanes_below());
-      ks[p] = k;
-      ka[p] = v[e];
+    int8_t c[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) c[b] = cf[k[b]];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const bool mm = base + b * 64 + lane < a1 && m[b] && k[b] != i;
+      const bool sc = mm && c[b] == kC, sf = mm && c[b] == kF;
+      unsigned long long bal = __ballot(sc);
+      if (sc) cand[len + __popcll(bal & lanes_below())] = k[b];
+      len += __popcll(bal);
+      bal = __ballot(sf);
+      if (sf) {
+        int p = nk + __popcll(bal & lanes_below());
+        ks[p] = k[b];
+        ka[p] = x[b];
+      }
+      nk += __popcll(bal);
     }
-    nk += __popcll(b);
   }
   __syncthreads();
   // neighbour rows: start, length, flattened offsets
@@ -573,107 +654,164 @@ __global__ void __launch_bounds__(64) k_exti_flat(
   if (lane < nk) ko[lane + 1] = incl;
   const int flat = __shfl(incl, 63, 64);
   __syncthreads();
-  for (int q0 = 0; q0 < flat; q0 += 64) {
-    int q = q0 + lane;
-    bool c = false;
-    int col = 0;
-    if (q < flat) {
-      int lo = 0, hi = nk;
-      while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (ko[mid] <= q) lo = mid;
-        else hi = mid;
+  {
+    constexpr int FB = 8;  // flattened entries per lane in flight (clamped reads, one wait)
+    const int top = lift_top(nk);
+    for (int q0 = 0; q0 < flat; q0 += 64 * FB) {
+      int q[FB], seg[FB];
+#pragma unroll
+      for (int b = 0; b < FB; ++b) q[b] = min(q0 + b * 64 + lane, flat - 1);
+      segment_of_batch<FB>(ko, nk, top, q, seg);
+      int col[FB];
+      uint8_t m[FB];
+      double x[FB];
+#pragma unroll
+      for (int b = 0; b < FB; ++b) {
+        const int f = kst[seg[b]] + (q[b] - ko[seg[b]]);
+        col[b] = ci[f];
+        m[b] = mask[f];
+        x[b] = v[f];
       }
-      int f = kst[lo] + (q - ko[lo]);
-      col = ci[f];
-      double x = v[f];
-      fcol[q] = col;
-      fval[q] = x;
-      if (col == ks[lo]) kdg[lo] = x;
-      c = mask[f] && cf[col] == kC;
+      int8_t c[FB];
+#pragma unroll
+      for (int b = 0; b < FB; ++b) c[b] = cf[col[b]];
+#pragma unroll
+      for (int b = 0; b < FB; ++b) {
+        const bool in = q0 + b * 64 + lane < flat;
+        if (in) {
+          fcol[q[b]] = col[b];
+          fval[q[b]] = x[b];
+          if (col[b] == ks[seg[b]]) kdg[seg[b]] = x[b];
+        }
+        const bool isc = in && m[b] && c[b] == kC;
+        unsigned long long bal = __ballot(isc);
+        if (isc) cand[len + __popcll(bal & lanes_below())] = col[b];
+        len += __popcll(bal);
+      }
     }
-    unsigned long long b = __ballot(c);
-    if (c) cand[len + __popcll(b & lanes_below())] = col;
-    len += __popcll(b);
   }
-  // sorted unique candidates
+  __syncthreads();
+  // sorted unique candidates (register bitonic network, one wavefront)
   int p2 = 1;
   while (p2 < len) p2 <<= 1;
-  for (int t = len + lane; t < p2; t += 64) cand[t] = INT_MAX;
-  __syncthreads();
-  for (int k = 2; k <= p2; k <<= 1)
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int t = lane; t < p2; t += 64) {
-        int q = t ^ j;
-        if (q > t) {
-          int x = cand[t], y = cand[q];
-          bool up = (t & k) == 0;
-          if ((x > y) == up) {
-            cand[t] = y;
-            cand[q] = x;
-          }
-        }
-      }
-      __syncthreads();
+  {
+    int kr[PC];
+#pragma unroll
+    for (int q = 0; q < PC; ++q) {
+      const int t = q * 64 + lane;
+      kr[q] = t < len ? cand[t] : INT_MAX;
     }
+    bitonic_regs<PC>(kr, 0, lane, p2, cand);
+#pragma unroll
+    for (int q = 0; q < PC; ++q) cand[q * 64 + lane] = kr[q];
+  }
+  __syncthreads();
   int m = 0;
   for (int base = 0; base < p2; base += 64) {
     int t = base + lane;
-    bool f = t < p2 && cand[t] != INT_MAX && (t == 0 || cand[t - 1] != cand[t]);
+    bool f = t < len && (t == 0 || cand[t - 1] != cand[t]);
     unsigned long long b = __ballot(f);
     if (f) uniq[m + __popcll(b & lanes_below())] = cand[t];
     m += __popcll(b);
   }
   for (int t = lane; t < m; t += 64) w[t] = 0.0;
+  int top = 0;
+  if (m > 0) {
+    top = 1;
+    while (2 * top <= m) top <<= 1;
+  }
   __syncthreads();
+  // candidate index of every flattened entry (in place of its column)
+  for (int q0 = 0; q0 < flat; q0 += 64 * kB) {
+    int key[kB], pos[kB];
+#pragma unroll
+    for (int b = 0; b < kB; ++b) {
+      const int q = q0 + b * 64 + lane;
+      key[b] = q < flat ? fcol[q] : -1;
+    }
+    lds_find_batch<kB>(uniq, m, top, key, pos);
+#pragma unroll
+    for (int b = 0; b < kB; ++b) {
+      const int q = q0 + b * 64 + lane;
+      if (q < flat) fcol[q] = key[b] == i ? -2 : pos[b];
+    }
+  }
   // direct couplings; weak entries outside C^_i go to the diagonal
   double aii = 0.0, lump = 0.0;
-  for (int e = a0 + lane; e < a1; e += 64) {
-    int j = ci[e];
-    if (j == i) {
-      aii = v[e];
-      continue;
+  for (int base = a0; base < a1; base += 64 * RB) {
+    int key[RB], pos[RB];
+    double x[RB];
+    bool sfm[RB];
+    uint8_t mk[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const int e = min(base + b * 64 + lane, a1 - 1);
+      key[b] = ci[e];
+      x[b] = v[e];
+      mk[b] = mask[e];
     }
-    int t = lds_find(uniq, m, j);
-    if (t >= 0)
-      w[t] += v[e];
-    else if (!(mask[e] && cf[j] == kF))
-      lump += v[e];
+    int8_t c[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) c[b] = cf[key[b]];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) sfm[b] = mk[b] && c[b] == kF;
+    lds_find_batch<RB>(uniq, m, top, key, pos);
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const int e = base + b * 64 + lane;
+      if (e >= a1) continue;
+      const int j = key[b];
+      if (j == i)
+        aii = x[b];
+      else if (pos[b] >= 0)
+        w[pos[b]] += x[b];
+      else if (!sfm[b])
+        lump += x[b];
+    }
   }
   aii = wave_sum(aii);
   lump = wave_sum(lump);
   __syncthreads();
-  double extra = 0.0;  // uniform across lanes
-  for (int s = 0; s < nk; ++s) {
-    const int q0 = ko[s], q1 = ko[s + 1];
-    const double aik = ka[s];
-    const double sk = kdg[s] < 0.0 ? -1.0 : 1.0;
+  // d_ik: one neighbour row per lane, in row order (eight entries in flight)
+  if (lane < nk) {
+    const double sk = kdg[lane] < 0.0 ? -1.0 : 1.0;
+    const int q1 = ko[lane + 1];
     double d = 0.0;
-    for (int q = q0 + lane; q < q1; q += 64) {
-      int l = fcol[q];
-      double x = fval[q];
-      if (sk * x < 0.0 && (l == i || lds_find(uniq, m, l) >= 0)) d += x;
+    for (int q0 = ko[lane]; q0 < q1; q0 += 8) {
+      double x[8];
+      int c[8];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        x[b] = fval[min(q0 + b, q1 - 1)];
+        c[b] = fcol[min(q0 + b, q1 - 1)];
+      }
+#pragma unroll
+      for (int b = 0; b < 8; ++b)
+        if (q0 + b < q1 && sk * x[b] < 0.0 && c[b] != -1) d += x[b];
     }
-    d = __shfl(wave_sum(d), 0, 64);
+    kd[lane] = d;
+  }
+  __syncthreads();
+  double extra = 0.0, toi = 0.0;  // extra uniform across lanes, toi per lane
+  for (int s = 0; s < nk; ++s) {
+    const double aik = ka[s], d = kd[s];
     if (d == 0.0) {
       extra += aik;
       continue;
     }
-    double toi = 0.0;
-    for (int q = q0 + lane; q < q1; q += 64) {
-      double x = fval[q];
+    const double sk = kdg[s] < 0.0 ? -1.0 : 1.0;
+    for (int q = ko[s] + lane; q < ko[s + 1]; q += 64) {
+      const double x = fval[q];
       if (!(sk * x < 0.0)) continue;
-      int l = fcol[q];
-      int t = lds_find(uniq, m, l);
+      const int t = fcol[q];
       if (t >= 0)
         w[t] += aik * x / d;
-      else if (l == i)
+      else if (t == -2)
         toi += aik * x / d;
     }
-    extra += __shfl(wave_sum(toi), 0, 64);
     __syncthreads();
   }
-  double atil = __shfl(aii + lump, 0, 64) + extra;
+  const double atil = __shfl(aii + lump, 0, 64) + extra + __shfl(wave_sum(toi), 0, 64);
   __syncthreads();
   const int64_t o = toff[i];
   for (int t = lane; t < m; t += 64) {

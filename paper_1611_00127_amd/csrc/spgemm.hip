@@ -124,8 +124,9 @@ struct Caps {
   int c[kClasses - 1];   // product bound of each class
   int la[kClasses - 1];  // bound on A's row length
 };
+// smallest class from `first` on whose bounds the row fits
 __global__ void k_spgemm_classify(int nrows, const int* __restrict__ ub,
-                                  const int* __restrict__ arp, Caps caps,
+                                  const int* __restrict__ arp, Caps caps, int first,
                                   int* __restrict__ counts, int* __restrict__ lists) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int c = -1;
@@ -134,7 +135,7 @@ __global__ void k_spgemm_classify(int nrows, const int* __restrict__ ub,
     c = kClasses - 1;
 #pragma unroll
     for (int k = kClasses - 2; k >= 0; --k)
-      if (u <= caps.c[k] && la <= caps.la[k]) c = k;
+      if (k >= first && u <= caps.c[k] && la <= caps.la[k]) c = k;
   }
   block_append<kClasses, 256>(c, i, nrows, counts, lists);
 }
@@ -277,12 +278,13 @@ __global__ void __launch_bounds__(BLOCK) k_spgemm_sorted(
   }
 }
 
-// Flattened product list (rows with at most CAP products and CAP entries in
-// A's row): product t of row i is (e, p) with e found from the prefix of the
-// B row lengths; keys (col << 32 | t) are bitonic-sorted so that equal
-// columns are adjacent in increasing t, i.e. in A's column order, and each
-// output value is the sequential sum over its run.
-// Keys are (column, product index) packed into KEY: 32 bits when the column
+// Flattened product list (rows with at most CAP products and LACAP entries
+// in A's row): product t of row i is (e, p) with e the last entry of A's row
+// whose B-row prefix offset is <= t.  Keys (col << bits | t) are
+// bitonic-sorted, so equal columns are adjacent in increasing t, i.e. in A's
+// column order; each output value is the sum over its run, formed by the
+// threads holding the run's pieces (contiguous chunks of the sorted keys) and
+// a segmented scan across the threads.  Keys are 32 bits when the column
 // count leaves room for log2(CAP) index bits (the caller checks), else 64.
 template <class KEY, int CAP>
 struct FlatKey {
@@ -290,20 +292,60 @@ struct FlatKey {
   static constexpr KEY kIdxMask = (KEY(1) << kIdxBits) - 1;
 };
 
-template <int BLOCK, int CAP, bool FILL, class KEY, int LACAP = CAP>
-__global__ void __launch_bounds__(BLOCK) k_spgemm_flat(
+// Partial run sums: f = a run starts in the piece, (s, d) = product sum and
+// added-matrix term since the last start.
+struct RunPart {
+  int f;
+  double s, d;
+};
+__device__ inline RunPart run_combine(const RunPart& a, const RunPart& b) {
+  return b.f ? b : RunPart{a.f, a.s + b.s, a.d + b.d};
+}
+
+// Exclusive segmented scan of RunPart over the block's threads in thread
+// order (fixed combination order).  sh: BLOCK / 64 entries.
+template <int BLOCK>
+__device__ inline RunPart run_scan_exclusive(RunPart x, RunPart* sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    RunPart y{__shfl_up(x.f, off, 64), __shfl_up(x.s, off, 64), __shfl_up(x.d, off, 64)};
+    if (lane >= off) x = run_combine(y, x);
+  }
+  RunPart ex{__shfl_up(x.f, 1, 64), __shfl_up(x.s, 1, 64), __shfl_up(x.d, 1, 64)};
+  if (lane == 0) ex = RunPart{0, 0.0, 0.0};
+  if (BLOCK > 64) {
+    if (lane == 63) sh[wid] = x;
+    __syncthreads();
+    RunPart c{0, 0.0, 0.0};
+    for (int w = 0; w < wid; ++w) c = run_combine(c, sh[w]);
+    ex = lane == 0 ? c : run_combine(c, ex);
+  }
+  return ex;
+}
+
+template <int BLOCK, int CAP, class KEY, int LACAP = CAP>
+__global__ void __launch_bounds__(BLOCK, BLOCK == 64 ? 8 : (BLOCK == 256 ? 4 : 2)) k_spgemm_flat(
     const int* __restrict__ rows, const int* __restrict__ ub, const int* __restrict__ arp,
     const int* __restrict__ aci, const double* __restrict__ av, const int* __restrict__ brp,
     const int* __restrict__ bci, const double* __restrict__ bv, const int* __restrict__ drp,
     const int* __restrict__ dci, const double* __restrict__ dv, double alpha, double beta,
     int* __restrict__ cnt, const int64_t* __restrict__ toff, int* __restrict__ cci,
     double* __restrict__ cv) {
-  __shared__ int offs[LACAP + 1];
-  __shared__ int bst[LACAP];  // start of B row k_e for each entry e of A's row
   using FK = FlatKey<KEY, CAP>;
-  __shared__ KEY keys[CAP];
-  __shared__ double pv[FILL ? CAP : 1];
+  // LDS: the B-row prefix offsets and row starts of A's entries live until
+  // every product is located; the product values then take their place
+  // (the sorted keys follow the values and are written after the sort)
+  constexpr int kValBytes = CAP * int(sizeof(double));
+  static_assert((2 * LACAP + 1) * int(sizeof(int)) <= kValBytes + CAP * int(sizeof(KEY)),
+                "offsets must fit in the value and key areas");
+  __shared__ __attribute__((aligned(16))) unsigned char lds[kValBytes + CAP * sizeof(KEY)];
+  int* offs = reinterpret_cast<int*>(lds);      // LACAP + 1 entries
+  int* bst = offs + LACAP + 1;                  // start of B row k_e for each entry e
+  double* pv = reinterpret_cast<double*>(lds);  // CAP product values
+  KEY* keys = reinterpret_cast<KEY*>(lds + kValBytes);
   __shared__ int sh[BLOCK / 64 + 1];
+  __shared__ RunPart rsh[BLOCK / 64];
   int i = rows[blockIdx.x];
   int a0 = arp[i], a1 = arp[i + 1];
   int la = a1 - a0;
@@ -331,57 +373,62 @@ __global__ void __launch_bounds__(BLOCK) k_spgemm_flat(
   int u = nprod + nd;
   int p2 = 1;
   while (p2 < u) p2 <<= 1;
+  int top = 1;  // largest power of two below la
+  while (2 * top < la) top <<= 1;
   __syncthreads();
-  // products: each lane's CAP / BLOCK slots are located in LDS first, then
-  // all their loads are issued together
+  // products: each lane's CAP / BLOCK slots are located in LDS first (the
+  // searches of all slots advance together), then all their loads are issued
+  // before the first wait: every slot reads a valid position (slots past the
+  // B products repeat the last one, or read D's row), values are selected after
   constexpr int PER = CAP / BLOCK;
   // element t of this thread's slot q: wave w holds t in [w * 64 PER, (w + 1) * 64 PER)
   const int lane = threadIdx.x & 63, wbase = (threadIdx.x >> 6) * 64 * PER;
-  int src[PER], ent[PER];
+  int ent[PER];
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int t = wbase + q * 64 + lane;
-    src[q] = -1;
-    ent[q] = 0;
-    if (t < nprod) {
-      int lo = 0, hi = la;  // largest e with offs[e] <= t
-      while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (offs[mid] <= t) lo = mid;
-        else hi = mid;
-      }
-      while (lo + 1 < la && offs[lo + 1] <= t) ++lo;  // skip empty B rows
-      src[q] = bst[lo] + (t - offs[lo]);
-      ent[q] = lo;
-    } else if (t < u) {
-      src[q] = drp[i] + (t - nprod);
+  for (int q = 0; q < PER; ++q) ent[q] = 0;
+  const int tlast = nprod - 1;
+  for (int step = top; step > 0; step >>= 1) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int t = min(wbase + q * 64 + lane, tlast);
+      const int c = ent[q] + step;  // largest e with offs[e] <= t
+      if (c < la && offs[c] <= t) ent[q] = c;
     }
   }
+  const int d0 = nd > 0 ? drp[i] : 0;
   int col[PER];
   double val[PER];
+  if (u > 0) {
+    double x[PER], a[PER];
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int t = wbase + q * 64 + lane;
-    col[q] = 0;
-    val[q] = 0.0;
-    if (t < nprod) {
-      col[q] = bci[src[q]];
-      if (FILL) val[q] = av[a0 + ent[q]] * bv[src[q]];
-    } else if (t < u) {
-      col[q] = dci[src[q]];
-      if (FILL) val[q] = dv[src[q]];
+    for (int q = 0; q < PER; ++q) {
+      const int t = wbase + q * 64 + lane;
+      const bool fromb = nprod > 0 && (t < nprod || nd == 0);
+      const int tb = min(t, tlast);
+      const int idx = fromb ? bst[ent[q]] + (tb - offs[ent[q]]) : d0 + min(max(t - nprod, 0), nd - 1);
+      const int* cp = fromb ? bci : dci;
+      const double* vp = fromb ? bv : dv;
+      col[q] = cp[idx];
+      x[q] = vp[idx];
+      a[q] = la > 0 ? av[a0 + ent[q]] : 1.0;
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int t = wbase + q * 64 + lane;
+      val[q] = t < nprod ? a[q] * x[q] : x[q];
     }
   }
   // bitonic network in registers: exchanges inside a lane (distance 64 ..
   // 32 PER) in place, across lanes (distance < 64) through shuffles, across
   // wavefronts (distance >= 64 PER) through LDS
   KEY kr[PER];
+  __syncthreads();  // offsets and row starts are dead: values take their place
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int t = wbase + q * 64 + lane;
     kr[q] = t < u ? (static_cast<KEY>(static_cast<unsigned>(col[q])) << FK::kIdxBits) | KEY(t)
                   : ~KEY(0);
-    if (FILL && t < u) pv[t] = val[q];
+    if (t < u) pv[t] = val[q];
   }
   bitonic_regs<PER>(kr, wbase, lane, p2, keys);
 #pragma unroll
@@ -390,34 +437,56 @@ __global__ void __launch_bounds__(BLOCK) k_spgemm_flat(
     if (t < p2) keys[t] = kr[q];
   }
   __syncthreads();
-  // run heads -> output positions; each head sums its run in order
-  int64_t o = FILL ? toff[i] : 0;
-  int count = 0;
-  for (int base = 0; base < p2; base += BLOCK) {
-    int t = base + threadIdx.x;
-    int head = 0;
-    if (t < u) head = t == 0 || (keys[t - 1] >> FK::kIdxBits) != (keys[t] >> FK::kIdxBits);
-    int total;
-    int excl = block_exclusive_scan<int, BLOCK>(head, sh, total);
-    if (FILL && head) {
-      int col = int(keys[t] >> FK::kIdxBits);
-      double sum = 0.0, dterm = 0.0;
-      bool has_d = false;
-      for (int q = t; q < u && int(keys[q] >> FK::kIdxBits) == col; ++q) {
-        int src = int(keys[q] & FK::kIdxMask);
-        if (src < nprod) {
-          sum += pv[src];
-        } else {
-          dterm = pv[src];
-          has_d = true;
-        }
-      }
-      double val = alpha * sum;
-      if (has_d) val = beta * dterm + val;
-      cci[o + count + excl] = col;
-      cv[o + count + excl] = val;
+  // run sums: thread j takes the sorted elements [j PER, (j + 1) PER)
+  const int t0 = threadIdx.x * PER;
+  int rc[PER];
+  double rv[PER];
+  bool rd[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    rc[q] = -1;
+    rv[q] = 0.0;
+    rd[q] = false;
+    if (t0 + q < u) {
+      const KEY k = keys[t0 + q];
+      const int e = int(k & FK::kIdxMask);
+      rc[q] = int(k >> FK::kIdxBits);
+      rv[q] = pv[e];
+      rd[q] = e >= nprod;
     }
-    count += total;
+  }
+  const int cprev = (t0 > 0 && t0 < u) ? int(keys[t0 - 1] >> FK::kIdxBits) : -1;
+  const int cnext = (t0 + PER < u) ? int(keys[t0 + PER] >> FK::kIdxBits) : -1;
+  RunPart part{0, 0.0, 0.0};
+  int heads = 0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    if (t0 + q >= u) break;
+    if (rc[q] != (q ? rc[q - 1] : cprev)) {
+      part = RunPart{1, 0.0, 0.0};
+      ++heads;
+    }
+    if (rd[q]) part.d += rv[q];
+    else part.s += rv[q];
+  }
+  int count;
+  const int hx = block_exclusive_scan<int, BLOCK>(heads, sh, count);
+  RunPart acc = run_scan_exclusive<BLOCK>(part, rsh);
+  const int64_t o = toff[i];
+  int r = hx - 1;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    if (t0 + q >= u) break;
+    if (rc[q] != (q ? rc[q - 1] : cprev)) {
+      acc = RunPart{1, 0.0, 0.0};
+      ++r;
+    }
+    if (rd[q]) acc.d += rv[q];
+    else acc.s += rv[q];
+    if (rc[q] != (q + 1 < PER ? rc[q + 1] : cnext)) {
+      cci[o + r] = rc[q];
+      cv[o + r] = beta * acc.d + alpha * acc.s;
+    }
   }
   if (threadIdx.x == 0) cnt[i] = count;
 }
@@ -585,10 +654,30 @@ __global__ void __launch_bounds__(256) k_sort_long_rows(const int* __restrict__ 
   }
 }
 
+// Flags (bad = 1) a CSR matrix whose row pointers are not a non-decreasing
+// sequence from 0 to nnz or whose rows are not strictly increasing column
+// lists within [0, ncols).
+__global__ void k_csr_check(int nrows, int ncols, int64_t nnz, const int* __restrict__ rp,
+                            const int* __restrict__ ci, int* __restrict__ bad) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  int64_t a = rp[i], b = rp[i + 1];
+  bool ok = 0 <= a && a <= b && b <= nnz && (i > 0 || a == 0) && (i < nrows - 1 || b == nnz);
+  if (ok)
+    for (int64_t e = a; e < b; ++e) {
+      int c = ci[e];
+      if (c < 0 || c >= ncols || (e > a && ci[e - 1] >= c)) {
+        ok = false;
+        break;
+      }
+    }
+  if (!ok) atomicOr(bad, 1);
+}
+
 }  // namespace
 
 void spgemm(const CsrRef<double>& A, const CsrRef<double>& B, Csr<double>& C, hipStream_t s,
-            const CsrRef<double>* D, double alpha, double beta, bool reuse) {
+            const CsrRef<double>* D, double alpha, double beta, bool reuse, int first_class) {
   TPF_REQUIRE(A.ncols == B.nrows, TPF_ERR_INVALID_ARG, "spgemm: inner dimensions differ (%d vs %d)",
               A.ncols, B.nrows);
   if (D)
@@ -630,7 +719,8 @@ void spgemm(const CsrRef<double>& A, const CsrRef<double>& B, Csr<double>& C, hi
     });
     TPF_CHECK_LAUNCH();
   }
-  k_spgemm_classify<<<grid_for(n, 256), 256, 0, s>>>(n, ub.p, A.rp, caps, counts.p, lists.p);
+  k_spgemm_classify<<<grid_for(n, 256), 256, 0, s>>>(n, ub.p, A.rp, caps, first_class, counts.p,
+                                                      lists.p);
   TPF_CHECK_LAUNCH();
   // one pass: each row writes its sorted unique entries at its upper-bound
   // offset in a staging area, then the rows are packed
@@ -651,11 +741,11 @@ void spgemm(const CsrRef<double>& A, const CsrRef<double>& B, Csr<double>& C, hi
     constexpr int LC = decltype(la_tag)::value;
     if (hc[c] == 0) return;
     if (int64_t(B.ncols) < (int64_t(1) << (32 - __builtin_ctz(CP))))
-      k_spgemm_flat<BL, CP, true, uint32_t, LC><<<hc[c], BL, 0, s>>>(
+      k_spgemm_flat<BL, CP, uint32_t, LC><<<hc[c], BL, 0, s>>>(
           list(c), ub.p, A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha, beta, cnt.p, toff.p,
           tci.p, tv.p);
     else
-      k_spgemm_flat<BL, CP, true, uint64_t, LC><<<hc[c], BL, 0, s>>>(
+      k_spgemm_flat<BL, CP, uint64_t, LC><<<hc[c], BL, 0, s>>>(
           list(c), ub.p, A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha, beta, cnt.p, toff.p,
           tci.p, tv.p);
   };
@@ -724,4 +814,80 @@ void transpose(const CsrRef<double>& A, Csr<double>& C, hipStream_t s) {
   }
 }
 
+// Checks a caller's CSR matrix (see k_csr_check); synchronises the stream.
+static void check_csr(const CsrRef<double>& M, const char* name, hipStream_t s) {
+  TPF_REQUIRE(M.nrows >= 0 && M.ncols >= 0 && M.nnz >= 0 && M.rp && (M.nnz == 0 || M.ci),
+              TPF_ERR_INVALID_ARG, "tpf_csr_product: %s has invalid sizes or pointers", name);
+  TPF_REQUIRE(M.nnz <= INT_MAX, TPF_ERR_INVALID_ARG, "tpf_csr_product: %s has more than 2^31 entries",
+              name);
+  Buf<int> bad(1, s);
+  fill_int(bad.p, 0, 1, s);
+  if (M.nrows > 0) {
+    k_csr_check<<<grid_for(M.nrows, 256), 256, 0, s>>>(M.nrows, M.ncols, M.nnz, M.rp, M.ci, bad.p);
+    TPF_CHECK_LAUNCH();
+  }
+  TPF_REQUIRE(read_scalar(bad.p, s) == 0, TPF_ERR_INVALID_ARG,
+              "tpf_csr_product: %s is not a CSR matrix with sorted, in-range columns", name);
+}
+
 }  // namespace tpf
+
+extern "C" int tpf_csr_product(const tpf_csr_view* A, const tpf_csr_view* B,
+                               const tpf_csr_view* D, double alpha, double beta, int route,
+                               int pattern_given, int* c_row_ptr, int* c_col_idx, double* c_vals,
+                               int64_t c_cap, int64_t* c_nnz, void* stream) {
+  using namespace tpf;
+  return guarded([&] {
+    TPF_REQUIRE(A && B && c_row_ptr && c_nnz, TPF_ERR_INVALID_ARG, "tpf_csr_product: null argument");
+    TPF_REQUIRE((A->vals || A->nnz == 0) && (B->vals || B->nnz == 0) &&
+                    (!D || D->vals || D->nnz == 0),
+                TPF_ERR_INVALID_ARG, "tpf_csr_product: values are required");
+    TPF_REQUIRE(route >= 0 && route <= kClasses, TPF_ERR_INVALID_ARG,
+                "tpf_csr_product: route %d outside [0, %d]", route, kClasses);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto view = [](const tpf_csr_view* v) {
+      return CsrRef<double>{v->n_rows, v->n_cols, v->nnz, v->row_ptr, v->col_idx, v->vals};
+    };
+    const CsrRef<double> a = view(A), b = view(B);
+    CsrRef<double> d;
+    check_csr(a, "A", s);
+    check_csr(b, "B", s);
+    if (D) {
+      d = view(D);
+      check_csr(d, "D", s);
+    }
+    TPF_REQUIRE(a.ncols == b.nrows, TPF_ERR_INVALID_ARG,
+                "tpf_csr_product: inner dimensions differ (%d vs %d)", a.ncols, b.nrows);
+    const int n = a.nrows;
+    Csr<double> C;
+    if (pattern_given) {
+      TPF_REQUIRE(c_col_idx && c_vals, TPF_ERR_INVALID_ARG, "tpf_csr_product: pattern missing");
+      const CsrRef<double> cp{n, b.ncols, 0, c_row_ptr, c_col_idx, nullptr};
+      int64_t nnz = read_scalar(c_row_ptr + n, s);
+      TPF_REQUIRE(nnz >= 0 && nnz <= c_cap, TPF_ERR_INVALID_ARG,
+                  "tpf_csr_product: pattern has %lld entries, capacity %lld", (long long)nnz,
+                  (long long)c_cap);
+      check_csr(CsrRef<double>{cp.nrows, cp.ncols, nnz, cp.rp, cp.ci, nullptr}, "C", s);
+      C.nrows = n;
+      C.ncols = b.ncols;
+      C.nnz = nnz;
+      C.rp.alloc(n + 1, s);
+      copy(C.rp.p, c_row_ptr, n + 1, s);
+      C.ci.alloc(nnz > 0 ? nnz : 1, s);
+      copy(C.ci.p, c_col_idx, nnz, s);
+      C.v.alloc(nnz > 0 ? nnz : 1, s);
+      spgemm(a, b, C, s, D ? &d : nullptr, alpha, beta, true);
+      copy(c_vals, C.v.p, nnz, s);
+      *c_nnz = nnz;
+    } else {
+      spgemm(a, b, C, s, D ? &d : nullptr, alpha, beta, false, route > 0 ? route - 1 : 0);
+      copy(c_row_ptr, C.rp.p, n + 1, s);
+      *c_nnz = C.nnz;
+      if (C.nnz <= c_cap && c_col_idx && c_vals) {
+        copy(c_col_idx, C.ci.p, C.nnz, s);
+        copy(c_vals, C.v.p, C.nnz, s);
+      }
+    }
+    TPF_HIP(hipStreamSynchronize(s));
+  });
+}

@@ -198,10 +198,11 @@ void csr_residual(const CsrRef<T>& A, const T* x, const T* b, T* y, hipStream_t 
 
 // ---------------------------------------------------------------- spgemm / transpose
 // C = alpha * A * B (+ beta * D on the union pattern if D != nullptr).  When
-// reuse is true, C's pattern is kept and only values are recomputed.
+// reuse is true, C's pattern is kept and only values are recomputed.  Rows go
+// to the smallest kernel class (by product count) from first_class on.
 void spgemm(const CsrRef<double>& A, const CsrRef<double>& B, Csr<double>& C, hipStream_t s,
             const CsrRef<double>* D = nullptr, double alpha = 1.0, double beta = 1.0,
-            bool reuse = false);
+            bool reuse = false, int first_class = 0);
 // C = A^T (values copied when A.v != nullptr); rows of C sorted by column
 void transpose(const CsrRef<double>& A, Csr<double>& C, hipStream_t s);
 

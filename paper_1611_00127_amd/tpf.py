@@ -154,6 +154,10 @@ _SIGS = {
                                        ctypes.POINTER(c_void_p), ctypes.POINTER(c_int)]),
     "tpf_precond_bilu_dinv": (c_int, [c_void_p, ctypes.POINTER(c_void_p)]),
     "tpf_precond_vcycle": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
+    "tpf_csr_product": (c_int, [ctypes.POINTER(CsrView), ctypes.POINTER(CsrView),
+                                ctypes.POINTER(CsrView), c_double, c_double, c_int, c_int,
+                                c_void_p, c_void_p, c_void_p, c_int64, ctypes.POINTER(c_int64),
+                                c_void_p]),
     "tpf_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(SolveOpts),
                           ctypes.POINTER(SolveInfo), c_void_p]),
     "tpf_server_default_opts": (c_int, [ctypes.POINTER(ServerOpts)]),
@@ -373,6 +377,43 @@ def tpf_precond_bilu_dinv(M):
 
 def tpf_precond_vcycle(M, hier, b, x, stream=None):
     _check(load().tpf_precond_vcycle(M, hier, _ptr(b), _ptr(x), _stream(stream)))
+
+
+def _csr_arg(m):
+    """CsrView of a (row_ptr, col_idx, vals, n_cols) tuple of device tensors."""
+    rp, ci, v, ncols = m
+    return CsrView(len(rp) - 1, int(ncols), len(ci), _ptr(rp).value, _ptr(ci).value,
+                   _ptr(v).value)
+
+
+def tpf_csr_product(A, B, D=None, alpha=1.0, beta=1.0, route=0, pattern=None, stream=None):
+    """C = alpha A B (+ beta D).  A, B, D: (row_ptr, col_idx, vals, n_cols) with
+    int32 / float64 device tensors.  Returns (row_ptr, col_idx, vals) device
+    tensors; with pattern = (row_ptr, col_idx) only the values are computed."""
+    import torch
+    lib = load()
+    a, b = _csr_arg(A), _csr_arg(B)
+    d = ctypes.byref(_csr_arg(D)) if D is not None else None
+    n = len(A[0]) - 1
+    dev = A[0].device
+    nnz = c_int64()
+    if pattern is not None:
+        rp, ci = pattern
+        v = torch.empty(max(len(ci), 1), dtype=torch.float64, device=dev)
+        _check(lib.tpf_csr_product(ctypes.byref(a), ctypes.byref(b), d, alpha, beta, route, 1,
+                                   _ptr(rp), _ptr(ci), _ptr(v), len(ci), ctypes.byref(nnz),
+                                   _stream(stream)))
+        return rp, ci, v[:len(ci)]
+    rp = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    _check(lib.tpf_csr_product(ctypes.byref(a), ctypes.byref(b), d, alpha, beta, route, 0,
+                               _ptr(rp), None, None, 0, ctypes.byref(nnz), _stream(stream)))
+    m = nnz.value
+    ci = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+    v = torch.empty(max(m, 1), dtype=torch.float64, device=dev)
+    _check(lib.tpf_csr_product(ctypes.byref(a), ctypes.byref(b), d, alpha, beta, route, 0,
+                               _ptr(rp), _ptr(ci), _ptr(v), m, ctypes.byref(nnz),
+                               _stream(stream)))
+    return rp, ci[:m], v[:m]
 
 
 def tpf_solve(J, M, b, x, rtol=1e-8, restart=30, maxit=1000, stream=None):
