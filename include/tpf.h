@@ -21,7 +21,7 @@
  *     i = ix + nx*(iy + ny*iz).  They are owned by the caller.
  *   - Handles are owned by the library and released with the matching
  *     *_destroy call; their device memory comes from the allocator installed
- *     with tpf_set_allocator (hipMalloc/hipFree if none).
+ *     with tpf_set_allocator (the device's stream-ordered pool if none).
  *   - All device work is ordered on the hipStream_t passed as `stream`
  *     (NULL = the null stream).  Only tpf_solve, the setup of a
  *     preconditioner (which reads level sizes back) and tpf_kernel_stats
@@ -58,11 +58,16 @@ int tpf_last_error(char* buf, size_t n);
 typedef void* (*tpf_alloc_fn)(size_t bytes, void* stream, void* ctx);
 typedef void (*tpf_free_fn)(void* ptr, void* stream, void* ctx);
 /* Installs the device allocator used for all library memory (e.g. a caching
- * allocator of the host framework).  Pass NULLs to return to hipMalloc.
- * Must not change while handles allocated with the previous one live. */
+ * allocator of the host framework).  With NULLs (the default) the library
+ * allocates from the current device's stream-ordered memory pool
+ * (hipMallocAsync / hipFreeAsync), which keeps freed blocks cached.  Must
+ * not change while handles allocated with the previous one live. */
 int tpf_set_allocator(tpf_alloc_fn alloc, tpf_free_fn free_fn, void* ctx);
 /* Bytes currently held by the library through the allocator. */
 int tpf_memory_in_use(size_t* bytes);
+/* Returns the blocks the default pool of the current device keeps cached
+ * (synchronises the device).  No effect on an installed allocator. */
+int tpf_release_cached_memory(void);
 
 /* ---- problem (Sec. 2) -------------------------------------------------- */
 #define TPF_PC_BROOKS_COREY 0 /* P_c = P_d Sb^(-1/lambda), C1-linear below s_eps */

@@ -192,6 +192,66 @@ __global__ void k_pmis_update(int n, const int* __restrict__ srp, const int* __r
   if ((threadIdx.x & 63) == 0 && b) atomicAdd(undecided, int(__popcll(b)));
 }
 
+// All PMIS rounds of a small level in one work-group (the same select and
+// update steps as the two kernels above, with block barriers between them);
+// rounds[0] receives the number of rounds, or -1 if n + 1 rounds left
+// points undecided.
+constexpr int kPmisWg = 1024;
+constexpr int kPmisWgMax = 16384;  // levels up to this size use it
+__global__ void __launch_bounds__(kPmisWg) k_pmis_block(
+    int n, const int* __restrict__ srp, const int* __restrict__ sci,
+    const int* __restrict__ strp, const int* __restrict__ stci, const double* __restrict__ w,
+    int8_t* __restrict__ state, uint8_t* __restrict__ newc, int* __restrict__ rounds) {
+  __shared__ int left;
+  int r = 0;
+  while (true) {
+    if (threadIdx.x == 0) left = 0;
+    for (int i = threadIdx.x; i < n; i += kPmisWg) {
+      bool sel = state[i] == kUndecided;
+      if (sel) {
+        const double wi = w[i];
+        for (int e = srp[i]; e < srp[i + 1] && sel; ++e) {
+          const int j = sci[e];
+          if (state[j] == kUndecided && beats(w[j], j, wi, i)) sel = false;
+        }
+        for (int e = strp[i]; e < strp[i + 1] && sel; ++e) {
+          const int j = stci[e];
+          if (state[j] == kUndecided && beats(w[j], j, wi, i)) sel = false;
+        }
+      }
+      newc[i] = sel;
+    }
+    __syncthreads();
+    int und = 0;
+    for (int i = threadIdx.x; i < n; i += kPmisWg) {
+      if (state[i] != kUndecided) continue;
+      if (newc[i]) {
+        state[i] = kC;
+        continue;
+      }
+      bool f = false;
+      for (int e = srp[i]; e < srp[i + 1]; ++e)
+        if (newc[sci[e]]) {
+          f = true;
+          break;
+        }
+      if (f)
+        state[i] = kF;
+      else
+        ++und;
+    }
+    if (und) atomicAdd(&left, und);
+    __syncthreads();
+    ++r;
+    const int l = left;
+    __syncthreads();
+    if (l == 0 || r > n) {
+      if (threadIdx.x == 0) rounds[0] = l == 0 ? r : -1;
+      return;
+    }
+  }
+}
+
 __global__ void k_is_c(int n, const int8_t* __restrict__ cf, int* __restrict__ out) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = cf[i] == kC;
@@ -1403,24 +1463,38 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
     k_pmis_init<<<grid_for(n, 256), 256, 0, s>>>(n, o.seed, ST.rp.p, w.p, L.cf.p);
     TPF_CHECK_LAUNCH();
     int rounds = 0;
-    while (true) {
-      fill_int(und.p, 0, 1, s);
-      k_pmis_select<<<grid_for(n, 256), 256, 0, s>>>(n, L.S.rp.p, L.S.ci.p, ST.rp.p, ST.ci.p, w.p,
-                                                     L.cf.p, newc.p);
+    int* rounds_pinned = host_counts_slot();
+    if (n <= kPmisWgMax) {
+      // every round in one launch; the count comes back with the next scan
+      k_pmis_block<<<1, kPmisWg, 0, s>>>(n, L.S.rp.p, L.S.ci.p, ST.rp.p, ST.ci.p, w.p, L.cf.p,
+                                         newc.p, und.p);
       TPF_CHECK_LAUNCH();
-      k_pmis_update<<<grid_for(n, 256), 256, 0, s>>>(n, L.S.rp.p, L.S.ci.p, newc.p, L.cf.p, und.p);
-      TPF_CHECK_LAUNCH();
-      ++rounds;
-      int left = read_scalar(und.p, s);
-      if (left == 0) break;
-      TPF_REQUIRE(rounds <= n + 1, TPF_ERR_INVALID_ARG, "PMIS did not terminate");
+      TPF_HIP(hipMemcpyAsync(rounds_pinned, und.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    } else {
+      while (true) {
+        fill_int(und.p, 0, 1, s);
+        k_pmis_select<<<grid_for(n, 256), 256, 0, s>>>(n, L.S.rp.p, L.S.ci.p, ST.rp.p, ST.ci.p,
+                                                       w.p, L.cf.p, newc.p);
+        TPF_CHECK_LAUNCH();
+        k_pmis_update<<<grid_for(n, 256), 256, 0, s>>>(n, L.S.rp.p, L.S.ci.p, newc.p, L.cf.p,
+                                                       und.p);
+        TPF_CHECK_LAUNCH();
+        ++rounds;
+        int left = read_scalar(und.p, s);
+        if (left == 0) break;
+        TPF_REQUIRE(rounds <= n + 1, TPF_ERR_INVALID_ARG, "PMIS did not terminate");
+      }
     }
-    L.pmis_rounds = rounds;
     // coarse numbering
     Buf<int> isc(n, s), cidx(n + 1, s);
     k_is_c<<<grid_for(n, 256), 256, 0, s>>>(n, L.cf.p, isc.p);
     TPF_CHECK_LAUNCH();
-    int64_t nc = scan_exclusive(isc.p, cidx.p, n, s);
+    int64_t nc = scan_exclusive(isc.p, cidx.p, n, s);  // synchronises: the round count arrived
+    if (n <= kPmisWgMax) {
+      rounds = *rounds_pinned;
+      TPF_REQUIRE(rounds > 0, TPF_ERR_INVALID_ARG, "PMIS did not terminate");
+    }
+    L.pmis_rounds = rounds;
     if (nc == 0 || double(nc) > 0.9 * double(n)) break;
     // interpolation: direct, or extended+i
     L.P.nrows = n;

@@ -99,6 +99,19 @@ int64_t scan_exclusive(const int* in, int* out, int64_t n, hipStream_t s) {
   return total;
 }
 
+void scan_exclusive_async(const int* in, int* out, int64_t n, hipStream_t s) {
+  if (n == 0) {
+    fill_int(out, 0, 1, s);
+    return;
+  }
+  Buf<int64_t> tmp(n + 1, s);
+  scan_rec<int64_t, int>(in, tmp.p, n, s);
+  unsigned g = grid_for(n, 256);
+  k_scan_finish<int64_t, int, int><<<g > 4096 ? 4096 : g, 256, 0, s>>>(tmp.p, in, n, out, true,
+                                                                         tmp.p + n);
+  TPF_CHECK_LAUNCH();
+}
+
 int64_t scan_exclusive_wide(const int* in, int64_t* out, int64_t n, hipStream_t s) {
   if (n == 0) {
     fill(out, int64_t(0), 1, s);

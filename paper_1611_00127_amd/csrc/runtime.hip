@@ -51,6 +51,28 @@ void fail(int code, const char* fmt, ...) {
   throw Error(code, buf);
 }
 
+// Without an installed allocator, memory comes from the current device's
+// stream-ordered pool (hipMallocAsync / hipFreeAsync): freed blocks stay
+// cached in the pool (release threshold raised to the maximum the first
+// time a device is used) and are reused in stream order without a host
+// round trip.
+namespace {
+std::mutex g_pool_mu;
+std::vector<int> g_pool_ready;
+void prepare_pool() {
+  int dev = 0;
+  TPF_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  if (int(g_pool_ready.size()) <= dev) g_pool_ready.resize(dev + 1, 0);
+  if (g_pool_ready[dev]) return;
+  hipMemPool_t pool;
+  TPF_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
+  uint64_t keep = UINT64_MAX;
+  TPF_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+  g_pool_ready[dev] = 1;
+}
+}  // namespace
+
 void* dalloc(size_t bytes, hipStream_t s) {
   if (bytes == 0) return nullptr;
   void* p = nullptr;
@@ -58,10 +80,11 @@ void* dalloc(size_t bytes, hipStream_t s) {
     p = g_alloc(bytes, reinterpret_cast<void*>(s), g_ctx);
     if (!p) fail(TPF_ERR_OOM, "allocator returned NULL for %zu bytes", bytes);
   } else {
-    hipError_t e = hipMalloc(&p, bytes);
+    prepare_pool();
+    hipError_t e = hipMallocAsync(&p, bytes, s);
     if (e != hipSuccess) {
       (void)hipGetLastError();
-      fail(TPF_ERR_OOM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+      fail(TPF_ERR_OOM, "hipMallocAsync(%zu) failed: %s", bytes, hipGetErrorString(e));
     }
   }
   std::lock_guard<std::mutex> lk(g_mem_mu);
@@ -74,7 +97,7 @@ void dfree(void* p, size_t bytes, hipStream_t s) {
   if (g_free)
     g_free(p, reinterpret_cast<void*>(s), g_ctx);
   else
-    (void)hipFree(p);
+    (void)hipFreeAsync(p, s);
   std::lock_guard<std::mutex> lk(g_mem_mu);
   g_in_use -= bytes;
 }
@@ -136,6 +159,17 @@ int tpf_set_allocator(tpf_alloc_fn a, tpf_free_fn f, void* ctx) {
   g_free = f;
   g_ctx = ctx;
   return TPF_OK;
+}
+
+int tpf_release_cached_memory(void) {
+  return tpf::guarded([] {
+    int dev = 0;
+    TPF_HIP(hipGetDevice(&dev));
+    hipMemPool_t pool;
+    TPF_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
+    TPF_HIP(hipDeviceSynchronize());
+    TPF_HIP(hipMemPoolTrimTo(pool, 0));
+  });
 }
 
 int tpf_memory_in_use(size_t* bytes) {

@@ -171,6 +171,9 @@ inline unsigned grid_for(int64_t n, int block) {
 // ---------------------------------------------------------------- utilities (linalg.hip)
 // exclusive scan of n ints into out[0..n], out[n] = total; returns total (synchronises)
 int64_t scan_exclusive(const int* in, int* out, int64_t n, hipStream_t s);
+// the same without reading the total back (no synchronisation), for counts
+// whose total the caller knows fits in int32
+void scan_exclusive_async(const int* in, int* out, int64_t n, hipStream_t s);
 int64_t scan_exclusive64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);
 // int counts into 64-bit offsets out[0..n] (no overflow check needed)
 int64_t scan_exclusive_wide(const int* in, int64_t* out, int64_t n, hipStream_t s);
@@ -203,7 +206,8 @@ void csr_residual(const CsrRef<T>& A, const T* x, const T* b, T* y, hipStream_t 
 void spgemm(const CsrRef<double>& A, const CsrRef<double>& B, Csr<double>& C, hipStream_t s,
             const CsrRef<double>* D = nullptr, double alpha = 1.0, double beta = 1.0,
             bool reuse = false, int first_class = 0);
-// C = A^T (values copied when A.v != nullptr); rows of C sorted by column
+// C = A^T (values copied when A.v != nullptr); rows of C sorted by column.
+// A's columns must lie in [0, A.ncols) (not checked; no host round trip).
 void transpose(const CsrRef<double>& A, Csr<double>& C, hipStream_t s);
 
 }  // namespace tpf

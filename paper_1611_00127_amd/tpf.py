@@ -134,6 +134,7 @@ _SIGS = {
     "tpf_last_error": (c_int, [ctypes.c_char_p, c_size_t]),
     "tpf_set_allocator": (c_int, [c_void_p, c_void_p, c_void_p]),
     "tpf_memory_in_use": (c_int, [ctypes.POINTER(c_size_t)]),
+    "tpf_release_cached_memory": (c_int, []),
     "tpf_problem_create": (c_int, [ctypes.POINTER(ProblemDesc), c_void_p, ctypes.POINTER(c_void_p)]),
     "tpf_problem_destroy": (c_int, [c_void_p]),
     "tpf_problem_cells": (c_int, [c_void_p, ctypes.POINTER(c_int64)]),
@@ -241,15 +242,21 @@ def use_torch_allocator():
     _check(lib.tpf_set_allocator(ctypes.cast(_alloc_cb, c_void_p), ctypes.cast(_free_cb, c_void_p), None))
 
 
-def init():
-    """Loads the library for GPU use; raises if HIP/torch has no device."""
+def init(torch_allocator=True):
+    """Loads the library for GPU use; raises if HIP/torch has no device.
+    Library memory comes from torch's caching allocator, or with
+    torch_allocator=False from the device's stream-ordered pool."""
     import torch
     if not torch.cuda.is_available():
         raise RuntimeError("no GPU visible: the HIP library needs an MI355X (gfx950)")
     load()
-    if _alloc_cb is None:
+    if torch_allocator and _alloc_cb is None:
         use_torch_allocator()
     return _lib
+
+
+def tpf_release_cached_memory():
+    _check(load().tpf_release_cached_memory())
 
 
 # ---- entry points (same names as the C ABI) --------------------------------
