@@ -167,6 +167,9 @@ typedef struct tpf_precond_opts {
                            else two l1-Jacobi sweeps */
   int interp;           /* TPF_INTERP_* */
   uint64_t hash_seed;   /* seed of the PMIS tie-break weights */
+  int exti_route;       /* tests: 0 picks each F row's extended+i kernel by the row's size;
+                           r in 1..8 starts the search at class r-1 (0-5 flattened wavefront
+                           kernels, 6 wide wavefront, 7 one thread per row) */
 } tpf_precond_opts;
 /* Fills opts with the defaults above for the given kind. */
 int tpf_precond_default_opts(int kind, tpf_precond_opts* opts);
@@ -357,6 +360,15 @@ int tpf_server_destroy(tpf_server* sv);
 int tpf_kernel_timing(int enable);
 int tpf_kernel_stats(const char* name, int64_t* count, double* total_ms);
 int tpf_kernel_stats_reset(void);
+
+/* ---- launch mode ------------------------------------------------------- */
+/* Each AMG V-cycle (about five kernels per level) is recorded once as a HIP
+ * graph on a private stream, for the (input, output) buffers it is applied
+ * to, and replayed on the caller's stream; graphs are dropped whenever the
+ * hierarchy is rebuilt or refreshed.  Enabled by default; 0 launches every
+ * kernel directly (also the case while kernel timing is on).  Results are
+ * identical either way. */
+int tpf_set_graphs(int enable);
 
 #ifdef __cplusplus
 }

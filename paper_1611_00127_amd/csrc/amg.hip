@@ -443,12 +443,19 @@ __global__ void k_exti_fill(int nl, const int* __restrict__ rows, const int* __r
 // candidate set C^_i is sorted there and the weights accumulate over the
 // neighbours k in row order.  Rows whose bounds exceed the wavefront
 // kernels' capacities use the per-thread kernel above.
-constexpr int kExtK = 64;      // strong F neighbours per row (wavefront kernels)
-constexpr int kExtCap0 = 256;  // candidates (with duplicates) / flattened entries: class 0
-constexpr int kExtFlat0 = 512;
-constexpr int kExtCap1 = 1024;  // class 1
-constexpr int kExtFlat1 = 2048;
-constexpr int kExtCap2 = 4096;  // class 2: wide rows, neighbour rows from global memory
+// Row classes by (strong F neighbours, candidates with duplicates, flattened
+// neighbour entries): the flattened wavefront kernel at four sizes (the
+// small ones need little LDS, so many rows are in flight), then the wide
+// wavefront kernel (neighbour rows from global memory), then one thread per row.
+constexpr int kExtK = 64;  // strong F neighbours counted and kept by k_exti_ub
+struct ExtClass {
+  int k, cap, flat;
+};
+constexpr int kExtFlatN = 6;
+constexpr ExtClass kExtFlatClasses[kExtFlatN] = {{16, 64, 128},  {16, 64, 512},  {16, 64, 1024},
+                                                 {16, 64, 2048}, {64, 256, 512}, {64, 1024, 2048}};
+constexpr int kExtCapWide = 4096;
+constexpr int kExtClasses = kExtFlatN + 2;  // + wide wavefront + one thread per row
 
 __device__ inline unsigned long long lanes_below() {
   return (1ull << (threadIdx.x & 63)) - 1ull;
@@ -584,20 +591,24 @@ __global__ void __launch_bounds__(64) k_exti_ub(int n, const int* __restrict__ r
   }
 }
 
-// F rows by their bounds: classes 0 / 1 (flattened wavefront kernels), 2 (wide
-// wavefront kernel), 3 (per thread)
+// F rows by their bounds: the first fitting class from `first` on among the
+// flattened wavefront kernels, then the wide wavefront kernel, then one
+// thread per row
 __global__ void k_exti_classify(int n, const int* __restrict__ ub, const int* __restrict__ fl,
                                 const int* __restrict__ nk, const int8_t* __restrict__ cf,
-                                int* __restrict__ counts, int* __restrict__ lists) {
+                                int first, int* __restrict__ counts, int* __restrict__ lists) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int c = -1;
   if (i < n && cf[i] != kC) {
-    if (nk[i] <= kExtK && ub[i] <= kExtCap0 && fl[i] <= kExtFlat0) c = 0;
-    else if (nk[i] <= kExtK && ub[i] <= kExtCap1 && fl[i] <= kExtFlat1) c = 1;
-    else if (ub[i] <= kExtCap2) c = 2;
-    else c = 3;
+    c = kExtClasses - 1;
+    if (first <= kExtFlatN && ub[i] <= kExtCapWide) c = kExtFlatN;
+#pragma unroll
+    for (int k = kExtFlatN - 1; k >= 0; --k)
+      if (k >= first && nk[i] <= kExtFlatClasses[k].k && ub[i] <= kExtFlatClasses[k].cap &&
+          fl[i] <= kExtFlatClasses[k].flat)
+        c = k;
   }
-  block_append<4, 256>(c, i, n, counts, lists);
+  block_append<kExtClasses, 256>(c, i, n, counts, lists);
 }
 
 __device__ inline int lds_find(const int* u, int m, int key) {
@@ -639,30 +650,33 @@ __device__ inline void lds_find_batch(const int* u, int m, int top, const int (&
 // candidate index once (or -2 for column i, -1 otherwise); the sums d_ik run
 // one neighbour per lane; the weights then accumulate over the neighbours k
 // in row order, one neighbour row per step.
-template <int CAP, int FCAP>
-__global__ void __launch_bounds__(64) k_exti_flat(
+template <int KCAP, int CAP, int FCAP>
+__global__ void __launch_bounds__(64, CAP <= 64 ? 8 : 4) k_exti_flat(
     const int* __restrict__ rows, const int* __restrict__ rp, const int* __restrict__ ci,
     const double* __restrict__ v, const uint8_t* __restrict__ mask, const int8_t* __restrict__ cf,
     const int* __restrict__ cidx, const int64_t* __restrict__ toff, int* __restrict__ cnt,
     int* __restrict__ pci, double* __restrict__ pv) {
   constexpr int PC = CAP / 64;
-  constexpr int kB = 8;  // searches per lane in flight
+  // reads / searches per lane in flight (fewer in the small classes, whose
+  // LDS allows more wavefronts per CU when the registers do too)
+  constexpr int kBMax = CAP <= 64 ? 4 : 8;
+  constexpr int kB = FCAP / 64 < kBMax ? FCAP / 64 : kBMax;
   __shared__ int cand[CAP];
   __shared__ int uniq[CAP];
   __shared__ double w[CAP];
   __shared__ int fcol[FCAP];  // column, then candidate index / -2 (column i) / -1
   __shared__ double fval[FCAP];
-  __shared__ int ks[kExtK];
-  __shared__ int kst[kExtK];
-  __shared__ int ko[kExtK + 1];
-  __shared__ double ka[kExtK];
-  __shared__ double kdg[kExtK];
-  __shared__ double kd[kExtK];
+  __shared__ int ks[KCAP];
+  __shared__ int kst[KCAP];
+  __shared__ int ko[KCAP + 1];
+  __shared__ double ka[KCAP];
+  __shared__ double kdg[KCAP];
+  __shared__ double kd[KCAP];
   const int lane = threadIdx.x;
   const int i = rows[blockIdx.x];
   const int a0 = rp[i], a1 = rp[i + 1];
   // row i: strong C columns are candidates; strong F neighbours in row order
-  constexpr int RB = 4;  // row entries per lane in flight (clamped reads, one wait)
+  constexpr int RB = KCAP <= 16 ? 2 : 4;  // row entries per lane in flight (clamped reads)
   int len = 0, nk = 0;
   for (int base = a0; base < a1; base += 64 * RB) {
     int k[RB];
@@ -715,7 +729,7 @@ __global__ void __launch_bounds__(64) k_exti_flat(
   const int flat = __shfl(incl, 63, 64);
   __syncthreads();
   {
-    constexpr int FB = 8;  // flattened entries per lane in flight (clamped reads, one wait)
+    constexpr int FB = kB;  // flattened entries per lane in flight (clamped reads, one wait)
     const int top = lift_top(nk);
     for (int q0 = 0; q0 < flat; q0 += 64 * FB) {
       int q[FB], seg[FB];
@@ -1424,6 +1438,7 @@ template <> const float* dinv_of<float>(const Level& L) { return L.dinv32.p; }
 
 // ---------------------------------------------------------------- setup
 void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
+  drop_graphs();
   o = opts;
   s = st;
   lv.clear();
@@ -1501,44 +1516,57 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
     L.P.ncols = int(nc);
     L.P.rp.alloc(n + 1, s);
     if (o.ext_i) {
-      Buf<int> ub(n, s), fl(n, s), nk(n, s), counts(4, s), lists(4 * int64_t(n), s);
-      fill_int(counts.p, 0, 4, s);
+      constexpr int NC = kExtClasses;
+      Buf<int> ub(n, s), fl(n, s), nk(n, s), counts(NC, s), lists(NC * int64_t(n), s);
+      fill_int(counts.p, 0, NC, s);
       k_exti_ub<<<n, 64, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.mask.p, L.cf.p, ub.p, fl.p, nk.p);
       TPF_CHECK_LAUNCH();
-      k_exti_classify<<<grid_for(n, 256), 256, 0, s>>>(n, ub.p, fl.p, nk.p, L.cf.p, counts.p,
-                                                       lists.p);
+      k_exti_classify<<<grid_for(n, 256), 256, 0, s>>>(n, ub.p, fl.p, nk.p, L.cf.p, o.exti_first,
+                                                       counts.p, lists.p);
       TPF_CHECK_LAUNCH();
       // single pass: rows staged at their candidate bound, then packed
       Buf<int64_t> toff(size_t(n) + 1, s);
       int* hc_pinned = host_counts_slot();
-      TPF_HIP(hipMemcpyAsync(hc_pinned, counts.p, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+      TPF_HIP(hipMemcpyAsync(hc_pinned, counts.p, NC * sizeof(int), hipMemcpyDeviceToHost, s));
       int64_t staged = scan_exclusive_wide(ub.p, toff.p, n, s);  // synchronises
-      int hc[4];
+      int hc[NC];
       std::memcpy(hc, hc_pinned, sizeof(hc));
       Buf<int> tci(staged > 0 ? size_t(staged) : 1, s);
       Buf<double> tv(staged > 0 ? size_t(staged) : 1, s);
       Buf<int2> cur;
-      if (hc[3] > 0) cur.alloc(L.A.nnz > 0 ? L.A.nnz : 1, s);
-      const int* l0 = lists.p;
-      const int* l1 = lists.p + n;
-      const int* l2 = lists.p + 2 * int64_t(n);
-      const int* l3 = lists.p + 3 * int64_t(n);
+      if (hc[NC - 1] > 0) cur.alloc(L.A.nnz > 0 ? L.A.nnz : 1, s);
+      auto list = [&](int c) { return lists.p + c * int64_t(n); };
       k_inject_c<<<grid_for(n, 256), 256, 0, s>>>(n, L.cf.p, cidx.p, toff.p, cnt.p, tci.p, tv.p);
-      if (hc[0] > 0)
-        k_exti_flat<kExtCap0, kExtFlat0><<<hc[0], 64, 0, s>>>(l0, L.A.rp.p, L.A.ci.p, L.A.v.p,
-                                                              L.mask.p, L.cf.p, cidx.p, toff.p,
-                                                              cnt.p, tci.p, tv.p);
-      if (hc[1] > 0)
-        k_exti_flat<kExtCap1, kExtFlat1><<<hc[1], 64, 0, s>>>(l1, L.A.rp.p, L.A.ci.p, L.A.v.p,
-                                                              L.mask.p, L.cf.p, cidx.p, toff.p,
-                                                              cnt.p, tci.p, tv.p);
-      if (hc[2] > 0)
-        k_exti_wide<kExtCap2><<<hc[2], 64, 0, s>>>(l2, L.A.rp.p, L.A.ci.p, L.A.v.p, L.mask.p,
-                                                   L.cf.p, cidx.p, toff.p, cnt.p, tci.p, tv.p);
-      if (hc[3] > 0)
-        k_exti_fill<<<grid_for(hc[3], 128), 128, 0, s>>>(hc[3], l3, L.A.rp.p, L.A.ci.p, L.A.v.p,
-                                                         L.mask.p, L.cf.p, cidx.p, cur.p, toff.p,
-                                                         cnt.p, tci.p, tv.p);
+      auto flat = [&](auto kt, auto ct, auto ft, int c) {
+        constexpr int K = decltype(kt)::value, C = decltype(ct)::value, F = decltype(ft)::value;
+        static_assert(K <= kExtK && C <= kExtCapWide, "class table");
+        if (hc[c] > 0)
+          k_exti_flat<K, C, F><<<hc[c], 64, 0, s>>>(list(c), L.A.rp.p, L.A.ci.p, L.A.v.p,
+                                                      L.mask.p, L.cf.p, cidx.p, toff.p, cnt.p,
+                                                      tci.p, tv.p);
+      };
+      using I16 = std::integral_constant<int, 16>;
+      using I64 = std::integral_constant<int, 64>;
+      using I128 = std::integral_constant<int, 128>;
+      using I256 = std::integral_constant<int, 256>;
+      using I512 = std::integral_constant<int, 512>;
+      using I1024 = std::integral_constant<int, 1024>;
+      using I2048 = std::integral_constant<int, 2048>;
+      flat(I16{}, I64{}, I128{}, 0);  // the classes of kExtFlatClasses, in order
+      flat(I16{}, I64{}, I512{}, 1);
+      flat(I16{}, I64{}, I1024{}, 2);
+      flat(I16{}, I64{}, I2048{}, 3);
+      flat(I64{}, I256{}, I512{}, 4);
+      flat(I64{}, I1024{}, I2048{}, 5);
+      if (hc[NC - 2] > 0)
+        k_exti_wide<kExtCapWide><<<hc[NC - 2], 64, 0, s>>>(list(NC - 2), L.A.rp.p, L.A.ci.p,
+                                                           L.A.v.p, L.mask.p, L.cf.p, cidx.p,
+                                                           toff.p, cnt.p, tci.p, tv.p);
+      if (hc[NC - 1] > 0)
+        k_exti_fill<<<grid_for(hc[NC - 1], 128), 128, 0, s>>>(hc[NC - 1], list(NC - 1), L.A.rp.p,
+                                                              L.A.ci.p, L.A.v.p, L.mask.p, L.cf.p,
+                                                              cidx.p, cur.p, toff.p, cnt.p, tci.p,
+                                                              tv.p);
       TPF_CHECK_LAUNCH();
       L.P.nnz = scan_exclusive(cnt.p, L.P.rp.p, n, s);
       L.P.ci.alloc(L.P.nnz > 0 ? L.P.nnz : 1, s);
@@ -1566,6 +1594,7 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
 }
 
 void Hierarchy::refresh(hipStream_t st) {
+  drop_graphs();
   s = st;
   for (size_t l = 0; l + 1 < lv.size(); ++l) {
     Level& L = *lv[l];
@@ -1576,6 +1605,7 @@ void Hierarchy::refresh(hipStream_t st) {
 }
 
 void Hierarchy::finish_levels(hipStream_t st) {
+  drop_graphs();  // level buffers may move
   for (size_t l = 0; l < lv.size(); ++l) {
     Level& L = *lv[l];
     int n = L.A.nrows;
@@ -1789,11 +1819,50 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st) {
   }
 }
 
+void Hierarchy::drop_graphs() {
+  for (auto& g : vg) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g = VGraph{};
+  }
+}
+
+Hierarchy::~Hierarchy() {
+  drop_graphs();
+  if (cap_s) (void)hipStreamDestroy(cap_s);
+}
+
+// One V-cycle: its kernels (about five per level) are launched as one graph
+// when graphs are enabled and kernel timing is off, eagerly otherwise.
 template <class T>
 void Hierarchy::vcycle(const T* b, T* x, hipStream_t st) {
   TPF_REQUIRE(!lv.empty(), TPF_ERR_STATE, "AMG hierarchy not set up");
   if (std::is_same<T, float>::value) TPF_REQUIRE(o.fp32, TPF_ERR_STATE, "FP32 copies not built");
-  vcycle_level<T>(0, b, x, st);
+  if (timing_enabled() || !graphs_enabled()) {
+    vcycle_level<T>(0, b, x, st);
+    return;
+  }
+  VGraph& g = vg[std::is_same<T, float>::value ? 1 : 0];
+  if (!g.exec || g.b != b || g.x != x) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g = VGraph{};
+    if (!cap_s) TPF_HIP(hipStreamCreateWithFlags(&cap_s, hipStreamNonBlocking));
+    TPF_HIP(hipStreamBeginCapture(cap_s, hipStreamCaptureModeThreadLocal));
+    hipGraph_t gr = nullptr;
+    try {
+      vcycle_level<T>(0, b, x, cap_s);
+    } catch (...) {
+      (void)hipStreamEndCapture(cap_s, &gr);
+      if (gr) (void)hipGraphDestroy(gr);
+      throw;
+    }
+    TPF_HIP(hipStreamEndCapture(cap_s, &gr));
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    TPF_HIP(e);
+    g = VGraph{b, x, ex};
+  }
+  TPF_HIP(hipGraphLaunch(g.exec, st));
 }
 
 template void Hierarchy::vcycle<double>(const double*, double*, hipStream_t);

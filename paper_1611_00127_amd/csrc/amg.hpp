@@ -15,6 +15,7 @@ struct AmgOpts {
   uint64_t seed = 0x5eed;
   bool fp32 = false;
   bool ext_i = false;   // extended+i instead of direct interpolation
+  int exti_first = 0;   // extended+i rows start the kernel-class search here (tests)
 };
 
 struct Level {
@@ -56,6 +57,19 @@ struct Hierarchy {
   std::string tag = "A";  // operator name used in kernel-timer labels
   std::vector<int> stencil;  // level-0 diagonal offsets (empty: CSR only)
   Dia dia0;
+
+  // V-cycle graphs, one per value type: recorded on a private stream the
+  // first time a (b, x) pair is seen, replayed on the caller's stream after,
+  // dropped whenever the levels change.
+  struct VGraph {
+    const void* b = nullptr;
+    void* x = nullptr;
+    hipGraphExec_t exec = nullptr;
+  };
+  VGraph vg[2];
+  hipStream_t cap_s = nullptr;
+  void drop_graphs();
+  ~Hierarchy();
 
   // Full setup from the level-0 operator.
   void build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st);

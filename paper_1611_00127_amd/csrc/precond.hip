@@ -333,6 +333,7 @@ std::vector<int> stencil_offsets(const Phys& ph, int radius) {
 AmgOpts amg_opts(const tpf_precond_opts& o, bool pressure_like) {
   AmgOpts a;
   a.ext_i = o.interp == TPF_INTERP_EXTI || (o.interp == TPF_INTERP_AUTO && pressure_like);
+  a.exti_first = o.exti_route > 0 ? o.exti_route - 1 : 0;
   a.theta = o.theta;
   a.max_levels = o.max_levels;
   a.coarse_max = o.coarse_max;
@@ -458,7 +459,10 @@ void apply_t(tpf_precond* M, const double* r, double* z, hipStream_t s) {
         M->H[0]->vcycle<float>(M->fr.p, M->fu.p, s);
         cast<float, double>(z, M->fu.p, 2 * int64_t(N), s);
       } else {
-        M->H[0]->vcycle<double>(r, z, s);
+        // fixed buffers, so the recorded V-cycle graph is reused
+        copy(M->r2.p, r, 2 * int64_t(N), s);
+        M->H[0]->vcycle<double>(M->r2.p, M->u2.p, s);
+        copy(z, M->u2.p, 2 * int64_t(N), s);
       }
       break;
     }
@@ -530,7 +534,11 @@ tpf_precond::~tpf_precond() {
   H[0].reset();  // hierarchy buffers are released before their stream goes
   H[1].reset();
   if (aux_ev) (void)hipEventDestroy(aux_ev);
-  if (aux) (void)hipStreamDestroy(aux);
+  if (aux) {
+    (void)hipStreamSynchronize(aux);
+    tpf::forget_stream(aux);
+    (void)hipStreamDestroy(aux);
+  }
 }
 
 namespace {
@@ -583,6 +591,7 @@ int tpf_precond_default_opts(int kind, tpf_precond_opts* o) {
     o->dense_max = 1024;
     o->interp = TPF_INTERP_AUTO;
     o->hash_seed = 0x5eed;
+    o->exti_route = 0;
   });
 }
 
@@ -600,6 +609,8 @@ int tpf_precond_create(const tpf_precond_opts* o, tpf_precond** out) {
     TPF_REQUIRE(o->theta > 0 && o->theta < 1, TPF_ERR_INVALID_ARG, "theta must be in (0,1)");
     TPF_REQUIRE(o->interp >= TPF_INTERP_AUTO && o->interp <= TPF_INTERP_EXTI, TPF_ERR_INVALID_ARG,
                 "unknown interpolation");
+    TPF_REQUIRE(o->exti_route >= 0 && o->exti_route <= 8, TPF_ERR_INVALID_ARG,
+                "exti_route must be in [0, 8]");
     auto* M = new tpf_precond();
     M->o = *o;
     *out = M;

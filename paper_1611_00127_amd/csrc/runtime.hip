@@ -1,4 +1,5 @@
 // Runtime services: error state, allocator hook, kernel timing registry.
+#include <atomic>
 #include <cstdarg>
 #include <map>
 #include <mutex>
@@ -52,10 +53,8 @@ void fail(int code, const char* fmt, ...) {
 }
 
 // Without an installed allocator, memory comes from the current device's
-// stream-ordered pool (hipMallocAsync / hipFreeAsync): freed blocks stay
-// cached in the pool (release threshold raised to the maximum the first
-// time a device is used) and are reused in stream order without a host
-// round trip.
+// stream-ordered pool (hipMallocAsync / hipFreeAsync), whose release
+// threshold is raised to the maximum the first time a device is used.
 namespace {
 std::mutex g_pool_mu;
 std::vector<int> g_pool_ready;
@@ -71,22 +70,70 @@ void prepare_pool() {
   TPF_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
   g_pool_ready[dev] = 1;
 }
-}  // namespace
 
-void* dalloc(size_t bytes, hipStream_t s) {
-  if (bytes == 0) return nullptr;
+void* upstream_alloc(size_t bytes, hipStream_t s) {
   void* p = nullptr;
   if (g_alloc) {
     p = g_alloc(bytes, reinterpret_cast<void*>(s), g_ctx);
     if (!p) fail(TPF_ERR_OOM, "allocator returned NULL for %zu bytes", bytes);
-  } else {
-    prepare_pool();
-    hipError_t e = hipMallocAsync(&p, bytes, s);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      fail(TPF_ERR_OOM, "hipMallocAsync(%zu) failed: %s", bytes, hipGetErrorString(e));
+    return p;
+  }
+  prepare_pool();
+  hipError_t e = hipMallocAsync(&p, bytes, s);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    fail(TPF_ERR_OOM, "hipMallocAsync(%zu) failed: %s", bytes, hipGetErrorString(e));
+  }
+  return p;
+}
+
+void upstream_free(void* p, hipStream_t s) {
+  if (g_free)
+    g_free(p, reinterpret_cast<void*>(s), g_ctx);
+  else
+    (void)hipFreeAsync(p, s);
+}
+
+// Block cache in front of the upstream allocator: a freed block is kept
+// under (stream, size class) and handed to the next allocation of that class
+// on the same stream, which stream order makes safe; no callback or host
+// round trip per allocation.  Size classes are eight per octave (at most
+// 12.5% rounding).  Blocks of a stream the library destroys go back
+// upstream first (forget_stream); past kCacheLimit cached bytes, freed
+// blocks go straight back.
+constexpr size_t kCacheLimit = size_t(16) << 30;
+struct BlockCache {
+  std::mutex mu;
+  std::map<std::pair<hipStream_t, size_t>, std::vector<void*>> free;
+  size_t cached = 0;
+};
+BlockCache& cache() {
+  static BlockCache* c = new BlockCache();  // never destroyed (process teardown)
+  return *c;
+}
+size_t size_class(size_t b) {
+  if (b <= 512) return 512;
+  const int k = 63 - __builtin_clzll(b - 1);  // 2^k < b <= 2^(k+1)
+  const size_t step = size_t(1) << (k - 2 > 9 ? k - 2 : 9);
+  return (b + step - 1) / step * step;
+}
+}  // namespace
+
+void* dalloc(size_t bytes, hipStream_t s) {
+  if (bytes == 0) return nullptr;
+  const size_t cls = size_class(bytes);
+  void* p = nullptr;
+  {
+    BlockCache& c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.free.find({s, cls});
+    if (it != c.free.end() && !it->second.empty()) {
+      p = it->second.back();
+      it->second.pop_back();
+      c.cached -= cls;
     }
   }
+  if (!p) p = upstream_alloc(cls, s);
   std::lock_guard<std::mutex> lk(g_mem_mu);
   g_in_use += bytes;
   return p;
@@ -94,12 +141,53 @@ void* dalloc(size_t bytes, hipStream_t s) {
 
 void dfree(void* p, size_t bytes, hipStream_t s) {
   if (!p) return;
-  if (g_free)
-    g_free(p, reinterpret_cast<void*>(s), g_ctx);
-  else
-    (void)hipFreeAsync(p, s);
+  const size_t cls = size_class(bytes);
+  bool kept = false;
+  {
+    BlockCache& c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    if (c.cached + cls <= kCacheLimit) {
+      c.free[{s, cls}].push_back(p);
+      c.cached += cls;
+      kept = true;
+    }
+  }
+  if (!kept) upstream_free(p, s);
   std::lock_guard<std::mutex> lk(g_mem_mu);
   g_in_use -= bytes;
+}
+
+void forget_stream(hipStream_t s) {
+  std::vector<void*> back;
+  {
+    BlockCache& c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    for (auto it = c.free.begin(); it != c.free.end();) {
+      if (it->first.first == s) {
+        for (void* p : it->second) back.push_back(p);
+        c.cached -= it->first.second * it->second.size();
+        it = c.free.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  for (void* p : back) upstream_free(p, s);
+}
+
+void release_cache() {
+  std::vector<std::pair<void*, hipStream_t>> back;
+  {
+    BlockCache& c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    for (auto& kv : c.free)
+      for (void* p : kv.second) back.push_back({p, kv.first.first});
+    c.free.clear();
+    c.cached = 0;
+  }
+  if (back.empty()) return;
+  TPF_HIP(hipDeviceSynchronize());  // no queued work may still use the blocks
+  for (auto& b : back) upstream_free(b.first, b.second);
 }
 
 HostScratch& host_scratch() {
@@ -109,6 +197,11 @@ HostScratch& host_scratch() {
 }
 
 bool timing_enabled() { return g_timing; }
+
+namespace {
+std::atomic<bool> g_graphs{true};
+}
+bool graphs_enabled() { return g_graphs.load(std::memory_order_relaxed); }
 
 TimedScope::TimedScope(const char* n, hipStream_t st) : name(n), s(st) {
   if (!g_timing) return;
@@ -155,6 +248,8 @@ int tpf_set_allocator(tpf_alloc_fn a, tpf_free_fn f, void* ctx) {
     set_last_error(TPF_ERR_INVALID_ARG, "alloc and free must both be set or both be NULL");
     return TPF_ERR_INVALID_ARG;
   }
+  int rc = tpf::guarded([] { tpf::release_cache(); });  // blocks of the previous allocator
+  if (rc != TPF_OK) return rc;
   g_alloc = a;
   g_free = f;
   g_ctx = ctx;
@@ -163,12 +258,15 @@ int tpf_set_allocator(tpf_alloc_fn a, tpf_free_fn f, void* ctx) {
 
 int tpf_release_cached_memory(void) {
   return tpf::guarded([] {
-    int dev = 0;
-    TPF_HIP(hipGetDevice(&dev));
-    hipMemPool_t pool;
-    TPF_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
-    TPF_HIP(hipDeviceSynchronize());
-    TPF_HIP(hipMemPoolTrimTo(pool, 0));
+    tpf::release_cache();
+    if (!tpf::g_alloc) {
+      int dev = 0;
+      TPF_HIP(hipGetDevice(&dev));
+      hipMemPool_t pool;
+      TPF_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
+      TPF_HIP(hipDeviceSynchronize());
+      TPF_HIP(hipMemPoolTrimTo(pool, 0));
+    }
   });
 }
 
@@ -176,6 +274,11 @@ int tpf_memory_in_use(size_t* bytes) {
   if (!bytes) return TPF_ERR_INVALID_ARG;
   std::lock_guard<std::mutex> lk(g_mem_mu);
   *bytes = g_in_use;
+  return TPF_OK;
+}
+
+int tpf_set_graphs(int enable) {
+  tpf::g_graphs.store(enable != 0);
   return TPF_OK;
 }
 

@@ -583,10 +583,17 @@ extern "C" int tpf_server_destroy(tpf_server* sv) {
     if (sv->setup_s) (void)hipStreamSynchronize(sv->setup_s);
     for (auto& sl : sv->slots) {
       if (sl->ev) (void)hipEventDestroy(sl->ev);
-      if (sl->s) (void)hipStreamDestroy(sl->s);
+      if (sl->s) {
+        (void)hipStreamSynchronize(sl->s);
+        forget_stream(sl->s);
+        (void)hipStreamDestroy(sl->s);
+      }
     }
     if (sv->setup_ev) (void)hipEventDestroy(sv->setup_ev);
-    if (sv->setup_s) (void)hipStreamDestroy(sv->setup_s);
+    if (sv->setup_s) {
+      forget_stream(sv->setup_s);
+      (void)hipStreamDestroy(sv->setup_s);
+    }
     if (sv->host_block) (void)hipHostFree(sv->host_block);
   });
 }

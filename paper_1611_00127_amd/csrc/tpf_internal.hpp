@@ -58,8 +58,15 @@ int guarded(F&& body) {
 }
 
 // ---------------------------------------------------------------- memory
+// Device memory for stream s (cached per stream and size class; see
+// runtime.hip).  Buffers are freed on the stream they were allocated on.
 void* dalloc(size_t bytes, hipStream_t s);
 void dfree(void* p, size_t bytes, hipStream_t s);
+// Returns the blocks cached for stream s to the upstream allocator; call
+// after s is synchronised and before it is destroyed.
+void forget_stream(hipStream_t s);
+// Returns every cached block to the upstream allocator (device idle).
+void release_cache();
 
 // Owning device array; frees through the installed allocator.
 template <class T>
@@ -161,6 +168,8 @@ struct TimedScope {
   ~TimedScope();
 };
 bool timing_enabled();
+// V-cycles launched as recorded HIP graphs (default on; off: eager launches)
+bool graphs_enabled();
 
 inline unsigned grid_for(int64_t n, int block) {
   int64_t g = (n + block - 1) / block;

@@ -60,7 +60,7 @@ class CsrView(ctypes.Structure):
 class PrecondOpts(ctypes.Structure):
     _fields_ = [("kind", c_int), ("precision", c_int), ("theta", c_double), ("max_levels", c_int),
                 ("coarse_max", c_int), ("dense_max", c_int), ("interp", c_int),
-                ("hash_seed", c_uint64)]
+                ("hash_seed", c_uint64), ("exti_route", c_int)]
 
 
 class HierStats(ctypes.Structure):
@@ -170,6 +170,7 @@ _SIGS = {
     "tpf_server_stats": (c_int, [c_void_p, ctypes.POINTER(ServerCounters)]),
     "tpf_server_destroy": (c_int, [c_void_p]),
     "tpf_kernel_timing": (c_int, [c_int]),
+    "tpf_set_graphs": (c_int, [c_int]),
     "tpf_kernel_stats": (c_int, [ctypes.c_char_p, ctypes.POINTER(c_int64), ctypes.POINTER(c_double)]),
     "tpf_kernel_stats_reset": (c_int, []),
 }
@@ -481,6 +482,10 @@ def tpf_server_destroy(sv):
 
 def tpf_kernel_timing(enable):
     _check(load().tpf_kernel_timing(int(bool(enable))))
+
+
+def tpf_set_graphs(enable):
+    _check(load().tpf_set_graphs(int(bool(enable))))
 
 
 def tpf_kernel_stats(name):

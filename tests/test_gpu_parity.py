@@ -131,16 +131,9 @@ def test_schur_parity(gpu):
     M.close(); g.close()
 
 
-@pytest.mark.parametrize("kind,hier,interp", [("bf", 0, "direct"), ("bf", 1, "ext+i"),
-                                              ("cpr1", 0, "ext+i"), ("amg", 0, "direct"),
-                                              ("cpr2", 1, "direct")])
-def test_amg_setup_parity_per_level(gpu, kind, hier, interp):
+def _check_levels(tpf, M, hier, interp):
     """Each level's setup from the GPU's own level matrix (identical bits):
     strength graph, C/F, P (direct or extended+i), R and A_c."""
-    driver, tpf, torch = gpu
-    c = inputs.random_state(inputs.config_c1(), 7, s_lo=0.15, s_hi=0.85)
-    say(f"[amg-setup] kind={kind} hier={hier}")
-    g, M = _setup(driver, tpf, c, kind, coarse_max=40)
     st = M.stats()
     nlev = st.levels[hier]
     assert nlev >= 2
@@ -176,6 +169,32 @@ def test_amg_setup_parity_per_level(gpu, kind, hier, interp):
         assert np.array_equal(Ac.indptr, Aco.indptr) and np.array_equal(Ac.indices, Aco.indices)
         ok, worst = _row_scale_close(Ac.data, Aco.data, Aco.indptr, 1e-12)
         assert ok, (l, worst)
+    return nlev
+
+
+@pytest.mark.parametrize("kind,hier,interp", [("bf", 0, "direct"), ("bf", 1, "ext+i"),
+                                              ("cpr1", 0, "ext+i"), ("amg", 0, "direct"),
+                                              ("cpr2", 1, "direct")])
+def test_amg_setup_parity_per_level(gpu, kind, hier, interp):
+    driver, tpf, torch = gpu
+    c = inputs.random_state(inputs.config_c1(), 7, s_lo=0.15, s_hi=0.85)
+    say(f"[amg-setup] kind={kind} hier={hier}")
+    g, M = _setup(driver, tpf, c, kind, coarse_max=40)
+    _check_levels(tpf, M, hier, interp)
+    M.close(); g.close()
+
+
+@pytest.mark.parametrize("route", list(range(9)))
+def test_exti_every_kernel_class(gpu, route):
+    """Extended+i on the S~ hierarchy of a 3D case with the F rows pushed to
+    each kernel class in turn (route r: classes r-1 and up; 8 = one thread per
+    row), every level checked against the oracle."""
+    driver, tpf, torch = gpu
+    c = inputs.random_state(inputs.small_case(16, 14, 10, seed=21), 22, s_lo=0.15, s_hi=0.85)
+    say(f"[exti] 16x14x10 route {route}")
+    g, M = _setup(driver, tpf, c, "bf", coarse_max=40, exti_route=route)
+    nlev = _check_levels(tpf, M, 1, "ext+i")
+    say(f"  {nlev} levels")
     M.close(); g.close()
 
 
@@ -327,6 +346,60 @@ def test_fp32_vcycle_form_reaches_fp64_accuracy(gpu, kind):
     assert io["status"] == fgmres.CONVERGED
     assert err <= 1e-5
     M.close(); g.close()
+
+
+@pytest.mark.parametrize("kind,precision", [("bf", 0), ("bf", 1), ("cpr2", 0), ("amg", 0)])
+def test_graph_replays_match_eager(gpu, kind, precision):
+    """V-cycles replayed from recorded HIP graphs equal the eager launches
+    bit for bit on every replay (eager work and synchronisations between the
+    replays), on the null stream and on a side stream, and after a numeric
+    refresh of the hierarchy; a full solve is identical too."""
+    driver, tpf, torch = gpu
+    c = inputs.random_state(inputs.small_case(20, 16, 8, seed=31), 32, s_lo=0.15, s_hi=0.85)
+    say(f"[graphs] {kind} precision {precision}")
+    g, M = _setup(driver, tpf, c, kind, precision)
+    n = 2 * c.N
+    rng = np.random.default_rng(33)
+    rs = [torch.tensor(rng.standard_normal(n), device="cuda") for _ in range(3)]
+    side = torch.cuda.Stream()
+
+    def applies(stream=None):
+        out = []
+        for r in rs:
+            z = torch.full_like(r, float("nan"))
+            M.apply(r, z, stream=stream)
+            out.append(z)
+        torch.cuda.synchronize()
+        return [z.cpu().numpy() for z in out]
+
+    try:
+        for refresh in (False, True):
+            if refresh:
+                g.u.add_(1e-3 * torch.tensor(rng.standard_normal(n), device="cuda"))
+                g.assemble()
+                M.setup(g, reuse=True)
+                torch.cuda.synchronize()
+            tpf.tpf_set_graphs(False)
+            eager = applies()
+            tpf.tpf_set_graphs(True)
+            for rep in range(3):
+                got = applies(side if rep == 1 else None)
+                for k in range(len(rs)):
+                    assert np.array_equal(got[k], eager[k]), (refresh, rep, k)
+                y = torch.empty_like(rs[0])
+                tpf.tpf_spmv(g.J, rs[rep], y)  # eager work between replays
+                torch.cuda.synchronize()
+        b = g.R.clone()
+        xs, its = [], []
+        for graphs in (False, True):
+            tpf.tpf_set_graphs(graphs)
+            x = torch.empty_like(b)
+            info = driver.solve(g, M, b, x)
+            xs.append(x.cpu().numpy()); its.append(info.iterations)
+        assert its[0] == its[1] and np.array_equal(xs[0], xs[1])
+    finally:
+        tpf.tpf_set_graphs(True)
+        M.close(); g.close()
 
 
 def test_solve_edge_cases(gpu):
