@@ -234,10 +234,10 @@ int tpf_precond_vcycle(tpf_precond* M, int hier, const double* b, double* x, voi
  * level (Sec. 3.2) and S~ = A_pp - (A_ps D_ss^-1) A_sp (Sec. 3.4, Eq.
  * SIMPLE-Schur).  C's pattern is the symbolic product (plus D's pattern),
  * with no value dropping, rows sorted by column.
- *   route: 0 picks each row's kernel by its product count; r in 1..8 makes
- *     rows start the search at kernel class r-1 (0..5 register-sorted classes
- *     of at most 64/128/256/512/2048/8192 products, 6 the LDS-sorted class,
- *     7 the per-row merge), so tests can drive every kernel.
+ *   route: 0 picks each row's kernel by its product count; r in 1..9 makes
+ *     rows start the search at kernel class r-1 (0..6 register-sorted classes
+ *     of at most 64/128/256/512/1024/2048/8192 products, 7 the LDS-sorted
+ *     class, 8 the per-row merge), so tests can drive every kernel.
  *   pattern_given = 0: writes c_row_ptr (n_rows + 1 ints) and *c_nnz; when
  *     *c_nnz <= c_cap also c_col_idx and c_vals (call once with c_cap = 0 to
  *     size them).  pattern_given = 1: c_row_ptr / c_col_idx hold C's pattern
@@ -248,6 +248,14 @@ int tpf_precond_vcycle(tpf_precond* M, int hier, const double* b, double* x, voi
 int tpf_csr_product(const tpf_csr_view* A, const tpf_csr_view* B, const tpf_csr_view* D,
                     double alpha, double beta, int route, int pattern_given, int* c_row_ptr,
                     int* c_col_idx, double* c_vals, int64_t c_cap, int64_t* c_nnz, void* stream);
+
+/* C = A^T for a device CSR matrix with sorted rows (the restriction R = P^T
+ * of each AMG level and the transposed strength graph, Sec. 3.2): c_row_ptr
+ * n_cols + 1 ints, c_col_idx / c_vals nnz entries (c_vals may be NULL when
+ * A->vals is), caller-owned device memory; rows of C sorted.  Malformed input
+ * returns TPF_ERR_INVALID_ARG.  Synchronises `stream`. */
+int tpf_csr_transpose(const tpf_csr_view* A, int* c_row_ptr, int* c_col_idx, double* c_vals,
+                      void* stream);
 
 /* ---- Krylov solve (Sec. 3, Eq. precon-system) -------------------------- */
 #define TPF_CONVERGED 0

@@ -447,7 +447,7 @@ __global__ void k_exti_fill(int nl, const int* __restrict__ rows, const int* __r
 // neighbour entries): the flattened wavefront kernel at four sizes (the
 // small ones need little LDS, so many rows are in flight), then the wide
 // wavefront kernel (neighbour rows from global memory), then one thread per row.
-constexpr int kExtK = 64;  // strong F neighbours counted and kept by k_exti_ub
+constexpr int kExtK = 64;  // strong F neighbours a flattened-kernel class may hold
 struct ExtClass {
   int k, cap, flat;
 };
@@ -485,109 +485,68 @@ __device__ inline void segment_of_batch(const int* off, int nseg, int top, const
   }
 }
 
+// Strong C entries of each row: sc_k = #{f in row k : f strong, column C}.
+template <int LPR>
+__global__ void __launch_bounds__(256) k_strong_c_count(int n, const int* __restrict__ rp,
+                                                        const int* __restrict__ ci,
+                                                        const uint8_t* __restrict__ mask,
+                                                        const int8_t* __restrict__ cf,
+                                                        int* __restrict__ sc) {
+  int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int i = int(gid / LPR), lane = int(gid % LPR);
+  int a0 = 0, a1 = 0;
+  if (i < n) {
+    a0 = rp[i];
+    a1 = rp[i + 1];
+  }
+  int c = 0;
+  for (int e = a0 + lane; e < a1; e += LPR) c += mask[e] && cf[ci[e]] == kC;
+  c = group_sum<LPR>(c);
+  if (i < n && lane == 0) sc[i] = c;
+}
+
 // Per F row i: ub = strong C entries of row i and of the rows of its strong
-// F neighbours (duplicates counted), fl = summed length of those rows, nk =
-// number of strong F neighbours.  C rows get ub = 1 (their injection entry).
-__global__ void __launch_bounds__(64) k_exti_ub(int n, const int* __restrict__ rp,
-                                                const int* __restrict__ ci,
-                                                const uint8_t* __restrict__ mask,
-                                                const int8_t* __restrict__ cf,
-                                                int* __restrict__ ub, int* __restrict__ fl,
-                                                int* __restrict__ nko) {
-  __shared__ int kst[kExtK];
-  __shared__ int ko[kExtK + 1];
-  int i = blockIdx.x;
-  int lane = threadIdx.x;
-  if (i >= n) return;
-  if (cf[i] == kC) {
-    if (lane == 0) {
+// F neighbours k (duplicates counted: sc_i + sum sc_k), fl = summed length of
+// those rows, nk = number of strong F neighbours.  C rows get ub = 1 (their
+// injection entry).
+template <int LPR>
+__global__ void __launch_bounds__(256) k_exti_ub(int n, const int* __restrict__ rp,
+                                                 const int* __restrict__ ci,
+                                                 const uint8_t* __restrict__ mask,
+                                                 const int8_t* __restrict__ cf,
+                                                 const int* __restrict__ sc, int* __restrict__ ub,
+                                                 int* __restrict__ fl, int* __restrict__ nko) {
+  int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int i = int(gid / LPR), lane = int(gid % LPR);
+  const bool frow = i < n && cf[i] != kC;
+  int a0 = 0, a1 = 0;
+  if (frow) {
+    a0 = rp[i];
+    a1 = rp[i + 1];
+  }
+  int64_t t = 0, flat = 0;
+  int nk = 0;
+  for (int e = a0 + lane; e < a1; e += LPR) {
+    const int k = ci[e];
+    if (!mask[e] || k == i || cf[k] != kF) continue;
+    t += sc[k];
+    flat += rp[k + 1] - rp[k];
+    ++nk;
+  }
+  t = group_sum<LPR>(t);
+  flat = group_sum<LPR>(flat);
+  nk = group_sum<LPR>(nk);
+  if (i < n && lane == 0) {
+    if (frow) {
+      t += sc[i];
+      ub[i] = t > INT_MAX ? INT_MAX : int(t);
+      fl[i] = flat > INT_MAX ? INT_MAX : int(flat);
+      nko[i] = nk;
+    } else {
       ub[i] = 1;
       fl[i] = 0;
       nko[i] = 0;
     }
-    return;
-  }
-  int a0 = rp[i], a1 = rp[i + 1];
-  int64_t t = 0;
-  int nk = 0;
-  constexpr int RB = 4;  // row entries per lane in flight (clamped reads, one wait)
-  for (int base = a0; base < a1; base += 64 * RB) {
-    int k[RB];
-    uint8_t m[RB];
-#pragma unroll
-    for (int b = 0; b < RB; ++b) {
-      const int e = min(base + b * 64 + lane, a1 - 1);
-      k[b] = ci[e];
-      m[b] = mask[e];
-    }
-    int8_t c[RB];
-#pragma unroll
-    for (int b = 0; b < RB; ++b) c[b] = cf[k[b]];
-#pragma unroll
-    for (int b = 0; b < RB; ++b) {
-      const bool mm = base + b * 64 + lane < a1 && m[b] && k[b] != i;
-      const bool sc = mm && c[b] == kC, sf = mm && c[b] == kF;
-      t += sc;
-      unsigned long long bal = __ballot(sf);
-      int pos = nk + __popcll(bal & lanes_below());
-      if (sf && pos < kExtK) kst[pos] = k[b];
-      nk += __popcll(bal);
-    }
-  }
-  __syncthreads();
-  int64_t flat = 0;
-  if (nk <= kExtK) {
-    int len = 0;
-    if (lane < nk) {
-      int k = kst[lane];
-      int k0 = rp[k];
-      len = rp[k + 1] - k0;
-      kst[lane] = k0;
-    }
-    int incl = len;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      int y = __shfl_up(incl, d, 64);
-      if (lane >= d) incl += y;
-    }
-    if (lane == 0) ko[0] = 0;
-    if (lane < nk) ko[lane + 1] = incl;
-    flat = __shfl(incl, 63, 64);
-    __syncthreads();
-    constexpr int FB = 8;  // flattened entries per lane in flight (clamped reads, one wait)
-    const int top = lift_top(nk);
-    for (int q0 = 0; q0 < flat; q0 += 64 * FB) {
-      int q[FB], seg[FB];
-#pragma unroll
-      for (int b = 0; b < FB; ++b) q[b] = min(q0 + b * 64 + lane, int(flat) - 1);
-      segment_of_batch<FB>(ko, nk, top, q, seg);
-      int col[FB];
-      uint8_t m[FB];
-#pragma unroll
-      for (int b = 0; b < FB; ++b) {
-        const int f = kst[seg[b]] + (q[b] - ko[seg[b]]);
-        col[b] = ci[f];
-        m[b] = mask[f];
-      }
-      int8_t c[FB];
-#pragma unroll
-      for (int b = 0; b < FB; ++b) c[b] = cf[col[b]];
-#pragma unroll
-      for (int b = 0; b < FB; ++b) t += q0 + b * 64 + lane < flat && m[b] && c[b] == kC;
-    }
-  } else {
-    for (int e = a0; e < a1; ++e) {
-      int k = ci[e];
-      if (!(mask[e] && k != i && cf[k] == kF)) continue;
-      flat += rp[k + 1] - rp[k];
-      for (int f = rp[k] + lane; f < rp[k + 1]; f += 64) t += mask[f] && cf[ci[f]] == kC;
-    }
-  }
-  t = wave_sum(t);
-  if (lane == 0) {
-    ub[i] = t > INT_MAX ? INT_MAX : int(t);
-    fl[i] = flat > INT_MAX ? INT_MAX : int(flat);
-    nko[i] = nk;
   }
 }
 
@@ -1282,24 +1241,59 @@ __global__ void __launch_bounds__(256) k_dense_gemv(int n, const double* __restr
 
 // ---------------------------------------------------------------- level-0 diagonal layout
 struct DiagOffs {
-  int off[kMaxDiag];
+  int off[kMaxDiag];  // ascending
 };
 
-__global__ void k_csr_to_dia(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                             const double* __restrict__ v, int K, DiagOffs o,
-                             double* __restrict__ dv, int* __restrict__ flag) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  for (int e = rp[i]; e < rp[i + 1]; ++e) {
-    int d = ci[e] - i;
-    int k = 0;
-    while (k < K && o.off[k] != d) ++k;
-    if (k == K) {
-      *flag = 1;
-      continue;
+// Row i's entry at column i + off[k] goes to dv[k n + i] (zero where the row
+// has no entry).  A work-group takes kDiaRows consecutive rows: LPR lanes per
+// row read the entries (coalesced), place them in an LDS tile by diagonal
+// (binary search over the ascending offsets), then the tile is written out
+// one diagonal at a time (coalesced).  *placed counts the entries that lie on
+// a listed diagonal; the layout is usable when that equals nnz.
+constexpr int kDiaRows = 64;
+template <int LPR>
+__global__ void __launch_bounds__(256) k_csr_to_dia(int n, const int* __restrict__ rp,
+                                                    const int* __restrict__ ci,
+                                                    const double* __restrict__ v, int K,
+                                                    DiagOffs o, double* __restrict__ dv,
+                                                    unsigned long long* __restrict__ placed) {
+  __shared__ double tile[kMaxDiag][kDiaRows];
+  __shared__ int off[kMaxDiag];
+  __shared__ int sh[256 / 64];
+  const int i0 = blockIdx.x * kDiaRows;
+  const int rows = min(kDiaRows, n - i0);
+  for (int t = threadIdx.x; t < kMaxDiag * kDiaRows; t += 256) tile[t / kDiaRows][t % kDiaRows] = 0.0;
+  if (threadIdx.x < kMaxDiag) off[threadIdx.x] = o.off[threadIdx.x];
+  __syncthreads();
+  int top = 1;
+  while (2 * top <= K) top <<= 1;
+  int found = 0;
+  constexpr int RPP = 256 / LPR;  // rows per pass
+  const int g = threadIdx.x / LPR, lane = threadIdx.x % LPR;
+  for (int r0 = 0; r0 < rows; r0 += RPP) {
+    const int r = r0 + g;
+    if (r >= rows) continue;
+    const int i = i0 + r;
+    const int a0 = rp[i], a1 = rp[i + 1];
+    for (int e = a0 + lane; e < a1; e += LPR) {
+      const int d = ci[e] - i;
+      int lo = -1;  // off[lo] < d
+      for (int step = top; step > 0; step >>= 1)
+        if (lo + step < K && off[lo + step] < d) lo += step;
+      const int k = lo + 1;
+      if (k < K && off[k] == d) {
+        tile[k][r] = v[e];
+        ++found;
+      }
     }
-    dv[int64_t(k) * n + i] = v[e];
   }
+  __syncthreads();
+  for (int t = threadIdx.x; t < K * kDiaRows; t += 256) {
+    const int k = t / kDiaRows, r = t % kDiaRows;
+    if (r < rows) dv[int64_t(k) * n + i0 + r] = tile[k][r];
+  }
+  const int tot = block_sum<256>(found, sh);
+  if (threadIdx.x == 0 && tot) atomicAdd(placed, static_cast<unsigned long long>(tot));
 }
 
 __device__ inline int clampi(int j, int n) { return j < 0 ? 0 : (j >= n ? n - 1 : j); }
@@ -1519,8 +1513,16 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
       constexpr int NC = kExtClasses;
       Buf<int> ub(n, s), fl(n, s), nk(n, s), counts(NC, s), lists(NC * int64_t(n), s);
       fill_int(counts.p, 0, NC, s);
-      k_exti_ub<<<n, 64, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.mask.p, L.cf.p, ub.p, fl.p, nk.p);
-      TPF_CHECK_LAUNCH();
+      {
+        Buf<int> sc(n, s);
+        DISPATCH_LPR(lpr, LL, {
+          k_strong_c_count<LL><<<rblocks, 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.mask.p, L.cf.p,
+                                                        sc.p);
+          k_exti_ub<LL><<<rblocks, 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.mask.p, L.cf.p, sc.p,
+                                                ub.p, fl.p, nk.p);
+        });
+        TPF_CHECK_LAUNCH();
+      }
       k_exti_classify<<<grid_for(n, 256), 256, 0, s>>>(n, ub.p, fl.p, nk.p, L.cf.p, o.exti_first,
                                                        counts.p, lists.p);
       TPF_CHECK_LAUNCH();
@@ -1661,14 +1663,17 @@ void Hierarchy::finish_levels(hipStream_t st) {
     DiagOffs off;
     for (int k = 0; k < kMaxDiag; ++k) off.off[k] = k < K ? stencil[k] : 0;
     dia0.v.ensure(size_t(K) * n, st);
-    fill(dia0.v.p, 0.0, int64_t(K) * n, st);
-    Buf<int> flag(1, st);
-    fill_int(flag.p, 0, 1, st);
-    k_csr_to_dia<<<grid_for(n, 256), 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, L.A.v.p, K, off, dia0.v.p,
-                                                   flag.p);
+    Buf<int64_t> placed(1, st);
+    fill(placed.p, int64_t(0), 1, st);
+    auto* placed_u = reinterpret_cast<unsigned long long*>(placed.p);
+    if (K <= 8)  // lanes per row: about one entry each
+      k_csr_to_dia<8><<<grid_for(n, kDiaRows), 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, L.A.v.p, K, off,
+                                                             dia0.v.p, placed_u);
+    else
+      k_csr_to_dia<32><<<grid_for(n, kDiaRows), 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, L.A.v.p, K,
+                                                              off, dia0.v.p, placed_u);
     TPF_CHECK_LAUNCH();
-    int f = read_scalar(flag.p, st);
-    dia0.ok = f == 0;
+    dia0.ok = read_scalar(placed.p, st) == L.A.nnz;
     if (dia0.ok && o.fp32) {
       dia0.v32.ensure(size_t(K) * n, st);
       cast<double, float>(dia0.v32.p, dia0.v.p, int64_t(K) * n, st);

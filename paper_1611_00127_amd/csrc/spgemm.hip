@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(256) k_spgemm_ub(int nrows, const int* __restr
 // appends row i to the list of its size class: the first class whose cap
 // holds ub[i] (flattened wavefront / work-group kernels, then the
 // sorted-columns work-group), else the last list (per-thread merge)
-constexpr int kClasses = 8;
+constexpr int kClasses = 9;
 struct Caps {
   int c[kClasses - 1];   // product bound of each class
   int la[kClasses - 1];  // bound on A's row length
@@ -597,24 +597,65 @@ __device__ inline void sort_row(int a, int len, int* __restrict__ ci, double* __
   }
 }
 
-// One wavefront per row; rows longer than kSortCap are queued for
-// k_sort_long_rows.
+// Rows of at most kShortRow entries: kShortRow lanes per row, 256 / kShortRow
+// rows per work-group; each lane takes one entry and finds its rank (the
+// columns of a row are distinct) from the group's keys by shuffles, then
+// writes it in place (all reads precede the writes in the wavefront).
+// Longer rows are appended to `mid` for k_sort_mid_rows.
+constexpr int kShortRow = 16;
+__global__ void __launch_bounds__(256) k_sort_short_rows(int nrows, const int* __restrict__ rp,
+                                                         int* __restrict__ ci,
+                                                         double* __restrict__ v,
+                                                         int* __restrict__ nmid,
+                                                         int* __restrict__ mid) {
+  const int g = threadIdx.x / kShortRow, j = threadIdx.x % kShortRow;
+  const int i = blockIdx.x * (256 / kShortRow) + g;
+  int a = 0, len = 0;
+  if (i < nrows) {
+    a = rp[i];
+    len = rp[i + 1] - a;
+  }
+  const bool mine = len > 1 && len <= kShortRow;
+  block_append<1, 256>(len > kShortRow && j == 0 ? 0 : -1, i, nrows, nmid, mid);
+  int key = INT_MAX;
+  double val = 0.0;
+  if (mine && j < len) {
+    key = ci[a + j];
+    if (v) val = v[a + j];
+  }
+  const int base = threadIdx.x & 63 & ~(kShortRow - 1);
+  int rank = 0;
+#pragma unroll
+  for (int m = 0; m < kShortRow; ++m) rank += __shfl(key, base + m, 64) < key;
+  if (mine && j < len) {
+    ci[a + rank] = key;
+    if (v) v[a + rank] = val;
+  }
+}
+
+// The queued rows of more than kShortRow entries, one wavefront per row,
+// the work-groups striding over the queue (whose length they read); rows
+// longer than kSortCap are queued again for k_sort_long_rows.
 constexpr int kSortCap = 1024;
-__global__ void __launch_bounds__(64) k_sort_rows(int nrows, const int* __restrict__ rp,
-                                                  int* __restrict__ ci, double* __restrict__ v,
-                                                  int* __restrict__ nlong,
-                                                  int* __restrict__ long_rows) {
+__global__ void __launch_bounds__(64) k_sort_mid_rows(const int* __restrict__ nmid,
+                                                      const int* __restrict__ mid,
+                                                      const int* __restrict__ rp,
+                                                      int* __restrict__ ci, double* __restrict__ v,
+                                                      int* __restrict__ nlong,
+                                                      int* __restrict__ long_rows) {
   __shared__ int keys[kSortCap];
   __shared__ double vals[kSortCap];
-  int i = blockIdx.x;
-  if (i >= nrows) return;
-  int a = rp[i], len = rp[i + 1] - a;
-  if (len <= 1) return;
-  if (len > kSortCap) {
-    if (threadIdx.x == 0) long_rows[atomicAdd(nlong, 1)] = i;
-    return;
+  const int cnt = *nmid;
+  for (int q = blockIdx.x; q < cnt; q += gridDim.x) {
+    const int i = mid[q];
+    const int a = rp[i], len = rp[i + 1] - a;
+    if (len > kSortCap) {
+      if (threadIdx.x == 0) long_rows[atomicAdd(nlong, 1)] = i;
+    } else {
+      sort_row<64, kSortCap>(a, len, ci, v, keys, vals);
+    }
+    __syncthreads();
   }
-  sort_row<64, kSortCap>(a, len, ci, v, keys, vals);
 }
 
 // The queued long rows, one 256-thread work-group per row (bitonic sort in
@@ -706,9 +747,10 @@ void spgemm(const CsrRef<double>& A, const CsrRef<double>& B, Csr<double>& C, hi
     C.v.alloc(1, s);
     return;
   }
-  // caps ascending: flat<64,CAP> wavefront kernels, flat<256,2048>, flat<512,8192> (A rows of
-  // at most 2048 entries), sorted<256,16384>; beyond, the per-thread merge
-  const Caps caps{{64, 128, 256, 512, 2048, 8192, 16384}, {64, 128, 256, 512, 2048, 2048, 16384}};
+  // caps ascending: flat<64,CAP> wavefront kernels (CAP 64 .. 1024), flat<256,2048>,
+  // flat<512,8192> (A rows of at most 2048), sorted<256,16384>; beyond, the per-thread merge
+  const Caps caps{{64, 128, 256, 512, 1024, 2048, 8192, 16384},
+                  {64, 128, 256, 512, 1024, 2048, 2048, 16384}};
   Buf<int> ub(n, s), counts(kClasses, s), lists(kClasses * int64_t(n), s), cnt(n, s);
   fill_int(counts.p, 0, kClasses, s);
   {
@@ -756,21 +798,23 @@ void spgemm(const CsrRef<double>& A, const CsrRef<double>& B, Csr<double>& C, hi
   using C128 = std::integral_constant<int, 128>;
   using C256 = std::integral_constant<int, 256>;
   using C512 = std::integral_constant<int, 512>;
+  using C1024 = std::integral_constant<int, 1024>;
   using C2048 = std::integral_constant<int, 2048>;
   using C8192 = std::integral_constant<int, 8192>;
   flat(W1{}, C64{}, C64{}, 0);
   flat(W1{}, C128{}, C128{}, 1);
   flat(W1{}, C256{}, C256{}, 2);
   flat(W1{}, C512{}, C512{}, 3);
-  flat(W4{}, C2048{}, C2048{}, 4);
-  flat(W8{}, C8192{}, C2048{}, 5);
-  if (hc[6] > 0)
-    k_spgemm_sorted<256, 16384, true><<<hc[6], 256, 0, s>>>(list(6), ub.p, A.rp, A.ci, A.v, B.rp,
+  flat(W1{}, C1024{}, C1024{}, 4);
+  flat(W4{}, C2048{}, C2048{}, 5);
+  flat(W8{}, C8192{}, C2048{}, 6);
+  if (hc[7] > 0)
+    k_spgemm_sorted<256, 16384, true><<<hc[7], 256, 0, s>>>(list(7), ub.p, A.rp, A.ci, A.v, B.rp,
                                                             B.ci, B.v, drp, dci, dv, alpha, beta,
                                                             cnt.p, toff.p, tci.p, tv.p);
-  if (hc[7] > 0)
-    k_spgemm_merge<true><<<grid_for(hc[7], 128), 128, 0, s>>>(
-        hc[7], list(7), A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha, beta, cur.p, cnt.p,
+  if (hc[8] > 0)
+    k_spgemm_merge<true><<<grid_for(hc[8], 128), 128, 0, s>>>(
+        hc[8], list(8), A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha, beta, cur.p, cnt.p,
         toff.p, tci.p, tv.p);
   TPF_CHECK_LAUNCH();
   C.nnz = scan_exclusive(cnt.p, C.rp.p, n, s);
@@ -805,11 +849,15 @@ void transpose(const CsrRef<double>& A, Csr<double>& C, hipStream_t s) {
     TPF_CHECK_LAUNCH();
   }
   if (m > 0) {
-    Buf<int> nlong(1, s), long_rows(m, s);
-    fill_int(nlong.p, 0, 1, s);
-    k_sort_rows<<<m, 64, 0, s>>>(m, C.rp.p, C.ci.p, C.v.p, nlong.p, long_rows.p);
+    Buf<int> counts(2, s), mid(m, s), long_rows(m, s);  // counts: mid, long
+    fill_int(counts.p, 0, 2, s);
+    k_sort_short_rows<<<grid_for(m, 256 / kShortRow), 256, 0, s>>>(m, C.rp.p, C.ci.p, C.v.p,
+                                                                  counts.p, mid.p);
     TPF_CHECK_LAUNCH();
-    k_sort_long_rows<<<64, 256, 0, s>>>(nlong.p, long_rows.p, C.rp.p, C.ci.p, C.v.p);
+    k_sort_mid_rows<<<2048, 64, 0, s>>>(counts.p, mid.p, C.rp.p, C.ci.p, C.v.p, counts.p + 1,
+                                        long_rows.p);
+    TPF_CHECK_LAUNCH();
+    k_sort_long_rows<<<64, 256, 0, s>>>(counts.p + 1, long_rows.p, C.rp.p, C.ci.p, C.v.p);
     TPF_CHECK_LAUNCH();
   }
 }
@@ -831,6 +879,26 @@ static void check_csr(const CsrRef<double>& M, const char* name, hipStream_t s) 
 }
 
 }  // namespace tpf
+
+extern "C" int tpf_csr_transpose(const tpf_csr_view* A, int* c_row_ptr, int* c_col_idx,
+                                 double* c_vals, void* stream) {
+  using namespace tpf;
+  return guarded([&] {
+    TPF_REQUIRE(A && c_row_ptr && (A->nnz == 0 || (c_col_idx && (c_vals || !A->vals))),
+                TPF_ERR_INVALID_ARG, "tpf_csr_transpose: null argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const CsrRef<double> a{A->n_rows, A->n_cols, A->nnz, A->row_ptr, A->col_idx, A->vals};
+    check_csr(a, "A", s);
+    Csr<double> C;
+    transpose(a, C, s);
+    copy(c_row_ptr, C.rp.p, int64_t(a.ncols) + 1, s);
+    if (a.nnz > 0) {
+      copy(c_col_idx, C.ci.p, a.nnz, s);
+      if (a.v) copy(c_vals, C.v.p, a.nnz, s);
+    }
+    TPF_HIP(hipStreamSynchronize(s));
+  });
+}
 
 extern "C" int tpf_csr_product(const tpf_csr_view* A, const tpf_csr_view* B,
                                const tpf_csr_view* D, double alpha, double beta, int route,

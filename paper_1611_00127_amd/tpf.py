@@ -159,6 +159,7 @@ _SIGS = {
                                 ctypes.POINTER(CsrView), c_double, c_double, c_int, c_int,
                                 c_void_p, c_void_p, c_void_p, c_int64, ctypes.POINTER(c_int64),
                                 c_void_p]),
+    "tpf_csr_transpose": (c_int, [ctypes.POINTER(CsrView), c_void_p, c_void_p, c_void_p, c_void_p]),
     "tpf_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(SolveOpts),
                           ctypes.POINTER(SolveInfo), c_void_p]),
     "tpf_server_default_opts": (c_int, [ctypes.POINTER(ServerOpts)]),
@@ -422,6 +423,20 @@ def tpf_csr_product(A, B, D=None, alpha=1.0, beta=1.0, route=0, pattern=None, st
                                _ptr(rp), _ptr(ci), _ptr(v), m, ctypes.byref(nnz),
                                _stream(stream)))
     return rp, ci[:m], v[:m]
+
+
+def tpf_csr_transpose(A, stream=None):
+    """A^T of A = (row_ptr, col_idx, vals, n_cols) device tensors; returns
+    (row_ptr, col_idx, vals) device tensors."""
+    import torch
+    a = _csr_arg(A)
+    dev = A[0].device
+    m, nnz = int(A[3]), len(A[1])
+    rp = torch.empty(m + 1, dtype=torch.int32, device=dev)
+    ci = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+    v = torch.empty(max(nnz, 1), dtype=torch.float64, device=dev)
+    _check(load().tpf_csr_transpose(ctypes.byref(a), _ptr(rp), _ptr(ci), _ptr(v), _stream(stream)))
+    return rp, ci[:nnz], v[:nnz]
 
 
 def tpf_solve(J, M, b, x, rtol=1e-8, restart=30, maxit=1000, stream=None):

@@ -112,18 +112,18 @@ def _mixed(rng, ncols_b=3000, window=None, max_la=2100):
     return A, B
 
 
-@pytest.mark.parametrize("route", list(range(9)))
+@pytest.mark.parametrize("route", list(range(10)))
 def test_product_every_class(gpu, route):
     tpf, torch = gpu
     rng = np.random.default_rng(11)
     # the per-row merge costs (outputs x A's row length) per thread: shorter
     # A rows when every row is forced there
-    A, B = _mixed(rng, max_la=300 if route == 8 else 2100)
+    A, B = _mixed(rng, max_la=300 if route == 9 else 2100)
     say(f"[spgemm] mixed rows, route {route}")
     _check(tpf, torch, A, B, route=route, label=f"route {route}")
 
 
-@pytest.mark.parametrize("route", [0, 4, 5, 6, 7])
+@pytest.mark.parametrize("route", [0, 5, 6, 7, 8])
 def test_product_long_runs(gpu, route):
     """Products concentrated on 5 columns: runs of up to ~5,000 equal
     columns, spanning threads and wavefronts."""
@@ -134,21 +134,21 @@ def test_product_long_runs(gpu, route):
     _check(tpf, torch, A, B, route=route, label=f"long runs route {route}")
 
 
-@pytest.mark.parametrize("route", [0, 5, 8])
+@pytest.mark.parametrize("route", [0, 6, 9])
 def test_product_with_added_matrix(gpu, route):
     """C = -A B + D on the union pattern (the S~ form)."""
     tpf, torch = gpu
     rng = np.random.default_rng(13)
-    A, B = _mixed(rng, max_la=300 if route == 8 else 2100)
+    A, B = _mixed(rng, max_la=300 if route == 9 else 2100)
     ld = np.array([0, 1, 4, 30, 100])[np.arange(A.shape[0]) % 5]
     D = _random_csr(rng, ld, B.shape[1])
     say(f"[spgemm] with D, route {route}")
     _check(tpf, torch, A, B, D, alpha=-1.0, beta=1.0, route=route, label=f"D route {route}")
 
 
-@pytest.mark.parametrize("route", [0, 4, 5, 6])
+@pytest.mark.parametrize("route", [0, 4, 5, 6, 7])
 def test_product_wide_keys(gpu, route):
-    """8,388,613 columns: the 512-, 2048- and 8192-product classes take
+    """8,388,613 columns: the 512-, 1024-, 2048- and 8192-product classes take
     64-bit (column, index) keys."""
     tpf, torch = gpu
     rng = np.random.default_rng(14)
@@ -186,4 +186,32 @@ def test_product_refresh_and_edges(gpu):
     with pytest.raises(tpf.TpfError):
         tpf.tpf_csr_product(_dev(torch, A), _dev(torch, bad))
     with pytest.raises(tpf.TpfError):
-        tpf.tpf_csr_product(_dev(torch, A), _dev(torch, B), route=9)
+        tpf.tpf_csr_product(_dev(torch, A), _dev(torch, B), route=10)
+
+
+def test_transpose_every_row_class(gpu):
+    """Transposes whose rows span every sorting path: up to 16 entries (a
+    lane group per row), up to 1,024 (a wavefront), up to 4,096 (a
+    work-group) and beyond (one thread), against scipy's transpose."""
+    tpf, torch = gpu
+    rng = np.random.default_rng(16)
+    n, m = 6000, 3000
+    # column 0 in every row (6,000 entries in its transposed row), column 1 in
+    # every third (2,000), column 2 in every twelfth (500), plus 0-7 others
+    rows, cols = [], []
+    for i in range(n):
+        extra = rng.choice(np.arange(3, m), size=rng.integers(0, 8), replace=False)
+        c = np.unique(np.concatenate([[0], [1] if i % 3 == 0 else [], [2] if i % 12 == 0 else [],
+                                      extra]).astype(np.int64))
+        rows.append(np.full(len(c), i)); cols.append(c)
+    r = np.concatenate(rows); c = np.concatenate(cols)
+    A = sp.csr_matrix((0.5 + rng.random(len(r)), (r, c)), shape=(n, m))
+    A.sort_indices()
+    T = A.T.tocsr(); T.sort_indices()
+    lens = np.diff(T.indptr)
+    say(f"[transpose] row lengths of A^T: max {lens.max()}, >16: {(lens > 16).sum()}, "
+        f">1024: {(lens > 1024).sum()}, >4096: {(lens > 4096).sum()}")
+    assert (lens <= 16).any() and (lens > 1024).any() and (lens > 4096).any()
+    rp, ci, v = (t.cpu().numpy() for t in tpf.tpf_csr_transpose(_dev(torch, A)))
+    assert np.array_equal(rp, T.indptr) and np.array_equal(ci, T.indices)
+    assert np.array_equal(v, T.data)
