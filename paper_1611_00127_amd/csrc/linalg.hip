@@ -268,7 +268,10 @@ __global__ void __launch_bounds__(256) k_pack_rows(int n, const int64_t* __restr
 void pack_rows(int n, const int64_t* toff, const int* crp, int64_t nnz, const int* tci,
                const double* tv, int* cci, double* cv, hipStream_t s) {
   if (n <= 0) return;
-  const int lpr = lanes_per_row(n, nnz);
+  // a plain copy: about one entry per lane (staged rows are far apart, so
+  // short rows with one lane each would read a cache line per entry)
+  int lpr = 1;
+  while (lpr < 64 && int64_t(lpr) * n < nnz) lpr <<= 1;
   DISPATCH_LPR(lpr, LL, {
     k_pack_rows<LL><<<grid_for(int64_t(n) * lpr, 256), 256, 0, s>>>(n, toff, crp, tci, tv, cci,
                                                                      cv);
