@@ -197,7 +197,8 @@ __global__ void k_pmis_update(int n, const int* __restrict__ srp, const int* __r
 // rounds[0] receives the number of rounds, or -1 if n + 1 rounds left
 // points undecided.
 constexpr int kPmisWg = 1024;
-constexpr int kPmisWgMax = 16384;  // levels up to this size use it
+constexpr int kPmisWgMax = 4096;  // levels up to this size use it (on larger ones a
+                                  // kernel pair per round and a host check is faster)
 __global__ void __launch_bounds__(kPmisWg) k_pmis_block(
     int n, const int* __restrict__ srp, const int* __restrict__ sci,
     const int* __restrict__ strp, const int* __restrict__ stci, const double* __restrict__ w,
