@@ -491,6 +491,223 @@ __global__ void __launch_bounds__(BLOCK, BLOCK == 64 ? 8 : (BLOCK == 256 ? 4 : 2
   if (threadIdx.x == 0) cnt[i] = count;
 }
 
+// Bitonic sort of the p2 (a power of two, at most G PER) keys of a G-lane
+// group: element t = q G + ll sits in register q of group lane ll.  Exchanges
+// at distance >= G stay inside a lane, shorter ones are shuffles within the
+// group (groups are G-aligned, so lane ^ j stays in the group).
+template <int G, int PER, class KEY>
+__device__ inline void bitonic_group(KEY (&kr)[PER], int ll, int p2) {
+  for (int kk = 2; kk <= p2; kk <<= 1)
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      if (j >= G) {
+        const int qj = j / G;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          if ((q & qj) != 0) continue;
+          const int qp = q | qj;
+          if (qp >= PER) continue;
+          const bool up = ((q * G + ll) & kk) == 0;
+          const KEY x = kr[q], y = kr[qp];
+          const bool sw = (x > y) == up;
+          kr[q] = sw ? y : x;
+          kr[qp] = sw ? x : y;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          const KEY x = kr[q];
+          const KEY y = __shfl_xor(x, j, 64);
+          const bool up = ((q * G + ll) & kk) == 0, lower = (ll & j) == 0;
+          const KEY mn = x < y ? x : y, mx = x < y ? y : x;
+          kr[q] = lower == up ? mn : mx;
+        }
+      }
+    }
+}
+
+// Exclusive segmented scan of RunPart over the G lanes of a group.
+template <int G>
+__device__ inline RunPart run_scan_group(RunPart x, int ll) {
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) {
+    RunPart y{__shfl_up(x.f, off, G), __shfl_up(x.s, off, G), __shfl_up(x.d, off, G)};
+    if (ll >= off) x = run_combine(y, x);
+  }
+  RunPart ex{__shfl_up(x.f, 1, G), __shfl_up(x.s, 1, G), __shfl_up(x.d, 1, G)};
+  if (ll == 0) ex = RunPart{0, 0.0, 0.0};
+  return ex;
+}
+
+// The flattened-product row kernel with 64 / G rows per wavefront, a G-lane
+// group per row (at most G PER products and G PER entries in A's row): the
+// same steps as k_spgemm_flat (located products, loads issued together,
+// register bitonic sort, contiguous run-sum chunks with a segmented scan),
+// each group on its own LDS slice.  More rows in flight per CU for the many
+// short rows of the finest levels.
+template <int G, int PER, class KEY>
+__global__ void __launch_bounds__(64, 8) k_spgemm_group(
+    int nlist, const int* __restrict__ rows, const int* __restrict__ arp,
+    const int* __restrict__ aci, const double* __restrict__ av, const int* __restrict__ brp,
+    const int* __restrict__ bci, const double* __restrict__ bv, const int* __restrict__ drp,
+    const int* __restrict__ dci, const double* __restrict__ dv, double alpha, double beta,
+    int* __restrict__ cnt, const int64_t* __restrict__ toff, int* __restrict__ cci,
+    double* __restrict__ cv) {
+  constexpr int CAP = G * PER, RPW = 64 / G;
+  using FK = FlatKey<KEY, CAP>;
+  constexpr int kValBytes = CAP * int(sizeof(double));
+  constexpr int kSlice = kValBytes + CAP * int(sizeof(KEY));
+  static_assert((2 * CAP + 1) * int(sizeof(int)) <= kSlice, "offsets must fit in the slice");
+  __shared__ __attribute__((aligned(16))) unsigned char lds[RPW * kSlice];
+  const int lane = threadIdx.x, g = lane / G, ll = lane % G;
+  unsigned char* mine = lds + g * kSlice;
+  int* offs = reinterpret_cast<int*>(mine);      // CAP + 1
+  int* bst = offs + CAP + 1;                     // CAP
+  double* pv = reinterpret_cast<double*>(mine);  // CAP values (after the offsets are dead)
+  KEY* keys = reinterpret_cast<KEY*>(mine + kValBytes);
+  const int slot = blockIdx.x * RPW + g;
+  const bool live = slot < nlist;
+  const int i = live ? rows[slot] : 0;
+  const int a0 = live ? arp[i] : 0, a1 = live ? arp[i + 1] : 0;
+  const int la = a1 - a0;
+  int run = 0;
+  for (int base = 0; base < la; base += G) {
+    const int e = base + ll;
+    int len = 0, b0 = 0;
+    if (e < la) {
+      const int k = aci[a0 + e];
+      b0 = brp[k];
+      len = brp[k + 1] - b0;
+    }
+    int x = len;
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) {
+      const int y = __shfl_up(x, off, G);
+      if (ll >= off) x += y;
+    }
+    if (e < la) {
+      offs[e] = run + x - len;
+      bst[e] = b0;
+    }
+    run += __shfl(x, G - 1, G);
+  }
+  if (ll == 0) offs[la] = run;
+  const int nprod = run;
+  const int nd = live && drp ? drp[i + 1] - drp[i] : 0;
+  const int u = nprod + nd;
+  int p2 = 1;
+  while (p2 < u) p2 <<= 1;
+  int top = 1;
+  while (2 * top < la) top <<= 1;
+  __syncthreads();
+  int ent[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) ent[q] = 0;
+  const int tlast = nprod - 1;
+  for (int step = top; step > 0; step >>= 1) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int t = min(q * G + ll, tlast);
+      const int c = ent[q] + step;
+      if (c < la && offs[c] <= t) ent[q] = c;
+    }
+  }
+  const int d0 = nd > 0 ? drp[i] : 0;
+  int col[PER];
+  double val[PER];
+  if (u > 0) {
+    double x[PER], a[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int t = q * G + ll;
+      const bool fromb = nprod > 0 && (t < nprod || nd == 0);
+      const int tb = min(t, tlast);
+      const int idx = fromb ? bst[ent[q]] + (tb - offs[ent[q]]) : d0 + min(max(t - nprod, 0), nd - 1);
+      const int* cp = fromb ? bci : dci;
+      const double* vp = fromb ? bv : dv;
+      col[q] = cp[idx];
+      x[q] = vp[idx];
+      a[q] = la > 0 ? av[a0 + ent[q]] : 1.0;
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) val[q] = q * G + ll < nprod ? a[q] * x[q] : x[q];
+  }
+  KEY kr[PER];
+  __syncthreads();  // offsets and row starts are dead: values take their place
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int t = q * G + ll;
+    kr[q] = t < u ? (static_cast<KEY>(static_cast<unsigned>(col[q])) << FK::kIdxBits) | KEY(t)
+                  : ~KEY(0);
+    if (t < u) pv[t] = val[q];
+  }
+  bitonic_group<G, PER>(kr, ll, p2);
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int t = q * G + ll;
+    if (t < p2) keys[t] = kr[q];
+  }
+  __syncthreads();
+  // run sums: group lane ll takes the sorted elements [ll PER, (ll + 1) PER)
+  const int t0 = ll * PER;
+  int rc[PER];
+  double rv[PER];
+  bool rd[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    rc[q] = -1;
+    rv[q] = 0.0;
+    rd[q] = false;
+    if (t0 + q < u) {
+      const KEY k = keys[t0 + q];
+      const int e = int(k & FK::kIdxMask);
+      rc[q] = int(k >> FK::kIdxBits);
+      rv[q] = pv[e];
+      rd[q] = e >= nprod;
+    }
+  }
+  const int cprev = (t0 > 0 && t0 < u) ? int(keys[t0 - 1] >> FK::kIdxBits) : -1;
+  const int cnext = (t0 + PER < u) ? int(keys[t0 + PER] >> FK::kIdxBits) : -1;
+  RunPart part{0, 0.0, 0.0};
+  int heads = 0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    if (t0 + q >= u) break;
+    if (rc[q] != (q ? rc[q - 1] : cprev)) {
+      part = RunPart{1, 0.0, 0.0};
+      ++heads;
+    }
+    if (rd[q]) part.d += rv[q];
+    else part.s += rv[q];
+  }
+  int hx = heads;
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) {
+    const int y = __shfl_up(hx, off, G);
+    if (ll >= off) hx += y;
+  }
+  const int count = __shfl(hx, G - 1, G);
+  hx -= heads;
+  RunPart acc = run_scan_group<G>(part, ll);
+  if (!live) return;
+  const int64_t o = toff[i];
+  int r = hx - 1;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    if (t0 + q >= u) break;
+    if (rc[q] != (q ? rc[q - 1] : cprev)) {
+      acc = RunPart{1, 0.0, 0.0};
+      ++r;
+    }
+    if (rd[q]) acc.d += rv[q];
+    else acc.s += rv[q];
+    if (rc[q] != (q + 1 < PER ? rc[q + 1] : cnext)) {
+      cci[o + r] = rc[q];
+      cv[o + r] = beta * acc.d + alpha * acc.s;
+    }
+  }
+  if (ll == 0) cnt[i] = count;
+}
+
 // numeric refresh on a known pattern: one wavefront per row
 __global__ void __launch_bounds__(64) k_spgemm_values(
     int nrows, const int* __restrict__ arp, const int* __restrict__ aci,
@@ -801,8 +1018,22 @@ void spgemm(const CsrRef<double>& A, const CsrRef<double>& B, Csr<double>& C, hi
   using C1024 = std::integral_constant<int, 1024>;
   using C2048 = std::integral_constant<int, 2048>;
   using C8192 = std::integral_constant<int, 8192>;
-  flat(W1{}, C64{}, C64{}, 0);
-  flat(W1{}, C128{}, C128{}, 1);
+  // the two smallest classes: 16-lane groups, four rows per wavefront
+  auto group = [&](auto per_tag, int c) {
+    constexpr int PER = decltype(per_tag)::value, CP = 16 * PER;
+    if (hc[c] == 0) return;
+    const unsigned grid = grid_for(hc[c], 4);
+    if (int64_t(B.ncols) < (int64_t(1) << (32 - __builtin_ctz(CP))))
+      k_spgemm_group<16, PER, uint32_t><<<grid, 64, 0, s>>>(
+          hc[c], list(c), A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha, beta, cnt.p,
+          toff.p, tci.p, tv.p);
+    else
+      k_spgemm_group<16, PER, uint64_t><<<grid, 64, 0, s>>>(
+          hc[c], list(c), A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha, beta, cnt.p,
+          toff.p, tci.p, tv.p);
+  };
+  group(std::integral_constant<int, 4>{}, 0);
+  group(std::integral_constant<int, 8>{}, 1);
   flat(W1{}, C256{}, C256{}, 2);
   flat(W1{}, C512{}, C512{}, 3);
   flat(W1{}, C1024{}, C1024{}, 4);

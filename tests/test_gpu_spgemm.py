@@ -157,6 +157,19 @@ def test_product_wide_keys(gpu, route):
     _check(tpf, torch, A, B, route=route, label=f"wide route {route}")
 
 
+@pytest.mark.parametrize("route", [0, 2])
+def test_product_wide_keys_small_rows(gpu, route):
+    """67,108,869 columns: even the smallest classes (lane groups of 16,
+    four rows per wavefront) take 64-bit keys."""
+    tpf, torch = gpu
+    rng = np.random.default_rng(17)
+    nb, ncols = 500, (1 << 26) + 5
+    B = _random_csr(rng, np.arange(nb) % 6, ncols)
+    A = _random_csr(rng, np.arange(300) % 31, nb)
+    say(f"[spgemm] 2^26+5 columns, small rows, route {route}")
+    _check(tpf, torch, A, B, route=route, label=f"wide small route {route}")
+
+
 def test_product_refresh_and_edges(gpu):
     tpf, torch = gpu
     rng = np.random.default_rng(15)
