@@ -1011,30 +1011,29 @@ void spgemm(const CsrRef<double>& A, const CsrRef<double>& B, Csr<double>& C, hi
   using W1 = std::integral_constant<int, 64>;
   using W4 = std::integral_constant<int, 256>;
   using W8 = std::integral_constant<int, 512>;
-  using C64 = std::integral_constant<int, 64>;
-  using C128 = std::integral_constant<int, 128>;
-  using C256 = std::integral_constant<int, 256>;
   using C512 = std::integral_constant<int, 512>;
   using C1024 = std::integral_constant<int, 1024>;
   using C2048 = std::integral_constant<int, 2048>;
   using C8192 = std::integral_constant<int, 8192>;
-  // the two smallest classes: 16-lane groups, four rows per wavefront
-  auto group = [&](auto per_tag, int c) {
-    constexpr int PER = decltype(per_tag)::value, CP = 16 * PER;
+  // the three smallest classes: lane groups, four (16 lanes) or two (32) rows per wavefront
+  auto group = [&](auto g_tag, auto per_tag, int c) {
+    constexpr int G = decltype(g_tag)::value, PER = decltype(per_tag)::value, CP = G * PER;
     if (hc[c] == 0) return;
-    const unsigned grid = grid_for(hc[c], 4);
+    const unsigned grid = grid_for(hc[c], 64 / G);
     if (int64_t(B.ncols) < (int64_t(1) << (32 - __builtin_ctz(CP))))
-      k_spgemm_group<16, PER, uint32_t><<<grid, 64, 0, s>>>(
+      k_spgemm_group<G, PER, uint32_t><<<grid, 64, 0, s>>>(
           hc[c], list(c), A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha, beta, cnt.p,
           toff.p, tci.p, tv.p);
     else
-      k_spgemm_group<16, PER, uint64_t><<<grid, 64, 0, s>>>(
+      k_spgemm_group<G, PER, uint64_t><<<grid, 64, 0, s>>>(
           hc[c], list(c), A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha, beta, cnt.p,
           toff.p, tci.p, tv.p);
   };
-  group(std::integral_constant<int, 4>{}, 0);
-  group(std::integral_constant<int, 8>{}, 1);
-  flat(W1{}, C256{}, C256{}, 2);
+  using G16 = std::integral_constant<int, 16>;
+  using G32 = std::integral_constant<int, 32>;
+  group(G16{}, std::integral_constant<int, 4>{}, 0);
+  group(G16{}, std::integral_constant<int, 8>{}, 1);
+  group(G32{}, std::integral_constant<int, 8>{}, 2);
   flat(W1{}, C512{}, C512{}, 3);
   flat(W1{}, C1024{}, C1024{}, 4);
   flat(W4{}, C2048{}, C2048{}, 5);
