@@ -1179,6 +1179,21 @@ __global__ void __launch_bounds__(256) k_vc_pre(int n, const int* __restrict__ r
   if (lane == 0) r[row] = b[row] - sum;
 }
 
+// r = b - A g with g = D^{-1} b formed beforehand (large levels: one gather
+// per entry instead of two)
+template <class T, int LPR>
+__global__ void __launch_bounds__(256) k_vc_pre_g(int n, const int* __restrict__ rp,
+                                                  const int* __restrict__ ci,
+                                                  const T* __restrict__ v,
+                                                  const T* __restrict__ g,
+                                                  const T* __restrict__ b, T* __restrict__ r) {
+  int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int row = int(gid / LPR), lane = int(gid % LPR);
+  if (row >= n) return;
+  T sum = row_dot<T, LPR>(row, lane, rp, ci, v, [&](int j) { return g[j]; });
+  if (lane == 0) r[row] = b[row] - sum;
+}
+
 // y = D^{-1} b + P x_c: prolongation added to the pre-smoothed iterate
 template <class T, int LPR>
 __global__ void __launch_bounds__(256) k_vc_prolong(int n, const int* __restrict__ prp,
@@ -1730,6 +1745,8 @@ size_t Hierarchy::bytes() const {
 }
 
 // ---------------------------------------------------------------- V-cycle
+constexpr int kGuessRows = 65536;  // CSR levels from this size form D^{-1} b first
+
 template <class T>
 void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st) {
   Level& L = *lv[l];
@@ -1768,8 +1785,10 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st) {
     else
       dv = dia0.v.p;
   }
-  if (dia) {
-    // y holds D^{-1} b until the prolongation overwrites it
+  // large levels form g = D^{-1} b once (in y, until the prolongation
+  // overwrites it), so the residual gathers one vector
+  const bool guess = dia || n >= kGuessRows;
+  if (guess) {
     TimedScope ts(L.t_guess.c_str(), st);
     k_jacobi_guess<T><<<grid_for(n, 256), 256, 0, st>>>(n, dinv, b, y);
     TPF_CHECK_LAUNCH();
@@ -1786,6 +1805,10 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st) {
           k_dia_pre<T, KK><<<grid_for(n, 256), 256, 0, st>>>(n, doff, dv, y, b, r);
         });
       }
+    } else if (guess) {
+      DISPATCH_LPR(lpr, LL, {
+        k_vc_pre_g<T, LL><<<blocks, 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, Av, y, b, r);
+      });
     } else {
       DISPATCH_LPR(lpr, LL, {
         k_vc_pre<T, LL><<<blocks, 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, Av, dinv, b, r);

@@ -67,7 +67,7 @@ __device__ inline T block_exclusive_scan(T v, T* sh, T& total) {
 
 // Dot of CSR row `row` with gathered values g(col); LPR consecutive lanes
 // share the row, each lane summing entries lane, lane + LPR, ... in order
-// (loads issued four entries ahead); result valid in the group's first lane.
+// (loads issued four entries at a time); result valid in the group's first lane.
 template <class T, int LPR, class G>
 __device__ inline T row_dot(int row, int lane, const int* __restrict__ rp,
                             const int* __restrict__ ci, const T* __restrict__ v, G g) {
@@ -84,7 +84,25 @@ __device__ inline T row_dot(int row, int lane, const int* __restrict__ rp,
     sum += p2;
     sum += p3;
   }
-  for (; e < e1; e += LPR) sum += v[e] * g(ci[e]);
+  if (e < e1) {
+    // the last up to four entries: indices clamped to the row's last entry so
+    // that every load is valid and all are issued before the first wait;
+    // entries past the row add nothing
+    int c[4];
+    T a[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int f = min(e + u * LPR, e1 - 1);
+      c[u] = ci[f];
+      a[u] = v[f];
+    }
+    T x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[u] = g(c[u]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (e + u * LPR < e1) sum += a[u] * x[u];
+  }
 #pragma unroll
   for (int off = LPR / 2; off > 0; off >>= 1) sum += __shfl_down(sum, off, LPR);
   return sum;
