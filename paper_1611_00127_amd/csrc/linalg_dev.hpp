@@ -67,40 +67,31 @@ __device__ inline T block_exclusive_scan(T v, T* sh, T& total) {
 
 // Dot of CSR row `row` with gathered values g(col); LPR consecutive lanes
 // share the row, each lane summing entries lane, lane + LPR, ... in order
-// (loads issued four entries at a time); result valid in the group's first lane.
+// (loads issued eight entries at a time); result valid in the group's first lane.
 template <class T, int LPR, class G>
 __device__ inline T row_dot(int row, int lane, const int* __restrict__ rp,
                             const int* __restrict__ ci, const T* __restrict__ v, G g) {
   T sum = T(0);
   const int e1 = rp[row + 1];
   int e = rp[row] + lane;
-  for (; e + 3 * LPR < e1; e += 4 * LPR) {
-    T p0 = v[e] * g(ci[e]);
-    T p1 = v[e + LPR] * g(ci[e + LPR]);
-    T p2 = v[e + 2 * LPR] * g(ci[e + 2 * LPR]);
-    T p3 = v[e + 3 * LPR] * g(ci[e + 3 * LPR]);
-    sum += p0;
-    sum += p1;
-    sum += p2;
-    sum += p3;
-  }
-  if (e < e1) {
-    // the last up to four entries: indices clamped to the row's last entry so
-    // that every load is valid and all are issued before the first wait;
-    // entries past the row add nothing
-    int c[4];
-    T a[4];
+  // eight entries per lane at a time: every position clamped to the row's
+  // last entry, so all loads are valid and issued before the first wait;
+  // positions past the row add nothing (the sums keep the entry order)
+  constexpr int B = 8;
+  for (; e < e1; e += B * LPR) {
+    int c[B];
+    T a[B];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < B; ++u) {
       const int f = min(e + u * LPR, e1 - 1);
       c[u] = ci[f];
       a[u] = v[f];
     }
-    T x[4];
+    T x[B];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) x[u] = g(c[u]);
+    for (int u = 0; u < B; ++u) x[u] = g(c[u]);
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < B; ++u)
       if (e + u * LPR < e1) sum += a[u] * x[u];
   }
 #pragma unroll
