@@ -45,6 +45,8 @@ def parse():
                     help="first run a plain device copy of this many MiB (calibrates the "
                          "FETCH_SIZE/WRITE_SIZE counters of a profiler run)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
+    ap.add_argument("--graphs", action="store_true",
+                    help="replay recorded V-cycle graphs instead of launching every kernel")
     ap.add_argument("--serve-full", action="store_true",
                     help="the full stream: 64 realizations x 16 Newton-step requests, "
                          "grids up to 128^3")
@@ -407,6 +409,7 @@ def main():
 
     from paper_1611_00127_amd import driver, inputs, tpf
     tpf.init()
+    tpf.tpf_set_graphs(args.graphs)
     if args.study:
         fn = study_c2 if args.study == "c2" else study_newton
         print(json.dumps(fn(torch, tpf, driver, inputs, args)), flush=True)

@@ -370,12 +370,14 @@ int tpf_kernel_stats(const char* name, int64_t* count, double* total_ms);
 int tpf_kernel_stats_reset(void);
 
 /* ---- launch mode ------------------------------------------------------- */
-/* Each AMG V-cycle (about five kernels per level) is recorded once as a HIP
- * graph on a private stream, for the (input, output) buffers it is applied
- * to, and replayed on the caller's stream; graphs are dropped whenever the
- * hierarchy is rebuilt or refreshed.  Enabled by default; 0 launches every
- * kernel directly (also the case while kernel timing is on).  Results are
- * identical either way. */
+/* With graphs enabled, each AMG V-cycle (about five kernels per level) is
+ * recorded once as a HIP graph on a private stream, for the (input, output)
+ * buffers it is applied to, and replayed on the caller's stream; graphs are
+ * dropped whenever the hierarchy is rebuilt or refreshed.  Disabled by
+ * default (every kernel launched directly, as also while kernel timing is
+ * on): on the 1M-cell workload a replay starts about 28 us after the
+ * preceding kernel and the solve is 0.2 ms slower; replays save host work
+ * when one thread drives many requests.  Results are identical either way. */
 int tpf_set_graphs(int enable);
 
 #ifdef __cplusplus

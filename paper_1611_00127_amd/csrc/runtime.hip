@@ -199,7 +199,7 @@ HostScratch& host_scratch() {
 bool timing_enabled() { return g_timing; }
 
 namespace {
-std::atomic<bool> g_graphs{true};
+std::atomic<bool> g_graphs{false};
 }
 bool graphs_enabled() { return g_graphs.load(std::memory_order_relaxed); }
 

@@ -398,7 +398,7 @@ def test_graph_replays_match_eager(gpu, kind, precision):
             xs.append(x.cpu().numpy()); its.append(info.iterations)
         assert its[0] == its[1] and np.array_equal(xs[0], xs[1])
     finally:
-        tpf.tpf_set_graphs(True)
+        tpf.tpf_set_graphs(False)  # the library default
         M.close(); g.close()
 
 
