@@ -1611,13 +1611,16 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
   finish_levels(s);
 }
 
+// The Galerkin products are recomputed in full: the single-pass product
+// yields the same pattern and is faster than a values-only pass over the
+// kept one (k_spgemm_values searches B's rows per output entry).
 void Hierarchy::refresh(hipStream_t st) {
   drop_graphs();
   s = st;
   for (size_t l = 0; l + 1 < lv.size(); ++l) {
     Level& L = *lv[l];
-    spgemm(ref(L.A), ref(L.P), L.AP, s, nullptr, 1.0, 1.0, true);
-    spgemm(ref(L.R), ref(L.AP), lv[l + 1]->A, s, nullptr, 1.0, 1.0, true);
+    spgemm(ref(L.A), ref(L.P), L.AP, s);
+    spgemm(ref(L.R), ref(L.AP), lv[l + 1]->A, s);
   }
   finish_levels(s);
 }

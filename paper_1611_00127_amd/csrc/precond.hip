@@ -745,7 +745,7 @@ int tpf_precond_setup(tpf_precond* M, const tpf_jacobian* J, int reuse, void* st
               H->build(std::move(S), ao_p, ms);
               M->H[1] = std::move(H);
             } else {
-              spgemm(Y, Asp, M->H[1]->A0(), ms, &App, -1.0, 1.0, true);
+              spgemm(Y, Asp, M->H[1]->A0(), ms, &App, -1.0, 1.0);  // same pattern, in full
               M->H[1]->refresh(ms);
             }
           });
