@@ -21,9 +21,11 @@ namespace tpf {
 namespace {
 constexpr int kKBlock = 256;
 
+constexpr int kKGridMax = 2048;  // blocks of the streaming passes (partial sums per block)
+
 int krylov_grid(int64_t n) {
   int64_t g = (n + kKBlock * 4 - 1) / (kKBlock * 4);
-  if (g > 1024) g = 1024;
+  if (g > kKGridMax) g = kKGridMax;
   if (g < 1) g = 1;
   return int(g);
 }
@@ -220,9 +222,15 @@ __global__ void k_update_x(int64_t n, int k, const double* __restrict__ Z,
   }
 }
 
+// register arrays sized to the basis length in steps of four up to 24 (the
+// pass-2 kernel holds KMAX basis values and KMAX sums per thread, so the
+// step sets its occupancy)
 #define DISPATCH_K(nk, KM, ...)                                  \
   if (nk <= 8) { constexpr int KM = 8; __VA_ARGS__ }             \
+  else if (nk <= 12) { constexpr int KM = 12; __VA_ARGS__ }      \
   else if (nk <= 16) { constexpr int KM = 16; __VA_ARGS__ }      \
+  else if (nk <= 20) { constexpr int KM = 20; __VA_ARGS__ }      \
+  else if (nk <= 24) { constexpr int KM = 24; __VA_ARGS__ }      \
   else if (nk <= 32) { constexpr int KM = 32; __VA_ARGS__ }      \
   else { constexpr int KM = 64; __VA_ARGS__ }
 
@@ -248,7 +256,7 @@ void Fgmres::alloc(int64_t nn, int mm, hipStream_t st) {
   g.alloc(m + 1, st);
   h1.alloc(kMaxRestart + 1, st);
   h2.alloc(kMaxRestart + 1, st);
-  part.alloc(size_t(1024) * 64, st);
+  part.alloc(size_t(kKGridMax) * 64, st);
   y.alloc(m, st);
   r.alloc(n, st);
   st_dev.alloc(4, st);
