@@ -55,15 +55,23 @@ template <int KMAX>
 __global__ void __launch_bounds__(kKBlock) k_cgs_dots(int64_t n, int nk, const double* __restrict__ V,
                                                       const double* __restrict__ w,
                                                       double* __restrict__ part) {
+  // entries in pairs (n is even and every basis vector 16-byte aligned)
   double acc[KMAX];
 #pragma unroll
   for (int k = 0; k < KMAX; ++k) acc[k] = 0.0;
-  for (int64_t i = int64_t(blockIdx.x) * kKBlock + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * kKBlock) {
-    double wi = w[i];
+  const int64_t n2 = n / 2;
+  const double2* V2 = reinterpret_cast<const double2*>(V);
+  const double2* w2 = reinterpret_cast<const double2*>(w);
+  for (int64_t p = int64_t(blockIdx.x) * kKBlock + threadIdx.x; p < n2;
+       p += int64_t(gridDim.x) * kKBlock) {
+    const double2 wi = w2[p];
 #pragma unroll
     for (int k = 0; k < KMAX; ++k)
-      if (k < nk) acc[k] += V[k * n + i] * wi;
+      if (k < nk) {
+        const double2 v = V2[k * n2 + p];
+        acc[k] += v.x * wi.x;
+        acc[k] += v.y * wi.y;
+      }
   }
   reduce_store<KMAX>(acc, nk, part);
 }
@@ -110,14 +118,22 @@ __global__ void __launch_bounds__(kKBlock) k_cgs_axpy_norm(int64_t n, int nk,
   for (int k = threadIdx.x; k < nk; k += kKBlock) hs[k] = h[k];
   __syncthreads();
   double acc[1] = {0.0};
-  for (int64_t i = int64_t(blockIdx.x) * kKBlock + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * kKBlock) {
-    double wi = w[i];
+  const int64_t n2 = n / 2;  // entries in pairs, as in k_cgs_dots
+  const double2* V2 = reinterpret_cast<const double2*>(V);
+  double2* w2 = reinterpret_cast<double2*>(w);
+  for (int64_t p = int64_t(blockIdx.x) * kKBlock + threadIdx.x; p < n2;
+       p += int64_t(gridDim.x) * kKBlock) {
+    double2 wi = w2[p];
 #pragma unroll
     for (int k = 0; k < KMAX; ++k)
-      if (k < nk) wi -= hs[k] * V[k * n + i];
-    w[i] = wi;
-    acc[0] += wi * wi;
+      if (k < nk) {
+        const double2 v = V2[k * n2 + p];
+        wi.x -= hs[k] * v.x;
+        wi.y -= hs[k] * v.y;
+      }
+    w2[p] = wi;
+    acc[0] += wi.x * wi.x;
+    acc[0] += wi.y * wi.y;
   }
   reduce_store<1>(acc, 1, part);
 }
@@ -282,7 +298,7 @@ void Fgmres::begin(const tpf_jacobian* J_, tpf_precond* M_, const double* b_, do
   s = st;
   TPF_REQUIRE(host_slot, TPF_ERR_INVALID_ARG, "null host slot");
   host = host_slot;
-  alloc(2 * int64_t(J->nb), o.restart, s);
+  alloc(2 * int64_t(J->nb), o.restart, s);  // n even: the streaming passes read pairs
   G = krylov_grid(n);
   total = 0;
   est = 1.0;
