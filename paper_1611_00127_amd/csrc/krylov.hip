@@ -76,35 +76,58 @@ __global__ void __launch_bounds__(kKBlock) k_cgs_dots(int64_t n, int nk, const d
   reduce_store<KMAX>(acc, nk, part);
 }
 
-// pass 2: w -= V h; part = V^T w
+// pass 2: w -= V h; part = V^T w.  Two lanes per entry, each holding half
+// of the basis (so half the registers): each lane sums h_k v_k over its half,
+// the pair adds the two sums (the same value in both lanes), the first lane
+// writes w, and each lane accumulates its half of the dot products.
 template <int KMAX>
 __global__ void __launch_bounds__(kKBlock) k_cgs_axpy_dots(int64_t n, int nk,
                                                            const double* __restrict__ V,
                                                            const double* __restrict__ h,
                                                            double* __restrict__ w,
                                                            double* __restrict__ part) {
-  __shared__ double hs[KMAX];
-  for (int k = threadIdx.x; k < nk; k += kKBlock) hs[k] = h[k];
+  constexpr int KH = (KMAX + 1) / 2;
+  __shared__ double hs[2 * KH];
+  __shared__ double sh[kKBlock / 64][2 * KH];
+  for (int k = threadIdx.x; k < 2 * KH; k += kKBlock) hs[k] = k < nk ? h[k] : 0.0;
   __syncthreads();
-  double acc[KMAX];
+  const int half = threadIdx.x & 1, k0 = half * KH;
+  double acc[KH];
 #pragma unroll
-  for (int k = 0; k < KMAX; ++k) acc[k] = 0.0;
-  for (int64_t i = int64_t(blockIdx.x) * kKBlock + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * kKBlock) {
-    double v[KMAX];
-    double wi = w[i];
+  for (int u = 0; u < KH; ++u) acc[u] = 0.0;
+  for (int64_t i = (int64_t(blockIdx.x) * kKBlock + threadIdx.x) >> 1; i < n;
+       i += int64_t(gridDim.x) * (kKBlock / 2)) {
+    double v[KH];
+    double sw = 0.0;
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k)
-      if (k < nk) {
-        v[k] = V[k * n + i];
-        wi -= hs[k] * v[k];
+    for (int u = 0; u < KH; ++u) {
+      v[u] = 0.0;
+      if (k0 + u < nk) {
+        v[u] = V[int64_t(k0 + u) * n + i];
+        sw += hs[k0 + u] * v[u];
       }
-    w[i] = wi;
+    }
+    const double wi = w[i] - (sw + __shfl_xor(sw, 1, 64));
+    if (half == 0) w[i] = wi;
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k)
-      if (k < nk) acc[k] += v[k] * wi;
+    for (int u = 0; u < KH; ++u)
+      if (k0 + u < nk) acc[u] += v[u] * wi;
   }
-  reduce_store<KMAX>(acc, nk, part);
+  // block sums per basis vector: lanes of one half (every other lane) first
+  const int lane = threadIdx.x & 63, wid = threadIdx.x / 64;
+#pragma unroll
+  for (int u = 0; u < KH; ++u) {
+    double t = acc[u];
+#pragma unroll
+    for (int off = 32; off >= 2; off >>= 1) t += __shfl_down(t, off, 64);
+    if (lane < 2) sh[wid][lane * KH + u] = t;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < nk; k += kKBlock) {
+    double t = 0.0;
+    for (int ww = 0; ww < kKBlock / 64; ++ww) t += sh[ww][k];
+    part[int64_t(blockIdx.x) * KMAX + k] = t;
+  }
 }
 
 // pass 3: w -= V h; part = ||w||^2
