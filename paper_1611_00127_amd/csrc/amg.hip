@@ -167,6 +167,9 @@ __global__ void k_pmis_select(int n, const int* __restrict__ srp, const int* __r
   newc[i] = sel;
 }
 
+// `undecided` is set to 1 (plain stores, all of the same value) when a point
+// stays undecided.  A count would take one same-address atomic per wavefront,
+// and those serialise: on a million points they cost more than the round.
 __global__ void k_pmis_update(int n, const int* __restrict__ srp, const int* __restrict__ sci,
                               const uint8_t* __restrict__ newc, int8_t* __restrict__ state,
                               int* __restrict__ undecided) {
@@ -188,8 +191,7 @@ __global__ void k_pmis_update(int n, const int* __restrict__ srp, const int* __r
         und = true;
     }
   }
-  unsigned long long b = __ballot(und);
-  if ((threadIdx.x & 63) == 0 && b) atomicAdd(undecided, int(__popcll(b)));
+  if (__ballot(und) && (threadIdx.x & 63) == 0) *undecided = 1;
 }
 
 // All PMIS rounds of a small level in one work-group (the same select and
@@ -557,18 +559,21 @@ __global__ void __launch_bounds__(256) k_exti_ub(int n, const int* __restrict__ 
 __global__ void k_exti_classify(int n, const int* __restrict__ ub, const int* __restrict__ fl,
                                 const int* __restrict__ nk, const int8_t* __restrict__ cf,
                                 int first, int* __restrict__ counts, int* __restrict__ lists) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int c = -1;
-  if (i < n && cf[i] != kC) {
-    c = kExtClasses - 1;
-    if (first <= kExtFlatN && ub[i] <= kExtCapWide) c = kExtFlatN;
+  block_append_rows<kExtClasses, 256, kClassifyRows>(
+      n,
+      [&](int i) {
+        if (cf[i] == kC) return -1;
+        const int u = ub[i], f = fl[i], k0 = nk[i];
+        int c = kExtClasses - 1;
+        if (first <= kExtFlatN && u <= kExtCapWide) c = kExtFlatN;
 #pragma unroll
-    for (int k = kExtFlatN - 1; k >= 0; --k)
-      if (k >= first && nk[i] <= kExtFlatClasses[k].k && ub[i] <= kExtFlatClasses[k].cap &&
-          fl[i] <= kExtFlatClasses[k].flat)
-        c = k;
-  }
-  block_append<kExtClasses, 256>(c, i, n, counts, lists);
+        for (int k = kExtFlatN - 1; k >= 0; --k)
+          if (k >= first && k0 <= kExtFlatClasses[k].k && u <= kExtFlatClasses[k].cap &&
+              f <= kExtFlatClasses[k].flat)
+            c = k;
+        return c;
+      },
+      n, counts, lists);
 }
 
 __device__ inline int lds_find(const int* u, int m, int key) {
@@ -1264,15 +1269,17 @@ struct DiagOffs {
 // has no entry).  A work-group takes kDiaRows consecutive rows: LPR lanes per
 // row read the entries (coalesced), place them in an LDS tile by diagonal
 // (binary search over the ascending offsets), then the tile is written out
-// one diagonal at a time (coalesced).  *placed counts the entries that lie on
-// a listed diagonal; the layout is usable when that equals nnz.
+// one diagonal at a time (coalesced).  A work-group whose rows hold an entry
+// off the listed diagonals sets *missed to 1 (a plain store: one
+// same-address atomic per work-group would serialise over the whole grid);
+// the layout is usable when *missed stays 0.
 constexpr int kDiaRows = 64;
 template <int LPR>
 __global__ void __launch_bounds__(256) k_csr_to_dia(int n, const int* __restrict__ rp,
                                                     const int* __restrict__ ci,
                                                     const double* __restrict__ v, int K,
                                                     DiagOffs o, double* __restrict__ dv,
-                                                    unsigned long long* __restrict__ placed) {
+                                                    int* __restrict__ missed) {
   __shared__ double tile[kMaxDiag][kDiaRows];
   __shared__ int off[kMaxDiag];
   __shared__ int sh[256 / 64];
@@ -1309,7 +1316,7 @@ __global__ void __launch_bounds__(256) k_csr_to_dia(int n, const int* __restrict
     if (r < rows) dv[int64_t(k) * n + i0 + r] = tile[k][r];
   }
   const int tot = block_sum<256>(found, sh);
-  if (threadIdx.x == 0 && tot) atomicAdd(placed, static_cast<unsigned long long>(tot));
+  if (threadIdx.x == 0 && tot != rp[i0 + rows] - rp[i0]) *missed = 1;
 }
 
 __device__ inline int clampi(int j, int n) { return j < 0 ? 0 : (j >= n ? n - 1 : j); }
@@ -1539,7 +1546,7 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
         });
         TPF_CHECK_LAUNCH();
       }
-      k_exti_classify<<<grid_for(n, 256), 256, 0, s>>>(n, ub.p, fl.p, nk.p, L.cf.p, o.exti_first,
+      k_exti_classify<<<grid_for(n, 256 * kClassifyRows), 256, 0, s>>>(n, ub.p, fl.p, nk.p, L.cf.p, o.exti_first,
                                                        counts.p, lists.p);
       TPF_CHECK_LAUNCH();
       // single pass: rows staged at their candidate bound, then packed
@@ -1682,17 +1689,16 @@ void Hierarchy::finish_levels(hipStream_t st) {
     DiagOffs off;
     for (int k = 0; k < kMaxDiag; ++k) off.off[k] = k < K ? stencil[k] : 0;
     dia0.v.ensure(size_t(K) * n, st);
-    Buf<int64_t> placed(1, st);
-    fill(placed.p, int64_t(0), 1, st);
-    auto* placed_u = reinterpret_cast<unsigned long long*>(placed.p);
+    Buf<int> missed(1, st);
+    fill_int(missed.p, 0, 1, st);
     if (K <= 8)  // lanes per row: about one entry each
       k_csr_to_dia<8><<<grid_for(n, kDiaRows), 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, L.A.v.p, K, off,
-                                                             dia0.v.p, placed_u);
+                                                             dia0.v.p, missed.p);
     else
       k_csr_to_dia<32><<<grid_for(n, kDiaRows), 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, L.A.v.p, K,
-                                                              off, dia0.v.p, placed_u);
+                                                              off, dia0.v.p, missed.p);
     TPF_CHECK_LAUNCH();
-    dia0.ok = read_scalar(placed.p, st) == L.A.nnz;
+    dia0.ok = read_scalar(missed.p, st) == 0;
     if (dia0.ok && o.fp32) {
       dia0.v32.ensure(size_t(K) * n, st);
       cast<double, float>(dia0.v32.p, dia0.v.p, int64_t(K) * n, st);

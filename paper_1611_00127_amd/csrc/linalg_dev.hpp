@@ -99,52 +99,60 @@ __device__ inline T row_dot(int row, int lane, const int* __restrict__ rp,
   return sum;
 }
 
-// Appends `item` to list number `cls` (cls < 0: nothing) with one atomic per
-// list per wavefront; lists are laid out as nlists rows of `stride` entries.
-// The order inside a list is not specified.
-__device__ inline void wave_append(int cls, int nlists, int item, int stride, int* counts,
-                                   int* lists) {
-  int lane = threadIdx.x & (kWave - 1);
-  for (int c = 0; c < nlists; ++c) {
-    unsigned long long b = __ballot(cls == c);
-    if (!b) continue;
-    int leader = __ffsll(b) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&counts[c], int(__popcll(b)));
-    base = __shfl(base, leader, kWave);
-    if (cls == c) lists[int64_t(c) * stride + base + __popcll(b & ((1ull << lane) - 1ull))] = item;
-  }
-}
-
-// Appends `item` to list number `cls` (cls < 0: nothing) with one atomic per
-// list per work-group of BLOCK threads; every thread of the block must call
-// it.  Lists are nlists rows of `stride` entries; order inside a list is not
-// specified.
-template <int NL, int BLOCK>
-__device__ inline void block_append(int cls, int item, int stride, int* counts, int* lists) {
+// Sorts rows into lists by class: a work-group of BLOCK threads takes R*BLOCK
+// consecutive rows (row base + r * BLOCK + threadIdx.x at step r), class_of(i)
+// gives row i's list (< 0: none), and each list receives one atomic per
+// work-group.  Same-address atomics serialise, so fewer, larger work-groups
+// append faster than one per BLOCK rows.  Launch with
+// ceil(n / (R * BLOCK)) work-groups; order inside a list is not specified.
+constexpr int kClassifyRows = 8;  // R of the row classifiers
+template <int NL, int BLOCK, int R, class ClassOf>
+__device__ inline void block_append_rows(int n, ClassOf class_of, int stride, int* counts,
+                                         int* lists) {
   __shared__ int wcnt[BLOCK / kWave][NL];
   __shared__ int base[NL];
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  int myoff = 0;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  const int64_t i0 = int64_t(blockIdx.x) * (BLOCK * R) + threadIdx.x;
+  int cls[R], off[R], run[NL];
 #pragma unroll
-  for (int c = 0; c < NL; ++c) {
-    unsigned long long b = __ballot(cls == c);
-    if (cls == c) myoff = __popcll(b & ((1ull << lane) - 1ull));
-    if (lane == 0) wcnt[w][c] = __popcll(b);
+  for (int c = 0; c < NL; ++c) run[c] = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t i = i0 + int64_t(r) * BLOCK;
+    cls[r] = i < n ? class_of(int(i)) : -1;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    off[r] = 0;
+#pragma unroll
+    for (int c = 0; c < NL; ++c) {
+      const unsigned long long b = __ballot(cls[r] == c);
+      if (cls[r] == c) off[r] = run[c] + __popcll(b & below);
+      run[c] += __popcll(b);
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int c = 0; c < NL; ++c) wcnt[w][c] = run[c];
   }
   __syncthreads();
   if (threadIdx.x < NL) {
     const int c = threadIdx.x;
     int tot = 0;
     for (int ww = 0; ww < BLOCK / kWave; ++ww) {
-      int t = wcnt[ww][c];
+      const int t = wcnt[ww][c];
       wcnt[ww][c] = tot;
       tot += t;
     }
     base[c] = tot ? atomicAdd(&counts[c], tot) : 0;
   }
   __syncthreads();
-  if (cls >= 0) lists[int64_t(cls) * stride + base[cls] + wcnt[w][cls] + myoff] = item;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (cls[r] >= 0)
+      lists[int64_t(cls[r]) * stride + base[cls[r]] + wcnt[w][cls[r]] + off[r]] =
+          int(i0 + int64_t(r) * BLOCK);
 }
 
 // Sum / max over a group of LPR consecutive lanes (xor butterfly: every lane

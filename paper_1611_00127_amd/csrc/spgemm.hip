@@ -128,16 +128,17 @@ struct Caps {
 __global__ void k_spgemm_classify(int nrows, const int* __restrict__ ub,
                                   const int* __restrict__ arp, Caps caps, int first,
                                   int* __restrict__ counts, int* __restrict__ lists) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int c = -1;
-  if (i < nrows) {
-    int u = ub[i], la = arp[i + 1] - arp[i];
-    c = kClasses - 1;
+  block_append_rows<kClasses, 256, kClassifyRows>(
+      nrows,
+      [&](int i) {
+        const int u = ub[i], la = arp[i + 1] - arp[i];
+        int c = kClasses - 1;
 #pragma unroll
-    for (int k = kClasses - 2; k >= 0; --k)
-      if (k >= first && u <= caps.c[k] && la <= caps.la[k]) c = k;
-  }
-  block_append<kClasses, 256>(c, i, nrows, counts, lists);
+        for (int k = kClasses - 2; k >= 0; --k)
+          if (k >= first && u <= caps.c[k] && la <= caps.la[k]) c = k;
+        return c;
+      },
+      nrows, counts, lists);
 }
 
 __device__ inline int bsearch_col(const int* __restrict__ c, int lo, int hi, int key) {
@@ -818,13 +819,11 @@ __device__ inline void sort_row(int a, int len, int* __restrict__ ci, double* __
 // rows per work-group; each lane takes one entry and finds its rank (the
 // columns of a row are distinct) from the group's keys by shuffles, then
 // writes it in place (all reads precede the writes in the wavefront).
-// Longer rows are appended to `mid` for k_sort_mid_rows.
+// Longer rows are left to k_sort_mid_rows.
 constexpr int kShortRow = 16;
 __global__ void __launch_bounds__(256) k_sort_short_rows(int nrows, const int* __restrict__ rp,
                                                          int* __restrict__ ci,
-                                                         double* __restrict__ v,
-                                                         int* __restrict__ nmid,
-                                                         int* __restrict__ mid) {
+                                                         double* __restrict__ v) {
   const int g = threadIdx.x / kShortRow, j = threadIdx.x % kShortRow;
   const int i = blockIdx.x * (256 / kShortRow) + g;
   int a = 0, len = 0;
@@ -833,7 +832,6 @@ __global__ void __launch_bounds__(256) k_sort_short_rows(int nrows, const int* _
     len = rp[i + 1] - a;
   }
   const bool mine = len > 1 && len <= kShortRow;
-  block_append<1, 256>(len > kShortRow && j == 0 ? 0 : -1, i, nrows, nmid, mid);
   int key = INT_MAX;
   double val = 0.0;
   if (mine && j < len) {
@@ -850,28 +848,33 @@ __global__ void __launch_bounds__(256) k_sort_short_rows(int nrows, const int* _
   }
 }
 
-// The queued rows of more than kShortRow entries, one wavefront per row,
-// the work-groups striding over the queue (whose length they read); rows
-// longer than kSortCap are queued again for k_sort_long_rows.
+// Rows of more than kShortRow entries, one wavefront per row: each
+// work-group (one wavefront) strides over chunks of 64 rows, finds the long
+// ones of a chunk by a ballot and sorts them in turn (a queue filled by the
+// short-row kernel would take one same-address atomic per work-group there).
+// Rows longer than kSortCap are queued for k_sort_long_rows.
 constexpr int kSortCap = 1024;
-__global__ void __launch_bounds__(64) k_sort_mid_rows(const int* __restrict__ nmid,
-                                                      const int* __restrict__ mid,
-                                                      const int* __restrict__ rp,
+__global__ void __launch_bounds__(64) k_sort_mid_rows(int nrows, const int* __restrict__ rp,
                                                       int* __restrict__ ci, double* __restrict__ v,
                                                       int* __restrict__ nlong,
                                                       int* __restrict__ long_rows) {
   __shared__ int keys[kSortCap];
   __shared__ double vals[kSortCap];
-  const int cnt = *nmid;
-  for (int q = blockIdx.x; q < cnt; q += gridDim.x) {
-    const int i = mid[q];
-    const int a = rp[i], len = rp[i + 1] - a;
-    if (len > kSortCap) {
-      if (threadIdx.x == 0) long_rows[atomicAdd(nlong, 1)] = i;
-    } else {
-      sort_row<64, kSortCap>(a, len, ci, v, keys, vals);
+  for (int base = blockIdx.x * 64; base < nrows; base += gridDim.x * 64) {
+    const int r = base + int(threadIdx.x);
+    const int rlen = r < nrows ? rp[r + 1] - rp[r] : 0;
+    unsigned long long b = __ballot(rlen > kShortRow);
+    while (b) {
+      const int i = base + __ffsll(b) - 1;
+      b &= b - 1;
+      const int a = rp[i], len = rp[i + 1] - a;
+      if (len > kSortCap) {
+        if (threadIdx.x == 0) long_rows[atomicAdd(nlong, 1)] = i;
+      } else {
+        sort_row<64, kSortCap>(a, len, ci, v, keys, vals);
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
@@ -978,7 +981,7 @@ void spgemm(const CsrRef<double>& A, const CsrRef<double>& B, Csr<double>& C, hi
     });
     TPF_CHECK_LAUNCH();
   }
-  k_spgemm_classify<<<grid_for(n, 256), 256, 0, s>>>(n, ub.p, A.rp, caps, first_class, counts.p,
+  k_spgemm_classify<<<grid_for(n, 256 * kClassifyRows), 256, 0, s>>>(n, ub.p, A.rp, caps, first_class, counts.p,
                                                       lists.p);
   TPF_CHECK_LAUNCH();
   // one pass: each row writes its sorted unique entries at its upper-bound
@@ -1079,15 +1082,14 @@ void transpose(const CsrRef<double>& A, Csr<double>& C, hipStream_t s) {
     TPF_CHECK_LAUNCH();
   }
   if (m > 0) {
-    Buf<int> counts(2, s), mid(m, s), long_rows(m, s);  // counts: mid, long
-    fill_int(counts.p, 0, 2, s);
-    k_sort_short_rows<<<grid_for(m, 256 / kShortRow), 256, 0, s>>>(m, C.rp.p, C.ci.p, C.v.p,
-                                                                  counts.p, mid.p);
+    Buf<int> nlong(1, s), long_rows(m, s);
+    fill_int(nlong.p, 0, 1, s);
+    k_sort_short_rows<<<grid_for(m, 256 / kShortRow), 256, 0, s>>>(m, C.rp.p, C.ci.p, C.v.p);
     TPF_CHECK_LAUNCH();
-    k_sort_mid_rows<<<2048, 64, 0, s>>>(counts.p, mid.p, C.rp.p, C.ci.p, C.v.p, counts.p + 1,
-                                        long_rows.p);
+    const unsigned mid_grid = grid_for(m, 64) < 2048u ? grid_for(m, 64) : 2048u;
+    k_sort_mid_rows<<<mid_grid, 64, 0, s>>>(m, C.rp.p, C.ci.p, C.v.p, nlong.p, long_rows.p);
     TPF_CHECK_LAUNCH();
-    k_sort_long_rows<<<64, 256, 0, s>>>(counts.p + 1, long_rows.p, C.rp.p, C.ci.p, C.v.p);
+    k_sort_long_rows<<<64, 256, 0, s>>>(nlong.p, long_rows.p, C.rp.p, C.ci.p, C.v.p);
     TPF_CHECK_LAUNCH();
   }
 }
