@@ -19,6 +19,7 @@
 //                       cursor each.
 // Every row is written once, at an upper-bound offset in a staging area, and
 // the rows are packed afterwards.
+#include <algorithm>
 #include <climits>
 #include <type_traits>
 
@@ -848,25 +849,31 @@ __global__ void __launch_bounds__(256) k_sort_short_rows(int nrows, const int* _
   }
 }
 
-// Rows of more than kShortRow entries, one wavefront per row: each
-// work-group (one wavefront) strides over chunks of 64 rows, finds the long
-// ones of a chunk by a ballot and sorts them in turn (a queue filled by the
-// short-row kernel would take one same-address atomic per work-group there).
-// Rows longer than kSortCap are queued for k_sort_long_rows.
+// Rows of more than kShortRow entries, one wavefront per row.  Rows come in
+// chunks of 64; a chunk's long rows are found by a ballot over their lengths
+// (a queue filled by the short-row kernel would take one same-address atomic
+// per work-group there) and dealt to `sub` work-groups in turn, so small
+// matrices with many long rows still spread over the chip.  Work-groups
+// stride over the (chunk, share) pairs.  Rows longer than kSortCap are
+// queued for k_sort_long_rows.
 constexpr int kSortCap = 1024;
-__global__ void __launch_bounds__(64) k_sort_mid_rows(int nrows, const int* __restrict__ rp,
+constexpr int kSortMidGroups = 4096;  // work-groups of k_sort_mid_rows at most
+__global__ void __launch_bounds__(64) k_sort_mid_rows(int nrows, int sub, const int* __restrict__ rp,
                                                       int* __restrict__ ci, double* __restrict__ v,
                                                       int* __restrict__ nlong,
                                                       int* __restrict__ long_rows) {
   __shared__ int keys[kSortCap];
   __shared__ double vals[kSortCap];
-  for (int base = blockIdx.x * 64; base < nrows; base += gridDim.x * 64) {
+  const int64_t total = int64_t((nrows + 63) / 64) * sub;
+  for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
+    const int base = int(g / sub) * 64, share = int(g % sub);
     const int r = base + int(threadIdx.x);
     const int rlen = r < nrows ? rp[r + 1] - rp[r] : 0;
     unsigned long long b = __ballot(rlen > kShortRow);
-    while (b) {
+    for (int k = 0; b; ++k) {
       const int i = base + __ffsll(b) - 1;
       b &= b - 1;
+      if (k % sub != share) continue;
       const int a = rp[i], len = rp[i + 1] - a;
       if (len > kSortCap) {
         if (threadIdx.x == 0) long_rows[atomicAdd(nlong, 1)] = i;
@@ -882,6 +889,7 @@ __global__ void __launch_bounds__(64) k_sort_mid_rows(int nrows, const int* __re
 // LDS up to kSortLongCap entries, else an insertion sort by one thread).  The
 // work-groups stride over the queue, whose length they read.
 constexpr int kSortLongCap = 4096;
+constexpr int kSortLongGroups = 512;  // two per CU (48 KiB of LDS each)
 __global__ void __launch_bounds__(256) k_sort_long_rows(const int* __restrict__ nlong,
                                                          const int* __restrict__ long_rows,
                                                          const int* __restrict__ rp,
@@ -1086,10 +1094,12 @@ void transpose(const CsrRef<double>& A, Csr<double>& C, hipStream_t s) {
     fill_int(nlong.p, 0, 1, s);
     k_sort_short_rows<<<grid_for(m, 256 / kShortRow), 256, 0, s>>>(m, C.rp.p, C.ci.p, C.v.p);
     TPF_CHECK_LAUNCH();
-    const unsigned mid_grid = grid_for(m, 64) < 2048u ? grid_for(m, 64) : 2048u;
-    k_sort_mid_rows<<<mid_grid, 64, 0, s>>>(m, C.rp.p, C.ci.p, C.v.p, nlong.p, long_rows.p);
+    const int64_t chunks = (int64_t(m) + 63) / 64;
+    const int sub = int(std::max<int64_t>(1, std::min<int64_t>(64, kSortMidGroups / chunks)));
+    const int mid_grid = int(std::min<int64_t>(chunks * sub, kSortMidGroups));
+    k_sort_mid_rows<<<mid_grid, 64, 0, s>>>(m, sub, C.rp.p, C.ci.p, C.v.p, nlong.p, long_rows.p);
     TPF_CHECK_LAUNCH();
-    k_sort_long_rows<<<64, 256, 0, s>>>(nlong.p, long_rows.p, C.rp.p, C.ci.p, C.v.p);
+    k_sort_long_rows<<<kSortLongGroups, 256, 0, s>>>(nlong.p, long_rows.p, C.rp.p, C.ci.p, C.v.p);
     TPF_CHECK_LAUNCH();
   }
 }
