@@ -1562,13 +1562,19 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
       if (hc[NC - 1] > 0) cur.alloc(L.A.nnz > 0 ? L.A.nnz : 1, s);
       auto list = [&](int c) { return lists.p + c * int64_t(n); };
       k_inject_c<<<grid_for(n, 256), 256, 0, s>>>(n, L.cf.p, cidx.p, toff.p, cnt.p, tci.p, tv.p);
+      // the widest flattened class, the wide kernel and the per-thread rows:
+      // few rows that each take long, on the side stream beside the others
+      int nshort = 0, nlong = 0;
+      for (int c = 0; c < NC; ++c) (c < kExtFlatN - 1 ? nshort : nlong) += hc[c];
+      SideFork fork(s, nshort > 0 && nlong > 0);
+      const hipStream_t ls = fork.side;
       auto flat = [&](auto kt, auto ct, auto ft, int c) {
         constexpr int K = decltype(kt)::value, C = decltype(ct)::value, F = decltype(ft)::value;
         static_assert(K <= kExtK && C <= kExtCapWide, "class table");
         if (hc[c] > 0)
-          k_exti_flat<K, C, F><<<hc[c], 64, 0, s>>>(list(c), L.A.rp.p, L.A.ci.p, L.A.v.p,
-                                                      L.mask.p, L.cf.p, cidx.p, toff.p, cnt.p,
-                                                      tci.p, tv.p);
+          k_exti_flat<K, C, F><<<hc[c], 64, 0, c < kExtFlatN - 1 ? s : ls>>>(
+              list(c), L.A.rp.p, L.A.ci.p, L.A.v.p, L.mask.p, L.cf.p, cidx.p, toff.p, cnt.p, tci.p,
+              tv.p);
       };
       using I16 = std::integral_constant<int, 16>;
       using I64 = std::integral_constant<int, 64>;
@@ -1577,22 +1583,24 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
       using I512 = std::integral_constant<int, 512>;
       using I1024 = std::integral_constant<int, 1024>;
       using I2048 = std::integral_constant<int, 2048>;
-      flat(I16{}, I64{}, I128{}, 0);  // the classes of kExtFlatClasses, in order
+      // the classes of kExtFlatClasses (long-row ones first, on the side stream)
+      if (hc[NC - 2] > 0)
+        k_exti_wide<kExtCapWide><<<hc[NC - 2], 64, 0, ls>>>(list(NC - 2), L.A.rp.p, L.A.ci.p,
+                                                            L.A.v.p, L.mask.p, L.cf.p, cidx.p,
+                                                            toff.p, cnt.p, tci.p, tv.p);
+      if (hc[NC - 1] > 0)
+        k_exti_fill<<<grid_for(hc[NC - 1], 128), 128, 0, ls>>>(hc[NC - 1], list(NC - 1), L.A.rp.p,
+                                                               L.A.ci.p, L.A.v.p, L.mask.p, L.cf.p,
+                                                               cidx.p, cur.p, toff.p, cnt.p, tci.p,
+                                                               tv.p);
+      flat(I64{}, I1024{}, I2048{}, 5);
+      flat(I16{}, I64{}, I128{}, 0);
       flat(I16{}, I64{}, I512{}, 1);
       flat(I16{}, I64{}, I1024{}, 2);
       flat(I16{}, I64{}, I2048{}, 3);
       flat(I64{}, I256{}, I512{}, 4);
-      flat(I64{}, I1024{}, I2048{}, 5);
-      if (hc[NC - 2] > 0)
-        k_exti_wide<kExtCapWide><<<hc[NC - 2], 64, 0, s>>>(list(NC - 2), L.A.rp.p, L.A.ci.p,
-                                                           L.A.v.p, L.mask.p, L.cf.p, cidx.p,
-                                                           toff.p, cnt.p, tci.p, tv.p);
-      if (hc[NC - 1] > 0)
-        k_exti_fill<<<grid_for(hc[NC - 1], 128), 128, 0, s>>>(hc[NC - 1], list(NC - 1), L.A.rp.p,
-                                                              L.A.ci.p, L.A.v.p, L.mask.p, L.cf.p,
-                                                              cidx.p, cur.p, toff.p, cnt.p, tci.p,
-                                                              tv.p);
       TPF_CHECK_LAUNCH();
+      fork.join();
       L.P.nnz = scan_exclusive(cnt.p, L.P.rp.p, n, s);
       L.P.ci.alloc(L.P.nnz > 0 ? L.P.nnz : 1, s);
       L.P.v.alloc(L.P.nnz > 0 ? L.P.nnz : 1, s);

@@ -157,7 +157,59 @@ void dfree(void* p, size_t bytes, hipStream_t s) {
   g_in_use -= bytes;
 }
 
+namespace {
+struct Side {
+  hipStream_t st = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+std::mutex g_side_mu;
+std::map<hipStream_t, Side>& sides() {
+  static auto* m = new std::map<hipStream_t, Side>();  // never destroyed (process teardown)
+  return *m;
+}
+Side& side_of(hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  Side& sd = sides()[s];
+  if (!sd.st) {
+    TPF_HIP(hipStreamCreateWithFlags(&sd.st, hipStreamNonBlocking));
+    TPF_HIP(hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming));
+    TPF_HIP(hipEventCreateWithFlags(&sd.join, hipEventDisableTiming));
+  }
+  return sd;
+}
+}  // namespace
+
+hipStream_t fork_side(hipStream_t s) {
+  Side& sd = side_of(s);
+  TPF_HIP(hipEventRecord(sd.fork, s));
+  TPF_HIP(hipStreamWaitEvent(sd.st, sd.fork, 0));
+  return sd.st;
+}
+
+void join_side(hipStream_t s) {
+  Side& sd = side_of(s);
+  TPF_HIP(hipEventRecord(sd.join, sd.st));
+  TPF_HIP(hipStreamWaitEvent(s, sd.join, 0));
+}
+
 void forget_stream(hipStream_t s) {
+  {
+    Side sd;
+    {
+      std::lock_guard<std::mutex> lk(g_side_mu);
+      auto it = sides().find(s);
+      if (it != sides().end()) {
+        sd = it->second;
+        sides().erase(it);
+      }
+    }
+    if (sd.st) {
+      (void)hipStreamSynchronize(sd.st);
+      (void)hipEventDestroy(sd.fork);
+      (void)hipEventDestroy(sd.join);
+      (void)hipStreamDestroy(sd.st);
+    }
+  }
   std::vector<void*> back;
   {
     BlockCache& c = cache();

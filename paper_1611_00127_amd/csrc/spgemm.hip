@@ -1005,17 +1005,25 @@ void spgemm(const CsrRef<double>& A, const CsrRef<double>& B, Csr<double>& C, hi
   Buf<int2> cur;
   if (hc[kClasses - 1] > 0) cur.alloc(A.nnz > 0 ? A.nnz : 1, s);
   auto list = [&](int c) { return lists.p + int64_t(c) * n; };
+  // The classes of long rows (work-groups of 256 threads and more, and the
+  // per-thread merge) have few rows that each take long, leaving most of
+  // the chip idle: they run on the side stream, beside the wavefront classes.
+  int nshort = 0, nlong = 0;
+  for (int c = 0; c < kClasses; ++c) (c < 5 ? nshort : nlong) += hc[c];
+  SideFork fork(s, nshort > 0 && nlong > 0);
+  const hipStream_t ls = fork.side;
   // 32-bit keys when the column count leaves room for the product index
   auto flat = [&](auto block_tag, auto cap_tag, auto la_tag, int c) {
     constexpr int BL = decltype(block_tag)::value, CP = decltype(cap_tag)::value;
     constexpr int LC = decltype(la_tag)::value;
     if (hc[c] == 0) return;
+    const hipStream_t st = c < 5 ? s : ls;
     if (int64_t(B.ncols) < (int64_t(1) << (32 - __builtin_ctz(CP))))
-      k_spgemm_flat<BL, CP, uint32_t, LC><<<hc[c], BL, 0, s>>>(
+      k_spgemm_flat<BL, CP, uint32_t, LC><<<hc[c], BL, 0, st>>>(
           list(c), ub.p, A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha, beta, cnt.p, toff.p,
           tci.p, tv.p);
     else
-      k_spgemm_flat<BL, CP, uint64_t, LC><<<hc[c], BL, 0, s>>>(
+      k_spgemm_flat<BL, CP, uint64_t, LC><<<hc[c], BL, 0, st>>>(
           list(c), ub.p, A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha, beta, cnt.p, toff.p,
           tci.p, tv.p);
   };
@@ -1042,22 +1050,24 @@ void spgemm(const CsrRef<double>& A, const CsrRef<double>& B, Csr<double>& C, hi
   };
   using G16 = std::integral_constant<int, 16>;
   using G32 = std::integral_constant<int, 32>;
+  // long-row classes first (side stream), then the wavefront classes
+  flat(W8{}, C8192{}, C2048{}, 6);
+  if (hc[7] > 0)
+    k_spgemm_sorted<256, 16384, true><<<hc[7], 256, 0, ls>>>(list(7), ub.p, A.rp, A.ci, A.v, B.rp,
+                                                             B.ci, B.v, drp, dci, dv, alpha, beta,
+                                                             cnt.p, toff.p, tci.p, tv.p);
+  if (hc[8] > 0)
+    k_spgemm_merge<true><<<grid_for(hc[8], 128), 128, 0, ls>>>(
+        hc[8], list(8), A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha, beta, cur.p, cnt.p,
+        toff.p, tci.p, tv.p);
+  flat(W4{}, C2048{}, C2048{}, 5);
   group(G16{}, std::integral_constant<int, 4>{}, 0);
   group(G16{}, std::integral_constant<int, 8>{}, 1);
   group(G32{}, std::integral_constant<int, 8>{}, 2);
   flat(W1{}, C512{}, C512{}, 3);
   flat(W1{}, C1024{}, C1024{}, 4);
-  flat(W4{}, C2048{}, C2048{}, 5);
-  flat(W8{}, C8192{}, C2048{}, 6);
-  if (hc[7] > 0)
-    k_spgemm_sorted<256, 16384, true><<<hc[7], 256, 0, s>>>(list(7), ub.p, A.rp, A.ci, A.v, B.rp,
-                                                            B.ci, B.v, drp, dci, dv, alpha, beta,
-                                                            cnt.p, toff.p, tci.p, tv.p);
-  if (hc[8] > 0)
-    k_spgemm_merge<true><<<grid_for(hc[8], 128), 128, 0, s>>>(
-        hc[8], list(8), A.rp, A.ci, A.v, B.rp, B.ci, B.v, drp, dci, dv, alpha, beta, cur.p, cnt.p,
-        toff.p, tci.p, tv.p);
   TPF_CHECK_LAUNCH();
+  fork.join();
   C.nnz = scan_exclusive(cnt.p, C.rp.p, n, s);
   C.ci.alloc(C.nnz > 0 ? C.nnz : 1, s);
   C.v.alloc(C.nnz > 0 ? C.nnz : 1, s);

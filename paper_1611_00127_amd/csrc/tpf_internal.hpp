@@ -65,6 +65,36 @@ void dfree(void* p, size_t bytes, hipStream_t s);
 // Returns the blocks cached for stream s to the upstream allocator; call
 // after s is synchronised and before it is destroyed.
 void forget_stream(hipStream_t s);
+// Side stream of stream s, for kernels that may overlap the rest of s's
+// work (independent row classes of one product).  fork_side(s) orders the
+// side stream after everything queued on s so far and returns it;
+// join_side(s) orders s after everything queued on the side stream.  Memory
+// the side kernels use must be allocated on s before the fork and freed on
+// s after the join.  Created on first use (default priority), destroyed by
+// forget_stream(s).
+hipStream_t fork_side(hipStream_t s);
+void join_side(hipStream_t s);
+// Forks the side stream of s when `use` holds (else `side` is s itself);
+// join() orders s after the side work, and so does the destructor if join()
+// was not reached (an error between the two).
+struct SideFork {
+  hipStream_t s, side;
+  SideFork(hipStream_t s_, bool use) : s(s_), side(use ? fork_side(s_) : s_) {}
+  void join() {
+    if (side != s) join_side(s);
+    side = s;
+  }
+  ~SideFork() {
+    if (side != s) {
+      try {
+        join_side(s);
+      } catch (...) {
+      }
+    }
+  }
+  SideFork(const SideFork&) = delete;
+  SideFork& operator=(const SideFork&) = delete;
+};
 // Returns every cached block to the upstream allocator (device idle).
 void release_cache();
 
