@@ -1503,18 +1503,28 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
       TPF_CHECK_LAUNCH();
       TPF_HIP(hipMemcpyAsync(rounds_pinned, und.p, sizeof(int), hipMemcpyDeviceToHost, s));
     } else {
-      while (true) {
-        fill_int(und.p, 0, 1, s);
+      // Rounds run back to back: round r + 1 is queued before the host reads
+      // round r's flag, so the GPU does not wait for the host between rounds.
+      // Once a round leaves no point undecided, the round queued after it
+      // changes nothing.
+      Buf<int> flags(2, s);
+      int* hflag = host_counts_slot();
+      auto launch_round = [&](int k) {
+        fill_int(flags.p + k, 0, 1, s);
         k_pmis_select<<<grid_for(n, 256), 256, 0, s>>>(n, L.S.rp.p, L.S.ci.p, ST.rp.p, ST.ci.p,
                                                        w.p, L.cf.p, newc.p);
-        TPF_CHECK_LAUNCH();
         k_pmis_update<<<grid_for(n, 256), 256, 0, s>>>(n, L.S.rp.p, L.S.ci.p, newc.p, L.cf.p,
-                                                       und.p);
+                                                       flags.p + k);
         TPF_CHECK_LAUNCH();
-        ++rounds;
-        int left = read_scalar(und.p, s);
-        if (left == 0) break;
+        TPF_HIP(hipMemcpyAsync(hflag + k, flags.p + k, sizeof(int), hipMemcpyDeviceToHost, s));
+        TPF_HIP(hipEventRecord(thread_event(k), s));
+      };
+      launch_round(0);
+      for (rounds = 1;; ++rounds) {
         TPF_REQUIRE(rounds <= n + 1, TPF_ERR_INVALID_ARG, "PMIS did not terminate");
+        launch_round(rounds % 2);
+        TPF_HIP(hipEventSynchronize(thread_event((rounds - 1) % 2)));
+        if (hflag[(rounds - 1) % 2] == 0) break;
       }
     }
     // coarse numbering

@@ -248,6 +248,16 @@ HostScratch& host_scratch() {
   return *hs;
 }
 
+hipEvent_t thread_event(int k) {
+  struct Events {
+    hipEvent_t e[4] = {};
+  };
+  static thread_local Events* ev = new Events();  // kept until the process ends
+  TPF_REQUIRE(k >= 0 && k < 4, TPF_ERR_INVALID_ARG, "thread_event: index %d", k);
+  if (!ev->e[k]) TPF_HIP(hipEventCreateWithFlags(&ev->e[k], hipEventDisableTiming));
+  return ev->e[k];
+}
+
 bool timing_enabled() { return g_timing; }
 
 namespace {

@@ -153,6 +153,10 @@ inline int* host_counts_slot() {
   return reinterpret_cast<int*>(host_scratch().get<char>(4096) + 1024);
 }
 
+// Event k (k < 4) of the calling thread, without timing (created on first
+// use, kept until the process ends).
+hipEvent_t thread_event(int k);
+
 template <class T>
 T read_scalar(const T* dptr, hipStream_t s) {
   T* h = host_scratch().get<T>(1);
