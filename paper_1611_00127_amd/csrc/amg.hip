@@ -260,55 +260,87 @@ __global__ void k_is_c(int n, const int8_t* __restrict__ cf, int* __restrict__ o
   if (i < n) out[i] = cf[i] == kC;
 }
 
-__global__ void k_interp_count(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                               const uint8_t* __restrict__ mask, const int8_t* __restrict__ cf,
-                               int* __restrict__ cnt) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (cf[i] == kC) {
-    cnt[i] = 1;
-    return;
+// Direct interpolation, LPR lanes per row (the rows of coarse Galerkin
+// operators run to hundreds of entries): number of entries of each P row.
+template <int LPR>
+__global__ void __launch_bounds__(256) k_interp_count(int n, const int* __restrict__ rp,
+                                                      const int* __restrict__ ci,
+                                                      const uint8_t* __restrict__ mask,
+                                                      const int8_t* __restrict__ cf,
+                                                      int* __restrict__ cnt) {
+  int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int i = int(gid / LPR), lane = int(gid % LPR);
+  const bool frow = i < n && cf[i] != kC;
+  int a0 = 0, a1 = 0;
+  if (frow) {
+    a0 = rp[i];
+    a1 = rp[i + 1];
   }
   int c = 0;
-  for (int e = rp[i]; e < rp[i + 1]; ++e) c += mask[e] && cf[ci[e]] == kC;
-  cnt[i] = c;
+  for (int e = a0 + lane; e < a1; e += LPR) c += mask[e] && cf[ci[e]] == kC;
+  c = group_sum<LPR>(c);
+  if (i < n && lane == 0) cnt[i] = frow ? c : 1;
 }
 
-__global__ void k_interp_fill(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                              const double* __restrict__ v, const uint8_t* __restrict__ mask,
-                              const int8_t* __restrict__ cf, const int* __restrict__ cidx,
-                              const int* __restrict__ prp, int* __restrict__ pci,
-                              double* __restrict__ pv) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int o = prp[i];
-  if (cf[i] == kC) {
+// Direct interpolation weights of each row, LPR lanes per row; the strong C
+// entries are written in row order (ballot over the group).
+template <int LPR>
+__global__ void __launch_bounds__(256) k_interp_fill(int n, const int* __restrict__ rp,
+                                                     const int* __restrict__ ci,
+                                                     const double* __restrict__ v,
+                                                     const uint8_t* __restrict__ mask,
+                                                     const int8_t* __restrict__ cf,
+                                                     const int* __restrict__ cidx,
+                                                     const int* __restrict__ prp,
+                                                     int* __restrict__ pci,
+                                                     double* __restrict__ pv) {
+  int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int i = int(gid / LPR), lane = int(gid % LPR);
+  const bool live = i < n;
+  const bool crow = live && cf[i] == kC;
+  int a0 = 0, a1 = 0, o = 0;
+  if (live) {
+    o = prp[i];
+    if (!crow) {
+      a0 = rp[i];
+      a1 = rp[i + 1];
+    }
+  }
+  if (crow && lane == 0) {
     pci[o] = cidx[i];
     pv[o] = 1.0;
-    return;
   }
-  int a0 = rp[i], a1 = rp[i + 1];
-  double aii = row_diag(i, a0, a1, ci, v);
-  double s = aii < 0.0 ? -1.0 : 1.0;
+  double aii = 0.0;
+  for (int e = a0 + lane; e < a1; e += LPR)
+    if (ci[e] == i) aii += v[e];
+  aii = group_sum<LPR>(aii);
+  const double s = aii < 0.0 ? -1.0 : 1.0;
   double sn_opp = 0.0, sn_same = 0.0, sp_opp = 0.0;
-  for (int e = a0; e < a1; ++e) {
-    int j = ci[e];
+  for (int e = a0 + lane; e < a1; e += LPR) {
+    const int j = ci[e];
     if (j == i) continue;
-    double a = v[e];
-    if (s * a < 0.0) sn_opp += a;
-    else if (s * a > 0.0) sn_same += a;
+    const double a = v[e];
+    if (s * a < 0.0)
+      sn_opp += a;
+    else if (s * a > 0.0)
+      sn_same += a;
+    if (mask[e] && cf[j] == kC) sp_opp += a;
   }
-  for (int e = a0; e < a1; ++e)
-    if (mask[e] && cf[ci[e]] == kC) sp_opp += v[e];
-  double atil = aii + sn_same;
-  for (int e = a0; e < a1; ++e) {
-    int j = ci[e];
-    if (mask[e] && cf[j] == kC) {
-      double alpha = sn_opp / sp_opp;
-      pci[o] = cidx[j];
-      pv[o] = -alpha * v[e] / atil;
-      ++o;
+  sn_opp = group_sum<LPR>(sn_opp);
+  sn_same = group_sum<LPR>(sn_same);
+  sp_opp = group_sum<LPR>(sp_opp);
+  const double atil = aii + sn_same;
+  const double alpha = sn_opp / sp_opp;
+  for (int base = a0; base < a1; base += LPR) {
+    const int e = base + lane;
+    const bool f = e < a1 && mask[e] && cf[ci[e]] == kC;
+    const unsigned long long g = group_ballot<LPR>(f);
+    if (f) {
+      const int q = o + __popcll(g & ((1ull << lane) - 1ull));
+      pci[q] = cidx[ci[e]];
+      pv[q] = -alpha * v[e] / atil;
     }
+    o += __popcll(g);
   }
 }
 
@@ -1616,14 +1648,18 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
       L.P.v.alloc(L.P.nnz > 0 ? L.P.nnz : 1, s);
       pack_rows(n, toff.p, L.P.rp.p, L.P.nnz, tci.p, tv.p, L.P.ci.p, L.P.v.p, s);
     } else {
-      k_interp_count<<<grid_for(n, 256), 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.mask.p, L.cf.p,
-                                                      cnt.p);
+      DISPATCH_LPR(lpr, LL, {  // lanes per row of A, as for the strength kernels
+        k_interp_count<LL><<<rblocks, 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.mask.p, L.cf.p,
+                                                   cnt.p);
+      });
       TPF_CHECK_LAUNCH();
       L.P.nnz = scan_exclusive(cnt.p, L.P.rp.p, n, s);
       L.P.ci.alloc(L.P.nnz, s);
       L.P.v.alloc(L.P.nnz, s);
-      k_interp_fill<<<grid_for(n, 256), 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.A.v.p, L.mask.p,
-                                                     L.cf.p, cidx.p, L.P.rp.p, L.P.ci.p, L.P.v.p);
+      DISPATCH_LPR(lpr, LL, {
+        k_interp_fill<LL><<<rblocks, 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.A.v.p, L.mask.p,
+                                                  L.cf.p, cidx.p, L.P.rp.p, L.P.ci.p, L.P.v.p);
+      });
       TPF_CHECK_LAUNCH();
     }
     transpose(ref(L.P), L.R, s);
