@@ -30,7 +30,8 @@ int krylov_grid(int64_t n) {
   return int(g);
 }
 
-// block-wise reduction of KMAX running sums into part[block][k]
+// block-wise reduction of KMAX running sums into part[k][block] (one row of
+// gridDim.x partial sums per basis vector, read contiguously by the reduction)
 template <int KMAX>
 __device__ inline void reduce_store(double* acc, int nk, double* part) {
   __shared__ double sh[kKBlock / 64][KMAX];
@@ -46,7 +47,7 @@ __device__ inline void reduce_store(double* acc, int nk, double* part) {
   for (int k = threadIdx.x; k < nk; k += kKBlock) {
     double t = 0.0;
     for (int w = 0; w < kKBlock / 64; ++w) t += sh[w][k];
-    part[int64_t(blockIdx.x) * KMAX + k] = t;
+    part[int64_t(k) * gridDim.x + blockIdx.x] = t;
   }
 }
 
@@ -126,7 +127,7 @@ __global__ void __launch_bounds__(kKBlock) k_cgs_axpy_dots(int64_t n, int nk,
   for (int k = threadIdx.x; k < nk; k += kKBlock) {
     double t = 0.0;
     for (int ww = 0; ww < kKBlock / 64; ++ww) t += sh[ww][k];
-    part[int64_t(blockIdx.x) * KMAX + k] = t;
+    part[int64_t(k) * gridDim.x + blockIdx.x] = t;
   }
 }
 
@@ -161,15 +162,21 @@ __global__ void __launch_bounds__(kKBlock) k_cgs_axpy_norm(int64_t n, int nk,
   reduce_store<1>(acc, 1, part);
 }
 
-// out[k] = sum_b part[b][k]: one wavefront per column k, lanes stride over
-// the blocks, fixed reduction tree (deterministic)
-__global__ void __launch_bounds__(64) k_reduce_parts(int nb, int kstride,
-                                                     const double* __restrict__ part,
-                                                     double* __restrict__ out) {
-  int k = blockIdx.x;
+// out[k] = sum of the nb partial sums of row k (one work-group per row,
+// fixed order)
+constexpr int kRedBlock = 256;
+__device__ inline double sum_parts(int nb, const double* __restrict__ row) {
+  __shared__ double sh[kRedBlock / 64];
   double t = 0.0;
-  for (int b = threadIdx.x; b < nb; b += 64) t += part[int64_t(b) * kstride + k];
-  t = wave_sum(t);
+  for (int b = threadIdx.x; b < nb; b += kRedBlock) t += row[b];
+  return block_sum<kRedBlock>(t, sh);
+}
+
+__global__ void __launch_bounds__(kRedBlock) k_reduce_parts(int nb,
+                                                            const double* __restrict__ part,
+                                                            double* __restrict__ out) {
+  const int k = blockIdx.x;
+  const double t = sum_parts(nb, part + int64_t(k) * nb);
   if (threadIdx.x == 0) out[k] = t;
 }
 
@@ -182,15 +189,15 @@ struct GState {
 
 // Givens update of column j (single thread): h = h1 + h2, apply previous
 // rotations, form the new one, update g.
-__global__ void __launch_bounds__(64) k_givens(int j, int m, const double* __restrict__ h1,
-                                               const double* __restrict__ h2,
-                                               const double* __restrict__ nrm2_part, int nparts,
-                                               double* __restrict__ H, double* __restrict__ cs,
-                                               double* __restrict__ sn, double* __restrict__ g,
-                                               GState* __restrict__ st) {
-  double ss = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += 64) ss += nrm2_part[b];
-  ss = wave_sum(ss);
+__global__ void __launch_bounds__(kRedBlock) k_givens(int j, int m, const double* __restrict__ h1,
+                                                      const double* __restrict__ h2,
+                                                      const double* __restrict__ nrm2_part,
+                                                      int nparts, double* __restrict__ H,
+                                                      double* __restrict__ cs,
+                                                      double* __restrict__ sn,
+                                                      double* __restrict__ g,
+                                                      GState* __restrict__ st) {
+  const double ss = sum_parts(nparts, nrm2_part);
   if (threadIdx.x != 0) return;
   double hn = sqrt(ss);
   double* col = H + int64_t(j) * (m + 1);
@@ -366,18 +373,18 @@ void Fgmres::launch_step() {
     DISPATCH_K(nk, KM, {
       k_cgs_dots<KM><<<G, kKBlock, 0, s>>>(n, nk, V.p, wv, part.p);
       TPF_CHECK_LAUNCH();
-      k_reduce_parts<<<nk, 64, 0, s>>>(G, KM, part.p, h1.p);
+      k_reduce_parts<<<nk, kRedBlock, 0, s>>>(G, part.p, h1.p);
       TPF_CHECK_LAUNCH();
       k_cgs_axpy_dots<KM><<<G, kKBlock, 0, s>>>(n, nk, V.p, h1.p, wv, part.p);
       TPF_CHECK_LAUNCH();
-      k_reduce_parts<<<nk, 64, 0, s>>>(G, KM, part.p, h2.p);
+      k_reduce_parts<<<nk, kRedBlock, 0, s>>>(G, part.p, h2.p);
       TPF_CHECK_LAUNCH();
       k_cgs_axpy_norm<KM><<<G, kKBlock, 0, s>>>(n, nk, V.p, h2.p, wv, part.p);
       TPF_CHECK_LAUNCH();
     });
   }
   GState* gs = reinterpret_cast<GState*>(st_dev.p);
-  k_givens<<<1, 64, 0, s>>>(j, m, h1.p, h2.p, part.p, G, H.p, cs.p, sn.p, g.p, gs);
+  k_givens<<<1, kRedBlock, 0, s>>>(j, m, h1.p, h2.p, part.p, G, H.p, cs.p, sn.p, g.p, gs);
   TPF_CHECK_LAUNCH();
   k_scale<<<vec_grid(n), 256, 0, s>>>(n, wv, gs, wv);
   TPF_CHECK_LAUNCH();
