@@ -13,6 +13,7 @@
 // factorisation and both triangular solves proceed by anti-diagonal
 // wavefronts ix+iy+iz = const, whose cells are mutually independent.
 #include <algorithm>
+#include <climits>
 #include <cstdlib>
 #include <exception>
 #include <thread>
@@ -90,6 +91,138 @@ __global__ void k_scale_cols(int n, const int* __restrict__ rp, const int* __res
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   for (int e = rp[i]; e < rp[i + 1]; ++e) out[e] = v[e] * dinv[ci[e]];
+}
+
+// ---------------------------------------------------------------- S~ on the grid
+// On the 3D grid every block row couples a cell to its in-grid face
+// neighbours (offsets kN1, ascending in the cell numbering), so
+// S~ = A_pp - A_ps diag(A_ss)^{-1} A_sp couples it to the in-grid cells
+// within two face steps (kN2, ascending when every direction has at least
+// five cells).  Entry (i, i + t) sums Y_{i,a} (A_sp)_{i+a,b} over the pairs
+// a + b = t in ascending a, with Y = A_ps diag(A_ss)^{-1}: the terms and
+// the pattern of the general sparse product, formed in one pass without
+// sorting.
+struct Off3 {
+  int x, y, z;
+};
+__device__ constexpr Off3 kN1[7] = {{0, 0, -1}, {0, -1, 0}, {-1, 0, 0}, {0, 0, 0},
+                                    {1, 0, 0},  {0, 1, 0},  {0, 0, 1}};
+__device__ constexpr Off3 kN2[25] = {
+    {0, 0, -2},  {0, -1, -1}, {-1, 0, -1}, {0, 0, -1}, {1, 0, -1}, {0, 1, -1}, {0, -2, 0},
+    {-1, -1, 0}, {0, -1, 0},  {1, -1, 0},  {-2, 0, 0}, {-1, 0, 0}, {0, 0, 0},  {1, 0, 0},
+    {2, 0, 0},   {-1, 1, 0},  {0, 1, 0},   {1, 1, 0},  {0, 2, 0},  {0, -1, 1}, {-1, 0, 1},
+    {0, 0, 1},   {1, 0, 1},   {0, 1, 1},   {0, 0, 2}};
+
+__device__ inline bool in_grid(int x, int y, int z, int nx, int ny, int nz) {
+  return x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz;
+}
+
+__global__ void __launch_bounds__(256) k_schur_count(int nx, int ny, int nz,
+                                                     int* __restrict__ cnt) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t sxy = int64_t(nx) * ny;
+  if (i >= sxy * nz) return;
+  const int x = int(i % nx), y = int((i / nx) % ny), z = int(i / sxy);
+  int c = 0;
+#pragma unroll
+  for (int t = 0; t < 25; ++t) c += in_grid(x + kN2[t].x, y + kN2[t].y, z + kN2[t].z, nx, ny, nz);
+  cnt[i] = c;
+}
+
+// Rows of S~ at srp (from k_schur_count); rp: the block pattern's rows.  One
+// wavefront per work-group takes kSchurRows consecutive rows, stages their
+// entries in LDS and writes the (contiguous) range coalesced.
+constexpr int kSchurRows = 64;
+__global__ void __launch_bounds__(kSchurRows) k_schur_fill(int nx, int ny, int nz,
+                                                    const int* __restrict__ rp,
+                                                    const double* __restrict__ app,
+                                                    const double* __restrict__ aps,
+                                                    const double* __restrict__ asp,
+                                                    const double* __restrict__ dinv,
+                                                    const int* __restrict__ srp,
+                                                    int* __restrict__ sci,
+                                                    double* __restrict__ sv) {
+  __shared__ int lc[kSchurRows * 25];
+  __shared__ double lv[kSchurRows * 25];
+  const int64_t sxy = int64_t(nx) * ny, n = sxy * nz;
+  const int64_t i0 = int64_t(blockIdx.x) * kSchurRows;
+  const int64_t i1 = i0 + kSchurRows < n ? i0 + kSchurRows : n;
+  const int64_t i = i0 + threadIdx.x < i1 ? i0 + threadIdx.x : i1 - 1;  // clamped: valid row
+  const int base = srp[i0];
+  const int x = int(i % nx), y = int((i / nx) % ny), z = int(i / sxy);
+  auto lin = [&](int dx, int dy, int dz) { return int64_t(dx) + int64_t(nx) * dy + sxy * dz; };
+  // Every load below is issued unconditionally at a position clamped into
+  // its row (which holds at least the diagonal), so all are in flight
+  // before the first wait; entries of out-of-grid neighbours are zeroed.
+  bool in1[7];
+  int before[7], cnt = 0;
+#pragma unroll
+  for (int a = 0; a < 7; ++a) {
+    in1[a] = in_grid(x + kN1[a].x, y + kN1[a].y, z + kN1[a].z, nx, ny, nz);
+    before[a] = cnt;
+    cnt += in1[a];
+  }
+  int64_t nbr[7];
+  int rs[7];
+  const int r0 = rp[i];
+#pragma unroll
+  for (int a = 0; a < 7; ++a) {
+    nbr[a] = in1[a] ? i + lin(kN1[a].x, kN1[a].y, kN1[a].z) : i;
+    rs[a] = rp[nbr[a]];
+  }
+  // row i of Y and A_pp by neighbour
+  double yv[7], pv[7];
+#pragma unroll
+  for (int a = 0; a < 7; ++a) {
+    const int e = r0 + before[a] - (in1[a] ? 0 : (before[a] == cnt ? 1 : 0));
+    const double ya = aps[e] * dinv[nbr[a]];
+    const double pa = app[e];
+    yv[a] = in1[a] ? ya : 0.0;
+    pv[a] = in1[a] ? pa : 0.0;
+  }
+  // rows of A_sp of the neighbours, by neighbour of the neighbour
+  double m[7][7];
+#pragma unroll
+  for (int a = 0; a < 7; ++a) {
+    const int xa = x + kN1[a].x, ya = y + kN1[a].y, za = z + kN1[a].z;
+    int c = 0;
+#pragma unroll
+    for (int b = 0; b < 7; ++b) {
+      const bool in = in1[a] && in_grid(xa + kN1[b].x, ya + kN1[b].y, za + kN1[b].z, nx, ny, nz);
+      // position of entry b in row nbr[a], or of the row's first entry
+      const double v = asp[rs[a] + (in ? c : 0)];
+      m[a][b] = in ? v : 0.0;
+      c += in;
+    }
+  }
+  const bool mine = i0 + threadIdx.x < i1;
+  int o = srp[i] - base;
+#pragma unroll
+  for (int t = 0; t < 25; ++t) {
+    const Off3 T = kN2[t];
+    if (!in_grid(x + T.x, y + T.y, z + T.z, nx, ny, nz)) continue;
+    double acc = 0.0, d = 0.0;
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+#pragma unroll
+      for (int b = 0; b < 7; ++b)
+        if (kN1[a].x + kN1[b].x == T.x && kN1[a].y + kN1[b].y == T.y &&
+            kN1[a].z + kN1[b].z == T.z)
+          acc += yv[a] * m[a][b];
+      if (kN1[a].x == T.x && kN1[a].y == T.y && kN1[a].z == T.z) d = pv[a];
+    }
+    if (mine) {
+      lc[o] = int(i + lin(T.x, T.y, T.z));
+      lv[o] = d - acc;
+    }
+    ++o;
+  }
+  __syncthreads();
+  const int cnt_all = srp[i1] - base;
+  for (int q = threadIdx.x; q < cnt_all; q += kSchurRows) {
+    sci[base + q] = lc[q];
+    sv[base + q] = lv[q];
+  }
 }
 
 template <class T>
@@ -328,6 +461,48 @@ std::vector<int> stencil_offsets(const Phys& ph, int radius) {
     if (off[k] == off[k - 1]) return {};
   if (radius >= 2 && (ph.nx < 5 || (ph.ny > 1 && ph.ny < 5) || (ph.nz > 1 && ph.nz < 5))) return {};
   return off;
+}
+
+// In-grid cells at each offset (dx,dy,dz) with |dx|+|dy|+|dz| <= radius, summed.
+int64_t stencil_entries(const Phys& ph, int radius) {
+  int64_t t = 0;
+  for (int dz = -radius; dz <= radius; ++dz)
+    for (int dy = -radius; dy <= radius; ++dy)
+      for (int dx = -radius; dx <= radius; ++dx)
+        if (std::abs(dx) + std::abs(dy) + std::abs(dz) <= radius)
+          t += int64_t(std::max(ph.nx - std::abs(dx), 0)) * std::max(ph.ny - std::abs(dy), 0) *
+               std::max(ph.nz - std::abs(dz), 0);
+  return t;
+}
+
+// S~ by the grid kernels: a 3D grid of at least five cells per direction
+// whose block pattern is the face-neighbour stencil
+bool schur_on_grid_ok(const Phys& ph, int64_t nnzb) {
+  return ph.nx >= 5 && ph.ny >= 5 && ph.nz >= 5 && nnzb == stencil_entries(ph, 1) &&
+         stencil_entries(ph, 2) <= INT_MAX;
+}
+
+// S~ = A_pp - A_ps diag(A_ss)^{-1} A_sp on the grid; with pattern_given the
+// rows and columns of S are those of an earlier call and only the values
+// (and the same columns) are rewritten.
+void schur_on_grid(tpf_precond* M, const Phys& ph, Csr<double>& S, bool pattern_given,
+                   hipStream_t s) {
+  const int64_t N = ph.N;
+  if (!pattern_given) {
+    S.nrows = S.ncols = int(N);
+    S.nnz = stencil_entries(ph, 2);
+    S.rp.alloc(N + 1, s);
+    Buf<int> cnt(N, s);
+    k_schur_count<<<grid_for(N, 256), 256, 0, s>>>(ph.nx, ph.ny, ph.nz, cnt.p);
+    TPF_CHECK_LAUNCH();
+    scan_exclusive_async(cnt.p, S.rp.p, N, s);  // the counts add up to S.nnz
+    S.ci.alloc(S.nnz, s);
+    S.v.alloc(S.nnz, s);
+  }
+  k_schur_fill<<<grid_for(N, kSchurRows), kSchurRows, 0, s>>>(ph.nx, ph.ny, ph.nz, M->brp.p, M->app_v.p,
+                                                M->aps_v.p, M->asp_v.p, M->ass_dinv.p, S.rp.p,
+                                                S.ci.p, S.v.p);
+  TPF_CHECK_LAUNCH();
 }
 
 AmgOpts amg_opts(const tpf_precond_opts& o, bool pressure_like) {
@@ -710,13 +885,17 @@ int tpf_precond_setup(tpf_precond* M, const tpf_jacobian* J, int reuse, void* st
     } else {  // BF
       M->n_hier = 2;
       M->ass_dinv.ensure(N, s);
-      M->y_v.ensure(nnzb, s);
       k_diag_inv<<<grid_for(N, 256), 256, 0, s>>>(N, M->brp.p, M->bci.p, M->ass_v.p,
                                                   M->ass_dinv.p);
       TPF_CHECK_LAUNCH();
-      k_scale_cols<<<grid_for(N, 256), 256, 0, s>>>(N, M->brp.p, M->bci.p, M->aps_v.p,
-                                                    M->ass_dinv.p, M->y_v.p);
-      TPF_CHECK_LAUNCH();
+      const Phys& ph = J->prob->ph;
+      const bool on_grid = schur_on_grid_ok(ph, nnzb);
+      if (!on_grid) {  // Y = A_ps diag(A_ss)^{-1} for the general sparse product
+        M->y_v.ensure(nnzb, s);
+        k_scale_cols<<<grid_for(N, 256), 256, 0, s>>>(N, M->brp.p, M->bci.p, M->aps_v.p,
+                                                      M->ass_dinv.p, M->y_v.p);
+        TPF_CHECK_LAUNCH();
+      }
       CsrRef<double> Y{N, N, nnzb, M->brp.p, M->bci.p, M->y_v.p};
       CsrRef<double> Asp{N, N, nnzb, M->brp.p, M->bci.p, M->asp_v.p};
       CsrRef<double> App{N, N, nnzb, M->brp.p, M->bci.p, M->app_v.p};
@@ -738,14 +917,20 @@ int tpf_precond_setup(tpf_precond* M, const tpf_jacobian* J, int reuse, void* st
           [&](hipStream_t ms) {
             if (!re) {
               Csr<double> S;
-              spgemm(Y, Asp, S, ms, &App, -1.0, 1.0, false);
+              if (on_grid)
+                schur_on_grid(M, ph, S, false, ms);
+              else
+                spgemm(Y, Asp, S, ms, &App, -1.0, 1.0, false);
               auto H = std::make_unique<Hierarchy>();
               H->tag = "Schur";
               H->stencil = stencil_offsets(J->prob->ph, 2);
               H->build(std::move(S), ao_p, ms);
               M->H[1] = std::move(H);
             } else {
-              spgemm(Y, Asp, M->H[1]->A0(), ms, &App, -1.0, 1.0);  // same pattern, in full
+              if (on_grid)
+                schur_on_grid(M, ph, M->H[1]->A0(), true, ms);
+              else
+                spgemm(Y, Asp, M->H[1]->A0(), ms, &App, -1.0, 1.0);  // same pattern, in full
               M->H[1]->refresh(ms);
             }
           });
