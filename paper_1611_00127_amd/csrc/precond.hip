@@ -411,6 +411,143 @@ __global__ void __launch_bounds__(1024) k_bilu_sweep_wg(int nf, const int* __res
   }
 }
 
+// Sweeps on 2D grids of at most kFront2d rows (fronts of at most that many
+// cells): thread t takes the cell of row y = lo + t of each front; the
+// previous front's results come from LDS (slot y, two buffers by front
+// parity) instead of global memory.  A cell's row start follows from the
+// 5-point pattern in closed form, so its blocks are loaded with no
+// dependent load, two fronts ahead (fronts alternate between two register
+// sets), and stay in flight across the LDS-only barriers: a front costs a
+// barrier and one LDS exchange.  The work-group has as many threads as the
+// longest front (rounded to wavefronts).  Same terms in the same order as the cell
+// functions above.  FWD: forward sweep, else backward.
+constexpr int kFront2d = 1024;
+template <class T>
+struct Bilu2dCell {
+  T b0[4], b1[4], d[4], v[2];  // lower (FWD) / upper (BWD) blocks, D^{-1}, r (FWD) or w (BWD)
+  bool has0, has1, live;
+  int y;
+  int64_t i;
+};
+
+template <class T, bool FWD>
+__device__ inline void bilu_2d_load(int nx, int ny, int L, const T* __restrict__ jv,
+                                    const T* __restrict__ dinv, const double* __restrict__ r,
+                                    const T* __restrict__ w, Bilu2dCell<T>& c) {
+  const int lo = L - nx + 1 > 0 ? L - nx + 1 : 0, hi = L < ny - 1 ? L : ny - 1;
+  c.y = lo + int(threadIdx.x);
+  c.live = c.y <= hi;
+  const int y = c.live ? c.y : 0, x = c.live ? L - y : 0;
+  c.i = int64_t(y) * nx + x;
+  // row start: full rows below (3 nx - 2 entries each, plus the south and
+  // north couplings that exist), then the cells to the left in this row
+  const int64_t rp_i = int64_t(y) * (3 * nx - 2) + int64_t(nx) * (y > 0 ? y - 1 : 0) +
+                       int64_t(nx) * (y < ny - 1 ? y : ny - 1) +
+                       int64_t(x) * (1 + (y > 0) + (y < ny - 1)) + (x > 0 ? x - 1 : 0) +
+                       (x < nx - 1 ? x : nx - 1);
+  // row entries: south (y > 0), west (x > 0), self, east (x < nx-1), north (y < ny-1)
+  const int64_t self = rp_i + (y > 0) + (x > 0);
+  int64_t e0, e1;
+  if (FWD) {
+    c.has0 = c.live && y > 0;  // south, column i - nx
+    c.has1 = c.live && x > 0;  // west, column i - 1
+    e0 = rp_i;
+    e1 = rp_i + (y > 0);
+  } else {
+    c.has0 = c.live && x < nx - 1;  // east, column i + 1
+    c.has1 = c.live && y < ny - 1;  // north, column i + nx
+    e0 = self + 1;
+    e1 = self + 1 + (x < nx - 1);
+  }
+  e0 = c.has0 ? e0 : self;
+  e1 = c.has1 ? e1 : self;
+  // only the front's cells load (one CU's memory pipe carries every front)
+  if (c.live) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      c.b0[q] = jv[4 * e0 + q];
+      c.b1[q] = jv[4 * e1 + q];
+      c.d[q] = dinv[4 * c.i + q];
+    }
+    if (FWD) {
+      c.v[0] = T(r[2 * c.i]);
+      c.v[1] = T(r[2 * c.i + 1]);
+    } else {
+      c.v[0] = w[2 * c.i];
+      c.v[1] = w[2 * c.i + 1];
+    }
+  }
+}
+
+// one front: the previous front's results from buf[(q + 1) & 1], this
+// front's into buf[q & 1].  Branch-free (missing couplings add zero, slots
+// clamped), so the loads of later fronts keep their own wait counts.
+template <class T, bool FWD>
+__device__ inline void bilu_2d_step(const Bilu2dCell<T>& c, T (*buf)[kFront2d][2], int q,
+                                    T* __restrict__ w, T* __restrict__ z) {
+  const int y = c.y < kFront2d ? c.y : kFront2d - 1;
+  const T(*prev)[2] = buf[(q + 1) & 1];
+  const int s0 = FWD ? (y > 0 ? y - 1 : 0) : y;             // FWD south, BWD east
+  const int s1 = FWD ? y : (y + 1 < kFront2d ? y + 1 : y);  // FWD west, BWD north
+  const T u0 = prev[s0][0], u1 = prev[s0][1], v0 = prev[s1][0], v1 = prev[s1][1];
+  T a0 = 0, a1 = 0;
+  a0 += c.has0 ? c.b0[0] * u0 + c.b0[1] * u1 : T(0);
+  a1 += c.has0 ? c.b0[2] * u0 + c.b0[3] * u1 : T(0);
+  a0 += c.has1 ? c.b1[0] * v0 + c.b1[1] * v1 : T(0);
+  a1 += c.has1 ? c.b1[2] * v0 + c.b1[3] * v1 : T(0);
+  T o0, o1;
+  if (FWD) {
+    const T x0 = c.v[0] - a0, x1 = c.v[1] - a1;
+    o0 = c.d[0] * x0 + c.d[1] * x1;
+    o1 = c.d[2] * x0 + c.d[3] * x1;
+  } else {
+    o0 = c.v[0] - (c.d[0] * a0 + c.d[1] * a1);
+    o1 = c.v[1] - (c.d[2] * a0 + c.d[3] * a1);
+  }
+  if (c.live) {
+    T* out = FWD ? w : z;
+    out[2 * c.i] = o0;
+    out[2 * c.i + 1] = o1;
+    buf[q & 1][y][0] = o0;
+    buf[q & 1][y][1] = o1;
+  }
+}
+
+// LDS-only release/acquire around the barrier: global loads stay in flight
+// across it (no thread reads another's global writes inside the sweep)
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <class T, bool FWD>
+__global__ void __launch_bounds__(kFront2d) k_bilu_sweep_2d(int nx, int ny,
+                                                            const T* __restrict__ jv,
+                                                            const T* __restrict__ dinv,
+                                                            const double* __restrict__ r,
+                                                            T* __restrict__ w, T* __restrict__ z) {
+  __shared__ T buf[2][kFront2d][2];
+  const int nf = nx + ny - 1;
+  auto front = [&](int q) { return FWD ? q : nf - 1 - q; };
+  // fronts past the last are loaded as no cells (live false), so the loop
+  // body has no branch around its loads
+  auto load = [&](int q, Bilu2dCell<T>& c) {
+    bilu_2d_load<T, FWD>(nx, ny, q < nf ? front(q) : (FWD ? nf : -1), jv, dinv, r, w, c);
+  };
+  Bilu2dCell<T> ca, cb;  // fronts q (even) and q + 1
+  load(0, ca);
+  load(1, cb);
+  for (int q = 0; q < nf; q += 2) {
+    bilu_2d_step<T, FWD>(ca, buf, q, w, z);
+    load(q + 2, ca);
+    lds_barrier();
+    bilu_2d_step<T, FWD>(cb, buf, q + 1, w, z);
+    load(q + 3, cb);
+    lds_barrier();
+  }
+}
+
 __global__ void __launch_bounds__(1024) k_bilu_factor_wg(int nf, const int* __restrict__ fptr,
                                                          const int* __restrict__ cells,
                                                          const int* __restrict__ rp,
@@ -588,6 +725,16 @@ void bilu_apply(tpf_precond* M, const double* r, T* w, T* z, hipStream_t s) {
   }
   int nf = int(M->front_ptr.size()) - 1;
   TimedScope ts("bilu_solve", s);
+  const Phys& ph = J->prob->ph;
+  if (ph.nz == 1 && ph.ny <= kFront2d && ph.nx >= 1 && int64_t(ph.nx) * ph.ny == ph.N) {
+    const int longest = std::min(ph.nx, ph.ny);  // cells of the longest front
+    const int threads = (longest + kWave - 1) / kWave * kWave;
+    k_bilu_sweep_2d<T, true><<<1, threads, 0, s>>>(ph.nx, ph.ny, jv, dinv, r, w, z);
+    TPF_CHECK_LAUNCH();
+    k_bilu_sweep_2d<T, false><<<1, threads, 0, s>>>(ph.nx, ph.ny, jv, dinv, r, w, z);
+    TPF_CHECK_LAUNCH();
+    return;
+  }
   if (M->front_max <= kFrontWg) {
     k_bilu_sweep_wg<T, true><<<1, 1024, 0, s>>>(nf, M->front_ptr_dev.p, M->front_cells.p, J->rp.p,
                                                J->ci.p, jv, dinv, r, w, z);
