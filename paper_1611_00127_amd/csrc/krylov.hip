@@ -332,6 +332,8 @@ void Fgmres::begin(const tpf_jacobian* J_, tpf_precond* M_, const double* b_, do
   G = krylov_grid(n);
   total = 0;
   est = 1.0;
+  spec_j = -1;
+  ev_pending = false;
   status = -1;
   relres = 0.0;
   t0 = std::chrono::steady_clock::now();
@@ -342,6 +344,8 @@ void Fgmres::begin(const tpf_jacobian* J_, tpf_precond* M_, const double* b_, do
 }
 
 void Fgmres::launch_cycle_start(const double* rsrc, double beta) {
+  spec_j = -1;
+  spec_est = beta / beta0;
   k_scale_by<<<vec_grid(n), 256, 0, s>>>(n, rsrc, 1.0 / beta, V.p);
   TPF_CHECK_LAUNCH();
   fill(g.p, 0.0, m + 1, s);
@@ -351,18 +355,24 @@ void Fgmres::launch_cycle_start(const double* rsrc, double beta) {
   launch_step();
 }
 
+// z_col = M^{-1} v_col
+void Fgmres::apply_precond(int col) {
+  TimedScope ts("precond_apply", s);
+  int rc = tpf_precond_apply(M, V.p + int64_t(col) * n, Z.p + int64_t(col) * n, s);
+  if (rc != TPF_OK) {
+    char msg[1024];
+    tpf_last_error(msg, sizeof msg);
+    fail(rc, "%s", msg);
+  }
+}
+
 void Fgmres::launch_step() {
   double* vj = V.p + int64_t(j) * n;
   double* zj = Z.p + int64_t(j) * n;
   double* wv = V.p + int64_t(j + 1) * n;
   if (M && M->o.kind != TPF_PREC_NONE) {
-    TimedScope ts("precond_apply", s);
-    int rc = tpf_precond_apply(M, vj, zj, s);
-    if (rc != TPF_OK) {
-      char msg[1024];
-      tpf_last_error(msg, sizeof msg);
-      fail(rc, "%s", msg);
-    }
+    if (spec_j != j) apply_precond(j);
+    spec_j = -1;
   } else {
     copy(zj, vj, n, s);
   }
@@ -390,6 +400,17 @@ void Fgmres::launch_step() {
   TPF_CHECK_LAUNCH();
   TPF_HIP(hipMemcpyAsync(host, gs, sizeof(GState), hipMemcpyDeviceToHost, s));
   phase = kStep;
+  // the next step's preconditioning behind the scalars, unless this step
+  // may end the cycle (last column, iteration cap, estimate near the
+  // tolerance: the factor leaves room for two steps of fast convergence)
+  if (speculate && M && M->o.kind != TPF_PREC_NONE && j + 1 < m && total + 1 < o.maxit &&
+      spec_est > 50.0 * o.rtol) {
+    if (!ready) ready = thread_event(2);
+    TPF_HIP(hipEventRecord(ready, s));
+    ev_pending = true;
+    apply_precond(j + 1);
+    spec_j = j + 1;
+  }
 }
 
 void Fgmres::launch_cycle_end() {
@@ -440,6 +461,7 @@ bool Fgmres::complete() {
       } else {
         k = j + 1;
         est = gst.est / beta0;
+        spec_est = est;
         end = gst.est <= o.rtol * beta0 || gst.hn == 0.0 || total >= o.maxit || j + 1 >= m;
       }
       if (end) {
@@ -494,10 +516,15 @@ extern "C" int tpf_solve(const tpf_jacobian* J, tpf_precond* M, const double* b,
     TPF_REQUIRE(J && b && x && o && info, TPF_ERR_INVALID_ARG, "null argument");
     hipStream_t s = static_cast<hipStream_t>(stream);
     Fgmres f;  // workspace drawn from (and returned to) the installed allocator
+    f.speculate = true;
     f.begin(J, M, b, x, *o, s, host_scratch().get<double>(8));
     bool done = false;
     while (!done) {
-      TPF_HIP(hipStreamSynchronize(s));
+      if (f.ev_pending)
+        TPF_HIP(hipEventSynchronize(f.ready));
+      else
+        TPF_HIP(hipStreamSynchronize(s));
+      f.ev_pending = false;
       done = f.complete();
     }
     TPF_HIP(hipStreamSynchronize(s));

@@ -43,6 +43,18 @@ struct Fgmres {
   int status = -1;
   std::chrono::steady_clock::time_point t0;
 
+  // Speculative preconditioning (a caller driving one solve sets it before
+  // begin()): after step j's scalars are queued, M^{-1} v_{j+1} is queued
+  // behind them while the estimate of the last decision is far from the
+  // tolerance, so the GPU does not idle while the host decides.  The
+  // scalars are then marked by `ready` (ev_pending): wait on it, not on the
+  // stream.  The results are those of the plain sequence.
+  bool speculate = false;
+  int spec_j = -1;          // Z column already holding M^{-1} v for that step
+  double spec_est = 0.0;    // relative residual estimate of the last decision
+  bool ev_pending = false;
+  hipEvent_t ready = nullptr;
+
   void begin(const tpf_jacobian* J, tpf_precond* M, const double* b, double* x,
              const tpf_solve_opts& o, hipStream_t s, void* host_slot);
   bool complete();
@@ -55,6 +67,7 @@ struct Fgmres {
   void launch_cycle_start(const double* r, double beta);
   void launch_step();
   void launch_cycle_end();
+  void apply_precond(int col);
 };
 
 }  // namespace tpf
