@@ -411,6 +411,15 @@ __global__ void __launch_bounds__(1024) k_bilu_sweep_wg(int nf, const int* __res
   }
 }
 
+// Row start of cell (x, y) in the 5-point block pattern of a 2D grid: full
+// rows below (3 nx - 2 entries each, plus the south and north couplings that
+// exist), then the cells to its left.
+__device__ inline int64_t rp_5pt(int x, int y, int nx, int ny) {
+  return int64_t(y) * (3 * nx - 2) + int64_t(nx) * (y > 0 ? y - 1 : 0) +
+         int64_t(nx) * (y < ny - 1 ? y : ny - 1) + int64_t(x) * (1 + (y > 0) + (y < ny - 1)) +
+         (x > 0 ? x - 1 : 0) + (x < nx - 1 ? x : nx - 1);
+}
+
 // Sweeps on 2D grids of at most kFront2d rows (fronts of at most that many
 // cells): thread t takes the cell of row y = lo + t of each front; the
 // previous front's results come from LDS (slot y, two buffers by front
@@ -439,12 +448,7 @@ __device__ inline void bilu_2d_load(int nx, int ny, int L, const T* __restrict__
   c.live = c.y <= hi;
   const int y = c.live ? c.y : 0, x = c.live ? L - y : 0;
   c.i = int64_t(y) * nx + x;
-  // row start: full rows below (3 nx - 2 entries each, plus the south and
-  // north couplings that exist), then the cells to the left in this row
-  const int64_t rp_i = int64_t(y) * (3 * nx - 2) + int64_t(nx) * (y > 0 ? y - 1 : 0) +
-                       int64_t(nx) * (y < ny - 1 ? y : ny - 1) +
-                       int64_t(x) * (1 + (y > 0) + (y < ny - 1)) + (x > 0 ? x - 1 : 0) +
-                       (x < nx - 1 ? x : nx - 1);
+  const int64_t rp_i = rp_5pt(x, y, nx, ny);
   // row entries: south (y > 0), west (x > 0), self, east (x < nx-1), north (y < ny-1)
   const int64_t self = rp_i + (y > 0) + (x > 0);
   int64_t e0, e1;
@@ -543,6 +547,101 @@ __global__ void __launch_bounds__(kFront2d) k_bilu_sweep_2d(int nx, int ny,
     load(q + 2, ca);
     lds_barrier();
     bilu_2d_step<T, FWD>(cb, buf, q + 1, w, z);
+    load(q + 3, cb);
+    lds_barrier();
+  }
+}
+
+// The factorisation on the same fronts: D_i = A_ii - A_is D_s^{-1} A_si -
+// A_iw D_w^{-1} A_wi (s, w: the south and west neighbours, on the previous
+// front, whose D^{-1} come from LDS), the terms in bilu_factor_cell's order.
+struct Bilu2dFac {
+  double as[4], aw[4], ad[4], sa[4], wa[4];  // A_is, A_iw, A_ii, A_si, A_wi
+  bool hs, hw, live;
+  int y;
+  int64_t i;
+};
+
+__device__ inline void bilu_2d_fac_load(int nx, int ny, int L, const double* __restrict__ jv,
+                                        Bilu2dFac& c) {
+  const int lo = L - nx + 1 > 0 ? L - nx + 1 : 0, hi = L < ny - 1 ? L : ny - 1;
+  c.y = lo + int(threadIdx.x);
+  c.live = c.y <= hi;
+  const int y = c.live ? c.y : 0, x = c.live ? L - y : 0;
+  c.i = int64_t(y) * nx + x;
+  c.hs = c.live && y > 0;
+  c.hw = c.live && x > 0;
+  const int64_t r0 = rp_5pt(x, y, nx, ny);
+  const int64_t ed = r0 + (y > 0) + (x > 0);
+  // south cell (x, y - 1): its north entry is its last; west cell (x - 1, y):
+  // its east entry follows its diagonal
+  const int64_t es = c.hs ? r0 : ed;
+  const int64_t ew = c.hw ? r0 + (y > 0) : ed;
+  const int64_t fs = c.hs ? rp_5pt(x, y - 1, nx, ny) + (y - 1 > 0) + (x > 0) + (x < nx - 1) + 1 : ed;
+  const int64_t fw = c.hw ? rp_5pt(x - 1, y, nx, ny) + (y > 0) + (x - 1 > 0) + 1 : ed;
+  if (c.live) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      c.as[q] = jv[4 * es + q];
+      c.aw[q] = jv[4 * ew + q];
+      c.ad[q] = jv[4 * ed + q];
+      c.sa[q] = jv[4 * fs + q];
+      c.wa[q] = jv[4 * fw + q];
+    }
+  }
+}
+
+__device__ inline void bilu_2d_fac_step(const Bilu2dFac& c, double (*buf)[kFront2d][4], int q,
+                                        double* __restrict__ dinv, int* __restrict__ flag) {
+  const int y = c.y < kFront2d ? c.y : kFront2d - 1;
+  const double(*prev)[4] = buf[(q + 1) & 1];
+  const int ss = y > 0 ? y - 1 : 0;
+  double ds[4], dw[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    ds[t] = prev[ss][t];
+    dw[t] = prev[y][t];
+  }
+  double tmp[4], cs_[4], cw_[4];
+  mm2(c.as, ds, tmp);
+  mm2(tmp, c.sa, cs_);
+  mm2(c.aw, dw, tmp);
+  mm2(tmp, c.wa, cw_);
+  double d[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    double acc = 0.0;
+    acc += c.hs ? cs_[t] : 0.0;
+    acc += c.hw ? cw_[t] : 0.0;
+    d[t] = c.ad[t] - acc;
+  }
+  const double det = d[0] * d[3] - d[1] * d[2];
+  const double o[4] = {d[3] / det, -d[1] / det, -d[2] / det, d[0] / det};
+  if (c.live) {
+    if (det == 0.0 || !isfinite(det)) *flag = 1;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      dinv[4 * c.i + t] = o[t];
+      buf[q & 1][y][t] = o[t];
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kFront2d) k_bilu_factor_2d(int nx, int ny,
+                                                             const double* __restrict__ jv,
+                                                             double* __restrict__ dinv,
+                                                             int* __restrict__ flag) {
+  __shared__ double buf[2][kFront2d][4];
+  const int nf = nx + ny - 1;
+  auto load = [&](int q, Bilu2dFac& c) { bilu_2d_fac_load(nx, ny, q < nf ? q : nf, jv, c); };
+  Bilu2dFac ca, cb;  // fronts q (even) and q + 1
+  load(0, ca);
+  load(1, cb);
+  for (int q = 0; q < nf; q += 2) {
+    bilu_2d_fac_step(ca, buf, q, dinv, flag);
+    load(q + 2, ca);
+    lds_barrier();
+    bilu_2d_fac_step(cb, buf, q + 1, dinv, flag);
     load(q + 3, cb);
     lds_barrier();
   }
@@ -689,7 +788,12 @@ void bilu_setup(tpf_precond* M, bool reuse, hipStream_t s) {
   Buf<int> flag(1, s);
   fill_int(flag.p, 0, 1, s);
   int nf = int(M->front_ptr.size()) - 1;
-  if (M->front_max <= kFrontWg) {
+  if (ph.nz == 1 && ph.ny <= kFront2d && int64_t(ph.nx) * ph.ny == N) {
+    const int longest = std::min(ph.nx, ph.ny);  // cells of the longest front
+    const int threads = (longest + kWave - 1) / kWave * kWave;
+    k_bilu_factor_2d<<<1, threads, 0, s>>>(ph.nx, ph.ny, J->v.p, M->bilu_dinv.p, flag.p);
+    TPF_CHECK_LAUNCH();
+  } else if (M->front_max <= kFrontWg) {
     k_bilu_factor_wg<<<1, 1024, 0, s>>>(nf, M->front_ptr_dev.p, M->front_cells.p, J->rp.p,
                                         J->ci.p, J->v.p, M->bilu_dinv.p, flag.p);
     TPF_CHECK_LAUNCH();

@@ -267,6 +267,21 @@ def test_bilu_parity(gpu):
     M.close(); g.close()
 
 
+@pytest.mark.parametrize("nx,ny", [(37, 23), (9, 70)])
+def test_bilu_parity_2d(gpu, nx, ny):
+    """Pivot blocks of the block ILU(0) on 2D grids (factorised front by front
+    with the previous front's pivots in LDS) against the oracle."""
+    driver, tpf, torch = gpu
+    c = inputs.random_state(inputs.small_case(nx, ny, 1, seed=44), 45, s_lo=0.15, s_hi=0.85)
+    say(f"[bilu 2d] {nx}x{ny}")
+    g, M = _setup(driver, tpf, c, "cpr1")
+    rp, ci, vals = g.bcsr_numpy()
+    B = ilu.Bilu0(rp, ci, vals, c.nx, c.ny, c.nz)
+    dv = tpf.device_array(tpf.tpf_precond_bilu_dinv(M.M), 4 * c.N, np.float64).reshape(-1, 2, 2)
+    assert np.max(np.abs(dv - B.Dinv)) <= 1e-12 * np.max(np.abs(B.Dinv))
+    M.close(); g.close()
+
+
 @pytest.mark.parametrize("kind", ["amg", "cpr1", "cpr2", "bf"])
 def test_precond_apply_parity(gpu, kind):
     """z = M^{-1} r: GPU vs the oracle preconditioner built from the GPU's J."""
