@@ -79,6 +79,41 @@ __global__ void k_scan_finish(const T* __restrict__ tmp, const In* __restrict__ 
 
 // reads the 64-bit total written by k_scan_finish (one round trip)
 int64_t read_total(const int64_t* tot, hipStream_t s) { return read_scalar(tot, s); }
+
+// Short inputs (the coarse levels): the whole scan in one work-group, tile
+// by tile with a running carry, in place of the tile / block-sum / add /
+// finish launches.  out[n] and *tot receive the total.
+constexpr int kScanOneBlock = 1024;
+constexpr int64_t kScanOneMax = 16384;
+template <class In, class Out>
+__global__ void __launch_bounds__(kScanOneBlock) k_scan_one(const In* __restrict__ in,
+                                                            Out* __restrict__ out, int64_t n,
+                                                            int64_t* __restrict__ tot) {
+  __shared__ int64_t sh[kScanOneBlock / 64 + 1];
+  int64_t carry = 0;
+  for (int64_t base = 0; base < n; base += int64_t(kScanOneBlock) * kScanItems) {
+    const int64_t i0 = base + int64_t(threadIdx.x) * kScanItems;
+    int64_t v[kScanItems];
+    int64_t local = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      v[k] = i0 + k < n ? int64_t(in[i0 + k]) : 0;
+      local += v[k];
+    }
+    int64_t total;
+    int64_t excl = block_exclusive_scan<int64_t, kScanOneBlock>(local, sh, total) + carry;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      if (i0 + k < n) out[i0 + k] = Out(excl);
+      excl += v[k];
+    }
+    carry += total;
+  }
+  if (threadIdx.x == 0) {
+    out[n] = Out(carry);
+    *tot = carry;
+  }
+}
 }  // namespace
 
 int64_t scan_exclusive(const int* in, int* out, int64_t n, hipStream_t s) {
@@ -86,6 +121,15 @@ int64_t scan_exclusive(const int* in, int* out, int64_t n, hipStream_t s) {
   if (n == 0) {
     fill_int(out, 0, 1, s);
     return 0;
+  }
+  if (n <= kScanOneMax) {
+    Buf<int64_t> tot(1, s);
+    k_scan_one<int, int><<<1, kScanOneBlock, 0, s>>>(in, out, n, tot.p);
+    TPF_CHECK_LAUNCH();
+    const int64_t total = read_total(tot.p, s);
+    TPF_REQUIRE(total < (int64_t(1) << 31), TPF_ERR_INVALID_ARG,
+                "index count %lld exceeds the int32 range", (long long)total);
+    return total;
   }
   Buf<int64_t> tmp(n + 1, s);
   scan_rec<int64_t, int>(in, tmp.p, n, s);
@@ -104,6 +148,12 @@ void scan_exclusive_async(const int* in, int* out, int64_t n, hipStream_t s) {
     fill_int(out, 0, 1, s);
     return;
   }
+  if (n <= kScanOneMax) {
+    Buf<int64_t> tot(1, s);
+    k_scan_one<int, int><<<1, kScanOneBlock, 0, s>>>(in, out, n, tot.p);
+    TPF_CHECK_LAUNCH();
+    return;
+  }
   Buf<int64_t> tmp(n + 1, s);
   scan_rec<int64_t, int>(in, tmp.p, n, s);
   unsigned g = grid_for(n, 256);
@@ -118,8 +168,12 @@ int64_t scan_exclusive_wide(const int* in, int64_t* out, int64_t n, hipStream_t 
     return 0;
   }
   Buf<int64_t> tot(1, s);
-  scan_rec<int64_t, int>(in, out, n, s);
-  k_scan_finish<int64_t, int, int64_t><<<1, 64, 0, s>>>(out, in, n, out, false, tot.p);
+  if (n <= kScanOneMax) {
+    k_scan_one<int, int64_t><<<1, kScanOneBlock, 0, s>>>(in, out, n, tot.p);
+  } else {
+    scan_rec<int64_t, int>(in, out, n, s);
+    k_scan_finish<int64_t, int, int64_t><<<1, 64, 0, s>>>(out, in, n, out, false, tot.p);
+  }
   TPF_CHECK_LAUNCH();
   return read_total(tot.p, s);
 }
@@ -130,8 +184,12 @@ int64_t scan_exclusive64(const int64_t* in, int64_t* out, int64_t n, hipStream_t
     return 0;
   }
   Buf<int64_t> tot(1, s);
-  scan_rec<int64_t, int64_t>(in, out, n, s);
-  k_scan_finish<int64_t, int64_t, int64_t><<<1, 64, 0, s>>>(out, in, n, out, false, tot.p);
+  if (n <= kScanOneMax) {
+    k_scan_one<int64_t, int64_t><<<1, kScanOneBlock, 0, s>>>(in, out, n, tot.p);
+  } else {
+    scan_rec<int64_t, int64_t>(in, out, n, s);
+    k_scan_finish<int64_t, int64_t, int64_t><<<1, 64, 0, s>>>(out, in, n, out, false, tot.p);
+  }
   TPF_CHECK_LAUNCH();
   return read_total(tot.p, s);
 }
