@@ -79,14 +79,41 @@ __global__ void __launch_bounds__(256) k_strength(int n, const int* __restrict__
     a0 = rp[i];
     a1 = rp[i + 1];
   }
+  // rows of at most kB entries per lane keep them in registers for both
+  // passes (loads at clamped positions, all issued before the first wait)
+  constexpr int kB = 8;
+  const bool inreg = a1 - a0 <= kB * LPR;
+  int cr[kB];
+  double vr[kB];
+  if (inreg) {
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const int e = min(a0 + lane + u * LPR, a1 - 1);
+      cr[u] = a1 > a0 ? ci[e] : i;
+      vr[u] = a1 > a0 ? v[e] : 0.0;
+    }
+  }
   double dg = 0.0, mpos = -INFINITY, mneg = -INFINITY;
-  for (int e = a0 + lane; e < a1; e += LPR) {
-    double x = v[e];
-    if (ci[e] == i) {
-      dg += x;
-    } else {
-      mpos = fmax(mpos, x);
-      mneg = fmax(mneg, -x);
+  if (inreg) {
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      if (a0 + lane + u * LPR >= a1) break;
+      if (cr[u] == i) {
+        dg += vr[u];
+      } else {
+        mpos = fmax(mpos, vr[u]);
+        mneg = fmax(mneg, -vr[u]);
+      }
+    }
+  } else {
+    for (int e = a0 + lane; e < a1; e += LPR) {
+      double x = v[e];
+      if (ci[e] == i) {
+        dg += x;
+      } else {
+        mpos = fmax(mpos, x);
+        mneg = fmax(mneg, -x);
+      }
     }
   }
   dg = group_sum<LPR>(dg);
@@ -96,10 +123,21 @@ __global__ void __launch_bounds__(256) k_strength(int n, const int* __restrict__
   double m = dg < 0.0 ? mpos : mneg;  // max of -s a_ij
   double thr = theta * m;
   int c = 0;
-  for (int e = a0 + lane; e < a1; e += LPR) {
-    bool st = ci[e] != i && m > 0.0 && (-s * v[e]) >= thr;
-    mask[e] = st;
-    c += st;
+  if (inreg) {
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const int e = a0 + lane + u * LPR;
+      if (e >= a1) break;
+      const bool st = cr[u] != i && m > 0.0 && (-s * vr[u]) >= thr;
+      mask[e] = st;
+      c += st;
+    }
+  } else {
+    for (int e = a0 + lane; e < a1; e += LPR) {
+      bool st = ci[e] != i && m > 0.0 && (-s * v[e]) >= thr;
+      mask[e] = st;
+      c += st;
+    }
   }
   c = group_sum<LPR>(c);
   if (i < n && lane == 0) cnt[i] = c;
