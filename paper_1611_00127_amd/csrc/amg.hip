@@ -1481,6 +1481,56 @@ __global__ void __launch_bounds__(256) k_dia_post2(int n, DiagOffs o, const T* _
   *reinterpret_cast<T2*>(x + i) = out;
 }
 
+// FP32 forms of the two kernels above with four rows per thread (16-byte
+// loads of the diagonals and row vectors, as the FP64 forms read); each
+// row's terms are summed in the same order.
+using nt4f = float __attribute__((ext_vector_type(4)));
+template <int K>
+__global__ void __launch_bounds__(256) k_dia_pre4f(int n, DiagOffs o, const float* __restrict__ v,
+                                                   const float* __restrict__ g,
+                                                   const float* __restrict__ b,
+                                                   float* __restrict__ r) {
+  const int i = 4 * (xcd_contiguous_block() * blockDim.x + threadIdx.x);
+  if (i >= n) return;
+  float s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const nt4f a = __builtin_nontemporal_load(reinterpret_cast<const nt4f*>(v + int64_t(k) * n + i));
+    s[0] += a.x * g[clampi(i + o.off[k], n)];
+    s[1] += a.y * g[clampi(i + 1 + o.off[k], n)];
+    s[2] += a.z * g[clampi(i + 2 + o.off[k], n)];
+    s[3] += a.w * g[clampi(i + 3 + o.off[k], n)];
+  }
+  const float4 bb = *reinterpret_cast<const float4*>(b + i);
+  *reinterpret_cast<float4*>(r + i) =
+      make_float4(bb.x - s[0], bb.y - s[1], bb.z - s[2], bb.w - s[3]);
+}
+
+template <int K>
+__global__ void __launch_bounds__(256) k_dia_post4f(int n, DiagOffs o, const float* __restrict__ v,
+                                                    const float* __restrict__ dinv,
+                                                    const float* __restrict__ b,
+                                                    const float* __restrict__ y,
+                                                    float* __restrict__ x) {
+  const int i = 4 * (xcd_contiguous_block() * blockDim.x + threadIdx.x);
+  if (i >= n) return;
+  float s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const nt4f a = __builtin_nontemporal_load(reinterpret_cast<const nt4f*>(v + int64_t(k) * n + i));
+    s[0] += a.x * y[clampi(i + o.off[k], n)];
+    s[1] += a.y * y[clampi(i + 1 + o.off[k], n)];
+    s[2] += a.z * y[clampi(i + 2 + o.off[k], n)];
+    s[3] += a.w * y[clampi(i + 3 + o.off[k], n)];
+  }
+  const float4 yy = *reinterpret_cast<const float4*>(y + i);
+  const float4 dd = *reinterpret_cast<const float4*>(dinv + i);
+  const float4 bb = *reinterpret_cast<const float4*>(b + i);
+  *reinterpret_cast<float4*>(x + i) =
+      make_float4(yy.x + dd.x * (bb.x - s[0]), yy.y + dd.y * (bb.y - s[1]),
+                  yy.z + dd.z * (bb.z - s[2]), yy.w + dd.w * (bb.w - s[3]));
+}
+
 // x = y + D^{-1} (b - A y)
 template <class T, int K>
 __global__ void __launch_bounds__(256) k_dia_post(int n, DiagOffs o, const T* __restrict__ v,
@@ -1877,6 +1927,9 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st) {
   // the two-row diagonal kernels read pairs: n even and every vector aligned
   auto al2 = [](const void* p) { return reinterpret_cast<uintptr_t>(p) % (2 * sizeof(T)) == 0; };
   const bool pairs = n % 2 == 0 && al2(b) && al2(x) && al2(r) && al2(y) && al2(dinv);
+  // FP32: four rows per thread (16-byte loads) when n % 4 == 0 and every
+  // vector and diagonal is 16-byte aligned
+  auto al16 = [](const void* p) { return reinterpret_cast<uintptr_t>(p) % 16 == 0; };
   DiagOffs doff;
   const T* dv = nullptr;
   if (dia) {
@@ -1886,6 +1939,8 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st) {
     else
       dv = dia0.v.p;
   }
+  const bool quads = std::is_same<T, float>::value && dia && n % 4 == 0 && al16(b) && al16(x) &&
+                     al16(r) && al16(y) && al16(dinv) && al16(dv);
   // large levels form g = D^{-1} b once (in y, until the prolongation
   // overwrites it), so the residual gathers one vector
   const bool guess = dia || n >= kGuessRows;
@@ -1897,7 +1952,13 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st) {
   {
     TimedScope ts(L.t_pre.c_str(), st);
     if (dia) {
-      if (pairs) {
+      if (quads) {
+        DISPATCH_DIAG(dia0.K, KK, {
+          k_dia_pre4f<KK><<<grid_for(n / 4, 256), 256, 0, st>>>(
+              n, doff, reinterpret_cast<const float*>(dv), reinterpret_cast<const float*>(y),
+              reinterpret_cast<const float*>(b), reinterpret_cast<float*>(r));
+        });
+      } else if (pairs) {
         DISPATCH_DIAG(dia0.K, KK, {
           k_dia_pre2<T, KK><<<grid_for(n / 2, 256), 256, 0, st>>>(n, doff, dv, y, b, r);
         });
@@ -1931,7 +1992,14 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st) {
   {
     TimedScope ts(L.t_post.c_str(), st);
     if (dia) {
-      if (pairs) {
+      if (quads) {
+        DISPATCH_DIAG(dia0.K, KK, {
+          k_dia_post4f<KK><<<grid_for(n / 4, 256), 256, 0, st>>>(
+              n, doff, reinterpret_cast<const float*>(dv), reinterpret_cast<const float*>(dinv),
+              reinterpret_cast<const float*>(b), reinterpret_cast<const float*>(y),
+              reinterpret_cast<float*>(x));
+        });
+      } else if (pairs) {
         DISPATCH_DIAG(dia0.K, KK, {
           k_dia_post2<T, KK><<<grid_for(n / 2, 256), 256, 0, st>>>(n, doff, dv, dinv, b, y, x);
         });
