@@ -116,10 +116,13 @@ def _setup(driver, tpf, c, kind, precision=0, **opts):
     return g, M
 
 
-def test_schur_parity(gpu):
+@pytest.mark.parametrize("nx,ny,nz", [(13, 12, 7), (16, 11, 1), (12, 9, 3)])
+def test_schur_parity(gpu, nx, ny, nz):
+    """S~ against the oracle: formed on the grid (3D, at least five cells per
+    direction) and by the general sparse product (2D, thin 3D)."""
     driver, tpf, torch = gpu
-    c = inputs.small_case(13, 12, 7, seed=6)
-    say("[schur] 13x12x7")
+    c = inputs.small_case(nx, ny, nz, seed=6)
+    say(f"[schur] {nx}x{ny}x{nz}")
     g, M = _setup(driver, tpf, c, "bf")
     rp, ci, vals = g.bcsr_numpy()
     blk = [blocks.block(rp, ci, vals, a, b) for a, b in [(0, 0), (0, 1), (1, 0), (1, 1)]]
