@@ -1574,6 +1574,18 @@ template <> const float* dinv_of<float>(const Level& L) { return L.dinv32.p; }
 }  // namespace
 
 // ---------------------------------------------------------------- setup
+// A_c = R A P with the intermediate kept in L.T: (R A) P when ra_first, else
+// R (A P)
+static void galerkin(Level& L, bool ra_first, Csr<double>& Ac, hipStream_t s) {
+  if (ra_first) {
+    spgemm(ref(L.R), ref(L.A), L.T, s);
+    spgemm(ref(L.T), ref(L.P), Ac, s);
+  } else {
+    spgemm(ref(L.A), ref(L.P), L.T, s);
+    spgemm(ref(L.R), ref(L.T), Ac, s);
+  }
+}
+
 void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
   drop_graphs();
   o = opts;
@@ -1751,10 +1763,12 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
       TPF_CHECK_LAUNCH();
     }
     transpose(ref(L.P), L.R, s);
-    // Galerkin product A_c = R (A P)
-    spgemm(ref(L.A), ref(L.P), L.AP, s);
+    // Galerkin product A_c = R A P, as (R A) P on level 0 (R's rows of a
+    // few fine points times the stencil rows, then P's short rows: about a
+    // quarter fewer products than R (A P)), as R (A P) on the coarser levels
+    // (whose dense rows would make R A the larger product)
     auto next = std::make_unique<Level>();
-    spgemm(ref(L.R), ref(L.AP), next->A, s);
+    galerkin(L, lv.size() == 1, next->A, s);
     lv.push_back(std::move(next));
   }
   finish_levels(s);
@@ -1768,8 +1782,7 @@ void Hierarchy::refresh(hipStream_t st) {
   s = st;
   for (size_t l = 0; l + 1 < lv.size(); ++l) {
     Level& L = *lv[l];
-    spgemm(ref(L.A), ref(L.P), L.AP, s);
-    spgemm(ref(L.R), ref(L.AP), lv[l + 1]->A, s);
+    galerkin(L, l == 0, lv[l + 1]->A, s);
   }
   finish_levels(s);
 }
@@ -1888,7 +1901,7 @@ size_t Hierarchy::bytes() const {
   for (auto& Lp : lv) {
     const Level& L = *Lp;
     b += L.A.bytes() + L.dinv.bytes() + L.mask.bytes() + L.S.bytes() + L.cf.bytes() + L.P.bytes() +
-         L.R.bytes() + L.AP.bytes() + L.Av32.bytes() + L.Pv32.bytes() + L.Rv32.bytes() +
+         L.R.bytes() + L.T.bytes() + L.Av32.bytes() + L.Pv32.bytes() + L.Rv32.bytes() +
          L.dinv32.bytes() + L.r.bytes() + L.y.bytes() + L.b.bytes() + L.x.bytes() +
          L.r32.bytes() + L.y32.bytes() + L.b32.bytes() + L.x32.bytes();
   }
