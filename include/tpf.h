@@ -23,7 +23,11 @@
  *     *_destroy call; their device memory comes from the allocator installed
  *     with tpf_set_allocator (the device's stream-ordered pool if none).
  *   - All device work is ordered on the hipStream_t passed as `stream`
- *     (NULL = the null stream).  Only tpf_solve, the setup of a
+ *     (NULL = the null stream).  Setups may fork independent kernels onto
+ *     library-owned side streams (created per caller stream on first use,
+ *     default priority, kept until the process ends); they are ordered
+ *     after the work queued on `stream` before the call, and `stream` waits
+ *     for them before the call returns.  Only tpf_solve, the setup of a
  *     preconditioner (which reads level sizes back) and tpf_kernel_stats
  *     synchronise the stream.
  *   - Handles are not thread safe.
