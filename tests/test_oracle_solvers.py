@@ -193,6 +193,65 @@ def test_extended_i_closed_forms():
     np.testing.assert_allclose(rs[nonempty], 1.0, rtol=1e-13)
 
 
+def _non_m_matrix():
+    """Six points, not an M-matrix (positive off-diagonals, a negative
+    diagonal).  Row 0 (diagonal 10, F): strong C point 1 (-4), strong F point
+    2 (-4), weak C point 3 (-0.5 < 0.25 * 4), weak F point 4 (+1, positive),
+    strong F point 5 (-2).  Row 2 (diagonal -5, F): entries +2 (point 0,
+    strong F), -1 (point 1, same sign as its diagonal, so weak), +1.5
+    (point 3, strong C).  Row 5 (diagonal 3): +1 to point 0 (same sign as
+    its diagonal), -1 to point 4.  Points 1, 3, 4 have only a diagonal."""
+    D = np.zeros((6, 6))
+    D[0, [0, 1, 2, 3, 4, 5]] = [10.0, -4.0, -4.0, -0.5, 1.0, -2.0]
+    D[1, 1] = 1.0
+    D[2, [0, 1, 2, 3]] = [2.0, -1.0, -5.0, 1.5]
+    D[3, 3] = 1.0
+    D[4, 4] = 1.0
+    D[5, [0, 4, 5]] = [1.0, -1.0, 3.0]
+    A = sp.csr_matrix(D)
+    A.sort_indices()
+    cf = np.array([2, 1, 2, 1, 2, 2], np.int8)
+    return A, cf
+
+
+def test_extended_i_non_m_matrix_hand_weights():
+    """Extended+i (De Sterck, Falgout, Nolting, Yang 2008) on a matrix that is
+    not an M-matrix, weights worked out by hand.
+
+    Row 0: C^_0 = {1} (strong C) u {3} (strong C of its strong F neighbour 2;
+    point 5's only strong neighbour is the F point 4).  The filtered entries
+    a-bar_2l keep the signs opposite to a_22 = -5, i.e. the positive ones:
+    a-bar_20 = 2, a-bar_21 = 0, a-bar_23 = 1.5, so d_02 = 3.5.  Point 5 has
+    no opposite-signed entry in C^_0 u {0} (a_50 = +1 shares a_55's sign),
+    d_05 = 0, so a_05 = -2 is lumped into the diagonal, as is the weak F
+    entry a_04 = +1, while the weak entry a_03 = -0.5 (3 in C^_0) stays in
+    the numerator:
+      a~_00 = 10 + 1 + (-4)(2)/3.5 + (-2) = 47/7
+      w_01  = -(-4) / (47/7) = 28/47
+      w_03  = -(-0.5 + (-4)(1.5)/3.5) / (47/7) = 31/94.
+    Row 2 (negative diagonal): C^_2 = {3} u {1} (strong C of point 0); row 0's
+    filtered entries keep the negative ones (a_00 > 0): d_20 = -4 - 0.5 - 4
+    = -8.5 over {1, 3, 2}:
+      a~_22 = -5 + 2(-4)/(-8.5) = -69/17
+      w_21  = -(-1 + 2(-4)/(-8.5)) / (-69/17) = -1/69
+      w_23  = -(1.5 + 2(-0.5)/(-8.5)) / (-69/17) = 55/138.
+    Each of these moves if a-bar takes a_ii's sign instead of a_kk's, if a
+    weak entry in C^_i is lumped, or if a d_ik = 0 neighbour is dropped."""
+    A, cf = _non_m_matrix()
+    mask = amg.strength(A, 0.25)
+    rows = amg.row_index(A)
+    strong = {(int(r), int(c)) for r, c, k in zip(rows, A.indices, mask) if k}
+    assert strong == {(0, 1), (0, 2), (0, 5), (2, 0), (2, 3), (5, 4)}
+    P, cidx = amg.extended_i_interpolation(A, mask, cf)
+    Pd = P.toarray()
+    assert list(cidx[[1, 3]]) == [0, 1]
+    np.testing.assert_allclose(Pd[0], [28 / 47, 31 / 94], rtol=1e-15)
+    np.testing.assert_allclose(Pd[2], [-1 / 69, 55 / 138], rtol=1e-14)
+    np.testing.assert_array_equal(Pd[[1, 3]], np.eye(2))
+    # rows 4 and 5 have no interpolatory set: empty rows
+    assert np.diff(P.indptr)[4] == 0 and np.diff(P.indptr)[5] == 0
+
+
 def test_extended_i_restores_scalable_schur_cycle():
     """On the heterogeneous S~ of the 3D workload family the direct
     interpolation cycle degrades with the grid while extended+i stays flat
@@ -440,3 +499,26 @@ def test_bf_converges_across_capillarity(pd):
     c = inputs.workload_2d_corner(48, 48, 2.0, 8.0, pd, 50.0, 2)
     _, info, _ = newton.solve(c, "bf")
     assert info["status"] == fgmres.CONVERGED and info["relres"] <= 1e-8
+
+
+# ----------------------------------------------------------------- Newton
+
+
+def test_newton_update_chop_and_clamp_closed_form():
+    """Newton update of Sec. 3 with the build's reading of the paper's
+    unspecified variant: saturation increments limited to [-ds_max, ds_max],
+    then S_n clamped to [0, 1]; pressures move by the full increment."""
+    u = np.array([[1.0, 0.5], [2.0, 0.1], [-1.0, 0.95], [0.0, 0.3], [3.0, 0.6]])
+    d = np.array([[0.3, 0.5], [-0.5, -0.15], [0.25, 0.1], [1.5, -0.35], [-2.0, 0.05]])
+    # with the chop at 0.2:
+    #   0.5 + min(0.5, 0.2) = 0.7;   0.1 - 0.15 = -0.05 -> 0;  0.95 + 0.1 = 1.05 -> 1;
+    #   0.3 - min(0.35, 0.2) = 0.1;  0.6 + 0.05 = 0.65
+    un = newton.update(u, d.reshape(-1), ds_max=0.2)
+    np.testing.assert_array_equal(un[:, 0], [1.3, 1.5, -0.75, 1.5, 1.0])
+    np.testing.assert_allclose(un[:, 1], [0.7, 0.0, 1.0, 0.1, 0.65], rtol=0, atol=1e-16)
+    # no chop (ds_max = 0): 0.5 + 0.5 = 1;  0.3 - 0.35 = -0.05 -> 0
+    un0 = newton.update(u, d.reshape(-1), ds_max=0.0)
+    np.testing.assert_allclose(un0[:, 1], [1.0, 0.0, 1.0, 0.0, 0.65], rtol=0, atol=1e-16)
+    np.testing.assert_array_equal(un0[:, 0], un[:, 0])
+    # the input state is not modified
+    assert u[0, 1] == 0.5 and u[3, 1] == 0.3
