@@ -30,8 +30,19 @@ deterministic, data-parallel ones; this module states exactly those:
 5. stop when n <= coarse_max, n_c == 0, n_c > 0.9 n, or max_levels; the
    coarsest level is solved by dense LU with partial pivoting when it has at
    most dense_max rows, otherwise by two l1-Jacobi sweeps;
-6. V(1,1) cycle with l1-Jacobi, d_i = a_ii + s_i sum_{j!=i} |a_ij| (rows
-   with d_i = 0 are not smoothed), zero initial guess on every level.
+6. V(nu1, nu2) cycle, zero initial guess on every level, with nu1 pre- and
+   nu2 post-smoothing steps (default 1 and 1) of either smoother:
+   * l1-Jacobi (Baker, Falgout, Kolev, Yang 2011): x <- x + D^{-1}(b - A x),
+     d_i = a_ii + s_i sum_{j!=i} |a_ij| (rows with d_i = 0 are not smoothed);
+   * Chebyshev of degree k on D^{-1} A (D the same l1 diagonal): the
+     three-term Chebyshev iteration (Saad, Iterative Methods, Alg. 12.1)
+     for the interval [lo, hi], hi = 1.1 lambda^ and lo = 0.3 hi, where
+     lambda^ estimates the largest eigenvalue of D^{-1} A by power
+     iteration from the PMIS hash vector; its error propagator is the
+     scaled Chebyshev polynomial T_k((c - t)/h) / T_k(c/h), c = (hi+lo)/2,
+     h = (hi-lo)/2, in t = D^{-1} A.  The paper's own hybrid Gauss-Seidel
+     (Sec. 4.1 solver settings) is sequential; both smoothers here are
+     polynomials in A, applied row-parallel.
 """
 from __future__ import annotations
 
@@ -246,6 +257,54 @@ def l1_diag(A):
     return A.diagonal() + s * off
 
 
+def power_max_eig(A, dinv, iters, seed):
+    """Estimate of the largest eigenvalue magnitude of D^{-1} A: `iters`
+    power steps v <- w / ||w||, w = D^{-1} A v, from v = the PMIS hash
+    vector (u_i - 1/2) normalised; returns ||w|| of the last step."""
+    v = pmis_random(A.shape[0], seed) - 0.5
+    v = v / np.linalg.norm(v)
+    lam = 0.0
+    for _ in range(iters):
+        w = dinv * (A @ v)
+        lam = float(np.linalg.norm(w))
+        if lam == 0.0:
+            return 0.0
+        v = w / lam
+    return lam
+
+
+def chebyshev_bounds(lam, hi_factor=1.1, lo_fraction=0.3):
+    hi = hi_factor * lam
+    return lo_fraction * hi, hi
+
+
+def l1_jacobi_smooth(A, dinv, b, x):
+    """One l1-Jacobi step x + D^{-1}(b - A x)."""
+    return x + dinv * (b - A @ x)
+
+
+def chebyshev_smooth(A, dinv, b, x, lo, hi, degree):
+    """Chebyshev iteration of the given degree on D^{-1} A x = D^{-1} b over
+    the interval [lo, hi] (Saad, Alg. 12.1): with c = (hi+lo)/2, h =
+    (hi-lo)/2, sigma = c/h and rho_0 = 1/sigma,
+      d_0 = D^{-1}(b - A x_0) / c,  x_1 = x_0 + d_0,
+      rho_k = 1/(2 sigma - rho_{k-1}),
+      d_k = rho_k rho_{k-1} d_{k-1} + (2 rho_k / h) D^{-1}(b - A x_k),
+      x_{k+1} = x_k + d_k."""
+    c = 0.5 * (hi + lo)
+    h = 0.5 * (hi - lo)
+    sigma = c / h
+    rho = 1.0 / sigma
+    d = dinv * (b - A @ x) / c
+    x = x + d
+    for _ in range(degree - 1):
+        rho_new = 1.0 / (2.0 * sigma - rho)
+        d = rho_new * rho * d + (2.0 * rho_new / h) * (dinv * (b - A @ x))
+        x = x + d
+        rho = rho_new
+    return x
+
+
 class Level:
     def __init__(self, A):
         self.A = A.tocsr()
@@ -258,16 +317,26 @@ class Level:
         self.R = None
         self.mask = None
         self.cf = None
+        self.cheb = None  # (lo, hi) of the Chebyshev smoother
+
+    def smooth(self, b, x, H):
+        if H.smoother == "chebyshev":
+            lo, hi = self.cheb
+            return chebyshev_smooth(self.A, self.dinv, b, x, lo, hi, H.cheb_degree)
+        return l1_jacobi_smooth(self.A, self.dinv, b, x)
 
 
 class Hierarchy:
     """AMG hierarchy; ``levels[-1]`` is the coarsest."""
 
     def __init__(self, A, theta=0.25, coarse_max=128, max_levels=25, seed=0x5eed,
-                 dense_max=1024, interp="direct"):
+                 dense_max=1024, interp="direct", smoother="l1jacobi", nu1=1, nu2=1,
+                 cheb_degree=2, cheb_eig_iters=10):
         self.levels = []
         self.interp = interp
         self.dense_max = dense_max
+        self.smoother, self.nu1, self.nu2 = smoother, nu1, nu2
+        self.cheb_degree, self.cheb_eig_iters, self.seed = cheb_degree, cheb_eig_iters, seed
         A = A.tocsr()
         A.sort_indices()
         while True:
@@ -288,6 +357,13 @@ class Hierarchy:
         self.coarse_dense = last.n <= dense_max
         if self.coarse_dense:
             self.lu = sla.lu_factor(last.A.toarray())
+        self.smoother_setup()
+
+    def smoother_setup(self):
+        if self.smoother == "chebyshev":
+            for L in self.levels[:-1]:
+                lam = power_max_eig(L.A, L.dinv, self.cheb_eig_iters, self.seed)
+                L.cheb = chebyshev_bounds(lam)
 
     def coarse_solve(self, b):
         last = self.levels[-1]
@@ -297,15 +373,19 @@ class Hierarchy:
         return x + last.dinv * (b - last.A @ x)
 
     def vcycle(self, b, level=0):
-        """One V(1,1) cycle with zero initial guess."""
+        """One V(nu1, nu2) cycle with zero initial guess."""
         if level == len(self.levels) - 1:
             return self.coarse_solve(b)
         L = self.levels[level]
-        x = L.dinv * b
+        x = np.zeros_like(b)
+        for _ in range(self.nu1):
+            x = L.smooth(b, x, self)
         r = b - L.A @ x
         xc = self.vcycle(L.R @ r, level + 1)
         x = x + L.P @ xc
-        return x + L.dinv * (b - L.A @ x)
+        for _ in range(self.nu2):
+            x = L.smooth(b, x, self)
+        return x
 
     def stats(self):
         rows = [L.n for L in self.levels]
@@ -314,12 +394,15 @@ class Hierarchy:
                     operator_complexity=sum(nnz) / nnz[0], grid_complexity=sum(rows) / rows[0])
 
 
-def hierarchy_from_levels(As, Ps, dense_max=1024):
+def hierarchy_from_levels(As, Ps, dense_max=1024, smoother="l1jacobi", nu1=1, nu2=1,
+                          cheb_degree=2, cheb_eig_iters=10, seed=0x5eed):
     """An oracle Hierarchy holding given level operators and interpolations
     (used to apply the oracle's V-cycle to matrices produced elsewhere)."""
     H = Hierarchy.__new__(Hierarchy)
     H.levels = []
     H.dense_max = dense_max
+    H.smoother, H.nu1, H.nu2 = smoother, nu1, nu2
+    H.cheb_degree, H.cheb_eig_iters, H.seed = cheb_degree, cheb_eig_iters, seed
     for l, A in enumerate(As):
         L = Level(A)
         if l < len(Ps):
@@ -331,4 +414,5 @@ def hierarchy_from_levels(As, Ps, dense_max=1024):
     H.coarse_dense = last.n <= dense_max
     if H.coarse_dense:
         H.lu = sla.lu_factor(last.A.toarray())
+    H.smoother_setup()
     return H

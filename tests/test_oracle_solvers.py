@@ -320,6 +320,57 @@ def test_vcycle_symmetric_for_symmetric_matrix():
     np.testing.assert_allclose(M, M.T, rtol=0, atol=1e-12 * np.abs(M).max())
 
 
+def test_chebyshev_polynomial_on_diagonal_operator():
+    """Chebyshev smoothing of degree k on D^{-1} A over [lo, hi] (Saad,
+    Alg. 12.1) from x = 0: with A = diag(t) and D = I the error of each
+    component is multiplied by the scaled Chebyshev polynomial
+    T_k((c - t)/h) / T_k(c/h), c = (hi+lo)/2, h = (hi-lo)/2, with
+    T_2(u) = 2u^2 - 1 and T_3(u) = 4u^3 - 3u."""
+    t = np.linspace(0.0, 1.2, 25)
+    A = sp.diags(t).tocsr()
+    xt = inputs.random_vector(len(t), 50)
+    b = A @ xt
+    lo, hi = 0.3, 1.1
+    c, h = 0.5 * (hi + lo), 0.5 * (hi - lo)
+    T = {2: lambda u: 2 * u * u - 1, 3: lambda u: 4 * u ** 3 - 3 * u}
+    for k in (2, 3):
+        x = amg.chebyshev_smooth(A, np.ones(len(t)), b, np.zeros(len(t)), lo, hi, k)
+        p = T[k]((c - t) / h) / T[k](c / h)
+        np.testing.assert_allclose(xt - x, p * xt, rtol=0, atol=1e-14 * np.abs(xt).max())
+    # degree one is a damped Jacobi step with weight 1/c
+    x1 = amg.chebyshev_smooth(A, np.ones(len(t)), b, np.zeros(len(t)), lo, hi, 1)
+    np.testing.assert_allclose(x1, b / c, rtol=1e-15)
+    # power estimate on diag(t): K steps from v0 give ||t^K v0|| / ||t^(K-1) v0||
+    v0 = amg.pmis_random(len(t), 9) - 0.5
+    lam = amg.power_max_eig(A, np.ones(len(t)), 6, 9)
+    np.testing.assert_allclose(lam, np.linalg.norm(t ** 6 * v0) / np.linalg.norm(t ** 5 * v0),
+                               rtol=1e-14)
+    assert lam <= t.max()
+
+
+@pytest.mark.parametrize("smoother,nu", [("l1jacobi", 2), ("chebyshev", 1), ("chebyshev", 2)])
+def test_vcycle_variants_symmetric_and_convergent(smoother, nu):
+    """V(nu, nu) with l1-Jacobi or Chebyshev: for a symmetric matrix the cycle
+    operator B is symmetric (the post-smoother is the pre-smoother's adjoint),
+    and the stationary iteration x <- x + B(b - A x) converges: the spectral
+    radius of I - B A is below 1 and no larger than with V(1,1) l1-Jacobi."""
+    c, rp, ci, v = _small(10, 8, 2, seed=6)
+    App = blocks.block(rp, ci, v, 0, 0)
+    A = App.toarray()
+    n = App.shape[0]
+
+    def cycle_matrix(**kw):
+        H = amg.Hierarchy(App, coarse_max=15, **kw)
+        assert len(H.levels) >= 3
+        return np.column_stack([H.vcycle(e) for e in np.eye(n)])
+
+    M = cycle_matrix(smoother=smoother, nu1=nu, nu2=nu)
+    np.testing.assert_allclose(M, M.T, rtol=0, atol=1e-12 * np.abs(M).max())
+    rho = np.abs(np.linalg.eigvals(np.eye(n) - M @ A)).max()
+    rho1 = np.abs(np.linalg.eigvals(np.eye(n) - cycle_matrix() @ A)).max()
+    assert rho < 1.0 and rho <= rho1 + 1e-12, (rho, rho1)
+
+
 def test_single_level_is_exact():
     """n <= coarse_max: one level, dense LU -> AMG-GMRES converges in 1 step."""
     c, rp, ci, v = _small(5, 4, 2, seed=7)
