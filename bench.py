@@ -1,7 +1,13 @@
-"""Benchmark: time to a 1e-8 relative residual for the first Newton Jacobian
-of the 3D 128x128x64 heterogeneous workload (1,048,576 cells, 2.1M
-unknowns), block-factorisation preconditioner (Algorithm 3) with AMG
-V-cycles on A_ss and S~, right-preconditioned FGMRES(30).
+"""Benchmark: time to a 1e-8 relative residual for a Newton Jacobian of the
+3D 128x128x64 heterogeneous workload (1,048,576 cells, 2.1M unknowns),
+block-factorisation preconditioner (Algorithm 3) with AMG V-cycles on A_ss
+and S~, right-preconditioned FGMRES(30).
+
+The headline Jacobian is taken at Newton iterate 1 of the first time step,
+where every face has a pressure difference: A_ps carries the upwind
+coupling of the saturation equation.  At the initial condition (uniform
+pressure) every face is an upwind tie, A_ps is diagonal and most stored
+entries of S~ are zero; that state is timed beside it in FP64.
 
 One step = assembly of residual and Jacobian + full preconditioner setup
 (block views, S~, two AMG hierarchies) + FGMRES to ||b - Jx|| <= 1e-8 ||b||,
@@ -25,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+DS_MAX = 0.2  # Newton saturation chop
 METRIC = "time-to-1e-8 solve (FP64 vs FP32 V-cycle), V-cycle HBM GB/s, p99 latency"
 
 
@@ -39,8 +46,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--grid", type=str, default="128x128x64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-grid", type=str, default="80x80x40",
+    ap.add_argument("--cpu-grid", type=str, default="64x64x32",
                     help="grid of the oracle's bounded sample")
+    ap.add_argument("--state", choices=["newton1", "initial"], default="newton1",
+                    help="linearisation state of the headline Jacobian (the other state is "
+                         "timed in FP64 beside it)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="first run a plain device copy of this many MiB (calibrates the "
                          "FETCH_SIZE/WRITE_SIZE counters of a profiler run)")
@@ -57,40 +67,150 @@ def parse():
     ap.add_argument("--serve-active", type=int, default=8, help="requests in flight")
     ap.add_argument("--serve-load", type=float, default=0.8,
                     help="Poisson arrival rate as a fraction of the sequential FP64 throughput")
-    ap.add_argument("--study", choices=["c2", "newton"], default=None,
+    ap.add_argument("--study", choices=["c2", "newton", "simulate", "spectra"], default=None,
                     help="instead of the benchmark line, print one JSON line for a study: "
                          "c2 = first Jacobian of the 512x512 workload for P_d in {0, 0.1, 1} and "
                          "all four preconditioners; newton = 10 consecutive Newton Jacobians of "
-                         "the 256x256x128 workload, BF, rebuild vs reuse x FP64 vs FP32")
+                         "the 256x256x128 workload, BF, rebuild vs reuse x FP64 vs FP32; "
+                         "simulate = multi-step runs of the 2D stand-ins, all preconditioners; "
+                         "spectra = eigenvalues of J M^-1 with exact inner solves")
     ap.add_argument("--study-grid", type=str, default=None,
                     help="grid of the study workload (default: 512x512 / 256x256x128)")
     return ap.parse_args()
 
 
-def level0_bytes(nnz, n, w, kind, diagonals=0):
-    """Algorithmic bytes of one level-0 V-cycle kernel launch, value width w:
-    the operator once (diagonal layout: K*n values; CSR: values, int32
-    column indices and row pointers) and each dense vector once."""
-    mat = w * diagonals * n if diagonals else (w + 4) * nnz + 4 * (n + 1)
-    if kind == "pre":      # read b and D^{-1} b (CSR: dinv); write r
-        return mat + 3 * w * n
-    if kind == "post":     # read b, dinv, y; write x
-        return mat + 4 * w * n
-    raise ValueError(kind)
+def lanes_per_row(n, nnz):
+    """Lanes per row the CSR row kernels use: about eight entries per lane."""
+    avg = nnz / n if n else 1.0
+    lanes = 1
+    while lanes < 64 and 8 * lanes < avg:
+        lanes <<= 1
+    return lanes
 
 
-AMG_SRC = os.path.join(ROOT, "paper_1611_00127_amd", "csrc", "amg.hip")
+def vcycle_kernel_bytes(st, h, l, w):
+    """Algorithmic bytes per launch of each V-cycle kernel of level l of
+    hierarchy h (value width w): every array the kernel must touch, counted
+    once -- the operator (diagonal layout: K * n values; CSR: values, int32
+    columns, row pointers) and each dense vector.  Keys are the kernel-timer
+    names without the [hierarchy,level] suffix."""
+    n, nnz = int(st.rows[h][l]), int(st.nnz[h][l])
+    last = l == int(st.levels[h]) - 1
+    K = int(st.l0_diagonals[h]) if l == 0 else 0
+    mat = w * K * n if K else (w + 4) * nnz + 4 * (n + 1)
+    if last:
+        if st.coarse_dense[h]:
+            return {"vcycle_coarse": 8 * n * n + 2 * w * n}  # FP64 inverse, b, x
+        return {"vcycle_coarse": mat + 3 * w * n}           # two sweeps: dinv, b, x
+    nc, pnnz = int(st.rows[h][l + 1]), int(st.p_nnz[h][l])
+    tr = (w + 4) * pnnz
+    return {
+        "vcycle_jacobi_guess": 3 * w * n,                  # dinv, b -> g
+        "vcycle_pre_residual": mat + 3 * w * n,            # g (or dinv), b -> r
+        "vcycle_restrict": tr + 4 * (nc + 1) + w * n + w * nc,
+        "vcycle_prolong": tr + 4 * (n + 1) + w * nc + 3 * w * n,  # x_c, dinv, b -> y
+        "vcycle_post_smooth": mat + 4 * w * n,             # dinv, b, y -> x
+    }
 
 
-def kernel_digest(path=AMG_SRC, names=("clampi", "xcd_contiguous_block", "k_dia_pre2")):
-    """sha256 of the source text of the named device functions (each from
-    its name to the first closing brace at column 0): identifies the kernel
-    build that a stored counter measurement belongs to."""
+def kernel_symbol(st, h, l, timer, guess):
+    """Name of the HIP kernel behind a V-cycle timer (as rocprofv3 lists it)."""
+    n, nnz = int(st.rows[h][l]), int(st.nnz[h][l])
+    K = int(st.l0_diagonals[h]) if l == 0 else 0
+    if timer == "vcycle_pre_residual":
+        if K:
+            return f"k_dia_pre{'2' if n % 2 == 0 else ''}<double, {K}>"
+        return f"k_vc_pre{'_g' if guess else ''}<double, {lanes_per_row(n, nnz)}>"
+    if timer == "vcycle_post_smooth":
+        if K:
+            return f"k_dia_post{'2' if n % 2 == 0 else ''}<double, {K}>"
+        return f"k_vc_post<double, {lanes_per_row(n, nnz)}>"
+    if timer == "vcycle_prolong":
+        return f"k_vc_prolong<double, {lanes_per_row(n, int(st.p_nnz[h][l]))}>"
+    if timer == "vcycle_restrict":
+        return "k_csr_spmv"
+    if timer == "vcycle_jacobi_guess":
+        return "k_jacobi_guess<double>"
+    return "k_dense_gemv<double>" if st.coarse_dense[h] else "k_vc_two_sweeps<double>"
+
+
+HIER_TAGS = {"bf": ["Ass", "Schur"]}
+HIER_NAMES = {"Ass": "A_ss", "Schur": "S~"}
+
+
+def vcycle_table(tpf, st, tags, w=8):
+    """Per level of each hierarchy: rows, nnz, P entries, and for every
+    V-cycle kernel its launches, mean time (HIP events) and algorithmic
+    GB/s; per hierarchy the V-cycle's bytes and kernel time."""
+    out, kernels = [], []
+    for h, tag in enumerate(tags):
+        levels, tot_b, tot_ms, cycles = [], 0, 0.0, 0
+        for l in range(int(st.levels[h])):
+            kb = vcycle_kernel_bytes(st, h, l, w)
+            guess = tpf.tpf_kernel_stats(f"vcycle_jacobi_guess[{tag},l{l}]")[0] > 0
+            row = {"level": l, "rows": int(st.rows[h][l]), "nnz": int(st.nnz[h][l]),
+                   "p_nnz": int(st.p_nnz[h][l]), "kernels": {}}
+            lb, lms = 0, 0.0
+            for timer, b in kb.items():
+                cnt, ms = tpf.tpf_kernel_stats(f"{timer}[{tag},l{l}]")
+                if not cnt:
+                    continue
+                if l == 0 and timer == "vcycle_pre_residual":
+                    cycles = cnt
+                avg_us = 1e3 * ms / cnt
+                row["kernels"][timer] = {"launches": cnt, "avg_us": round(avg_us, 2),
+                                         "bytes": b, "gbs": round(b / (avg_us * 1e3), 1)}
+                kernels.append(dict(hier=tag, level=l, timer=timer, launches=cnt, total_ms=ms,
+                                    bytes=b, symbol=kernel_symbol(st, h, l, timer, guess)))
+                lb += b * cnt
+                lms += ms
+            row["share_of_cycle_bytes"] = lb
+            levels.append(row)
+            tot_b += lb
+            tot_ms += lms
+        for row in levels:
+            row["share_of_cycle_bytes"] = round(row["share_of_cycle_bytes"] / max(tot_b, 1), 4)
+        per_cycle_b = tot_b / max(cycles, 1)
+        per_cycle_ms = tot_ms / max(cycles, 1)
+        out.append({"hierarchy": HIER_NAMES.get(tag, tag), "levels": levels,
+                    "vcycles": cycles, "bytes_per_vcycle": int(per_cycle_b),
+                    "kernel_ms_per_vcycle": round(per_cycle_ms, 4),
+                    "kernel_gbs": round(per_cycle_b / (per_cycle_ms * 1e6), 1) if cycles else None})
+    return out, kernels
+
+
+def vcycle_wall(torch, tpf, M, h, n, reps=20, fp32=False):
+    """Mean wall time of one V-cycle of hierarchy h, from HIP events around
+    `reps` back-to-back cycles on the current stream (launch gaps included)."""
+    b = torch.ones(n, dtype=torch.float64, device="cuda")
+    x = torch.empty_like(b)
+    for _ in range(2):
+        tpf.tpf_precond_vcycle(M.M, h, b, x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        tpf.tpf_precond_vcycle(M.M, h, b, x)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+CSRC = os.path.join(ROOT, "paper_1611_00127_amd", "csrc")
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "vcycle_hbm_traffic_3d_128x128x64.json")
+
+
+def kernel_digest(names):
+    """sha256 of the source text of the named device functions, each given
+    as "file:function" under csrc/ (from the function's name to the first
+    closing brace at column 0): identifies the kernel build that a stored
+    counter measurement belongs to."""
     import hashlib
     import re
-    text = open(path).read()
     h = hashlib.sha256()
-    for nm in names:
+    for item in names:
+        fname, nm = item.split(":")
+        text = open(os.path.join(CSRC, fname)).read()
         m = re.search(r"\b" + re.escape(nm) + r"\(", text)
         if not m:
             return None
@@ -106,12 +226,11 @@ def stored_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
     WRITE_SIZE measurement (scaled by its copy-kernel calibration), or None
     when there is none or the kernel's source has changed since."""
-    path = os.path.join(ROOT, "profiles", "k_dia_d25_3d_128x128x64_hbm_traffic.json")
-    if not os.path.exists(path):
+    if not os.path.exists(TRAFFIC_JSON):
         return None
-    rec = json.load(open(path))
+    rec = json.load(open(TRAFFIC_JSON))
     k = rec["kernels"].get(kernel)
-    if k is None or k["source_sha256"] != kernel_digest(names=tuple(k["digest_of"])):
+    if k is None or k["source_sha256"] != kernel_digest(k["digest_of"]):
         return None
     kib = (k["fetch_kib_per_dispatch"] * rec["fetch_scale"]
            + k["write_kib_per_dispatch"] * rec["write_scale"])
@@ -182,11 +301,27 @@ def kernel_table(tpf, names):
     return out
 
 
-def cpu_baseline(grid):
+def host_info():
+    """CPU model and logical CPU count of the host running the benchmark."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+
+
+def cpu_baseline(grid, state):
     """The oracle (unmodified) on a bounded sample: the same workload family on
-    a smaller grid, one full step (assemble + BF setup + FGMRES to 1e-8),
-    BLAS limited to one thread; scaled by the cell ratio to the benchmark
-    grid (linear-cost assumption)."""
+    a smaller grid, one full step (assemble + BF setup + FGMRES to 1e-8) at
+    the same linearisation state, BLAS limited to one thread.  For the
+    Newton-iterate-1 state the oracle first takes its own first Newton step
+    (untimed).  Returns the time, the solve record, the sample case and the
+    oracle's solution of J x = -F there."""
     from threadpoolctl import threadpool_limits
 
     from oracle import newton
@@ -194,10 +329,35 @@ def cpu_baseline(grid):
     nx, ny, nz = (int(v) for v in grid.split("x"))
     c = inputs.config_c3(nx, ny, nz)
     with threadpool_limits(limits=1):
+        if state == "newton1":
+            x0, _, _ = newton.solve(c, "bf", rtol=1e-8)
+            c = c.replace(u=newton.update(c.u, x0, DS_MAX))
         t0 = time.perf_counter()
-        _, info, _ = newton.solve(c, "bf", rtol=1e-8)
+        x, info, _ = newton.solve(c, "bf", rtol=1e-8)
         dt = time.perf_counter() - t0
-    return dt, info, c.N
+    return dt, info, c, x
+
+
+def errors_vs_oracle(torch, tpf, driver, c, x_or):
+    """GPU solves of the sample case (same state as the oracle's) in both
+    forms: relative difference of each solution from the oracle's FP64
+    solution, and the true relative residuals."""
+    g = driver.GpuCase(c)
+    g.assemble()
+    b = g.rhs().contiguous()
+    out = {}
+    xo = np.asarray(x_or)
+    for precision, name in ((tpf.TPF_FP64, "fp64"), (tpf.TPF_FP32, "fp32_vcycle")):
+        M = driver.GpuPrecond("bf", precision)
+        M.setup(g)
+        x = torch.empty_like(b)
+        info = driver.solve(g, M, b, x, rtol=1e-8)
+        xs = x.cpu().numpy()
+        out[name] = {"rel_err_vs_oracle": float(np.linalg.norm(xs - xo) / np.linalg.norm(xo)),
+                     "relres_true": float(info.relres_true), "iterations": int(info.iterations)}
+        M.close()
+    g.close()
+    return out
 
 
 def pct(v, q):
@@ -399,6 +559,87 @@ def study_newton(torch, tpf, driver, inputs, args):
     return out
 
 
+def study_simulate(torch, tpf, driver, inputs, args):
+    """Multi-step simulations on the stand-ins of the paper's 2D experiments,
+    every preconditioner, FP64: NI, LI, LI/NI, wall time, status ('-' in the
+    paper's tables = diverged).  (1) Oil-water cross-section 100x1x20 for
+    Ex1-Ex3 with linear and Brooks-Corey P_c, 200 days at dt = 20 days
+    (Sec. 4.1 tables); (2) gravity box n x 1 x n, n in {20, 40, 80, 160},
+    three regimes (Sec. 4.2 tables); (3) the 80x80 advection regime with
+    dt in {1, 2, 4, 8} days to 8 days (Sec. 4.2 time-step table)."""
+    kinds = ("amg", "cpr1", "cpr2", "bf")
+    rows = []
+
+    def run(tag, case, t_final, dt, extra=None):
+        for kind in kinds:
+            r = driver.simulate(case, kind, t_final, dt=dt)
+            rec = {"experiment": tag, "kind": kind, "NI": r["NI"], "LI": r["LI"],
+                   "LI_per_NI": round(r["LI_per_NI"], 2), "time_s": round(r["wall_s"], 3),
+                   "status": r["status"], "steps": len(r["steps"])}
+            rec.update(extra or {})
+            log(f"[simulate] {tag} {kind}: NI {rec['NI']} LI {rec['LI']} LI/NI "
+                f"{rec['LI_per_NI']} {rec['time_s']} s {rec['status']}")
+            rows.append(rec)
+
+    for ex in (1, 2, 3):
+        for pcm, pname in ((inputs.PC_LINEAR, "linear"), (inputs.PC_BROOKS_COREY, "brooks-corey")):
+            run(f"oil-water ex{ex} {pname}", inputs.oil_water_xz(ex, pcm), 200.0, 20.0)
+    for regime, (_, dt, tf) in inputs.GRAVITY_REGIMES.items():
+        for n in (20, 40, 80, 160):
+            run(f"gravity {regime} {n}x{n}", inputs.gravity_box_xz(n, regime), tf, dt)
+    for dt in (1.0, 2.0, 4.0, 8.0):
+        run(f"gravity advection 80x80 dt {dt:g}", inputs.gravity_box_xz(80, "advection"), 8.0,
+            dt, {"NI_per_step": None})
+        for r in rows[-len(kinds):]:
+            r["NI_per_step"] = round(r["NI"] / max(r["steps"], 1), 2)
+    return {"study": "simulate", "precision": "f64", "newton_tol": 1e-6, "rtol": 1e-8,
+            "results": rows}
+
+
+def study_spectra(torch, tpf, driver, inputs, args):
+    """Eigenvalues of J M^{-1} with exact inner solves (Sec. 4.3) from the GPU
+    preconditioners, for the diffusion- (Ex1) and advection-dominated (Ex2)
+    oil-water stand-in with linear P_c (50x1x10, the first Jacobian)."""
+    rows = []
+    nx, nz = (int(v) for v in (args.study_grid or "50x10").split("x"))
+    for ex, regime in ((1, "diffusion"), (2, "advection")):
+        c = inputs.oil_water_xz(ex, inputs.PC_LINEAR, nx=nx, nz=nz)
+        g = driver.GpuCase(c)
+        g.assemble()
+        for kind in ("cpr1", "cpr2", "bf"):
+            M = driver.GpuPrecond(kind, **driver.exact_inner_opts(c.N))
+            M.setup(g)
+            ev = np.linalg.eigvals(driver.preconditioned_matrix(g, M))
+            a = np.abs(ev)
+            rec = {"regime": regime, "kind": kind, "n": int(len(ev)),
+                   "min_abs": float(a.min()), "max_abs": float(a.max()),
+                   "frac_abs_below_0.1": float(np.mean(a < 0.1)),
+                   "frac_within_0.5_of_1": float(np.mean(np.abs(ev - 1.0) < 0.5)),
+                   "re_range": [float(ev.real.min()), float(ev.real.max())],
+                   "max_abs_imag": float(np.abs(ev.imag).max())}
+            log(f"[spectra] {regime} {kind}: |lambda| in [{rec['min_abs']:.3g}, "
+                f"{rec['max_abs']:.3g}], {100 * rec['frac_abs_below_0.1']:.1f}% below 0.1")
+            rows.append(rec)
+            M.close()
+        g.close()
+    return {"study": "spectra", "grid": f"{nx}x1x{nz}", "inner": "exact (dense inverse)",
+            "results": rows}
+
+
+def linearisation_state(torch, driver, g, state):
+    """Device copy of the state the benchmark Jacobian is taken at: the
+    initial condition of the time step, or Newton iterate 1 (one FP64 BF
+    Newton step from it, saturation chop DS_MAX), computed on the GPU."""
+    if state == "initial":
+        return g.u.clone()
+    return driver.newton_states(g, 2, ds_max=DS_MAX)[1].clone()
+
+
+def state_text(state):
+    return ("Newton iterate 1 of the first time step" if state == "newton1"
+            else "initial condition of the time step (uniform P_w = 0, S_n = 0.2)")
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -411,7 +652,8 @@ def main():
     tpf.init()
     tpf.tpf_set_graphs(args.graphs)
     if args.study:
-        fn = study_c2 if args.study == "c2" else study_newton
+        fn = {"c2": study_c2, "newton": study_newton, "simulate": study_simulate,
+              "spectra": study_spectra}[args.study]
         print(json.dumps(fn(torch, tpf, driver, inputs, args)), flush=True)
         return
     if args.copy_probe > 0:
@@ -427,64 +669,84 @@ def main():
     log(f"[bench] generating workload {nx}x{ny}x{nz}")
     c = inputs.config_c3(nx, ny, nz)
     g = driver.GpuCase(c)
+    states = {st: linearisation_state(torch, driver, g, st) for st in ("newton1", "initial")}
+    head, other = args.state, ("initial" if args.state == "newton1" else "newton1")
+    g.u.copy_(states[head])
     torch.cuda.synchronize()
-    log("[bench] FP64 form")
+    log(f"[bench] FP64 form at {head}")
     M64, x64, r64 = run_form(torch, tpf, driver, g, tpf.TPF_FP64, args.steps, args.warmup, False)
-    # one more step with every kernel bracketed by HIP events, for the
-    # kernel table and the roofline (kept out of the timed steps above)
+    # one more step per form with every kernel bracketed by HIP events, for the
+    # per-level V-cycle table and the roofline (kept out of the timed steps)
     log("[bench] FP64 instrumented step")
     Mi, _, _ = run_form(torch, tpf, driver, g, tpf.TPF_FP64, 1, 0, True)
+    st64 = Mi.stats()
+    vc64, kern64 = vcycle_table(tpf, st64, HIER_TAGS["bf"], 8)
+    ktab = kernel_table(tpf, ["cgs2", "bcsr_spmv", "bf_rhs", "assemble", "precond_apply"])
+    walls = []
+    for h in range(st64.n_hier):
+        ms = vcycle_wall(torch, tpf, Mi, h, int(st64.rows[h][0]))
+        walls.append(ms)
+        vc64[h]["wall_ms_per_vcycle"] = round(ms, 4)
+        vc64[h]["wall_gbs"] = round(vc64[h]["bytes_per_vcycle"] / (ms * 1e6), 1)
     Mi.close()
-    names = []
-    for h, tag in enumerate(["Ass", "Schur"]):
-        for k in ["vcycle_pre_residual", "vcycle_post_smooth", "vcycle_restrict", "vcycle_prolong"]:
-            names.append(f"{k}[{tag},l0]")
-    names += ["cgs2", "bcsr_spmv", "bf_rhs", "assemble", "precond_apply"]
-    ktab = kernel_table(tpf, names)
     log("[bench] FP32-V-cycle form")
     M32, x32, r32 = run_form(torch, tpf, driver, g, tpf.TPF_FP32, args.steps, args.warmup, False)
-    # the two forms must agree at the stated accuracy
     err = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
-
-    # roofline of the dominant V-cycle kernel (largest summed time)
-    vk = {k: v for k, v in ktab.items() if k.startswith("vcycle_")}
-    dom = max(vk, key=lambda k: vk[k][1])
-    cnt, ms = vk[dom]
-    h = 1 if "Schur" in dom else 0
-    nnz, n = r64["l0_nnz"][h], r64["l0_rows"][h]
-    kind = "pre" if "pre_residual" in dom else "post"
-    bytes_per_launch = level0_bytes(nnz, n, 8, kind, r64["l0_diagonals"][h])
-    avg_ms = ms / cnt
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    K = r64["l0_diagonals"][h]
-    gpu_kernel = (f"k_dia_{kind}{'2' if n % 2 == 0 else ''}<double, {K}>" if K
-                  else f"k_vc_{kind}<double, *>")
-    roof = {"kernel": gpu_kernel, "timer": dom,
-            "layout": f"diagonal, {K} diagonals" if K else "csr",
-            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": stored_traffic(gpu_kernel),
-            "avg_launch_us": round(avg_ms * 1e3, 2), "launches": cnt,
-            "algorithmic_bytes_per_launch": bytes_per_launch}
-
+    log("[bench] FP32 instrumented step")
+    Mi, _, _ = run_form(torch, tpf, driver, g, tpf.TPF_FP32, 1, 0, True)
+    vc32, _ = vcycle_table(tpf, Mi.stats(), HIER_TAGS["bf"], 4)
+    Mi.close()
+    tpf.tpf_kernel_stats_reset()
     M64.close()
     M32.close()
+    log(f"[bench] FP64 form at {other}")
+    g.u.copy_(states[other])
+    Mo, _, ro = run_form(torch, tpf, driver, g, tpf.TPF_FP64, max(1, min(args.steps, 5)), 1, False)
+    Mo.close()
+    ro = {k: ro[k] for k in ("ms_per_step", "assemble_ms", "setup_ms", "solve_ms", "iterations",
+                             "relres_true", "converged", "op_complexity")}
     g.close()
+
+    # roofline of the dominant V-cycle kernel: the largest summed time over
+    # every level of both hierarchies (FP64 form)
+    dom = max(kern64, key=lambda k: k["total_ms"])
+    avg_ms = dom["total_ms"] / dom["launches"]
+    achieved = dom["bytes"] / (avg_ms * 1e-3) / 1e9
+    roof = {"kernel": dom["symbol"],
+            "timer": f"{dom['timer']}[{dom['hier']},l{dom['level']}]",
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": stored_traffic(dom["symbol"]),
+            "avg_launch_us": round(avg_ms * 1e3, 2), "launches": dom["launches"],
+            "algorithmic_bytes_per_launch": dom["bytes"],
+            "share_of_vcycle_kernel_time": round(
+                dom["total_ms"] / sum(k["total_ms"] for k in kern64), 4)}
+    tot_b = sum(v["bytes_per_vcycle"] for v in vc64)
+    tot_ms = sum(walls)
+    vgbs = {"fp64_wall_gbs_bf_apply_vcycles": round(tot_b / (tot_ms * 1e6), 1),
+            "fp64_kernel_gbs_bf_apply_vcycles": round(
+                tot_b / (sum(v["kernel_ms_per_vcycle"] for v in vc64) * 1e6), 1)}
+
     serving = None
     if not args.no_serve:
         log("[bench] serving stream")
         tpf.tpf_kernel_timing(0)
         serving = serve_stream(torch, tpf, driver, inputs, args)
 
-    cpu = None
+    cpu, vs_oracle = None, None
     if not args.no_cpu_baseline:
-        log(f"[bench] CPU baseline: oracle on {args.cpu_grid}")
-        dt, info, ncpu = cpu_baseline(args.cpu_grid)
-        scale = c.N / ncpu
+        log(f"[bench] CPU baseline: oracle on {args.cpu_grid} at {head}")
+        dt, info, cs, xo = cpu_baseline(args.cpu_grid, head)
+        scale = c.N / cs.N
         cpu = {"value": round(dt * scale * 1e3, 1), "unit": "ms", "cores": 1, "kind": "oracle",
                "sample": f"one full step (assemble + BF setup + FGMRES to 1e-8, "
-                         f"{info['iterations']} its) of the same workload on {args.cpu_grid} "
-                         f"({ncpu} cells) in {dt:.1f} s, scaled x{scale:.0f} by cell count"}
+                         f"{info['iterations']} its) of the same workload family on "
+                         f"{args.cpu_grid} ({cs.N} cells) at the {state_text(head)} (the "
+                         f"oracle's own), one thread, {dt:.1f} s, scaled x{scale:.0f} by "
+                         f"cell count",
+               "host": host_info()}
+        vs_oracle = dict(errors_vs_oracle(torch, tpf, driver, cs, xo), grid=args.cpu_grid,
+                         oracle_iterations=int(info["iterations"]))
 
     out = {
         "metric": METRIC,
@@ -500,12 +762,18 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"3d-{nx}x{ny}x{nz} log-normal sigma=3 kz/kx=0.1 layered, "
-                               f"Brooks-Corey lambda=2 Pd=0.5, five-spot, first Newton Jacobian",
+                               f"Brooks-Corey lambda=2 Pd=0.5, five-spot, CFL 10, Jacobian at "
+                               f"the {state_text(head)}",
                    "cells": c.N, "unknowns": 2 * c.N, "preconditioner": "bf",
                    "krylov": "fgmres(30)", "rtol": 1e-8},
         "fp64": r64,
         "fp32_vcycle": dict(r32, rel_diff_vs_fp64=err,
                             speedup_vs_fp64=round(r64["ms_per_step"] / r32["ms_per_step"], 3)),
+        "errors_vs_fp64_oracle": vs_oracle,
+        f"fp64_at_{other}": ro,
+        "vcycle_gbs": vgbs,
+        "vcycle_levels_fp64": vc64,
+        "vcycle_levels_fp32": vc32,
         "roofline": roof,
         "kernels_ms": {k: {"launches": v[0], "total_ms": round(v[1], 3),
                            "avg_us": round(1e3 * v[1] / v[0], 2)} for k, v in ktab.items()},

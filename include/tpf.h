@@ -147,6 +147,12 @@ int tpf_spmv(const tpf_jacobian* J, const double* x, double* y, void* stream);
 int tpf_newton_update(tpf_problem* p, double* u, const double* delta, double alpha,
                       double ds_max, void* stream);
 
+/* Euclidean norm of a device FP64 vector of n entries into *out (host): the
+ * Newton stopping test ||F(u_k)|| <= tol of Sec. 4.1 solver settings.  The
+ * sum of squares is reduced in a fixed order (deterministic).  Synchronises
+ * the stream. */
+int tpf_norm2(const double* x, int64_t n, double* out, void* stream);
+
 /* ---- preconditioners (Sec. 3.2-3.4) ------------------------------------ */
 #define TPF_PREC_AMG 0   /* one V-cycle on the point-ordered scalar J (Sec. 3.2) */
 #define TPF_PREC_CPR1 1  /* Algorithm 1 (combinative), block ILU(0) + V-cycle on A_pp */
@@ -157,6 +163,11 @@ int tpf_newton_update(tpf_problem* p, double* u, const double* delta, double alp
 #define TPF_INTERP_AUTO 0    /* extended+i for S~ and A_pp; direct for A_ss and the scalar J */
 #define TPF_INTERP_DIRECT 1  /* direct (distance-one) interpolation everywhere */
 #define TPF_INTERP_EXTI 2    /* extended+i (distance-two) interpolation everywhere */
+
+#define TPF_SMOOTH_L1_JACOBI 0  /* x <- x + D^{-1}(b - A x), D the l1 diagonal */
+#define TPF_SMOOTH_CHEBYSHEV 1  /* Chebyshev polynomial of degree cheb_degree in D^{-1} A on
+                                   [0.3 hi, hi], hi = 1.1 x a 10-step power estimate of its
+                                   largest eigenvalue */
 
 #define TPF_FP64 0       /* hierarchy and V-cycle in FP64 */
 #define TPF_FP32 1       /* hierarchy stored and V-cycle/ILU solves run in FP32; coarsest in FP64 */
@@ -174,6 +185,10 @@ typedef struct tpf_precond_opts {
   int exti_route;       /* tests: 0 picks each F row's extended+i kernel by the row's size;
                            r in 1..8 starts the search at class r-1 (0-5 flattened wavefront
                            kernels, 6 wide wavefront, 7 one thread per row) */
+  int smoother;         /* TPF_SMOOTH_* (l1-Jacobi); one V-cycle per inner solve, Sec. 4.1 */
+  int nu1, nu2;         /* pre- and post-smoothing steps per level, each in [0, 4], sum >= 1
+                           (1, 1); a Chebyshev step is one polynomial */
+  int cheb_degree;      /* Chebyshev polynomial degree in [1, 8] (2) */
 } tpf_precond_opts;
 /* Fills opts with the defaults above for the given kind. */
 int tpf_precond_default_opts(int kind, tpf_precond_opts* opts);
@@ -196,11 +211,14 @@ typedef struct tpf_hier_stats {
   int levels[3];
   int64_t rows[3][TPF_MAX_LEVELS];
   int64_t nnz[3][TPF_MAX_LEVELS];
+  int64_t p_nnz[3][TPF_MAX_LEVELS];    /* entries of P (level l -> l+1; R = P^T has as many);
+                                          0 on the coarsest level */
   double operator_complexity[3];
   double grid_complexity[3];
   int coarse_dense[3];
   int l0_diagonals[3];                 /* level-0 smoother layout: number of stored diagonals
                                           (diagonal layout), 0 = CSR */
+  int coarse_smooth_sweeps[3];         /* coarsest level: 0 = dense solve, else l1-Jacobi sweeps */
   size_t device_bytes;                 /* bytes held by the preconditioner */
   size_t hier_bytes[3];                /* of which each hierarchy (levels, transfer operators,
                                           work vectors, coarsest inverse) */

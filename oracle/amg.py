@@ -320,7 +320,8 @@ class Level:
         self.cheb = None  # (lo, hi) of the Chebyshev smoother
 
     def smooth(self, b, x, H):
-        if H.smoother == "chebyshev":
+        # a zero eigenvalue estimate (D^{-1} A = 0) leaves l1-Jacobi sweeps
+        if H.smoother == "chebyshev" and self.cheb[1] > 0.0:
             lo, hi = self.cheb
             return chebyshev_smooth(self.A, self.dinv, b, x, lo, hi, H.cheb_degree)
         return l1_jacobi_smooth(self.A, self.dinv, b, x)

@@ -1317,6 +1317,76 @@ __global__ void __launch_bounds__(256) k_vc_two_sweeps(int n, const int* __restr
   }
 }
 
+// One sweep of the generic smoothers: r = D^{-1}(b - A x), d <- cd d + cr r
+// (d may be null: Jacobi sweeps keep no direction), x_new = x + d.  x == null
+// stands for the zero iterate.  l1-Jacobi: cd = 0, cr = 1; Chebyshev: the
+// three-term recurrence's coefficients.
+template <class T, int LPR>
+__global__ void __launch_bounds__(256) k_smooth_sweep(int n, const int* __restrict__ rp,
+                                                      const int* __restrict__ ci,
+                                                      const T* __restrict__ v,
+                                                      const T* __restrict__ dinv,
+                                                      const T* __restrict__ b,
+                                                      const T* __restrict__ x, T* __restrict__ d,
+                                                      T cd, T cr, T* __restrict__ xn) {
+  int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int row = int(gid / LPR), lane = int(gid % LPR);
+  if (row >= n) return;
+  T sum = T(0);
+  if (x) sum = row_dot<T, LPR>(row, lane, rp, ci, v, [&](int j) { return x[j]; });
+  if (lane == 0) {
+    const T r = dinv[row] * (b[row] - sum);
+    T dn = cr * r;
+    if (d) {
+      if (cd != T(0)) dn = cd * d[row] + dn;
+      d[row] = dn;
+    }
+    xn[row] = x ? x[row] + dn : dn;
+  }
+}
+
+// y = x + P x_c (x == null: the zero iterate)
+template <class T, int LPR>
+__global__ void __launch_bounds__(256) k_vc_prolong_add(int n, const int* __restrict__ prp,
+                                                        const int* __restrict__ pci,
+                                                        const T* __restrict__ pv,
+                                                        const T* __restrict__ x,
+                                                        const T* __restrict__ xc,
+                                                        T* __restrict__ y) {
+  int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int row = int(gid / LPR), lane = int(gid % LPR);
+  if (row >= n) return;
+  T sum = row_dot<T, LPR>(row, lane, prp, pci, pv, [&](int c) { return xc[c]; });
+  if (lane == 0) y[row] = x ? x[row] + sum : sum;
+}
+
+// Power iteration for the Chebyshev interval: the start vector (the PMIS
+// hash u_i - 1/2), w = D^{-1} A v, v = w / s.
+__global__ void k_hash_centered(int n, uint64_t seed, double* __restrict__ v) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  v[i] = double(splitmix64(seed ^ uint64_t(i)) >> 40) * 0x1p-24 - 0.5;
+}
+
+template <int LPR>
+__global__ void __launch_bounds__(256) k_dinv_spmv(int n, const int* __restrict__ rp,
+                                                   const int* __restrict__ ci,
+                                                   const double* __restrict__ v,
+                                                   const double* __restrict__ dinv,
+                                                   const double* __restrict__ x,
+                                                   double* __restrict__ w) {
+  int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int row = int(gid / LPR), lane = int(gid % LPR);
+  if (row >= n) return;
+  double sum = row_dot<double, LPR>(row, lane, rp, ci, v, [&](int j) { return x[j]; });
+  if (lane == 0) w[row] = dinv[row] * sum;
+}
+
+__global__ void k_div_scalar(int n, const double* __restrict__ w, double s, double* __restrict__ v) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = w[i] / s;
+}
+
 // x = Ainv b in FP64 (one wavefront per row)
 template <class T>
 __global__ void __launch_bounds__(256) k_dense_gemv(int n, const double* __restrict__ Ainv,
@@ -1798,6 +1868,7 @@ void Hierarchy::finish_levels(hipStream_t st) {
     L.t_restrict = "vcycle_restrict" + sfx;
     L.t_prolong = "vcycle_prolong" + sfx;
     L.t_post = "vcycle_post_smooth" + sfx;
+    L.t_coarse = "vcycle_coarse" + sfx;
     L.dinv.ensure(n, st);
     {
       const int lpr = lanes_per_row(n, L.A.nnz);
@@ -1812,6 +1883,13 @@ void Hierarchy::finish_levels(hipStream_t st) {
     if (&L != lv[0].get()) {
       L.b.ensure(n, st);
       L.x.ensure(n, st);
+    }
+    const bool generic = !o.fused_cycle() && l + 1 < lv.size();
+    if (generic) {
+      L.xa.ensure(n, st);
+      L.xb.ensure(n, st);
+      if (o.smoother == 1) L.dd.ensure(n, st);
+      if (o.smoother == 1) chebyshev_setup(L, st);
     }
     if (o.fp32) {
       L.Av32.ensure(L.A.nnz, st);
@@ -1829,6 +1907,11 @@ void Hierarchy::finish_levels(hipStream_t st) {
       if (&L != lv[0].get()) {
         L.b32.ensure(n, st);
         L.x32.ensure(n, st);
+      }
+      if (generic) {
+        L.xa32.ensure(n, st);
+        L.xb32.ensure(n, st);
+        if (o.smoother == 1) L.dd32.ensure(n, st);
       }
     }
   }
@@ -1864,6 +1947,89 @@ void Hierarchy::finish_levels(hipStream_t st) {
     }
   }
   coarse_setup(st);
+}
+
+// Interval of the Chebyshev smoother on D^{-1} A: hi = 1.1 lambda^, lo = 0.3 hi,
+// lambda^ from cheb_eig_iters power steps started at the PMIS hash vector
+// (the estimate is ||w|| of the last step).  A zero estimate (D^{-1} A = 0)
+// leaves the level with l1-Jacobi sweeps.
+void Hierarchy::chebyshev_setup(Level& L, hipStream_t st) {
+  const int n = L.A.nrows;
+  Buf<double> v(n, st), w(n, st);
+  k_hash_centered<<<grid_for(n, 256), 256, 0, st>>>(n, o.seed, v.p);
+  TPF_CHECK_LAUNCH();
+  const double nv = nrm2_host(v.p, n, st);
+  double lam = 0.0;
+  if (nv > 0.0) {
+    k_div_scalar<<<grid_for(n, 256), 256, 0, st>>>(n, v.p, nv, v.p);
+    TPF_CHECK_LAUNCH();
+    const int lpr = lanes_per_row(n, L.A.nnz);
+    for (int it = 0; it < o.cheb_eig_iters; ++it) {
+      DISPATCH_LPR(lpr, LL, {
+        k_dinv_spmv<LL><<<grid_for(int64_t(n) * LL, 256), 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p,
+                                                                         L.A.v.p, L.dinv.p, v.p,
+                                                                         w.p);
+      });
+      TPF_CHECK_LAUNCH();
+      lam = nrm2_host(w.p, n, st);
+      if (lam == 0.0) break;
+      k_div_scalar<<<grid_for(n, 256), 256, 0, st>>>(n, w.p, lam, v.p);
+      TPF_CHECK_LAUNCH();
+    }
+  }
+  L.cheb_hi = 1.1 * lam;
+  L.cheb_lo = 0.3 * L.cheb_hi;
+}
+
+// `steps` smoothing steps (each one l1-Jacobi sweep, or one Chebyshev
+// polynomial of degree cheb_degree) on L from x0 (null: the zero iterate);
+// the final iterate goes to `out`, the intermediate ones alternate between
+// spare0 and spare1 (all distinct from x0 and out).
+template <class T>
+const T* Hierarchy::smooth(Level& L, const T* b, const T* x0, T* out, T* spare0, T* spare1,
+                           int steps, hipStream_t st) {
+  const int n = L.A.nrows;
+  const bool cheb = o.smoother == 1 && L.cheb_hi > 0.0;
+  const int per = cheb ? o.cheb_degree : 1;
+  const int sweeps = steps * per;
+  if (sweeps == 0) {
+    if (x0)
+      copy(out, x0, n, st);
+    else
+      fill(out, T(0), n, st);
+    return out;
+  }
+  const T* Av = vals_of<T>(L.A, L.Av32);
+  const T* dinv = dinv_of<T>(L);
+  T* d = cheb ? work<T>(L.dd, L.dd32) : nullptr;
+  const int lpr = lanes_per_row(n, L.A.nnz);
+  const unsigned blocks = grid_for(int64_t(n) * lpr, 256);
+  const double c = 0.5 * (L.cheb_hi + L.cheb_lo), h = 0.5 * (L.cheb_hi - L.cheb_lo);
+  const double sigma = cheb ? c / h : 0.0;
+  const T* cur = x0;
+  double rho = 0.0;
+  for (int k = 0; k < sweeps; ++k) {
+    T* nxt = k == sweeps - 1 ? out : (k % 2 == 0 ? spare0 : spare1);
+    double cd = 0.0, cr = 1.0;
+    if (cheb) {
+      if (k % per == 0) {  // a new polynomial: d_0 = r / c
+        rho = 1.0 / sigma;
+        cr = 1.0 / c;
+      } else {
+        const double rn = 1.0 / (2.0 * sigma - rho);
+        cd = rn * rho;
+        cr = 2.0 * rn / h;
+        rho = rn;
+      }
+    }
+    DISPATCH_LPR(lpr, LL, {
+      k_smooth_sweep<T, LL><<<blocks, 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, Av, dinv, b, cur, d,
+                                                    T(cd), T(cr), nxt);
+    });
+    TPF_CHECK_LAUNCH();
+    cur = nxt;
+  }
+  return out;
 }
 
 void Hierarchy::coarse_setup(hipStream_t st) {
@@ -1902,7 +2068,8 @@ size_t Hierarchy::bytes() const {
     const Level& L = *Lp;
     b += L.A.bytes() + L.dinv.bytes() + L.mask.bytes() + L.S.bytes() + L.cf.bytes() + L.P.bytes() +
          L.R.bytes() + L.T.bytes() + L.Av32.bytes() + L.Pv32.bytes() + L.Rv32.bytes() +
-         L.dinv32.bytes() + L.r.bytes() + L.y.bytes() + L.b.bytes() + L.x.bytes() +
+         L.dinv32.bytes() + L.r.bytes() + L.y.bytes() + L.b.bytes() + L.x.bytes() + L.xa.bytes() +
+         L.xb.bytes() + L.dd.bytes() + L.xa32.bytes() + L.xb32.bytes() + L.dd32.bytes() +
          L.r32.bytes() + L.y32.bytes() + L.b32.bytes() + L.x32.bytes();
   }
   return b;
@@ -1921,6 +2088,7 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st) {
   unsigned blocks = grid_for(int64_t(n) * lpr, 256);
   bool last = l == int(lv.size()) - 1;
   if (last) {
+    TimedScope ts(L.t_coarse.c_str(), st);
     if (coarse_dense) {
       k_dense_gemv<T><<<grid_for(int64_t(n) * kWave, 256), 256, 0, st>>>(n, Ainv.p, b, x);
     } else {
@@ -1936,6 +2104,40 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st) {
   T* y = work<T>(L.y, L.y32);
   T* bc = work<T>(C.b, C.b32);
   T* xc = work<T>(C.x, C.x32);
+  if (!o.fused_cycle()) {
+    // V(nu1, nu2) with the generic sweeps (CSR operator on every level)
+    T* xa = work<T>(L.xa, L.xa32);
+    T* xb = work<T>(L.xb, L.xb32);
+    const T* xpre = nullptr;
+    {
+      TimedScope ts(L.t_pre.c_str(), st);
+      if (o.nu1 > 0) xpre = smooth<T>(L, b, nullptr, xa, xb, r, o.nu1, st);
+      if (xpre) {
+        DISPATCH_LPR(lpr, LL, {
+          k_vc_pre_g<T, LL><<<blocks, 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, Av, xpre, b, r);
+        });
+        TPF_CHECK_LAUNCH();
+      } else {
+        copy(r, b, n, st);
+      }
+    }
+    csr_spmv<T>(ref_with<T>(L.R, vals_of<T>(L.R, L.Rv32)), r, bc, st, L.t_restrict.c_str());
+    vcycle_level<T>(l + 1, bc, xc, st);
+    {
+      const int plpr = lanes_per_row(n, L.P.nnz);
+      TimedScope ts(L.t_prolong.c_str(), st);
+      DISPATCH_LPR(plpr, LL, {
+        k_vc_prolong_add<T, LL><<<grid_for(int64_t(n) * LL, 256), 256, 0, st>>>(
+            n, L.P.rp.p, L.P.ci.p, vals_of<T>(L.P, L.Pv32), xpre, xc, y);
+      });
+      TPF_CHECK_LAUNCH();
+    }
+    {
+      TimedScope ts(L.t_post.c_str(), st);
+      smooth<T>(L, b, y, x, xa, xb, o.nu2, st);
+    }
+    return;
+  }
   bool dia = l == 0 && dia0.ok;
   // the two-row diagonal kernels read pairs: n even and every vector aligned
   auto al2 = [](const void* p) { return reinterpret_cast<uintptr_t>(p) % (2 * sizeof(T)) == 0; };
@@ -2076,6 +2278,10 @@ void Hierarchy::vcycle(const T* b, T* x, hipStream_t st) {
   TPF_HIP(hipGraphLaunch(g.exec, st));
 }
 
+template const double* Hierarchy::smooth<double>(Level&, const double*, const double*, double*,
+                                                 double*, double*, int, hipStream_t);
+template const float* Hierarchy::smooth<float>(Level&, const float*, const float*, float*, float*,
+                                               float*, int, hipStream_t);
 template void Hierarchy::vcycle<double>(const double*, double*, hipStream_t);
 template void Hierarchy::vcycle<float>(const float*, float*, hipStream_t);
 

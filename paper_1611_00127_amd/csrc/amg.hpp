@@ -16,6 +16,13 @@ struct AmgOpts {
   bool fp32 = false;
   bool ext_i = false;   // extended+i instead of direct interpolation
   int exti_first = 0;   // extended+i rows start the kernel-class search here (tests)
+  int smoother = 0;     // 0 l1-Jacobi, 1 Chebyshev on D^{-1} A
+  int nu1 = 1, nu2 = 1; // pre- and post-smoothing steps
+  int cheb_degree = 2;
+  int cheb_eig_iters = 10;  // power steps estimating the top eigenvalue of D^{-1} A
+  // V(1,1) l1-Jacobi runs the fused smoother kernels; anything else the
+  // generic sweeps
+  bool fused_cycle() const { return smoother == 0 && nu1 == 1 && nu2 == 1; }
 };
 
 struct Level {
@@ -28,12 +35,17 @@ struct Level {
                         // for numeric refresh)
   // FP32 copies of the values (patterns shared)
   Buf<float> Av32, Pv32, Rv32, dinv32;
+  // generic smoothing sweeps: two iterates and the Chebyshev direction, and
+  // the Chebyshev interval [cheb_lo, cheb_hi] of D^{-1} A
+  Buf<double> xa, xb, dd;
+  Buf<float> xa32, xb32, dd32;
+  double cheb_lo = 0.0, cheb_hi = 0.0;
   // workspace: r, y always; b, x on levels >= 1
   Buf<double> r, y, b, x;
   Buf<float> r32, y32, b32, x32;
   int64_t pmis_rounds = 0;
   // kernel-timer labels of this level (persistent storage for TimedScope)
-  std::string t_pre, t_guess, t_restrict, t_prolong, t_post;
+  std::string t_pre, t_guess, t_restrict, t_prolong, t_post, t_coarse;
 };
 
 // Level-0 operator in diagonal (stencil) layout: value of row i on diagonal
@@ -85,6 +97,10 @@ struct Hierarchy {
  private:
   void finish_levels(hipStream_t st);
   void coarse_setup(hipStream_t st);
+  void chebyshev_setup(Level& L, hipStream_t st);
+  template <class T>
+  const T* smooth(Level& L, const T* b, const T* x0, T* out, T* spare0, T* spare1, int steps,
+                  hipStream_t st);
   template <class T>
   void vcycle_level(int l, const T* b, T* x, hipStream_t st);
 };

@@ -751,6 +751,10 @@ AmgOpts amg_opts(const tpf_precond_opts& o, bool pressure_like) {
   a.dense_max = o.dense_max;
   a.seed = o.hash_seed;
   a.fp32 = o.precision == TPF_FP32;
+  a.smoother = o.smoother;
+  a.nu1 = o.nu1;
+  a.nu2 = o.nu2;
+  a.cheb_degree = o.cheb_degree;
   return a;
 }
 
@@ -1018,6 +1022,10 @@ int tpf_precond_default_opts(int kind, tpf_precond_opts* o) {
     o->interp = TPF_INTERP_AUTO;
     o->hash_seed = 0x5eed;
     o->exti_route = 0;
+    o->smoother = TPF_SMOOTH_L1_JACOBI;
+    o->nu1 = 1;
+    o->nu2 = 1;
+    o->cheb_degree = 2;
   });
 }
 
@@ -1037,6 +1045,12 @@ int tpf_precond_create(const tpf_precond_opts* o, tpf_precond** out) {
                 "unknown interpolation");
     TPF_REQUIRE(o->exti_route >= 0 && o->exti_route <= 8, TPF_ERR_INVALID_ARG,
                 "exti_route must be in [0, 8]");
+    TPF_REQUIRE(o->smoother == TPF_SMOOTH_L1_JACOBI || o->smoother == TPF_SMOOTH_CHEBYSHEV,
+                TPF_ERR_INVALID_ARG, "unknown smoother %d", o->smoother);
+    TPF_REQUIRE(o->nu1 >= 0 && o->nu1 <= 4 && o->nu2 >= 0 && o->nu2 <= 4 && o->nu1 + o->nu2 >= 1,
+                TPF_ERR_INVALID_ARG, "nu1, nu2 must be in [0, 4] with nu1 + nu2 >= 1");
+    TPF_REQUIRE(o->cheb_degree >= 1 && o->cheb_degree <= 8, TPF_ERR_INVALID_ARG,
+                "cheb_degree must be in [1, 8]");
     auto* M = new tpf_precond();
     M->o = *o;
     *out = M;
@@ -1216,6 +1230,7 @@ int tpf_precond_stats(const tpf_precond* M, tpf_hier_stats* out) {
       for (int l = 0; l < H.levels(); ++l) {
         out->rows[h][l] = H.lv[l]->A.nrows;
         out->nnz[h][l] = H.lv[l]->A.nnz;
+        out->p_nnz[h][l] = l + 1 < H.levels() ? H.lv[l]->P.nnz : 0;
         if (l == 0) {
           nnz0 = double(H.lv[l]->A.nnz);
           rows0 = double(H.lv[l]->A.nrows);
@@ -1227,6 +1242,7 @@ int tpf_precond_stats(const tpf_precond* M, tpf_hier_stats* out) {
       out->grid_complexity[h] = srows / rows0;
       out->coarse_dense[h] = H.coarse_dense;
       out->l0_diagonals[h] = H.dia0.ok ? H.dia0.K : 0;
+      out->coarse_smooth_sweeps[h] = H.coarse_dense ? 0 : 2;
     }
     out->device_bytes = M->bytes();
     for (int h = 0; h < M->n_hier; ++h) out->hier_bytes[h] = M->H[h]->bytes();

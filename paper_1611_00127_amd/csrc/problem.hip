@@ -693,4 +693,11 @@ int tpf_newton_update(tpf_problem* p, double* u, const double* du, double alpha,
   });
 }
 
+int tpf_norm2(const double* x, int64_t n, double* out, void* stream) {
+  return guarded([&] {
+    TPF_REQUIRE(out && n >= 0 && (n == 0 || x), TPF_ERR_INVALID_ARG, "null argument");
+    *out = n == 0 ? 0.0 : nrm2_host(x, n, static_cast<hipStream_t>(stream));
+  });
+}
+
 }  // extern "C"

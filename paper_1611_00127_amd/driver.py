@@ -118,7 +118,7 @@ def newton_sequence(gcase, M, n_jacobians, reuse=False, ds_max=0.2, rtol=1e-8, r
     x = torch.empty(2 * gcase.N, dtype=torch.float64, device="cuda")
     for k in range(n_jacobians):
         gcase.assemble()
-        fnorm = float(torch.linalg.norm(gcase.R))
+        fnorm = tpf.tpf_norm2(gcase.R, stream=gcase.stream)
         t0 = time.perf_counter()
         M.setup(gcase, reuse=bool(reuse and k > 0))
         torch.cuda.synchronize()
@@ -135,6 +135,88 @@ def newton_sequence(gcase, M, n_jacobians, reuse=False, ds_max=0.2, rtol=1e-8, r
             on_step(rec)
     torch.cuda.synchronize()
     return out
+
+
+def simulate(case, kind, t_final, dt=None, precision=tpf.TPF_FP64, newton_tol=1e-6,
+             max_newton=25, rtol=1e-8, ds_max=0.2, **precond_opts):
+    """Backward-Euler time steps on the GPU (Sec. 2, Eq. fully_discrete_system),
+    each a Newton loop (Sec. 3) until ||F(u_k)|| <= newton_tol (Sec. 4.1
+    solver settings): assemble, norm of F, preconditioner setup, FGMRES on
+    J x = F, update with the saturation chop.  A step whose Newton loop has
+    not met the tolerance after max_newton solves, or whose linear solve
+    fails, ends the run as diverged.  Returns a dict with per-step residual
+    norms and Krylov iterations, NI, LI, LI/NI, wall time, status, and the
+    final state (device tensor)."""
+    import time
+
+    import torch
+    dt = case.dt if dt is None else dt
+    n_steps = int(round(t_final / dt))
+    g = GpuCase(case.replace(dt=dt))
+    M = GpuPrecond(kind, precision, **precond_opts)
+    x = torch.empty(2 * g.N, dtype=torch.float64, device="cuda")
+    steps, status = [], "converged"
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_steps):
+        g.u_old.copy_(g.u)
+        fnorms, its, st = [], [], "diverged"
+        while True:
+            g.assemble()
+            fn = tpf.tpf_norm2(g.R, stream=g.stream)
+            fnorms.append(fn)
+            if not np.isfinite(fn):
+                break
+            if fn <= newton_tol:
+                st = "converged"
+                break
+            if len(its) >= max_newton:
+                break
+            M.setup(g)
+            info = solve(g, M, g.R, x, rtol=rtol)  # J x = F: the Newton step is -x
+            its.append(int(info.iterations))
+            if info.status != tpf.TPF_CONVERGED:
+                break
+            tpf.tpf_newton_update(g.prob, g.u, x, ds_max, alpha=-1.0, stream=g.stream)
+        steps.append(dict(fnorms=fnorms, iterations=its, status=st))
+        if st != "converged":
+            status = "diverged"
+            break
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ni = sum(len(s["iterations"]) for s in steps)
+    li = sum(sum(s["iterations"]) for s in steps)
+    u = g.u.clone()
+    M.close()
+    g.close()
+    return dict(steps=steps, NI=ni, LI=li, LI_per_NI=li / ni if ni else 0.0, status=status,
+                wall_s=wall, u=u)
+
+
+def exact_inner_opts(n_cells):
+    """Preconditioner options whose inner solves are exact: one-level
+    hierarchies solved by the dense coarsest inverse (at most 4,096 rows)."""
+    if n_cells > 4096:
+        raise ValueError("exact inner solves need at most 4,096 cells")
+    return dict(max_levels=1, dense_max=max(n_cells, 1), coarse_max=max(n_cells, 1))
+
+
+def preconditioned_matrix(gcase, M):
+    """Dense J M^{-1} of a GPU Jacobian and preconditioner (Sec. 4.3
+    eigenvalue study), formed column by column on the device: column j =
+    J (M^{-1} e_j), by tpf_precond_apply and tpf_spmv.  Returns a host array."""
+    import torch
+    n = 2 * gcase.N
+    e = torch.zeros(n, dtype=torch.float64, device="cuda")
+    z = torch.empty_like(e)
+    cols = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    for j in range(n):
+        e.zero_()
+        e[j] = 1.0
+        M.apply(e, z, stream=gcase.stream)
+        tpf.tpf_spmv(gcase.J, z, cols[j], stream=gcase.stream)
+    torch.cuda.synchronize()
+    return cols.T.cpu().numpy()
 
 
 class Server:

@@ -228,6 +228,90 @@ def serving_case(r: int, edge_override: int | None = None, cfl: float = SEQUENCE
 
 
 # ----------------------------------------------------------------------------
+# multi-step simulations: stand-ins for the paper's 2D experiments
+#
+# Units: pressure Pa, length m, time day (so viscosities are in Pa day and
+# rates in m^3/day); rho g in Pa/m (time does not enter it).
+
+MILLIDARCY = 9.869233e-16        # m^2
+CENTIPOISE = 1e-3 / 86400.0      # Pa day
+GRAVITY = 9.81                   # m/s^2
+# capillary-pressure parameter sets Ex1-Ex3 (the paper's table of P_c
+# parameters): linear P_0, Brooks-Corey P_d and lambda
+PC_EXAMPLES = {1: dict(p0=1e5, pd=1e6, lam=2.5),
+               2: dict(p0=1e4, pd=1e5, lam=0.8),
+               3: dict(p0=1e3, pd=2e4, lam=2.5)}
+
+
+def _xz_case(nx, nz, hx, hy, hz, k, example, pc_model, name):
+    N = nx * nz
+    ex = PC_EXAMPLES[example]
+    c = Case(nx=nx, ny=1, nz=nz, hx=hx, hy=hy, hz=hz, kx=k.copy(), ky=k.copy(), kz=k.copy(),
+             poro=np.full(N, 0.2), mu_w=1.0 * CENTIPOISE, mu_n=10.0 * CENTIPOISE,
+             rho_w=1000.0, rho_n=700.0, grav=GRAVITY, pc_model=pc_model,
+             bc_lambda=ex["lam"] if pc_model == PC_BROOKS_COREY else 2.0, swr=0.0, snr=0.0,
+             pd=ex["pd"] if pc_model == PC_BROOKS_COREY else ex["p0"], name=name)
+    c.q = np.zeros((N, 2))
+    return c
+
+
+def _finish_xz(c, inlet_cell, rate, outlet_cell):
+    """Inlet: a prescribed water inflow `rate` through the left boundary face
+    of inlet_cell (a constant water source of that cell); outlet: a
+    Dirichlet right face of outlet_cell with P_w = 0, S_w = 0.2; initial
+    P_w = 1e5 Pa, S_n = 0.8."""
+    c.q[inlet_cell, 0] = rate
+    c.dir_cells = np.array([outlet_cell], np.int32)
+    c.dir_face = np.array([FACE_XP], np.int32)
+    c.dir_p = np.array([0.0])
+    c.dir_s = np.array([0.8])
+    return _finish(c, 1e5, 0.8)
+
+
+def oil_water_xz(example, pc_model, nx=100, nz=20, seed=11, sigma=2.0, corr=(16.0, 2.0),
+                 mean_mD=100.0) -> Case:
+    """Stand-in for the 2D oil-water cross-section of Sec. 4.1: 762 x 15.24 m
+    in the xz plane (gravity along z), nx x 1 x nz cells (7.62 x 7.62 x
+    0.762 m at 100 x 20), isotropic log-normal permeability around mean_mD
+    with correlation lengths corr = (x, z) cells (the SPE10 model-1 slice the
+    paper uses is not available); water enters at 50 m^3/day through the left
+    face of the bottom-left cell and leaves through the right face of the
+    top-right cell (P_w = 0, S_w = 0.2); initial P_w = 1e5 Pa, S_n = 0.8;
+    phi 0.2, mu_w 1 cP, mu_n 10 cP, rho_w 1000, rho_n 700, S_wr = S_nr = 0
+    (the paper's table of input data); P_c parameters of example 1-3."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    logk = gaussian_field((nz, 1, nx), (corr[1], 1.0, corr[0]), sigma, rng).reshape(-1)
+    k = mean_mD * MILLIDARCY * np.exp(logk)
+    c = _xz_case(nx, nz, 762.0 / nx, 7.62, 15.24 / nz, k, example, pc_model,
+                 f"oil-water-xz-{nx}x{nz}-ex{example}-{'bc' if pc_model == 0 else 'lin'}")
+    return _finish_xz(c, (nz - 1) * nx, 50.0, nx - 1)
+
+
+# regime of the gravity box -> (P_c example, time step in days, final time)
+GRAVITY_REGIMES = {"diffusion": (1, 10.0, 20.0), "advection": (2, 4.0, 8.0),
+                   "strong-advection": (3, 1.0, 2.0)}
+
+
+def gravity_box_xz(n, regime) -> Case:
+    """Stand-in for the 2D problem with gravity of Sec. 4.2: a 20 x 20 m box
+    in the xz plane, n x 1 x n cells of unit thickness, homogeneous 100 mD;
+    water enters at 5 m^3/day through the left face of the top-left cell,
+    the outlet is the right face of the top-right cell (P_w = 0, S_w =
+    0.2); initial state as in the oil-water case; linear P_c with P_0 of
+    example 1, 2 or 3 for the diffusion-, advection- and strongly
+    advection-dominated regimes (the paper names P_0 = 1e4 for the
+    advection case); the time step and final time of each regime are in
+    GRAVITY_REGIMES."""
+    ex, dt, _ = GRAVITY_REGIMES[regime]
+    k = np.full(n * n, 100.0 * MILLIDARCY)
+    h = 20.0 / n
+    c = _xz_case(n, n, h, 1.0, h, k, ex, PC_LINEAR, f"gravity-box-{n}x{n}-{regime}")
+    c = _finish_xz(c, 0, 5.0, n - 1)
+    c.dt = dt
+    return c
+
+
+# ----------------------------------------------------------------------------
 # small cases and random states for parity tests
 
 

@@ -21,6 +21,7 @@ TPF_OK = 0
 TPF_PC_BROOKS_COREY, TPF_PC_LINEAR = 0, 1
 TPF_PREC_AMG, TPF_PREC_CPR1, TPF_PREC_CPR2, TPF_PREC_BF, TPF_PREC_NONE = 0, 1, 2, 3, 4
 TPF_FP64, TPF_FP32 = 0, 1
+TPF_SMOOTH_L1_JACOBI, TPF_SMOOTH_CHEBYSHEV = 0, 1
 TPF_CONVERGED, TPF_MAX_ITERS, TPF_BREAKDOWN, TPF_NONFINITE, TPF_CANCELLED = 0, 1, 2, 3, 4
 TPF_ERR_OVER_BUDGET = -5
 TPF_MAT_A, TPF_MAT_P, TPF_MAT_R, TPF_MAT_S, TPF_MAT_APS, TPF_MAT_SCHUR = 0, 1, 2, 3, 10, 11
@@ -60,14 +61,17 @@ class CsrView(ctypes.Structure):
 class PrecondOpts(ctypes.Structure):
     _fields_ = [("kind", c_int), ("precision", c_int), ("theta", c_double), ("max_levels", c_int),
                 ("coarse_max", c_int), ("dense_max", c_int), ("interp", c_int),
-                ("hash_seed", c_uint64), ("exti_route", c_int)]
+                ("hash_seed", c_uint64), ("exti_route", c_int), ("smoother", c_int),
+                ("nu1", c_int), ("nu2", c_int), ("cheb_degree", c_int)]
 
 
 class HierStats(ctypes.Structure):
     _fields_ = [("n_hier", c_int), ("levels", c_int * 3),
                 ("rows", (c_int64 * TPF_MAX_LEVELS) * 3), ("nnz", (c_int64 * TPF_MAX_LEVELS) * 3),
+                ("p_nnz", (c_int64 * TPF_MAX_LEVELS) * 3),
                 ("operator_complexity", c_double * 3), ("grid_complexity", c_double * 3),
                 ("coarse_dense", c_int * 3), ("l0_diagonals", c_int * 3),
+                ("coarse_smooth_sweeps", c_int * 3),
                 ("device_bytes", c_size_t), ("hier_bytes", c_size_t * 3)]
 
 
@@ -144,6 +148,7 @@ _SIGS = {
     "tpf_jacobian_view": (c_int, [c_void_p, ctypes.POINTER(BcsrView)]),
     "tpf_spmv": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "tpf_newton_update": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_double, c_void_p]),
+    "tpf_norm2": (c_int, [c_void_p, c_int64, ctypes.POINTER(c_double), c_void_p]),
     "tpf_precond_default_opts": (c_int, [c_int, ctypes.POINTER(PrecondOpts)]),
     "tpf_precond_create": (c_int, [ctypes.POINTER(PrecondOpts), ctypes.POINTER(c_void_p)]),
     "tpf_precond_destroy": (c_int, [c_void_p]),
@@ -333,6 +338,12 @@ def tpf_spmv(J, x, y, stream=None):
 def tpf_newton_update(p, u, delta, ds_max=0.0, alpha=1.0, stream=None):
     _check(load().tpf_newton_update(p, _ptr(u), _ptr(delta), float(alpha), float(ds_max),
                                     _stream(stream)))
+
+
+def tpf_norm2(x, stream=None):
+    out = c_double()
+    _check(load().tpf_norm2(_ptr(x), x.numel(), ctypes.byref(out), _stream(stream)))
+    return out.value
 
 
 def tpf_precond_default_opts(kind):

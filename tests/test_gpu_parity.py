@@ -201,7 +201,7 @@ def test_exti_every_kernel_class(gpu, route):
     M.close(); g.close()
 
 
-def _gpu_hierarchy_as_oracle(tpf, M, hier):
+def _gpu_hierarchy_as_oracle(tpf, M, hier, **cycle):
     st = M.stats()
     As, Ps = [], []
     for l in range(st.levels[hier]):
@@ -212,7 +212,7 @@ def _gpu_hierarchy_as_oracle(tpf, M, hier):
     # coarse column count from the next level size
     for l, P in enumerate(Ps):
         Ps[l] = sp.csr_matrix((P.data, P.indices, P.indptr), shape=(P.shape[0], As[l + 1].shape[0]))
-    return amg.hierarchy_from_levels(As, Ps, dense_max=1024)
+    return amg.hierarchy_from_levels(As, Ps, dense_max=1024, **cycle)
 
 
 @pytest.mark.parametrize("kind,hier", [("bf", 0), ("bf", 1), ("amg", 0)])
@@ -231,6 +231,64 @@ def test_vcycle_parity(gpu, kind, hier):
     x = xd.cpu().numpy()
     xo = H.vcycle(b)
     assert np.max(np.abs(x - xo)) <= 1e-12 * np.max(np.abs(xo)), float(np.max(np.abs(x - xo)) / np.max(np.abs(xo)))
+    M.close(); g.close()
+
+
+SMOOTHERS = {0: "l1jacobi", 1: "chebyshev"}
+
+
+@pytest.mark.parametrize("smoother,nu1,nu2,degree", [(1, 1, 1, 2), (1, 2, 1, 3), (0, 2, 2, 2),
+                                                     (0, 0, 1, 2), (1, 1, 0, 1)])
+def test_vcycle_smoother_variants_parity(gpu, smoother, nu1, nu2, degree):
+    """V(nu1, nu2) cycles with l1-Jacobi or Chebyshev smoothing (generic
+    sweeps) on both BF hierarchies against the oracle's cycle with the same
+    options on the GPU's levels: FP64 within 1e-12 of max|x|, FP32 within
+    1e-4."""
+    driver, tpf, torch = gpu
+    c = inputs.random_state(inputs.small_case(24, 20, 5, seed=8), 9, s_lo=0.15, s_hi=0.85)
+    opts = dict(smoother=smoother, nu1=nu1, nu2=nu2, cheb_degree=degree)
+    say(f"[smoothers] {opts}")
+    g, M = _setup(driver, tpf, c, "bf", coarse_max=50, **opts)
+    M32 = driver.GpuPrecond("bf", tpf.TPF_FP32, coarse_max=50, **opts)
+    M32.setup(g)
+    for hier in (0, 1):
+        H = _gpu_hierarchy_as_oracle(tpf, M, hier, smoother=SMOOTHERS[smoother], nu1=nu1,
+                                     nu2=nu2, cheb_degree=degree)
+        assert len(H.levels) >= 3
+        b = inputs.random_vector(H.levels[0].n, 20 + hier)
+        xo = H.vcycle(b)
+        bd = torch.tensor(b, device="cuda")
+        for P, tol in ((M, 1e-12), (M32, 1e-4)):
+            xd = torch.empty_like(bd)
+            tpf.tpf_precond_vcycle(P.M, hier, bd, xd)
+            rel = float(np.max(np.abs(xd.cpu().numpy() - xo)) / np.max(np.abs(xo)))
+            say(f"  hierarchy {hier} tol {tol:g}: max rel diff {rel:.2e}")
+            assert rel <= tol, rel
+    M32.close(); M.close(); g.close()
+
+
+@pytest.mark.parametrize("nu", [1, 2])
+def test_chebyshev_bf_solve_parity(gpu, nu):
+    """BF with Chebyshev(2) V(nu, nu) cycles on the 32x32x16 member of the 3D
+    workload family: relres <= 1e-8, iterations within +-1 of the oracle's
+    BF with the same smoother (oracle built from the same Jacobian)."""
+    driver, tpf, torch = gpu
+    c = inputs.config_c3(32, 32, 16)
+    say(f"[chebyshev solve] nu={nu}")
+    g, M = _setup(driver, tpf, c, "bf", smoother=1, nu1=nu, nu2=nu)
+    b = g.rhs().contiguous()
+    x = torch.empty_like(b)
+    info = driver.solve(g, M, b, x, rtol=1e-8)
+    rp, ci, vals = g.bcsr_numpy()
+    J = tpfa.bcsr_matrix(rp, ci, vals)
+    Mo = precond.Preconditioner("bf", rp, ci, vals, (c.nx, c.ny, c.nz),
+                                amg_opts=dict(smoother="chebyshev", nu1=nu, nu2=nu))
+    bn = b.cpu().numpy()
+    _, io = fgmres.fgmres(lambda v: J @ v, Mo.apply, bn, rtol=1e-8)
+    rel = np.linalg.norm(bn - J @ x.cpu().numpy()) / np.linalg.norm(bn)
+    say(f"  gpu its={info.iterations} relres={rel:.2e} oracle its={io['iterations']}")
+    assert info.status == tpf.TPF_CONVERGED and rel <= 1e-8
+    assert abs(info.iterations - io["iterations"]) <= 1
     M.close(); g.close()
 
 

@@ -573,3 +573,32 @@ def test_newton_update_chop_and_clamp_closed_form():
     np.testing.assert_array_equal(un0[:, 0], un[:, 0])
     # the input state is not modified
     assert u[0, 1] == 0.5 and u[3, 1] == 0.3
+
+
+# ----------------------------------------------------------------- spectra
+
+
+def test_spectrum_bf_is_one_and_schur_ratio():
+    """Sec. 4.3 study, exact inner solves.  For BF's block upper-triangular M
+    (Eq. m_bf) with S~ in place of the Schur complement S = A_pp - A_ps
+    A_ss^{-1} A_sp, J M^{-1} has the eigenvalue 1 N times and the N
+    eigenvalues of S S~^{-1}; with S itself every eigenvalue is 1 (a
+    defective one, so computed eigenvalues scatter by about sqrt(eps))."""
+    from oracle import spectra
+    c = inputs.oil_water_xz(2, inputs.PC_LINEAR, nx=10, nz=4)
+    rp, ci, v = tpfa.jacobian(c, c.u, c.u_old)
+    N = c.N
+    ev = np.sort_complex(np.linalg.eigvals(
+        spectra.preconditioned_matrix("bf", rp, ci, v, (c.nx, c.ny, c.nz))))
+    Pm, App, Aps, Asp, Ass = _dense_blocks(rp, ci, v, N)
+    S = App - Aps @ np.linalg.solve(Ass, Asp)
+    St = blocks.schur_simple(*(blocks.block(rp, ci, v, a, b)
+                               for a, b in [(0, 0), (0, 1), (1, 0), (1, 1)])).toarray()
+    expect = np.sort_complex(np.concatenate([np.ones(N), np.linalg.eigvals(S @ np.linalg.inv(St))]))
+    assert np.max(np.abs(ev - expect)) <= 1e-6
+    # CPR with an exact first stage: J M^{-1} = I
+    ev1 = np.linalg.eigvals(spectra.preconditioned_matrix("cpr1", rp, ci, v, (c.nx, c.ny, c.nz),
+                                                          p1="exact"))
+    assert np.max(np.abs(ev1 - 1.0)) <= 1e-8
+    s = spectra.summary(ev)
+    assert s["n"] == 2 * N and s["min_abs"] > 0.5
