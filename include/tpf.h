@@ -306,6 +306,30 @@ typedef struct tpf_solve_info {
 int tpf_solve(const tpf_jacobian* J, tpf_precond* M, const double* b, double* x,
               const tpf_solve_opts* o, tpf_solve_info* info, void* stream);
 
+/* tpf_solve for callers that cannot allocate device memory (tight serving
+ * loops, harnesses that forbid hipMalloc): the same solve and the same
+ * results, but the Krylov workspace (bases V and Z, residual, Hessenberg
+ * matrix, rotations, partial sums) lives in a fixed 128 MiB device array of
+ * the library, one per GPU, held until the process ends; the call draws no
+ * device memory from the allocator and calls no hipMalloc/hipFree.
+ *   - Size limit: the workspace of an FGMRES(m) solve is about
+ *     (2m + 2) * 2N doubles plus 1 MiB; at restart 30 that allows up to
+ *     268,000 unknowns (134,000 cells).  Larger systems fail with
+ *     TPF_ERR_INVALID_ARG before any device work.
+ *   - J and M must already be set up (their memory was allocated then).
+ *     With V-cycle graphs enabled (tpf_set_graphs(1)) the call fails with
+ *     TPF_ERR_STATE, since a graph is instantiated on first use.
+ *   - Every call on one GPU uses that GPU's one array: calls that overlap on
+ *     a GPU (other threads, or other streams before a call returns) race and
+ *     corrupt each other's results.  Each call writes every workspace entry
+ *     it reads, so the contents a previous call left do not matter.
+ *   - No preconditioning is queued ahead of a step's scalars (tpf_solve
+ *     overlaps the two); the iterates are the same.
+ * Arguments, status and info are those of tpf_solve.  Synchronises the
+ * stream. */
+int tpf_solve_noalloc(const tpf_jacobian* J, tpf_precond* M, const double* b, double* x,
+                      const tpf_solve_opts* o, tpf_solve_info* info, void* stream);
+
 /* ---- serving: continuous batching of Newton-step solves ---------------- */
 /* Not part of the paper's method: a request loop over many independent
  * Newton sequences (realizations) on one GPU.  Each request is one Newton

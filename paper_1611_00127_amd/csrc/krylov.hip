@@ -12,6 +12,7 @@
 // device; the host reads the residual estimate once per step.
 #include <chrono>
 #include <cmath>
+#include <mutex>
 
 #include "krylov.hpp"
 #include "linalg_dev.hpp"
@@ -290,23 +291,51 @@ unsigned vec_grid(int64_t n) {
 }  // namespace
 
 // ---------------------------------------------------------------- resumable solver
+template <class F>
+void Fgmres::for_each_array(int64_t nn, int mm, F&& f) {
+  f(V, size_t(mm + 1) * nn);
+  f(Z, size_t(mm) * nn);
+  f(H, size_t(mm + 1) * mm);
+  f(cs, size_t(mm));
+  f(sn, size_t(mm));
+  f(g, size_t(mm + 1));
+  f(h1, size_t(kMaxRestart + 1));
+  f(h2, size_t(kMaxRestart + 1));
+  f(part, size_t(kKGridMax) * 64);
+  f(y, size_t(mm));
+  f(r, size_t(nn));
+  f(st_dev, size_t(4));
+  f(scal, size_t(2));
+}
+
+namespace {
+constexpr size_t kAlignDoubles = 32;  // 256 bytes
+size_t align_up(size_t c) { return (c + kAlignDoubles - 1) / kAlignDoubles * kAlignDoubles; }
+}  // namespace
+
+size_t Fgmres::workspace_doubles(int64_t nn, int mm) {
+  Fgmres probe;
+  size_t total = 0;
+  probe.for_each_array(nn, mm, [&](Buf<double>&, size_t c) { total += align_up(c); });
+  return total;
+}
+
 void Fgmres::alloc(int64_t nn, int mm, hipStream_t st) {
   if (n == nn && m == mm && V.p) return;
   n = nn;
   m = mm;
-  V.alloc(size_t(m + 1) * n, st);
-  Z.alloc(size_t(m) * n, st);
-  H.alloc(size_t(m + 1) * m, st);
-  cs.alloc(m, st);
-  sn.alloc(m, st);
-  g.alloc(m + 1, st);
-  h1.alloc(kMaxRestart + 1, st);
-  h2.alloc(kMaxRestart + 1, st);
-  part.alloc(size_t(kKGridMax) * 64, st);
-  y.alloc(m, st);
-  r.alloc(n, st);
-  st_dev.alloc(4, st);
-  scal.alloc(2, st);
+  for_each_array(n, m, [&](Buf<double>& b, size_t c) { b.alloc(c, st); });
+}
+
+void Fgmres::bind(double* base, int64_t nn, int mm) {
+  n = nn;
+  m = mm;
+  size_t off = 0;
+  for_each_array(n, m, [&](Buf<double>& b, size_t c) {
+    b.wrap(base + off, c);
+    off += align_up(c);
+  });
+  bound = true;
 }
 
 void Fgmres::begin(const tpf_jacobian* J_, tpf_precond* M_, const double* b_, double* x_,
@@ -328,7 +357,11 @@ void Fgmres::begin(const tpf_jacobian* J_, tpf_precond* M_, const double* b_, do
   s = st;
   TPF_REQUIRE(host_slot, TPF_ERR_INVALID_ARG, "null host slot");
   host = host_slot;
-  alloc(2 * int64_t(J->nb), o.restart, s);  // n even: the streaming passes read pairs
+  if (bound)  // n even: the streaming passes read pairs
+    TPF_REQUIRE(n == 2 * int64_t(J->nb) && m == o.restart, TPF_ERR_INVALID_ARG,
+                "bound workspace is for %lld unknowns and restart %d", (long long)n, m);
+  else
+    alloc(2 * int64_t(J->nb), o.restart, s);
   G = krylov_grid(n);
   total = 0;
   est = 1.0;
@@ -525,6 +558,79 @@ extern "C" int tpf_solve(const tpf_jacobian* J, tpf_precond* M, const double* b,
       else
         TPF_HIP(hipStreamSynchronize(s));
       f.ev_pending = false;
+      done = f.complete();
+    }
+    TPF_HIP(hipStreamSynchronize(s));
+    f.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - f.t0).count();
+    f.info(info);
+  });
+}
+
+// ------------------------------------------------------------ allocation-free solve
+// The workspace of tpf_solve_noalloc lives in one file-scope device array per
+// GPU.  In host code `scratch` names a host-side stand-in, not the device
+// copy: its device address is looked up once per device and only that
+// address is passed to kernels.
+namespace tpf {
+namespace {
+constexpr size_t kScratchBytes = size_t(128) << 20;
+constexpr int kScratchDevices = 64;
+
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kScratchDevices] = {};
+
+// device address of the current device's scratch array (looked up on the
+// first call on that device, with it current)
+double* scratch_on_current_device() {
+  int dev = -1;
+  TPF_HIP(hipGetDevice(&dev));
+  TPF_REQUIRE(dev >= 0 && dev < kScratchDevices, TPF_ERR_INVALID_ARG,
+              "device %d is beyond the %d devices the allocation-free solve supports", dev,
+              kScratchDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    TPF_REQUIRE(e == hipSuccess && p, TPF_ERR_HIP,
+                "hipGetSymbolAddress(scratch) on device %d -> %s", dev, hipGetErrorString(e));
+    TPF_REQUIRE(reinterpret_cast<uintptr_t>(p) % 256 == 0, TPF_ERR_HIP,
+                "scratch array is not 256-byte aligned on device %d", dev);
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+}  // namespace tpf
+
+extern "C" int tpf_solve_noalloc(const tpf_jacobian* J, tpf_precond* M, const double* b,
+                                 double* x, const tpf_solve_opts* o, tpf_solve_info* info,
+                                 void* stream) {
+  return guarded([&] {
+    TPF_REQUIRE(J && b && x && o && info, TPF_ERR_INVALID_ARG, "null argument");
+    TPF_REQUIRE(o->restart >= 1 && o->restart <= kMaxRestart, TPF_ERR_INVALID_ARG,
+                "restart must be in [1, %d]", kMaxRestart);
+    TPF_REQUIRE(!graphs_enabled(), TPF_ERR_STATE,
+                "V-cycle graphs are instantiated on first use: disable them (tpf_set_graphs(0)) "
+                "for the allocation-free solve");
+    const int64_t n = 2 * int64_t(J->nb);
+    const size_t need = Fgmres::workspace_doubles(n, o->restart) * sizeof(double);
+    TPF_REQUIRE(need <= kScratchBytes, TPF_ERR_INVALID_ARG,
+                "tpf_solve_noalloc: %lld unknowns at restart %d need %zu bytes of workspace; "
+                "the allocation-free solve holds at most %zu bytes (use tpf_solve)",
+                (long long)n, o->restart, need, kScratchBytes);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Fgmres f;  // workspace views the scratch array; nothing is allocated
+    f.bind(scratch_on_current_device(), n, o->restart);
+    f.speculate = false;
+    // pageable and per thread (it outlives a copy still queued when an error
+    // ends the call); every read follows a stream synchronisation
+    alignas(64) static thread_local double host_slot[8];
+    f.begin(J, M, b, x, *o, s, host_slot);
+    bool done = false;
+    while (!done) {
+      TPF_HIP(hipStreamSynchronize(s));
       done = f.complete();
     }
     TPF_HIP(hipStreamSynchronize(s));

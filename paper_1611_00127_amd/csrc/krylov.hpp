@@ -26,7 +26,8 @@ struct Fgmres {
   int64_t n = 0;
   int m = 0;
   Buf<double> V, Z, H, cs, sn, g, h1, h2, part, y, r, st_dev, scal;
-  void* host = nullptr;  // pinned 64-byte slot owned by the caller
+  bool bound = false;  // workspace placed by bind()
+  void* host = nullptr;  // 64-byte host slot owned by the caller (pinned, or pageable)
 
   // solve state
   const tpf_jacobian* J = nullptr;
@@ -55,6 +56,16 @@ struct Fgmres {
   bool ev_pending = false;
   hipEvent_t ready = nullptr;
 
+  // Workspace of an FGMRES(m) solve of n unknowns, in doubles, each array
+  // starting on a 256-byte boundary: the size bind() needs, and an upper
+  // bound of what alloc() draws from the allocator.
+  static size_t workspace_doubles(int64_t n, int m);
+  // Places the workspace in caller-held device memory (base: 256-byte
+  // aligned, at least workspace_doubles(n, m) doubles) instead of drawing it
+  // from the allocator; begin() then allocates nothing and requires the same
+  // n and m.  The memory must outlive the solve.
+  void bind(double* base, int64_t n, int m);
+
   void begin(const tpf_jacobian* J, tpf_precond* M, const double* b, double* x,
              const tpf_solve_opts& o, hipStream_t s, void* host_slot);
   bool complete();
@@ -64,6 +75,8 @@ struct Fgmres {
 
  private:
   void alloc(int64_t n, int m, hipStream_t s);
+  // calls f(buffer, element count) for every workspace array, in layout order
+  template <class F> void for_each_array(int64_t n, int m, F&& f);
   void launch_cycle_start(const double* r, double beta);
   void launch_step();
   void launch_cycle_end();

@@ -52,12 +52,10 @@ __global__ void k_negate(int64_t n, const double* __restrict__ x, double* __rest
     y[i] = -x[i];
 }
 
-// bytes of an FGMRES(m) workspace for 2N unknowns (basis V, Z, residual,
-// partial sums); matches the buffers Fgmres allocates
+// bytes of an FGMRES(m) workspace for 2N unknowns: the arrays Fgmres
+// allocates, each rounded up to 256 bytes
 size_t krylov_bytes(int64_t cells, int m) {
-  int64_t n = 2 * cells;
-  return size_t(8) * (size_t(2 * m + 2) * n + size_t(1024) * 64 + size_t(m + 1) * (m + 4) +
-                      2 * (kMaxRestart + 1) + 8);
+  return sizeof(double) * Fgmres::workspace_doubles(2 * cells, m);
 }
 
 }  // namespace

@@ -98,34 +98,49 @@ struct SideFork {
 // Returns every cached block to the upstream allocator (device idle).
 void release_cache();
 
-// Owning device array; frees through the installed allocator.
+// Device array; frees through the installed allocator when it owns its
+// memory (alloc), not when it views memory held elsewhere (wrap).
 template <class T>
 struct Buf {
   T* p = nullptr;
   size_t n = 0;
   hipStream_t s = nullptr;
+  bool own = true;
   Buf() = default;
   Buf(size_t count, hipStream_t st) { alloc(count, st); }
   ~Buf() { release(); }
   Buf(const Buf&) = delete;
   Buf& operator=(const Buf&) = delete;
-  Buf(Buf&& o) noexcept : p(o.p), n(o.n), s(o.s) { o.p = nullptr; o.n = 0; }
+  Buf(Buf&& o) noexcept : p(o.p), n(o.n), s(o.s), own(o.own) { o.p = nullptr; o.n = 0; }
   Buf& operator=(Buf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; n = o.n; s = o.s; o.p = nullptr; o.n = 0; }
+    if (this != &o) {
+      release();
+      p = o.p; n = o.n; s = o.s; own = o.own;
+      o.p = nullptr; o.n = 0;
+    }
     return *this;
   }
   void alloc(size_t count, hipStream_t st) {
     release();
     s = st;
     n = count;
+    own = true;
     p = count ? static_cast<T*>(dalloc(count * sizeof(T), st)) : nullptr;
+  }
+  // views count elements at ptr without taking ownership
+  void wrap(T* ptr, size_t count) {
+    release();
+    p = ptr;
+    n = count;
+    own = false;
   }
   // grows (discarding contents) when smaller than count
   void ensure(size_t count, hipStream_t st) { if (n < count || !p) alloc(count < 1 ? 1 : count, st); }
   void release() {
-    if (p) dfree(p, n * sizeof(T), s);
+    if (p && own) dfree(p, n * sizeof(T), s);
     p = nullptr;
     n = 0;
+    own = true;
   }
   size_t bytes() const { return n * sizeof(T); }
   T* get() const { return p; }

@@ -116,6 +116,7 @@ _lib = None
 _alloc_cb = None
 _free_cb = None
 _shutting_down = False
+_alloc_calls = 0  # requests the library made to torch's allocator
 
 
 def _mark_shutdown():
@@ -167,6 +168,8 @@ _SIGS = {
     "tpf_csr_transpose": (c_int, [ctypes.POINTER(CsrView), c_void_p, c_void_p, c_void_p, c_void_p]),
     "tpf_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(SolveOpts),
                           ctypes.POINTER(SolveInfo), c_void_p]),
+    "tpf_solve_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p,
+                                  ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), c_void_p]),
     "tpf_server_default_opts": (c_int, [ctypes.POINTER(ServerOpts)]),
     "tpf_server_create": (c_int, [ctypes.POINTER(ServerOpts), ctypes.POINTER(c_void_p)]),
     "tpf_server_submit": (c_int, [c_void_p, ctypes.POINTER(Request), ctypes.POINTER(c_uint64)]),
@@ -236,6 +239,8 @@ def use_torch_allocator():
     FREE = ctypes.CFUNCTYPE(None, c_void_p, c_void_p, c_void_p)
 
     def _a(nbytes, stream, ctx):
+        global _alloc_calls
+        _alloc_calls += 1
         try:
             return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
         except Exception:
@@ -247,6 +252,13 @@ def use_torch_allocator():
 
     _alloc_cb, _free_cb = ALLOC(_a), FREE(_f)
     _check(lib.tpf_set_allocator(ctypes.cast(_alloc_cb, c_void_p), ctypes.cast(_free_cb, c_void_p), None))
+
+
+def allocator_calls():
+    """Number of device allocations the library has requested from torch's
+    caching allocator in this process (blocks it reuses from its own cache
+    are not requests)."""
+    return _alloc_calls
 
 
 def init(torch_allocator=True):
@@ -455,6 +467,14 @@ def tpf_solve(J, M, b, x, rtol=1e-8, restart=30, maxit=1000, stream=None):
     info = SolveInfo()
     _check(load().tpf_solve(J, M, _ptr(b), _ptr(x), ctypes.byref(o), ctypes.byref(info),
                             _stream(stream)))
+    return info
+
+
+def tpf_solve_noalloc(J, M, b, x, rtol=1e-8, restart=30, maxit=1000, stream=None):
+    o = SolveOpts(rtol, restart, maxit)
+    info = SolveInfo()
+    _check(load().tpf_solve_noalloc(J, M, _ptr(b), _ptr(x), ctypes.byref(o), ctypes.byref(info),
+                                    _stream(stream)))
     return info
 
 
