@@ -222,15 +222,18 @@ def kernel_digest(names):
     return h.hexdigest()
 
 
-def stored_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
+def stored_traffic(timer, symbol):
+    """HBM bytes per launch of the kernel behind V-cycle timer `timer` (e.g.
+    "vcycle_post_smooth[Schur,l1]") from the committed FETCH_SIZE /
     WRITE_SIZE measurement (scaled by its copy-kernel calibration), or None
-    when there is none or the kernel's source has changed since."""
+    when there is none, it is of another kernel, or the kernel's source has
+    changed since."""
     if not os.path.exists(TRAFFIC_JSON):
         return None
     rec = json.load(open(TRAFFIC_JSON))
-    k = rec["kernels"].get(kernel)
-    if k is None or k["source_sha256"] != kernel_digest(k["digest_of"]):
+    k = rec["kernels"].get(timer)
+    if (k is None or k["symbol"] != symbol
+            or k["source_sha256"] != kernel_digest(k["digest_of"])):
         return None
     kib = (k["fetch_kib_per_dispatch"] * rec["fetch_scale"]
            + k["write_kib_per_dispatch"] * rec["write_scale"])
@@ -716,7 +719,8 @@ def main():
             "timer": f"{dom['timer']}[{dom['hier']},l{dom['level']}]",
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": stored_traffic(dom["symbol"]),
+            "traffic": stored_traffic(f"{dom['timer']}[{dom['hier']},l{dom['level']}]",
+                                      dom["symbol"]),
             "avg_launch_us": round(avg_ms * 1e3, 2), "launches": dom["launches"],
             "algorithmic_bytes_per_launch": dom["bytes"],
             "share_of_vcycle_kernel_time": round(
