@@ -60,10 +60,13 @@ def parse():
     ap.add_argument("--serve-full", action="store_true",
                     help="the full stream: 64 realizations x 16 Newton-step requests, "
                          "grids up to 128^3")
-    ap.add_argument("--serve-realizations", type=int, default=8)
-    ap.add_argument("--serve-requests", type=int, default=4, help="requests per realization")
-    ap.add_argument("--serve-max-edge", type=int, default=64,
-                    help="grid edges drawn above this are clamped to it")
+    ap.add_argument("--serve-realizations", type=int, default=32,
+                    help="realizations of the serving stream (the first R of its 64)")
+    ap.add_argument("--serve-requests", type=int, default=8, help="requests per realization")
+    ap.add_argument("--serve-max-edge", type=int, default=128,
+                    help="grid edges drawn above this are clamped to it (128: none)")
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0,
+                    help="HBM admission budget of the serving engine")
     ap.add_argument("--serve-active", type=int, default=8, help="requests in flight")
     ap.add_argument("--serve-load", type=float, default=0.8,
                     help="Poisson arrival rate as a fraction of the sequential FP64 throughput")
@@ -418,8 +421,14 @@ def serve_stream(torch, tpf, driver, inputs, args):
     thr_b = n / base_s
     log(f"[serve] baseline: {n} requests in {base_s:.2f} s ({thr_b:.1f} solves/s)")
 
+    budget = int(args.serve_budget_gib * 2 ** 30)
+
     def run(rate):
-        sv = driver.Server("bf", precision=tpf.TPF_FP32, max_active=args.serve_active)
+        torch.cuda.synchronize()
+        base, _ = tpf.allocator_bytes()
+        tpf.reset_allocator_peak()
+        sv = driver.Server("bf", precision=tpf.TPF_FP32, max_active=args.serve_active,
+                           hbm_budget_bytes=budget)
         arr = np.zeros(n) if rate is None else np.cumsum(rng.exponential(1.0 / rate, n))
         xs = [torch.empty(2 * seqs[r][0].N, dtype=torch.float64, device="cuda") for r, _ in order]
         torch.cuda.synchronize()
@@ -451,6 +460,7 @@ def serve_stream(torch, tpf, driver, inputs, args):
                 done += 1
         total = time.perf_counter() - t0
         st = sv.stats()
+        drawn = tpf.allocator_bytes()[1] - base
         sv.close()
         torch.cuda.synchronize()
         for j, (r, k) in enumerate(order):
@@ -462,7 +472,9 @@ def serve_stream(torch, tpf, driver, inputs, args):
                 "mean_iterations": round(float(np.mean(its)), 2),
                 "max_relres_true": float(np.max(rel)),
                 "max_rel_diff_vs_fp64": float(np.max(errs)),
-                "peak_bytes": int(st.peak_bytes), "evictions": int(st.evictions)}
+                "peak_bytes": int(st.peak_bytes),
+                "peak_bytes_drawn_from_allocator": int(drawn),
+                "evictions": int(st.evictions)}
 
     log("[serve] burst: every request queued at t = 0")
     burst = run(None)
@@ -475,7 +487,7 @@ def serve_stream(torch, tpf, driver, inputs, args):
     return {
         "workload": f"{R} realizations x {K} Newton-step requests, edges {edges}, "
                     f"BF FP32 V-cycle, rtol 1e-8",
-        "requests": n, "max_active": args.serve_active,
+        "requests": n, "max_active": args.serve_active, "hbm_budget_bytes": budget,
         "baseline_fp64_sequential": {"solves_per_s": round(thr_b, 2), "wall_s": round(base_s, 3),
                                      "p50_latency_ms": round(pct(lat_b, 50), 2),
                                      "p99_latency_ms": round(pct(lat_b, 99), 2)},

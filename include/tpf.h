@@ -67,10 +67,14 @@ typedef void (*tpf_free_fn)(void* ptr, void* stream, void* ctx);
  * (hipMallocAsync / hipFreeAsync), which keeps freed blocks cached.  Must
  * not change while handles allocated with the previous one live. */
 int tpf_set_allocator(tpf_alloc_fn alloc, tpf_free_fn free_fn, void* ctx);
-/* Bytes currently held by the library through the allocator. */
+/* Device bytes the library currently holds from the allocator: blocks in
+ * use plus freed blocks it keeps cached for reuse (per stream, at most
+ * 16 GiB), each at its allocated size (the request rounded up to one of
+ * eight size classes per power of two, at most 12.5% more). */
 int tpf_memory_in_use(size_t* bytes);
-/* Returns the blocks the default pool of the current device keeps cached
- * (synchronises the device).  No effect on an installed allocator. */
+/* Returns the blocks the library keeps cached to the allocator, and without
+ * an installed allocator trims the device's memory pool (synchronises the
+ * device). */
 int tpf_release_cached_memory(void);
 
 /* ---- problem (Sec. 2) -------------------------------------------------- */
@@ -341,9 +345,20 @@ int tpf_solve_noalloc(const tpf_jacobian* J, tpf_precond* M, const double* b, do
  *   - Up to max_active requests of different sequences are in flight, each
  *     on its own stream; tpf_server_step advances every active request by
  *     one phase (an Arnoldi step, a cycle end), so their kernels overlap.
- *   - Admission: a queued request starts only while the bytes held by
- *     resident sequences and active solves, plus its estimate, fit in
- *     hbm_budget_bytes; idle sequences are evicted least recently used first.
+ *   - Admission: a queued request starts only while the device bytes the
+ *     server holds, plus the reservations of setups still running, plus its
+ *     own estimate, fit in hbm_budget_bytes.
+ *       - Held bytes are every block drawn on the server's streams (the setup
+ *         stream, the slot streams, each resident preconditioner's second
+ *         setup stream), whether in use or cached for reuse, at allocated
+ *         sizes.
+ *       - A request's estimate is its FGMRES workspace plus, for a new
+ *         sequence, the resident and setup bytes measured on built sequences
+ *         of that size (scaled up from smaller ones), or, for a built
+ *         sequence, the extra bytes its last setup drew.
+ *       - To make room the server first returns idle streams' cached blocks
+ *         to the allocator, then evicts idle sequences, least recently used
+ *         first.
  *     A request that cannot fit alone fails with TPF_ERR_OVER_BUDGET.
  *   - A result does not depend on what else is in flight: every kernel is
  *     deterministic and a sequence's requests run in order.
@@ -383,8 +398,8 @@ typedef struct tpf_result {
 typedef struct tpf_server_counters {
   int queued, active, resident_sequences;
   int64_t submitted, completed;
-  size_t bytes_in_use;    /* resident sequences + active solves */
-  size_t peak_bytes;      /* maximum of bytes_in_use */
+  size_t bytes_in_use;    /* device bytes held on the server's streams (in use or cached) */
+  size_t peak_bytes;      /* maximum of bytes_in_use, sampled at each admission and step */
   int64_t evictions;
 } tpf_server_counters;
 

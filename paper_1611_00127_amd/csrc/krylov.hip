@@ -320,6 +320,13 @@ size_t Fgmres::workspace_doubles(int64_t nn, int mm) {
   return total;
 }
 
+size_t Fgmres::workspace_footprint(int64_t nn, int mm) {
+  Fgmres probe;
+  size_t total = 0;
+  probe.for_each_array(nn, mm, [&](Buf<double>&, size_t c) { total += alloc_footprint(c * sizeof(double)); });
+  return total;
+}
+
 void Fgmres::alloc(int64_t nn, int mm, hipStream_t st) {
   if (n == nn && m == mm && V.p) return;
   n = nn;

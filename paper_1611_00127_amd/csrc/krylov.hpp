@@ -60,6 +60,8 @@ struct Fgmres {
   // starting on a 256-byte boundary: the size bind() needs, and an upper
   // bound of what alloc() draws from the allocator.
   static size_t workspace_doubles(int64_t n, int m);
+  // Device bytes alloc() draws for that workspace (allocated sizes).
+  static size_t workspace_footprint(int64_t n, int m);
   // Places the workspace in caller-held device memory (base: 256-byte
   // aligned, at least workspace_doubles(n, m) doubles) instead of drawing it
   // from the allocator; begin() then allocates nothing and requires the same

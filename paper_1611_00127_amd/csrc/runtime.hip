@@ -15,7 +15,16 @@ thread_local char g_last_msg[1024] = "";
 tpf_alloc_fn g_alloc = nullptr;
 tpf_free_fn g_free = nullptr;
 void* g_ctx = nullptr;
-size_t g_in_use = 0;
+// Byte counts at allocated (size-class) sizes, under g_mem_mu: blocks handed
+// out, blocks held from the upstream allocator (handed out or cached), and
+// the peak of the latter since the last reset.
+size_t g_live = 0;
+size_t g_held = 0;
+size_t g_held_peak = 0;
+struct StreamHeld {
+  size_t held = 0, peak = 0;
+};
+std::map<hipStream_t, StreamHeld> g_stream_held;  // blocks drawn per stream
 std::mutex g_mem_mu;
 
 bool g_timing = false;
@@ -71,27 +80,40 @@ void prepare_pool() {
   g_pool_ready[dev] = 1;
 }
 
+void count_held(hipStream_t s, size_t add, size_t sub) {
+  std::lock_guard<std::mutex> lk(g_mem_mu);
+  g_held = g_held + add - sub;
+  if (g_held > g_held_peak) g_held_peak = g_held;
+  StreamHeld& h = g_stream_held[s];
+  h.held = h.held + add - sub;
+  if (h.held > h.peak) h.peak = h.held;
+  if (h.held == 0 && h.peak == 0) g_stream_held.erase(s);
+}
+
 void* upstream_alloc(size_t bytes, hipStream_t s) {
   void* p = nullptr;
   if (g_alloc) {
     p = g_alloc(bytes, reinterpret_cast<void*>(s), g_ctx);
     if (!p) fail(TPF_ERR_OOM, "allocator returned NULL for %zu bytes", bytes);
-    return p;
+  } else {
+    prepare_pool();
+    hipError_t e = hipMallocAsync(&p, bytes, s);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      fail(TPF_ERR_OOM, "hipMallocAsync(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
   }
-  prepare_pool();
-  hipError_t e = hipMallocAsync(&p, bytes, s);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    fail(TPF_ERR_OOM, "hipMallocAsync(%zu) failed: %s", bytes, hipGetErrorString(e));
-  }
+  count_held(s, bytes, 0);
   return p;
 }
 
-void upstream_free(void* p, hipStream_t s) {
+// bytes: the block's allocated (size-class) size
+void upstream_free(void* p, size_t bytes, hipStream_t s) {
   if (g_free)
     g_free(p, reinterpret_cast<void*>(s), g_ctx);
   else
     (void)hipFreeAsync(p, s);
+  count_held(s, 0, bytes);
 }
 
 // Block cache in front of the upstream allocator: a freed block is kept
@@ -135,9 +157,11 @@ void* dalloc(size_t bytes, hipStream_t s) {
   }
   if (!p) p = upstream_alloc(cls, s);
   std::lock_guard<std::mutex> lk(g_mem_mu);
-  g_in_use += bytes;
+  g_live += cls;
   return p;
 }
+
+size_t alloc_footprint(size_t bytes) { return bytes ? size_class(bytes) : 0; }
 
 void dfree(void* p, size_t bytes, hipStream_t s) {
   if (!p) return;
@@ -152,9 +176,60 @@ void dfree(void* p, size_t bytes, hipStream_t s) {
       kept = true;
     }
   }
-  if (!kept) upstream_free(p, s);
+  if (!kept) upstream_free(p, cls, s);
   std::lock_guard<std::mutex> lk(g_mem_mu);
-  g_in_use -= bytes;
+  g_live -= cls;
+}
+
+size_t cached_bytes(hipStream_t s) {
+  BlockCache& c = cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  size_t b = 0;
+  for (auto it = c.free.lower_bound({s, 0}); it != c.free.end() && it->first.first == s; ++it)
+    b += it->first.second * it->second.size();
+  return b;
+}
+
+void release_stream_cache(hipStream_t s) {
+  std::vector<std::pair<void*, size_t>> back;
+  {
+    BlockCache& c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    for (auto it = c.free.lower_bound({s, 0}); it != c.free.end() && it->first.first == s;) {
+      for (void* p : it->second) back.push_back({p, it->first.second});
+      c.cached -= it->first.second * it->second.size();
+      it = c.free.erase(it);
+    }
+  }
+  for (auto& b : back) upstream_free(b.first, b.second, s);
+}
+
+size_t held_bytes() {
+  std::lock_guard<std::mutex> lk(g_mem_mu);
+  return g_held;
+}
+
+size_t held_peak() {
+  std::lock_guard<std::mutex> lk(g_mem_mu);
+  return g_held_peak;
+}
+
+void reset_held_peak() {
+  std::lock_guard<std::mutex> lk(g_mem_mu);
+  g_held_peak = g_held;
+}
+
+std::pair<size_t, size_t> stream_held(hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_mem_mu);
+  auto it = g_stream_held.find(s);
+  return it == g_stream_held.end() ? std::pair<size_t, size_t>{0, 0}
+                                   : std::pair<size_t, size_t>{it->second.held, it->second.peak};
+}
+
+void reset_stream_held_peak(hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_mem_mu);
+  auto it = g_stream_held.find(s);
+  if (it != g_stream_held.end()) it->second.peak = it->second.held;
 }
 
 namespace {
@@ -210,36 +285,27 @@ void forget_stream(hipStream_t s) {
       (void)hipStreamDestroy(sd.st);
     }
   }
-  std::vector<void*> back;
-  {
-    BlockCache& c = cache();
-    std::lock_guard<std::mutex> lk(c.mu);
-    for (auto it = c.free.begin(); it != c.free.end();) {
-      if (it->first.first == s) {
-        for (void* p : it->second) back.push_back(p);
-        c.cached -= it->first.second * it->second.size();
-        it = c.free.erase(it);
-      } else {
-        ++it;
-      }
-    }
-  }
-  for (void* p : back) upstream_free(p, s);
+  release_stream_cache(s);
 }
 
 void release_cache() {
-  std::vector<std::pair<void*, hipStream_t>> back;
+  struct Back {
+    void* p;
+    size_t bytes;
+    hipStream_t s;
+  };
+  std::vector<Back> back;
   {
     BlockCache& c = cache();
     std::lock_guard<std::mutex> lk(c.mu);
     for (auto& kv : c.free)
-      for (void* p : kv.second) back.push_back({p, kv.first.first});
+      for (void* p : kv.second) back.push_back({p, kv.first.second, kv.first.first});
     c.free.clear();
     c.cached = 0;
   }
   if (back.empty()) return;
   TPF_HIP(hipDeviceSynchronize());  // no queued work may still use the blocks
-  for (auto& b : back) upstream_free(b.first, b.second);
+  for (auto& b : back) upstream_free(b.p, b.bytes, b.s);
 }
 
 HostScratch& host_scratch() {
@@ -335,7 +401,7 @@ int tpf_release_cached_memory(void) {
 int tpf_memory_in_use(size_t* bytes) {
   if (!bytes) return TPF_ERR_INVALID_ARG;
   std::lock_guard<std::mutex> lk(g_mem_mu);
-  *bytes = g_in_use;
+  *bytes = g_held;
   return TPF_OK;
 }
 

@@ -20,6 +20,7 @@
 #include <condition_variable>
 #include <deque>
 #include <memory>
+#include <map>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -52,11 +53,9 @@ __global__ void k_negate(int64_t n, const double* __restrict__ x, double* __rest
     y[i] = -x[i];
 }
 
-// bytes of an FGMRES(m) workspace for 2N unknowns: the arrays Fgmres
-// allocates, each rounded up to 256 bytes
-size_t krylov_bytes(int64_t cells, int m) {
-  return sizeof(double) * Fgmres::workspace_doubles(2 * cells, m);
-}
+// device bytes of an FGMRES(m) workspace for 2N unknowns: the arrays Fgmres
+// allocates, at their allocated sizes
+size_t krylov_bytes(int64_t cells, int m) { return Fgmres::workspace_footprint(2 * cells, m); }
 
 }  // namespace
 
@@ -70,12 +69,15 @@ struct Resident {
   bool built = false;  // preconditioner structure exists
   bool busy = false;
   std::atomic<size_t> bytes{0};
+  std::atomic<size_t> setup_extra{0};  // held beyond its own bytes during its last setup
+  std::atomic<hipStream_t> aux{nullptr};  // the preconditioner's second setup stream
   uint64_t last_use = 0;
   ~Resident() {
     if (M) tpf_precond_destroy(M);
     if (J) tpf_jacobian_destroy(J);
   }
-  // device bytes this sequence holds (Jacobian, preconditioner, right-hand side)
+  // device bytes this sequence holds (Jacobian, preconditioner, right-hand
+  // side), at allocated sizes
   size_t measure() const {
     size_t b = rhs.bytes();
     if (J) b += J->rp.bytes() + J->ci.bytes() + J->v.bytes();
@@ -135,36 +137,109 @@ struct tpf_server {
   std::condition_variable cv_job, cv_done;
   std::deque<Slot*> jobs;
   bool stop = false;
-  std::vector<std::pair<int64_t, size_t>> seen;  // (cells, resident bytes) of built sequences
+  // (cells, resident bytes, extra bytes held during the setup) of built sequences
+  struct Seen {
+    int64_t cells;
+    size_t resident, extra;
+  };
+  std::vector<Seen> seen;
   std::thread worker;
 
-  size_t resident_bytes() const {
-    size_t b = 0;
-    for (auto& kv : res) b += kv.second->bytes.load();
+  // Device bytes the server holds: every block drawn on its streams (the
+  // setup stream, the slot streams, each resident preconditioner's second
+  // setup stream), in use or cached for reuse, at allocated sizes.
+  size_t held() const {
+    size_t b = stream_held(setup_s).first;
+    for (auto& sl : slots) b += stream_held(sl->s).first;
+    for (auto& kv : res) {
+      hipStream_t a = kv.second->aux.load();
+      if (a) b += stream_held(a).first;
+    }
     return b;
   }
-  size_t active_bytes() const {
+  // bytes reserved for setups not finished yet (their draws so far are also
+  // in held(): the sum errs high)
+  size_t reserved() const {
     size_t b = 0;
     for (auto& sl : slots)
-      if (sl->busy()) b += sl->ws_bytes;
+      if (sl->state.load(std::memory_order_acquire) == kSetup) b += sl->ws_bytes;
     return b;
   }
-  size_t in_use() const { return resident_bytes() + active_bytes(); }
-  void note_peak() { peak = std::max(peak, in_use()); }
+  size_t in_use() const { return held() + reserved(); }
+  void note_peak() { peak = std::max(peak, held()); }
 
-  // Resident bytes a new sequence of `cells` cells is expected to need: the
-  // footprint of a built sequence at least as large, else one scaled up
-  // linearly from the largest smaller one (fixed costs scale too, so this
-  // errs high); 3 KiB per cell before any sequence has been built.
-  size_t resident_estimate(int64_t cells) {
+  bool setup_in_flight() {
     std::lock_guard<std::mutex> lk(mu);
-    double best = -1.0;
-    for (auto& ob : seen) {
-      double e = cells <= ob.first ? double(ob.second)
-                                   : double(ob.second) * double(cells) / double(ob.first);
-      if (best < 0 || e < best) best = e;
+    if (!jobs.empty()) return true;
+    for (auto& sl : slots)
+      if (sl->state.load(std::memory_order_acquire) == kSetup) return true;
+    return false;
+  }
+
+  // Returns the cached blocks of idle streams to the allocator: free slots,
+  // resident sequences not in use, and the setup stream when no setup runs.
+  // Each such stream has been synchronised since its blocks were freed.
+  void trim_caches() {
+    for (auto& sl : slots)
+      if (!sl->busy()) release_stream_cache(sl->s);
+    for (auto& kv : res) {
+      hipStream_t a = kv.second->aux.load();
+      if (!kv.second->busy && a) release_stream_cache(a);
     }
-    return best < 0 ? size_t(3072) * size_t(cells) : size_t(best);
+    if (!setup_in_flight()) {
+      TPF_HIP(hipStreamSynchronize(setup_s));
+      release_stream_cache(setup_s);
+    }
+  }
+
+  // Frees device memory until in_use() + need fits the budget: idle caches
+  // first, then idle sequences (least recently used first).  Returns whether
+  // it fits.
+  bool make_room(size_t need, uint64_t keep) {
+    if (in_use() + need <= o.hbm_budget_bytes) return true;
+    trim_caches();
+    while (in_use() + need > o.hbm_budget_bytes) {
+      if (!evict_one(keep)) return false;
+      trim_caches();  // the evicted sequence's blocks went to the setup stream's cache
+    }
+    return true;
+  }
+
+  // Resident bytes and setup bytes a new sequence of `cells` cells is
+  // expected to need.  Realizations of one grid size differ, so each size
+  // keeps the largest footprint built so far, with a 10% margin:
+  //   (a) that of the smallest built size at least as large;
+  //   (b) else that of the largest smaller size, scaled by 1.25 times the
+  //       cell ratio (deeper hierarchies hold a little more per cell);
+  //   (c) before any build, and whenever it is smaller, 2 MiB plus 3 KiB per
+  //       cell for each (small grids are dominated by fixed costs, large
+  //       ones hold about 4 KiB per cell with the FP32 copies).
+  std::pair<size_t, size_t> estimate(int64_t cells) {
+    std::lock_guard<std::mutex> lk(mu);
+    std::map<int64_t, std::pair<double, double>> worst;  // cells -> largest (resident, extra)
+    for (auto& ob : seen) {
+      auto& w = worst[ob.cells];
+      if (double(ob.resident) + double(ob.extra) > w.first + w.second)
+        w = {double(ob.resident), double(ob.extra)};
+    }
+    double br = double(size_t(2) << 20) + 3072.0 * double(cells), bx = 3072.0 * double(cells);
+    double f = 0.0, er = 0.0, ex = 0.0;
+    auto up = worst.lower_bound(cells);
+    if (up != worst.end()) {
+      f = 1.1;
+      er = up->second.first;
+      ex = up->second.second;
+    } else if (!worst.empty()) {
+      auto lo = std::prev(worst.end());
+      f = 1.1 * 1.25 * double(cells) / double(lo->first);
+      er = lo->second.first;
+      ex = lo->second.second;
+    }
+    if (f > 0.0 && f * (er + ex) < br + bx) {
+      br = f * er;
+      bx = f * ex;
+    }
+    return {size_t(br), size_t(bx)};
   }
 
   bool evict_one(uint64_t keep) {
@@ -214,6 +289,13 @@ struct tpf_server {
     Resident* r = sl.res;
     const Pending& p = sl.req;
     const int64_t cells = sl.cells;
+    // blocks the setup draws, on the setup stream and the preconditioner's
+    // second setup stream (no other thread allocates on either meanwhile)
+    hipStream_t aux0 = r->M ? r->M->aux : nullptr;
+    reset_stream_held_peak(setup_s);
+    if (aux0) reset_stream_held_peak(aux0);
+    const size_t held0 = stream_held(setup_s).first + (aux0 ? stream_held(aux0).first : 0);
+    const size_t own0 = r->bytes.load();
     try {
       if (!r->J) check_rc(tpf_jacobian_create(r->prob, setup_s, &r->J));
       if (!r->M) {
@@ -232,6 +314,13 @@ struct tpf_server {
       r->built = true;
       sl.refreshed = reuse ? 1 : 0;
       r->bytes.store(r->measure());
+      // device memory drawn beyond what the sequence keeps (temporaries, now
+      // cached for the setup streams): reserved for its next setup
+      const size_t pk = stream_held(setup_s).second + (r->M->aux ? stream_held(r->M->aux).second : 0);
+      const size_t grow = pk > held0 ? pk - held0 : 0;
+      const size_t kept = r->bytes.load() - std::min(own0, r->bytes.load());
+      r->setup_extra.store(grow > kept ? grow - kept : 0);
+      r->aux.store(r->M->aux);
       sl.setup_ms = ms_since(t0);
       TPF_HIP(hipEventRecord(setup_ev, setup_s));
       TPF_HIP(hipStreamWaitEvent(sl.s, setup_ev, 0));
@@ -262,7 +351,8 @@ struct tpf_server {
       run_setup(*sl);
       {
         std::lock_guard<std::mutex> lk(mu);
-        if (sl->err_code == TPF_OK && sl->fresh) seen.emplace_back(sl->cells, sl->res->bytes.load());
+        if (sl->err_code == TPF_OK && sl->fresh)
+          seen.push_back({sl->cells, sl->res->bytes.load(), sl->res->setup_extra.load()});
         sl->state.store(sl->err_code == TPF_OK ? kReady : kFailed, std::memory_order_release);
       }
       cv_done.notify_all();
@@ -337,17 +427,21 @@ struct tpf_server {
         check_rc(tpf_problem_cells(p.rq.problem, &cells));
       }
       const size_t ws = krylov_bytes(cells, o.solve.restart);
-      const size_t est = rit == res.end() ? resident_estimate(cells) : 0;
-      const size_t need = ws + est;
+      size_t need = ws;
+      if (rit == res.end()) {
+        auto e = estimate(cells);
+        need += e.first + e.second;
+      } else {
+        need += rit->second->setup_extra.load();
+      }
       if (need > o.hbm_budget_bytes) {
         Pending bad = p;
         it = queue.erase(it);
+        set_last_error(TPF_ERR_OVER_BUDGET, "request does not fit in the HBM budget");
         finish_request(bad, TPF_ERR_OVER_BUDGET, 0, NAN, NAN, 0.0, 0.0, 0);
         continue;
       }
-      while (in_use() + need > o.hbm_budget_bytes && evict_one(p.rq.sequence)) {
-      }
-      if (in_use() + need > o.hbm_budget_bytes) {
+      if (!make_room(need, p.rq.sequence)) {
         bool any_active = false;
         for (auto& x : slots) any_active |= x->busy();
         if (any_active) return;  // waits for active solves to retire
@@ -402,8 +496,7 @@ struct tpf_server {
         // and idle sequences give way if the estimate was low
         sl.started = true;
         sl.ws_bytes = krylov_bytes(sl.cells, o.solve.restart);
-        while (in_use() > o.hbm_budget_bytes && evict_one(sl.res->seq)) {
-        }
+        make_room(0, sl.res->seq);
         note_peak();
       }
       TPF_HIP(hipEventSynchronize(sl.ev));
@@ -561,7 +654,7 @@ extern "C" int tpf_server_stats(const tpf_server* sv, tpf_server_counters* out) 
     out->resident_sequences = int(sv->res.size());
     out->submitted = sv->submitted;
     out->completed = sv->completed;
-    out->bytes_in_use = sv->in_use();
+    out->bytes_in_use = sv->held();
     out->peak_bytes = sv->peak;
     out->evictions = sv->evictions;
   });

@@ -97,6 +97,22 @@ struct SideFork {
 };
 // Returns every cached block to the upstream allocator (device idle).
 void release_cache();
+// Allocated size of a block of `bytes` bytes (its size class).
+size_t alloc_footprint(size_t bytes);
+// Bytes of freed blocks cached for stream s (allocated sizes).
+size_t cached_bytes(hipStream_t s);
+// Returns the blocks cached for stream s to the upstream allocator; no work
+// queued on s may still use them (s synchronised since they were freed).
+void release_stream_cache(hipStream_t s);
+// Bytes held from the upstream allocator (blocks in use plus cached ones, at
+// allocated sizes), and the peak of that figure since reset_held_peak().
+size_t held_bytes();
+size_t held_peak();
+void reset_held_peak();
+// The same for the blocks allocated on stream s: (held, peak since
+// reset_stream_held_peak(s)).
+std::pair<size_t, size_t> stream_held(hipStream_t s);
+void reset_stream_held_peak(hipStream_t s);
 
 // Device array; frees through the installed allocator when it owns its
 // memory (alloc), not when it views memory held elsewhere (wrap).
@@ -142,7 +158,8 @@ struct Buf {
     n = 0;
     own = true;
   }
-  size_t bytes() const { return n * sizeof(T); }
+  // device bytes the buffer occupies (its allocated size; 0 for a view)
+  size_t bytes() const { return p && own ? alloc_footprint(n * sizeof(T)) : 0; }
   T* get() const { return p; }
 };
 

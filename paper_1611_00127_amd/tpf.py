@@ -117,6 +117,9 @@ _alloc_cb = None
 _free_cb = None
 _shutting_down = False
 _alloc_calls = 0  # requests the library made to torch's allocator
+_held = {}         # pointer -> bytes the library holds from torch's allocator
+_held_bytes = 0
+_held_peak = 0
 
 
 def _mark_shutdown():
@@ -239,14 +242,20 @@ def use_torch_allocator():
     FREE = ctypes.CFUNCTYPE(None, c_void_p, c_void_p, c_void_p)
 
     def _a(nbytes, stream, ctx):
-        global _alloc_calls
+        global _alloc_calls, _held_bytes, _held_peak
         _alloc_calls += 1
         try:
-            return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+            p = torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
         except Exception:
             return None
+        _held[p] = int(nbytes)
+        _held_bytes += int(nbytes)
+        _held_peak = max(_held_peak, _held_bytes)
+        return p
 
     def _f(p, stream, ctx):
+        global _held_bytes
+        _held_bytes -= _held.pop(int(p), 0)
         if not _shutting_down:
             torch.cuda.caching_allocator_delete(int(p))
 
@@ -259,6 +268,17 @@ def allocator_calls():
     caching allocator in this process (blocks it reuses from its own cache
     are not requests)."""
     return _alloc_calls
+
+
+def allocator_bytes():
+    """(current, peak) device bytes the library holds from torch's caching
+    allocator: blocks in use plus the freed blocks it keeps cached."""
+    return _held_bytes, _held_peak
+
+
+def reset_allocator_peak():
+    global _held_peak
+    _held_peak = _held_bytes
 
 
 def init(torch_allocator=True):
