@@ -26,6 +26,13 @@ deterministic, data-parallel ones; this module states exactly those:
    a~_ii = a_ii + (off-diagonal entries of row i that are neither in C^_i
    nor strong F) + sum_k a_ik a-bar_ki / d_ik, and a strong F neighbour with
    d_ik = 0 is lumped into a~_ii;
+   or classical interpolation (Ruge, Stueben 1987; Stueben 2001, in the
+   modified form that filters signs, as BoomerAMG's classical interpolation
+   does) for an F point i: C_i = C n S_i, d_ik = sum over m in C_i of
+   a-bar_km for each strong F neighbour k (a-bar as above),
+   w_ij = -(a_ij + sum_k a_ik a-bar_kj / d_ik) / a~_ii,
+   a~_ii = a_ii + (weak off-diagonal entries of row i) + (a_ik of every
+   strong F neighbour with d_ik = 0);
 4. R = P^T, A_c = R (A P) with the symbolic pattern (no dropping);
 5. stop when n <= coarse_max, n_c == 0, n_c > 0.9 n, or max_levels; the
    coarsest level is solved by dense LU with partial pivoting when it has at
@@ -40,9 +47,16 @@ deterministic, data-parallel ones; this module states exactly those:
      lambda^ estimates the largest eigenvalue of D^{-1} A by power
      iteration from the PMIS hash vector; its error propagator is the
      scaled Chebyshev polynomial T_k((c - t)/h) / T_k(c/h), c = (hi+lo)/2,
-     h = (hi-lo)/2, in t = D^{-1} A.  The paper's own hybrid Gauss-Seidel
-     (Sec. 4.1 solver settings) is sequential; both smoothers here are
-     polynomials in A, applied row-parallel.
+     h = (hi-lo)/2, in t = D^{-1} A;
+   * multicolour Gauss-Seidel, standing in for the paper's hybrid
+     Gauss-Seidel (Sec. 4.1 solver settings), which is sequential within a
+     process: the points are coloured so that no two neighbours in the
+     pattern of A + A^T share a colour (round r colours the points whose
+     hash key beats every uncoloured neighbour's), and a sweep updates
+     x_i <- x_i + (b_i - (A x)_i) / a_ii colour by colour, in ascending
+     colour order before the coarse-grid correction and descending after
+     it.  The l1-Jacobi and Chebyshev smoothers are polynomials in A
+     applied row-parallel.
 """
 from __future__ import annotations
 
@@ -233,9 +247,67 @@ def extended_i_interpolation(A, mask, cf):
     return P, cidx
 
 
+def classical_interpolation(A, mask, cf):
+    """Classical (Ruge-Stueben) interpolation in its modified form, one F
+    row at a time (see module docstring): interpolatory set C_i = C n S_i;
+    each strong F neighbour k is distributed over C_i through the entries of
+    row k whose sign is opposite to a_kk, or lumped into the diagonal when
+    none of them falls in C_i; weak entries are lumped into the diagonal."""
+    A = A.tocsr()
+    n = A.shape[0]
+    rp, ci, av = A.indptr, A.indices, A.data
+    diag = A.diagonal()
+    s = diag_sign(A)
+    isc = cf == C_PT
+    cidx = np.cumsum(isc) - 1
+    nc = int(isc.sum())
+    r_out, c_out, v_out = [], [], []
+    for i in range(n):
+        if isc[i]:
+            r_out.append(i)
+            c_out.append(cidx[i])
+            v_out.append(1.0)
+            continue
+        row = range(rp[i], rp[i + 1])
+        ci_set = sorted(int(ci[e]) for e in row if mask[e] and isc[ci[e]])
+        strong_f = [e for e in row if mask[e] and ci[e] != i and not isc[ci[e]]]
+        w = dict.fromkeys(ci_set, 0.0)
+        atil = diag[i]
+        for e in row:
+            j = int(ci[e])
+            if j == i:
+                continue
+            if j in w and mask[e]:
+                w[j] += av[e]
+            elif not mask[e]:
+                atil += av[e]
+        for e in strong_f:
+            k = ci[e]
+            aik = av[e]
+            kr = range(rp[k], rp[k + 1])
+            d = sum(av[f] for f in kr if s[k] * av[f] < 0 and int(ci[f]) in w)
+            if d == 0.0:
+                atil += aik
+                continue
+            for f in kr:
+                m = int(ci[f])
+                if s[k] * av[f] < 0 and m in w:
+                    w[m] += aik * av[f] / d
+        for j in ci_set:
+            r_out.append(i)
+            c_out.append(cidx[j])
+            v_out.append(-w[j] / atil)
+    P = sp.csr_matrix((np.array(v_out, float), (np.array(r_out, np.int64), np.array(c_out, np.int64))),
+                      shape=(n, nc))
+    P.sort_indices()
+    return P, cidx
+
+
 def interpolation(A, mask, cf, kind):
     if kind == "ext+i":
         return extended_i_interpolation(A, mask, cf)
+    if kind == "classical":
+        return classical_interpolation(A, mask, cf)
     return direct_interpolation(A, mask, cf)
 
 
@@ -305,6 +377,51 @@ def chebyshev_smooth(A, dinv, b, x, lo, hi, degree):
     return x
 
 
+def gs_colors(A, seed):
+    """Colouring for the multicolour Gauss-Seidel smoother.  The graph is
+    the stored off-diagonal pattern of A + A^T.  Round r gives colour r to
+    every uncoloured point whose key (u_i, i) exceeds the key of each
+    uncoloured neighbour, u_i being the PMIS hash weight; points of one
+    colour are therefore never neighbours.  Returns (colour per point,
+    number of colours)."""
+    A = A.tocsr()
+    n = A.shape[0]
+    pat = sp.csr_matrix((np.ones(A.nnz), A.indices, A.indptr), shape=A.shape)
+    G = (pat + pat.T).tocsr()
+    G.setdiag(0)
+    G.eliminate_zeros()
+    G.sort_indices()
+    rows = np.repeat(np.arange(n), np.diff(G.indptr))
+    k = (splitmix64_vec(np.uint64(seed) ^ np.arange(n, dtype=np.uint64)) >> np.uint64(40)).astype(np.int64)
+    key = (k << 32) | np.arange(n, dtype=np.int64)
+    color = np.full(n, -1, np.int64)
+    r = 0
+    while (color < 0).any():
+        und = color < 0
+        nb = np.where(und[G.indices], key[G.indices], -1)
+        best = np.full(n, -1, np.int64)
+        np.maximum.at(best, rows, nb)
+        pick = und & (key > best)
+        color[pick] = r
+        r += 1
+    return color, r
+
+
+def gs_sweep(A, diag, color_rows, b, x, reverse):
+    """One multicolour Gauss-Seidel sweep, colours in ascending order
+    (backward: descending): for the points i of each colour,
+    x_i <- x_i + (b_i - (A x)_i) / a_ii with the x of the colours already
+    swept; points with a_ii = 0 are left as they are."""
+    x = x.copy()
+    order = range(len(color_rows) - 1, -1, -1) if reverse else range(len(color_rows))
+    for c in order:
+        idx, Ac = color_rows[c]
+        d = diag[idx]
+        r = b[idx] - Ac @ x
+        x[idx] += np.divide(r, d, out=np.zeros_like(r), where=d != 0)
+    return x
+
+
 class Level:
     def __init__(self, A):
         self.A = A.tocsr()
@@ -318,8 +435,13 @@ class Level:
         self.mask = None
         self.cf = None
         self.cheb = None  # (lo, hi) of the Chebyshev smoother
+        self.gs = None    # (colour per point, [(points, their rows of A)] per colour)
 
-    def smooth(self, b, x, H):
+    def smooth(self, b, x, H, post=False):
+        # multicolour Gauss-Seidel: forward sweeps before the coarse-grid
+        # correction, backward after it (a symmetric cycle)
+        if H.smoother == "gs":
+            return gs_sweep(self.A, self.A.diagonal(), self.gs[1], b, x, reverse=post)
         # a zero eigenvalue estimate (D^{-1} A = 0) leaves l1-Jacobi sweeps
         if H.smoother == "chebyshev" and self.cheb[1] > 0.0:
             lo, hi = self.cheb
@@ -365,6 +487,11 @@ class Hierarchy:
             for L in self.levels[:-1]:
                 lam = power_max_eig(L.A, L.dinv, self.cheb_eig_iters, self.seed)
                 L.cheb = chebyshev_bounds(lam)
+        if self.smoother == "gs":
+            for L in self.levels[:-1]:
+                color, nc = gs_colors(L.A, self.seed)
+                rows = [np.flatnonzero(color == c) for c in range(nc)]
+                L.gs = (color, [(idx, L.A[idx]) for idx in rows])
 
     def coarse_solve(self, b):
         last = self.levels[-1]
@@ -385,7 +512,7 @@ class Hierarchy:
         xc = self.vcycle(L.R @ r, level + 1)
         x = x + L.P @ xc
         for _ in range(self.nu2):
-            x = L.smooth(b, x, self)
+            x = L.smooth(b, x, self, post=True)
         return x
 
     def stats(self):

@@ -252,6 +252,100 @@ def test_extended_i_non_m_matrix_hand_weights():
     assert np.diff(P.indptr)[4] == 0 and np.diff(P.indptr)[5] == 0
 
 
+def test_classical_interpolation_non_m_matrix_hand_weights():
+    """Classical (modified Ruge-Stueben) interpolation on the same matrix,
+    weights worked out by hand.
+
+    Row 0: C_0 = {1} (point 3 is a weak C neighbour).  Strong F neighbour 2:
+    row 2 keeps its positive entries (a_22 = -5), and its only entry in C_0,
+    a_21 = -1, is negative, so d_02 = 0 and a_02 = -4 is lumped; strong F
+    neighbour 5 has no entry in C_0, so a_05 = -2 is lumped too.  The weak
+    entries a_03 = -0.5 and a_04 = +1 are lumped:
+      a~_00 = 10 - 0.5 + 1 - 4 - 2 = 4.5,  w_01 = -(-4) / 4.5 = 8/9.
+    Row 2: C_2 = {3}.  Strong F neighbour 0 keeps its negative entries
+    (a_00 > 0); in C_2 that is a_03 = -0.5 = d_20, so a_20 = 2 moves to point 3
+    in full; the weak entry a_21 = -1 is lumped:
+      a~_22 = -5 - 1 = -6,  w_23 = -(1.5 + 2 (-0.5) / (-0.5)) / (-6) = 7/12.
+    Using a_ii's sign for the filter, or leaving the weak or d = 0 entries
+    out of a~_ii, moves both weights."""
+    A, cf = _non_m_matrix()
+    mask = amg.strength(A, 0.25)
+    P, cidx = amg.classical_interpolation(A, mask, cf)
+    Pd = P.toarray()
+    np.testing.assert_allclose(Pd[0], [8 / 9, 0.0], rtol=1e-15)
+    np.testing.assert_allclose(Pd[2], [0.0, 7 / 12], rtol=1e-15)
+    np.testing.assert_array_equal(Pd[[1, 3]], np.eye(2))
+    assert np.diff(P.indptr)[4] == 0 and np.diff(P.indptr)[5] == 0
+
+
+def test_classical_interpolation_closed_forms():
+    """1D Laplacian: C F C gives (1/2, 1/2); in C F F C the F points have no
+    common C point (d = 0), so each takes its one C neighbour with weight 1.
+    On a zero-row-sum M-matrix every F row with a nonempty interpolatory set
+    sums to exactly 1 whether or not a strong F neighbour is lumped:
+    -(sum_C a_ij + sum_k a_ik) = a_ii + weak + lumped = a~_ii."""
+    n = 10
+    A = sp.diags([-np.ones(n - 1), 2 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1]).tocsr()
+    mask = amg.strength(A, 0.25)
+    cf = np.array([1, 2, 1, 2, 2, 1, 2, 2, 1, 1], np.int8)
+    Pd = amg.classical_interpolation(A, mask, cf)[0].toarray()
+    np.testing.assert_allclose(Pd[1, [0, 1]], [0.5, 0.5], rtol=1e-15)
+    np.testing.assert_allclose(Pd[3], [0, 1, 0, 0, 0], rtol=0, atol=0)
+    np.testing.assert_allclose(Pd[4], [0, 0, 1, 0, 0], rtol=0, atol=0)
+    L = _laplace2d(9).tolil()
+    L = sp.csr_matrix(L)
+    L = (L - sp.diags(np.asarray(L.sum(axis=1)).ravel())).tocsr()
+    L.sort_indices()
+    m = amg.strength(L, 0.25)
+    cf2, _ = amg.pmis(L, m, 3)
+    P2, _ = amg.classical_interpolation(L, m, cf2)
+    rs = np.asarray(P2.sum(axis=1)).ravel()
+    nonempty = np.diff(P2.indptr) > 0
+    assert nonempty.sum() == L.shape[0]
+    np.testing.assert_allclose(rs, 1.0, rtol=1e-13)
+    # the same rows and columns as direct interpolation (C n S_i)
+    Pdir, _ = amg.direct_interpolation(L, m, cf2)
+    np.testing.assert_array_equal(P2.indptr, Pdir.indptr)
+    np.testing.assert_array_equal(P2.indices, Pdir.indices)
+
+
+def test_gs_coloring_and_sweeps_are_triangular_solves():
+    """Multicolour Gauss-Seidel on a nonsymmetric TPFA block: no two
+    neighbours of A + A^T share a colour, and a forward sweep equals the
+    Gauss-Seidel step of A with its rows and columns ordered by colour,
+    x' = (D + L)^{-1}(b - U x) (L, U strictly lower/upper in that order), a
+    backward sweep (D + U)^{-1}(b - L x); the order inside a colour does not
+    matter."""
+    c, rp, ci, v = _small(7, 6, 2, seed=8)
+    A = blocks.block(rp, ci, v, 0, 1) + blocks.block(rp, ci, v, 0, 0)
+    A = A.tocsr()
+    A.sort_indices()
+    n = A.shape[0]
+    color, nc = amg.gs_colors(A, 0x5eed)
+    assert nc >= 2 and (color >= 0).all() and color.max() == nc - 1
+    Ad = A.toarray()
+    nbr = (Ad != 0) | (Ad.T != 0)
+    np.fill_diagonal(nbr, False)
+    ii, jj = np.nonzero(nbr)
+    assert (color[ii] != color[jj]).all()
+    perm = np.lexsort((np.arange(n), color))
+    Ap = Ad[np.ix_(perm, perm)]
+    Lo, Up, D = np.tril(Ap, -1), np.triu(Ap, 1), np.diag(np.diag(Ap))
+    rng = np.random.default_rng(2)
+    b, x = rng.standard_normal(n), rng.standard_normal(n)
+    rows = [(np.flatnonzero(color == k), A[np.flatnonzero(color == k)]) for k in range(nc)]
+    fwd = amg.gs_sweep(A, A.diagonal(), rows, b, x, reverse=False)
+    bwd = amg.gs_sweep(A, A.diagonal(), rows, b, x, reverse=True)
+    ref_f = np.linalg.solve(D + Lo, b[perm] - Up @ x[perm])
+    ref_b = np.linalg.solve(D + Up, b[perm] - Lo @ x[perm])
+    np.testing.assert_allclose(fwd[perm], ref_f, rtol=1e-12, atol=1e-12 * np.abs(ref_f).max())
+    np.testing.assert_allclose(bwd[perm], ref_b, rtol=1e-12, atol=1e-12 * np.abs(ref_b).max())
+    # within a colour the order is irrelevant: reversing it changes nothing
+    rows_rev = [(idx[::-1].copy(), A[idx[::-1]]) for idx, _ in rows]
+    np.testing.assert_allclose(amg.gs_sweep(A, A.diagonal(), rows_rev, b, x, False), fwd,
+                               rtol=1e-14, atol=1e-14 * np.abs(fwd).max())
+
+
 def test_extended_i_restores_scalable_schur_cycle():
     """On the heterogeneous S~ of the 3D workload family the direct
     interpolation cycle degrades with the grid while extended+i stays flat
@@ -348,9 +442,11 @@ def test_chebyshev_polynomial_on_diagonal_operator():
     assert lam <= t.max()
 
 
-@pytest.mark.parametrize("smoother,nu", [("l1jacobi", 2), ("chebyshev", 1), ("chebyshev", 2)])
+@pytest.mark.parametrize("smoother,nu", [("l1jacobi", 2), ("chebyshev", 1), ("chebyshev", 2),
+                                         ("gs", 1), ("gs", 2)])
 def test_vcycle_variants_symmetric_and_convergent(smoother, nu):
-    """V(nu, nu) with l1-Jacobi or Chebyshev: for a symmetric matrix the cycle
+    """V(nu, nu) with l1-Jacobi, Chebyshev or multicolour Gauss-Seidel
+    (forward sweeps before, backward after): for a symmetric matrix the cycle
     operator B is symmetric (the post-smoother is the pre-smoother's adjoint),
     and the stationary iteration x <- x + B(b - A x) converges: the spectral
     radius of I - B A is below 1 and no larger than with V(1,1) l1-Jacobi."""
