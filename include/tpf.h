@@ -167,11 +167,19 @@ int tpf_norm2(const double* x, int64_t n, double* out, void* stream);
 #define TPF_INTERP_AUTO 0    /* extended+i for S~ and A_pp; direct for A_ss and the scalar J */
 #define TPF_INTERP_DIRECT 1  /* direct (distance-one) interpolation everywhere */
 #define TPF_INTERP_EXTI 2    /* extended+i (distance-two) interpolation everywhere */
+#define TPF_INTERP_CLASSICAL 3  /* classical (modified Ruge-Stueben) interpolation everywhere,
+                                   the paper's BoomerAMG setting (Sec. 4.1): strong C
+                                   neighbours, strong F neighbours distributed over them */
 
 #define TPF_SMOOTH_L1_JACOBI 0  /* x <- x + D^{-1}(b - A x), D the l1 diagonal */
 #define TPF_SMOOTH_CHEBYSHEV 1  /* Chebyshev polynomial of degree cheb_degree in D^{-1} A on
                                    [0.3 hi, hi], hi = 1.1 x a 10-step power estimate of its
                                    largest eigenvalue */
+#define TPF_SMOOTH_MC_GS 2      /* multicolour Gauss-Seidel, standing in for the paper's hybrid
+                                   Gauss-Seidel (Sec. 4.1): points coloured so that no two
+                                   neighbours of A + A^T share a colour, x_i += (b_i - (A x)_i)
+                                   / a_ii colour by colour, ascending before the coarse-grid
+                                   correction and descending after it; a step is one sweep */
 
 #define TPF_FP64 0       /* hierarchy and V-cycle in FP64 */
 #define TPF_FP32 1       /* hierarchy stored and V-cycle/ILU solves run in FP32; coarsest in FP64 */
@@ -241,6 +249,8 @@ typedef struct tpf_csr_view {
 #define TPF_MAT_P 1       /* interpolation (level -> level+1) */
 #define TPF_MAT_R 2       /* restriction P^T */
 #define TPF_MAT_S 3       /* strength graph (pattern only) */
+#define TPF_MAT_GS_COLORS 4  /* Gauss-Seidel colours: row c lists the points of colour c
+                                (order inside a colour unspecified); n_rows = colours */
 #define TPF_MAT_APS 10    /* A_ps block (level ignored) */
 #define TPF_MAT_SCHUR 11  /* S~ (BF) */
 /* View of matrix `which` of hierarchy `hier` at `level` (FP64 copy). */

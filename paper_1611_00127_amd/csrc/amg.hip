@@ -382,6 +382,131 @@ __global__ void __launch_bounds__(256) k_interp_fill(int n, const int* __restric
   }
 }
 
+// ---------------------------------------------------------------- classical
+// Position of column `key` in the sorted columns ci[lo..hi), or -1.
+__device__ inline int find_col(const int* __restrict__ ci, int lo, int hi, int key) {
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const int c = ci[mid];
+    if (c == key) return mid;
+    if (c < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return -1;
+}
+
+// Classical (modified Ruge-Stueben) interpolation weights, LPR lanes per
+// row; the pattern is direct interpolation's (C n S_i), counted by
+// k_interp_count.  For an F row i:
+//   1. the strong C entries are written in row order with a_ij as the
+//      running numerator (fine column index for now); the diagonal a~_ii
+//      starts as a_ii plus the weak off-diagonal entries;
+//   2. every strong F neighbour k, in row order: d = sum of the entries of
+//      row k whose sign is opposite to a_kk and whose column is in C_i;
+//      d = 0 lumps a_ik into a~_ii, else each P entry j gains
+//      a_ik a_kj / d when a_kj has that sign;
+//   3. w_ij = -numerator / a~_ii, columns renumbered to coarse indices.
+// Lane l owns the P entries l, l + LPR, ... in steps 2 and 3.
+template <int LPR>
+__global__ void __launch_bounds__(256) k_classical_fill(int n, const int* __restrict__ rp,
+                                                        const int* __restrict__ ci,
+                                                        const double* __restrict__ v,
+                                                        const uint8_t* __restrict__ mask,
+                                                        const int8_t* __restrict__ cf,
+                                                        const int* __restrict__ cidx,
+                                                        const int* __restrict__ prp,
+                                                        int* __restrict__ pci,
+                                                        double* __restrict__ pv) {
+  int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int i = int(gid / LPR), lane = int(gid % LPR);
+  const bool live = i < n;
+  const bool crow = live && cf[i] == kC;
+  int a0 = 0, a1 = 0, o = 0, np = 0;
+  if (live) {
+    o = prp[i];
+    np = prp[i + 1] - o;
+    if (!crow) {
+      a0 = rp[i];
+      a1 = rp[i + 1];
+    }
+  }
+  if (crow && lane == 0) {
+    pci[o] = cidx[i];
+    pv[o] = 1.0;
+  }
+  // step 1
+  double dpart = 0.0;
+  for (int base = a0; base < a1; base += LPR) {
+    const int e = base + lane;
+    int j = -1;
+    bool f = false;
+    if (e < a1) {
+      j = ci[e];
+      if (j == i)
+        dpart += v[e];
+      else if (!mask[e])
+        dpart += v[e];
+      else
+        f = cf[j] == kC;
+    }
+    const unsigned long long g = group_ballot<LPR>(f);
+    if (f) {
+      const int q = o + __popcll(g & ((1ull << lane) - 1ull));
+      pci[q] = j;
+      pv[q] = v[e];
+    }
+    o += __popcll(g);
+  }
+  double atil = group_sum<LPR>(dpart);
+  o -= np;  // back to the row start (C rows: a0 == a1, o unchanged)
+  __threadfence_block();  // the group reads the entries its lanes wrote
+  // step 2
+  for (int base = a0; base < a1; base += LPR) {
+    const int e = base + lane;
+    const bool sf = e < a1 && mask[e] && ci[e] != i && cf[ci[e]] != kC;
+    unsigned long long g = group_ballot<LPR>(sf);
+    while (g) {
+      const int src = __ffsll(static_cast<long long>(g)) - 1;
+      g &= g - 1;
+      const int ek = base + src;  // the strong F entry (same in every lane)
+      const int k = ci[ek];
+      const double aik = v[ek];
+      const int k0 = rp[k], k1 = rp[k + 1];
+      double akk = 0.0;
+      for (int f = k0 + lane; f < k1; f += LPR)
+        if (ci[f] == k) akk += v[f];
+      akk = group_sum<LPR>(akk);
+      const double sk = akk < 0.0 ? -1.0 : 1.0;
+      double d = 0.0;
+      for (int f = k0 + lane; f < k1; f += LPR) {
+        const int m = ci[f];
+        const double a = v[f];
+        if (sk * a < 0.0 && cf[m] == kC) {
+          const int pos = find_col(ci, a0, a1, m);
+          if (pos >= 0 && mask[pos]) d += a;
+        }
+      }
+      d = group_sum<LPR>(d);
+      if (d == 0.0) {
+        atil += aik;
+        continue;
+      }
+      for (int q = o + lane; q < o + np; q += LPR) {
+        const int pos = find_col(ci, k0, k1, pci[q]);
+        if (pos >= 0 && sk * v[pos] < 0.0) pv[q] += aik * v[pos] / d;
+      }
+    }
+  }
+  // step 3
+  if (!crow && live)
+    for (int q = o + lane; q < o + np; q += LPR) {
+      pv[q] = -pv[q] / atil;
+      pci[q] = cidx[pci[q]];
+    }
+}
+
 // ---------------------------------------------------------------- extended+i
 // Interpolation set of an F point i: strong C neighbours of i and of every
 // strong F neighbour k, merged in ascending fine index by advancing one
@@ -1740,7 +1865,7 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
     }
     L.pmis_rounds = rounds;
     if (nc == 0 || double(nc) > 0.9 * double(n)) break;
-    // interpolation: direct, or extended+i
+    // interpolation: direct, classical, or extended+i
     L.P.nrows = n;
     L.P.ncols = int(nc);
     L.P.rp.alloc(n + 1, s);
@@ -1826,10 +1951,18 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
       L.P.nnz = scan_exclusive(cnt.p, L.P.rp.p, n, s);
       L.P.ci.alloc(L.P.nnz, s);
       L.P.v.alloc(L.P.nnz, s);
-      DISPATCH_LPR(lpr, LL, {
-        k_interp_fill<LL><<<rblocks, 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.A.v.p, L.mask.p,
-                                                  L.cf.p, cidx.p, L.P.rp.p, L.P.ci.p, L.P.v.p);
-      });
+      if (o.classical) {
+        DISPATCH_LPR(lpr, LL, {
+          k_classical_fill<LL><<<rblocks, 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.A.v.p, L.mask.p,
+                                                       L.cf.p, cidx.p, L.P.rp.p, L.P.ci.p,
+                                                       L.P.v.p);
+        });
+      } else {
+        DISPATCH_LPR(lpr, LL, {
+          k_interp_fill<LL><<<rblocks, 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.A.v.p, L.mask.p,
+                                                    L.cf.p, cidx.p, L.P.rp.p, L.P.ci.p, L.P.v.p);
+        });
+      }
       TPF_CHECK_LAUNCH();
     }
     transpose(ref(L.P), L.R, s);
@@ -1890,6 +2023,7 @@ void Hierarchy::finish_levels(hipStream_t st) {
       L.xb.ensure(n, st);
       if (o.smoother == 1) L.dd.ensure(n, st);
       if (o.smoother == 1) chebyshev_setup(L, st);
+      if (o.smoother == 2) gs_setup(L, st);
     }
     if (o.fp32) {
       L.Av32.ensure(L.A.nnz, st);
@@ -1953,6 +2087,88 @@ void Hierarchy::finish_levels(hipStream_t st) {
 // lambda^ from cheb_eig_iters power steps started at the PMIS hash vector
 // (the estimate is ||w|| of the last step).  A zero estimate (D^{-1} A = 0)
 // leaves the level with l1-Jacobi sweeps.
+// ---------------------------------------------------------------- multicolour Gauss-Seidel
+// Key of point i: the 24-bit PMIS hash weight above the index, so keys are
+// distinct and ordered as (u_i, i).
+__global__ void k_gs_keys(int n, uint64_t seed, int64_t* __restrict__ key) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t h = splitmix64(seed ^ uint64_t(i)) >> 40;
+  key[i] = int64_t((h << 32) | uint64_t(i));
+}
+
+// One colouring round r: an uncoloured point takes colour r when its key
+// beats that of every neighbour in the patterns of A and A^T that was
+// uncoloured when the round began (a neighbour coloured in this round still
+// counts, so the picked points are independent whatever the thread order).
+// *flag is set when a point stays uncoloured.
+__global__ void __launch_bounds__(256) k_gs_color_round(int n, const int* __restrict__ rp,
+                                                        const int* __restrict__ ci,
+                                                        const int* __restrict__ trp,
+                                                        const int* __restrict__ tci,
+                                                        const int64_t* __restrict__ key,
+                                                        int* __restrict__ color, int r,
+                                                        int* __restrict__ flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || color[i] >= 0) return;
+  const int64_t ki = key[i];
+  bool best = true;
+  for (int e = rp[i]; e < rp[i + 1] && best; ++e) {
+    const int j = ci[e];
+    const int cj = color[j];
+    if (j != i && (cj < 0 || cj == r) && key[j] > ki) best = false;
+  }
+  for (int e = trp[i]; e < trp[i + 1] && best; ++e) {
+    const int j = tci[e];
+    const int cj = color[j];
+    if (j != i && (cj < 0 || cj == r) && key[j] > ki) best = false;
+  }
+  if (best)
+    color[i] = r;
+  else
+    *flag = 1;
+}
+
+__global__ void k_gs_color_count(int n, const int* __restrict__ color, int* __restrict__ cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) atomicAdd(&cnt[color[i]], 1);
+}
+
+__global__ void k_gs_color_place(int n, const int* __restrict__ color, int* __restrict__ pos,
+                                 int* __restrict__ rows) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) rows[atomicAdd(&pos[color[i]], 1)] = i;
+}
+
+// 1/a_ii, 0 where the diagonal is zero or absent
+__global__ void k_plain_dinv(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                             const double* __restrict__ v, double* __restrict__ d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double a = 0.0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e)
+    if (ci[e] == i) a += v[e];
+  d[i] = a != 0.0 ? 1.0 / a : 0.0;
+}
+
+// One colour of a Gauss-Seidel sweep: x_i += (b_i - (A x)_i) / a_ii for the
+// m points rows[0..m), LPR lanes per row.  No two points of a colour are
+// neighbours, so each update reads only other colours' values.
+template <class T, int LPR>
+__global__ void __launch_bounds__(256) k_gs_color(int m, const int* __restrict__ rows,
+                                                  const int* __restrict__ rp,
+                                                  const int* __restrict__ ci,
+                                                  const T* __restrict__ v,
+                                                  const T* __restrict__ gd,
+                                                  const T* __restrict__ b, T* __restrict__ x) {
+  int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int t = int(gid / LPR), lane = int(gid % LPR);
+  if (t >= m) return;
+  const int i = rows[t];
+  T sum = row_dot<T, LPR>(i, lane, rp, ci, v, [&](int j) { return x[j]; });
+  if (lane == 0) x[i] += gd[i] * (b[i] - sum);
+}
+
 void Hierarchy::chebyshev_setup(Level& L, hipStream_t st) {
   const int n = L.A.nrows;
   Buf<double> v(n, st), w(n, st);
@@ -1981,14 +2197,98 @@ void Hierarchy::chebyshev_setup(Level& L, hipStream_t st) {
   L.cheb_lo = 0.3 * L.cheb_hi;
 }
 
+// Colouring, colour lists and 1/a_ii of level L for the multicolour
+// Gauss-Seidel smoother.  Rounds run in batches of eight per read-back;
+// rounds after the last point is coloured change nothing.
+void Hierarchy::gs_setup(Level& L, hipStream_t st) {
+  const int n = L.A.nrows;
+  L.gsd.ensure(n, st);
+  k_plain_dinv<<<grid_for(n, 256), 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, L.A.v.p, L.gsd.p);
+  TPF_CHECK_LAUNCH();
+  if (int(L.gs_ptr.size()) == 0 || L.gs_rows.n != size_t(n)) {
+    Csr<double> AT;
+    transpose(CsrRef<double>{n, n, L.A.nnz, L.A.rp.p, L.A.ci.p, nullptr}, AT, st);
+    Buf<int64_t> key(n, st);
+    Buf<int> color(n, st);
+    k_gs_keys<<<grid_for(n, 256), 256, 0, st>>>(n, o.seed, key.p);
+    TPF_CHECK_LAUNCH();
+    fill_int(color.p, -1, n, st);
+    constexpr int kBatch = 8;
+    int* hflag = host_counts_slot();
+    int ncolors = 0;
+    for (int r0 = 0; ncolors == 0; r0 += kBatch) {
+      TPF_REQUIRE(r0 <= n, TPF_ERR_INVALID_ARG, "colouring did not terminate");
+      Buf<int> flag(kBatch, st);
+      fill_int(flag.p, 0, kBatch, st);
+      for (int k = 0; k < kBatch; ++k) {  // flag[k]: a point is left after round r0 + k
+        k_gs_color_round<<<grid_for(n, 256), 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, AT.rp.p,
+                                                           AT.ci.p, key.p, color.p, r0 + k,
+                                                           flag.p + k);
+        TPF_CHECK_LAUNCH();
+      }
+      TPF_HIP(hipMemcpyAsync(hflag, flag.p, kBatch * sizeof(int), hipMemcpyDeviceToHost, st));
+      TPF_HIP(hipStreamSynchronize(st));
+      for (int k = 0; k < kBatch; ++k)
+        if (hflag[k] == 0) {
+          ncolors = r0 + k + 1;
+          break;
+        }
+    }
+    Buf<int> cnt(ncolors, st), pos(ncolors + 1, st);
+    fill_int(cnt.p, 0, ncolors, st);
+    k_gs_color_count<<<grid_for(n, 256), 256, 0, st>>>(n, color.p, cnt.p);
+    TPF_CHECK_LAUNCH();
+    scan_exclusive(cnt.p, pos.p, ncolors, st);  // synchronises
+    L.gs_ptr.assign(ncolors + 1, 0);
+    TPF_HIP(hipMemcpyAsync(L.gs_ptr.data(), pos.p, (ncolors + 1) * sizeof(int),
+                           hipMemcpyDeviceToHost, st));
+    TPF_HIP(hipStreamSynchronize(st));
+    L.gs_ptr_dev.alloc(ncolors + 1, st);
+    copy(L.gs_ptr_dev.p, pos.p, ncolors + 1, st);
+    L.gs_rows.alloc(n, st);
+    k_gs_color_place<<<grid_for(n, 256), 256, 0, st>>>(n, color.p, pos.p, L.gs_rows.p);
+    TPF_CHECK_LAUNCH();
+  }
+  if (o.fp32) {
+    L.gsd32.ensure(n, st);
+    cast<double, float>(L.gsd32.p, L.gsd.p, n, st);
+  }
+}
+
 // `steps` smoothing steps (each one l1-Jacobi sweep, or one Chebyshev
 // polynomial of degree cheb_degree) on L from x0 (null: the zero iterate);
 // the final iterate goes to `out`, the intermediate ones alternate between
 // spare0 and spare1 (all distinct from x0 and out).
 template <class T>
 const T* Hierarchy::smooth(Level& L, const T* b, const T* x0, T* out, T* spare0, T* spare1,
-                           int steps, hipStream_t st) {
+                           int steps, bool post, hipStream_t st) {
   const int n = L.A.nrows;
+  if (o.smoother == 2) {  // multicolour Gauss-Seidel, in place in `out`
+    if (x0)
+      copy(out, x0, n, st);
+    else
+      fill(out, T(0), n, st);
+    const T* Av = vals_of<T>(L.A, L.Av32);
+    const T* gd;
+    if constexpr (std::is_same<T, float>::value)
+      gd = L.gsd32.p;
+    else
+      gd = L.gsd.p;
+    const int lpr = lanes_per_row(n, L.A.nnz);
+    const int nc = int(L.gs_ptr.size()) - 1;
+    for (int k = 0; k < steps; ++k)
+      for (int q = 0; q < nc; ++q) {
+        const int c = post ? nc - 1 - q : q;
+        const int m = L.gs_ptr[c + 1] - L.gs_ptr[c];
+        if (m == 0) continue;
+        DISPATCH_LPR(lpr, LL, {
+          k_gs_color<T, LL><<<grid_for(int64_t(m) * LL, 256), 256, 0, st>>>(
+              m, L.gs_rows.p + L.gs_ptr[c], L.A.rp.p, L.A.ci.p, Av, gd, b, out);
+        });
+        TPF_CHECK_LAUNCH();
+      }
+    return out;
+  }
   const bool cheb = o.smoother == 1 && L.cheb_hi > 0.0;
   const int per = cheb ? o.cheb_degree : 1;
   const int sweeps = steps * per;
@@ -2111,7 +2411,7 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st) {
     const T* xpre = nullptr;
     {
       TimedScope ts(L.t_pre.c_str(), st);
-      if (o.nu1 > 0) xpre = smooth<T>(L, b, nullptr, xa, xb, r, o.nu1, st);
+      if (o.nu1 > 0) xpre = smooth<T>(L, b, nullptr, xa, xb, r, o.nu1, false, st);
       if (xpre) {
         DISPATCH_LPR(lpr, LL, {
           k_vc_pre_g<T, LL><<<blocks, 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, Av, xpre, b, r);
@@ -2134,7 +2434,7 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st) {
     }
     {
       TimedScope ts(L.t_post.c_str(), st);
-      smooth<T>(L, b, y, x, xa, xb, o.nu2, st);
+      smooth<T>(L, b, y, x, xa, xb, o.nu2, true, st);
     }
     return;
   }
@@ -2279,9 +2579,9 @@ void Hierarchy::vcycle(const T* b, T* x, hipStream_t st) {
 }
 
 template const double* Hierarchy::smooth<double>(Level&, const double*, const double*, double*,
-                                                 double*, double*, int, hipStream_t);
+                                                  double*, double*, int, bool, hipStream_t);
 template const float* Hierarchy::smooth<float>(Level&, const float*, const float*, float*, float*,
-                                               float*, int, hipStream_t);
+                                               float*, int, bool, hipStream_t);
 template void Hierarchy::vcycle<double>(const double*, double*, hipStream_t);
 template void Hierarchy::vcycle<float>(const float*, float*, hipStream_t);
 

@@ -15,8 +15,9 @@ struct AmgOpts {
   uint64_t seed = 0x5eed;
   bool fp32 = false;
   bool ext_i = false;   // extended+i instead of direct interpolation
+  bool classical = false;  // classical (modified Ruge-Stueben) instead of direct
   int exti_first = 0;   // extended+i rows start the kernel-class search here (tests)
-  int smoother = 0;     // 0 l1-Jacobi, 1 Chebyshev on D^{-1} A
+  int smoother = 0;     // 0 l1-Jacobi, 1 Chebyshev on D^{-1} A, 2 multicolour Gauss-Seidel
   int nu1 = 1, nu2 = 1; // pre- and post-smoothing steps
   int cheb_degree = 2;
   int cheb_eig_iters = 10;  // power steps estimating the top eigenvalue of D^{-1} A
@@ -40,6 +41,13 @@ struct Level {
   Buf<double> xa, xb, dd;
   Buf<float> xa32, xb32, dd32;
   double cheb_lo = 0.0, cheb_hi = 0.0;
+  // multicolour Gauss-Seidel: the points sorted by colour (order inside a
+  // colour unspecified), colour c's at gs_rows[gs_ptr[c] .. gs_ptr[c+1]),
+  // gs_ptr on the host and on the device, and 1/a_ii (0 where a_ii = 0)
+  Buf<int> gs_rows, gs_ptr_dev;
+  std::vector<int> gs_ptr;
+  Buf<double> gsd;
+  Buf<float> gsd32;
   // workspace: r, y always; b, x on levels >= 1
   Buf<double> r, y, b, x;
   Buf<float> r32, y32, b32, x32;
@@ -98,9 +106,10 @@ struct Hierarchy {
   void finish_levels(hipStream_t st);
   void coarse_setup(hipStream_t st);
   void chebyshev_setup(Level& L, hipStream_t st);
+  void gs_setup(Level& L, hipStream_t st);
   template <class T>
   const T* smooth(Level& L, const T* b, const T* x0, T* out, T* spare0, T* spare1, int steps,
-                  hipStream_t st);
+                  bool post, hipStream_t st);
   template <class T>
   void vcycle_level(int l, const T* b, T* x, hipStream_t st);
 };

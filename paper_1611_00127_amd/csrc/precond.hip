@@ -744,6 +744,7 @@ void schur_on_grid(tpf_precond* M, const Phys& ph, Csr<double>& S, bool pattern_
 AmgOpts amg_opts(const tpf_precond_opts& o, bool pressure_like) {
   AmgOpts a;
   a.ext_i = o.interp == TPF_INTERP_EXTI || (o.interp == TPF_INTERP_AUTO && pressure_like);
+  a.classical = o.interp == TPF_INTERP_CLASSICAL;
   a.exti_first = o.exti_route > 0 ? o.exti_route - 1 : 0;
   a.theta = o.theta;
   a.max_levels = o.max_levels;
@@ -1041,11 +1042,12 @@ int tpf_precond_create(const tpf_precond_opts* o, tpf_precond** out) {
     TPF_REQUIRE(o->coarse_max >= 1 && o->dense_max >= 1 && o->dense_max <= 4096,
                 TPF_ERR_INVALID_ARG, "coarse_max >= 1 and 1 <= dense_max <= 4096 required");
     TPF_REQUIRE(o->theta > 0 && o->theta < 1, TPF_ERR_INVALID_ARG, "theta must be in (0,1)");
-    TPF_REQUIRE(o->interp >= TPF_INTERP_AUTO && o->interp <= TPF_INTERP_EXTI, TPF_ERR_INVALID_ARG,
+    TPF_REQUIRE(o->interp >= TPF_INTERP_AUTO && o->interp <= TPF_INTERP_CLASSICAL, TPF_ERR_INVALID_ARG,
                 "unknown interpolation");
     TPF_REQUIRE(o->exti_route >= 0 && o->exti_route <= 8, TPF_ERR_INVALID_ARG,
                 "exti_route must be in [0, 8]");
-    TPF_REQUIRE(o->smoother == TPF_SMOOTH_L1_JACOBI || o->smoother == TPF_SMOOTH_CHEBYSHEV,
+    TPF_REQUIRE(o->smoother == TPF_SMOOTH_L1_JACOBI || o->smoother == TPF_SMOOTH_CHEBYSHEV ||
+                    o->smoother == TPF_SMOOTH_MC_GS,
                 TPF_ERR_INVALID_ARG, "unknown smoother %d", o->smoother);
     TPF_REQUIRE(o->nu1 >= 0 && o->nu1 <= 4 && o->nu2 >= 0 && o->nu2 <= 4 && o->nu1 + o->nu2 >= 1,
                 TPF_ERR_INVALID_ARG, "nu1, nu2 must be in [0, 4] with nu1 + nu2 >= 1");
@@ -1273,6 +1275,17 @@ int tpf_precond_matrix(const tpf_precond* M, int hier, int level, int which, tpf
     const Hierarchy& H = *M->H[hier];
     TPF_REQUIRE(level >= 0 && level < H.levels(), TPF_ERR_INVALID_ARG, "level out of range");
     const Level& L = *H.lv[level];
+    if (which == TPF_MAT_GS_COLORS) {
+      TPF_REQUIRE(L.gs_rows.p != nullptr, TPF_ERR_INVALID_ARG,
+                  "no Gauss-Seidel colouring on this level");
+      out->n_rows = int(L.gs_ptr.size()) - 1;
+      out->n_cols = L.A.nrows;
+      out->nnz = L.A.nrows;
+      out->row_ptr = L.gs_ptr_dev.p;
+      out->col_idx = L.gs_rows.p;
+      out->vals = nullptr;
+      return;
+    }
     const Csr<double>* C = nullptr;
     switch (which) {
       case TPF_MAT_A: C = &L.A; break;

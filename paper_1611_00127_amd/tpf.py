@@ -21,12 +21,13 @@ TPF_OK = 0
 TPF_PC_BROOKS_COREY, TPF_PC_LINEAR = 0, 1
 TPF_PREC_AMG, TPF_PREC_CPR1, TPF_PREC_CPR2, TPF_PREC_BF, TPF_PREC_NONE = 0, 1, 2, 3, 4
 TPF_FP64, TPF_FP32 = 0, 1
-TPF_SMOOTH_L1_JACOBI, TPF_SMOOTH_CHEBYSHEV = 0, 1
+TPF_SMOOTH_L1_JACOBI, TPF_SMOOTH_CHEBYSHEV, TPF_SMOOTH_MC_GS = 0, 1, 2
 TPF_CONVERGED, TPF_MAX_ITERS, TPF_BREAKDOWN, TPF_NONFINITE, TPF_CANCELLED = 0, 1, 2, 3, 4
 TPF_ERR_OVER_BUDGET = -5
-TPF_MAT_A, TPF_MAT_P, TPF_MAT_R, TPF_MAT_S, TPF_MAT_APS, TPF_MAT_SCHUR = 0, 1, 2, 3, 10, 11
+TPF_MAT_A, TPF_MAT_P, TPF_MAT_R, TPF_MAT_S, TPF_MAT_GS_COLORS = 0, 1, 2, 3, 4
+TPF_MAT_APS, TPF_MAT_SCHUR = 10, 11
 TPF_MAX_LEVELS = 25
-TPF_INTERP_AUTO, TPF_INTERP_DIRECT, TPF_INTERP_EXTI = 0, 1, 2
+TPF_INTERP_AUTO, TPF_INTERP_DIRECT, TPF_INTERP_EXTI, TPF_INTERP_CLASSICAL = 0, 1, 2, 3
 KINDS = {"amg": TPF_PREC_AMG, "cpr1": TPF_PREC_CPR1, "cpr2": TPF_PREC_CPR2, "bf": TPF_PREC_BF,
          "none": TPF_PREC_NONE}
 
