@@ -7,7 +7,7 @@ deterministic, data-parallel ones; this module states exactly those:
 
 1. strength: s_i = sign(a_ii) (+1 for a_ii >= 0), m_i = max_{k!=i} -s_i a_ik;
    j is strong for i iff m_i > 0 and -s_i a_ij >= theta m_i;
-2. PMIS coarsening (De Sterck, Yang, Heys): weights w_i = |S^T_i| + u_i with
+2. PMIS coarsening (De Sterck, Yang, Heys), or CLJP (see cljp()): weights w_i = |S^T_i| + u_i with
    u_i = (splitmix64(seed ^ i) >> 40) * 2^-24; points with |S^T_i| = 0 start
    as F; each round an undecided i becomes C iff (w_i, i) beats (w_j, j)
    lexicographically for every undecided j in S_i u S^T_i; then every
@@ -150,6 +150,68 @@ def pmis(A, mask, seed):
         hasc[Sr[newc[Sc]]] = True
         state[und & ~newc & hasc] = F_PT
     return state, rounds
+
+
+def cljp(A, mask, seed):
+    """CLJP C/F splitting (Cleary, Falgout, Henson, Jones 1998), the
+    coarsening of the paper's BoomerAMG settings (Sec. 4.1).  S is the
+    strength graph (edge i -> j when i depends on j, j in S_i).
+
+    w_i = |S^T_i| + u_i (u_i the PMIS hash weight); points with w_i < 1 are
+    F from the start.  Each round, on the edges not yet removed:
+      1. D = undecided points whose (w_i, i) beats that of every undecided
+         point joined to them by an edge (either direction); D becomes C;
+      2. for c in D: every j that c depends on loses 1 (edge c -> j
+         removed); for every j and k that both depend on c with k depending
+         on j, j loses 1 and the edge k -> j is removed (j is less needed
+         as a C point: k can take its value from c); then the edges into c
+         are removed;
+      3. undecided points with w < 1 become F.
+    Each removed edge lowers its target's weight once, so a round does not
+    depend on the order in which D is processed.  Returns (splitting,
+    number of rounds)."""
+    n = A.shape[0]
+    S = strength_matrix(A, mask).tocsr()
+    S.sort_indices()
+    ST = S.T.tocsr()
+    ST.sort_indices()
+    alive = {(int(i), int(j)) for i, j in zip(row_index(S), S.indices)}
+    out_nb = [set(S.indices[S.indptr[i]:S.indptr[i + 1]].tolist()) for i in range(n)]
+    in_nb = [set(ST.indices[ST.indptr[i]:ST.indptr[i + 1]].tolist()) for i in range(n)]
+    w = np.diff(ST.indptr) + pmis_random(n, seed)
+    state = np.full(n, UNDECIDED, np.int8)
+    state[w < 1.0] = F_PT
+    rounds = 0
+    while np.any(state == UNDECIDED):
+        rounds += 1
+        und = state == UNDECIDED
+        D = []
+        for i in np.flatnonzero(und):
+            nb = [j for j in out_nb[i] if (i, j) in alive] + [j for j in in_nb[i] if (j, i) in alive]
+            if all(not und[j] or (w[i], i) > (w[j], j) for j in nb if j != i):
+                D.append(int(i))
+        removed = set()
+        for c in D:
+            for j in out_nb[c]:
+                if (c, j) in alive:
+                    removed.add((c, j))
+            deps = [j for j in in_nb[c] if (j, c) in alive]
+            for j in deps:
+                for k in deps:
+                    if k != j and (k, j) in alive:
+                        removed.add((k, j))
+        for (_, j) in removed:
+            w[j] -= 1.0
+        alive -= removed
+        for c in D:
+            alive -= {(j, c) for j in in_nb[c]}
+        state[D] = C_PT
+        state[(state == UNDECIDED) & (w < 1.0)] = F_PT
+    return state, rounds
+
+
+def coarsen(A, mask, seed, kind="pmis"):
+    return cljp(A, mask, seed) if kind == "cljp" else pmis(A, mask, seed)
 
 
 def direct_interpolation(A, mask, cf):
@@ -454,7 +516,7 @@ class Hierarchy:
 
     def __init__(self, A, theta=0.25, coarse_max=128, max_levels=25, seed=0x5eed,
                  dense_max=1024, interp="direct", smoother="l1jacobi", nu1=1, nu2=1,
-                 cheb_degree=2, cheb_eig_iters=10):
+                 cheb_degree=2, cheb_eig_iters=10, coarsening="pmis"):
         self.levels = []
         self.interp = interp
         self.dense_max = dense_max
@@ -468,7 +530,7 @@ class Hierarchy:
             if lvl.n <= coarse_max or len(self.levels) >= max_levels:
                 break
             mask = strength(lvl.A, theta)
-            cf, _ = pmis(lvl.A, mask, seed)
+            cf, _ = coarsen(lvl.A, mask, seed, coarsening)
             nc = int((cf == C_PT).sum())
             if nc == 0 or nc > 0.9 * lvl.n:
                 break

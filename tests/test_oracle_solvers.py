@@ -131,6 +131,70 @@ def test_pmis_invariants_and_determinism():
     assert not np.any(isc3[r2] & isc3[S2.indices])
 
 
+def _cljp_sequential(A, mask, seed):
+    """CLJP as its definition reads, one C point at a time: D from the
+    round's start, then each c of D (here in descending order) with its
+    edges removed and weights lowered at once."""
+    n = A.shape[0]
+    S = amg.strength_matrix(A, mask).tocsr()
+    S.sort_indices()
+    ST = S.T.tocsr()
+    edges = {(int(i), int(j)) for i, j in zip(amg.row_index(S), S.indices)}
+    w = np.diff(ST.indptr) + amg.pmis_random(n, seed)
+    state = np.full(n, amg.UNDECIDED, np.int8)
+    state[w < 1] = amg.F_PT
+    while (state == amg.UNDECIDED).any():
+        und = state == amg.UNDECIDED
+        D = []
+        for i in np.flatnonzero(und):
+            nb = [j for (a, j) in edges if a == i] + [a for (a, j) in edges if j == i]
+            if all(not und[j] or (w[i], i) > (w[j], j) for j in nb if j != i):
+                D.append(int(i))
+        for c in sorted(D, reverse=True):
+            for (a, j) in list(edges):
+                if a == c:
+                    w[j] -= 1
+                    edges.discard((a, j))
+            deps = [a for (a, j) in edges if j == c]
+            for j in deps:
+                for k in deps:
+                    if k != j and (k, j) in edges:
+                        w[j] -= 1
+                        edges.discard((k, j))
+            for j in deps:
+                edges.discard((j, c))
+        state[D] = amg.C_PT
+        state[(state == amg.UNDECIDED) & (w < 1)] = amg.F_PT
+    return state
+
+
+@pytest.mark.parametrize("which", ["App", "Ass", "S"])
+def test_cljp_equals_sequential_and_keeps_ff_pairs_covered(which):
+    """CLJP on the blocks and S~ of a 3D case: the round-parallel form equals
+    the algorithm run one C point at a time in another order (each removed
+    edge lowers its target's weight once), every point is decided, and every
+    strong F-F connection i -> j shares a C point (S_j n C_i nonempty): the
+    property CLJP's second heuristic provides and classical interpolation
+    relies on; PMIS gives no such guarantee and gives fewer C points."""
+    c = inputs.random_state(inputs.config_c3(9, 8, 5), 5, s_lo=0.15, s_hi=0.85)
+    rp, ci, v = tpfa.jacobian(c, c.u, c.u_old)
+    blk = [blocks.block(rp, ci, v, a, b) for a, b in [(0, 0), (0, 1), (1, 0), (1, 1)]]
+    A = {"App": blk[0], "Ass": blk[3], "S": blocks.schur_simple(*blk)}[which].tocsr()
+    A.sort_indices()
+    m = amg.strength(A, 0.25)
+    cf, rounds = amg.cljp(A, m, 0x5eed)
+    assert rounds >= 2 and set(np.unique(cf)) == {amg.C_PT, amg.F_PT}
+    np.testing.assert_array_equal(cf, _cljp_sequential(A, m, 0x5eed))
+    S = amg.strength_matrix(A, m).tocsr()
+    for i in np.flatnonzero(cf == amg.F_PT):
+        Si = S.indices[S.indptr[i]:S.indptr[i + 1]]
+        Ci = {j for j in Si if cf[j] == amg.C_PT}
+        for j in Si:
+            if cf[j] == amg.F_PT:
+                assert set(S.indices[S.indptr[j]:S.indptr[j + 1]]) & Ci, (i, j)
+    assert (cf == amg.C_PT).sum() > (amg.pmis(A, m, 0x5eed)[0] == amg.C_PT).sum()
+
+
 def test_splitmix64_published_value():
     """SplitMix64 from state 0: first output 0xE220A8397B1DCDAF (the
     published reference sequence of the generator)."""
