@@ -181,6 +181,12 @@ int tpf_norm2(const double* x, int64_t n, double* out, void* stream);
                                    / a_ii colour by colour, ascending before the coarse-grid
                                    correction and descending after it; a step is one sweep */
 
+#define TPF_COARSEN_PMIS 0  /* PMIS (De Sterck, Yang, Heys): independent sets of hash-weighted
+                               points, every undecided point with a new C neighbour F */
+#define TPF_COARSEN_CLJP 1  /* CLJP (Cleary, Falgout, Henson, Jones), the paper's BoomerAMG
+                               setting (Sec. 4.1): weights lowered by two edge-removal
+                               heuristics each round; every strong F-F pair shares a C point */
+
 #define TPF_FP64 0       /* hierarchy and V-cycle in FP64 */
 #define TPF_FP32 1       /* hierarchy stored and V-cycle/ILU solves run in FP32; coarsest in FP64 */
 
@@ -201,6 +207,7 @@ typedef struct tpf_precond_opts {
   int nu1, nu2;         /* pre- and post-smoothing steps per level, each in [0, 4], sum >= 1
                            (1, 1); a Chebyshev step is one polynomial */
   int cheb_degree;      /* Chebyshev polynomial degree in [1, 8] (2) */
+  int coarsening;       /* TPF_COARSEN_* (PMIS) */
 } tpf_precond_opts;
 /* Fills opts with the defaults above for the given kind. */
 int tpf_precond_default_opts(int kind, tpf_precond_opts* opts);

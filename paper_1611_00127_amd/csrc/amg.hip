@@ -507,6 +507,100 @@ __global__ void __launch_bounds__(256) k_classical_fill(int n, const int* __rest
     }
 }
 
+// ---------------------------------------------------------------- CLJP
+// CLJP coarsening (Cleary, Falgout, Henson, Jones).  Edges of the strength
+// graph S (i -> j: i depends on j) are alive until a heuristic removes them;
+// st2s maps each S^T entry (c, k) to the S entry of edge k -> c.  Weights
+// start as in PMIS (k_pmis_init), so points influencing nothing are F.
+
+// st2s[e] for every entry e of S^T row c: the position of c in S row k
+__global__ void k_cljp_st2s(int n, const int* __restrict__ srp, const int* __restrict__ sci,
+                            const int* __restrict__ strp, const int* __restrict__ stci,
+                            int* __restrict__ st2s) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  for (int e = strp[c]; e < strp[c + 1]; ++e) {
+    const int k = stci[e];
+    st2s[e] = find_col(sci, srp[k], srp[k + 1], c);
+  }
+}
+
+// D: undecided points whose (w, i) beats every undecided point joined to
+// them by an alive edge, either direction
+__global__ void k_cljp_select(int n, const int* __restrict__ srp, const int* __restrict__ sci,
+                              const int* __restrict__ strp, const int* __restrict__ stci,
+                              const int* __restrict__ st2s, const int* __restrict__ alive,
+                              const double* __restrict__ w, const int8_t* __restrict__ state,
+                              uint8_t* __restrict__ newc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (state[i] != kUndecided) {
+    newc[i] = 0;
+    return;
+  }
+  const double wi = w[i];
+  bool sel = true;
+  for (int e = srp[i]; e < srp[i + 1] && sel; ++e) {
+    const int j = sci[e];
+    if (alive[e] && state[j] == kUndecided && beats(w[j], j, wi, i)) sel = false;
+  }
+  for (int e = strp[i]; e < strp[i + 1] && sel; ++e) {
+    const int j = stci[e];
+    const int es = st2s[e];
+    if (es >= 0 && alive[es] && state[j] == kUndecided && beats(w[j], j, wi, i)) sel = false;
+  }
+  newc[i] = sel;
+}
+
+// The two heuristics for every c of D (one thread per point).  Edge k -> j
+// is removed once whichever c reaches it (atomic exchange), and lowers w_j
+// by exactly 1, so the round does not depend on thread order.  Edges into
+// c are read here and removed by k_cljp_remove_in afterwards: no other c of
+// D touches them (D is independent).
+__global__ void k_cljp_heuristics(int n, const int* __restrict__ srp, const int* __restrict__ sci,
+                                  const int* __restrict__ strp, const int* __restrict__ stci,
+                                  const int* __restrict__ st2s, int* __restrict__ alive,
+                                  double* __restrict__ w, const uint8_t* __restrict__ newc) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n || !newc[c]) return;
+  // c's neighbours it depends on are less needed as C points
+  for (int e = srp[c]; e < srp[c + 1]; ++e)
+    if (atomicExch(&alive[e], 0)) atomicAdd(&w[sci[e]], -1.0);
+  // j and k both depend on c, k depends on j: k can take its value from c
+  for (int a = strp[c]; a < strp[c + 1]; ++a) {
+    if (st2s[a] < 0 || !alive[st2s[a]]) continue;
+    const int j = stci[a];
+    for (int b = strp[c]; b < strp[c + 1]; ++b) {
+      if (b == a || st2s[b] < 0 || !alive[st2s[b]]) continue;
+      const int k = stci[b];
+      const int pos = find_col(sci, srp[k], srp[k + 1], j);
+      if (pos >= 0 && atomicExch(&alive[pos], 0)) atomicAdd(&w[j], -1.0);
+    }
+  }
+}
+
+__global__ void k_cljp_remove_in(int n, const int* __restrict__ strp, const int* __restrict__ st2s,
+                                 int* __restrict__ alive, const uint8_t* __restrict__ newc) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n || !newc[c]) return;
+  for (int a = strp[c]; a < strp[c + 1]; ++a)
+    if (st2s[a] >= 0) alive[st2s[a]] = 0;
+}
+
+// D becomes C, undecided points with w < 1 become F; *undecided is set when
+// a point is left
+__global__ void k_cljp_state(int n, const uint8_t* __restrict__ newc, const double* __restrict__ w,
+                             int8_t* __restrict__ state, int* __restrict__ undecided) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || state[i] != kUndecided) return;
+  if (newc[i])
+    state[i] = kC;
+  else if (w[i] < 1.0)
+    state[i] = kF;
+  else
+    *undecided = 1;
+}
+
 // ---------------------------------------------------------------- extended+i
 // Interpolation set of an F point i: strong C neighbours of i and of every
 // strong F neighbour k, merged in ascending fine index by advancing one
@@ -1823,7 +1917,31 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
     TPF_CHECK_LAUNCH();
     int rounds = 0;
     int* rounds_pinned = host_counts_slot();
-    if (n <= kPmisWgMax) {
+    if (o.cljp) {
+      // CLJP: one read-back per round
+      const int64_t snnz = L.S.nnz > 0 ? L.S.nnz : 1;
+      Buf<int> alive(snnz, s), st2s(snnz, s);
+      fill_int(alive.p, 1, snnz, s);
+      k_cljp_st2s<<<grid_for(n, 256), 256, 0, s>>>(n, L.S.rp.p, L.S.ci.p, ST.rp.p, ST.ci.p,
+                                                   st2s.p);
+      TPF_CHECK_LAUNCH();
+      int* hflag = host_counts_slot();
+      for (rounds = 1;; ++rounds) {
+        TPF_REQUIRE(rounds <= n + 1, TPF_ERR_INVALID_ARG, "CLJP did not terminate");
+        fill_int(und.p, 0, 1, s);
+        const unsigned g = grid_for(n, 256);
+        k_cljp_select<<<g, 256, 0, s>>>(n, L.S.rp.p, L.S.ci.p, ST.rp.p, ST.ci.p, st2s.p, alive.p,
+                                        w.p, L.cf.p, newc.p);
+        k_cljp_heuristics<<<g, 256, 0, s>>>(n, L.S.rp.p, L.S.ci.p, ST.rp.p, ST.ci.p, st2s.p,
+                                            alive.p, w.p, newc.p);
+        k_cljp_remove_in<<<g, 256, 0, s>>>(n, ST.rp.p, st2s.p, alive.p, newc.p);
+        k_cljp_state<<<g, 256, 0, s>>>(n, newc.p, w.p, L.cf.p, und.p);
+        TPF_CHECK_LAUNCH();
+        TPF_HIP(hipMemcpyAsync(hflag, und.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        TPF_HIP(hipStreamSynchronize(s));
+        if (*hflag == 0) break;
+      }
+    } else if (n <= kPmisWgMax) {
       // every round in one launch; the count comes back with the next scan
       k_pmis_block<<<1, kPmisWg, 0, s>>>(n, L.S.rp.p, L.S.ci.p, ST.rp.p, ST.ci.p, w.p, L.cf.p,
                                          newc.p, und.p);
@@ -1859,7 +1977,7 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
     k_is_c<<<grid_for(n, 256), 256, 0, s>>>(n, L.cf.p, isc.p);
     TPF_CHECK_LAUNCH();
     int64_t nc = scan_exclusive(isc.p, cidx.p, n, s);  // synchronises: the round count arrived
-    if (n <= kPmisWgMax) {
+    if (!o.cljp && n <= kPmisWgMax) {
       rounds = *rounds_pinned;
       TPF_REQUIRE(rounds > 0, TPF_ERR_INVALID_ARG, "PMIS did not terminate");
     }

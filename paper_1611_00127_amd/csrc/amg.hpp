@@ -16,6 +16,7 @@ struct AmgOpts {
   bool fp32 = false;
   bool ext_i = false;   // extended+i instead of direct interpolation
   bool classical = false;  // classical (modified Ruge-Stueben) instead of direct
+  bool cljp = false;       // CLJP coarsening instead of PMIS
   int exti_first = 0;   // extended+i rows start the kernel-class search here (tests)
   int smoother = 0;     // 0 l1-Jacobi, 1 Chebyshev on D^{-1} A, 2 multicolour Gauss-Seidel
   int nu1 = 1, nu2 = 1; // pre- and post-smoothing steps

@@ -745,6 +745,7 @@ AmgOpts amg_opts(const tpf_precond_opts& o, bool pressure_like) {
   AmgOpts a;
   a.ext_i = o.interp == TPF_INTERP_EXTI || (o.interp == TPF_INTERP_AUTO && pressure_like);
   a.classical = o.interp == TPF_INTERP_CLASSICAL;
+  a.cljp = o.coarsening == TPF_COARSEN_CLJP;
   a.exti_first = o.exti_route > 0 ? o.exti_route - 1 : 0;
   a.theta = o.theta;
   a.max_levels = o.max_levels;
@@ -1027,6 +1028,7 @@ int tpf_precond_default_opts(int kind, tpf_precond_opts* o) {
     o->nu1 = 1;
     o->nu2 = 1;
     o->cheb_degree = 2;
+    o->coarsening = TPF_COARSEN_PMIS;
   });
 }
 
@@ -1053,6 +1055,8 @@ int tpf_precond_create(const tpf_precond_opts* o, tpf_precond** out) {
                 TPF_ERR_INVALID_ARG, "nu1, nu2 must be in [0, 4] with nu1 + nu2 >= 1");
     TPF_REQUIRE(o->cheb_degree >= 1 && o->cheb_degree <= 8, TPF_ERR_INVALID_ARG,
                 "cheb_degree must be in [1, 8]");
+    TPF_REQUIRE(o->coarsening == TPF_COARSEN_PMIS || o->coarsening == TPF_COARSEN_CLJP,
+                TPF_ERR_INVALID_ARG, "unknown coarsening %d", o->coarsening);
     auto* M = new tpf_precond();
     M->o = *o;
     *out = M;

@@ -22,6 +22,7 @@ TPF_PC_BROOKS_COREY, TPF_PC_LINEAR = 0, 1
 TPF_PREC_AMG, TPF_PREC_CPR1, TPF_PREC_CPR2, TPF_PREC_BF, TPF_PREC_NONE = 0, 1, 2, 3, 4
 TPF_FP64, TPF_FP32 = 0, 1
 TPF_SMOOTH_L1_JACOBI, TPF_SMOOTH_CHEBYSHEV, TPF_SMOOTH_MC_GS = 0, 1, 2
+TPF_COARSEN_PMIS, TPF_COARSEN_CLJP = 0, 1
 TPF_CONVERGED, TPF_MAX_ITERS, TPF_BREAKDOWN, TPF_NONFINITE, TPF_CANCELLED = 0, 1, 2, 3, 4
 TPF_ERR_OVER_BUDGET = -5
 TPF_MAT_A, TPF_MAT_P, TPF_MAT_R, TPF_MAT_S, TPF_MAT_GS_COLORS = 0, 1, 2, 3, 4
@@ -63,7 +64,7 @@ class PrecondOpts(ctypes.Structure):
     _fields_ = [("kind", c_int), ("precision", c_int), ("theta", c_double), ("max_levels", c_int),
                 ("coarse_max", c_int), ("dense_max", c_int), ("interp", c_int),
                 ("hash_seed", c_uint64), ("exti_route", c_int), ("smoother", c_int),
-                ("nu1", c_int), ("nu2", c_int), ("cheb_degree", c_int)]
+                ("nu1", c_int), ("nu2", c_int), ("cheb_degree", c_int), ("coarsening", c_int)]
 
 
 class HierStats(ctypes.Structure):

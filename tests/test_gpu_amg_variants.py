@@ -10,7 +10,10 @@ smoother), against the oracle, through the C ABI:
   a~_ii in the oracle as well, so that hierarchy keeps direct interpolation);
 * multicolour Gauss-Seidel smoothing: the colouring of every level
   bit-exact, one V-cycle within 1e-12 (FP64) and 1e-4 (FP32) of the
-  oracle's cycle on the GPU's levels, and BF solves within +-1 iteration.
+  oracle's cycle on the GPU's levels, and BF solves within +-1 iteration;
+* CLJP coarsening: every level's C/F splitting bit-exact (with PMIS- and
+  CLJP-built coarse levels and each interpolation), and BF solves with all
+  three of the paper's components together.
 """
 import numpy as np
 import pytest
@@ -62,7 +65,9 @@ def _oracle_solve(g, c, amg_opts):
 
 @pytest.mark.parametrize("variant,case", [("classical", "3d"), ("gs", "3d"),
                                           ("gs-classical", "3d"), ("gs", "c1"),
-                                          ("classical", "c1")])
+                                          ("classical", "c1"), ("cljp", "3d"),
+                                          ("cljp-classical-gs", "3d"),
+                                          ("cljp-classical-gs", "c1")])
 def test_bf_solve_variants_vs_oracle(gpu, variant, case):
     """BF FGMRES(30) with the variant in both hierarchies, at the initial
     condition of the 3D workload family (24x20x8) and of the 32x32 case:
@@ -75,9 +80,12 @@ def test_bf_solve_variants_vs_oracle(gpu, variant, case):
     if "classical" in variant:
         opts["interp"] = tpf.TPF_INTERP_CLASSICAL
         oopts["interp"] = "classical"
-    if variant.startswith("gs"):
+    if "gs" in variant:
         opts["smoother"] = tpf.TPF_SMOOTH_MC_GS
         oopts["smoother"] = "gs"
+    if "cljp" in variant:
+        opts["coarsening"] = tpf.TPF_COARSEN_CLJP
+        oopts["coarsening"] = "cljp"
     say(f"[variant] {variant}")
     g, M = _setup(driver, tpf, c, "bf", **opts)
     b = g.rhs().contiguous()
@@ -131,3 +139,23 @@ def test_gs_colouring_and_vcycle(gpu, precision):
             say(f"  hierarchy {hier}: {len(H.levels)} levels, max rel diff {rel:.2e}")
             assert rel <= (1e-4 if precision else 1e-12), rel
         M.close(); g.close()
+
+
+@pytest.mark.parametrize("kind,hier,interp,case", [("bf", 1, "ext+i", "3d"), ("bf", 0, "direct", "3d"),
+                                                   ("bf", 1, "classical", "3d"),
+                                                   ("cpr2", 1, "classical", "c1"),
+                                                   ("bf", 0, "direct", "c1")])
+def test_cljp_levels(gpu, kind, hier, interp, case):
+    """CLJP on every level: the strength graph, the C/F splitting
+    (bit-exact), P, R and A_c against the oracle on the GPU's own levels."""
+    driver, tpf, torch = gpu
+    c = _case3d() if case == "3d" else inputs.random_state(inputs.config_c1(), 7, s_lo=0.15,
+                                                           s_hi=0.85)
+    opts = dict(coarse_max=40, coarsening=tpf.TPF_COARSEN_CLJP)
+    if interp == "classical":
+        opts["interp"] = tpf.TPF_INTERP_CLASSICAL
+    say(f"[cljp] {kind} hierarchy {hier} ({interp}) on {case}")
+    g, M = _setup(driver, tpf, c, kind, **opts)
+    nlev = _check_levels(tpf, M, hier, interp, coarsening="cljp")
+    say(f"  {nlev} levels")
+    M.close(); g.close()

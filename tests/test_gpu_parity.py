@@ -134,9 +134,10 @@ def test_schur_parity(gpu, nx, ny, nz):
     M.close(); g.close()
 
 
-def _check_levels(tpf, M, hier, interp):
+def _check_levels(tpf, M, hier, interp, coarsening="pmis"):
     """Each level's setup from the GPU's own level matrix (identical bits):
-    strength graph, C/F, P (direct or extended+i), R and A_c."""
+    strength graph, C/F (PMIS or CLJP), P (direct, classical or extended+i),
+    R and A_c."""
     st = M.stats()
     nlev = st.levels[hier]
     assert nlev >= 2
@@ -154,7 +155,7 @@ def _check_levels(tpf, M, hier, interp):
         assert np.array_equal(Sg[0], So.indptr) and np.array_equal(Sg[1], So.indices), f"S level {l}"
         cf_p, _, _ = tpf.tpf_precond_level_data(M.M, hier, l)
         cf = tpf.device_array(cf_p, n, np.int8)
-        ocf, _ = amg.pmis(A, mask, 0x5eed)
+        ocf, _ = amg.coarsen(A, mask, 0x5eed, coarsening)
         assert np.array_equal(cf, ocf), f"C/F level {l}"
         P = tpf.csr_to_numpy(tpf.tpf_precond_matrix(M.M, hier, l, tpf.TPF_MAT_P))
         Po, _ = amg.interpolation(A, mask, ocf, interp)
