@@ -70,13 +70,17 @@ def parse():
     ap.add_argument("--serve-active", type=int, default=8, help="requests in flight")
     ap.add_argument("--serve-load", type=float, default=0.8,
                     help="Poisson arrival rate as a fraction of the sequential FP64 throughput")
-    ap.add_argument("--study", choices=["c2", "newton", "simulate", "spectra"], default=None,
+    ap.add_argument("--study", choices=["c2", "newton", "simulate", "spectra", "amg-variants"],
+                    default=None,
                     help="instead of the benchmark line, print one JSON line for a study: "
                          "c2 = first Jacobian of the 512x512 workload for P_d in {0, 0.1, 1} and "
                          "all four preconditioners; newton = 10 consecutive Newton Jacobians of "
                          "the 256x256x128 workload, BF, rebuild vs reuse x FP64 vs FP32; "
                          "simulate = multi-step runs of the 2D stand-ins, all preconditioners; "
-                         "spectra = eigenvalues of J M^-1 with exact inner solves")
+                         "spectra = eigenvalues of J M^-1 with exact inner solves; "
+                         "amg-variants = the 128x128x64 Jacobian at Newton iterate 1 with the "
+                         "paper's AMG components (CLJP, classical interpolation, multicolour "
+                         "Gauss-Seidel) against the defaults")
     ap.add_argument("--study-grid", type=str, default=None,
                     help="grid of the study workload (default: 512x512 / 256x256x128)")
     return ap.parse_args()
@@ -641,6 +645,59 @@ def study_spectra(torch, tpf, driver, inputs, args):
             "results": rows}
 
 
+def study_amg_variants(torch, tpf, driver, inputs, args):
+    """BF on the 3D workload's Jacobian at Newton iterate 1, FP64, with each
+    AMG variant in both hierarchies: setup and solve time (median of three
+    after a warm-up), FGMRES iterations, true residual, operator complexity."""
+    nx, ny, nz = (int(v) for v in (args.study_grid or "128x128x64").split("x"))
+    c = inputs.config_c3(nx, ny, nz)
+    g = driver.GpuCase(c)
+    g.u.copy_(linearisation_state(torch, driver, g, "newton1"))
+    g.assemble()
+    b = g.R
+    x = torch.empty_like(b)
+    variants = [
+        ("default: PMIS, ext+i (S~) / direct (A_ss), l1-Jacobi", {}),
+        ("PMIS, classical, l1-Jacobi", dict(interp=tpf.TPF_INTERP_CLASSICAL)),
+        ("PMIS, default interpolation, multicolour GS", dict(smoother=tpf.TPF_SMOOTH_MC_GS)),
+        ("CLJP, default interpolation, l1-Jacobi", dict(coarsening=tpf.TPF_COARSEN_CLJP)),
+        ("CLJP, classical, multicolour GS (the paper's components)",
+         dict(coarsening=tpf.TPF_COARSEN_CLJP, interp=tpf.TPF_INTERP_CLASSICAL,
+              smoother=tpf.TPF_SMOOTH_MC_GS)),
+    ]
+    rows = []
+    for name, opts in variants:
+        M = driver.GpuPrecond("bf", **opts)
+        t_set, t_sol, info = [], [], None
+        for rep_ in range(4):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            M.setup(g)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            info = driver.solve(g, M, b, x, rtol=1e-8)
+            t2 = time.perf_counter()
+            if rep_:
+                t_set.append(t1 - t0)
+                t_sol.append(t2 - t1)
+        st = M.stats()
+        rec = {"variant": name, "iterations": int(info.iterations), "status": int(info.status),
+               "relres_true": float(info.relres_true),
+               "setup_ms": round(1e3 * float(np.median(t_set)), 2),
+               "solve_ms": round(1e3 * float(np.median(t_sol)), 2),
+               "levels": [int(st.levels[h]) for h in range(st.n_hier)],
+               "op_complexity": [round(float(st.operator_complexity[h]), 3)
+                                 for h in range(st.n_hier)]}
+        rec["total_ms"] = round(rec["setup_ms"] + rec["solve_ms"], 2)
+        log(f"[amg-variants] {name}: {rec['iterations']} its, setup {rec['setup_ms']} ms, "
+            f"solve {rec['solve_ms']} ms")
+        rows.append(rec)
+        M.close()
+    g.close()
+    return {"study": "amg-variants", "workload": f"3d-{nx}x{ny}x{nz} BF at Newton iterate 1, FP64",
+            "results": rows}
+
+
 def linearisation_state(torch, driver, g, state):
     """Device copy of the state the benchmark Jacobian is taken at: the
     initial condition of the time step, or Newton iterate 1 (one FP64 BF
@@ -668,7 +725,7 @@ def main():
     tpf.tpf_set_graphs(args.graphs)
     if args.study:
         fn = {"c2": study_c2, "newton": study_newton, "simulate": study_simulate,
-              "spectra": study_spectra}[args.study]
+              "spectra": study_spectra, "amg-variants": study_amg_variants}[args.study]
         print(json.dumps(fn(torch, tpf, driver, inputs, args)), flush=True)
         return
     if args.copy_probe > 0:
