@@ -25,8 +25,9 @@ from .fgmres import CONVERGED
 def simulate(case, kind, t_final, dt=None, newton_tol=1e-6, max_newton=25, rtol=1e-8,
              ds_max=0.2, amg_opts=None):
     """Returns (record, final state).  record: per time step the residual
-    norms before each Newton iteration, the Krylov iterations of each solve
-    and the step's status; totals NI, LI and the overall status."""
+    norms before each Newton iteration, the Krylov iterations of each solve,
+    the step's status and its final state; totals NI, LI and the overall
+    status."""
     dt = case.dt if dt is None else dt
     n_steps = int(round(t_final / dt))
     u = case.u.copy()
@@ -51,7 +52,7 @@ def simulate(case, kind, t_final, dt=None, newton_tol=1e-6, max_newton=25, rtol=
             if info["status"] != CONVERGED:
                 break
             c = c.replace(u=newton.update(c.u, x, ds_max))
-        steps.append(dict(fnorms=fnorms, iterations=its, status=st))
+        steps.append(dict(fnorms=fnorms, iterations=its, status=st, u=c.u.copy()))
         u = c.u
         if st != "converged":
             status = "diverged"

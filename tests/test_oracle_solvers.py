@@ -738,6 +738,37 @@ def test_newton_update_chop_and_clamp_closed_form():
 # ----------------------------------------------------------------- spectra
 
 
+def test_simulation_conserves_nonwetting_volume():
+    """Backward Euler over several steps of the gravity box (wells through
+    boundary faces, gravity, linear P_c): the stored nonwetting volume
+    changes by dt times the net inflow at each step's converged state,
+    sum_i phi_i V (S_K - S_0)_i = -dt sum_k sum_i R_n,i(u_k, u_k), up to the
+    Newton tolerance.  With u_old = u the accumulation term vanishes and the
+    interior fluxes cancel, so sum_i R_n,i(u, u) is minus the net inflow.  A
+    step that kept the wrong u_old, used another dt or stopped short of the
+    tolerance breaks the balance."""
+    from oracle import simulate
+    c = inputs.gravity_box_xz(10, "advection")
+    K = 3
+    rec, u = simulate.simulate(c, "bf", K * c.dt, dt=c.dt)
+    assert rec["status"] == "converged" and len(rec["steps"]) == K
+    states = [c.u] + [st["u"] for st in rec["steps"]]
+    np.testing.assert_array_equal(states[-1], u)
+    V = c.hx * c.hy * c.hz
+    poro = np.asarray(c.poro).reshape(-1)
+    stored = float(np.sum(poro * V * (states[-1][:, 1] - states[0][:, 1])))
+    inflow = 0.0
+    for k in range(1, K + 1):
+        ck = c.replace(u=states[k], u_old=states[k])
+        inflow -= c.dt * float(np.sum(tpfa.residual(ck, ck.u, ck.u_old)[:, 1]))
+        # the step itself met the Newton tolerance
+        cs = c.replace(u=states[k], u_old=states[k - 1])
+        assert np.linalg.norm(tpfa.residual(cs, cs.u, cs.u_old)) <= 1e-6
+    bound = K * c.dt * np.sqrt(2 * c.N) * 1e-6
+    assert abs(stored) > 100 * bound  # the balance is not trivially zero
+    assert abs(stored - inflow) <= bound, (stored, inflow, bound)
+
+
 def test_spectrum_bf_is_one_and_schur_ratio():
     """Sec. 4.3 study, exact inner solves.  For BF's block upper-triangular M
     (Eq. m_bf) with S~ in place of the Schur complement S = A_pp - A_ps
