@@ -302,6 +302,39 @@ def run_form(torch, tpf, driver, g, precision, steps, warmup, timing):
     return M, x, res
 
 
+SETUP_PHASES = ("strength", "coarsen", "interp", "transpose", "galerkin", "finish")
+
+
+def setup_breakdown(torch, tpf, driver, g, precision):
+    """One more full BF setup (after a warm-up one) with each phase bracketed
+    by HIP events on its stream: block extraction, S~, and per hierarchy
+    (summed over its levels) strength graph, coarsening, interpolation,
+    transpose, Galerkin product, and finishing the levels (smoother
+    diagonals, FP32 copies, level-0 diagonal layout, coarsest inverse).  The
+    two hierarchies are built concurrently on two streams, so their phases
+    overlap in time.  Also the number of host round trips the setup makes."""
+    M = driver.GpuPrecond("bf", precision)
+    M.setup(g)
+    torch.cuda.synchronize()
+    tpf.tpf_kernel_stats_reset()
+    tpf.tpf_kernel_timing(True)
+    t0 = time.perf_counter()
+    M.setup(g)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tpf.tpf_kernel_timing(False)
+    out = {"wall_ms_with_timers": round(1e3 * wall, 2),
+           "host_round_trips": int(tpf.tpf_kernel_stats("host_syncs")[0])}
+    for name in ("setup_blocks", "setup_schur"):
+        out[name[6:] + "_ms"] = round(tpf.tpf_kernel_stats(name)[1], 3)
+    for tag in HIER_TAGS["bf"]:
+        out[HIER_NAMES[tag]] = {ph + "_ms": round(tpf.tpf_kernel_stats(f"setup_{ph}[{tag}]")[1], 3)
+                                for ph in SETUP_PHASES}
+    tpf.tpf_kernel_stats_reset()
+    M.close()
+    return out
+
+
 def kernel_table(tpf, names):
     out = {}
     for n in names:
@@ -761,6 +794,8 @@ def main():
         vc64[h]["wall_ms_per_vcycle"] = round(ms, 4)
         vc64[h]["wall_gbs"] = round(vc64[h]["bytes_per_vcycle"] / (ms * 1e6), 1)
     Mi.close()
+    log("[bench] FP64 setup phases")
+    setup64 = setup_breakdown(torch, tpf, driver, g, tpf.TPF_FP64)
     log("[bench] FP32-V-cycle form")
     M32, x32, r32 = run_form(torch, tpf, driver, g, tpf.TPF_FP32, args.steps, args.warmup, False)
     err = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
@@ -839,7 +874,7 @@ def main():
                                f"the {state_text(head)}",
                    "cells": c.N, "unknowns": 2 * c.N, "preconditioner": "bf",
                    "krylov": "fgmres(30)", "rtol": 1e-8},
-        "fp64": r64,
+        "fp64": dict(r64, setup_phases=setup64),
         "fp32_vcycle": dict(r32, rel_diff_vs_fp64=err,
                             speedup_vs_fp64=round(r64["ms_per_step"] / r32["ms_per_step"], 3)),
         "errors_vs_fp64_oracle": vs_oracle,

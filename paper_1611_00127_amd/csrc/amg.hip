@@ -1883,10 +1883,18 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
   auto L0 = std::make_unique<Level>();
   L0->A = std::move(A0);
   lv.push_back(std::move(L0));
+  // setup phase timers (recorded while kernel timing is on), summed over levels
+  const std::string ph_strength = "setup_strength[" + tag + "]",
+                    ph_coarsen = "setup_coarsen[" + tag + "]",
+                    ph_interp = "setup_interp[" + tag + "]",
+                    ph_transpose = "setup_transpose[" + tag + "]",
+                    ph_galerkin = "setup_galerkin[" + tag + "]",
+                    ph_finish = "setup_finish[" + tag + "]";
   while (true) {
     Level& L = *lv.back();
     int n = L.A.nrows;
     if (n <= o.coarse_max || int(lv.size()) >= o.max_levels) break;
+    std::unique_ptr<TimedScope> phase(new TimedScope(ph_strength.c_str(), s));
     // strength of connection
     L.mask.alloc(L.A.nnz > 0 ? L.A.nnz : 1, s);
     Buf<int> cnt(n, s);
@@ -1908,6 +1916,8 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
     TPF_CHECK_LAUNCH();
     Csr<double> ST;
     transpose(CsrRef<double>{n, n, L.S.nnz, L.S.rp.p, L.S.ci.p, nullptr}, ST, s);
+    phase.reset();
+    phase.reset(new TimedScope(ph_coarsen.c_str(), s));
     // PMIS
     Buf<double> w(n, s);
     L.cf.alloc(n, s);
@@ -1938,6 +1948,7 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
         k_cljp_state<<<g, 256, 0, s>>>(n, newc.p, w.p, L.cf.p, und.p);
         TPF_CHECK_LAUNCH();
         TPF_HIP(hipMemcpyAsync(hflag, und.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        note_host_sync();
         TPF_HIP(hipStreamSynchronize(s));
         if (*hflag == 0) break;
       }
@@ -1968,6 +1979,7 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
       for (rounds = 1;; ++rounds) {
         TPF_REQUIRE(rounds <= n + 1, TPF_ERR_INVALID_ARG, "PMIS did not terminate");
         launch_round(rounds % 2);
+        note_host_sync();
         TPF_HIP(hipEventSynchronize(thread_event((rounds - 1) % 2)));
         if (hflag[(rounds - 1) % 2] == 0) break;
       }
@@ -1983,6 +1995,8 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
     }
     L.pmis_rounds = rounds;
     if (nc == 0 || double(nc) > 0.9 * double(n)) break;
+    phase.reset();
+    phase.reset(new TimedScope(ph_interp.c_str(), s));
     // interpolation: direct, classical, or extended+i
     L.P.nrows = n;
     L.P.ncols = int(nc);
@@ -2083,7 +2097,11 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
       }
       TPF_CHECK_LAUNCH();
     }
+    phase.reset();
+    phase.reset(new TimedScope(ph_transpose.c_str(), s));
     transpose(ref(L.P), L.R, s);
+    phase.reset();
+    phase.reset(new TimedScope(ph_galerkin.c_str(), s));
     // Galerkin product A_c = R A P, as (R A) P on level 0 (R's rows of a
     // few fine points times the stencil rows, then P's short rows: about a
     // quarter fewer products than R (A P)), as R (A P) on the coarser levels
@@ -2092,6 +2110,7 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
     galerkin(L, lv.size() == 1, next->A, s);
     lv.push_back(std::move(next));
   }
+  TimedScope fin(ph_finish.c_str(), s);
   finish_levels(s);
 }
 
@@ -2345,6 +2364,7 @@ void Hierarchy::gs_setup(Level& L, hipStream_t st) {
         TPF_CHECK_LAUNCH();
       }
       TPF_HIP(hipMemcpyAsync(hflag, flag.p, kBatch * sizeof(int), hipMemcpyDeviceToHost, st));
+      note_host_sync();
       TPF_HIP(hipStreamSynchronize(st));
       for (int k = 0; k < kBatch; ++k)
         if (hflag[k] == 0) {
@@ -2360,6 +2380,7 @@ void Hierarchy::gs_setup(Level& L, hipStream_t st) {
     L.gs_ptr.assign(ncolors + 1, 0);
     TPF_HIP(hipMemcpyAsync(L.gs_ptr.data(), pos.p, (ncolors + 1) * sizeof(int),
                            hipMemcpyDeviceToHost, st));
+    note_host_sync();
     TPF_HIP(hipStreamSynchronize(st));
     L.gs_ptr_dev.alloc(ncolors + 1, st);
     copy(L.gs_ptr_dev.p, pos.p, ncolors + 1, st);
@@ -2477,6 +2498,7 @@ void Hierarchy::coarse_setup(hipStream_t st) {
   TPF_REQUIRE(f == 0, TPF_ERR_SINGULAR, "coarsest AMG matrix (n = %d) is singular", n);
   k_dense_extract<<<grid_for(int64_t(n) * n, 256), 256, 0, st>>>(n, M.p, Ainv.p);
   TPF_CHECK_LAUNCH();
+  note_host_sync();
   TPF_HIP(hipStreamSynchronize(st));
 }
 

@@ -788,6 +788,7 @@ void bilu_setup(tpf_precond* M, bool reuse, hipStream_t s) {
     k_front_place<<<grid_for(N, 256), 256, 0, s>>>(Grid3{ph.nx, ph.ny, ph.nz}, M->front_ptr_dev.p,
                                                    M->front_cells.p);
     TPF_CHECK_LAUNCH();
+    note_host_sync();
     TPF_HIP(hipStreamSynchronize(s));
     M->bilu_dinv.alloc(4 * int64_t(N), s);
   }
@@ -1105,9 +1106,12 @@ int tpf_precond_setup(tpf_precond* M, const tpf_jacobian* J, int reuse, void* st
         M->fr.alloc(2 * int64_t(N), s);
       }
     }
-    k_extract_blocks<<<grid_for(nnzb, 256), 256, 0, s>>>(nnzb, J->v.p, M->app_v.p, M->aps_v.p,
-                                                         M->asp_v.p, M->ass_v.p);
-    TPF_CHECK_LAUNCH();
+    {
+      TimedScope ts("setup_blocks", s);
+      k_extract_blocks<<<grid_for(nnzb, 256), 256, 0, s>>>(nnzb, J->v.p, M->app_v.p, M->aps_v.p,
+                                                           M->asp_v.p, M->ass_v.p);
+      TPF_CHECK_LAUNCH();
+    }
     if (kind == TPF_PREC_AMG) {
       M->n_hier = 1;
       if (!re) {
@@ -1188,10 +1192,13 @@ int tpf_precond_setup(tpf_precond* M, const tpf_jacobian* J, int reuse, void* st
           [&](hipStream_t ms) {
             if (!re) {
               Csr<double> S;
-              if (on_grid)
-                schur_on_grid(M, ph, S, false, ms);
-              else
-                spgemm(Y, Asp, S, ms, &App, -1.0, 1.0, false);
+              {
+                TimedScope ts("setup_schur", ms);
+                if (on_grid)
+                  schur_on_grid(M, ph, S, false, ms);
+                else
+                  spgemm(Y, Asp, S, ms, &App, -1.0, 1.0, false);
+              }
               auto H = std::make_unique<Hierarchy>();
               H->tag = "Schur";
               H->stencil = stencil_offsets(J->prob->ph, 2);
@@ -1206,6 +1213,7 @@ int tpf_precond_setup(tpf_precond* M, const tpf_jacobian* J, int reuse, void* st
             }
           });
     }
+    note_host_sync();
     TPF_HIP(hipStreamSynchronize(s));
     M->ready = true;
   });

@@ -33,6 +33,7 @@ struct TimedRecord {
 };
 std::mutex g_time_mu;
 std::map<std::string, std::vector<TimedRecord>> g_records;
+std::atomic<int64_t> g_host_syncs{0};
 std::vector<hipEvent_t> g_event_pool;
 
 hipEvent_t get_event() {
@@ -331,6 +332,8 @@ std::atomic<bool> g_graphs{false};
 }
 bool graphs_enabled() { return g_graphs.load(std::memory_order_relaxed); }
 
+void note_host_sync() { g_host_syncs.fetch_add(1, std::memory_order_relaxed); }
+
 TimedScope::TimedScope(const char* n, hipStream_t st) : name(n), s(st) {
   if (!g_timing) return;
   std::lock_guard<std::mutex> lk(g_time_mu);
@@ -421,6 +424,10 @@ int tpf_kernel_stats(const char* name, int64_t* count, double* total_ms) {
     std::lock_guard<std::mutex> lk(g_time_mu);
     *count = 0;
     *total_ms = 0.0;
+    if (std::strcmp(name, "host_syncs") == 0) {
+      *count = g_host_syncs.load();
+      return;
+    }
     auto it = g_records.find(name);
     if (it == g_records.end()) return;
     for (auto& r : it->second) {
@@ -443,6 +450,7 @@ int tpf_kernel_stats_reset(void) {
         g_event_pool.push_back(r.e1);
       }
     g_records.clear();
+    g_host_syncs.store(0);
   });
 }
 

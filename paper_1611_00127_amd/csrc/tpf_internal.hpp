@@ -189,8 +189,13 @@ inline int* host_counts_slot() {
 // use, kept until the process ends).
 hipEvent_t thread_event(int k);
 
+// Host round trips (a stream or event synchronisation the host waits on),
+// counted for the setup accounting; read back as tpf_kernel_stats("host_syncs").
+void note_host_sync();
+
 template <class T>
 T read_scalar(const T* dptr, hipStream_t s) {
+  note_host_sync();
   T* h = host_scratch().get<T>(1);
   TPF_HIP(hipMemcpyAsync(h, dptr, sizeof(T), hipMemcpyDeviceToHost, s));
   TPF_HIP(hipStreamSynchronize(s));
