@@ -1959,29 +1959,32 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
       TPF_CHECK_LAUNCH();
       TPF_HIP(hipMemcpyAsync(rounds_pinned, und.p, sizeof(int), hipMemcpyDeviceToHost, s));
     } else {
-      // Rounds run back to back: round r + 1 is queued before the host reads
-      // round r's flag, so the GPU does not wait for the host between rounds.
-      // Once a round leaves no point undecided, the round queued after it
-      // changes nothing.
-      Buf<int> flags(2, s);
+      // Rounds are queued in batches of kPmisBatch with one read-back of
+      // their flags per batch (a round takes a few microseconds on the GPU,
+      // less than the host's turn-around).  Once a round leaves no point
+      // undecided, the rounds after it change nothing.
+      constexpr int kPmisBatch = 4;
+      Buf<int> flags(kPmisBatch, s);
       int* hflag = host_counts_slot();
-      auto launch_round = [&](int k) {
-        fill_int(flags.p + k, 0, 1, s);
-        k_pmis_select<<<grid_for(n, 256), 256, 0, s>>>(n, L.S.rp.p, L.S.ci.p, ST.rp.p, ST.ci.p,
-                                                       w.p, L.cf.p, newc.p);
-        k_pmis_update<<<grid_for(n, 256), 256, 0, s>>>(n, L.S.rp.p, L.S.ci.p, newc.p, L.cf.p,
-                                                       flags.p + k);
-        TPF_CHECK_LAUNCH();
-        TPF_HIP(hipMemcpyAsync(hflag + k, flags.p + k, sizeof(int), hipMemcpyDeviceToHost, s));
-        TPF_HIP(hipEventRecord(thread_event(k), s));
-      };
-      launch_round(0);
-      for (rounds = 1;; ++rounds) {
-        TPF_REQUIRE(rounds <= n + 1, TPF_ERR_INVALID_ARG, "PMIS did not terminate");
-        launch_round(rounds % 2);
+      rounds = 0;
+      for (int r0 = 0; rounds == 0; r0 += kPmisBatch) {
+        TPF_REQUIRE(r0 <= n + 1, TPF_ERR_INVALID_ARG, "PMIS did not terminate");
+        fill_int(flags.p, 0, kPmisBatch, s);
+        for (int k = 0; k < kPmisBatch; ++k) {
+          k_pmis_select<<<grid_for(n, 256), 256, 0, s>>>(n, L.S.rp.p, L.S.ci.p, ST.rp.p,
+                                                         ST.ci.p, w.p, L.cf.p, newc.p);
+          k_pmis_update<<<grid_for(n, 256), 256, 0, s>>>(n, L.S.rp.p, L.S.ci.p, newc.p, L.cf.p,
+                                                         flags.p + k);
+          TPF_CHECK_LAUNCH();
+        }
+        TPF_HIP(hipMemcpyAsync(hflag, flags.p, kPmisBatch * sizeof(int), hipMemcpyDeviceToHost, s));
         note_host_sync();
-        TPF_HIP(hipEventSynchronize(thread_event((rounds - 1) % 2)));
-        if (hflag[(rounds - 1) % 2] == 0) break;
+        TPF_HIP(hipStreamSynchronize(s));
+        for (int k = 0; k < kPmisBatch; ++k)
+          if (hflag[k] == 0) {
+            rounds = r0 + k + 1;
+            break;
+          }
       }
     }
     // coarse numbering
