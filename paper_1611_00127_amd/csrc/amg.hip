@@ -1863,8 +1863,10 @@ template <> const float* dinv_of<float>(const Level& L) { return L.dinv32.p; }
 }  // namespace
 
 // ---------------------------------------------------------------- setup
-// A_c = R A P with the intermediate kept in L.T: (R A) P when ra_first, else
-// R (A P)
+// A_c = R A P through the intermediate L.T: (R A) P when ra_first, else
+// R (A P).  The intermediate is released afterwards (a numeric refresh
+// recomputes it); its blocks stay cached for the stream, where the next
+// level's product finds them.
 static void galerkin(Level& L, bool ra_first, Csr<double>& Ac, hipStream_t s) {
   if (ra_first) {
     spgemm(ref(L.R), ref(L.A), L.T, s);
@@ -1873,6 +1875,7 @@ static void galerkin(Level& L, bool ra_first, Csr<double>& Ac, hipStream_t s) {
     spgemm(ref(L.A), ref(L.P), L.T, s);
     spgemm(ref(L.R), ref(L.T), Ac, s);
   }
+  L.T = Csr<double>{};
 }
 
 void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {

@@ -33,8 +33,8 @@ struct Level {
   Buf<uint8_t> mask;    // strength mask over A's entries
   Csr<double> S;        // strength graph (pattern only)
   Buf<int8_t> cf;       // 1 = C, 2 = F
-  Csr<double> P, R, T;  // interpolation, restriction, and R*A (level 0) or A*P (kept
-                        // for numeric refresh)
+  Csr<double> P, R, T;  // interpolation, restriction, and the Galerkin intermediate
+                        // R*A (level 0) or A*P while the product runs (empty after)
   // FP32 copies of the values (patterns shared)
   Buf<float> Av32, Pv32, Rv32, dinv32;
   // generic smoothing sweeps: two iterates and the Chebyshev direction, and
