@@ -2154,17 +2154,22 @@ void Hierarchy::finish_levels(hipStream_t st) {
       });
     }
     TPF_CHECK_LAUNCH();
-    L.r.ensure(n, st);
-    L.y.ensure(n, st);
-    if (&L != lv[0].get()) {
-      L.b.ensure(n, st);
-      L.x.ensure(n, st);
-    }
+    // FP64 cycle work vectors (the FP32 form cycles in FP32 only)
     const bool generic = !o.fused_cycle() && l + 1 < lv.size();
+    if (!o.fp32) {
+      L.r.ensure(n, st);
+      L.y.ensure(n, st);
+      if (&L != lv[0].get()) {
+        L.b.ensure(n, st);
+        L.x.ensure(n, st);
+      }
+      if (generic) {
+        L.xa.ensure(n, st);
+        L.xb.ensure(n, st);
+        if (o.smoother == 1) L.dd.ensure(n, st);
+      }
+    }
     if (generic) {
-      L.xa.ensure(n, st);
-      L.xb.ensure(n, st);
-      if (o.smoother == 1) L.dd.ensure(n, st);
       if (o.smoother == 1) chebyshev_setup(L, st);
       if (o.smoother == 2) gs_setup(L, st);
     }
@@ -2221,6 +2226,8 @@ void Hierarchy::finish_levels(hipStream_t st) {
     if (!dia0.ok) {
       dia0.v.release();
       dia0.v32.release();
+    } else if (o.fp32) {
+      dia0.v.release();  // only the FP32 copy is cycled
     }
   }
   coarse_setup(st);
