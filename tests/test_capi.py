@@ -49,6 +49,44 @@ def test_host_side_errors_without_gpu():
     assert tpf.tpf_status_string(-4) == "singular pivot"
 
 
+def test_amg_variant_options_host_checks():
+    """The options of the paper's AMG components (classical interpolation,
+    multicolour Gauss-Seidel, CLJP) are accepted, their defaults are PMIS /
+    l1-Jacobi / the automatic interpolation, and out-of-range values are
+    rejected before any device work."""
+    o = tpf.tpf_precond_default_opts(tpf.TPF_PREC_BF)
+    assert o.coarsening == tpf.TPF_COARSEN_PMIS and o.smoother == tpf.TPF_SMOOTH_L1_JACOBI
+    assert o.interp == tpf.TPF_INTERP_AUTO and o.nu1 == 1 and o.nu2 == 1
+    good = dict(interp=tpf.TPF_INTERP_CLASSICAL, smoother=tpf.TPF_SMOOTH_MC_GS,
+                coarsening=tpf.TPF_COARSEN_CLJP)
+    o2 = tpf.tpf_precond_default_opts(tpf.TPF_PREC_BF)
+    for k, v in good.items():
+        setattr(o2, k, v)
+    tpf.tpf_precond_destroy(tpf.tpf_precond_create(o2))
+    for field, bad_value in (("interp", 4), ("smoother", 3), ("coarsening", 2), ("coarsening", -1)):
+        b = tpf.tpf_precond_default_opts(tpf.TPF_PREC_BF)
+        setattr(b, field, bad_value)
+        with pytest.raises(tpf.TpfError) as e:
+            tpf.tpf_precond_create(b)
+        assert e.value.code == -1, (field, bad_value)
+
+
+def test_noalloc_solve_host_checks():
+    """tpf_solve_noalloc rejects null arguments and restarts outside
+    [1, 64] before any device work."""
+    lib = tpf.load()
+    o = tpf.SolveOpts(1e-8, 30, 1000)
+    info = tpf.SolveInfo()
+    assert lib.tpf_solve_noalloc(None, None, None, None, ctypes.byref(o), ctypes.byref(info),
+                                 None) == -1
+    p = ctypes.c_void_p(8)
+    o.restart = 0
+    assert lib.tpf_solve_noalloc(p, None, p, p, ctypes.byref(o), ctypes.byref(info), None) == -1
+    buf = ctypes.create_string_buffer(256)
+    lib.tpf_last_error(buf, 256)
+    assert b"restart" in buf.value
+
+
 def test_server_host_side_checks():
     lib = tpf.load()
     o = tpf.tpf_server_default_opts()
