@@ -55,6 +55,9 @@ def parse():
                     help="first run a plain device copy of this many MiB (calibrates the "
                          "FETCH_SIZE/WRITE_SIZE counters of a profiler run)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
+    ap.add_argument("--no-c4", action="store_true",
+                    help="skip the 256x256x128 Newton sequence (10 Jacobians, rebuild vs reuse, "
+                         "FP64 vs FP32, HBM footprint)")
     ap.add_argument("--graphs", action="store_true",
                     help="replay recorded V-cycle graphs instead of launching every kernel")
     ap.add_argument("--serve-full", action="store_true",
@@ -841,6 +844,11 @@ def main():
         tpf.tpf_kernel_timing(0)
         serving = serve_stream(torch, tpf, driver, inputs, args)
 
+    c4 = None
+    if not args.no_c4:
+        log("[bench] 256x256x128 Newton sequence")
+        c4 = study_newton(torch, tpf, driver, inputs, args)
+
     cpu, vs_oracle = None, None
     if not args.no_cpu_baseline:
         log(f"[bench] CPU baseline: oracle on {args.cpu_grid} at {head}")
@@ -887,6 +895,7 @@ def main():
                            "avg_us": round(1e3 * v[1] / v[0], 2)} for k, v in ktab.items()},
         "cpu_baseline": cpu,
         "serving": serving,
+        "c4_newton_sequence": c4,
         "p99_latency_ms": serving["poisson"]["p99_latency_ms"] if serving else None,
     }
     print(json.dumps(out), flush=True)
