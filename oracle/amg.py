@@ -33,6 +33,16 @@ deterministic, data-parallel ones; this module states exactly those:
    w_ij = -(a_ij + sum_k a_ik a-bar_kj / d_ik) / a~_ii,
    a~_ii = a_ii + (weak off-diagonal entries of row i) + (a_ik of every
    strong F neighbour with d_ik = 0);
+3a. interpolation truncation (a setting of this build; the paper leaves the
+   sparsity of P to its AMG package): with pmax > 0 or factor > 0, each row
+   of P ranks its entries by |w_ij| rounded to FP32 (larger first; the lower
+   column first among equal magnitudes) and keeps those ranked below pmax
+   (all when pmax = 0) whose rounded magnitude is at least factor times the
+   row's largest; the kept positive entries are then scaled by
+   (sum of the row's positive entries) / (sum of the kept positive ones),
+   and the negative ones likewise, so each sign's row sum is unchanged
+   (a sign with no kept entry loses its sum); sums run in ascending column
+   order.  Default pmax = 3, factor = 0 on every level;
 4. R = P^T, A_c = R (A P) with the symbolic pattern (no dropping);
 5. stop when n <= coarse_max, n_c == 0, n_c > 0.9 n, or max_levels; the
    coarsest level is solved by dense LU with partial pivoting when it has at
@@ -365,12 +375,62 @@ def classical_interpolation(A, mask, cf):
     return P, cidx
 
 
-def interpolation(A, mask, cf, kind):
+TRUNC_PMAX = 3       # default: at most three interpolatory points per row
+TRUNC_FACTOR = 0.0
+
+
+def truncate_interpolation(P, pmax, factor=0.0):
+    """Interpolation truncation (module docstring, item 3a)."""
+    P = P.tocsr()
+    P.sort_indices()
+    if pmax <= 0 and factor <= 0.0:
+        return P
+    rp, ci, pv = P.indptr, P.indices, P.data
+    keep = np.ones(P.nnz, bool)
+    val = pv.astype(float).copy()
+    lengths = np.diff(rp)
+    # rows that can change (factor < 1: a single entry is always kept, and
+    # with factor = 0 a row of at most pmax entries keeps all of them)
+    may_change = lengths > 1 if factor > 0.0 else lengths > pmax
+    for i in np.flatnonzero(may_change):
+        ents = list(range(rp[i], rp[i + 1]))        # ascending column
+        key = {e: float(np.float32(abs(pv[e]))) for e in ents}
+        largest = max(key.values())
+        ranked = sorted(ents, key=lambda e: (-key[e], ci[e]))
+        kept = {e for r, e in enumerate(ranked)
+                if (pmax <= 0 or r < pmax) and key[e] >= factor * largest}
+        pos_all = neg_all = pos_kept = neg_kept = 0.0
+        for e in ents:
+            if pv[e] > 0:
+                pos_all += pv[e]
+                if e in kept:
+                    pos_kept += pv[e]
+            elif pv[e] < 0:
+                neg_all += pv[e]
+                if e in kept:
+                    neg_kept += pv[e]
+        for e in ents:
+            if e not in kept:
+                keep[e] = False
+            elif pv[e] > 0:
+                val[e] = pv[e] * (pos_all / pos_kept)
+            elif pv[e] < 0:
+                val[e] = pv[e] * (neg_all / neg_kept)
+    rows = np.repeat(np.arange(P.shape[0]), lengths)[keep]
+    Q = sp.csr_matrix((val[keep], (rows, ci[keep])), shape=P.shape)
+    Q.sort_indices()
+    return Q
+
+
+def interpolation(A, mask, cf, kind, pmax=0, factor=0.0):
+    """P of the given kind, then truncated (item 3a) when pmax or factor is set."""
     if kind == "ext+i":
-        return extended_i_interpolation(A, mask, cf)
-    if kind == "classical":
-        return classical_interpolation(A, mask, cf)
-    return direct_interpolation(A, mask, cf)
+        P, cidx = extended_i_interpolation(A, mask, cf)
+    elif kind == "classical":
+        P, cidx = classical_interpolation(A, mask, cf)
+    else:
+        P, cidx = direct_interpolation(A, mask, cf)
+    return truncate_interpolation(P, pmax, factor), cidx
 
 
 def galerkin(A, P):
@@ -516,7 +576,8 @@ class Hierarchy:
 
     def __init__(self, A, theta=0.25, coarse_max=128, max_levels=25, seed=0x5eed,
                  dense_max=1024, interp="direct", smoother="l1jacobi", nu1=1, nu2=1,
-                 cheb_degree=2, cheb_eig_iters=10, coarsening="pmis"):
+                 cheb_degree=2, cheb_eig_iters=10, coarsening="pmis", trunc_pmax=TRUNC_PMAX,
+                 trunc_factor=TRUNC_FACTOR):
         self.levels = []
         self.interp = interp
         self.dense_max = dense_max
@@ -534,7 +595,7 @@ class Hierarchy:
             nc = int((cf == C_PT).sum())
             if nc == 0 or nc > 0.9 * lvl.n:
                 break
-            P, _ = interpolation(lvl.A, mask, cf, interp)
+            P, _ = interpolation(lvl.A, mask, cf, interp, trunc_pmax, trunc_factor)
             Ac, R = galerkin(lvl.A, P)
             lvl.mask, lvl.cf, lvl.P, lvl.R = mask, cf, P, R
             A = Ac

@@ -373,6 +373,89 @@ def test_classical_interpolation_closed_forms():
     np.testing.assert_array_equal(P2.indices, Pdir.indices)
 
 
+def _row(P, i):
+    P = P.tocsr()
+    sl = slice(P.indptr[i], P.indptr[i + 1])
+    return list(P.indices[sl]), list(P.data[sl])
+
+
+def test_truncation_hand_weights():
+    """Interpolation truncation by hand.  Row 0 holds w = (0.5, -0.1, 0.3,
+    0.3, 0.05, -0.2) in columns 0..5: its positive sum is 1.15, its negative
+    sum -0.3.
+    * pmax 3 keeps columns 0, 2, 3; the positives scale by 1.15/1.1 and the
+      negative sum is lost (no negative kept);
+    * pmax 2 keeps 0 and 2 (the tie of 0.3 goes to the lower column), scale
+      1.15/0.8;
+    * pmax 4 also keeps column 5, whose sign's sum -0.3 it then carries;
+    * factor 0.5 alone drops everything below 0.25 (the same as pmax 3);
+    * a large negative entry ranks by magnitude (row 1: (-0.9, 0.2, 0.1),
+      pmax 1 keeps -0.9 unchanged);
+    * magnitudes equal in FP32 tie (row 2: 0.3 and 0.3(1 + 2^-40), pmax 1
+      keeps column 0 although column 1 is larger in FP64);
+    * pmax 0 and factor 0 leave P as it is."""
+    w0 = [0.5, -0.1, 0.3, 0.3, 0.05, -0.2]
+    w2 = [0.3, 0.3 * (1 + 2.0 ** -40)]
+    rows = [0] * 6 + [1] * 3 + [2] * 2
+    cols = list(range(6)) + [0, 1, 2] + [0, 1]
+    vals = w0 + [-0.9, 0.2, 0.1] + w2
+    P = sp.csr_matrix((vals, (rows, cols)), shape=(3, 6))
+    k = 1.15 / 1.1
+    c, v = _row(amg.truncate_interpolation(P, 3), 0)
+    assert c == [0, 2, 3]
+    np.testing.assert_allclose(v, [0.5 * k, 0.3 * k, 0.3 * k], rtol=1e-15)
+    c, v = _row(amg.truncate_interpolation(P, 2), 0)
+    assert c == [0, 2]
+    np.testing.assert_allclose(v, [0.5 * 1.15 / 0.8, 0.3 * 1.15 / 0.8], rtol=1e-15)
+    c, v = _row(amg.truncate_interpolation(P, 4), 0)
+    assert c == [0, 2, 3, 5]
+    np.testing.assert_allclose(v, [0.5 * k, 0.3 * k, 0.3 * k, -0.3], rtol=1e-15)
+    assert abs(sum(v) - sum(w0)) <= 1e-15
+    c, v = _row(amg.truncate_interpolation(P, 0, 0.5), 0)
+    assert c == [0, 2, 3]
+    np.testing.assert_allclose(v, [0.5 * k, 0.3 * k, 0.3 * k], rtol=1e-15)
+    assert _row(amg.truncate_interpolation(P, 1), 1) == ([0], [-0.9])
+    c, v = _row(amg.truncate_interpolation(P, 1), 2)
+    assert c == [0]
+    np.testing.assert_allclose(v, [sum(w2)], rtol=1e-15)
+    Q = amg.truncate_interpolation(P, 0, 0.0)
+    assert (Q != P).nnz == 0
+
+
+def test_truncation_keeps_row_sums_and_default_hierarchy():
+    """On the S~ of the 3D workload family: with the default (pmax 3) every
+    P row holds at most three entries, every row whose signs each keep an
+    entry keeps its sum, rows of at most three entries are untouched, and
+    the hierarchy's operator complexity falls below the untruncated one's."""
+    c = inputs.config_c3(16, 16, 8)
+    rp, ci, v, _ = newton.linear_system(c)
+    M = precond.Preconditioner("bf", rp, ci, v, (16, 16, 8))
+    S = M.S.tocsr()
+    mask = amg.strength(S, 0.25)
+    cf, _ = amg.pmis(S, mask, 0x5eed)
+    P, _ = amg.extended_i_interpolation(S, mask, cf)
+    Q, _ = amg.interpolation(S, mask, cf, "ext+i", amg.TRUNC_PMAX, amg.TRUNC_FACTOR)
+    assert amg.TRUNC_PMAX == 3 and amg.TRUNC_FACTOR == 0.0
+    lp, lq = np.diff(P.indptr), np.diff(Q.indptr)
+    assert lq.max() <= 3 and (lp > 3).any()
+    short = np.flatnonzero(lp <= 3)
+    for i in short[:2000]:
+        assert _row(P, i) == _row(Q, i)
+    checked = 0
+    for i in np.flatnonzero(lp > 3):
+        _, pv = _row(P, i)
+        _, qv = _row(Q, i)
+        pv, qv = np.array(pv), np.array(qv)
+        if ((qv > 0).any() or not (pv > 0).any()) and ((qv < 0).any() or not (pv < 0).any()):
+            assert abs(qv.sum() - pv.sum()) <= 1e-14 * np.abs(pv).sum()
+            checked += 1
+    assert checked > 0
+    Hd = amg.Hierarchy(S, interp="ext+i")
+    Hn = amg.Hierarchy(S, interp="ext+i", trunc_pmax=0)
+    assert all(np.diff(L.P.indptr).max() <= 3 for L in Hd.levels[:-1])
+    assert Hd.stats()["operator_complexity"] < Hn.stats()["operator_complexity"]
+
+
 def test_gs_coloring_and_sweeps_are_triangular_solves():
     """Multicolour Gauss-Seidel on a nonsymmetric TPFA block: no two
     neighbours of A + A^T share a colour, and a forward sweep equals the
