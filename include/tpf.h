@@ -208,6 +208,15 @@ typedef struct tpf_precond_opts {
                            (1, 1); a Chebyshev step is one polynomial */
   int cheb_degree;      /* Chebyshev polynomial degree in [1, 8] (2) */
   int coarsening;       /* TPF_COARSEN_* (PMIS) */
+  int trunc_pmax;       /* interpolation truncation, every level: each row of P keeps at most
+                           this many entries, ranked by magnitude rounded to FP32 (larger
+                           first, lower column first among equal ones); 0 = no limit; in
+                           [0, 64] (3) */
+  double trunc_factor;  /* and drops entries below trunc_factor times the row's largest
+                           magnitude; in [0, 1) (0).  The kept positive and the kept negative
+                           entries are rescaled so that each sign's row sum is unchanged.  A
+                           setting of this library: the paper leaves the sparsity of P to its
+                           AMG package (Sec. 3.2, Sec. 4.1) */
 } tpf_precond_opts;
 /* Fills opts with the defaults above for the given kind. */
 int tpf_precond_default_opts(int kind, tpf_precond_opts* opts);

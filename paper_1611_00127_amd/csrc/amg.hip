@@ -507,6 +507,78 @@ __global__ void __launch_bounds__(256) k_classical_fill(int n, const int* __rest
     }
 }
 
+// ---------------------------------------------------------------- truncation
+// Interpolation truncation, one thread per row of P (rows hold a few
+// entries; a rank is a count over the row).  Entry a is ranked by its
+// magnitude rounded to FP32, larger first, the lower column first among
+// equal magnitudes; it is kept if its rank is below pmax (every rank when
+// pmax = 0) and its rounded magnitude reaches factor times the row's largest.
+// The kept positive entries are scaled by (sum of the row's positive
+// entries) / (sum of the kept positive ones), the negative ones likewise.
+// Row i's entries sit at [start[i], start[i] + len[i]) in ascending column
+// order (len == nullptr: CSR, len = start[i+1] - start[i]).  Without out_rp
+// the kept count goes to cnt[i]; with it the kept entries are written from
+// out_rp[i] on.
+__device__ inline double trunc_key(double w) { return double(float(fabs(w))); }
+
+template <class Off>
+__global__ void __launch_bounds__(256) k_truncate(int n, const Off* __restrict__ start,
+                                                  const int* __restrict__ len,
+                                                  const int* __restrict__ ci,
+                                                  const double* __restrict__ v, int pmax,
+                                                  double factor, int* __restrict__ cnt,
+                                                  const int* __restrict__ out_rp,
+                                                  int* __restrict__ out_ci,
+                                                  double* __restrict__ out_v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t lo = int64_t(start[i]);
+  const int m = len ? len[i] : int(int64_t(start[i + 1]) - lo);
+  const int* rci = ci + lo;
+  const double* rv = v + lo;
+  double largest = 0.0;
+  for (int a = 0; a < m; ++a) largest = fmax(largest, trunc_key(rv[a]));
+  const double thr = factor * largest;
+  auto kept = [&](int a) {
+    const double ka = trunc_key(rv[a]);
+    if (!(ka >= thr)) return false;
+    if (pmax <= 0) return true;
+    int rank = 0;
+    for (int b = 0; b < m && rank < pmax; ++b) {
+      const double kb = trunc_key(rv[b]);
+      rank += kb > ka || (kb == ka && rci[b] < rci[a]);
+    }
+    return rank < pmax;
+  };
+  double pos = 0.0, neg = 0.0, kpos = 0.0, kneg = 0.0;
+  int k = 0;
+  for (int a = 0; a < m; ++a) {
+    const double w = rv[a];
+    const bool keep = kept(a);
+    k += keep;
+    if (w > 0.0) {
+      pos += w;
+      if (keep) kpos += w;
+    } else if (w < 0.0) {
+      neg += w;
+      if (keep) kneg += w;
+    }
+  }
+  if (!out_rp) {
+    cnt[i] = k;
+    return;
+  }
+  const double spos = kpos != 0.0 ? pos / kpos : 1.0, sneg = kneg != 0.0 ? neg / kneg : 1.0;
+  int q = out_rp[i];
+  for (int a = 0; a < m; ++a) {
+    if (!kept(a)) continue;
+    const double w = rv[a];
+    out_ci[q] = rci[a];
+    out_v[q] = w > 0.0 ? w * spos : (w < 0.0 ? w * sneg : w);
+    ++q;
+  }
+}
+
 // ---------------------------------------------------------------- CLJP
 // CLJP coarsening (Cleary, Falgout, Henson, Jones).  Edges of the strength
 // graph S (i -> j: i depends on j) are alive until a heuristic removes them;
@@ -2076,10 +2148,26 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
       flat(I64{}, I256{}, I512{}, 4);
       TPF_CHECK_LAUNCH();
       fork.join();
-      L.P.nnz = scan_exclusive(cnt.p, L.P.rp.p, n, s);
-      L.P.ci.alloc(L.P.nnz > 0 ? L.P.nnz : 1, s);
-      L.P.v.alloc(L.P.nnz > 0 ? L.P.nnz : 1, s);
-      pack_rows(n, toff.p, L.P.rp.p, L.P.nnz, tci.p, tv.p, L.P.ci.p, L.P.v.p, s);
+      if (o.truncates()) {
+        // truncation packs the staged rows itself
+        Buf<int> kept(n, s);
+        k_truncate<int64_t><<<grid_for(n, 256), 256, 0, s>>>(
+            n, toff.p, cnt.p, tci.p, tv.p, o.trunc_pmax, o.trunc_factor, kept.p, nullptr, nullptr,
+            nullptr);
+        TPF_CHECK_LAUNCH();
+        L.P.nnz = scan_exclusive(kept.p, L.P.rp.p, n, s);
+        L.P.ci.alloc(L.P.nnz > 0 ? L.P.nnz : 1, s);
+        L.P.v.alloc(L.P.nnz > 0 ? L.P.nnz : 1, s);
+        k_truncate<int64_t><<<grid_for(n, 256), 256, 0, s>>>(
+            n, toff.p, cnt.p, tci.p, tv.p, o.trunc_pmax, o.trunc_factor, nullptr, L.P.rp.p,
+            L.P.ci.p, L.P.v.p);
+        TPF_CHECK_LAUNCH();
+      } else {
+        L.P.nnz = scan_exclusive(cnt.p, L.P.rp.p, n, s);
+        L.P.ci.alloc(L.P.nnz > 0 ? L.P.nnz : 1, s);
+        L.P.v.alloc(L.P.nnz > 0 ? L.P.nnz : 1, s);
+        pack_rows(n, toff.p, L.P.rp.p, L.P.nnz, tci.p, tv.p, L.P.ci.p, L.P.v.p, s);
+      }
     } else {
       DISPATCH_LPR(lpr, LL, {  // lanes per row of A, as for the strength kernels
         k_interp_count<LL><<<rblocks, 256, 0, s>>>(n, L.A.rp.p, L.A.ci.p, L.mask.p, L.cf.p,
@@ -2102,6 +2190,24 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
         });
       }
       TPF_CHECK_LAUNCH();
+      if (o.truncates()) {
+        Csr<double> Pt;
+        Pt.nrows = n;
+        Pt.ncols = int(nc);
+        Pt.rp.alloc(n + 1, s);
+        k_truncate<int><<<grid_for(n, 256), 256, 0, s>>>(n, L.P.rp.p, nullptr, L.P.ci.p, L.P.v.p,
+                                                         o.trunc_pmax, o.trunc_factor, cnt.p,
+                                                         nullptr, nullptr, nullptr);
+        TPF_CHECK_LAUNCH();
+        Pt.nnz = scan_exclusive(cnt.p, Pt.rp.p, n, s);
+        Pt.ci.alloc(Pt.nnz > 0 ? Pt.nnz : 1, s);
+        Pt.v.alloc(Pt.nnz > 0 ? Pt.nnz : 1, s);
+        k_truncate<int><<<grid_for(n, 256), 256, 0, s>>>(n, L.P.rp.p, nullptr, L.P.ci.p, L.P.v.p,
+                                                         o.trunc_pmax, o.trunc_factor, nullptr,
+                                                         Pt.rp.p, Pt.ci.p, Pt.v.p);
+        TPF_CHECK_LAUNCH();
+        L.P = std::move(Pt);
+      }
     }
     phase.reset();
     phase.reset(new TimedScope(ph_transpose.c_str(), s));

@@ -22,6 +22,11 @@ struct AmgOpts {
   int nu1 = 1, nu2 = 1; // pre- and post-smoothing steps
   int cheb_degree = 2;
   int cheb_eig_iters = 10;  // power steps estimating the top eigenvalue of D^{-1} A
+  // interpolation truncation: at most trunc_pmax entries per row of P (0: no
+  // limit), none below trunc_factor times the row's largest magnitude
+  int trunc_pmax = 0;
+  double trunc_factor = 0.0;
+  bool truncates() const { return trunc_pmax > 0 || trunc_factor > 0.0; }
   // V(1,1) l1-Jacobi runs the fused smoother kernels; anything else the
   // generic sweeps
   bool fused_cycle() const { return smoother == 0 && nu1 == 1 && nu2 == 1; }

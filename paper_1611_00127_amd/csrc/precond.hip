@@ -757,6 +757,8 @@ AmgOpts amg_opts(const tpf_precond_opts& o, bool pressure_like) {
   a.nu1 = o.nu1;
   a.nu2 = o.nu2;
   a.cheb_degree = o.cheb_degree;
+  a.trunc_pmax = o.trunc_pmax;
+  a.trunc_factor = o.trunc_factor;
   return a;
 }
 
@@ -1030,6 +1032,8 @@ int tpf_precond_default_opts(int kind, tpf_precond_opts* o) {
     o->nu2 = 1;
     o->cheb_degree = 2;
     o->coarsening = TPF_COARSEN_PMIS;
+    o->trunc_pmax = 3;
+    o->trunc_factor = 0.0;
   });
 }
 
@@ -1058,6 +1062,10 @@ int tpf_precond_create(const tpf_precond_opts* o, tpf_precond** out) {
                 "cheb_degree must be in [1, 8]");
     TPF_REQUIRE(o->coarsening == TPF_COARSEN_PMIS || o->coarsening == TPF_COARSEN_CLJP,
                 TPF_ERR_INVALID_ARG, "unknown coarsening %d", o->coarsening);
+    TPF_REQUIRE(o->trunc_pmax >= 0 && o->trunc_pmax <= 64, TPF_ERR_INVALID_ARG,
+                "trunc_pmax must be in [0, 64]");
+    TPF_REQUIRE(o->trunc_factor >= 0.0 && o->trunc_factor < 1.0, TPF_ERR_INVALID_ARG,
+                "trunc_factor must be in [0, 1)");
     auto* M = new tpf_precond();
     M->o = *o;
     *out = M;

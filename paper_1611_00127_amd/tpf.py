@@ -64,7 +64,8 @@ class PrecondOpts(ctypes.Structure):
     _fields_ = [("kind", c_int), ("precision", c_int), ("theta", c_double), ("max_levels", c_int),
                 ("coarse_max", c_int), ("dense_max", c_int), ("interp", c_int),
                 ("hash_seed", c_uint64), ("exti_route", c_int), ("smoother", c_int),
-                ("nu1", c_int), ("nu2", c_int), ("cheb_degree", c_int), ("coarsening", c_int)]
+                ("nu1", c_int), ("nu2", c_int), ("cheb_degree", c_int), ("coarsening", c_int),
+                ("trunc_pmax", c_int), ("trunc_factor", c_double)]
 
 
 class HierStats(ctypes.Structure):

@@ -13,7 +13,9 @@ smoother), against the oracle, through the C ABI:
   oracle's cycle on the GPU's levels, and BF solves within +-1 iteration;
 * CLJP coarsening: every level's C/F splitting bit-exact (with PMIS- and
   CLJP-built coarse levels and each interpolation), and BF solves with all
-  three of the paper's components together.
+  three of the paper's components together;
+* interpolation truncation settings besides the default (at most three
+  entries per row): every level, and BF solves within +-1 iteration.
 """
 import numpy as np
 import pytest
@@ -158,4 +160,35 @@ def test_cljp_levels(gpu, kind, hier, interp, case):
     g, M = _setup(driver, tpf, c, kind, **opts)
     nlev = _check_levels(tpf, M, hier, interp, coarsening="cljp")
     say(f"  {nlev} levels")
+    M.close(); g.close()
+
+
+@pytest.mark.parametrize("pmax,factor", [(0, 0.0), (2, 0.0), (0, 0.3), (4, 0.2)])
+def test_truncation_levels_and_solve(gpu, pmax, factor):
+    """Interpolation truncation settings other than the default (no
+    truncation, two entries per row, a relative threshold alone, both): every
+    level of both BF hierarchies against the oracle's truncated P, and the BF
+    solve at the initial condition of the 3D workload family within +-1
+    iteration of the oracle's, relres <= 1e-8, solution within 1e-6."""
+    driver, tpf, torch = gpu
+    say(f"[truncation] pmax {pmax} factor {factor}")
+    g, M = _setup(driver, tpf, _case3d(), "bf", coarse_max=40, trunc_pmax=pmax,
+                  trunc_factor=factor)
+    for hier, interp in ((1, "ext+i"), (0, "direct")):
+        nlev = _check_levels(tpf, M, hier, interp)
+        say(f"  hierarchy {hier}: {nlev} levels")
+    M.close(); g.close()
+    c = inputs.config_c3(24, 20, 8)
+    g, M = _setup(driver, tpf, c, "bf", trunc_pmax=pmax, trunc_factor=factor)
+    b = g.rhs().contiguous()
+    x = torch.empty_like(b)
+    info = driver.solve(g, M, b, x, rtol=1e-8)
+    J, bn, xo, io = _oracle_solve(g, c, dict(trunc_pmax=pmax, trunc_factor=factor))
+    xs = x.cpu().numpy()
+    rel = np.linalg.norm(bn - J @ xs) / np.linalg.norm(bn)
+    err = np.linalg.norm(xs - xo) / np.linalg.norm(xo)
+    say(f"  gpu its={info.iterations} oracle its={io['iterations']} relres={rel:.2e} err={err:.2e}")
+    assert info.status == tpf.TPF_CONVERGED and rel <= 1e-8
+    assert abs(info.iterations - io["iterations"]) <= 1
+    assert err <= 1e-6
     M.close(); g.close()

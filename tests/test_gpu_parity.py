@@ -136,8 +136,8 @@ def test_schur_parity(gpu, nx, ny, nz):
 
 def _check_levels(tpf, M, hier, interp, coarsening="pmis"):
     """Each level's setup from the GPU's own level matrix (identical bits):
-    strength graph, C/F (PMIS or CLJP), P (direct, classical or extended+i),
-    R and A_c."""
+    strength graph, C/F (PMIS or CLJP), P (direct, classical or extended+i,
+    truncated as the preconditioner's options say), R and A_c."""
     st = M.stats()
     nlev = st.levels[hier]
     assert nlev >= 2
@@ -158,7 +158,7 @@ def _check_levels(tpf, M, hier, interp, coarsening="pmis"):
         ocf, _ = amg.coarsen(A, mask, 0x5eed, coarsening)
         assert np.array_equal(cf, ocf), f"C/F level {l}"
         P = tpf.csr_to_numpy(tpf.tpf_precond_matrix(M.M, hier, l, tpf.TPF_MAT_P))
-        Po, _ = amg.interpolation(A, mask, ocf, interp)
+        Po, _ = amg.interpolation(A, mask, ocf, interp, M.opts.trunc_pmax, M.opts.trunc_factor)
         assert np.array_equal(P[0], Po.indptr) and np.array_equal(P[1], Po.indices), f"P level {l}"
         ok, worst = _row_scale_close(P[2], Po.data, Po.indptr, 1e-12)
         assert ok, (l, worst)
