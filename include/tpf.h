@@ -419,6 +419,9 @@ typedef struct tpf_result {
   double solve_ms;        /* FGMRES, first phase queued to last phase read */
   double latency_ms;      /* submit to completion */
   int refreshed;          /* 1 if the hierarchy was refreshed, 0 if built */
+  size_t reserved_bytes;  /* bytes of the HBM budget the request was admitted with: its FGMRES
+                             workspace plus, for a sequence not resident, the expected bytes of
+                             its build (for TPF_ERR_OVER_BUDGET: the bytes that did not fit) */
 } tpf_result;
 
 typedef struct tpf_server_counters {

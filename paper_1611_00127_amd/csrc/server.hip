@@ -109,6 +109,7 @@ struct Slot {
   double setup_ms = 0.0;
   int refreshed = 0;
   size_t ws_bytes = 0;   // reserved while in setup, the FGMRES workspace after
+  size_t admitted = 0;   // bytes of the budget reserved at admission
   int err_code = TPF_OK;
   std::string err_msg;
   bool busy() const { return state.load(std::memory_order_acquire) != kFree; }
@@ -256,8 +257,9 @@ struct tpf_server {
   }
 
   void finish_request(const Pending& p, int status, int iters, double est, double rel,
-                      double setup_ms, double solve_ms, int refreshed) {
+                      double setup_ms, double solve_ms, int refreshed, size_t reserved = 0) {
     tpf_result r{};
+    r.reserved_bytes = reserved;
     r.status = status;
     r.iterations = iters;
     r.relres_est = est;
@@ -384,6 +386,7 @@ struct tpf_server {
     sl.started = false;
     sl.refreshed = 0;
     sl.ws_bytes = reserve;
+    sl.admitted = reserve;
     sl.err_code = TPF_OK;
     sl.err_msg.clear();
     {
@@ -438,7 +441,7 @@ struct tpf_server {
         Pending bad = p;
         it = queue.erase(it);
         set_last_error(TPF_ERR_OVER_BUDGET, "request does not fit in the HBM budget");
-        finish_request(bad, TPF_ERR_OVER_BUDGET, 0, NAN, NAN, 0.0, 0.0, 0);
+        finish_request(bad, TPF_ERR_OVER_BUDGET, 0, NAN, NAN, 0.0, 0.0, 0, need);
         continue;
       }
       if (!make_room(need, p.rq.sequence)) {
@@ -448,7 +451,7 @@ struct tpf_server {
         Pending bad = p;         // cannot fit even with the device to itself
         it = queue.erase(it);
         set_last_error(TPF_ERR_OVER_BUDGET, "request does not fit in the HBM budget");
-        finish_request(bad, TPF_ERR_OVER_BUDGET, 0, NAN, NAN, 0.0, 0.0, 0);
+        finish_request(bad, TPF_ERR_OVER_BUDGET, 0, NAN, NAN, 0.0, 0.0, 0, need);
         continue;
       }
       Pending go = p;
@@ -484,9 +487,10 @@ struct tpf_server {
         uint64_t seq = p.rq.sequence;
         double setup_ms = sl.setup_ms;
         int code = sl.err_code;
+        const size_t admitted = sl.admitted;
         release(sl);
         res.erase(seq);  // rebuilt from scratch by the next request
-        finish_request(p, code, 0, NAN, NAN, setup_ms, 0.0, 0);
+        finish_request(p, code, 0, NAN, NAN, setup_ms, 0.0, 0, admitted);
         ++done;
         continue;
       }
@@ -521,7 +525,7 @@ struct tpf_server {
       }
       TPF_HIP(hipStreamSynchronize(sl.s));
       finish_request(sl.req, f.status, f.total, f.est, f.relres, sl.setup_ms, ms_since(f.t0),
-                     sl.refreshed);
+                     sl.refreshed, sl.admitted);
       release(sl);
       ++done;
     }

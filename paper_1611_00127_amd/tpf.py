@@ -100,7 +100,8 @@ class Request(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("status", c_int), ("iterations", c_int), ("relres_est", c_double),
                 ("relres_true", c_double), ("setup_ms", c_double), ("solve_ms", c_double),
-                ("latency_ms", c_double), ("refreshed", c_int)]
+                ("latency_ms", c_double), ("refreshed", c_int),
+                ("reserved_bytes", c_size_t)]
 
 
 class ServerCounters(ctypes.Structure):

@@ -136,13 +136,17 @@ def test_budget_admission_and_eviction(env):
         g = driver.GpuCase(case)
         same.append((case, g, [g.u.clone()]))
     torch.cuda.synchronize()
-    single = 0
+    single = first = 0
     for r in range(3):
-        _, st = _serve(driver, torch, same, [(r, 0)], max_active=1)
+        out, st = _serve(driver, torch, same, [(r, 0)], max_active=1)
         single = max(single, st.peak_bytes)
-    budget = int(1.4 * single)   # room for one resident sequence and its solve
+        first = max(first, out[(r, 0)][1].reserved_bytes)
+    # room for one resident sequence and its solve; at least what a fresh
+    # server reserves for the first build of an unseen grid size (its
+    # estimate before any build is conservative)
+    budget = max(int(1.4 * single), first)
     order = [(r, 0) for r in range(3)] * 2
-    say(f"budget {budget} bytes (single-request peak {single})")
+    say(f"budget {budget} bytes (single-request peak {single}, first admission {first})")
     torch.cuda.synchronize()
     base, _ = tpf.allocator_bytes()
     tpf.reset_allocator_peak()
@@ -153,13 +157,15 @@ def test_budget_admission_and_eviction(env):
     # device memory actually drawn from torch's allocator while serving, not
     # the server's own bookkeeping, stays within the budget
     assert drawn <= budget
-    assert st.evictions >= 5
+    assert st.evictions >= 3
     assert len(res) == 3  # keys repeat: the second round overwrote the first
     for key, (x, r) in res.items():
         assert r.status == tpf.TPF_CONVERGED, key
+        assert 0 < r.reserved_bytes <= budget
         assert np.all(np.isfinite(x))
     tiny, _ = _serve(driver, torch, same, [(0, 0)], hbm_budget_bytes=1 << 20)
     assert tiny[(0, 0)][1].status == tpf.TPF_ERR_OVER_BUDGET
+    assert tiny[(0, 0)][1].reserved_bytes > 1 << 20
     for _, g, _ in same:
         g.close()
 
