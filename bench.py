@@ -86,6 +86,14 @@ def parse():
                          "Gauss-Seidel) against the defaults")
     ap.add_argument("--study-grid", type=str, default=None,
                     help="grid of the study workload (default: 512x512 / 256x256x128)")
+    ap.add_argument("--traffic-spec", type=str, default=None,
+                    help="write, for the heaviest V-cycle kernels of the FP64 form, the kernel "
+                         "symbol, launch size, algorithmic bytes and source functions to this "
+                         "JSON file (read by --reduce-traffic)")
+    ap.add_argument("--reduce-traffic", type=str, default=None, metavar="DIR",
+                    help="no GPU work: reduce the rocprofv3 outputs under DIR (prof/ kernel "
+                         "trace, pmc_fetch/ and pmc_write/ counters, traffic_spec.json) to the "
+                         "per-kernel HBM traffic file under profiles/")
     return ap.parse_args()
 
 
@@ -230,6 +238,130 @@ def kernel_digest(names):
             return None
         h.update(text[start:end + 3].encode())
     return h.hexdigest()
+
+
+# source functions whose text identifies each V-cycle kernel family's build
+KERNEL_SOURCES = {
+    "k_vc_post": ["amg.hip:k_vc_post", "linalg_dev.hpp:row_dot"],
+    "k_vc_pre_g": ["amg.hip:k_vc_pre_g", "linalg_dev.hpp:row_dot"],
+    "k_vc_pre": ["amg.hip:k_vc_pre", "linalg_dev.hpp:row_dot"],
+    "k_dia_pre2": ["amg.hip:clampi", "amg.hip:xcd_contiguous_block", "amg.hip:k_dia_pre2"],
+    "k_dia_post2": ["amg.hip:clampi", "amg.hip:xcd_contiguous_block", "amg.hip:k_dia_post2"],
+}
+
+# rocprofv3 runs whose outputs --reduce-traffic reads (GPU machine, repository root)
+TRAFFIC_COMMANDS = [
+    "cd /tmp && export TMPDIR=/tmp",
+    "rocprofv3 --kernel-trace --stats --output-format csv -d $GRAFT_REPO_ROOT/gpurun_out/prof "
+    "-o bench -- python3 $GRAFT_REPO_ROOT/bench.py --steps 2 --warmup 1 --no-cpu-baseline "
+    "--no-serve --no-c4",
+    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $GRAFT_REPO_ROOT/gpurun_out/pmc_fetch "
+    "-o fetch -- python3 $GRAFT_REPO_ROOT/bench.py --steps 1 --warmup 0 --no-cpu-baseline "
+    "--no-serve --no-c4 --copy-probe 512 --traffic-spec $GRAFT_REPO_ROOT/gpurun_out/"
+    "traffic_spec.json",
+    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $GRAFT_REPO_ROOT/gpurun_out/pmc_write "
+    "-o write -- python3 $GRAFT_REPO_ROOT/bench.py --steps 1 --warmup 0 --no-cpu-baseline "
+    "--no-serve --no-c4 --copy-probe 512",
+    "python bench.py --reduce-traffic gpurun_out   (here: writes this file)",
+]
+
+
+def launch_threads(st, h, l, timer):
+    """Threads in the launch grid of a V-cycle kernel (256-thread work-groups):
+    how rocprofv3 tells one level's dispatches of a kernel from another's."""
+    n, nnz = int(st.rows[h][l]), int(st.nnz[h][l])
+    K = int(st.l0_diagonals[h]) if l == 0 else 0
+    if K and timer in ("vcycle_pre_residual", "vcycle_post_smooth"):
+        work = n // 2 if n % 2 == 0 else n
+    else:
+        work = n * lanes_per_row(n, nnz)
+    return -(-work // 256) * 256
+
+
+def write_traffic_spec(path, st, kern64, top=4):
+    """The `top` V-cycle kernels of the FP64 form by summed time whose family
+    has listed sources: timer -> [symbol, launch threads, algorithmic bytes,
+    source functions]."""
+    spec = {}
+    for k in sorted(kern64, key=lambda k: -k["total_ms"]):
+        fam = k["symbol"].split("<")[0]
+        if fam not in KERNEL_SOURCES:
+            continue
+        h = HIER_TAGS["bf"].index(k["hier"])
+        timer = f"{k['timer']}[{k['hier']},l{k['level']}]"
+        spec[timer] = [k["symbol"], launch_threads(st, h, k["level"], k["timer"]), k["bytes"],
+                       KERNEL_SOURCES[fam]]
+        if len(spec) == top:
+            break
+    with open(path, "w") as f:
+        json.dump(spec, f, indent=1)
+
+
+def reduce_traffic(d):
+    """Per-kernel HBM traffic from the rocprofv3 runs of TRAFFIC_COMMANDS:
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of each listed kernel's
+    dispatches at its level's launch size, each scaled by what the counter
+    reads for the 512 MiB device copy of the same run, and the kernel-trace
+    durations of the same dispatches.  Writes TRAFFIC_JSON."""
+    import collections
+    import csv
+
+    def counters(path):
+        out = collections.defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            out[(r["Kernel_Name"], int(r["Grid_Size"]))].append(float(r["Counter_Value"]))
+        return out
+
+    fetch = counters(os.path.join(d, "pmc_fetch", "fetch_counter_collection.csv"))
+    write = counters(os.path.join(d, "pmc_write", "write_counter_collection.csv"))
+
+    def copy_kib(c):
+        return max(max(v) for k, v in c.items() if k[0] == "__amd_rocclr_copyBuffer")
+
+    moved = 512 * 1024  # KiB read and written by the copy
+    fk, wk = copy_kib(fetch), copy_kib(write)
+    fs, ws = moved / fk, moved / wk
+    trace = collections.defaultdict(list)
+    for r in csv.DictReader(open(os.path.join(d, "prof", "bench_kernel_trace.csv"))):
+        g = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+        trace[(r["Kernel_Name"], g)].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    spec = json.load(open(os.path.join(d, "traffic_spec.json")))
+    out = {"workload": "3d-128x128x64 BF at Newton iterate 1, FP64 V-cycle kernels of the "
+                       "heaviest summed time",
+           "fetch_scale": round(fs, 6), "write_scale": round(ws, 6),
+           "calibration": f"one 512 MiB device-to-device copy (torch copy_ -> "
+                          f"__amd_rocclr_copyBuffer) in the same runs: FETCH_SIZE {fk} KiB, "
+                          f"WRITE_SIZE {wk} KiB for {moved} KiB moved each way",
+           "commands": TRAFFIC_COMMANDS,
+           "method": "per kernel: dispatches of that symbol whose grid has the stated number "
+                     "of threads (the level's launch); fetch/write = mean FETCH_SIZE / "
+                     "WRITE_SIZE (KiB) per dispatch; HBM bytes = 1024 (fetch_scale * fetch + "
+                     "write_scale * write); trace_* = durations of the same dispatches in the "
+                     "kernel trace",
+           "kernels": {}}
+    for timer, (sym, grid, alg, dig) in spec.items():
+        keys = [k for k in fetch if k[1] == grid and sym in k[0]]
+        if len(keys) != 1:
+            raise SystemExit(f"{len(keys)} kernels named {sym} with {grid} threads in the "
+                             f"counter runs")
+        key = keys[0]
+        fv, wv = fetch[key], write[key]
+        tv = trace.get(key, [])
+        f_avg, w_avg = sum(fv) / len(fv), sum(wv) / len(wv)
+        hbm = (f_avg * fs + w_avg * ws) * 1024
+        out["kernels"][timer] = {
+            "symbol": sym, "grid_threads": grid, "digest_of": dig,
+            "source_sha256": kernel_digest(dig), "dispatches": len(fv),
+            "fetch_kib_per_dispatch": round(f_avg, 2), "write_kib_per_dispatch": round(w_avg, 2),
+            "algorithmic_bytes_per_dispatch": alg, "hbm_bytes_per_dispatch": int(hbm),
+            "traffic_over_algorithmic": round(hbm / alg, 4), "trace_dispatches": len(tv),
+            "trace_avg_us": round(sum(tv) / len(tv) / 1e3, 2) if tv else None,
+            "trace_min_us": round(min(tv) / 1e3, 2) if tv else None,
+            "trace_max_us": round(max(tv) / 1e3, 2) if tv else None}
+    with open(TRAFFIC_JSON, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    return out
 
 
 def stored_traffic(timer, symbol):
@@ -754,6 +886,12 @@ def main():
         print(f"bench.py measures one GPU only: this build runs on a single MI355X "
               f"(--gpus {args.gpus} is not supported)", file=sys.stderr)
         sys.exit(2)
+    if args.reduce_traffic:
+        rec = reduce_traffic(args.reduce_traffic)
+        for timer, k in rec["kernels"].items():
+            log(f"{timer} {k['symbol']}: {k['traffic_over_algorithmic']}x the algorithmic "
+                f"bytes, {k['trace_avg_us']} us")
+        return
     import torch
 
     from paper_1611_00127_amd import driver, inputs, tpf
@@ -819,6 +957,8 @@ def main():
 
     # roofline of the dominant V-cycle kernel: the largest summed time over
     # every level of both hierarchies (FP64 form)
+    if args.traffic_spec:
+        write_traffic_spec(args.traffic_spec, st64, kern64)
     dom = max(kern64, key=lambda k: k["total_ms"])
     avg_ms = dom["total_ms"] / dom["launches"]
     achieved = dom["bytes"] / (avg_ms * 1e-3) / 1e9

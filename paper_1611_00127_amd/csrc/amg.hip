@@ -509,17 +509,21 @@ __global__ void __launch_bounds__(256) k_classical_fill(int n, const int* __rest
 
 // ---------------------------------------------------------------- truncation
 // Interpolation truncation, one thread per row of P (rows hold a few
-// entries; a rank is a count over the row).  Entry a is ranked by its
-// magnitude rounded to FP32, larger first, the lower column first among
-// equal magnitudes; it is kept if its rank is below pmax (every rank when
-// pmax = 0) and its rounded magnitude reaches factor times the row's largest.
-// The kept positive entries are scaled by (sum of the row's positive
-// entries) / (sum of the kept positive ones), the negative ones likewise.
-// Row i's entries sit at [start[i], start[i] + len[i]) in ascending column
-// order (len == nullptr: CSR, len = start[i+1] - start[i]).  Without out_rp
-// the kept count goes to cnt[i]; with it the kept entries are written from
-// out_rp[i] on.
+// entries).  Entries rank by magnitude rounded to FP32, larger first, the
+// lower column first among equal magnitudes; an entry is kept if its rank is
+// below pmax (every rank when pmax = 0) and its rounded magnitude reaches
+// factor times the row's largest.  The kept positive entries are scaled by
+// (sum of the row's positive entries) / (sum of the kept positive ones), the
+// negative ones likewise.  Row i's entries sit at [start[i], start[i] +
+// len[i]) in ascending column order (len == nullptr: CSR, len = start[i+1] -
+// start[i]).  Without out_rp the kept count goes to cnt[i]; with it the kept
+// entries are written from out_rp[i] on.
 __device__ inline double trunc_key(double w) { return double(float(fabs(w))); }
+// (ka, ca) ranks before (kb, cb)
+__device__ inline bool trunc_before(double ka, int ca, double kb, int cb) {
+  return ka > kb || (ka == kb && ca < cb);
+}
+constexpr int kTruncTop = 8;  // pmax up to this selects in registers
 
 template <class Off>
 __global__ void __launch_bounds__(256) k_truncate(int n, const Off* __restrict__ start,
@@ -539,15 +543,49 @@ __global__ void __launch_bounds__(256) k_truncate(int n, const Off* __restrict__
   double largest = 0.0;
   for (int a = 0; a < m; ++a) largest = fmax(largest, trunc_key(rv[a]));
   const double thr = factor * largest;
+  // the last kept rank: the pmax-th entry of the ranking (none when the row
+  // is no longer than pmax)
+  const bool ranked = pmax > 0 && m > pmax;
+  double last_k = -1.0;
+  int last_c = INT_MAX;
+  if (ranked && pmax <= kTruncTop) {
+    double tk[kTruncTop];
+    int tc[kTruncTop];
+#pragma unroll
+    for (int q = 0; q < kTruncTop; ++q) {
+      tk[q] = -1.0;
+      tc[q] = INT_MAX;
+    }
+    for (int a = 0; a < m; ++a) {
+      double k = trunc_key(rv[a]);
+      int c = rci[a];
+      // insertion into the best kTruncTop, best first
+#pragma unroll
+      for (int q = 0; q < kTruncTop; ++q)
+        if (trunc_before(k, c, tk[q], tc[q])) {
+          const double tkq = tk[q];
+          const int tcq = tc[q];
+          tk[q] = k;
+          tc[q] = c;
+          k = tkq;
+          c = tcq;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kTruncTop; ++q)
+      if (q == pmax - 1) {
+        last_k = tk[q];
+        last_c = tc[q];
+      }
+  }
   auto kept = [&](int a) {
     const double ka = trunc_key(rv[a]);
     if (!(ka >= thr)) return false;
-    if (pmax <= 0) return true;
+    if (!ranked) return true;
+    if (pmax <= kTruncTop) return !trunc_before(last_k, last_c, ka, rci[a]);
     int rank = 0;
-    for (int b = 0; b < m && rank < pmax; ++b) {
-      const double kb = trunc_key(rv[b]);
-      rank += kb > ka || (kb == ka && rci[b] < rci[a]);
-    }
+    for (int b = 0; b < m && rank < pmax; ++b)
+      rank += trunc_before(trunc_key(rv[b]), rci[b], ka, rci[a]);
     return rank < pmax;
   };
   double pos = 0.0, neg = 0.0, kpos = 0.0, kneg = 0.0;
