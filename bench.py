@@ -443,8 +443,8 @@ SETUP_PHASES = ("strength", "coarsen", "interp", "transpose", "galerkin", "finis
 def setup_breakdown(torch, tpf, driver, g, precision):
     """One more full BF setup (after a warm-up one) with each phase bracketed
     by HIP events on its stream: block extraction, S~, and per hierarchy
-    (summed over its levels) strength graph, coarsening, interpolation,
-    transpose, Galerkin product, and finishing the levels (smoother
+    (per level and summed over the levels) strength graph, coarsening,
+    interpolation, transpose, Galerkin product, and finishing the levels (smoother
     diagonals, FP32 copies, level-0 diagonal layout, coarsest inverse).  The
     two hierarchies are built concurrently on two streams, so their phases
     overlap in time.  Also the number of host round trips the setup makes."""
@@ -462,9 +462,19 @@ def setup_breakdown(torch, tpf, driver, g, precision):
            "host_round_trips": int(tpf.tpf_kernel_stats("host_syncs")[0])}
     for name in ("setup_blocks", "setup_schur"):
         out[name[6:] + "_ms"] = round(tpf.tpf_kernel_stats(name)[1], 3)
-    for tag in HIER_TAGS["bf"]:
-        out[HIER_NAMES[tag]] = {ph + "_ms": round(tpf.tpf_kernel_stats(f"setup_{ph}[{tag}]")[1], 3)
-                                for ph in SETUP_PHASES}
+    st = M.stats()
+    for h, tag in enumerate(HIER_TAGS["bf"]):
+        per_level = []
+        for l in range(int(st.levels[h])):
+            rec = {ph: round(tpf.tpf_kernel_stats(f"setup_{ph}[{tag},l{l}]")[1], 3)
+                   for ph in SETUP_PHASES if ph != "finish"}
+            if any(rec.values()):  # the coarsest level has no phases (or only the first two)
+                per_level.append(rec)
+        rec = {ph + "_ms": round(sum(p[ph] for p in per_level), 3)
+               for ph in SETUP_PHASES if ph != "finish"}
+        rec["finish_ms"] = round(tpf.tpf_kernel_stats(f"setup_finish[{tag}]")[1], 3)
+        rec["per_level_ms"] = per_level
+        out[HIER_NAMES[tag]] = rec
     tpf.tpf_kernel_stats_reset()
     M.close()
     return out

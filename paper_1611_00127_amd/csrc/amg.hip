@@ -1996,17 +1996,16 @@ void Hierarchy::build(Csr<double>&& A0, const AmgOpts& opts, hipStream_t st) {
   auto L0 = std::make_unique<Level>();
   L0->A = std::move(A0);
   lv.push_back(std::move(L0));
-  // setup phase timers (recorded while kernel timing is on), summed over levels
-  const std::string ph_strength = "setup_strength[" + tag + "]",
-                    ph_coarsen = "setup_coarsen[" + tag + "]",
-                    ph_interp = "setup_interp[" + tag + "]",
-                    ph_transpose = "setup_transpose[" + tag + "]",
-                    ph_galerkin = "setup_galerkin[" + tag + "]",
-                    ph_finish = "setup_finish[" + tag + "]";
+  // setup phase timers (recorded while kernel timing is on), per level
+  const std::string ph_finish = "setup_finish[" + tag + "]";
   while (true) {
     Level& L = *lv.back();
     int n = L.A.nrows;
     if (n <= o.coarse_max || int(lv.size()) >= o.max_levels) break;
+    const std::string sfx = "[" + tag + ",l" + std::to_string(lv.size() - 1) + "]";
+    const std::string ph_strength = "setup_strength" + sfx, ph_coarsen = "setup_coarsen" + sfx,
+                      ph_interp = "setup_interp" + sfx, ph_transpose = "setup_transpose" + sfx,
+                      ph_galerkin = "setup_galerkin" + sfx;
     std::unique_ptr<TimedScope> phase(new TimedScope(ph_strength.c_str(), s));
     // strength of connection
     L.mask.alloc(L.A.nnz > 0 ? L.A.nnz : 1, s);

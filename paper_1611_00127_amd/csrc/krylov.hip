@@ -12,7 +12,9 @@
 // device; the host reads the residual estimate once per step.
 #include <chrono>
 #include <cmath>
+#include <map>
 #include <mutex>
+#include <utility>
 
 #include "krylov.hpp"
 #include "linalg_dev.hpp"
@@ -29,6 +31,35 @@ int krylov_grid(int64_t n) {
   if (g > kKGridMax) g = kKGridMax;
   if (g < 1) g = 1;
   return int(g);
+}
+
+// Work-groups of a grid-stride pass of `kernel` over n entries: at most as
+// many as the device holds resident at once (the larger bases take more
+// registers per thread, and a second, partial round of work-groups would
+// leave most compute units idle at the end), and at most krylov_grid(n).
+template <class K>
+int resident_grid(K kernel, int64_t n) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, int> fit;  // (device, kernel) -> work-groups
+  int dev = 0;
+  TPF_HIP(hipGetDevice(&dev));
+  const auto key = std::make_pair(dev, reinterpret_cast<const void*>(kernel));
+  int g = 0;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = fit.find(key);
+    if (it != fit.end()) {
+      g = it->second;
+    } else {
+      int per_cu = 0, cus = 0;
+      TPF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kKBlock, 0));
+      TPF_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+      g = per_cu > 0 && cus > 0 ? per_cu * cus : kKGridMax;
+      fit[key] = g;
+    }
+  }
+  const int cap = krylov_grid(n);
+  return g < cap ? g : cap;
 }
 
 // block-wise reduction of KMAX running sums into part[k][block] (one row of
@@ -52,77 +83,23 @@ __device__ inline void reduce_store(double* acc, int nk, double* part) {
   }
 }
 
-// pass 1: part = V^T w  (nk vectors)
-template <int KMAX>
-__global__ void __launch_bounds__(kKBlock) k_cgs_dots(int64_t n, int nk, const double* __restrict__ V,
-                                                      const double* __restrict__ w,
-                                                      double* __restrict__ part) {
-  // entries in pairs (n is even and every basis vector 16-byte aligned)
-  double acc[KMAX];
-#pragma unroll
-  for (int k = 0; k < KMAX; ++k) acc[k] = 0.0;
-  const int64_t n2 = n / 2;
-  const double2* V2 = reinterpret_cast<const double2*>(V);
-  const double2* w2 = reinterpret_cast<const double2*>(w);
-  for (int64_t p = int64_t(blockIdx.x) * kKBlock + threadIdx.x; p < n2;
-       p += int64_t(gridDim.x) * kKBlock) {
-    const double2 wi = w2[p];
-#pragma unroll
-    for (int k = 0; k < KMAX; ++k)
-      if (k < nk) {
-        const double2 v = V2[k * n2 + p];
-        acc[k] += v.x * wi.x;
-        acc[k] += v.y * wi.y;
-      }
-  }
-  reduce_store<KMAX>(acc, nk, part);
-}
-
-// pass 2: w -= V h; part = V^T w.  Two lanes per entry, each holding half
-// of the basis (so half the registers): each lane sums h_k v_k over its half,
-// the pair adds the two sums (the same value in both lanes), the first lane
-// writes w, and each lane accumulates its half of the dot products.
-template <int KMAX>
-__global__ void __launch_bounds__(kKBlock) k_cgs_axpy_dots(int64_t n, int nk,
-                                                           const double* __restrict__ V,
-                                                           const double* __restrict__ h,
-                                                           double* __restrict__ w,
-                                                           double* __restrict__ part) {
-  constexpr int KH = (KMAX + 1) / 2;
-  __shared__ double hs[2 * KH];
-  __shared__ double sh[kKBlock / 64][2 * KH];
-  for (int k = threadIdx.x; k < 2 * KH; k += kKBlock) hs[k] = k < nk ? h[k] : 0.0;
-  __syncthreads();
-  const int half = threadIdx.x & 1, k0 = half * KH;
-  double acc[KH];
-#pragma unroll
-  for (int u = 0; u < KH; ++u) acc[u] = 0.0;
-  for (int64_t i = (int64_t(blockIdx.x) * kKBlock + threadIdx.x) >> 1; i < n;
-       i += int64_t(gridDim.x) * (kKBlock / 2)) {
-    double v[KH];
-    double sw = 0.0;
-#pragma unroll
-    for (int u = 0; u < KH; ++u) {
-      v[u] = 0.0;
-      if (k0 + u < nk) {
-        v[u] = V[int64_t(k0 + u) * n + i];
-        sw += hs[k0 + u] * v[u];
-      }
-    }
-    const double wi = w[i] - (sw + __shfl_xor(sw, 1, 64));
-    if (half == 0) w[i] = wi;
-#pragma unroll
-    for (int u = 0; u < KH; ++u)
-      if (k0 + u < nk) acc[u] += v[u] * wi;
-  }
-  // block sums per basis vector: lanes of one half (every other lane) first
+// Block sums of per-lane running sums: lane q of each group of L lanes holds
+// the sums of basis vectors q*KH .. q*KH+KH-1; part[k][block] gets vector k's.
+template <int KH, int L>
+__device__ inline void reduce_store_lanes(const double* acc, int nk, double* part) {
+  __shared__ double sh[kKBlock / 64][L * KH];
   const int lane = threadIdx.x & 63, wid = threadIdx.x / 64;
 #pragma unroll
   for (int u = 0; u < KH; ++u) {
+    if (u >= nk) break;  // no lane holds vector u or beyond (the same for every lane)
     double t = acc[u];
+    if constexpr (L == 1) {
+      t = wave_sum(t);
+    } else {
 #pragma unroll
-    for (int off = 32; off >= 2; off >>= 1) t += __shfl_down(t, off, 64);
-    if (lane < 2) sh[wid][lane * KH + u] = t;
+      for (int off = 32; off >= L; off >>= 1) t += __shfl_down(t, off, 64);
+    }
+    if (lane < L) sh[wid][lane * KH + u] = t;
   }
   __syncthreads();
   for (int k = threadIdx.x; k < nk; k += kKBlock) {
@@ -130,6 +107,90 @@ __global__ void __launch_bounds__(kKBlock) k_cgs_axpy_dots(int64_t n, int nk,
     for (int ww = 0; ww < kKBlock / 64; ++ww) t += sh[ww][k];
     part[int64_t(k) * gridDim.x + blockIdx.x] = t;
   }
+}
+
+// pass 1: part = V^T w  (nk vectors).  L lanes per pair of entries, lane q
+// holding basis vectors q*KH .. q*KH+KH-1 (fewer registers per lane for the
+// larger bases).
+template <int KMAX, int L>
+__global__ void __launch_bounds__(kKBlock) k_cgs_dots(int64_t n, int nk, const double* __restrict__ V,
+                                                      const double* __restrict__ w,
+                                                      double* __restrict__ part) {
+  constexpr int KH = (KMAX + L - 1) / L;
+  // entries in pairs (n is even and every basis vector 16-byte aligned)
+  const int q = threadIdx.x % L, k0 = q * KH;
+  double acc[KH];
+#pragma unroll
+  for (int u = 0; u < KH; ++u) acc[u] = 0.0;
+  const int64_t n2 = n / 2;
+  const double2* V2 = reinterpret_cast<const double2*>(V);
+  const double2* w2 = reinterpret_cast<const double2*>(w);
+  for (int64_t p = (int64_t(blockIdx.x) * kKBlock + threadIdx.x) / L; p < n2;
+       p += int64_t(gridDim.x) * (kKBlock / L)) {
+    const double2 wi = w2[p];
+#pragma unroll
+    for (int u = 0; u < KH; ++u)
+      if (k0 + u < nk) {
+        const double2 v = V2[(k0 + u) * n2 + p];
+        acc[u] += v.x * wi.x;
+        acc[u] += v.y * wi.y;
+      }
+  }
+  reduce_store_lanes<KH, L>(acc, nk, part);
+}
+
+// pass 2: w -= V h; part = V^T w.  L lanes per pair of entries, lane q
+// holding basis vectors q*KH .. q*KH+KH-1: each lane sums h_k v_k over its
+// part, the L lanes add their sums (a butterfly: the same value in every
+// lane), the first lane writes w, and each lane accumulates its part of the
+// dot products.
+template <int KMAX, int L>
+__global__ void __launch_bounds__(kKBlock) k_cgs_axpy_dots(int64_t n, int nk,
+                                                           const double* __restrict__ V,
+                                                           const double* __restrict__ h,
+                                                           double* __restrict__ w,
+                                                           double* __restrict__ part) {
+  constexpr int KH = (KMAX + L - 1) / L;
+  __shared__ double hs[L * KH];
+  for (int k = threadIdx.x; k < L * KH; k += kKBlock) hs[k] = k < nk ? h[k] : 0.0;
+  __syncthreads();
+  const int q = threadIdx.x % L, k0 = q * KH;
+  double acc[KH];
+#pragma unroll
+  for (int u = 0; u < KH; ++u) acc[u] = 0.0;
+  const int64_t n2 = n / 2;  // entries in pairs, as in k_cgs_dots
+  const double2* V2 = reinterpret_cast<const double2*>(V);
+  double2* w2 = reinterpret_cast<double2*>(w);
+  for (int64_t p = (int64_t(blockIdx.x) * kKBlock + threadIdx.x) / L; p < n2;
+       p += int64_t(gridDim.x) * (kKBlock / L)) {
+    double2 v[KH];
+    double sx = 0.0, sy = 0.0;
+#pragma unroll
+    for (int u = 0; u < KH; ++u) {
+      v[u] = make_double2(0.0, 0.0);
+      if (k0 + u < nk) {
+        v[u] = V2[int64_t(k0 + u) * n2 + p];
+        sx += hs[k0 + u] * v[u].x;
+        sy += hs[k0 + u] * v[u].y;
+      }
+    }
+#pragma unroll
+    for (int off = 1; off < L; off <<= 1) {
+      sx += __shfl_xor(sx, off, 64);
+      sy += __shfl_xor(sy, off, 64);
+    }
+    double2 wi = w2[p];
+    wi.x -= sx;
+    wi.y -= sy;
+    if (q == 0) w2[p] = wi;
+#pragma unroll
+    for (int u = 0; u < KH; ++u)
+      if (k0 + u < nk) {
+        acc[u] += v[u].x * wi.x;
+        acc[u] += v[u].y * wi.y;
+      }
+  }
+  reduce_store_lanes<KH, L>(acc, nk, part);
 }
 
 // pass 3: w -= V h; part = ||w||^2
@@ -369,7 +430,6 @@ void Fgmres::begin(const tpf_jacobian* J_, tpf_precond* M_, const double* b_, do
                 "bound workspace is for %lld unknowns and restart %d", (long long)n, m);
   else
     alloc(2 * int64_t(J->nb), o.restart, s);
-  G = krylov_grid(n);
   total = 0;
   est = 1.0;
   spec_j = -1;
@@ -421,20 +481,26 @@ void Fgmres::launch_step() {
   {
     TimedScope ts("cgs2", s);
     DISPATCH_K(nk, KM, {
-      k_cgs_dots<KM><<<G, kKBlock, 0, s>>>(n, nk, V.p, wv, part.p);
+      // lanes per entry: pass 1 holds KM / L1 sums per lane, pass 2 also
+      // KM / L2 basis values
+      constexpr int L1 = KM <= 16 ? 1 : 2, L2 = KM <= 12 ? 1 : (KM <= 20 ? 2 : 4);
+      const int g1 = resident_grid(k_cgs_dots<KM, L1>, n),
+                g2 = resident_grid(k_cgs_axpy_dots<KM, L2>, n);
+      g_norm = resident_grid(k_cgs_axpy_norm<KM>, n);
+      k_cgs_dots<KM, L1><<<g1, kKBlock, 0, s>>>(n, nk, V.p, wv, part.p);
       TPF_CHECK_LAUNCH();
-      k_reduce_parts<<<nk, kRedBlock, 0, s>>>(G, part.p, h1.p);
+      k_reduce_parts<<<nk, kRedBlock, 0, s>>>(g1, part.p, h1.p);
       TPF_CHECK_LAUNCH();
-      k_cgs_axpy_dots<KM><<<G, kKBlock, 0, s>>>(n, nk, V.p, h1.p, wv, part.p);
+      k_cgs_axpy_dots<KM, L2><<<g2, kKBlock, 0, s>>>(n, nk, V.p, h1.p, wv, part.p);
       TPF_CHECK_LAUNCH();
-      k_reduce_parts<<<nk, kRedBlock, 0, s>>>(G, part.p, h2.p);
+      k_reduce_parts<<<nk, kRedBlock, 0, s>>>(g2, part.p, h2.p);
       TPF_CHECK_LAUNCH();
-      k_cgs_axpy_norm<KM><<<G, kKBlock, 0, s>>>(n, nk, V.p, h2.p, wv, part.p);
+      k_cgs_axpy_norm<KM><<<g_norm, kKBlock, 0, s>>>(n, nk, V.p, h2.p, wv, part.p);
       TPF_CHECK_LAUNCH();
     });
   }
   GState* gs = reinterpret_cast<GState*>(st_dev.p);
-  k_givens<<<1, kRedBlock, 0, s>>>(j, m, h1.p, h2.p, part.p, G, H.p, cs.p, sn.p, g.p, gs);
+  k_givens<<<1, kRedBlock, 0, s>>>(j, m, h1.p, h2.p, part.p, g_norm, H.p, cs.p, sn.p, g.p, gs);
   TPF_CHECK_LAUNCH();
   k_scale<<<vec_grid(n), 256, 0, s>>>(n, wv, gs, wv);
   TPF_CHECK_LAUNCH();

@@ -37,7 +37,7 @@ struct Fgmres {
   tpf_solve_opts o{};
   hipStream_t s = nullptr;
   Phase phase = kIdle;
-  int G = 1;
+  int g_norm = 1;  // work-groups of the last step's norm pass (its partial sums)
   int j = 0, k = 0, total = 0;
   bool breakdown = false;
   double beta0 = 0.0, est = 1.0, relres = 0.0, ms = 0.0;
