@@ -1613,6 +1613,46 @@ __global__ void __launch_bounds__(256) k_vc_prolong(int n, const int* __restrict
   if (lane == 0) y[row] = dinv[row] * b[row] + sum;
 }
 
+// y = D^{-1} b + P x_c with P in ELL form (W slots per row, column-major):
+// the entries are summed in row order, as the CSR kernel does with one lane
+template <class T, int W>
+__global__ void __launch_bounds__(256) k_vc_prolong_ell(int n, const int* __restrict__ eci,
+                                                        const T* __restrict__ ev,
+                                                        const T* __restrict__ dinv,
+                                                        const T* __restrict__ b,
+                                                        const T* __restrict__ xc,
+                                                        T* __restrict__ y) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  int c[W];
+  T a[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    c[k] = eci[int64_t(k) * n + row];
+    a[k] = ev[int64_t(k) * n + row];
+  }
+  T sum = T(0);
+#pragma unroll
+  for (int k = 0; k < W; ++k)
+    if (c[k] >= 0) sum += a[k] * xc[c[k]];
+  y[row] = dinv[row] * b[row] + sum;
+}
+
+// CSR rows of at most W entries -> ELL slots (see Level::pe_ci)
+template <class T>
+__global__ void __launch_bounds__(256) k_csr_to_ell(int n, int W, const int* __restrict__ rp,
+                                                    const int* __restrict__ ci,
+                                                    const double* __restrict__ v,
+                                                    int* __restrict__ eci, T* __restrict__ ev) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  const int e0 = rp[row], len = rp[row + 1] - e0;
+  for (int k = 0; k < W; ++k) {
+    eci[int64_t(k) * n + row] = k < len ? ci[e0 + k] : -1;
+    ev[int64_t(k) * n + row] = k < len ? T(v[e0 + k]) : T(0);
+  }
+}
+
 // x = y + D^{-1} (b - A y): post-smoothing
 template <class T, int LPR>
 __global__ void __launch_bounds__(256) k_vc_post(int n, const int* __restrict__ rp,
@@ -1967,6 +2007,17 @@ template <class T> T* work(Buf<double>& d, Buf<float>& f);
 template <> double* work<double>(Buf<double>& d, Buf<float>&) { return d.p; }
 template <> float* work<float>(Buf<double>&, Buf<float>& f) { return f.p; }
 template <class T> const T* dinv_of(const Level& L);
+template <class T> const T* ell_vals(const Level& L);
+template <> const double* ell_vals<double>(const Level& L) { return L.pe_v.p; }
+template <> const float* ell_vals<float>(const Level& L) { return L.pe_v32.p; }
+constexpr int kEllMaxW = 4;  // widest ELL form of P
+#define DISPATCH_ELL(w, W, ...)                         \
+  switch (w) {                                          \
+    case 1: { constexpr int W = 1; __VA_ARGS__ } break; \
+    case 2: { constexpr int W = 2; __VA_ARGS__ } break; \
+    case 3: { constexpr int W = 3; __VA_ARGS__ } break; \
+    default: { constexpr int W = 4; __VA_ARGS__ } break; \
+  }
 template <> const double* dinv_of<double>(const Level& L) { return L.dinv.p; }
 template <> const float* dinv_of<float>(const Level& L) { return L.dinv32.p; }
 
@@ -2339,6 +2390,30 @@ void Hierarchy::finish_levels(hipStream_t st) {
         if (o.smoother == 1) L.dd32.ensure(n, st);
       }
     }
+    // ELL form of P for the fused cycle's prolongation: truncation to
+    // trunc_pmax entries bounds every row of P
+    const int W = o.trunc_pmax;
+    if (o.fused_cycle() && L.P.rp.p && W >= 1 && W <= kEllMaxW) {
+      L.pe_ci.ensure(size_t(W) * n, st);
+      if (o.fp32) {
+        L.pe_v.release();
+        L.pe_v32.ensure(size_t(W) * n, st);
+        k_csr_to_ell<float><<<grid_for(n, 256), 256, 0, st>>>(n, W, L.P.rp.p, L.P.ci.p, L.P.v.p,
+                                                              L.pe_ci.p, L.pe_v32.p);
+      } else {
+        L.pe_v32.release();
+        L.pe_v.ensure(size_t(W) * n, st);
+        k_csr_to_ell<double><<<grid_for(n, 256), 256, 0, st>>>(n, W, L.P.rp.p, L.P.ci.p, L.P.v.p,
+                                                               L.pe_ci.p, L.pe_v.p);
+      }
+      TPF_CHECK_LAUNCH();
+      L.pe_w = W;
+    } else {
+      L.pe_w = 0;
+      L.pe_ci.release();
+      L.pe_v.release();
+      L.pe_v32.release();
+    }
   }
   // level-0 diagonal layout
   dia0.ok = false;
@@ -2666,7 +2741,8 @@ size_t Hierarchy::bytes() const {
          L.R.bytes() + L.T.bytes() + L.Av32.bytes() + L.Pv32.bytes() + L.Rv32.bytes() +
          L.dinv32.bytes() + L.r.bytes() + L.y.bytes() + L.b.bytes() + L.x.bytes() + L.xa.bytes() +
          L.xb.bytes() + L.dd.bytes() + L.xa32.bytes() + L.xb32.bytes() + L.dd32.bytes() +
-         L.r32.bytes() + L.y32.bytes() + L.b32.bytes() + L.x32.bytes();
+         L.r32.bytes() + L.y32.bytes() + L.b32.bytes() + L.x32.bytes() + L.pe_ci.bytes() +
+         L.pe_v.bytes() + L.pe_v32.bytes();
   }
   return b;
 }
@@ -2792,12 +2868,20 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st) {
   csr_spmv<T>(ref_with<T>(L.R, vals_of<T>(L.R, L.Rv32)), r, bc, st, L.t_restrict.c_str());
   vcycle_level<T>(l + 1, bc, xc, st);
   {
-    int plpr = lanes_per_row(n, L.P.nnz);
     TimedScope ts(L.t_prolong.c_str(), st);
-    DISPATCH_LPR(plpr, LL, {
-      k_vc_prolong<T, LL><<<grid_for(int64_t(n) * LL, 256), 256, 0, st>>>(
-          n, L.P.rp.p, L.P.ci.p, vals_of<T>(L.P, L.Pv32), dinv, b, xc, y);
-    });
+    const T* pev = ell_vals<T>(L);
+    if (L.pe_w > 0 && pev) {
+      DISPATCH_ELL(L.pe_w, WW, {
+        k_vc_prolong_ell<T, WW><<<grid_for(n, 256), 256, 0, st>>>(n, L.pe_ci.p, pev, dinv, b,
+                                                                   xc, y);
+      });
+    } else {
+      int plpr = lanes_per_row(n, L.P.nnz);
+      DISPATCH_LPR(plpr, LL, {
+        k_vc_prolong<T, LL><<<grid_for(int64_t(n) * LL, 256), 256, 0, st>>>(
+            n, L.P.rp.p, L.P.ci.p, vals_of<T>(L.P, L.Pv32), dinv, b, xc, y);
+      });
+    }
     TPF_CHECK_LAUNCH();
   }
   {

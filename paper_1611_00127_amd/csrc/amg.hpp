@@ -42,6 +42,13 @@ struct Level {
                         // R*A (level 0) or A*P while the product runs (empty after)
   // FP32 copies of the values (patterns shared)
   Buf<float> Av32, Pv32, Rv32, dinv32;
+  // P in ELL form for the cycle's prolongation when truncation bounds its
+  // rows: slot k of row i at k * n + i (column -1 and value 0 past the
+  // row's end), pe_w slots; FP64 or FP32 values as the cycle runs
+  int pe_w = 0;
+  Buf<int> pe_ci;
+  Buf<double> pe_v;
+  Buf<float> pe_v32;
   // generic smoothing sweeps: two iterates and the Chebyshev direction, and
   // the Chebyshev interval [cheb_lo, cheb_hi] of D^{-1} A
   Buf<double> xa, xb, dd;
