@@ -106,12 +106,25 @@ def lanes_per_row(n, nnz):
     return lanes
 
 
-def vcycle_kernel_bytes(st, h, l, w):
+GUESS_ROWS = 65536  # CSR levels from this size (above the coarsest) cycle from g = D^-1 b
+
+
+def guess_level(st, h, l):
+    """Whether level l's pre-smoothing gathers a formed g = D^-1 b: the
+    diagonal-layout level 0, and CSR levels of at least GUESS_ROWS rows above
+    the coarsest (whose g the restriction into them forms)."""
+    if l == int(st.levels[h]) - 1:
+        return False
+    return bool(l == 0 and int(st.l0_diagonals[h])) or int(st.rows[h][l]) >= GUESS_ROWS
+
+
+def vcycle_kernel_bytes(st, h, l, w, ell_w=0):
     """Algorithmic bytes per launch of each V-cycle kernel of level l of
     hierarchy h (value width w): every array the kernel must touch, counted
     once -- the operator (diagonal layout: K * n values; CSR: values, int32
-    columns, row pointers) and each dense vector.  Keys are the kernel-timer
-    names without the [hierarchy,level] suffix."""
+    columns, row pointers; P in ELL form: ell_w slots per row) and each dense
+    vector.  Keys are the kernel-timer names without the [hierarchy,level]
+    suffix."""
     n, nnz = int(st.rows[h][l]), int(st.nnz[h][l])
     last = l == int(st.levels[h]) - 1
     K = int(st.l0_diagonals[h]) if l == 0 else 0
@@ -122,30 +135,40 @@ def vcycle_kernel_bytes(st, h, l, w):
         return {"vcycle_coarse": mat + 3 * w * n}           # two sweeps: dinv, b, x
     nc, pnnz = int(st.rows[h][l + 1]), int(st.p_nnz[h][l])
     tr = (w + 4) * pnnz
-    return {
-        "vcycle_jacobi_guess": 3 * w * n,                  # dinv, b -> g
-        "vcycle_pre_residual": mat + 3 * w * n,            # g (or dinv), b -> r
-        "vcycle_restrict": tr + 4 * (nc + 1) + w * n + w * nc,
-        "vcycle_prolong": tr + 4 * (n + 1) + w * nc + 3 * w * n,  # x_c, dinv, b -> y
-        "vcycle_post_smooth": mat + 4 * w * n,             # dinv, b, y -> x
-    }
+    out = {}
+    if l == 0 and guess_level(st, h, 0):
+        out["vcycle_jacobi_guess"] = 3 * w * n                 # dinv, b -> g
+    out["vcycle_pre_residual"] = mat + 3 * w * n               # g (or dinv), b -> r
+    # R, r -> b_c (and dinv_c -> g_c when the coarse level cycles from g_c)
+    out["vcycle_restrict"] = (tr + 4 * (nc + 1) + w * n + w * nc
+                              + (2 * w * nc if guess_level(st, h, l + 1) else 0))
+    ptr = (w + 4) * ell_w * n if ell_w else tr + 4 * (n + 1)
+    out["vcycle_prolong"] = ptr + w * nc + 3 * w * n           # x_c, dinv, b -> y
+    out["vcycle_post_smooth"] = mat + 4 * w * n                # dinv, b, y -> x
+    return out
 
 
-def kernel_symbol(st, h, l, timer, guess):
+def kernel_symbol(st, h, l, timer, ell_w=0):
     """Name of the HIP kernel behind a V-cycle timer (as rocprofv3 lists it)."""
     n, nnz = int(st.rows[h][l]), int(st.nnz[h][l])
     K = int(st.l0_diagonals[h]) if l == 0 else 0
     if timer == "vcycle_pre_residual":
         if K:
             return f"k_dia_pre{'2' if n % 2 == 0 else ''}<double, {K}>"
-        return f"k_vc_pre{'_g' if guess else ''}<double, {lanes_per_row(n, nnz)}>"
+        g = "_g" if guess_level(st, h, l) else ""
+        return f"k_vc_pre{g}<double, {lanes_per_row(n, nnz)}>"
     if timer == "vcycle_post_smooth":
         if K:
             return f"k_dia_post{'2' if n % 2 == 0 else ''}<double, {K}>"
         return f"k_vc_post<double, {lanes_per_row(n, nnz)}>"
     if timer == "vcycle_prolong":
+        if ell_w:
+            return f"k_vc_prolong_ell<double, {ell_w}>"
         return f"k_vc_prolong<double, {lanes_per_row(n, int(st.p_nnz[h][l]))}>"
     if timer == "vcycle_restrict":
+        if guess_level(st, h, l + 1):
+            nc = int(st.rows[h][l + 1])
+            return f"k_vc_restrict_guess<double, {lanes_per_row(nc, int(st.p_nnz[h][l]))}>"
         return "k_csr_spmv"
     if timer == "vcycle_jacobi_guess":
         return "k_jacobi_guess<double>"
@@ -156,7 +179,7 @@ HIER_TAGS = {"bf": ["Ass", "Schur"]}
 HIER_NAMES = {"Ass": "A_ss", "Schur": "S~"}
 
 
-def vcycle_table(tpf, st, tags, w=8):
+def vcycle_table(tpf, st, tags, w=8, ell_w=0):
     """Per level of each hierarchy: rows, nnz, P entries, and for every
     V-cycle kernel its launches, mean time (HIP events) and algorithmic
     GB/s; per hierarchy the V-cycle's bytes and kernel time."""
@@ -164,8 +187,7 @@ def vcycle_table(tpf, st, tags, w=8):
     for h, tag in enumerate(tags):
         levels, tot_b, tot_ms, cycles = [], 0, 0.0, 0
         for l in range(int(st.levels[h])):
-            kb = vcycle_kernel_bytes(st, h, l, w)
-            guess = tpf.tpf_kernel_stats(f"vcycle_jacobi_guess[{tag},l{l}]")[0] > 0
+            kb = vcycle_kernel_bytes(st, h, l, w, ell_w)
             row = {"level": l, "rows": int(st.rows[h][l]), "nnz": int(st.nnz[h][l]),
                    "p_nnz": int(st.p_nnz[h][l]), "kernels": {}}
             lb, lms = 0, 0.0
@@ -179,7 +201,7 @@ def vcycle_table(tpf, st, tags, w=8):
                 row["kernels"][timer] = {"launches": cnt, "avg_us": round(avg_us, 2),
                                          "bytes": b, "gbs": round(b / (avg_us * 1e3), 1)}
                 kernels.append(dict(hier=tag, level=l, timer=timer, launches=cnt, total_ms=ms,
-                                    bytes=b, symbol=kernel_symbol(st, h, l, timer, guess)))
+                                    bytes=b, symbol=kernel_symbol(st, h, l, timer, ell_w)))
                 lb += b * cnt
                 lms += ms
             row["share_of_cycle_bytes"] = lb
@@ -936,7 +958,9 @@ def main():
     log("[bench] FP64 instrumented step")
     Mi, _, _ = run_form(torch, tpf, driver, g, tpf.TPF_FP64, 1, 0, True)
     st64 = Mi.stats()
-    vc64, kern64 = vcycle_table(tpf, st64, HIER_TAGS["bf"], 8)
+    # the cycle's prolongation reads P in ELL form when truncation bounds its rows
+    ell_w = int(Mi.opts.trunc_pmax) if 1 <= int(Mi.opts.trunc_pmax) <= 4 else 0
+    vc64, kern64 = vcycle_table(tpf, st64, HIER_TAGS["bf"], 8, ell_w)
     ktab = kernel_table(tpf, ["cgs2", "bcsr_spmv", "bf_rhs", "assemble", "precond_apply"])
     walls = []
     for h in range(st64.n_hier):
@@ -952,7 +976,7 @@ def main():
     err = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
     log("[bench] FP32 instrumented step")
     Mi, _, _ = run_form(torch, tpf, driver, g, tpf.TPF_FP32, 1, 0, True)
-    vc32, _ = vcycle_table(tpf, Mi.stats(), HIER_TAGS["bf"], 4)
+    vc32, _ = vcycle_table(tpf, Mi.stats(), HIER_TAGS["bf"], 4, ell_w)
     Mi.close()
     tpf.tpf_kernel_stats_reset()
     M64.close()

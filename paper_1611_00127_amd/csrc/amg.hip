@@ -1653,6 +1653,25 @@ __global__ void __launch_bounds__(256) k_csr_to_ell(int n, int W, const int* __r
   }
 }
 
+// restriction b_c = R r that also forms the next level's Jacobi guess
+// g_c = D_c^{-1} b_c (a large coarse level's pre-smoothing gathers g_c)
+template <class T, int LPR>
+__global__ void __launch_bounds__(256) k_vc_restrict_guess(int nc, const int* __restrict__ rrp,
+                                                           const int* __restrict__ rci,
+                                                           const T* __restrict__ rv,
+                                                           const T* __restrict__ r,
+                                                           const T* __restrict__ dinv_c,
+                                                           T* __restrict__ bc, T* __restrict__ gc) {
+  int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int row = int(gid / LPR), lane = int(gid % LPR);
+  if (row >= nc) return;
+  T sum = row_dot<T, LPR>(row, lane, rrp, rci, rv, [&](int j) { return r[j]; });
+  if (lane == 0) {
+    bc[row] = sum;
+    gc[row] = dinv_c[row] * sum;
+  }
+}
+
 // x = y + D^{-1} (b - A y): post-smoothing
 template <class T, int LPR>
 __global__ void __launch_bounds__(256) k_vc_post(int n, const int* __restrict__ rp,
@@ -2751,7 +2770,7 @@ size_t Hierarchy::bytes() const {
 constexpr int kGuessRows = 65536;  // CSR levels from this size form D^{-1} b first
 
 template <class T>
-void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st) {
+void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st, bool g_ready) {
   Level& L = *lv[l];
   int n = L.A.nrows;
   const T* Av = vals_of<T>(L.A, L.Av32);
@@ -2831,7 +2850,7 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st) {
   // large levels form g = D^{-1} b once (in y, until the prolongation
   // overwrites it), so the residual gathers one vector
   const bool guess = dia || n >= kGuessRows;
-  if (guess) {
+  if (guess && !g_ready) {
     TimedScope ts(L.t_guess.c_str(), st);
     k_jacobi_guess<T><<<grid_for(n, 256), 256, 0, st>>>(n, dinv, b, y);
     TPF_CHECK_LAUNCH();
@@ -2865,8 +2884,21 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st) {
     }
     TPF_CHECK_LAUNCH();
   }
-  csr_spmv<T>(ref_with<T>(L.R, vals_of<T>(L.R, L.Rv32)), r, bc, st, L.t_restrict.c_str());
-  vcycle_level<T>(l + 1, bc, xc, st);
+  // a large coarse level above the coarsest forms its guess in the restriction
+  const bool c_guess = l + 2 < int(lv.size()) && C.A.nrows >= kGuessRows;
+  if (c_guess) {
+    TimedScope ts(L.t_restrict.c_str(), st);
+    const int rlpr = lanes_per_row(C.A.nrows, L.R.nnz);
+    DISPATCH_LPR(rlpr, LL, {
+      k_vc_restrict_guess<T, LL><<<grid_for(int64_t(C.A.nrows) * LL, 256), 256, 0, st>>>(
+          C.A.nrows, L.R.rp.p, L.R.ci.p, vals_of<T>(L.R, L.Rv32), r, dinv_of<T>(C), bc,
+          work<T>(C.y, C.y32));
+    });
+    TPF_CHECK_LAUNCH();
+  } else {
+    csr_spmv<T>(ref_with<T>(L.R, vals_of<T>(L.R, L.Rv32)), r, bc, st, L.t_restrict.c_str());
+  }
+  vcycle_level<T>(l + 1, bc, xc, st, c_guess);
   {
     TimedScope ts(L.t_prolong.c_str(), st);
     const T* pev = ell_vals<T>(L);

@@ -123,8 +123,9 @@ struct Hierarchy {
   template <class T>
   const T* smooth(Level& L, const T* b, const T* x0, T* out, T* spare0, T* spare1, int steps,
                   bool post, hipStream_t st);
+  // g_ready: the caller's restriction already put D^{-1} b in the level's y
   template <class T>
-  void vcycle_level(int l, const T* b, T* x, hipStream_t st);
+  void vcycle_level(int l, const T* b, T* x, hipStream_t st, bool g_ready = false);
 };
 
 }  // namespace tpf
