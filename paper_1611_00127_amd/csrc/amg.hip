@@ -2959,14 +2959,16 @@ Hierarchy::~Hierarchy() {
 // One V-cycle: its kernels (about five per level) are launched as one graph
 // when graphs are enabled and kernel timing is off, eagerly otherwise.
 template <class T>
-void Hierarchy::vcycle(const T* b, T* x, hipStream_t st) {
+void Hierarchy::vcycle(const T* b, T* x, hipStream_t st, bool g_ready) {
   TPF_REQUIRE(!lv.empty(), TPF_ERR_STATE, "AMG hierarchy not set up");
   if (std::is_same<T, float>::value) TPF_REQUIRE(o.fp32, TPF_ERR_STATE, "FP32 copies not built");
+  TPF_REQUIRE(!g_ready || guess_buffer<T>(), TPF_ERR_STATE,
+              "this hierarchy's cycle does not start from a formed guess");
   if (timing_enabled() || !graphs_enabled()) {
-    vcycle_level<T>(0, b, x, st);
+    vcycle_level<T>(0, b, x, st, g_ready);
     return;
   }
-  VGraph& g = vg[std::is_same<T, float>::value ? 1 : 0];
+  VGraph& g = vg[(std::is_same<T, float>::value ? 1 : 0) + (g_ready ? 2 : 0)];
   if (!g.exec || g.b != b || g.x != x) {
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
     g = VGraph{};
@@ -2974,7 +2976,7 @@ void Hierarchy::vcycle(const T* b, T* x, hipStream_t st) {
     TPF_HIP(hipStreamBeginCapture(cap_s, hipStreamCaptureModeThreadLocal));
     hipGraph_t gr = nullptr;
     try {
-      vcycle_level<T>(0, b, x, cap_s);
+      vcycle_level<T>(0, b, x, cap_s, g_ready);
     } catch (...) {
       (void)hipStreamEndCapture(cap_s, &gr);
       if (gr) (void)hipGraphDestroy(gr);
@@ -2994,7 +2996,25 @@ template const double* Hierarchy::smooth<double>(Level&, const double*, const do
                                                   double*, double*, int, bool, hipStream_t);
 template const float* Hierarchy::smooth<float>(Level&, const float*, const float*, float*, float*,
                                                float*, int, bool, hipStream_t);
-template void Hierarchy::vcycle<double>(const double*, double*, hipStream_t);
-template void Hierarchy::vcycle<float>(const float*, float*, hipStream_t);
+template void Hierarchy::vcycle<double>(const double*, double*, hipStream_t, bool);
+template void Hierarchy::vcycle<float>(const float*, float*, hipStream_t, bool);
+
+// Level 0's guess buffer when the fused cycle starts from g = D^-1 b there
+// (diagonal layout or a large CSR level above the coarsest), else null.
+template <class T>
+T* Hierarchy::guess_buffer() {
+  if (lv.size() < 2 || !o.fused_cycle()) return nullptr;
+  Level& L = *lv[0];
+  if (!(dia0.ok || L.A.nrows >= kGuessRows)) return nullptr;
+  return work<T>(L.y, L.y32);
+}
+template <class T>
+const T* Hierarchy::level0_dinv() const {
+  return dinv_of<T>(*lv[0]);
+}
+template double* Hierarchy::guess_buffer<double>();
+template float* Hierarchy::guess_buffer<float>();
+template const double* Hierarchy::level0_dinv<double>() const;
+template const float* Hierarchy::level0_dinv<float>() const;
 
 }  // namespace tpf

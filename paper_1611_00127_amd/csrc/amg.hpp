@@ -100,7 +100,7 @@ struct Hierarchy {
     void* x = nullptr;
     hipGraphExec_t exec = nullptr;
   };
-  VGraph vg[2];
+  VGraph vg[4];  // FP64 / FP32, each with and without a formed level-0 guess
   hipStream_t cap_s = nullptr;
   void drop_graphs();
   ~Hierarchy();
@@ -110,8 +110,15 @@ struct Hierarchy {
   // Numeric refresh after lv[0]->A values changed (same pattern): keeps C/F, P, R.
   void refresh(hipStream_t st);
   Csr<double>& A0() { return lv[0]->A; }
+  // g_ready: the caller formed g = D^-1 b of level 0 in guess_buffer()
   template <class T>
-  void vcycle(const T* b, T* x, hipStream_t st);
+  void vcycle(const T* b, T* x, hipStream_t st, bool g_ready = false);
+  // level 0's buffer for g = D^-1 b when the cycle starts from it (else null),
+  // and level 0's inverse l1 diagonal
+  template <class T>
+  T* guess_buffer();
+  template <class T>
+  const T* level0_dinv() const;
   size_t bytes() const;
   int levels() const { return int(lv.size()); }
 

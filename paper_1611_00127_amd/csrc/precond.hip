@@ -244,18 +244,38 @@ __global__ void k_add_comp(int n, double* __restrict__ z, int comp, const T* __r
   if (i < n) z[2 * i + comp] += double(v[i]);
 }
 
-// t_i = r_{p,i} - sum_j (A_ps)_ij s_j   (Algorithm 3, step 3)
+// out = component comp of r, and g = dinv .* out (the first level's Jacobi
+// guess of the V-cycle that takes out as its right-hand side)
+template <class T>
+__global__ void k_gather_guess(int n, const double* __restrict__ r, int comp,
+                               const T* __restrict__ dinv, T* __restrict__ out,
+                               T* __restrict__ g) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const T v = T(r[2 * i + comp]);
+    out[i] = v;
+    g[i] = dinv[i] * v;
+  }
+}
+
+// t_i = r_{p,i} - sum_j (A_ps)_ij s_j   (Algorithm 3, step 3); with g, also
+// g_i = dinv_i t_i (the S~ cycle's first Jacobi guess)
 template <class T, int LPR>
 __global__ void __launch_bounds__(256) k_bf_rhs(int n, const int* __restrict__ rp,
                                                 const int* __restrict__ ci,
                                                 const double* __restrict__ aps,
                                                 const double* __restrict__ r,
-                                                const T* __restrict__ s, T* __restrict__ t) {
+                                                const T* __restrict__ s, T* __restrict__ t,
+                                                const T* __restrict__ dinv, T* __restrict__ g) {
   int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   int row = int(gid / LPR), lane = int(gid % LPR);
   if (row >= n) return;
   double sum = row_dot<double, LPR>(row, lane, rp, ci, aps, [&](int j) { return double(s[j]); });
-  if (lane == 0) t[row] = T(r[2 * row] - sum);
+  if (lane == 0) {
+    const T tv = T(r[2 * row] - sum);
+    t[row] = tv;
+    if (g) g[row] = dinv[row] * tv;
+  }
 }
 
 // ---------------------------------------------------------------- block ILU(0)
@@ -926,19 +946,27 @@ void apply_t(tpf_precond* M, const double* r, double* z, hipStream_t s) {
       break;
     }
     case TPF_PREC_BF: {
-      k_gather<T><<<g, 256, 0, s>>>(N, r, 1, v1);
+      // each cycle's first Jacobi guess is formed with its right-hand side
+      // when the cycle starts from one
+      T* g0 = M->H[0]->guess_buffer<T>();
+      T* g1 = M->H[1]->guess_buffer<T>();
+      if (g0)
+        k_gather_guess<T><<<g, 256, 0, s>>>(N, r, 1, M->H[0]->level0_dinv<T>(), v1, g0);
+      else
+        k_gather<T><<<g, 256, 0, s>>>(N, r, 1, v1);
       TPF_CHECK_LAUNCH();
-      M->H[0]->vcycle<T>(v1, v2, s);  // s = V(A_ss; R_s r)
+      M->H[0]->vcycle<T>(v1, v2, s, g0 != nullptr);  // s = V(A_ss; R_s r)
       int lpr = lanes_per_row(N, M->J->nnzb);
       {
         TimedScope ts("bf_rhs", s);
+        const T* d1 = g1 ? M->H[1]->level0_dinv<T>() : nullptr;
         DISPATCH_LPR(lpr, L, {
-          k_bf_rhs<T, L><<<grid_for(int64_t(N) * L, 256), 256, 0, s>>>(N, M->brp.p, M->bci.p,
-                                                                       M->aps_v.p, r, v2, v3);
+          k_bf_rhs<T, L><<<grid_for(int64_t(N) * L, 256), 256, 0, s>>>(
+              N, M->brp.p, M->bci.p, M->aps_v.p, r, v2, v3, d1, g1);
         });
         TPF_CHECK_LAUNCH();
       }
-      M->H[1]->vcycle<T>(v3, v4, s);  // p = V(S~; t)
+      M->H[1]->vcycle<T>(v3, v4, s, g1 != nullptr);  // p = V(S~; t)
       k_scatter2<T><<<g, 256, 0, s>>>(N, v4, v2, z);
       TPF_CHECK_LAUNCH();
       break;
