@@ -857,7 +857,8 @@ def study_amg_variants(torch, tpf, driver, inputs, args):
     b = g.R
     x = torch.empty_like(b)
     variants = [
-        ("default: PMIS, ext+i (S~) / direct (A_ss), l1-Jacobi", {}),
+        ("default: PMIS, ext+i (S~) / direct (A_ss), l1-Jacobi, P rows truncated to 3", {}),
+        ("default without interpolation truncation", dict(trunc_pmax=0)),
         ("PMIS, classical, l1-Jacobi", dict(interp=tpf.TPF_INTERP_CLASSICAL)),
         ("PMIS, default interpolation, multicolour GS", dict(smoother=tpf.TPF_SMOOTH_MC_GS)),
         ("CLJP, default interpolation, l1-Jacobi", dict(coarsening=tpf.TPF_COARSEN_CLJP)),
