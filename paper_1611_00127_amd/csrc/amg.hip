@@ -540,6 +540,19 @@ __global__ void __launch_bounds__(256) k_truncate(int n, const Off* __restrict__
   const int m = len ? len[i] : int(int64_t(start[i + 1]) - lo);
   const int* rci = ci + lo;
   const double* rv = v + lo;
+  if (factor <= 0.0 && (pmax <= 0 || m <= pmax)) {
+    // nothing to drop: every scale factor would be x / x = 1
+    if (!out_rp) {
+      cnt[i] = m;
+    } else {
+      const int q = out_rp[i];
+      for (int a = 0; a < m; ++a) {
+        out_ci[q + a] = rci[a];
+        out_v[q + a] = rv[a];
+      }
+    }
+    return;
+  }
   double largest = 0.0;
   for (int a = 0; a < m; ++a) largest = fmax(largest, trunc_key(rv[a]));
   const double thr = factor * largest;
