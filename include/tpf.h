@@ -379,12 +379,18 @@ int tpf_solve_noalloc(const tpf_jacobian* J, tpf_precond* M, const double* b, do
  *         setup stream), whether in use or cached for reuse, at allocated
  *         sizes.
  *       - A request's estimate is its FGMRES workspace plus, for a new
- *         sequence, the resident and setup bytes measured on built sequences
- *         of that size (scaled up from smaller ones), or, for a built
- *         sequence, the extra bytes its last setup drew.
+ *         sequence, 1.25 times the largest resident and setup bytes measured
+ *         on built sequences of that size (scaled up from smaller ones), or,
+ *         for a built sequence, 1.25 times the extra bytes its last setup
+ *         drew.  The budget holds as long as no setup draws more than its
+ *         estimate: it is not a hard limit on the allocator.
+ *       - Requests of resident sequences are considered before those that
+ *         need a build; a request that does not fit yet is passed over (with
+ *         the later requests of its sequence), so a sequence's requests start
+ *         in submission order while other sequences go ahead.
  *       - To make room the server first returns idle streams' cached blocks
- *         to the allocator, then evicts idle sequences, least recently used
- *         first.
+ *         to the allocator, then evicts idle sequences, those with no queued
+ *         request first, least recently used first.
  *     A request that cannot fit alone fails with TPF_ERR_OVER_BUDGET.
  *   - A result does not depend on what else is in flight: every kernel is
  *     deterministic and a sequence's requests run in order.

@@ -25,6 +25,7 @@
 #include <string>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "krylov.hpp"
@@ -194,21 +195,23 @@ struct tpf_server {
   }
 
   // Frees device memory until in_use() + need fits the budget: idle caches
-  // first, then idle sequences (least recently used first).  Returns whether
-  // it fits.
-  bool make_room(size_t need, uint64_t keep) {
+  // first, then idle sequences, those with no queued request before the
+  // others, least recently used first.  Returns whether it fits.
+  bool make_room(size_t need, uint64_t keep,
+                 const std::unordered_map<uint64_t, int>& queued = {}) {
     if (in_use() + need <= o.hbm_budget_bytes) return true;
     trim_caches();
     while (in_use() + need > o.hbm_budget_bytes) {
-      if (!evict_one(keep)) return false;
+      if (!evict_one(keep, queued)) return false;
       trim_caches();  // the evicted sequence's blocks went to the setup stream's cache
     }
     return true;
   }
 
   // Resident bytes and setup bytes a new sequence of `cells` cells is
-  // expected to need.  Realizations of one grid size differ, so each size
-  // keeps the largest footprint built so far, with a 10% margin:
+  // expected to need.  Realizations of one grid size differ (their
+  // hierarchies follow their permeability fields), so each size keeps the
+  // largest footprint built so far, with a 25% margin:
   //   (a) that of the smallest built size at least as large;
   //   (b) else that of the largest smaller size, scaled by 1.25 times the
   //       cell ratio (deeper hierarchies hold a little more per cell);
@@ -227,12 +230,12 @@ struct tpf_server {
     double f = 0.0, er = 0.0, ex = 0.0;
     auto up = worst.lower_bound(cells);
     if (up != worst.end()) {
-      f = 1.1;
+      f = 1.25;
       er = up->second.first;
       ex = up->second.second;
     } else if (!worst.empty()) {
       auto lo = std::prev(worst.end());
-      f = 1.1 * 1.25 * double(cells) / double(lo->first);
+      f = 1.25 * 1.25 * double(cells) / double(lo->first);
       er = lo->second.first;
       ex = lo->second.second;
     }
@@ -243,12 +246,18 @@ struct tpf_server {
     return {size_t(br), size_t(bx)};
   }
 
-  bool evict_one(uint64_t keep) {
+  bool evict_one(uint64_t keep, const std::unordered_map<uint64_t, int>& queued = {}) {
+    auto waits = [&](const Resident* r) {
+      auto q = queued.find(r->seq);
+      return q != queued.end() && q->second > 0;
+    };
     Resident* victim = nullptr;
     for (auto& kv : res) {
       Resident* r = kv.second.get();
       if (r->busy || r->seq == keep) continue;
-      if (!victim || r->last_use < victim->last_use) victim = r;
+      if (!victim || std::make_pair(waits(r), r->last_use) <
+                         std::make_pair(waits(victim), victim->last_use))
+        victim = r;
     }
     if (!victim) return false;
     res.erase(victim->seq);
@@ -406,57 +415,85 @@ struct tpf_server {
     sl.state.store(kFree, std::memory_order_release);
   }
 
+  // Admission, in two passes over the queue in submission order: the first
+  // takes requests whose sequence is resident (a workspace and a refresh),
+  // the second those that need a build.  A request that does not fit now is
+  // passed over, and so are the later requests of its sequence, so a
+  // sequence's requests still start in submission order while other
+  // sequences go ahead.
   void admit() {
-    for (auto it = queue.begin(); it != queue.end();) {
-      Slot* sl = free_slot();
-      if (!sl) return;
-      const Pending& p = *it;
-      if (sequence_busy(p.rq.sequence)) {
-        ++it;  // waits for the sequence's running request; later sequences may pass
-        continue;
-      }
-      int64_t cells = 0;
-      auto rit = res.find(p.rq.sequence);
-      if (rit != res.end()) {
-        cells = rit->second->cells;
-        if (rit->second->prob != p.rq.problem) {
-          Pending bad = p;
-          it = queue.erase(it);
-          set_last_error(TPF_ERR_INVALID_ARG, "request names another problem than its sequence");
-          finish_request(bad, TPF_ERR_INVALID_ARG, 0, NAN, NAN, 0.0, 0.0, 0);
+    std::unordered_map<uint64_t, int> queued;  // queued requests per sequence
+    for (auto& q : queue) ++queued[q.rq.sequence];
+    std::unordered_set<uint64_t> passed;  // sequences passed over in this call
+    for (int pass = 0; pass < 2; ++pass) {
+      for (auto it = queue.begin(); it != queue.end();) {
+        Slot* sl = free_slot();
+        if (!sl) return;
+        const Pending& p = *it;
+        const uint64_t seq = p.rq.sequence;
+        auto rit = res.find(seq);
+        const bool resident = rit != res.end();
+        if (resident != (pass == 0)) {  // the other pass takes it
+          ++it;
           continue;
         }
-      } else {
-        check_rc(tpf_problem_cells(p.rq.problem, &cells));
-      }
-      const size_t ws = krylov_bytes(cells, o.solve.restart);
-      size_t need = ws;
-      if (rit == res.end()) {
-        auto e = estimate(cells);
-        need += e.first + e.second;
-      } else {
-        need += rit->second->setup_extra.load();
-      }
-      if (need > o.hbm_budget_bytes) {
-        Pending bad = p;
+        if (passed.count(seq) || sequence_busy(seq)) {
+          passed.insert(seq);  // its later requests wait behind this one
+          ++it;
+          continue;
+        }
+        int64_t cells = 0;
+        if (resident) {
+          cells = rit->second->cells;
+          if (rit->second->prob != p.rq.problem) {
+            Pending bad = p;
+            it = queue.erase(it);
+            --queued[seq];
+            set_last_error(TPF_ERR_INVALID_ARG, "request names another problem than its sequence");
+            finish_request(bad, TPF_ERR_INVALID_ARG, 0, NAN, NAN, 0.0, 0.0, 0);
+            continue;
+          }
+        } else {
+          check_rc(tpf_problem_cells(p.rq.problem, &cells));
+        }
+        const size_t ws = krylov_bytes(cells, o.solve.restart);
+        size_t need = ws;
+        if (!resident) {
+          auto e = estimate(cells);
+          need += e.first + e.second;
+        } else {
+          // a refresh draws about what the sequence's last setup drew beyond its
+          // own bytes; 25% more covers a state whose products come out larger
+          need += rit->second->setup_extra.load() + rit->second->setup_extra.load() / 4;
+        }
+        if (need > o.hbm_budget_bytes) {
+          Pending bad = p;
+          it = queue.erase(it);
+          --queued[seq];
+          set_last_error(TPF_ERR_OVER_BUDGET, "request does not fit in the HBM budget");
+          finish_request(bad, TPF_ERR_OVER_BUDGET, 0, NAN, NAN, 0.0, 0.0, 0, need);
+          continue;
+        }
+        if (!make_room(need, seq, queued)) {
+          bool any_active = false;
+          for (auto& x : slots) any_active |= x->busy();
+          if (any_active) {  // waits for active solves to retire; later ones may fit
+            passed.insert(seq);
+            ++it;
+            continue;
+          }
+          Pending bad = p;  // cannot fit even with the device to itself
+          it = queue.erase(it);
+          --queued[seq];
+          set_last_error(TPF_ERR_OVER_BUDGET, "request does not fit in the HBM budget");
+          finish_request(bad, TPF_ERR_OVER_BUDGET, 0, NAN, NAN, 0.0, 0.0, 0, need);
+          continue;
+        }
+        Pending go = p;
         it = queue.erase(it);
-        set_last_error(TPF_ERR_OVER_BUDGET, "request does not fit in the HBM budget");
-        finish_request(bad, TPF_ERR_OVER_BUDGET, 0, NAN, NAN, 0.0, 0.0, 0, need);
-        continue;
+        --queued[seq];
+        start(*sl, go, cells, need);
       }
-      if (!make_room(need, p.rq.sequence)) {
-        bool any_active = false;
-        for (auto& x : slots) any_active |= x->busy();
-        if (any_active) return;  // waits for active solves to retire
-        Pending bad = p;         // cannot fit even with the device to itself
-        it = queue.erase(it);
-        set_last_error(TPF_ERR_OVER_BUDGET, "request does not fit in the HBM budget");
-        finish_request(bad, TPF_ERR_OVER_BUDGET, 0, NAN, NAN, 0.0, 0.0, 0, need);
-        continue;
-      }
-      Pending go = p;
-      it = queue.erase(it);
-      start(*sl, go, cells, need);
     }
   }
 

@@ -7,7 +7,8 @@
 * A served update solves the oracle's Newton system J(u) x = -F(u) to the
   requested 1e-8 relative residual.
 * Admission keeps the bytes in use within the HBM budget, evicting idle
-  sequences; a request that cannot fit fails with TPF_ERR_OVER_BUDGET.
+  sequences, and starts requests of resident sequences before builds; a
+  request that cannot fit fails with TPF_ERR_OVER_BUDGET.
 * Cancellation of queued and active requests.
 """
 import sys
@@ -157,7 +158,8 @@ def test_budget_admission_and_eviction(env):
     # device memory actually drawn from torch's allocator while serving, not
     # the server's own bookkeeping, stays within the budget
     assert drawn <= budget
-    assert st.evictions >= 3
+    # the budget holds one or two resident sequences: builds evict
+    assert st.evictions >= 1
     assert len(res) == 3  # keys repeat: the second round overwrote the first
     for key, (x, r) in res.items():
         assert r.status == tpf.TPF_CONVERGED, key
