@@ -636,7 +636,7 @@ def serve_stream(torch, tpf, driver, inputs, args):
         arr = np.zeros(n) if rate is None else np.cumsum(rng.exponential(1.0 / rate, n))
         xs = [torch.empty(2 * seqs[r][0].N, dtype=torch.float64, device="cuda") for r, _ in order]
         torch.cuda.synchronize()
-        lat, its, rel, errs = [None] * n, [0] * n, [0.0] * n, [0.0] * n
+        lat, its, rel, errs, ref = [None] * n, [0] * n, [0.0] * n, [0.0] * n, [0] * n
         tick, i, done = {}, 0, 0
         t0 = time.perf_counter()
         while done < n:
@@ -660,6 +660,7 @@ def serve_stream(torch, tpf, driver, inputs, args):
                 lat[j] = 1e3 * (time.perf_counter() - t0 - arr[j])
                 its[j] = res.iterations
                 rel[j] = res.relres_true
+                ref[j] = res.refreshed
                 assert res.status == tpf.TPF_CONVERGED, (order[j], res.status)
                 done += 1
         total = time.perf_counter() - t0
@@ -670,9 +671,16 @@ def serve_stream(torch, tpf, driver, inputs, args):
         for j, (r, k) in enumerate(order):
             # served x is the Newton step; the baseline solved J x = F (its negative)
             errs[j] = float(torch.linalg.norm(xs[j] + xb[(r, k)]) / torch.linalg.norm(xb[(r, k)]))
+        by_edge = {}
+        for e in sorted({seqs[r][0].nx for r, _ in order}):
+            le = [lat[j] for j, (r, _) in enumerate(order) if seqs[r][0].nx == e]
+            by_edge[str(e)] = {"requests": len(le), "p50_ms": round(pct(le, 50), 2),
+                               "p99_ms": round(pct(le, 99), 2)}
+        refreshed = sum(1 for j in range(n) if ref[j])
         return {"arrival_rate_per_s": None if rate is None else round(rate, 2),
                 "solves_per_s": round(n / total, 2), "wall_s": round(total, 3),
                 "p50_latency_ms": round(pct(lat, 50), 2), "p99_latency_ms": round(pct(lat, 99), 2),
+                "latency_by_edge": by_edge, "refreshed_requests": refreshed,
                 "mean_iterations": round(float(np.mean(its)), 2),
                 "max_relres_true": float(np.max(rel)),
                 "max_rel_diff_vs_fp64": float(np.max(errs)),
