@@ -148,6 +148,9 @@ def vcycle_kernel_bytes(st, h, l, w, ell_w=0):
     return out
 
 
+STREAM_LANES = 8  # large CSR levels with rows of up to this many lanes take the streamed kernels
+
+
 def kernel_symbol(st, h, l, timer, ell_w=0):
     """Name of the HIP kernel behind a V-cycle timer (as rocprofv3 lists it)."""
     n, nnz = int(st.rows[h][l]), int(st.nnz[h][l])
@@ -155,12 +158,15 @@ def kernel_symbol(st, h, l, timer, ell_w=0):
     if timer == "vcycle_pre_residual":
         if K:
             return f"k_dia_pre{'2' if n % 2 == 0 else ''}<double, {K}>"
-        g = "_g" if guess_level(st, h, l) else ""
-        return f"k_vc_pre{g}<double, {lanes_per_row(n, nnz)}>"
+        lpr = lanes_per_row(n, nnz)
+        g = ("_gs" if lpr <= STREAM_LANES else "_g") if guess_level(st, h, l) else ""
+        return f"k_vc_pre{g}<double, {lpr}>"
     if timer == "vcycle_post_smooth":
         if K:
             return f"k_dia_post{'2' if n % 2 == 0 else ''}<double, {K}>"
-        return f"k_vc_post<double, {lanes_per_row(n, nnz)}>"
+        lpr = lanes_per_row(n, nnz)
+        s = "s" if guess_level(st, h, l) and lpr <= STREAM_LANES else ""
+        return f"k_vc_post{s}<double, {lpr}>"
     if timer == "vcycle_prolong":
         if ell_w:
             return f"k_vc_prolong_ell<double, {ell_w}>"
@@ -263,8 +269,12 @@ def kernel_digest(names):
 
 
 # source functions whose text identifies each V-cycle kernel family's build
+STREAM_SOURCES = ["amg.hip:xcd_contiguous_block", "amg.hip:wave_lds_sync",
+                  "amg.hip:stream_window", "amg.hip:stream_rows_dot", "amg.hip:stream_first_row"]
 KERNEL_SOURCES = {
     "k_vc_post": ["amg.hip:k_vc_post", "linalg_dev.hpp:row_dot"],
+    "k_vc_posts": STREAM_SOURCES + ["amg.hip:k_vc_posts"],
+    "k_vc_pre_gs": STREAM_SOURCES + ["amg.hip:k_vc_pre_gs"],
     "k_vc_pre_g": ["amg.hip:k_vc_pre_g", "linalg_dev.hpp:row_dot"],
     "k_vc_pre": ["amg.hip:k_vc_pre", "linalg_dev.hpp:row_dot"],
     "k_dia_pre2": ["amg.hip:clampi", "amg.hip:xcd_contiguous_block", "amg.hip:k_dia_pre2"],

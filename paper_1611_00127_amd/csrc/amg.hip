@@ -2019,6 +2019,137 @@ __global__ void __launch_bounds__(256) k_dia_post(int n, DiagOffs o, const T* __
   x[i] = y[i] + dinv[i] * (b[i] - sum);
 }
 
+// ---------------------------------------------------------------- streamed CSR rows
+// Smoother kernels of the large CSR levels (the Galerkin operators below
+// level 0) whose rows take at most 8 lanes (64 entries on average).  A
+// wavefront takes R = 64 / LPR consecutive rows, as the row kernels' grid
+// assigns them, but reads their entries as one contiguous range: every load
+// instruction covers 64 consecutive values and column indices, where the row
+// kernels' lane groups read R separate pieces of 8 LPR bytes (wider groups
+// already read whole 128-byte lines and keep the row kernels).  The products
+// a_ij g_j go to the wavefront's LDS window of kStreamWin entries; each row's
+// LPR lanes then sum their row's part of the window and reduce across the
+// group.  A range longer than the window takes several windows.  Work-groups
+// are numbered XCD-contiguously, so the columns a stretch of rows gathers
+// stay in one XCD's L2.  The pre-smoother reads the level's values and
+// indices with ordinary loads, leaving what the memory-side cache keeps of
+// them for the post-smoother, which reads them non-temporally as their last
+// use in the cycle.
+constexpr int kStreamWin = 512;
+constexpr int kStreamLanes = 8;  // rows of up to this many lanes are streamed
+
+// LDS written by some lanes of a wavefront and then read by others: the LDS
+// operations of one wavefront complete in order, so ordering the compiler's
+// view at wavefront scope is enough
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Products of window entries ws + u * 64 + lane (u < U) into win; positions
+// clamped to the window's last entry we - 1, so all loads are valid and
+// issued before the first wait.  NT: values and indices read non-temporally.
+template <class T, int U, bool NT, class G>
+__device__ inline void stream_window(int ws, int we, int lane, const int* __restrict__ ci,
+                                     const T* __restrict__ v, G g, T* __restrict__ win) {
+  int c[U];
+  T a[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int f = min(ws + u * kWave + lane, we - 1);
+    if constexpr (NT) {
+      c[u] = __builtin_nontemporal_load(ci + f);
+      a[u] = __builtin_nontemporal_load(v + f);
+    } else {
+      c[u] = ci[f];
+      a[u] = v[f];
+    }
+  }
+  T x[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) x[u] = g(c[u]);
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (ws + u * kWave + lane < we) win[u * kWave + lane] = a[u] * x[u];
+}
+
+// Row r0 + lane / LPR's dot with the gathered values g(col), valid in the
+// group's first lane (0 for a row at or past n).  win: the wavefront's
+// kStreamWin-entry LDS window.  A window of m entries issues the fewest
+// 64-entry loads of 2, 4, 6 or 8 that cover it.
+template <class T, int LPR, bool NT, class G>
+__device__ inline T stream_rows_dot(int n, int r0, int lane, const int* __restrict__ rp,
+                                    const int* __restrict__ ci, const T* __restrict__ v, G g,
+                                    T* __restrict__ win) {
+  constexpr int R = kWave / LPR;
+  static_assert(kStreamWin == 8 * kWave, "windows of up to eight loads");
+  const int s = rp[r0], t = rp[min(r0 + R, n)];
+  const int row = r0 + lane / LPR, q = lane % LPR;
+  const int lo = rp[min(row, n)], hi = rp[min(row + 1, n)];
+  T sum = T(0);
+  for (int ws = s; ws < t; ws += kStreamWin) {
+    const int we = min(ws + kStreamWin, t), m = we - ws;
+    if (m > 6 * kWave)
+      stream_window<T, 8, NT>(ws, we, lane, ci, v, g, win);
+    else if (m > 4 * kWave)
+      stream_window<T, 6, NT>(ws, we, lane, ci, v, g, win);
+    else if (m > 2 * kWave)
+      stream_window<T, 4, NT>(ws, we, lane, ci, v, g, win);
+    else
+      stream_window<T, 2, NT>(ws, we, lane, ci, v, g, win);
+    wave_lds_sync();
+    const int je = min(hi, we);
+    for (int j = max(lo, ws) + q; j < je; j += LPR) sum += win[j - ws];
+    wave_lds_sync();  // the window is rewritten next
+  }
+#pragma unroll
+  for (int off = LPR / 2; off > 0; off >>= 1) sum += __shfl_down(sum, off, LPR);
+  return sum;
+}
+
+// first row of this wavefront's R rows (wavefront-uniform)
+template <int LPR>
+__device__ inline int stream_first_row() {
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  return (xcd_contiguous_block() * (256 / kWave) + w) * (kWave / LPR);
+}
+
+// r = b - A g with g = D^{-1} b formed beforehand; grid as k_vc_pre_g's
+template <class T, int LPR>
+__global__ void __launch_bounds__(256) k_vc_pre_gs(int n, const int* __restrict__ rp,
+                                                   const int* __restrict__ ci,
+                                                   const T* __restrict__ v,
+                                                   const T* __restrict__ g,
+                                                   const T* __restrict__ b, T* __restrict__ r) {
+  __shared__ T win[256 / kWave][kStreamWin];
+  const int r0 = stream_first_row<LPR>();
+  if (r0 >= n) return;  // the whole wavefront
+  const int lane = threadIdx.x % kWave;
+  const T sum = stream_rows_dot<T, LPR, false>(
+      n, r0, lane, rp, ci, v, [&](int j) { return g[j]; }, win[threadIdx.x / kWave]);
+  const int row = r0 + lane / LPR;
+  if (lane % LPR == 0 && row < n) r[row] = b[row] - sum;
+}
+
+// x = y + D^{-1} (b - A y); grid as k_vc_post's
+template <class T, int LPR>
+__global__ void __launch_bounds__(256) k_vc_posts(int n, const int* __restrict__ rp,
+                                                  const int* __restrict__ ci,
+                                                  const T* __restrict__ v,
+                                                  const T* __restrict__ dinv,
+                                                  const T* __restrict__ b,
+                                                  const T* __restrict__ y, T* __restrict__ x) {
+  __shared__ T win[256 / kWave][kStreamWin];
+  const int r0 = stream_first_row<LPR>();
+  if (r0 >= n) return;
+  const int lane = threadIdx.x % kWave;
+  const T sum = stream_rows_dot<T, LPR, true>(
+      n, r0, lane, rp, ci, v, [&](int j) { return y[j]; }, win[threadIdx.x / kWave]);
+  const int row = r0 + lane / LPR;
+  if (lane % LPR == 0 && row < n) x[row] = y[row] + dinv[row] * (b[row] - sum);
+}
+
 #define DISPATCH_DIAG(K, KK, ...)                               \
   switch (K) {                                                  \
     case 5: { constexpr int KK = 5; __VA_ARGS__ } break;        \
@@ -2863,6 +2994,7 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st, bool g_rea
   // large levels form g = D^{-1} b once (in y, until the prolongation
   // overwrites it), so the residual gathers one vector
   const bool guess = dia || n >= kGuessRows;
+  const bool stream = guess && !dia && lpr <= kStreamLanes;
   if (guess && !g_ready) {
     TimedScope ts(L.t_guess.c_str(), st);
     k_jacobi_guess<T><<<grid_for(n, 256), 256, 0, st>>>(n, dinv, b, y);
@@ -2886,6 +3018,10 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st, bool g_rea
           k_dia_pre<T, KK><<<grid_for(n, 256), 256, 0, st>>>(n, doff, dv, y, b, r);
         });
       }
+    } else if (stream) {
+      DISPATCH_LPR(lpr, LL, {
+        k_vc_pre_gs<T, LL><<<blocks, 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, Av, y, b, r);
+      });
     } else if (guess) {
       DISPATCH_LPR(lpr, LL, {
         k_vc_pre_g<T, LL><<<blocks, 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, Av, y, b, r);
@@ -2948,6 +3084,10 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st, bool g_rea
           k_dia_post<T, KK><<<grid_for(n, 256), 256, 0, st>>>(n, doff, dv, dinv, b, y, x);
         });
       }
+    } else if (stream) {
+      DISPATCH_LPR(lpr, LL, {
+        k_vc_posts<T, LL><<<blocks, 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, Av, dinv, b, y, x);
+      });
     } else {
       DISPATCH_LPR(lpr, LL, {
         k_vc_post<T, LL><<<blocks, 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, Av, dinv, b, y, x);

@@ -52,12 +52,18 @@ def test_vcycle_kernel_bytes_by_hand():
     assert not bench.guess_level(st, 0, 2) and not bench.guess_level(st, 0, 3)
     # the kernels rocprofv3 names for the timers
     assert bench.kernel_symbol(st, 0, 0, "vcycle_pre_residual") == "k_dia_pre2<double, 25>"
-    assert bench.kernel_symbol(st, 0, 1, "vcycle_post_smooth") == "k_vc_post<double, 8>"
-    assert bench.kernel_symbol(st, 0, 1, "vcycle_pre_residual") == "k_vc_pre_g<double, 8>"
+    assert bench.kernel_symbol(st, 0, 1, "vcycle_post_smooth") == "k_vc_posts<double, 8>"
+    assert bench.kernel_symbol(st, 0, 1, "vcycle_pre_residual") == "k_vc_pre_gs<double, 8>"
+    assert bench.kernel_symbol(st, 0, 2, "vcycle_post_smooth") == "k_vc_post<double, 8>"
     assert bench.kernel_symbol(st, 0, 2, "vcycle_pre_residual") == "k_vc_pre<double, 8>"
     assert bench.kernel_symbol(st, 0, 0, "vcycle_restrict").startswith("k_vc_restrict_guess")
     assert bench.kernel_symbol(st, 0, 1, "vcycle_restrict") == "k_csr_spmv"
     assert bench.kernel_symbol(st, 0, 0, "vcycle_prolong", 3) == "k_vc_prolong_ell<double, 3>"
+    # a large level of long rows (80 entries: 16 lanes) keeps the row kernels
+    st16 = _stats([1_000_000, 100_000, 100], [25_000_000, 8_000_000, 5_000],
+                  [2_400_000, 300_000, 0], 25)
+    assert bench.kernel_symbol(st16, 0, 1, "vcycle_pre_residual") == "k_vc_pre_g<double, 16>"
+    assert bench.kernel_symbol(st16, 0, 1, "vcycle_post_smooth") == "k_vc_post<double, 16>"
     # launch sizes: two rows per thread in the diagonal kernels, lanes per row in CSR ones
     assert bench.launch_threads(st, 0, 0, "vcycle_post_smooth") == 500_224  # 500,000 rounded up
     assert bench.launch_threads(st, 0, 1, "vcycle_post_smooth") == 400_000 * 8
@@ -76,7 +82,7 @@ def test_reduce_traffic_scales_counters_by_the_copy(tmp_path, monkeypatch):
     what the same counters read for the 512 MiB copy, and the kernel-trace
     durations of the same dispatches."""
     d = tmp_path
-    sym, grid = "k_vc_post<double, 8>", 3_070_720
+    sym, grid = "k_vc_posts<double, 8>", 3_070_720
     name = f"void tpf::(anonymous namespace)::{sym}(int, int const*)"
     copy = "__amd_rocclr_copyBuffer"
     _write_csv(str(d / "pmc_fetch" / "fetch_counter_collection.csv"),
@@ -93,7 +99,7 @@ def test_reduce_traffic_scales_counters_by_the_copy(tmp_path, monkeypatch):
                 [name, 2048, 1, 1, 0, 10]])
     alg = 266_497_228
     (d / "traffic_spec.json").write_text(json.dumps(
-        {"vcycle_post_smooth[Schur,l1]": [sym, grid, alg, bench.KERNEL_SOURCES["k_vc_post"]]}))
+        {"vcycle_post_smooth[Schur,l1]": [sym, grid, alg, bench.KERNEL_SOURCES["k_vc_posts"]]}))
     out = tmp_path / "traffic.json"
     monkeypatch.setattr(bench, "TRAFFIC_JSON", str(out))
     rec = bench.reduce_traffic(str(d))
@@ -104,10 +110,10 @@ def test_reduce_traffic_scales_counters_by_the_copy(tmp_path, monkeypatch):
     assert k["hbm_bytes_per_dispatch"] == int(hbm)
     assert k["traffic_over_algorithmic"] == pytest.approx(hbm / alg, abs=1e-4)
     assert k["trace_avg_us"] == pytest.approx(75.5)
-    assert k["source_sha256"] == bench.kernel_digest(bench.KERNEL_SOURCES["k_vc_post"])
+    assert k["source_sha256"] == bench.kernel_digest(bench.KERNEL_SOURCES["k_vc_posts"])
     # the stored file feeds the bench line while the kernel's source is unchanged
     assert bench.stored_traffic("vcycle_post_smooth[Schur,l1]", sym) == round(hbm)
-    assert bench.stored_traffic("vcycle_post_smooth[Schur,l1]", "k_vc_post<double, 16>") is None
+    assert bench.stored_traffic("vcycle_post_smooth[Schur,l1]", "k_vc_posts<double, 16>") is None
 
 
 def test_more_than_one_gpu_is_refused():

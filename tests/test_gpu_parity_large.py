@@ -7,7 +7,8 @@ five-spot, CFL 10):
   level of both BF hierarchies against the oracle (S~ level 1 has more than
   65,536 rows, so its V-cycle takes the D^{-1}b-first CSR smoother, and the
   levels above 4,096 rows take the multi-launch PMIS rounds), one V-cycle in
-  FP64 and FP32, the full BF solve (iterations within +-1), and CPR1, whose
+  FP64 and FP32 (the streamed CSR smoothers, some wavefronts over several
+  LDS windows), the full BF solve (iterations within +-1), and CPR1, whose
   block ILU(0) runs the per-front kernels (fronts of up to 2,496 cells).
 * 128x128x64 (1,048,576 cells), the benchmark grid itself: residual,
   Jacobian, SpMV, S~, and the strength graph and C/F splitting of S~'s first
@@ -106,6 +107,18 @@ def test_large_setup_levels(gpu, newton1):
     M.close(); g.close()
 
 
+def _longest_wavefront_range(A):
+    """Entries of the longest run of rows one wavefront of the streamed CSR
+    smoothers takes: 64 / LPR rows, LPR the lanes per row the library picks
+    from the mean row length (the smallest power of two with 8 LPR >= mean)."""
+    n = A.shape[0]
+    lpr = 1
+    while lpr < 64 and 8 * lpr < A.nnz / n:
+        lpr *= 2
+    r0 = np.arange(0, n, 64 // lpr)
+    return int(np.max(A.indptr[np.minimum(r0 + 64 // lpr, n)] - A.indptr[r0]))
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_large_vcycle(gpu, newton1, precision):
     """One V-cycle of each BF hierarchy against the oracle's cycle on the
@@ -118,8 +131,12 @@ def test_large_vcycle(gpu, newton1, precision):
     M32 = driver.GpuPrecond("bf", tpf.TPF_FP32) if precision else None
     if M32 is not None:
         M32.setup(g)
+    longest = 0
     for hier in (1, 0):
         H = _gpu_hierarchy_as_oracle(tpf, M, hier)
+        for L in H.levels[1:]:
+            if L.n >= 65536:
+                longest = max(longest, _longest_wavefront_range(L.A))
         n = H.levels[0].n
         b = inputs.random_vector(n, 40 + hier)
         bd = torch.tensor(b, device="cuda")
@@ -130,6 +147,8 @@ def test_large_vcycle(gpu, newton1, precision):
         rel = float(np.max(np.abs(x - xo)) / np.max(np.abs(xo)))
         say(f"  hierarchy {hier}: {len(H.levels)} levels, max rel diff {rel:.2e}")
         assert rel <= (1e-4 if precision else 1e-12), rel
+    # some wavefront of the streamed smoothers takes more than one 512-entry window
+    assert longest > 512, longest
     if M32 is not None:
         M32.close()
     M.close(); g.close()
