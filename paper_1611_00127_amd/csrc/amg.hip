@@ -2026,10 +2026,13 @@ __global__ void __launch_bounds__(256) k_dia_post(int n, DiagOffs o, const T* __
 // assigns them, but reads their entries as one contiguous range: every load
 // instruction covers 64 consecutive values and column indices, where the row
 // kernels' lane groups read R separate pieces of 8 LPR bytes (wider groups
-// already read whole 128-byte lines and keep the row kernels).  The products
-// a_ij g_j go to the wavefront's LDS window of kStreamWin entries; each row's
-// LPR lanes then sum their row's part of the window and reduce across the
-// group.  A range longer than the window takes several windows.  Work-groups
+// already read whole 128-byte lines and keep the row kernels).  The range is
+// cut into windows of kStreamWin entries, and setup sorts each window's
+// entries by column (Level::sw_ci): a load instruction's 64 gathers of g_j
+// then touch a few cache lines of g instead of one or two per row segment.
+// The products a_ij g_j go back to their CSR positions in the wavefront's LDS
+// window; each row's LPR lanes then sum their row's part of the window, in
+// CSR order, and reduce across the group.  Work-groups
 // are numbered XCD-contiguously, so the columns a stretch of rows gathers
 // stay in one XCD's L2.  The pre-smoother reads the level's values and
 // indices with ordinary loads, leaving what the memory-side cache keeps of
@@ -2037,6 +2040,11 @@ __global__ void __launch_bounds__(256) k_dia_post(int n, DiagOffs o, const T* __
 // use in the cycle.
 constexpr int kStreamWin = 512;
 constexpr int kStreamLanes = 8;  // rows of up to this many lanes are streamed
+constexpr int kGuessRows = 65536;  // CSR levels from this size form D^{-1} b first
+// window-sorted entries: column in the low 23 bits, window position above
+constexpr int kSwColBits = 23;
+constexpr int kSwColMask = (1 << kSwColBits) - 1;
+static_assert(kStreamWin <= (1 << (32 - kSwColBits)), "window positions fit above the column");
 
 // LDS written by some lanes of a wavefront and then read by others: the LDS
 // operations of one wavefront complete in order, so ordering the compiler's
@@ -2047,11 +2055,12 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Products of window entries ws + u * 64 + lane (u < U) into win; positions
-// clamped to the window's last entry we - 1, so all loads are valid and
-// issued before the first wait.  NT: values and indices read non-temporally.
+// Products of the window's sorted entries ws + u * 64 + lane (u < U) into
+// win at their CSR positions; positions clamped to the window's last entry
+// we - 1, so all loads are valid and issued before the first wait.  NT:
+// values and indices read non-temporally.
 template <class T, int U, bool NT, class G>
-__device__ inline void stream_window(int ws, int we, int lane, const int* __restrict__ ci,
+__device__ inline void stream_window(int ws, int we, int lane, const int* __restrict__ sci,
                                      const T* __restrict__ v, G g, T* __restrict__ win) {
   int c[U];
   T a[U];
@@ -2059,19 +2068,19 @@ __device__ inline void stream_window(int ws, int we, int lane, const int* __rest
   for (int u = 0; u < U; ++u) {
     const int f = min(ws + u * kWave + lane, we - 1);
     if constexpr (NT) {
-      c[u] = __builtin_nontemporal_load(ci + f);
+      c[u] = __builtin_nontemporal_load(sci + f);
       a[u] = __builtin_nontemporal_load(v + f);
     } else {
-      c[u] = ci[f];
+      c[u] = sci[f];
       a[u] = v[f];
     }
   }
   T x[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) x[u] = g(c[u]);
+  for (int u = 0; u < U; ++u) x[u] = g(c[u] & kSwColMask);
 #pragma unroll
   for (int u = 0; u < U; ++u)
-    if (ws + u * kWave + lane < we) win[u * kWave + lane] = a[u] * x[u];
+    if (ws + u * kWave + lane < we) win[unsigned(c[u]) >> kSwColBits] = a[u] * x[u];
 }
 
 // Row r0 + lane / LPR's dot with the gathered values g(col), valid in the
@@ -2106,6 +2115,53 @@ __device__ inline T stream_rows_dot(int n, int r0, int lane, const int* __restri
 #pragma unroll
   for (int off = LPR / 2; off > 0; off >>= 1) sum += __shfl_down(sum, off, LPR);
   return sum;
+}
+
+// Setup of Level::sw_ci / sw_v / sw_v32: one wavefront per R = 64 / LPR
+// rows (the smoothers' assignment, without the XCD renumbering); each
+// window's keys column << 9 | position are sorted in LDS by a bitonic
+// network, then the packed entries and the values they point at are written.
+// Columns must be below 2^23.
+template <int LPR>
+__global__ void __launch_bounds__(256) k_window_sort(int n, const int* __restrict__ rp,
+                                                     const int* __restrict__ ci,
+                                                     const double* __restrict__ v,
+                                                     int* __restrict__ sci,
+                                                     double* __restrict__ sv,
+                                                     float* __restrict__ sv32) {
+  __shared__ unsigned keys[256 / kWave][kStreamWin];
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int r0 = (blockIdx.x * (256 / kWave) + w) * (kWave / LPR);
+  if (r0 >= n) return;  // the whole wavefront
+  const int s = rp[r0], t = rp[min(r0 + kWave / LPR, n)];
+  unsigned* K = keys[w];
+  for (int ws = s; ws < t; ws += kStreamWin) {
+    const int m = min(kStreamWin, t - ws);
+    for (int k = lane; k < kStreamWin; k += kWave)
+      K[k] = k < m ? (unsigned(ci[ws + k]) << (32 - kSwColBits)) | unsigned(k) : 0xffffffffu;
+    wave_lds_sync();
+    for (int size = 2; size <= kStreamWin; size <<= 1) {
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int q = lane; q < kStreamWin / 2; q += kWave) {
+          const int i = 2 * q - (q & (stride - 1)), j = i + stride;
+          const unsigned a = K[i], b = K[j];
+          if ((a > b) == ((i & size) == 0)) {
+            K[i] = b;
+            K[j] = a;
+          }
+        }
+        wave_lds_sync();
+      }
+    }
+    for (int k = lane; k < m; k += kWave) {
+      const unsigned key = K[k];
+      const int p = int(key & (kStreamWin - 1)), c = int(key >> (32 - kSwColBits));
+      sci[ws + k] = int(unsigned(c) | (unsigned(p) << kSwColBits));
+      if (sv) sv[ws + k] = v[ws + p];
+      if (sv32) sv32[ws + k] = float(v[ws + p]);
+    }
+    wave_lds_sync();  // the keys are rewritten next
+  }
 }
 
 // first row of this wavefront's R rows (wavefront-uniform)
@@ -2173,6 +2229,9 @@ template <class T> const T* dinv_of(const Level& L);
 template <class T> const T* ell_vals(const Level& L);
 template <> const double* ell_vals<double>(const Level& L) { return L.pe_v.p; }
 template <> const float* ell_vals<float>(const Level& L) { return L.pe_v32.p; }
+template <class T> const T* sw_vals(const Level& L);
+template <> const double* sw_vals<double>(const Level& L) { return L.sw_v.p; }
+template <> const float* sw_vals<float>(const Level& L) { return L.sw_v32.p; }
 constexpr int kEllMaxW = 4;  // widest ELL form of P
 #define DISPATCH_ELL(w, W, ...)                         \
   switch (w) {                                          \
@@ -2611,7 +2670,43 @@ void Hierarchy::finish_levels(hipStream_t st) {
       dia0.v.release();  // only the FP32 copy is cycled
     }
   }
+  // window-sorted copies for the streamed smoothers
+  for (size_t l = 0; l + 1 < lv.size(); ++l) {
+    Level& L = *lv[l];
+    const int n = L.A.nrows;
+    const int lpr = lanes_per_row(n, L.A.nnz);
+    if (streamed_level(int(l), n, lpr)) {
+      L.sw_ci.ensure(L.A.nnz, st);
+      if (o.fp32) {
+        L.sw_v.release();
+        L.sw_v32.ensure(L.A.nnz, st);
+      } else {
+        L.sw_v32.release();
+        L.sw_v.ensure(L.A.nnz, st);
+      }
+      const int64_t waves = (n + kWave / lpr - 1) / (kWave / lpr);
+      DISPATCH_LPR(lpr, LL, {
+        k_window_sort<LL><<<unsigned((waves + 3) / 4), 256, 0, st>>>(
+            n, L.A.rp.p, L.A.ci.p, L.A.v.p, L.sw_ci.p, L.sw_v.p, L.sw_v32.p);
+      });
+      TPF_CHECK_LAUNCH();
+      L.Av32.release();  // the FP32 cycle reads sw_v32 only
+    } else {
+      L.sw_ci.release();
+      L.sw_v.release();
+      L.sw_v32.release();
+    }
+  }
   coarse_setup(st);
+}
+
+// Levels whose smoothers stream their rows: fused V(1,1) cycles, CSR levels
+// (not the diagonal level 0) of kGuessRows rows or more, below the coarsest,
+// with rows of at most kStreamLanes lanes and columns that fit the packed
+// entries
+bool Hierarchy::streamed_level(int l, int n, int lpr) const {
+  return o.fused_cycle() && l + 1 < int(lv.size()) && !(l == 0 && dia0.ok) && n >= kGuessRows &&
+         lpr <= kStreamLanes && n <= kSwColMask + 1;
 }
 
 // Interval of the Chebyshev smoother on D^{-1} A: hi = 1.1 lambda^, lo = 0.3 hi,
@@ -2905,13 +3000,12 @@ size_t Hierarchy::bytes() const {
          L.dinv32.bytes() + L.r.bytes() + L.y.bytes() + L.b.bytes() + L.x.bytes() + L.xa.bytes() +
          L.xb.bytes() + L.dd.bytes() + L.xa32.bytes() + L.xb32.bytes() + L.dd32.bytes() +
          L.r32.bytes() + L.y32.bytes() + L.b32.bytes() + L.x32.bytes() + L.pe_ci.bytes() +
-         L.pe_v.bytes() + L.pe_v32.bytes();
+         L.pe_v.bytes() + L.pe_v32.bytes() + L.sw_ci.bytes() + L.sw_v.bytes() + L.sw_v32.bytes();
   }
   return b;
 }
 
 // ---------------------------------------------------------------- V-cycle
-constexpr int kGuessRows = 65536;  // CSR levels from this size form D^{-1} b first
 
 template <class T>
 void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st, bool g_ready) {
@@ -2994,7 +3088,8 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st, bool g_rea
   // large levels form g = D^{-1} b once (in y, until the prolongation
   // overwrites it), so the residual gathers one vector
   const bool guess = dia || n >= kGuessRows;
-  const bool stream = guess && !dia && lpr <= kStreamLanes;
+  const T* swv = sw_vals<T>(L);
+  const bool stream = L.sw_ci.p && swv;
   if (guess && !g_ready) {
     TimedScope ts(L.t_guess.c_str(), st);
     k_jacobi_guess<T><<<grid_for(n, 256), 256, 0, st>>>(n, dinv, b, y);
@@ -3020,7 +3115,7 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st, bool g_rea
       }
     } else if (stream) {
       DISPATCH_LPR(lpr, LL, {
-        k_vc_pre_gs<T, LL><<<blocks, 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, Av, y, b, r);
+        k_vc_pre_gs<T, LL><<<blocks, 256, 0, st>>>(n, L.A.rp.p, L.sw_ci.p, swv, y, b, r);
       });
     } else if (guess) {
       DISPATCH_LPR(lpr, LL, {
@@ -3086,7 +3181,7 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st, bool g_rea
       }
     } else if (stream) {
       DISPATCH_LPR(lpr, LL, {
-        k_vc_posts<T, LL><<<blocks, 256, 0, st>>>(n, L.A.rp.p, L.A.ci.p, Av, dinv, b, y, x);
+        k_vc_posts<T, LL><<<blocks, 256, 0, st>>>(n, L.A.rp.p, L.sw_ci.p, swv, dinv, b, y, x);
       });
     } else {
       DISPATCH_LPR(lpr, LL, {

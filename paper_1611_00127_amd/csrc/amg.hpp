@@ -49,6 +49,14 @@ struct Level {
   Buf<int> pe_ci;
   Buf<double> pe_v;
   Buf<float> pe_v32;
+  // A for the streamed smoothers (large levels whose rows take at most 8
+  // lanes): inside each 512-entry window of a wavefront's rows the entries
+  // are in ascending column order; entry k holds column | p << 23, p its
+  // position in the window in CSR order, and the value from that position;
+  // FP64 or FP32 values as the cycle runs
+  Buf<int> sw_ci;
+  Buf<double> sw_v;
+  Buf<float> sw_v32;
   // generic smoothing sweeps: two iterates and the Chebyshev direction, and
   // the Chebyshev interval [cheb_lo, cheb_hi] of D^{-1} A
   Buf<double> xa, xb, dd;
@@ -124,6 +132,7 @@ struct Hierarchy {
 
  private:
   void finish_levels(hipStream_t st);
+  bool streamed_level(int l, int n, int lpr) const;
   void coarse_setup(hipStream_t st);
   void chebyshev_setup(Level& L, hipStream_t st);
   void gs_setup(Level& L, hipStream_t st);
