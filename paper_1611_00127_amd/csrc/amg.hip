@@ -2055,32 +2055,43 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Products of the window's sorted entries ws + u * 64 + lane (u < U) into
-// win at their CSR positions; positions clamped to the window's last entry
-// we - 1, so all loads are valid and issued before the first wait.  NT:
-// values and indices read non-temporally.
+// Products of the window's sorted entries into win at their CSR positions.
+// Lane l takes the entry pairs (e, e + 1), e = base + 2 (u * 64 + l) for
+// u < U, base = ws rounded down to even, so values and packed indices are
+// read as 16- and 8-byte pairs; pairs are clamped to the window's last one,
+// so all loads are valid (the arrays carry one zero entry past the end) and
+// issued before the first wait, and entries outside [ws, we) are dropped.
+// NT: values and indices read non-temporally.
 template <class T, int U, bool NT, class G>
 __device__ inline void stream_window(int ws, int we, int lane, const int* __restrict__ sci,
                                      const T* __restrict__ v, G g, T* __restrict__ win) {
-  int c[U];
-  T a[U];
+  using I2 = int __attribute__((ext_vector_type(2)));
+  const int base = ws & ~1, last = (we - 1) & ~1;
+  I2 c[U];
+  nt2<T> a[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int f = min(ws + u * kWave + lane, we - 1);
+    const int e = min(base + 2 * (u * kWave + lane), last);
     if constexpr (NT) {
-      c[u] = __builtin_nontemporal_load(sci + f);
-      a[u] = __builtin_nontemporal_load(v + f);
+      c[u] = __builtin_nontemporal_load(reinterpret_cast<const I2*>(sci + e));
+      a[u] = __builtin_nontemporal_load(reinterpret_cast<const nt2<T>*>(v + e));
     } else {
-      c[u] = sci[f];
-      a[u] = v[f];
+      c[u] = *reinterpret_cast<const I2*>(sci + e);
+      a[u] = *reinterpret_cast<const nt2<T>*>(v + e);
     }
   }
-  T x[U];
+  T x0[U], x1[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) x[u] = g(c[u] & kSwColMask);
+  for (int u = 0; u < U; ++u) {
+    x0[u] = g(c[u].x & kSwColMask);
+    x1[u] = g(c[u].y & kSwColMask);
+  }
 #pragma unroll
-  for (int u = 0; u < U; ++u)
-    if (ws + u * kWave + lane < we) win[unsigned(c[u]) >> kSwColBits] = a[u] * x[u];
+  for (int u = 0; u < U; ++u) {
+    const int e = base + 2 * (u * kWave + lane);
+    if (e >= ws && e < we) win[unsigned(c[u].x) >> kSwColBits] = a[u].x * x0[u];
+    if (e + 1 < we) win[unsigned(c[u].y) >> kSwColBits] = a[u].y * x1[u];
+  }
 }
 
 // Row r0 + lane / LPR's dot with the gathered values g(col), valid in the
@@ -2092,21 +2103,24 @@ __device__ inline T stream_rows_dot(int n, int r0, int lane, const int* __restri
                                     const int* __restrict__ ci, const T* __restrict__ v, G g,
                                     T* __restrict__ win) {
   constexpr int R = kWave / LPR;
-  static_assert(kStreamWin == 8 * kWave, "windows of up to eight loads");
+  static_assert(kStreamWin == 8 * kWave, "windows of up to five pair loads");
   const int s = rp[r0], t = rp[min(r0 + R, n)];
   const int row = r0 + lane / LPR, q = lane % LPR;
   const int lo = rp[min(row, n)], hi = rp[min(row + 1, n)];
   T sum = T(0);
   for (int ws = s; ws < t; ws += kStreamWin) {
-    const int we = min(ws + kStreamWin, t), m = we - ws;
-    if (m > 6 * kWave)
-      stream_window<T, 8, NT>(ws, we, lane, ci, v, g, win);
-    else if (m > 4 * kWave)
-      stream_window<T, 6, NT>(ws, we, lane, ci, v, g, win);
-    else if (m > 2 * kWave)
+    const int we = min(ws + kStreamWin, t);
+    const int pairs = (we - (ws & ~1) + 1) / 2;  // at most kStreamWin / 2 + 1
+    if (pairs > 4 * kWave)
+      stream_window<T, 5, NT>(ws, we, lane, ci, v, g, win);
+    else if (pairs > 3 * kWave)
       stream_window<T, 4, NT>(ws, we, lane, ci, v, g, win);
-    else
+    else if (pairs > 2 * kWave)
+      stream_window<T, 3, NT>(ws, we, lane, ci, v, g, win);
+    else if (pairs > kWave)
       stream_window<T, 2, NT>(ws, we, lane, ci, v, g, win);
+    else
+      stream_window<T, 1, NT>(ws, we, lane, ci, v, g, win);
     wave_lds_sync();
     const int je = min(hi, we);
     for (int j = max(lo, ws) + q; j < je; j += LPR) sum += win[j - ws];
@@ -2131,6 +2145,12 @@ __global__ void __launch_bounds__(256) k_window_sort(int n, const int* __restric
                                                      float* __restrict__ sv32) {
   __shared__ unsigned keys[256 / kWave][kStreamWin];
   const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {  // the zero entry past the end
+    const int z = rp[n];
+    sci[z] = 0;
+    if (sv) sv[z] = 0.0;
+    if (sv32) sv32[z] = 0.0f;
+  }
   const int r0 = (blockIdx.x * (256 / kWave) + w) * (kWave / LPR);
   if (r0 >= n) return;  // the whole wavefront
   const int s = rp[r0], t = rp[min(r0 + kWave / LPR, n)];
@@ -2676,13 +2696,13 @@ void Hierarchy::finish_levels(hipStream_t st) {
     const int n = L.A.nrows;
     const int lpr = lanes_per_row(n, L.A.nnz);
     if (streamed_level(int(l), n, lpr)) {
-      L.sw_ci.ensure(L.A.nnz, st);
+      L.sw_ci.ensure(L.A.nnz + 1, st);
       if (o.fp32) {
         L.sw_v.release();
-        L.sw_v32.ensure(L.A.nnz, st);
+        L.sw_v32.ensure(L.A.nnz + 1, st);
       } else {
         L.sw_v32.release();
-        L.sw_v.ensure(L.A.nnz, st);
+        L.sw_v.ensure(L.A.nnz + 1, st);
       }
       const int64_t waves = (n + kWave / lpr - 1) / (kWave / lpr);
       DISPATCH_LPR(lpr, LL, {

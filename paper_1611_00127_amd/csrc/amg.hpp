@@ -53,7 +53,7 @@ struct Level {
   // lanes): inside each 512-entry window of a wavefront's rows the entries
   // are in ascending column order; entry k holds column | p << 23, p its
   // position in the window in CSR order, and the value from that position;
-  // FP64 or FP32 values as the cycle runs
+  // FP64 or FP32 values as the cycle runs; one zero entry past the end
   Buf<int> sw_ci;
   Buf<double> sw_v;
   Buf<float> sw_v32;
