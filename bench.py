@@ -647,6 +647,7 @@ def serve_stream(torch, tpf, driver, inputs, args):
         xs = [torch.empty(2 * seqs[r][0].N, dtype=torch.float64, device="cuda") for r, _ in order]
         torch.cuda.synchronize()
         lat, its, rel, errs, ref = [None] * n, [0] * n, [0.0] * n, [0.0] * n, [0] * n
+        t_setup, t_solve, t_lat = [0.0] * n, [0.0] * n, [0.0] * n
         tick, i, done = {}, 0, 0
         t0 = time.perf_counter()
         while done < n:
@@ -671,6 +672,7 @@ def serve_stream(torch, tpf, driver, inputs, args):
                 its[j] = res.iterations
                 rel[j] = res.relres_true
                 ref[j] = res.refreshed
+                t_setup[j], t_solve[j], t_lat[j] = res.setup_ms, res.solve_ms, res.latency_ms
                 assert res.status == tpf.TPF_CONVERGED, (order[j], res.status)
                 done += 1
         total = time.perf_counter() - t0
@@ -687,10 +689,20 @@ def serve_stream(torch, tpf, driver, inputs, args):
             by_edge[str(e)] = {"requests": len(le), "p50_ms": round(pct(le, 50), 2),
                                "p99_ms": round(pct(le, 99), 2)}
         refreshed = sum(1 for j in range(n) if ref[j])
+        # where the slowest 1% of requests spent their time (the server's own clocks:
+        # waiting = submit to completion minus setup and solve)
+        cut = pct(lat, 99)
+        slow = [j for j in range(n) if lat[j] >= cut]
+        tail = {k: round(float(np.mean([f(j) for j in slow])), 2) for k, f in (
+            ("setup_ms", lambda j: t_setup[j]), ("solve_ms", lambda j: t_solve[j]),
+            ("waiting_ms", lambda j: t_lat[j] - t_setup[j] - t_solve[j]))}
+        tail["requests"] = len(slow)
+        tail["p99_setup_ms_all"] = round(pct(t_setup, 99), 2)
+        tail["p99_solve_ms_all"] = round(pct(t_solve, 99), 2)
         return {"arrival_rate_per_s": None if rate is None else round(rate, 2),
                 "solves_per_s": round(n / total, 2), "wall_s": round(total, 3),
                 "p50_latency_ms": round(pct(lat, 50), 2), "p99_latency_ms": round(pct(lat, 99), 2),
-                "latency_by_edge": by_edge, "refreshed_requests": refreshed,
+                "latency_by_edge": by_edge, "slowest_1pct": tail, "refreshed_requests": refreshed,
                 "mean_iterations": round(float(np.mean(its)), 2),
                 "max_relres_true": float(np.max(rel)),
                 "max_rel_diff_vs_fp64": float(np.max(errs)),

@@ -162,6 +162,9 @@ def test_budget_admission_and_eviction(env):
     assert st.evictions >= 1
     assert len(res) == 3  # keys repeat: the second round overwrote the first
     for key, (x, r) in res.items():
+        say(f"  {key}: status {r.status}, reserved {r.reserved_bytes}, "
+            f"latency {r.latency_ms:.1f} ms, refreshed {r.refreshed}")
+    for key, (x, r) in res.items():
         assert r.status == tpf.TPF_CONVERGED, key
         assert 0 < r.reserved_bytes <= budget
         assert np.all(np.isfinite(x))
