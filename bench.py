@@ -174,7 +174,9 @@ def kernel_symbol(st, h, l, timer, ell_w=0):
     if timer == "vcycle_restrict":
         if guess_level(st, h, l + 1):
             nc = int(st.rows[h][l + 1])
-            return f"k_vc_restrict_guess<double, {lanes_per_row(nc, int(st.p_nnz[h][l]))}>"
+            lpr = lanes_per_row(nc, int(st.p_nnz[h][l]))
+            kind = "gs" if lpr <= STREAM_LANES else "guess"
+            return f"k_vc_restrict_{kind}<double, {lpr}>"
         return "k_csr_spmv"
     if timer == "vcycle_jacobi_guess":
         return "k_jacobi_guess<double>"

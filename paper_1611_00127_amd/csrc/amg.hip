@@ -2226,6 +2226,29 @@ __global__ void __launch_bounds__(256) k_vc_posts(int n, const int* __restrict__
   if (lane % LPR == 0 && row < n) x[row] = y[row] + dinv[row] * (b[row] - sum);
 }
 
+// b_c = R r and g_c = D_c^{-1} b_c from R's window-sorted copy (the rows of
+// R are the coarse points); grid as k_vc_restrict_guess's.  R is read once
+// per cycle: non-temporal.
+template <class T, int LPR>
+__global__ void __launch_bounds__(256) k_vc_restrict_gs(int nc, const int* __restrict__ rrp,
+                                                        const int* __restrict__ rci,
+                                                        const T* __restrict__ rv,
+                                                        const T* __restrict__ r,
+                                                        const T* __restrict__ dinv_c,
+                                                        T* __restrict__ bc, T* __restrict__ gc) {
+  __shared__ T win[256 / kWave][kStreamWin];
+  const int r0 = stream_first_row<LPR>();
+  if (r0 >= nc) return;
+  const int lane = threadIdx.x % kWave;
+  const T sum = stream_rows_dot<T, LPR, true>(
+      nc, r0, lane, rrp, rci, rv, [&](int j) { return r[j]; }, win[threadIdx.x / kWave]);
+  const int row = r0 + lane / LPR;
+  if (lane % LPR == 0 && row < nc) {
+    bc[row] = sum;
+    gc[row] = dinv_c[row] * sum;
+  }
+}
+
 #define DISPATCH_DIAG(K, KK, ...)                               \
   switch (K) {                                                  \
     case 5: { constexpr int KK = 5; __VA_ARGS__ } break;        \
@@ -2252,6 +2275,9 @@ template <> const float* ell_vals<float>(const Level& L) { return L.pe_v32.p; }
 template <class T> const T* sw_vals(const Level& L);
 template <> const double* sw_vals<double>(const Level& L) { return L.sw_v.p; }
 template <> const float* sw_vals<float>(const Level& L) { return L.sw_v32.p; }
+template <class T> const T* rw_vals(const Level& L);
+template <> const double* rw_vals<double>(const Level& L) { return L.rw_v.p; }
+template <> const float* rw_vals<float>(const Level& L) { return L.rw_v32.p; }
 constexpr int kEllMaxW = 4;  // widest ELL form of P
 #define DISPATCH_ELL(w, W, ...)                         \
   switch (w) {                                          \
@@ -2716,8 +2742,42 @@ void Hierarchy::finish_levels(hipStream_t st) {
       L.sw_v.release();
       L.sw_v32.release();
     }
+    if (streamed_restriction(int(l))) {
+      const int nc = L.R.nrows;
+      const int rl = lanes_per_row(nc, L.R.nnz);
+      L.rw_ci.ensure(L.R.nnz + 1, st);
+      if (o.fp32) {
+        L.rw_v.release();
+        L.rw_v32.ensure(L.R.nnz + 1, st);
+      } else {
+        L.rw_v32.release();
+        L.rw_v.ensure(L.R.nnz + 1, st);
+      }
+      const int64_t waves = (nc + kWave / rl - 1) / (kWave / rl);
+      DISPATCH_LPR(rl, LL, {
+        k_window_sort<LL><<<unsigned((waves + 3) / 4), 256, 0, st>>>(
+            nc, L.R.rp.p, L.R.ci.p, L.R.v.p, L.rw_ci.p, L.rw_v.p, L.rw_v32.p);
+      });
+      TPF_CHECK_LAUNCH();
+    } else {
+      L.rw_ci.release();
+      L.rw_v.release();
+      L.rw_v32.release();
+    }
   }
   coarse_setup(st);
+}
+
+// Restrictions into a coarse level that forms its guess there (fused
+// cycles, coarse level of kGuessRows rows or more above the coarsest), with
+// rows of at most kStreamLanes lanes and fine columns that fit the packed
+// entries
+bool Hierarchy::streamed_restriction(int l) const {
+  if (!o.fused_cycle() || l + 2 >= int(lv.size())) return false;
+  const Level& L = *lv[l];
+  const int nc = L.R.nrows;
+  return nc >= kGuessRows && lanes_per_row(nc, L.R.nnz) <= kStreamLanes &&
+         L.A.nrows <= kSwColMask + 1;
 }
 
 // Levels whose smoothers stream their rows: fused V(1,1) cycles, CSR levels
@@ -3020,7 +3080,8 @@ size_t Hierarchy::bytes() const {
          L.dinv32.bytes() + L.r.bytes() + L.y.bytes() + L.b.bytes() + L.x.bytes() + L.xa.bytes() +
          L.xb.bytes() + L.dd.bytes() + L.xa32.bytes() + L.xb32.bytes() + L.dd32.bytes() +
          L.r32.bytes() + L.y32.bytes() + L.b32.bytes() + L.x32.bytes() + L.pe_ci.bytes() +
-         L.pe_v.bytes() + L.pe_v32.bytes() + L.sw_ci.bytes() + L.sw_v.bytes() + L.sw_v32.bytes();
+         L.pe_v.bytes() + L.pe_v32.bytes() + L.sw_ci.bytes() + L.sw_v.bytes() + L.sw_v32.bytes() +
+         L.rw_ci.bytes() + L.rw_v.bytes() + L.rw_v32.bytes();
   }
   return b;
 }
@@ -3153,11 +3214,19 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st, bool g_rea
   if (c_guess) {
     TimedScope ts(L.t_restrict.c_str(), st);
     const int rlpr = lanes_per_row(C.A.nrows, L.R.nnz);
-    DISPATCH_LPR(rlpr, LL, {
-      k_vc_restrict_guess<T, LL><<<grid_for(int64_t(C.A.nrows) * LL, 256), 256, 0, st>>>(
-          C.A.nrows, L.R.rp.p, L.R.ci.p, vals_of<T>(L.R, L.Rv32), r, dinv_of<T>(C), bc,
-          work<T>(C.y, C.y32));
-    });
+    const T* rwv = rw_vals<T>(L);
+    if (L.rw_ci.p && rwv) {
+      DISPATCH_LPR(rlpr, LL, {
+        k_vc_restrict_gs<T, LL><<<grid_for(int64_t(C.A.nrows) * LL, 256), 256, 0, st>>>(
+            C.A.nrows, L.R.rp.p, L.rw_ci.p, rwv, r, dinv_of<T>(C), bc, work<T>(C.y, C.y32));
+      });
+    } else {
+      DISPATCH_LPR(rlpr, LL, {
+        k_vc_restrict_guess<T, LL><<<grid_for(int64_t(C.A.nrows) * LL, 256), 256, 0, st>>>(
+            C.A.nrows, L.R.rp.p, L.R.ci.p, vals_of<T>(L.R, L.Rv32), r, dinv_of<T>(C), bc,
+            work<T>(C.y, C.y32));
+      });
+    }
     TPF_CHECK_LAUNCH();
   } else {
     csr_spmv<T>(ref_with<T>(L.R, vals_of<T>(L.R, L.Rv32)), r, bc, st, L.t_restrict.c_str());

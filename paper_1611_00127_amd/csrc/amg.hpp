@@ -57,6 +57,11 @@ struct Level {
   Buf<int> sw_ci;
   Buf<double> sw_v;
   Buf<float> sw_v32;
+  // R in the same window-sorted form, for the streamed restriction into a
+  // coarse level that forms its guess there
+  Buf<int> rw_ci;
+  Buf<double> rw_v;
+  Buf<float> rw_v32;
   // generic smoothing sweeps: two iterates and the Chebyshev direction, and
   // the Chebyshev interval [cheb_lo, cheb_hi] of D^{-1} A
   Buf<double> xa, xb, dd;
@@ -133,6 +138,7 @@ struct Hierarchy {
  private:
   void finish_levels(hipStream_t st);
   bool streamed_level(int l, int n, int lpr) const;
+  bool streamed_restriction(int l) const;
   void coarse_setup(hipStream_t st);
   void chebyshev_setup(Level& L, hipStream_t st);
   void gs_setup(Level& L, hipStream_t st);
