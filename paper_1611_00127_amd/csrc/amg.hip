@@ -2021,23 +2021,23 @@ __global__ void __launch_bounds__(256) k_dia_post(int n, DiagOffs o, const T* __
 
 // ---------------------------------------------------------------- streamed CSR rows
 // Smoother kernels of the large CSR levels (the Galerkin operators below
-// level 0) whose rows take at most 8 lanes (64 entries on average).  A
-// wavefront takes R = 64 / LPR consecutive rows, as the row kernels' grid
-// assigns them, but reads their entries as one contiguous range: every load
-// instruction covers 64 consecutive values and column indices, where the row
-// kernels' lane groups read R separate pieces of 8 LPR bytes (wider groups
-// already read whole 128-byte lines and keep the row kernels).  The range is
-// cut into windows of kStreamWin entries, and setup sorts each window's
-// entries by column (Level::sw_ci): a load instruction's 64 gathers of g_j
-// then touch a few cache lines of g instead of one or two per row segment.
-// The products a_ij g_j go back to their CSR positions in the wavefront's LDS
-// window; each row's LPR lanes then sum their row's part of the window, in
-// CSR order, and reduce across the group.  Work-groups
-// are numbered XCD-contiguously, so the columns a stretch of rows gathers
-// stay in one XCD's L2.  The pre-smoother reads the level's values and
-// indices with ordinary loads, leaving what the memory-side cache keeps of
-// them for the post-smoother, which reads them non-temporally as their last
-// use in the cycle.
+// level 0) whose rows take at most 8 lanes (64 entries on average), and the
+// restriction into such levels.  A wavefront takes R = 64 / LPR consecutive
+// rows, as the row kernels' grid assigns them, but reads their entries as
+// one contiguous range: every load instruction covers 128 consecutive values
+// and column indices (a pair per lane), where the row kernels' lane groups
+// read R separate pieces of 8 LPR bytes (wider groups already read whole
+// 128-byte lines and keep the row kernels).  The range is cut into windows
+// of kStreamWin entries, and setup sorts each window's entries by column
+// (Level::sw_ci): a load's gathers of g_j then touch a few cache lines of g
+// instead of one or two per row segment.  The products a_ij g_j go back to
+// their CSR positions in the wavefront's LDS window; each row's LPR lanes
+// then sum their row's part of the window, in CSR order, and reduce across
+// the group.  Work-groups are numbered XCD-contiguously, so the columns a
+// stretch of rows gathers stay in one XCD's L2.  The pre-smoother reads the
+// level's values and indices with ordinary loads, leaving what the
+// memory-side cache keeps of them for the post-smoother, which reads them
+// non-temporally as their last use in the cycle.
 constexpr int kStreamWin = 512;
 constexpr int kStreamLanes = 8;  // rows of up to this many lanes are streamed
 constexpr int kGuessRows = 65536;  // CSR levels from this size form D^{-1} b first
