@@ -283,20 +283,18 @@ KERNEL_SOURCES = {
     "k_dia_post2": ["amg.hip:clampi", "amg.hip:xcd_contiguous_block", "amg.hip:k_dia_post2"],
 }
 
-# rocprofv3 runs whose outputs --reduce-traffic reads (GPU machine, repository root)
+# rocprofv3 runs whose outputs --reduce-traffic reads; <repo> is the repository
+# root and <out> the folder later given to --reduce-traffic
 TRAFFIC_COMMANDS = [
     "cd /tmp && export TMPDIR=/tmp",
-    "rocprofv3 --kernel-trace --stats --output-format csv -d $GRAFT_REPO_ROOT/gpurun_out/prof "
-    "-o bench -- python3 $GRAFT_REPO_ROOT/bench.py --steps 2 --warmup 1 --no-cpu-baseline "
-    "--no-serve --no-c4",
-    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $GRAFT_REPO_ROOT/gpurun_out/pmc_fetch "
-    "-o fetch -- python3 $GRAFT_REPO_ROOT/bench.py --steps 1 --warmup 0 --no-cpu-baseline "
-    "--no-serve --no-c4 --copy-probe 512 --traffic-spec $GRAFT_REPO_ROOT/gpurun_out/"
-    "traffic_spec.json",
-    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $GRAFT_REPO_ROOT/gpurun_out/pmc_write "
-    "-o write -- python3 $GRAFT_REPO_ROOT/bench.py --steps 1 --warmup 0 --no-cpu-baseline "
-    "--no-serve --no-c4 --copy-probe 512",
-    "python bench.py --reduce-traffic gpurun_out   (here: writes this file)",
+    "rocprofv3 --kernel-trace --stats --output-format csv -d <out>/prof -o bench -- python3 "
+    "<repo>/bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-serve --no-c4",
+    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/pmc_fetch -o fetch -- python3 "
+    "<repo>/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-serve --no-c4 --copy-probe 512 "
+    "--traffic-spec <out>/traffic_spec.json",
+    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/pmc_write -o write -- python3 "
+    "<repo>/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-serve --no-c4 --copy-probe 512",
+    "python bench.py --reduce-traffic <out>   (writes this file)",
 ]
 
 
