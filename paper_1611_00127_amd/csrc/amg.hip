@@ -2131,11 +2131,12 @@ __device__ inline T stream_rows_dot(int n, int r0, int lane, const int* __restri
   return sum;
 }
 
-// Setup of Level::sw_ci / sw_v / sw_v32: one wavefront per R = 64 / LPR
-// rows (the smoothers' assignment, without the XCD renumbering); each
-// window's keys column << 9 | position are sorted in LDS by a bitonic
-// network, then the packed entries and the values they point at are written.
-// Columns must be below 2^23.
+// Setup of Level::sw_ci / sw_v / sw_v32 (and of R's copy): one wavefront per
+// R = 64 / LPR rows (the smoothers' assignment, without the XCD
+// renumbering); each window's keys column << 9 | position are sorted in
+// registers by a bitonic network across the wavefront, then the packed
+// entries and the values they point at are written.  Columns must be below
+// 2^23.
 template <int LPR>
 __global__ void __launch_bounds__(256) k_window_sort(int n, const int* __restrict__ rp,
                                                      const int* __restrict__ ci,
@@ -2143,7 +2144,7 @@ __global__ void __launch_bounds__(256) k_window_sort(int n, const int* __restric
                                                      int* __restrict__ sci,
                                                      double* __restrict__ sv,
                                                      float* __restrict__ sv32) {
-  __shared__ unsigned keys[256 / kWave][kStreamWin];
+  constexpr int PER = kStreamWin / kWave;
   const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   if (blockIdx.x == 0 && threadIdx.x == 0) {  // the zero entry past the end
     const int z = rp[n];
@@ -2154,33 +2155,28 @@ __global__ void __launch_bounds__(256) k_window_sort(int n, const int* __restric
   const int r0 = (blockIdx.x * (256 / kWave) + w) * (kWave / LPR);
   if (r0 >= n) return;  // the whole wavefront
   const int s = rp[r0], t = rp[min(r0 + kWave / LPR, n)];
-  unsigned* K = keys[w];
   for (int ws = s; ws < t; ws += kStreamWin) {
     const int m = min(kStreamWin, t - ws);
-    for (int k = lane; k < kStreamWin; k += kWave)
-      K[k] = k < m ? (unsigned(ci[ws + k]) << (32 - kSwColBits)) | unsigned(k) : 0xffffffffu;
-    wave_lds_sync();
-    for (int size = 2; size <= kStreamWin; size <<= 1) {
-      for (int stride = size >> 1; stride > 0; stride >>= 1) {
-        for (int q = lane; q < kStreamWin / 2; q += kWave) {
-          const int i = 2 * q - (q & (stride - 1)), j = i + stride;
-          const unsigned a = K[i], b = K[j];
-          if ((a > b) == ((i & size) == 0)) {
-            K[i] = b;
-            K[j] = a;
-          }
-        }
-        wave_lds_sync();
+    unsigned key[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int k = q * kWave + lane;
+      key[q] = k < m ? (unsigned(ci[ws + k]) << (32 - kSwColBits)) | unsigned(k) : 0xffffffffu;
+    }
+    int p2 = 2;
+    while (p2 < m) p2 <<= 1;
+    // p2 <= kStreamWin = 64 PER: the network stays in registers and shuffles
+    bitonic_regs<PER>(key, 0, lane, p2, static_cast<unsigned*>(nullptr));
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int k = q * kWave + lane;
+      if (k < m) {
+        const int p = int(key[q] & (kStreamWin - 1)), c = int(key[q] >> (32 - kSwColBits));
+        sci[ws + k] = int(unsigned(c) | (unsigned(p) << kSwColBits));
+        if (sv) sv[ws + k] = v[ws + p];
+        if (sv32) sv32[ws + k] = float(v[ws + p]);
       }
     }
-    for (int k = lane; k < m; k += kWave) {
-      const unsigned key = K[k];
-      const int p = int(key & (kStreamWin - 1)), c = int(key >> (32 - kSwColBits));
-      sci[ws + k] = int(unsigned(c) | (unsigned(p) << kSwColBits));
-      if (sv) sv[ws + k] = v[ws + p];
-      if (sv32) sv32[ws + k] = float(v[ws + p]);
-    }
-    wave_lds_sync();  // the keys are rewritten next
   }
 }
 
