@@ -169,7 +169,7 @@ def kernel_symbol(st, h, l, timer, ell_w=0):
         return f"k_vc_post{s}<double, {lpr}>"
     if timer == "vcycle_prolong":
         if ell_w:
-            return f"k_vc_prolong_ell<double, {ell_w}>"
+            return f"k_vc_prolong_ell{'2' if n % 2 == 0 else ''}<double, {ell_w}>"
         return f"k_vc_prolong<double, {lanes_per_row(n, int(st.p_nnz[h][l]))}>"
     if timer == "vcycle_restrict":
         if guess_level(st, h, l + 1):

@@ -2019,6 +2019,41 @@ __global__ void __launch_bounds__(256) k_dia_post(int n, DiagOffs o, const T* __
   x[i] = y[i] + dinv[i] * (b[i] - sum);
 }
 
+// The ELL prolongation with two rows per thread (n even): slots, values and
+// row vectors read as pairs, each row's entries summed as in k_vc_prolong_ell;
+// P is read once per cycle, so its slots are read non-temporally.
+template <class T, int W>
+__global__ void __launch_bounds__(256) k_vc_prolong_ell2(int n, const int* __restrict__ eci,
+                                                         const T* __restrict__ ev,
+                                                         const T* __restrict__ dinv,
+                                                         const T* __restrict__ b,
+                                                         const T* __restrict__ xc,
+                                                         T* __restrict__ y) {
+  using T2 = typename Vec2<T>::type;
+  using I2 = int __attribute__((ext_vector_type(2)));
+  const int i = 2 * (xcd_contiguous_block() * blockDim.x + threadIdx.x);
+  if (i >= n) return;
+  I2 c[W];
+  nt2<T> a[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    c[k] = __builtin_nontemporal_load(reinterpret_cast<const I2*>(eci + int64_t(k) * n + i));
+    a[k] = __builtin_nontemporal_load(reinterpret_cast<const nt2<T>*>(ev + int64_t(k) * n + i));
+  }
+  T s0 = T(0), s1 = T(0);
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    if (c[k].x >= 0) s0 += a[k].x * xc[c[k].x];
+    if (c[k].y >= 0) s1 += a[k].y * xc[c[k].y];
+  }
+  const T2 dd = *reinterpret_cast<const T2*>(dinv + i);
+  const T2 bb = *reinterpret_cast<const T2*>(b + i);
+  T2 out;
+  out.x = dd.x * bb.x + s0;
+  out.y = dd.y * bb.y + s1;
+  *reinterpret_cast<T2*>(y + i) = out;
+}
+
 // ---------------------------------------------------------------- streamed CSR rows
 // Smoother kernels of the large CSR levels (the Galerkin operators below
 // level 0) whose rows take at most 8 lanes (64 entries on average), and the
@@ -3231,7 +3266,12 @@ void Hierarchy::vcycle_level(int l, const T* b, T* x, hipStream_t st, bool g_rea
   {
     TimedScope ts(L.t_prolong.c_str(), st);
     const T* pev = ell_vals<T>(L);
-    if (L.pe_w > 0 && pev) {
+    if (L.pe_w > 0 && pev && pairs && al2(pev)) {
+      DISPATCH_ELL(L.pe_w, WW, {
+        k_vc_prolong_ell2<T, WW><<<grid_for(n / 2, 256), 256, 0, st>>>(n, L.pe_ci.p, pev, dinv,
+                                                                        b, xc, y);
+      });
+    } else if (L.pe_w > 0 && pev) {
       DISPATCH_ELL(L.pe_w, WW, {
         k_vc_prolong_ell<T, WW><<<grid_for(n, 256), 256, 0, st>>>(n, L.pe_ci.p, pev, dinv, b,
                                                                    xc, y);

@@ -58,7 +58,7 @@ def test_vcycle_kernel_bytes_by_hand():
     assert bench.kernel_symbol(st, 0, 2, "vcycle_pre_residual") == "k_vc_pre<double, 8>"
     assert bench.kernel_symbol(st, 0, 0, "vcycle_restrict") == "k_vc_restrict_gs<double, 1>"
     assert bench.kernel_symbol(st, 0, 1, "vcycle_restrict") == "k_csr_spmv"
-    assert bench.kernel_symbol(st, 0, 0, "vcycle_prolong", 3) == "k_vc_prolong_ell<double, 3>"
+    assert bench.kernel_symbol(st, 0, 0, "vcycle_prolong", 3) == "k_vc_prolong_ell2<double, 3>"
     # a large level of long rows (80 entries: 16 lanes) keeps the row kernels
     st16 = _stats([1_000_000, 100_000, 100], [25_000_000, 8_000_000, 5_000],
                   [2_400_000, 300_000, 0], 25)
