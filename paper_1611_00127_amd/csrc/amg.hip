@@ -2131,8 +2131,8 @@ __device__ inline void stream_window(int ws, int we, int lane, const int* __rest
 
 // Row r0 + lane / LPR's dot with the gathered values g(col), valid in the
 // group's first lane (0 for a row at or past n).  win: the wavefront's
-// kStreamWin-entry LDS window.  A window of m entries issues the fewest
-// 64-entry loads of 2, 4, 6 or 8 that cover it.
+// kStreamWin-entry LDS window.  A window issues the fewest pair loads per
+// lane (1 to 5) that cover its entries.
 template <class T, int LPR, bool NT, class G>
 __device__ inline T stream_rows_dot(int n, int r0, int lane, const int* __restrict__ rp,
                                     const int* __restrict__ ci, const T* __restrict__ v, G g,
