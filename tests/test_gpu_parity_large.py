@@ -10,6 +10,9 @@ five-spot, CFL 10):
   FP64 and FP32 (the streamed CSR smoothers, some wavefronts over several
   LDS windows), the full BF solve (iterations within +-1), and CPR1, whose
   block ILU(0) runs the per-front kernels (fronts of up to 2,496 cells).
+* AMG on the point-ordered scalar Jacobian of a 220x200 2D case (88,000
+  unknowns, 10 entries per row): its CSR level 0 takes the streamed smoothers
+  with two lanes per row; one V-cycle in FP64 and FP32.
 * 128x128x64 (1,048,576 cells), the benchmark grid itself: residual,
   Jacobian, SpMV, S~, and the strength graph and C/F splitting of S~'s first
   level, element by element; BF solves against the oracle's stored solves
@@ -107,14 +110,20 @@ def test_large_setup_levels(gpu, newton1):
     M.close(); g.close()
 
 
+def _lanes_per_row(A):
+    """Lanes per row the library picks from the mean row length: the
+    smallest power of two with 8 LPR >= mean."""
+    lpr = 1
+    while lpr < 64 and 8 * lpr < A.nnz / A.shape[0]:
+        lpr *= 2
+    return lpr
+
+
 def _longest_wavefront_range(A):
     """Entries of the longest run of rows one wavefront of the streamed CSR
-    smoothers takes: 64 / LPR rows, LPR the lanes per row the library picks
-    from the mean row length (the smallest power of two with 8 LPR >= mean)."""
+    smoothers takes: 64 / LPR rows."""
     n = A.shape[0]
-    lpr = 1
-    while lpr < 64 and 8 * lpr < A.nnz / n:
-        lpr *= 2
+    lpr = _lanes_per_row(A)
     r0 = np.arange(0, n, 64 // lpr)
     return int(np.max(A.indptr[np.minimum(r0 + 64 // lpr, n)] - A.indptr[r0]))
 
@@ -149,6 +158,39 @@ def test_large_vcycle(gpu, newton1, precision):
         assert rel <= (1e-4 if precision else 1e-12), rel
     # some wavefront of the streamed smoothers takes more than one 512-entry window
     assert longest > 512, longest
+    if M32 is not None:
+        M32.close()
+    M.close(); g.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_streamed_two_lane_rows(gpu, precision):
+    """AMG on the point-ordered scalar Jacobian of a 2D case with 88,000
+    unknowns: level 0 is not a stencil layout, has 10 entries per row (2
+    lanes, 32 rows per wavefront) and takes the streamed smoothers; one
+    V-cycle against the oracle's cycle on the GPU's levels (FP64 within
+    1e-12 of max|x|, FP32 within 1e-4)."""
+    driver, tpf, torch = gpu
+    c = inputs.random_state(inputs.small_case(220, 200, 1, seed=5), 6, s_lo=0.15, s_hi=0.85)
+    say(f"[streamed 2-lane] precision {precision}")
+    g, M = _setup(driver, tpf, c, "amg")
+    M32 = driver.GpuPrecond("amg", tpf.TPF_FP32) if precision else None
+    if M32 is not None:
+        M32.setup(g)
+    H = _gpu_hierarchy_as_oracle(tpf, M, 0)
+    A0 = H.levels[0].A
+    say(f"  levels {[L.n for L in H.levels]}, level 0: {A0.nnz / A0.shape[0]:.1f} entries per row")
+    assert A0.shape[0] >= 65536 and _lanes_per_row(A0) == 2
+    assert int(M.stats().l0_diagonals[0]) == 0  # CSR level 0: the streamed kernels run on it
+    b = inputs.random_vector(A0.shape[0], 17)
+    bd = torch.tensor(b, device="cuda")
+    xd = torch.empty_like(bd)
+    tpf.tpf_precond_vcycle((M32 or M).M, 0, bd, xd)
+    x = xd.cpu().numpy()
+    xo = H.vcycle(b)
+    rel = float(np.max(np.abs(x - xo)) / np.max(np.abs(xo)))
+    say(f"  max rel diff {rel:.2e}")
+    assert rel <= (1e-4 if precision else 1e-12), rel
     if M32 is not None:
         M32.close()
     M.close(); g.close()
